@@ -1,0 +1,812 @@
+// Plain FP64 CPU oracle for the coupled two-species D2Q9 MRT lattice
+// Boltzmann scheme, its exact discrete adjoint (AMRT) and the cost gradient.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark may load this library.  It shares no code,
+// header, table or constant with the GPU path and is deliberately slow:
+// explicit 9x9 matrix products, explicit local Jacobians, push streaming,
+// a generic Gauss-Jordan inverse of the moment matrix.
+//
+// Paper: A. Belmiloudi, "Optimal Control for Chemotaxis Systems and
+// Adjoint-Based Optimization with Multiple-Relaxation-Time Lattice Boltzmann
+// Models" (arXiv:1908.03876).  Equation labels below are the paper's.
+//
+// Instance computed (two species, Theta in {u, v}, lattice units
+// h = tau = c = 1, 3 Cs^2 = c^2 so Cs^2 = 1/3, Section 3.1):
+//   * D2Q9 velocities and weights: Remark on DmQq lattices, (sumWi).
+//   * Moment matrix M = E0 M0 with E0 = I for c = 1 (Section 3.1, the
+//     transportation matrix); relaxation matrix Pi = diag(Lambda1, Lambda2,
+//     Lambda3) with the 2x2 K block coupling j_x and j_y.
+//   * K_Theta from D_Theta = d_Theta Cs^2 tau (K^-1 - I/2) (parameter
+//     choices at the end of the proof of Proposition 1, (PC14)).
+//   * Equilibrium (phieq) with convective flux and C-tensor set to zero.
+//   * Cross-diffusion source (S): S_u,i = w_i e_i.(A_u1 grad v)/Cs^2 with
+//     A_u1 = K_u D_u1 / tau and D_u1 = chi u C_chi (attraction-repulsion
+//     example (ARC), chi_k = X u I generalised to a tensor shape C_chi).
+//     grad v is computed locally from the distributions (LIBEG): from the
+//     first-moment balance (C146), tau Cs^2 d_v grad v = -K_v j_v^neq, and
+//     j_v^eq = 0, so grad v = -K_v j_v / (tau d_v Cs^2) with j_v the
+//     pre-collision first moment of v.
+//   * Reaction source (PhiS) with V = 0: Phi_Theta,i = w_i Phi_Theta,
+//     Phi_u = r_u u (1-u), Phi_v = a_uv u - b_v v + c(x) (control on v).
+//   * The second-order source term (tau^2/2)(kappa_t d/dt + ...) of (eq:LBE)
+//     is not included (first-order source reading).
+//   * One step = collision (MC) in moment space (MF), then streaming along
+//     e_i (eq:LBE); halfway bounce-back on solid cells and, when the lattice
+//     is not periodic, outside the domain.
+//   * Cost (classicJ)/(EJD-H): J = 1/2 sum_F (u^N - u_t)^2 + alpha/2 sum_F c^2.
+//   * Adjoint: AMRT (CAE), (AEDs), (RFS1) with Lambda* = C^T, adjoint
+//     streaming along -e_i backward in time (CAEL); terminal condition
+//     psi(T) = dI0/dphi; gradient (gradientLattice): sum over steps of
+//     sum_i psi_v,i dF_v,i/dc with dF_v,i/dc = tau w_i.
+//   * Sensitivity LBE (LIBEG-V) as a forward-mode linearisation (TLM).
+//   * Gradient step (Section 2.3, Step 5 and the heuristic step
+//     zeta = min(1, 1/||E||_inf)).
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+constexpr int Q = 9;
+constexpr double TAU = 1.0;
+constexpr double CS2 = 1.0 / 3.0;
+
+// D2Q9: e0 = 0, e1 = (1,0), e2 = (0,1), e3 = -e1, e4 = -e2, e5 = (1,1),
+// e6 = (-1,1), e7 = -e5, e8 = -e6.
+const int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int EY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double WGT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// M0 (Section 3.1): rows are the moments rho, e, epsilon, j_x, q_x, j_y,
+// q_y, p_xx, p_xy.
+const double M0[Q][Q] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+int opposite(int i) {
+  for (int j = 0; j < Q; ++j)
+    if (EX[j] == -EX[i] && EY[j] == -EY[i]) return j;
+  return -1;
+}
+
+// Generic Gauss-Jordan inverse with partial pivoting (n x n, row-major).
+bool invert(int n, const double* a, double* inv) {
+  std::vector<double> m(a, a + n * n);
+  for (int i = 0; i < n * n; ++i) inv[i] = 0.0;
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(m[r * n + col]) > std::fabs(m[piv * n + col])) piv = r;
+    if (std::fabs(m[piv * n + col]) < 1e-300) return false;
+    if (piv != col)
+      for (int k = 0; k < n; ++k) {
+        std::swap(m[piv * n + k], m[col * n + k]);
+        std::swap(inv[piv * n + k], inv[col * n + k]);
+      }
+    double p = m[col * n + col];
+    for (int k = 0; k < n; ++k) {
+      m[col * n + k] /= p;
+      inv[col * n + k] /= p;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      double f = m[r * n + col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        m[r * n + k] -= f * m[col * n + k];
+        inv[r * n + k] -= f * inv[col * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+void matmul(int n, const double* a, const double* b, double* c) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += a[i * n + k] * b[k * n + j];
+      c[i * n + j] = s;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+struct OrcSpecies {
+  double D[4];  // self-diffusion tensor, row-major 2x2
+  double d;     // equilibrium parameter d_Theta
+  double s[7];  // free relaxation rates s_0 .. s_6
+};
+
+struct OrcProblem {
+  int nx, ny;
+  int periodic;                // 1: periodic wrap; 0: outside is solid
+  const unsigned char* solid;  // ny*nx, 1 = solid, or NULL
+  OrcSpecies u, v;
+  double chi;
+  double Cchi[4];
+  double r_u, a_uv, b_v;
+  double alpha;
+  int control_on_u;  // 0: control enters Phi_v (default); 1: enters Phi_u
+};
+
+}  // extern "C"
+
+namespace {
+
+// Per-species precomputed operators.
+struct SpeciesOps {
+  double K[4];      // 2x2 relaxation block
+  double Pi[Q * Q]; // relaxation matrix in moment space
+  double C[Q * Q];  // M^-1 Pi M, the collision matrix in velocity space
+  double weq[Q];    // phi_eq_i = weq_i * Theta
+};
+
+struct Ops {
+  double Minv[Q * Q];
+  SpeciesOps u, v;
+  int opp[Q];
+};
+
+void k_from_D(const OrcSpecies& s, double K[4]) {
+  // K^-1 = D/(d Cs^2 tau) + I/2  (from D = d Cs^2 tau (K^-1 - I/2)).
+  double a = s.D[0] / (s.d * CS2 * TAU) + 0.5;
+  double b = s.D[1] / (s.d * CS2 * TAU);
+  double c = s.D[2] / (s.d * CS2 * TAU);
+  double e = s.D[3] / (s.d * CS2 * TAU) + 0.5;
+  double det = a * e - b * c;
+  K[0] = e / det;
+  K[1] = -b / det;
+  K[2] = -c / det;
+  K[3] = a / det;
+}
+
+void build_species(const OrcSpecies& s, const double* Minv, SpeciesOps& o) {
+  k_from_D(s, o.K);
+  for (int i = 0; i < Q * Q; ++i) o.Pi[i] = 0.0;
+  // Lambda1 = diag(s0, s1, s2) on (rho, e, epsilon)
+  o.Pi[0 * Q + 0] = s.s[0];
+  o.Pi[1 * Q + 1] = s.s[1];
+  o.Pi[2 * Q + 2] = s.s[2];
+  // Lambda2 = [[k11, 0, k12], [0, s3, 0], [k21, 0, k22]] on (j_x, q_x, j_y)
+  o.Pi[3 * Q + 3] = o.K[0];
+  o.Pi[3 * Q + 5] = o.K[1];
+  o.Pi[4 * Q + 4] = s.s[3];
+  o.Pi[5 * Q + 3] = o.K[2];
+  o.Pi[5 * Q + 5] = o.K[3];
+  // Lambda3 = diag(s4, s5, s6) on (q_y, p_xx, p_xy)
+  o.Pi[6 * Q + 6] = s.s[4];
+  o.Pi[7 * Q + 7] = s.s[5];
+  o.Pi[8 * Q + 8] = s.s[6];
+  double PiM[Q * Q];
+  matmul(Q, o.Pi, &M0[0][0], PiM);
+  matmul(Q, Minv, PiM, o.C);
+  // (phieq) with T = 0, C-tensor = 0:
+  // phi_eq_i = w_i (Theta + (d Cs^2 Theta - Cs^2 Theta) I:U_i / (2 Cs^4)),
+  // U_i = e_i (x) e_i - Cs^2 I, so I:U_i = |e_i|^2 - 2 Cs^2.
+  for (int i = 0; i < Q; ++i) {
+    double trU = double(EX[i] * EX[i] + EY[i] * EY[i]) - 2.0 * CS2;
+    o.weq[i] = WGT[i] * (1.0 + (s.d * CS2 - CS2) * trU / (2.0 * CS2 * CS2));
+  }
+}
+
+bool build_ops(const OrcProblem& p, Ops& ops) {
+  if (!invert(Q, &M0[0][0], ops.Minv)) return false;
+  build_species(p.u, ops.Minv, ops.u);
+  build_species(p.v, ops.Minv, ops.v);
+  for (int i = 0; i < Q; ++i) ops.opp[i] = opposite(i);
+  return true;
+}
+
+inline bool is_solid(const OrcProblem& p, int x, int y) {
+  if (x < 0 || y < 0 || x >= p.nx || y >= p.ny) return true;  // non-periodic only
+  return p.solid && p.solid[y * p.nx + x];
+}
+
+// Neighbour x + e_i (with periodic wrap when periodic); returns -1 if that
+// node is solid (or outside a non-periodic domain).
+inline int neighbour(const OrcProblem& p, int x, int y, int i, int sign) {
+  int xn = x + sign * EX[i], yn = y + sign * EY[i];
+  if (p.periodic) {
+    xn = (xn % p.nx + p.nx) % p.nx;
+    yn = (yn % p.ny + p.ny) % p.ny;
+  }
+  if (is_solid(p, xn, yn)) return -1;
+  return yn * p.nx + xn;
+}
+
+// ------------------------------------------------------------------ forward
+
+// Local collision at one fluid node (eq:LBE with (S), (PhiS), (MF), (MC)).
+// phi: pre-collision [2][Q] (species u then v); out: post-collision [2][Q].
+template <typename T>
+void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out) {
+  const T* fu = phi;
+  const T* fv = phi + Q;
+  // (UGS): macroscopic values; first moment of v.
+  T u = 0, v = 0, jx = 0, jy = 0;
+  for (int i = 0; i < Q; ++i) {
+    u += fu[i];
+    v += fv[i];
+    jx += double(EX[i]) * fv[i];
+    jy += double(EY[i]) * fv[i];
+  }
+  // grad v computed locally from the distributions.
+  const double* Kv = ops.v.K;
+  T gvx = -(Kv[0] * jx + Kv[1] * jy) / (TAU * p.v.d * CS2);
+  T gvy = -(Kv[2] * jx + Kv[3] * jy) / (TAU * p.v.d * CS2);
+  // D_u1 = chi u C_chi ; A_u1 = K_u D_u1 / tau ; a = A_u1 grad v.
+  T D1[4];
+  for (int k = 0; k < 4; ++k) D1[k] = p.chi * u * p.Cchi[k];
+  const double* Ku = ops.u.K;
+  T A[4];
+  A[0] = (Ku[0] * D1[0] + Ku[1] * D1[2]) / TAU;
+  A[1] = (Ku[0] * D1[1] + Ku[1] * D1[3]) / TAU;
+  A[2] = (Ku[2] * D1[0] + Ku[3] * D1[2]) / TAU;
+  A[3] = (Ku[2] * D1[1] + Ku[3] * D1[3]) / TAU;
+  T ax = A[0] * gvx + A[1] * gvy;
+  T ay = A[2] * gvx + A[3] * gvy;
+  // Kinetics.
+  T Phi_u = p.r_u * u * (1.0 - u);
+  T Phi_v = p.a_uv * u - p.b_v * v;
+  if (p.control_on_u)
+    Phi_u += c;
+  else
+    Phi_v += c;
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesOps& so = s == 0 ? ops.u : ops.v;
+    const T* f = s == 0 ? fu : fv;
+    T theta = s == 0 ? u : v;
+    T Phi = s == 0 ? Phi_u : Phi_v;
+    // (MF): m = M F, m_eq = M F_eq.
+    T feq[Q], m[Q], meq[Q], mcol[Q];
+    for (int i = 0; i < Q; ++i) feq[i] = so.weq[i] * theta;
+    for (int r = 0; r < Q; ++r) {
+      m[r] = 0;
+      meq[r] = 0;
+      for (int i = 0; i < Q; ++i) {
+        m[r] += M0[r][i] * f[i];
+        meq[r] += M0[r][i] * feq[i];
+      }
+    }
+    // (MC): m_col = m - Pi (m - m_eq).
+    for (int r = 0; r < Q; ++r) {
+      T acc = 0;
+      for (int k = 0; k < Q; ++k) acc += so.Pi[r * Q + k] * (m[k] - meq[k]);
+      mcol[r] = m[r] - acc;
+    }
+    for (int i = 0; i < Q; ++i) {
+      T back = 0;
+      for (int r = 0; r < Q; ++r) back += ops.Minv[i * Q + r] * mcol[r];
+      // (S): only the u equation carries a cross-diffusion source.
+      T S = 0;
+      if (s == 0) S = WGT[i] * (double(EX[i]) * ax + double(EY[i]) * ay) / CS2;
+      // (PhiS) with V = 0.
+      T PhiI = WGT[i] * Phi;
+      out[s * Q + i] = back + TAU * S + TAU * PhiI;
+    }
+  }
+}
+
+// State layout: f[(s*Q + i)*ncell + cell], cell = y*nx + x.
+template <typename T>
+void init_equilibrium(const OrcProblem& p, const Ops& ops, const T* u0,
+                      const T* v0, T* f) {
+  const int nc = p.nx * p.ny;
+  for (int cell = 0; cell < nc; ++cell) {
+    bool sol = p.solid && p.solid[cell];
+    for (int i = 0; i < Q; ++i) {
+      f[(0 * Q + i) * nc + cell] = sol ? T(0) : ops.u.weq[i] * u0[cell];
+      f[(1 * Q + i) * nc + cell] = sol ? T(0) : ops.v.weq[i] * v0[cell];
+    }
+  }
+}
+
+// One step: collide every fluid node, then push-stream along e_i with
+// halfway bounce-back (eq:LBE): phi_i(x + e_i, t+1) = phi*_i(x), or
+// phi_opp(i)(x, t+1) = phi*_i(x) when x + e_i is solid.
+template <typename T>
+void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
+          T* post, T* fnew) {
+  const int nc = p.nx * p.ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p.ny; ++y)
+    for (int x = 0; x < p.nx; ++x) {
+      int cell = y * p.nx + x;
+      if (p.solid && p.solid[cell]) {
+        for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = T(0);
+        continue;
+      }
+      T loc[2 * Q], out[2 * Q];
+      for (int k = 0; k < 2 * Q; ++k) loc[k] = f[k * nc + cell];
+      collide(p, ops, loc, ctrl ? ctrl[cell] : T(0), out);
+      for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = out[k];
+    }
+  for (int k = 0; k < 2 * Q * nc; ++k) fnew[k] = T(0);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p.ny; ++y)
+    for (int x = 0; x < p.nx; ++x) {
+      int cell = y * p.nx + x;
+      if (p.solid && p.solid[cell]) continue;
+      for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < Q; ++i) {
+          // Streaming into neighbours would race between rows under OpenMP
+          // only if two sources targeted one slot; each (target, i) has a
+          // unique source, so the writes are disjoint.
+          int nb = neighbour(p, x, y, i, +1);
+          T val = post[(s * Q + i) * nc + cell];
+          if (nb >= 0)
+            fnew[(s * Q + i) * nc + nb] = val;
+          else
+            fnew[(s * Q + ops.opp[i]) * nc + cell] = val;
+        }
+    }
+}
+
+// Jacobian of the local sources R = tau S + tau Phi of both species with
+// respect to the pre-collision node value (18 x 18, row = output (s,i),
+// column = input (s',j)), assembled from the partial derivatives of each
+// term of (S) and (PhiS).
+void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
+                     double* dR) {
+  const double* fu = phi;
+  const double* fv = phi + Q;
+  double u = 0, jx = 0, jy = 0;
+  for (int i = 0; i < Q; ++i) {
+    u += fu[i];
+    jx += EX[i] * fv[i];
+    jy += EY[i] * fv[i];
+  }
+  const int N2 = 2 * Q;
+  for (int k = 0; k < N2 * N2; ++k) dR[k] = 0.0;
+  const double* Kv = ops.v.K;
+  const double* Ku = ops.u.K;
+  double gvx = -(Kv[0] * jx + Kv[1] * jy) / (TAU * p.v.d * CS2);
+  double gvy = -(Kv[2] * jx + Kv[3] * jy) / (TAU * p.v.d * CS2);
+  // A_u1 / u = K_u chi C_chi / tau
+  double Au[4];
+  Au[0] = p.chi * (Ku[0] * p.Cchi[0] + Ku[1] * p.Cchi[2]) / TAU;
+  Au[1] = p.chi * (Ku[0] * p.Cchi[1] + Ku[1] * p.Cchi[3]) / TAU;
+  Au[2] = p.chi * (Ku[2] * p.Cchi[0] + Ku[3] * p.Cchi[2]) / TAU;
+  Au[3] = p.chi * (Ku[2] * p.Cchi[1] + Ku[3] * p.Cchi[3]) / TAU;
+  for (int i = 0; i < Q; ++i) {
+    double wi = WGT[i];
+    double ex = EX[i], ey = EY[i];
+    // dS_u,i/dphi_u,j = w_i e_i.(Au grad v)/Cs^2 (through u = sum phi_u)
+    double dSdu = wi * (ex * (Au[0] * gvx + Au[1] * gvy) +
+                        ey * (Au[2] * gvx + Au[3] * gvy)) / CS2;
+    for (int j = 0; j < Q; ++j) {
+      dR[(0 * Q + i) * N2 + (0 * Q + j)] += TAU * dSdu;
+      // dS_u,i/dphi_v,j = w_i e_i.(u Au dgradv/dphi_v,j)/Cs^2 with
+      // dgradv/dphi_v,j = -K_v e_j/(tau d_v Cs^2)
+      double dgx = -(Kv[0] * EX[j] + Kv[1] * EY[j]) / (TAU * p.v.d * CS2);
+      double dgy = -(Kv[2] * EX[j] + Kv[3] * EY[j]) / (TAU * p.v.d * CS2);
+      double dS = wi * u * (ex * (Au[0] * dgx + Au[1] * dgy) +
+                            ey * (Au[2] * dgx + Au[3] * dgy)) / CS2;
+      dR[(0 * Q + i) * N2 + (1 * Q + j)] += TAU * dS;
+      // Phi_u = r_u u (1-u): dPhi_u,i/dphi_u,j = w_i r_u (1 - 2u)
+      dR[(0 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.r_u * (1.0 - 2.0 * u);
+      // Phi_v = a u - b v + c
+      dR[(1 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.a_uv;
+      dR[(1 * Q + i) * N2 + (1 * Q + j)] += TAU * wi * (-p.b_v);
+    }
+  }
+}
+
+// Jacobian of the relaxation part phi - C (phi - phi_eq(phi)) of one
+// species: I - C + C O^T with O_ij = d phi_eq_j / d phi_i = weq_j (RFS1).
+void relaxation_jacobian(const SpeciesOps& so, double* Jr) {
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j) {
+      double cw = 0.0;
+      for (int k = 0; k < Q; ++k) cw += so.C[i * Q + k] * so.weq[k];
+      Jr[i * Q + j] = (i == j ? 1.0 : 0.0) - so.C[i * Q + j] + cw;
+    }
+}
+
+// Full local Jacobian of the collision map: block-diagonal relaxation part
+// plus the source part.
+void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
+                    double* Jac) {
+  const int N2 = 2 * Q;
+  source_jacobian(p, ops, phi, Jac);
+  for (int s = 0; s < 2; ++s) {
+    double Jr[Q * Q];
+    relaxation_jacobian(s == 0 ? ops.u : ops.v, Jr);
+    for (int i = 0; i < Q; ++i)
+      for (int j = 0; j < Q; ++j) Jac[(s * Q + i) * N2 + (s * Q + j)] += Jr[i * Q + j];
+  }
+}
+
+// Adjoint of the local collision following (CAE)/(AEDs): with
+// Lambda* = C^T and O_ij = d phi_eq_j / d phi_i,
+//   lambda_i = nu_i - [Lambda* (nu - psi_eq)]_i + R~_i,
+//   Lambda* (nu - psi_eq) = Lambda* nu - O Lambda* nu,
+//   R~_i = sum_k nu_k dR_k/dphi_i  (R = tau S + tau Phi over both species).
+void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
+                   const double* nu, double* lam) {
+  const int N2 = 2 * Q;
+  double dR[N2 * N2];
+  source_jacobian(p, ops, phi, dR);
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesOps& so = s == 0 ? ops.u : ops.v;
+    const double* n = nu + s * Q;
+    double Ln[Q];  // Lambda* nu = C^T nu
+    for (int i = 0; i < Q; ++i) {
+      Ln[i] = 0.0;
+      for (int k = 0; k < Q; ++k) Ln[i] += so.C[k * Q + i] * n[k];
+    }
+    for (int i = 0; i < Q; ++i) {
+      double OLn = 0.0;  // (O Lambda* nu)_i = sum_j dphi_eq_j/dphi_i (Lambda* nu)_j
+      for (int j = 0; j < Q; ++j) OLn += so.weq[j] * Ln[j];
+      double Rt = 0.0;
+      for (int k = 0; k < N2; ++k) Rt += nu[k] * dR[k * N2 + (s * Q + i)];
+      lam[s * Q + i] = n[i] - (Ln[i] - OLn) + Rt;
+    }
+  }
+}
+
+void run_forward(const OrcProblem& p, const Ops& ops, int nsteps,
+                 const double* u0, const double* v0, const double* c,
+                 std::vector<double>& f, std::vector<double>* traj) {
+  const size_t nc = size_t(p.nx) * p.ny;
+  f.assign(2 * Q * nc, 0.0);
+  std::vector<double> post(2 * Q * nc), fnew(2 * Q * nc);
+  init_equilibrium(p, ops, u0, v0, f.data());
+  if (traj) traj->assign(size_t(nsteps) * 2 * Q * nc, 0.0);
+  for (int n = 0; n < nsteps; ++n) {
+    if (traj) std::memcpy(traj->data() + size_t(n) * 2 * Q * nc, f.data(),
+                          sizeof(double) * 2 * Q * nc);
+    step(p, ops, f.data(), c, post.data(), fnew.data());
+    f.swap(fnew);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Tables for the lattice pins: E (9x2), weights, M0, M0^-1 (Gauss-Jordan).
+int orc_tables(double* E, double* w, double* M, double* Minv) {
+  for (int i = 0; i < Q; ++i) {
+    E[2 * i] = EX[i];
+    E[2 * i + 1] = EY[i];
+    w[i] = WGT[i];
+  }
+  std::memcpy(M, &M0[0][0], sizeof(double) * Q * Q);
+  return invert(Q, &M0[0][0], Minv) ? 0 : -1;
+}
+
+// K, Pi, C = M^-1 Pi M and the equilibrium weights of one species.
+int orc_species_ops(const OrcSpecies* s, double* K, double* Pi, double* C,
+                    double* weq) {
+  double Minv[Q * Q];
+  if (!invert(Q, &M0[0][0], Minv)) return -1;
+  SpeciesOps o;
+  build_species(*s, Minv, o);
+  std::memcpy(K, o.K, sizeof o.K);
+  std::memcpy(Pi, o.Pi, sizeof o.Pi);
+  std::memcpy(C, o.C, sizeof o.C);
+  std::memcpy(weq, o.weq, sizeof o.weq);
+  return 0;
+}
+
+// One local collision: phi[18] pre-collision -> out[18] post-collision.
+int orc_collide(const OrcProblem* p, const double* phi, double c, double* out) {
+  Ops ops;
+  if (!build_ops(*p, ops)) return -1;
+  collide<double>(*p, ops, phi, c, out);
+  return 0;
+}
+
+int orc_local_jacobian(const OrcProblem* p, const double* phi, double* Jac) {
+  Ops ops;
+  if (!build_ops(*p, ops)) return -1;
+  local_jacobian(*p, ops, phi, Jac);
+  return 0;
+}
+
+int orc_local_adjoint(const OrcProblem* p, const double* phi, const double* nu,
+                      double* lam) {
+  Ops ops;
+  if (!build_ops(*p, ops)) return -1;
+  local_adjoint(*p, ops, phi, nu, lam);
+  return 0;
+}
+
+// Forward solve: N steps from the equilibrium of (u0, v0).  Outputs u^N and
+// v^N (after the last streaming) and optionally the full distribution state
+// state[2][9][ny][nx] and the per-step pre-collision trajectory of u and j_v
+// (traj_u[N][ny*nx], traj_j[N][2][ny*nx]).
+int orc_forward(const OrcProblem* p, int nsteps, const double* u0,
+                const double* v0, const double* c, double* uN, double* vN,
+                double* state, double* traj_u, double* traj_j) {
+  Ops ops;
+  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<double> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc);
+  init_equilibrium(*p, ops, u0, v0, f.data());
+  for (int n = 0; n < nsteps; ++n) {
+    if (traj_u || traj_j)
+      for (size_t cell = 0; cell < nc; ++cell) {
+        double u = 0, jx = 0, jy = 0;
+        for (int i = 0; i < Q; ++i) {
+          u += f[(0 * Q + i) * nc + cell];
+          jx += EX[i] * f[(1 * Q + i) * nc + cell];
+          jy += EY[i] * f[(1 * Q + i) * nc + cell];
+        }
+        if (traj_u) traj_u[size_t(n) * nc + cell] = u;
+        if (traj_j) {
+          traj_j[(size_t(n) * 2 + 0) * nc + cell] = jx;
+          traj_j[(size_t(n) * 2 + 1) * nc + cell] = jy;
+        }
+      }
+    step<double>(*p, ops, f.data(), c, post.data(), fnew.data());
+    f.swap(fnew);
+  }
+  for (size_t cell = 0; cell < nc; ++cell) {
+    double u = 0, v = 0;
+    for (int i = 0; i < Q; ++i) {
+      u += f[(0 * Q + i) * nc + cell];
+      v += f[(1 * Q + i) * nc + cell];
+    }
+    if (uN) uN[cell] = u;
+    if (vN) vN[cell] = v;
+  }
+  if (state) std::memcpy(state, f.data(), sizeof(double) * 2 * Q * nc);
+  return 0;
+}
+
+// Cost (classicJ) on fluid nodes: J = 1/2 sum (uN - ut)^2 + alpha/2 sum c^2.
+double orc_cost(const OrcProblem* p, const double* uN, const double* ut,
+                const double* c, double* J_track, double* J_reg) {
+  const size_t nc = size_t(p->nx) * p->ny;
+  double jt = 0.0, jr = 0.0;
+  for (size_t cell = 0; cell < nc; ++cell) {
+    if (p->solid && p->solid[cell]) continue;
+    double d = uN[cell] - ut[cell];
+    jt += 0.5 * d * d;
+    if (c) jr += 0.5 * p->alpha * c[cell] * c[cell];
+  }
+  if (J_track) *J_track = jt;
+  if (J_reg) *J_reg = jr;
+  return jt + jr;
+}
+
+// Discrete adjoint sweep (AMRT) with terminal condition
+// psi_u,i(T) = seed_u, psi_v,i(T) = seed_v (seed_v may be NULL = 0).
+// Outputs g[cell] = sum_n tau sum_i w_i psi_v,i (the adjoint part of the
+// gradient w.r.t. the control; the control enters Phi_u instead when
+// control_on_u), and optionally dJ/du0, dJ/dv0 through the equilibrium
+// initialisation.
+int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
+                const double* v0, const double* c, const double* seed_u,
+                const double* seed_v, double* g, double* du0, double* dv0) {
+  Ops ops;
+  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<double> f, traj;
+  run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
+  std::vector<double> lam(2 * Q * nc, 0.0), nu(2 * Q * nc, 0.0);
+  for (size_t cell = 0; cell < nc; ++cell) {
+    if (p->solid && p->solid[cell]) continue;
+    for (int i = 0; i < Q; ++i) {
+      lam[(0 * Q + i) * nc + cell] = seed_u[cell];
+      lam[(1 * Q + i) * nc + cell] = seed_v ? seed_v[cell] : 0.0;
+    }
+  }
+  for (size_t cell = 0; cell < nc; ++cell) g[cell] = 0.0;
+  const int cs = p->control_on_u ? 0 : 1;
+  for (int n = nsteps - 1; n >= 0; --n) {
+    // Adjoint streaming along -e_i (transpose of push + bounce-back):
+    // nu_i(x) = lambda_i(x + e_i) if x + e_i is fluid, else lambda_opp(i)(x).
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int cell = y * p->nx + x;
+        if (p->solid && p->solid[cell]) continue;
+        for (int s = 0; s < 2; ++s)
+          for (int i = 0; i < Q; ++i) {
+            int nb = neighbour(*p, x, y, i, +1);
+            nu[(s * Q + i) * nc + cell] =
+                nb >= 0 ? lam[(s * Q + i) * nc + nb]
+                        : lam[(s * Q + ops.opp[i]) * nc + cell];
+          }
+      }
+    const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int cell = y * p->nx + x;
+        if (p->solid && p->solid[cell]) continue;
+        double loc[2 * Q], nl[2 * Q], out[2 * Q];
+        for (int k = 0; k < 2 * Q; ++k) {
+          loc[k] = fn[k * nc + cell];
+          nl[k] = nu[k * nc + cell];
+        }
+        // (gradientLattice): dF_Theta,i/dc = tau w_i.
+        double gc = 0.0;
+        for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * TAU * WGT[i];
+        g[cell] += gc;
+        local_adjoint(*p, ops, loc, nl, out);
+        for (int k = 0; k < 2 * Q; ++k) lam[k * nc + cell] = out[k];
+      }
+  }
+  // Transpose of the equilibrium initialisation phi_i^0 = weq_i Theta_0.
+  for (size_t cell = 0; cell < nc; ++cell) {
+    double a = 0.0, b = 0.0;
+    if (!(p->solid && p->solid[cell]))
+      for (int i = 0; i < Q; ++i) {
+        a += ops.u.weq[i] * lam[(0 * Q + i) * nc + cell];
+        b += ops.v.weq[i] * lam[(1 * Q + i) * nc + cell];
+      }
+    if (du0) du0[cell] = a;
+    if (dv0) dv0[cell] = b;
+  }
+  return 0;
+}
+
+// Sensitivity LBE (LIBEG-V), forward mode: directional derivative of
+// (u^N, v^N) for a perturbation (dc, du0, dv0) (any may be NULL = 0).
+int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
+            const double* v0, const double* c, const double* dc,
+            const double* du0, const double* dv0, double* duN, double* dvN) {
+  Ops ops;
+  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<double> f, traj;
+  run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
+  std::vector<double> d(2 * Q * nc, 0.0), dpost(2 * Q * nc), dnew(2 * Q * nc);
+  for (size_t cell = 0; cell < nc; ++cell) {
+    if (p->solid && p->solid[cell]) continue;
+    for (int i = 0; i < Q; ++i) {
+      d[(0 * Q + i) * nc + cell] = du0 ? ops.u.weq[i] * du0[cell] : 0.0;
+      d[(1 * Q + i) * nc + cell] = dv0 ? ops.v.weq[i] * dv0[cell] : 0.0;
+    }
+  }
+  const int cs = p->control_on_u ? 0 : 1;
+  const int N2 = 2 * Q;
+  for (int n = 0; n < nsteps; ++n) {
+    const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int cell = y * p->nx + x;
+        if (p->solid && p->solid[cell]) {
+          for (int k = 0; k < N2; ++k) dpost[k * nc + cell] = 0.0;
+          continue;
+        }
+        double loc[N2], Jac[N2 * N2];
+        for (int k = 0; k < N2; ++k) loc[k] = fn[k * nc + cell];
+        local_jacobian(*p, ops, loc, Jac);
+        for (int r = 0; r < N2; ++r) {
+          double acc = 0.0;
+          for (int k = 0; k < N2; ++k) acc += Jac[r * N2 + k] * d[k * nc + cell];
+          dpost[r * nc + cell] = acc;
+        }
+        if (dc)
+          for (int i = 0; i < Q; ++i)
+            dpost[(cs * Q + i) * nc + cell] += TAU * WGT[i] * dc[cell];
+      }
+    std::fill(dnew.begin(), dnew.end(), 0.0);
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int cell = y * p->nx + x;
+        if (p->solid && p->solid[cell]) continue;
+        for (int s = 0; s < 2; ++s)
+          for (int i = 0; i < Q; ++i) {
+            int nb = neighbour(*p, x, y, i, +1);
+            double val = dpost[(s * Q + i) * nc + cell];
+            if (nb >= 0)
+              dnew[(s * Q + i) * nc + nb] = val;
+            else
+              dnew[(s * Q + ops.opp[i]) * nc + cell] = val;
+          }
+      }
+    d.swap(dnew);
+  }
+  for (size_t cell = 0; cell < nc; ++cell) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      a += d[(0 * Q + i) * nc + cell];
+      b += d[(1 * Q + i) * nc + cell];
+    }
+    if (duN) duN[cell] = a;
+    if (dvN) dvN[cell] = b;
+  }
+  return 0;
+}
+
+// Complex-step evaluation of J at c + i h dc: the scheme is polynomial in
+// c (bounce-back is a fixed permutation), so Im J / h is the exact
+// directional derivative up to O(h^2).
+int orc_cost_complex_step(const OrcProblem* p, int nsteps, const double* u0,
+                          const double* v0, const double* c, const double* dc,
+                          double h, const double* ut, double* J_re,
+                          double* J_im) {
+  typedef std::complex<double> cd;
+  Ops ops;
+  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<cd> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc);
+  std::vector<cd> cu0(nc), cv0(nc), cc(nc);
+  for (size_t k = 0; k < nc; ++k) {
+    cu0[k] = u0[k];
+    cv0[k] = v0[k];
+    cc[k] = cd(c[k], h * dc[k]);
+  }
+  init_equilibrium<cd>(*p, ops, cu0.data(), cv0.data(), f.data());
+  for (int n = 0; n < nsteps; ++n) {
+    step<cd>(*p, ops, f.data(), cc.data(), post.data(), fnew.data());
+    f.swap(fnew);
+  }
+  cd J = 0.0;
+  for (size_t cell = 0; cell < nc; ++cell) {
+    if (p->solid && p->solid[cell]) continue;
+    cd u = 0.0;
+    for (int i = 0; i < Q; ++i) u += f[(0 * Q + i) * nc + cell];
+    cd dd = u - ut[cell];
+    J += 0.5 * dd * dd + 0.5 * p->alpha * cc[cell] * cc[cell];
+  }
+  *J_re = J.real();
+  *J_im = J.imag();
+  return 0;
+}
+
+// Full gradient (gradientLattice) of J: E = g + alpha c on fluid nodes and
+// 0 on solid nodes, from the adjoint seeded with dI0/dphi_u,i = u^N - u_t.
+// Also returns J and its two parts.
+int orc_cost_gradient(const OrcProblem* p, int nsteps, const double* u0,
+                      const double* v0, const double* c, const double* ut,
+                      double* grad, double* J, double* J_track, double* J_reg,
+                      double* uN_out) {
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<double> uN(nc), vN(nc), seed(nc, 0.0);
+  int rc = orc_forward(p, nsteps, u0, v0, c, uN.data(), vN.data(), nullptr,
+                       nullptr, nullptr);
+  if (rc) return rc;
+  *J = orc_cost(p, uN.data(), ut, c, J_track, J_reg);
+  for (size_t cell = 0; cell < nc; ++cell)
+    if (!(p->solid && p->solid[cell])) seed[cell] = uN[cell] - ut[cell];
+  rc = orc_adjoint(p, nsteps, u0, v0, c, seed.data(), nullptr, grad, nullptr,
+                   nullptr);
+  if (rc) return rc;
+  for (size_t cell = 0; cell < nc; ++cell)
+    grad[cell] = (p->solid && p->solid[cell]) ? 0.0 : grad[cell] + p->alpha * c[cell];
+  if (uN_out) std::memcpy(uN_out, uN.data(), sizeof(double) * nc);
+  return 0;
+}
+
+// Gradient step (Step 5): c <- clamp(c - zeta E, lo, hi); zeta <= 0 selects
+// the heuristic zeta = min(1, 1/||E||_inf).  Returns the zeta used.
+double orc_gd_step(int n, double* c, const double* E, double zeta, double lo,
+                   double hi) {
+  if (zeta <= 0.0) {
+    double emax = 0.0;
+    for (int k = 0; k < n; ++k) emax = std::fmax(emax, std::fabs(E[k]));
+    zeta = emax > 0.0 ? std::fmin(1.0, 1.0 / emax) : 1.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    double x = c[k] - zeta * E[k];
+    if (x < lo) x = lo;
+    if (x > hi) x = hi;
+    c[k] = x;
+  }
+  return zeta;
+}
+
+}  // extern "C"

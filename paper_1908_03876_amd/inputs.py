@@ -1,0 +1,288 @@
+"""Seeded synthetic inputs for the chemotaxis optimal-control workloads.
+
+This module is shared by the CPU oracle tests, the GPU parity tests and the
+benchmark.  It only draws random fields and parameters (initial states,
+obstacle masks, diffusion tensors, targets, controls); it contains none of the
+lattice Boltzmann arithmetic.  Everything is generated in float64 with
+``numpy.random.default_rng(seed)`` and cast by the caller.
+
+Problem statement followed (Section 1, eq. (ReacDiff) and (classicJ)):
+two species, cell density u and chemical v, on a 2-D lattice,
+
+    du/dt - div(D_u grad u) = r_u u (1 - u) - div(chi u C_chi grad v)
+    dv/dt - div(D_v grad v) = a_uv u - b_v v + c(x)
+
+with a static distributed control c on the v equation and the terminal
+tracking cost 1/2 ||u(T) - u_target||^2 + alpha/2 ||c||^2 (Section 2.1,
+(classicJ) with a_1 = 1 and a quadratic control penalty).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    """One control problem instance (lattice units: h = tau = 1)."""
+
+    nx: int
+    ny: int
+    nsteps: int
+    periodic: bool
+    solid: Optional[np.ndarray]  # uint8 [ny, nx], 1 = solid, or None
+    Du: np.ndarray               # 2x2 self-diffusion tensor of u
+    Dv: np.ndarray               # 2x2 self-diffusion tensor of v
+    chi: float                   # chemotactic sensitivity
+    Cchi: np.ndarray             # 2x2 shape of the chemotactic tensor
+    r_u: float = 1.0             # logistic rate of u
+    a_uv: float = 1.0            # production of v by u
+    b_v: float = 1.0             # decay of v
+    alpha: float = 1e-3          # control penalty weight
+    du: float = 1.0              # equilibrium parameter d_u
+    dv: float = 1.0              # equilibrium parameter d_v
+    su: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(7))
+    sv: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(7))
+    u0: np.ndarray = None        # [ny, nx]
+    v0: np.ndarray = None        # [ny, nx]
+    control: np.ndarray = None   # [ny, nx], initial guess of c
+    u_target: np.ndarray = None  # [ny, nx]
+    name: str = ""
+
+    @property
+    def fluid(self) -> np.ndarray:
+        if self.solid is None:
+            return np.ones((self.ny, self.nx), dtype=bool)
+        return self.solid == 0
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.fluid.sum())
+
+    def copy(self, **changes) -> "Problem":
+        p = dataclasses.replace(self, **changes)
+        for f in ("solid", "Du", "Dv", "Cchi", "su", "sv", "u0", "v0",
+                  "control", "u_target"):
+            val = getattr(p, f)
+            if isinstance(val, np.ndarray) and f not in changes:
+                setattr(p, f, val.copy())
+        return p
+
+
+# ---------------------------------------------------------------- helpers
+
+def random_spd(rng: np.random.Generator, lo: float = 0.05, hi: float = 1.0,
+               rmax: float = 0.3) -> np.ndarray:
+    """Symmetric tensor with diagonal ~ U[lo, hi] and off-diagonal
+    r*sqrt(D11*D22), r ~ U(-rmax, rmax): positive definite for rmax < 1."""
+    d1, d2 = rng.uniform(lo, hi, size=2)
+    r = rng.uniform(-rmax, rmax)
+    off = r * np.sqrt(d1 * d2)
+    return np.array([[d1, off], [off, d2]], dtype=np.float64)
+
+
+def periodic_sqdist(nx: int, ny: int, x0: float, y0: float) -> np.ndarray:
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    dx = np.abs(x[None, :] - x0)
+    dy = np.abs(y[:, None] - y0)
+    dx = np.minimum(dx, nx - dx)
+    dy = np.minimum(dy, ny - dy)
+    return dx * dx + dy * dy
+
+
+def plain_sqdist(nx: int, ny: int, x0: float, y0: float) -> np.ndarray:
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    return (x[None, :] - x0) ** 2 + (y[:, None] - y0) ** 2
+
+
+def gaussian_bumps(nx: int, ny: int, centres, sigmas, amps,
+                   periodic: bool) -> np.ndarray:
+    out = np.zeros((ny, nx), dtype=np.float64)
+    dist = periodic_sqdist if periodic else plain_sqdist
+    for (cx, cy), s, a in zip(centres, sigmas, amps):
+        out += a * np.exp(-dist(nx, ny, cx, cy) / (2.0 * s * s))
+    return out
+
+
+def disk_mask(nx: int, ny: int, rng: np.random.Generator, n_disks: int,
+              rmin: int, rmax: int, ring: bool = True) -> np.ndarray:
+    """uint8 mask, 1 = solid: union of disks (x-cx)^2+(y-cy)^2 <= r^2 on
+    integer cell coordinates (no wrap), plus a one-cell solid outer ring."""
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    cx = rng.uniform(0, nx, size=n_disks)
+    cy = rng.uniform(0, ny, size=n_disks)
+    rr = rng.integers(rmin, rmax + 1, size=n_disks)
+    for x0, y0, r in zip(cx, cy, rr):
+        xl, xh = max(int(np.floor(x0 - r)), 0), min(int(np.ceil(x0 + r)) + 1, nx)
+        yl, yh = max(int(np.floor(y0 - r)), 0), min(int(np.ceil(y0 + r)) + 1, ny)
+        if xl >= xh or yl >= yh:
+            continue
+        xs = np.arange(xl, xh, dtype=np.float64)
+        ys = np.arange(yl, yh, dtype=np.float64)
+        inside = (xs[None, :] - x0) ** 2 + (ys[:, None] - y0) ** 2 <= float(r) ** 2
+        solid[yl:yh, xl:xh] |= inside.astype(np.uint8)
+    if ring:
+        solid[0, :] = 1
+        solid[-1, :] = 1
+        solid[:, 0] = 1
+        solid[:, -1] = 1
+    return solid
+
+
+def noisy_initial_u(nx: int, ny: int, rng: np.random.Generator,
+                    amp: float = 0.1) -> np.ndarray:
+    return 1.0 + amp * rng.uniform(-1.0, 1.0, size=(ny, nx))
+
+
+def random_bump_control(nx: int, ny: int, rng: np.random.Generator,
+                        kmin: int = 1, kmax: int = 8, smin: float = 4.0,
+                        smax: float = 32.0, amax: float = 5.0,
+                        periodic: bool = True) -> np.ndarray:
+    """Sum of K ~ U{kmin..kmax} Gaussian bumps with uniform centres,
+    sigma ~ U[smin, smax] and amplitude ~ U[-amax, amax]."""
+    k = int(rng.integers(kmin, kmax + 1))
+    centres = list(zip(rng.uniform(0, nx, size=k), rng.uniform(0, ny, size=k)))
+    sig = rng.uniform(smin, smax, size=k)
+    amp = rng.uniform(-amax, amax, size=k)
+    return gaussian_bumps(nx, ny, centres, sig, amp, periodic)
+
+
+def _zero_solids(p: Problem) -> Problem:
+    if p.solid is not None:
+        f = p.solid != 0
+        for name in ("u0", "v0", "control", "u_target"):
+            arr = getattr(p, name)
+            arr[f] = 0.0
+    return p
+
+
+# ---------------------------------------------------------------- workloads
+
+def cfg1(seed: int = 1, L: int = 64, nsteps: int = 200) -> Problem:
+    """Plain method, FP64: L x L periodic, isotropic D_u = 0.1, D_v = 1.0,
+    chi = 0.5, logistic u, v driven by u, zero initial control, Gaussian
+    target bump of sigma = 8 cells."""
+    rng = np.random.default_rng(seed)
+    u0 = noisy_initial_u(L, L, rng)
+    x0, y0 = rng.uniform(0, L, size=2)
+    ut = 1.0 + 0.5 * np.exp(-periodic_sqdist(L, L, x0, y0) / (2.0 * 8.0 ** 2))
+    return Problem(nx=L, ny=L, nsteps=nsteps, periodic=True, solid=None,
+                   Du=0.1 * np.eye(2), Dv=1.0 * np.eye(2), chi=0.5,
+                   Cchi=np.eye(2), u0=u0, v0=np.zeros((L, L)),
+                   control=np.zeros((L, L)), u_target=ut, name=f"cfg1_L{L}")
+
+
+def cfg2(seed: int = 2, L: int = 2048, nsteps: int = 4000,
+         n_disks: int = 200, rmin: int = 5, rmax: int = 30,
+         n_target_bumps: int = 8, target_sigma: float = 64.0) -> Problem:
+    """Plain method at scale, FP32: L x L with a bounce-back mask of random
+    disks plus a solid outer ring, full anisotropic self and chemotactic
+    tensors (diagonal in [0.05, 1], off-diagonal U(-0.3, 0.3) of the
+    geometric mean of the diagonal)."""
+    rng = np.random.default_rng(seed)
+    solid = disk_mask(L, L, rng, n_disks, rmin, rmax, ring=True)
+    Du = random_spd(rng)
+    Dv = random_spd(rng)
+    Cchi = random_spd(rng)
+    u0 = noisy_initial_u(L, L, rng)
+    cen = list(zip(rng.uniform(0, L, n_target_bumps), rng.uniform(0, L, n_target_bumps)))
+    ut = 1.0 + gaussian_bumps(L, L, cen, [target_sigma] * n_target_bumps,
+                              [0.5] * n_target_bumps, periodic=False)
+    p = Problem(nx=L, ny=L, nsteps=nsteps, periodic=False, solid=solid,
+                Du=Du, Dv=Dv, chi=0.5, Cchi=Cchi, u0=u0,
+                v0=np.zeros((L, L)), control=np.zeros((L, L)),
+                u_target=ut, name=f"cfg2_L{L}_N{nsteps}")
+    return _zero_solids(p)
+
+
+def cfg2_small(seed: int = 2, L: int = 128, nsteps: int = 200) -> Problem:
+    """The small copy of the masked anisotropic workload: same tensor
+    recipe, 4 disks of radius 3..8 cells plus the outer ring."""
+    return cfg2(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3, rmax=8,
+                n_target_bumps=2, target_sigma=L / 8.0)
+
+
+def cfg3(seed: int = 3, L: int = 2048, nsteps: int = 10000) -> Problem:
+    """Differentiation form: the masked anisotropic workload at a longer
+    horizon."""
+    if L <= 256:
+        return cfg2(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3, rmax=8,
+                    n_target_bumps=2, target_sigma=L / 8.0)
+    return cfg2(seed=seed, L=L, nsteps=nsteps)
+
+
+def cfg4(seed: int = 4, n: int = 96, nsteps: int = 2000,
+         sizes=(128, 256, 384, 512, 768, 1024)) -> List[Problem]:
+    """Batched form: n independent periodic problems of uneven square size,
+    per-instance chi ~ U[0.1, 1], seeded tensors and one target bump of
+    sigma = L/8."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        L = int(rng.choice(sizes))
+        Du, Dv, Cchi = random_spd(rng), random_spd(rng), random_spd(rng)
+        chi = float(rng.uniform(0.1, 1.0))
+        u0 = noisy_initial_u(L, L, rng)
+        x0, y0 = rng.uniform(0, L, size=2)
+        ut = 1.0 + 0.5 * np.exp(-periodic_sqdist(L, L, x0, y0) / (2.0 * (L / 8.0) ** 2))
+        out.append(Problem(nx=L, ny=L, nsteps=nsteps, periodic=True, solid=None,
+                           Du=Du, Dv=Dv, chi=chi, Cchi=Cchi, u0=u0,
+                           v0=np.zeros((L, L)), control=np.zeros((L, L)),
+                           u_target=ut, name=f"cfg4_{k}_L{L}"))
+    return out
+
+
+def with_control_bump(p: Problem, seed: int = 11, amp: float = 5.0,
+                      sigma: float = None) -> Problem:
+    """Copy of p with a non-zero control (one Gaussian bump), so that the
+    state is not driven to the trivial fixed point u = v = 1."""
+    rng = np.random.default_rng(seed)
+    sigma = sigma if sigma is not None else max(p.nx, p.ny) / 8.0
+    cx, cy = rng.uniform(0, p.nx), rng.uniform(0, p.ny)
+    c = gaussian_bumps(p.nx, p.ny, [(cx, cy)], [sigma], [amp], p.periodic)
+    q = p.copy(control=c)
+    return _zero_solids(q)
+
+
+def slow_reaction(p: Problem, rate: float = 0.01) -> Problem:
+    """Copy of p with slow kinetics r_u = a_uv = b_v = rate."""
+    return p.copy(r_u=rate, a_uv=rate, b_v=rate)
+
+
+def random_direction(p: Problem, seed: int) -> np.ndarray:
+    """Random perturbation h ~ N(0,1) on fluid cells, scaled to max |h| = 1."""
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((p.ny, p.nx))
+    h[~p.fluid] = 0.0
+    return h / np.abs(h).max()
+
+
+def tiny(seed: int = 5, L: int = 8, nsteps: int = 10, masked: bool = False,
+         anisotropic: bool = True) -> Problem:
+    """Small randomised instance for brute-force checks (finite differences,
+    complex step, transposition identities)."""
+    rng = np.random.default_rng(seed)
+    if anisotropic:
+        Du, Dv, Cchi = random_spd(rng), random_spd(rng), random_spd(rng)
+    else:
+        Du, Dv, Cchi = 0.1 * np.eye(2), 1.0 * np.eye(2), np.eye(2)
+    solid = None
+    if masked:
+        solid = np.zeros((L, L), dtype=np.uint8)
+        solid[0, :] = solid[-1, :] = solid[:, 0] = solid[:, -1] = 1
+        solid[L // 2, L // 2] = 1
+    u0 = 1.0 + 0.3 * rng.uniform(-1, 1, size=(L, L))
+    v0 = 0.5 * rng.uniform(0, 1, size=(L, L))
+    c = rng.uniform(-1, 1, size=(L, L))
+    ut = 1.0 + 0.5 * rng.uniform(0, 1, size=(L, L))
+    su = rng.uniform(0.8, 1.6, size=7)
+    sv = rng.uniform(0.8, 1.6, size=7)
+    p = Problem(nx=L, ny=L, nsteps=nsteps, periodic=not masked, solid=solid,
+                Du=Du, Dv=Dv, chi=0.7, Cchi=Cchi, r_u=0.3, a_uv=0.4, b_v=0.2,
+                alpha=1e-2, su=su, sv=sv, u0=u0, v0=v0, control=c,
+                u_target=ut, name=f"tiny_L{L}")
+    return _zero_solids(p)
