@@ -1,0 +1,212 @@
+/*
+ * mrt.h - C-ABI of the MI355X (gfx950) hot path for adjoint-based optimal
+ * control of a coupled anisotropic chemotaxis system with a two-species
+ * D2Q9 multiple-relaxation-time lattice Boltzmann model (MRT) and its
+ * adjoint (AMRT).
+ *
+ * Method: A. Belmiloudi, "Optimal Control for Chemotaxis Systems and
+ * Adjoint-Based Optimization with Multiple-Relaxation-Time Lattice Boltzmann
+ * Models", arXiv:1908.03876 (equation labels below are the paper's).
+ *
+ * Problem solved (Section 1, (ReacDiff) with two species u = cells,
+ * v = chemical, null-flux walls (E2) as halfway bounce-back):
+ *   du/dt - div(D_u grad u) = r_u u (1-u) - div(chi u C_chi grad v)
+ *   dv/dt - div(D_v grad v) = a_uv u - b_v v + c(x)
+ * with a static distributed control c(x) on the v equation, and the cost
+ * (classicJ) J(c) = 1/2 sum (u(T) - u_target)^2 + alpha/2 sum c^2 over the
+ * fluid nodes.  Lattice units: h = tau = 1, Cs^2 = 1/3 (Section 3.1).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer unless marked "host".  The
+ *     caller allocates and owns it; the library never frees it.
+ *   - Fields are [ny][pitch] row-major, element (x, y) at y*pitch + x.
+ *     Only x < nx is read or written.
+ *   - Floating-point fields have the grid's dtype (MRT_F32: float,
+ *     MRT_F64: double), except grad_accum, which is always double.
+ *   - The distribution state is SoA: population i of species s (0 = u,
+ *     1 = v) of node (x, y) is at ((s*9 + i)*ny + y)*pitch + x, with the D2Q9
+ *     velocity order e0 = 0, e1 = (1,0), e2 = (0,1), e3 = -e1, e4 = -e2,
+ *     e5 = (1,1), e6 = (-1,1), e7 = -e5, e8 = -e6 (Remark on DmQq lattices).
+ *   - Solid nodes (mask = 1) carry no populations: every output is 0 there.
+ *   - Asynchronous calls enqueue work on `stream` (a hipStream_t; NULL is the
+ *     default stream) and return at once.  Calls that return host scalars
+ *     synchronise that stream.
+ *   - Return codes: MRT_OK or a negative MRT_E*; mrt_last_error() gives a
+ *     thread-local message.  On an error no work has been enqueued, except
+ *     MRT_EHIP (a HIP call failed) and MRT_ENONFINITE (work done, result
+ *     not finite).
+ *   - Calls are re-entrant given distinct tapes; one tape must not be used
+ *     by two calls at the same time.
+ */
+#ifndef MRT_H
+#define MRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MRT_OK = 0,
+  MRT_EINVAL = -1,     /* invalid argument or parameter set */
+  MRT_ENOMEM = -2,     /* device allocation failed or over the budget */
+  MRT_EHIP = -3,       /* a HIP runtime call failed */
+  MRT_ENONFINITE = -4, /* a reduced scalar is NaN or Inf */
+  MRT_ESTATE = -5      /* tape does not match the problem or call order */
+};
+
+enum { MRT_F32 = 0, MRT_F64 = 1 };
+
+/* Lattice (Section 3.1: uniform grid of spacing h, time step tau = T/N,
+ * DmQq velocity set). */
+typedef struct mrt_grid {
+  int32_t nx, ny;   /* nodes per axis, 1..32768 */
+  int32_t pitch;    /* row stride of every field, in elements, >= nx */
+  int32_t q;        /* velocity set size; must be 9 (D2Q9) */
+  int32_t periodic; /* 1: periodic wrap; 0: outside the grid is a wall */
+  int32_t dtype;    /* MRT_F32 or MRT_F64 */
+  int32_t nsteps;   /* N time steps, >= 1 */
+  int32_t reserved; /* must be 0 */
+  const uint8_t* mask; /* device [ny][pitch], 1 = solid node; NULL = none */
+} mrt_grid;
+
+/* One species Theta (Section 3.1): self-diffusion tensor D_Theta, the
+ * equilibrium parameter d_Theta of (phieq) and the free relaxation rates of
+ * Pi_Theta = diag(Lambda1, Lambda2, Lambda3): s[0..2] on (rho, e, epsilon),
+ * s[3] on q_x, s[4] on q_y, s[5] on p_xx, s[6] on p_xy.  The 2x2 block K
+ * coupling j_x and j_y follows from D_Theta = d_Theta Cs^2 tau (K^-1 - I/2)
+ * (end of the proof of Proposition 1). */
+typedef struct mrt_species {
+  double D[4];  /* row-major 2x2, symmetric positive definite */
+  double d;     /* > 0 */
+  double s[7];  /* each in (0, 2) */
+} mrt_species;
+
+/* The control problem.  Cross-diffusion of u by v is the chemotactic tensor
+ * D_{u,1} = chi u Cchi (example (ARC)); D_{v,1} = 0. */
+typedef struct mrt_problem {
+  mrt_grid grid;
+  mrt_species u, v;
+  double chi;      /* chemotactic sensitivity */
+  double Cchi[4];  /* row-major 2x2 shape of the chemotactic tensor */
+  double r_u;      /* Phi_u = r_u u (1 - u) */
+  double a_uv;     /* Phi_v = a_uv u - b_v v + c */
+  double b_v;
+  double alpha;    /* control penalty weight, >= 0 */
+} mrt_problem;
+
+/* Reduced scalars returned by cost_gradient (host struct). */
+typedef struct mrt_scalars {
+  double J;        /* J_track + J_reg */
+  double J_track;  /* 1/2 sum_F (u^N - u_target)^2 */
+  double J_reg;    /* alpha/2 sum_F c^2 */
+  double grad_inf; /* ||E||_inf (phase 2 only, else 0) */
+  double grad_l2;  /* ||E||_2   (phase 2 only, else 0) */
+  int64_t n_fluid; /* number of fluid nodes */
+} mrt_scalars;
+
+/* Description of a tape (host struct). */
+typedef struct mrt_tape_info {
+  int32_t mode;        /* 0 forward only, 1 store-all, 2 checkpointed */
+  int32_t ckpt_every;  /* segment length K in steps */
+  int32_t n_segments;  /* ceil(N / K) */
+  int32_t reserved;
+  int64_t n_fluid;     /* fluid nodes */
+  size_t device_bytes; /* device memory held by the tape */
+} mrt_tape_info;
+
+typedef struct mrt_tape mrt_tape;
+
+/* Host-only check of a problem (no device call).  Returns MRT_EINVAL when
+ * q != 9, nx or ny outside 1..32768, pitch < nx, nsteps < 1, dtype unknown,
+ * a D not symmetric positive definite, d <= 0, a rate outside (0, 2), a
+ * non-finite coefficient or alpha < 0 (Remark on the CFL-type condition of
+ * the explicit scheme: the derived K must have eigenvalues in (0, 2)). */
+int mrt_validate(const mrt_problem* p);
+
+/* Host-only: device bytes a tape for `p` with segment length ckpt_every
+ * would hold (ckpt_every: 0 forward only, >= nsteps store-all, else
+ * checkpoints every ckpt_every steps). */
+int mrt_tape_bytes(const mrt_problem* p, int32_t ckpt_every, size_t* bytes);
+
+/* Create the device workspace of a problem: ping-pong distribution
+ * buffers, the link mask built from grid.mask, reduction buffers and, for
+ * the adjoint, the trajectory tape.  The forward records the quantities the
+ * adjoint needs (u and the first moment j_v of every node and step, the
+ * state trajectory being an input of the backward solve, Section 3); when
+ * the whole record does not fit, states are checkpointed every ckpt_every
+ * steps and segments are recomputed in the adjoint.  mem_budget > 0 makes
+ * the call fail with MRT_ENOMEM if the tape would need more device bytes.
+ * The library owns the tape's memory; grid.mask is read here only. */
+int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
+                    size_t mem_budget, mrt_tape** out);
+void mrt_tape_destroy(mrt_tape* t);
+int mrt_tape_query(const mrt_tape* t, mrt_tape_info* info /* host */);
+
+/* Forward MRT solve (eq:LBEG with the sources (S), (PhiS); collision (MC) in
+ * moment space (MF); streaming with halfway bounce-back), N steps from the
+ * equilibrium of (u0, v0) (phieq).  Writes u^N, v^N after the last
+ * streaming and, if `state` is not NULL, the distribution state [2][9][ny]
+ * [pitch].  u^N / v^N may be NULL.  Records the adjoint tape when the tape
+ * was created for the adjoint.  Asynchronous. */
+int mrt_forward(const mrt_problem* p, mrt_tape* t, const void* u0,
+                const void* v0, const void* control, void* state, void* uN,
+                void* vN, void* stream);
+
+/* Adjoint MRT sweep (CAE, AEDs, RFS1; streaming along -e_i backward in time,
+ * CAEL) of the last mrt_forward on this tape, from the terminal condition
+ * psi_u,i(T) = seed_u, psi_v,i(T) = seed_v (seed_v NULL = 0), i.e. the
+ * gradient of a terminal functional of u^N, v^N.  u0, v0, control must be
+ * the same buffers (and contents) as in that forward call (they seed the
+ * segment recomputation).  Writes grad_accum[ny][pitch] (double) =
+ * sum_n tau sum_i w_i psi_v,i, the adjoint part of the gradient
+ * (gradientLattice), overwriting it.  If adj_u0 / adj_v0 are not NULL they
+ * receive dJ/du0 and dJ/dv0 (transpose of the equilibrium initialisation).
+ * MRT_ESTATE if the tape has no adjoint record or no forward ran.
+ * Asynchronous. */
+int amrt_adjoint(const mrt_problem* p, mrt_tape* t, const void* u0,
+                 const void* v0, const void* control, const void* seed_u,
+                 const void* seed_v, double* grad_accum, void* adj_u0,
+                 void* adj_v0, void* stream);
+
+/* Cost and gradient reduction (classicJ, EJD-H terminal term, gradient
+ * (gradientLattice)).  Phase 1 (grad_accum NULL): J, J_track, J_reg over the
+ * fluid nodes and, if seed_out is not NULL, the adjoint seed
+ * seed_out = u^N - u_target (0 on solids).  Phase 2 (grad_accum given): also
+ * grad_out = grad_accum + alpha * control on fluid nodes (0 on solids) and
+ * its norms.  Reductions are in double, deterministic (fixed order).
+ * Synchronises `stream`; MRT_ENONFINITE if a scalar is NaN or Inf. */
+int cost_gradient(const mrt_problem* p, mrt_tape* t, const void* uN,
+                  const void* u_target, const void* control,
+                  const double* grad_accum, void* seed_out, void* grad_out,
+                  mrt_scalars* out /* host */, void* stream);
+
+/* Gradient step (Section 2.3, Step 5): control <- clamp(control - zeta *
+ * grad, lo, hi) on fluid nodes.  zeta <= 0 selects the heuristic step
+ * zeta = min(1, 1/||grad||_inf) (Remark after Step 6), computed on the
+ * device.  lo/hi = -/+INFINITY for no box constraint.  If zeta_used is not
+ * NULL the stream is synchronised and the step used is returned there. */
+int gd_step(const mrt_problem* p, mrt_tape* t, void* control,
+            const void* grad, double zeta, double lo, double hi,
+            double* zeta_used /* host, NULL ok */, void* stream);
+
+/* Thread-local text of the last error. */
+const char* mrt_last_error(void);
+
+/* Kernel timing with HIP events recorded on the caller's stream around the
+ * step loops.  kind: 0 forward steps, 1 adjoint steps, 2 recompute steps.
+ * mrt_timing_read synchronises on the recorded events and returns the
+ * summed milliseconds and the number of kernel launches since the last
+ * reset. */
+int mrt_timing_enable(int32_t on);
+int mrt_timing_reset(void);
+int mrt_timing_read(int32_t kind, double* ms /* host */,
+                    int64_t* launches /* host */);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRT_H */

@@ -1,0 +1,194 @@
+"""ctypes binding of the C-ABI in include/mrt.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device
+memory comes from torch tensors (``data_ptr()``), streams from
+``torch.cuda.current_stream().cuda_stream``.  All computation runs in the
+HIP kernels of libmrt.so; if the library is missing this module raises at
+import time - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmrt.so")
+
+MRT_OK, MRT_EINVAL, MRT_ENOMEM, MRT_EHIP, MRT_ENONFINITE, MRT_ESTATE = 0, -1, -2, -3, -4, -5
+MRT_F32, MRT_F64 = 0, 1
+TIMING_FORWARD, TIMING_ADJOINT, TIMING_RECOMPUTE = 0, 1, 2
+
+
+class MrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class mrt_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("nsteps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mask", ctypes.c_void_p)]
+
+
+class mrt_species(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double * 4), ("d", ctypes.c_double),
+                ("s", ctypes.c_double * 7)]
+
+
+class mrt_problem(ctypes.Structure):
+    _fields_ = [("grid", mrt_grid), ("u", mrt_species), ("v", mrt_species),
+                ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 4),
+                ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
+                ("b_v", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class mrt_scalars(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_double), ("J_track", ctypes.c_double),
+                ("J_reg", ctypes.c_double), ("grad_inf", ctypes.c_double),
+                ("grad_l2", ctypes.c_double), ("n_fluid", ctypes.c_int64)]
+
+
+class mrt_tape_info(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
+                ("n_segments", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_fluid", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
+           "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
+           "cost_gradient", "gd_step", "mrt_last_error", "mrt_timing_enable",
+           "mrt_timing_reset", "mrt_timing_read"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1908_03876_amd.build`")
+    # torch first, so that libmrt.so binds to the HIP runtime torch loaded
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(mrt_problem)
+    vp = ctypes.c_void_p
+    L.mrt_validate.argtypes = [P]
+    L.mrt_tape_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.mrt_tape_create.argtypes = [P, ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.mrt_tape_destroy.argtypes = [vp]
+    L.mrt_tape_destroy.restype = None
+    L.mrt_tape_query.argtypes = [vp, ctypes.POINTER(mrt_tape_info)]
+    L.mrt_forward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.amrt_adjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cost_gradient.argtypes = [P, vp, vp, vp, vp, vp, vp, vp,
+                                ctypes.POINTER(mrt_scalars), vp]
+    L.gd_step.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_last_error.restype = ctypes.c_char_p
+    L.mrt_timing_enable.argtypes = [ctypes.c_int32]
+    L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int64)]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != MRT_OK:
+        raise MrtError(rc, lib.mrt_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ----------------------------------------------------------- entry points
+
+def mrt_validate(p: mrt_problem) -> None:
+    _check(lib.mrt_validate(ctypes.byref(p)))
+
+
+def mrt_tape_bytes(p: mrt_problem, ckpt_every: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.mrt_tape_bytes(ctypes.byref(p), int(ckpt_every), ctypes.byref(n)))
+    return n.value
+
+
+def mrt_tape_create(p: mrt_problem, ckpt_every: int, mem_budget: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.mrt_tape_create(ctypes.byref(p), int(ckpt_every), int(mem_budget),
+                               ctypes.byref(h)))
+    return h
+
+
+def mrt_tape_destroy(tape) -> None:
+    lib.mrt_tape_destroy(tape)
+
+
+def mrt_tape_query(tape) -> mrt_tape_info:
+    info = mrt_tape_info()
+    _check(lib.mrt_tape_query(tape, ctypes.byref(info)))
+    return info
+
+
+def mrt_forward(p, tape, u0, v0, control, state=None, uN=None, vN=None,
+                stream=None) -> None:
+    _check(lib.mrt_forward(ctypes.byref(p), tape, _ptr(u0), _ptr(v0),
+                           _ptr(control), _ptr(state), _ptr(uN), _ptr(vN),
+                           _stream(stream)))
+
+
+def amrt_adjoint(p, tape, u0, v0, control, seed_u, seed_v, grad_accum,
+                 adj_u0=None, adj_v0=None, stream=None) -> None:
+    _check(lib.amrt_adjoint(ctypes.byref(p), tape, _ptr(u0), _ptr(v0),
+                            _ptr(control), _ptr(seed_u), _ptr(seed_v),
+                            _ptr(grad_accum), _ptr(adj_u0), _ptr(adj_v0),
+                            _stream(stream)))
+
+
+def cost_gradient(p, tape, uN, u_target, control, grad_accum=None,
+                  seed_out=None, grad_out=None, stream=None) -> dict:
+    s = mrt_scalars()
+    _check(lib.cost_gradient(ctypes.byref(p), tape, _ptr(uN), _ptr(u_target),
+                             _ptr(control), _ptr(grad_accum), _ptr(seed_out),
+                             _ptr(grad_out), ctypes.byref(s), _stream(stream)))
+    return {"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
+            "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid}
+
+
+def gd_step(p, tape, control, grad, zeta=0.0, lo=-math.inf, hi=math.inf,
+            want_zeta=True, stream=None):
+    z = ctypes.c_double(0.0)
+    _check(lib.gd_step(ctypes.byref(p), tape, _ptr(control), _ptr(grad),
+                       float(zeta), float(lo), float(hi),
+                       ctypes.byref(z) if want_zeta else None, _stream(stream)))
+    return z.value if want_zeta else None
+
+
+def mrt_timing_enable(on: bool) -> None:
+    _check(lib.mrt_timing_enable(1 if on else 0))
+
+
+def mrt_timing_reset() -> None:
+    _check(lib.mrt_timing_reset())
+
+
+def mrt_timing_read(kind: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.mrt_timing_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

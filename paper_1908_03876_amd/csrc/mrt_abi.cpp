@@ -1,0 +1,725 @@
+// C-ABI runtime of the MRT/AMRT hot path: parameter validation, the
+// device workspace ("tape"), the forward / adjoint step loops with the
+// checkpoint schedule, reductions and the gradient step.  See include/mrt.h
+// for the contract of every entry point.
+#include "mrt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mrt_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(MRT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;  // 3 Cs^2 = c^2, c = 1
+constexpr double kTau = 1.0;
+
+bool finite_all(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// K = (D/(d Cs^2 tau) + I/2)^-1, from D = d Cs^2 tau (K^-1 - I/2).
+void k_block(const mrt_species& s, double K[4]) {
+  const double f = 1.0 / (s.d * kCs2 * kTau);
+  const double a = s.D[0] * f + 0.5, b = s.D[1] * f;
+  const double c = s.D[2] * f, e = s.D[3] * f + 0.5;
+  const double det = a * e - b * c;
+  K[0] = e / det;
+  K[1] = -b / det;
+  K[2] = -c / det;
+  K[3] = a / det;
+}
+
+int check_species(const mrt_species& s, const char* name) {
+  if (!finite_all(s.D, 4) || !std::isfinite(s.d) || !finite_all(s.s, 7))
+    return fail(MRT_EINVAL, "species %s: non-finite coefficient", name);
+  const double scale = std::max({std::fabs(s.D[0]), std::fabs(s.D[3]), 1e-300});
+  if (std::fabs(s.D[1] - s.D[2]) > 1e-12 * scale)
+    return fail(MRT_EINVAL, "species %s: D must be symmetric", name);
+  if (!(s.D[0] > 0.0) || !(s.D[0] * s.D[3] - s.D[1] * s.D[2] > 0.0))
+    return fail(MRT_EINVAL, "species %s: D must be positive definite", name);
+  if (!(s.d > 0.0)) return fail(MRT_EINVAL, "species %s: d must be > 0", name);
+  for (int j = 0; j < 7; ++j)
+    if (!(s.s[j] > 0.0 && s.s[j] < 2.0))
+      return fail(MRT_EINVAL, "species %s: rate s%d = %g outside (0, 2)", name,
+                  j, s.s[j]);
+  // eigenvalues of the symmetric K lie in (0, 2) for SPD D; checked anyway
+  double K[4];
+  k_block(s, K);
+  const double tr = K[0] + K[3], det = K[0] * K[3] - K[1] * K[2];
+  const double disc = std::sqrt(std::max(0.0, 0.25 * tr * tr - det));
+  const double lmin = 0.5 * tr - disc, lmax = 0.5 * tr + disc;
+  if (!(lmin > 0.0 && lmax < 2.0))
+    return fail(MRT_EINVAL, "species %s: K eigenvalues (%g, %g) outside (0, 2)",
+                name, lmin, lmax);
+  return MRT_OK;
+}
+
+int validate(const mrt_problem* p) {
+  if (!p) return fail(MRT_EINVAL, "problem is NULL");
+  const mrt_grid& g = p->grid;
+  if (g.q != 9) return fail(MRT_EINVAL, "q = %d: only D2Q9 (q = 9)", g.q);
+  if (g.nx < 1 || g.ny < 1 || g.nx > 32768 || g.ny > 32768)
+    return fail(MRT_EINVAL, "grid %d x %d outside 1..32768", g.nx, g.ny);
+  if (g.pitch < g.nx) return fail(MRT_EINVAL, "pitch %d < nx %d", g.pitch, g.nx);
+  if (g.nsteps < 1) return fail(MRT_EINVAL, "nsteps %d < 1", g.nsteps);
+  if (g.dtype != MRT_F32 && g.dtype != MRT_F64)
+    return fail(MRT_EINVAL, "unknown dtype %d", g.dtype);
+  if (g.periodic != 0 && g.periodic != 1)
+    return fail(MRT_EINVAL, "periodic must be 0 or 1");
+  if (g.reserved != 0) return fail(MRT_EINVAL, "grid.reserved must be 0");
+  int rc = check_species(p->u, "u");
+  if (rc) return rc;
+  rc = check_species(p->v, "v");
+  if (rc) return rc;
+  const double sc[8] = {p->chi, p->Cchi[0], p->Cchi[1], p->Cchi[2],
+                        p->Cchi[3], p->r_u, p->a_uv, p->b_v};
+  if (!finite_all(sc, 8) || !std::isfinite(p->alpha))
+    return fail(MRT_EINVAL, "non-finite model coefficient");
+  if (p->alpha < 0.0) return fail(MRT_EINVAL, "alpha < 0");
+  return MRT_OK;
+}
+
+template <typename T>
+mrt::SpeciesCoef<T> species_coef(const mrt_species& s, bool transpose_k) {
+  double K[4];
+  k_block(s, K);
+  if (transpose_k) std::swap(K[1], K[2]);
+  mrt::SpeciesCoef<T> c;
+  c.s1 = T(s.s[1] / 36.0);
+  c.s2 = T(s.s[2] / 36.0);
+  c.s3 = T(s.s[3] / 12.0);
+  c.s4 = T(s.s[4] / 12.0);
+  c.s5 = T(s.s[5] / 4.0);
+  c.s6 = T(s.s[6] / 4.0);
+  c.k00 = T(K[0] / 6.0);
+  c.k01 = T(K[1] / 6.0);
+  c.k10 = T(K[2] / 6.0);
+  c.k11 = T(K[3] / 6.0);
+  // m_eq (before (BC11)) with B = d Cs^2 Theta I: e = (2d - 4) Theta,
+  // epsilon = (3 - 2d) Theta
+  c.e_eq = T(2.0 * s.d - 4.0);
+  c.eps_eq = T(3.0 - 2.0 * s.d);
+  // phi_eq = M0^-1 m_eq by shell: rest 4(2-d)/9, axis (1+d)/18,
+  // diagonal (2d-1)/36
+  c.w_rest = T(4.0 * (2.0 - s.d) / 9.0);
+  c.w_axis = T((1.0 + s.d) / 18.0);
+  c.w_diag = T((2.0 * s.d - 1.0) / 36.0);
+  return c;
+}
+
+template <typename T>
+mrt::ModelCoef<T> model_coef(const mrt_problem* p) {
+  mrt::ModelCoef<T> m;
+  m.u = species_coef<T>(p->u, false);
+  m.v = species_coef<T>(p->v, false);
+  m.ut = species_coef<T>(p->u, true);
+  m.vt = species_coef<T>(p->v, true);
+  // A_u1 grad v = (K_u chi u Cchi / tau) (-K_v j_v / (tau d_v Cs^2))
+  //             = u * B * j_v
+  double Ku[4], Kv[4], KC[4], B[4];
+  k_block(p->u, Ku);
+  k_block(p->v, Kv);
+  KC[0] = Ku[0] * p->Cchi[0] + Ku[1] * p->Cchi[2];
+  KC[1] = Ku[0] * p->Cchi[1] + Ku[1] * p->Cchi[3];
+  KC[2] = Ku[2] * p->Cchi[0] + Ku[3] * p->Cchi[2];
+  KC[3] = Ku[2] * p->Cchi[1] + Ku[3] * p->Cchi[3];
+  const double f = -p->chi / (kTau * kTau * p->v.d * kCs2);
+  B[0] = f * (KC[0] * Kv[0] + KC[1] * Kv[2]);
+  B[1] = f * (KC[0] * Kv[1] + KC[1] * Kv[3]);
+  B[2] = f * (KC[2] * Kv[0] + KC[3] * Kv[2]);
+  B[3] = f * (KC[2] * Kv[1] + KC[3] * Kv[3]);
+  m.b00 = T(B[0]);
+  m.b01 = T(B[1]);
+  m.b10 = T(B[2]);
+  m.b11 = T(B[3]);
+  m.r_u = T(p->r_u);
+  m.a_uv = T(p->a_uv);
+  m.b_v = T(p->b_v);
+  return m;
+}
+
+// ---------------------------------------------------------------- timing
+
+struct TimedSpan {
+  int kind;
+  hipEvent_t a, b;
+  int64_t launches;
+};
+
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TimedSpan> pending;
+  double ms[3] = {0, 0, 0};
+  int64_t launches[3] = {0, 0, 0};
+};
+
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+
+struct SpanGuard {
+  bool active = false;
+  TimedSpan span{};
+  hipStream_t s;
+  SpanGuard(int kind, hipStream_t st) : s(st) {
+    Timing& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return;
+    span.kind = kind;
+    if (hipEventCreate(&span.a) != hipSuccess) return;
+    if (hipEventCreate(&span.b) != hipSuccess) {
+      (void)hipEventDestroy(span.a);
+      return;
+    }
+    (void)hipEventRecord(span.a, s);
+    active = true;
+  }
+  void count() { ++span.launches; }
+  ~SpanGuard() {
+    if (!active) return;
+    (void)hipEventRecord(span.b, s);
+    Timing& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.pending.push_back(span);
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ tape
+
+struct mrt_tape {
+  int nx, ny, pitch, nsteps, dtype, periodic, masked, device;
+  int mode, K, nseg;
+  size_t plane, elem, state_bytes, rec_slot_bytes, total_bytes;
+  void* buf[2] = {nullptr, nullptr};
+  void* abuf[2] = {nullptr, nullptr};
+  std::vector<void*> ckpt;  // ckpt[s] (s >= 1): post-collision state of step sK-1
+  void* rec = nullptr;      // record slots [K][3][plane]
+  uint16_t* link = nullptr;
+  double* partials = nullptr;
+  double* result = nullptr;
+  double* host = nullptr;   // pinned
+  int64_t n_fluid = 0;
+  // last forward
+  bool fwd_done = false;
+  const void* f_u0 = nullptr;
+  const void* f_v0 = nullptr;
+  const void* f_ctrl = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+size_t elem_size(int dtype) { return dtype == MRT_F64 ? 8 : 4; }
+
+struct Layout {
+  int mode, K, nseg;
+  size_t plane, elem, state_bytes, rec_slot_bytes, total;
+};
+
+Layout plan(const mrt_problem* p, int ckpt_every) {
+  Layout L{};
+  const mrt_grid& g = p->grid;
+  L.plane = size_t(g.ny) * size_t(g.pitch);
+  L.elem = elem_size(g.dtype);
+  L.state_bytes = 18 * L.plane * L.elem;
+  L.rec_slot_bytes = 3 * L.plane * L.elem;
+  if (ckpt_every <= 0) {
+    L.mode = 0;
+    L.K = g.nsteps;
+    L.nseg = 1;
+  } else if (ckpt_every >= g.nsteps) {
+    L.mode = 1;
+    L.K = g.nsteps;
+    L.nseg = 1;
+  } else {
+    L.mode = 2;
+    L.K = ckpt_every;
+    L.nseg = (g.nsteps + ckpt_every - 1) / ckpt_every;
+  }
+  const bool masked = g.mask != nullptr || !g.periodic;
+  size_t t = 2 * L.state_bytes;  // forward ping-pong
+  if (masked) t += L.plane * sizeof(uint16_t);
+  t += (size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double);
+  if (L.mode > 0) {
+    t += 2 * L.state_bytes;                          // adjoint ping-pong
+    t += size_t(L.nseg - 1) * L.state_bytes;          // checkpoints
+    t += size_t(L.K) * L.rec_slot_bytes;              // record slots
+  }
+  L.total = t;
+  return L;
+}
+
+int check_tape(const mrt_problem* p, const mrt_tape* t) {
+  if (!t) return fail(MRT_EINVAL, "tape is NULL");
+  const mrt_grid& g = p->grid;
+  const int masked = (g.mask != nullptr || !g.periodic) ? 1 : 0;
+  if (g.nx != t->nx || g.ny != t->ny || g.pitch != t->pitch ||
+      g.nsteps != t->nsteps || g.dtype != t->dtype ||
+      g.periodic != t->periodic || masked != t->masked)
+    return fail(MRT_ESTATE, "tape was created for another grid");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
+    return fail(MRT_ESTATE, "tape belongs to device %d, current is %d",
+                t->device, dev);
+  return MRT_OK;
+}
+
+mrt::Geometry geometry(const mrt_tape* t) {
+  mrt::Geometry g;
+  g.nx = t->nx;
+  g.ny = t->ny;
+  g.pitch = t->pitch;
+  g.masked = t->masked;
+  g.plane = t->plane;
+  g.link = t->masked ? t->link : nullptr;
+  return g;
+}
+
+template <typename T>
+T* slot(const mrt_tape* t, int k) {
+  return reinterpret_cast<T*>(static_cast<char*>(t->rec) +
+                              size_t(k) * t->rec_slot_bytes);
+}
+
+int last_launch_error() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(MRT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return MRT_OK;
+}
+
+// Forward steps [n0, n1) starting from `src` (null = equilibrium of u0, v0).
+// The output of step n goes to ckpt[(n+1)/K] when that step closes a
+// segment (checkpointed mode, forward pass), else to a ping-pong buffer.
+// Returns the buffer holding the last written state through *last.
+template <typename T>
+int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
+                      const mrt::Geometry& g, int n0, int n1, const T* src,
+                      const T* u0, const T* v0, const T* ctrl, bool record,
+                      bool write_ckpt, bool skip_last_write, int kind,
+                      hipStream_t s, const T** last) {
+  SpanGuard span(kind, s);
+  const int seg = n0 / t->K;
+  for (int n = n0; n < n1; ++n) {
+    mrt::FwdLaunch<T> a;
+    a.src = src;
+    a.u0 = u0;
+    a.v0 = v0;
+    a.ctrl = ctrl;
+    a.rec = record ? slot<T>(t, n - seg * t->K) : nullptr;
+    T* dst = static_cast<T*>(t->buf[n & 1]);
+    if (write_ckpt && t->mode == 2 && (n + 1) % t->K == 0 && n + 1 < t->nsteps)
+      dst = static_cast<T*>(t->ckpt[(n + 1) / t->K]);
+    if (skip_last_write && n + 1 == n1) dst = nullptr;
+    a.dst = dst;
+    mrt::launch_forward_step<T>(g, m, a, s);
+    span.count();
+    int rc = last_launch_error();
+    if (rc) return rc;
+    src = dst;
+  }
+  *last = src;
+  return MRT_OK;
+}
+
+template <typename T>
+int forward_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
+                 const void* v0, const void* control, void* state, void* uN,
+                 void* vN, hipStream_t s) {
+  const mrt::ModelCoef<T> m = model_coef<T>(p);
+  const mrt::Geometry g = geometry(t);
+  const int N = t->nsteps;
+  const bool adj = t->mode > 0;
+  const int last_seg = t->nseg - 1;
+  const T* cur = nullptr;
+  const T* tu0 = static_cast<const T*>(u0);
+  const T* tv0 = static_cast<const T*>(v0);
+  const T* tc = static_cast<const T*>(control);
+  t->fwd_done = false;
+  int rc;
+  // segments before the last: no record; the last one records the tape
+  const int rec_start = adj ? last_seg * t->K : N;
+  if (rec_start > 0) {
+    rc = run_forward_steps<T>(t, m, g, 0, rec_start, nullptr, tu0, tv0, tc,
+                              false, true, false, 0, s, &cur);
+    if (rc) return rc;
+  }
+  if (rec_start < N) {
+    rc = run_forward_steps<T>(t, m, g, rec_start, N, cur, tu0, tv0, tc, true,
+                              true, false, 0, s, &cur);
+    if (rc) return rc;
+  }
+  mrt::launch_finalize<T>(g, cur, static_cast<T*>(state), static_cast<T*>(uN),
+                          static_cast<T*>(vN), s);
+  rc = last_launch_error();
+  if (rc) return rc;
+  t->fwd_done = true;
+  t->f_u0 = u0;
+  t->f_v0 = v0;
+  t->f_ctrl = control;
+  return MRT_OK;
+}
+
+template <typename T>
+int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
+                 const void* v0, const void* control, const void* seed_u,
+                 const void* seed_v, double* gacc, void* adj_u0, void* adj_v0,
+                 hipStream_t s) {
+  const mrt::ModelCoef<T> m = model_coef<T>(p);
+  const mrt::Geometry g = geometry(t);
+  const int N = t->nsteps, K = t->K;
+  const T* tu0 = static_cast<const T*>(u0);
+  const T* tv0 = static_cast<const T*>(v0);
+  const T* tc = static_cast<const T*>(control);
+  const bool want0 = adj_u0 != nullptr || adj_v0 != nullptr;
+  const T* asrc = nullptr;
+  for (int seg = t->nseg - 1; seg >= 0; --seg) {
+    const int n0 = seg * K, n1 = std::min(N, n0 + K);
+    if (seg != t->nseg - 1) {
+      // recompute the segment from its checkpoint, recording u and j_v
+      const T* src = seg == 0 ? nullptr : static_cast<const T*>(t->ckpt[seg]);
+      const T* dummy = nullptr;
+      int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true,
+                                    false, true, 2, s, &dummy);
+      if (rc) return rc;
+    }
+    SpanGuard span(1, s);
+    for (int n = n1 - 1; n >= n0; --n) {
+      mrt::AdjLaunch<T> a;
+      a.src = asrc;
+      a.first = n == N - 1;
+      a.last = (n == 0 && want0) ? 1 : 0;
+      a.dst = n == 0 ? nullptr : static_cast<T*>(t->abuf[n & 1]);
+      a.seed_u = static_cast<const T*>(seed_u);
+      a.seed_v = static_cast<const T*>(seed_v);
+      a.rec = slot<T>(t, n - n0);
+      a.g = gacc;
+      a.adj_u0 = static_cast<T*>(adj_u0);
+      a.adj_v0 = static_cast<T*>(adj_v0);
+      mrt::launch_adjoint_step<T>(g, m, a, s);
+      span.count();
+      int rc = last_launch_error();
+      if (rc) return rc;
+      asrc = a.dst;
+    }
+  }
+  return MRT_OK;
+}
+
+int read_result(mrt_tape* t, hipStream_t s, int n) {
+  HIP_TRY(hipMemcpyAsync(t->host, t->result, sizeof(double) * n,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MRT_OK;
+}
+
+template <typename T>
+int cost_impl(mrt_tape* t, double alpha, const void* uN, const void* ut,
+              const void* ctrl, const double* gacc, void* seed, void* grad,
+              mrt_scalars* out, hipStream_t s) {
+  const mrt::Geometry g = geometry(t);
+  mrt::launch_cost_grad<T>(g, static_cast<const T*>(uN),
+                           static_cast<const T*>(ut),
+                           static_cast<const T*>(ctrl), gacc,
+                           static_cast<T*>(seed), static_cast<T*>(grad), alpha,
+                           t->partials, t->result, s);
+  int rc = last_launch_error();
+  if (rc) return rc;
+  rc = read_result(t, s, mrt::kRedSlots);
+  if (rc) return rc;
+  const double* h = t->host;
+  mrt_scalars r{};
+  r.J_track = h[0];
+  r.J_reg = h[1];
+  r.J = h[0] + h[1];
+  r.grad_l2 = gacc ? std::sqrt(h[2]) : 0.0;
+  r.grad_inf = gacc ? h[3] : 0.0;
+  r.n_fluid = t->n_fluid;
+  if (out) *out = r;
+  if (h[4] != 0.0 || !std::isfinite(r.J) || !std::isfinite(r.grad_l2))
+    return fail(MRT_ENONFINITE, "non-finite cost or gradient (%g values)", h[4]);
+  return MRT_OK;
+}
+
+void free_tape(mrt_tape* t) {
+  if (!t) return;
+  for (void* a : t->allocs) (void)hipFree(a);
+  if (t->host) (void)hipHostFree(t->host);
+  delete t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrt_validate(const mrt_problem* p) { return validate(p); }
+
+int mrt_tape_bytes(const mrt_problem* p, int32_t ckpt_every, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(MRT_EINVAL, "bytes is NULL");
+  *bytes = plan(p, ckpt_every).total;
+  return MRT_OK;
+}
+
+int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
+                    size_t mem_budget, mrt_tape** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return fail(MRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  const Layout L = plan(p, ckpt_every);
+  if (mem_budget > 0 && L.total > mem_budget)
+    return fail(MRT_ENOMEM, "tape needs %zu bytes, budget %zu", L.total,
+                mem_budget);
+  mrt_tape* t = new mrt_tape();
+  const mrt_grid& g = p->grid;
+  t->nx = g.nx;
+  t->ny = g.ny;
+  t->pitch = g.pitch;
+  t->nsteps = g.nsteps;
+  t->dtype = g.dtype;
+  t->periodic = g.periodic;
+  t->masked = (g.mask != nullptr || !g.periodic) ? 1 : 0;
+  t->mode = L.mode;
+  t->K = L.K;
+  t->nseg = L.nseg;
+  t->plane = L.plane;
+  t->elem = L.elem;
+  t->state_bytes = L.state_bytes;
+  t->rec_slot_bytes = L.rec_slot_bytes;
+  t->total_bytes = L.total;
+  auto alloc = [&](size_t bytes, void** ptr) -> int {
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MRT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes,
+                  hipGetErrorString(e));
+    }
+    t->allocs.push_back(*ptr);
+    return MRT_OK;
+  };
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    delete t;
+    return fail(MRT_EHIP, "no HIP device");
+  }
+  rc = alloc(L.state_bytes, &t->buf[0]);
+  if (!rc) rc = alloc(L.state_bytes, &t->buf[1]);
+  if (!rc && t->masked) rc = alloc(L.plane * sizeof(uint16_t), (void**)&t->link);
+  if (!rc)
+    rc = alloc((size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double),
+               (void**)&t->partials);
+  if (!rc && L.mode > 0) {
+    rc = alloc(L.state_bytes, &t->abuf[0]);
+    if (!rc) rc = alloc(L.state_bytes, &t->abuf[1]);
+    t->ckpt.assign(L.nseg, nullptr);
+    for (int k = 1; k < L.nseg && !rc; ++k) rc = alloc(L.state_bytes, &t->ckpt[k]);
+    if (!rc) rc = alloc(size_t(L.K) * L.rec_slot_bytes, &t->rec);
+  }
+  if (!rc && hipHostMalloc((void**)&t->host, 16 * sizeof(double)) != hipSuccess)
+    rc = fail(MRT_ENOMEM, "hipHostMalloc failed");
+  if (rc) {
+    free_tape(t);
+    return rc;
+  }
+  t->result = t->partials + size_t(mrt::kRedBlocks) * mrt::kRedSlots;
+  const mrt::Geometry geo = geometry(t);
+  hipStream_t s = nullptr;
+  if (t->masked) mrt::launch_build_link(geo, g.periodic, g.mask, t->link, s);
+  mrt::launch_count_fluid(geo, t->partials, t->result, s);
+  rc = last_launch_error();
+  if (!rc) rc = read_result(t, s, 1);
+  if (rc) {
+    free_tape(t);
+    return rc;
+  }
+  t->n_fluid = int64_t(t->host[0]);
+  *out = t;
+  return MRT_OK;
+}
+
+void mrt_tape_destroy(mrt_tape* t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  free_tape(t);
+}
+
+int mrt_tape_query(const mrt_tape* t, mrt_tape_info* info) {
+  if (!t || !info) return fail(MRT_EINVAL, "NULL argument");
+  info->mode = t->mode;
+  info->ckpt_every = t->K;
+  info->n_segments = t->nseg;
+  info->reserved = 0;
+  info->n_fluid = t->n_fluid;
+  info->device_bytes = t->total_bytes;
+  return MRT_OK;
+}
+
+int mrt_forward(const mrt_problem* p, mrt_tape* t, const void* u0,
+                const void* v0, const void* control, void* state, void* uN,
+                void* vN, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!u0 || !v0 || !control) return fail(MRT_EINVAL, "u0, v0, control required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->grid.dtype == MRT_F64
+             ? forward_impl<double>(p, t, u0, v0, control, state, uN, vN, s)
+             : forward_impl<float>(p, t, u0, v0, control, state, uN, vN, s);
+}
+
+int amrt_adjoint(const mrt_problem* p, mrt_tape* t, const void* u0,
+                 const void* v0, const void* control, const void* seed_u,
+                 const void* seed_v, double* grad_accum, void* adj_u0,
+                 void* adj_v0, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (t->mode == 0) return fail(MRT_ESTATE, "tape was created without adjoint record");
+  if (!t->fwd_done) return fail(MRT_ESTATE, "no forward solve recorded on this tape");
+  if (u0 != t->f_u0 || v0 != t->f_v0 || control != t->f_ctrl)
+    return fail(MRT_ESTATE, "u0/v0/control differ from the recorded forward");
+  if (!seed_u || !grad_accum) return fail(MRT_EINVAL, "seed_u and grad_accum required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->grid.dtype == MRT_F64
+             ? adjoint_impl<double>(p, t, u0, v0, control, seed_u, seed_v,
+                                    grad_accum, adj_u0, adj_v0, s)
+             : adjoint_impl<float>(p, t, u0, v0, control, seed_u, seed_v,
+                                   grad_accum, adj_u0, adj_v0, s);
+}
+
+int cost_gradient(const mrt_problem* p, mrt_tape* t, const void* uN,
+                  const void* u_target, const void* control,
+                  const double* grad_accum, void* seed_out, void* grad_out,
+                  mrt_scalars* out, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!uN || !u_target || !control)
+    return fail(MRT_EINVAL, "uN, u_target, control required");
+  if (grad_accum && !grad_out)
+    return fail(MRT_EINVAL, "grad_out required with grad_accum");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->grid.dtype == MRT_F64
+             ? cost_impl<double>(t, p->alpha, uN, u_target, control,
+                                 grad_accum, seed_out, grad_out, out, s)
+             : cost_impl<float>(t, p->alpha, uN, u_target, control, grad_accum,
+                                seed_out, grad_out, out, s);
+}
+
+int gd_step(const mrt_problem* p, mrt_tape* t, void* control, const void* grad,
+            double zeta, double lo, double hi, double* zeta_used,
+            void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!control || !grad) return fail(MRT_EINVAL, "control and grad required");
+  if (std::isnan(zeta) || std::isnan(lo) || std::isnan(hi) || lo > hi)
+    return fail(MRT_EINVAL, "invalid zeta or bounds");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const mrt::Geometry g = geometry(t);
+  if (p->grid.dtype == MRT_F64)
+    mrt::launch_gd_step<double>(g, static_cast<double*>(control),
+                                static_cast<const double*>(grad), zeta, lo, hi,
+                                t->partials, t->result, s);
+  else
+    mrt::launch_gd_step<float>(g, static_cast<float*>(control),
+                               static_cast<const float*>(grad), zeta, lo, hi,
+                               t->partials, t->result, s);
+  rc = last_launch_error();
+  if (rc) return rc;
+  if (zeta_used) {
+    HIP_TRY(hipMemcpyAsync(t->host + mrt::kRedSlots, t->result + mrt::kRedSlots,
+                           sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *zeta_used = t->host[mrt::kRedSlots];
+    if (!std::isfinite(*zeta_used))
+      return fail(MRT_ENONFINITE, "non-finite step (gradient not finite)");
+  }
+  return MRT_OK;
+}
+
+const char* mrt_last_error(void) { return g_err.c_str(); }
+
+int mrt_timing_enable(int32_t on) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.on = on != 0;
+  return MRT_OK;
+}
+
+int mrt_timing_reset(void) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  for (auto& sp : t.pending) {
+    (void)hipEventSynchronize(sp.b);
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  t.pending.clear();
+  for (int k = 0; k < 3; ++k) {
+    t.ms[k] = 0.0;
+    t.launches[k] = 0;
+  }
+  return MRT_OK;
+}
+
+int mrt_timing_read(int32_t kind, double* ms, int64_t* launches) {
+  if (kind < 0 || kind > 2) return fail(MRT_EINVAL, "kind must be 0, 1 or 2");
+  Timing& t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  for (auto& sp : t.pending) {
+    HIP_TRY(hipEventSynchronize(sp.b));
+    float e = 0.f;
+    HIP_TRY(hipEventElapsedTime(&e, sp.a, sp.b));
+    t.ms[sp.kind] += e;
+    t.launches[sp.kind] += sp.launches;
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  t.pending.clear();
+  if (ms) *ms = t.ms[kind];
+  if (launches) *launches = t.launches[kind];
+  return MRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal interface between the C-ABI runtime (mrt_abi.cpp) and the gfx950
+// kernels (mrt_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mrt {
+
+// Relaxation coefficients of one species, pre-scaled by the inverse squared
+// row norms of M0 (M0^-1 = M0^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12,
+// 1/4, 1/4), the rows of M0 being orthogonal).
+template <typename T>
+struct SpeciesCoef {
+  T s1, s2;               // s1/36, s2/36       on (e, epsilon)
+  T s3, s4;               // s3/12, s4/12       on (q_x, q_y)
+  T s5, s6;               // s5/4,  s6/4        on (p_xx, p_xy)
+  T k00, k01, k10, k11;   // K/6                on (j_x, j_y)
+  T e_eq, eps_eq;         // m_eq = Theta * (1, e_eq, eps_eq, 0, ..., 0)
+  T w_rest, w_axis, w_diag;  // phi_eq_i = w_i * Theta by velocity shell
+};
+
+// Per-step model coefficients (kernel argument, passed by value).
+template <typename T>
+struct ModelCoef {
+  SpeciesCoef<T> u, v;   // forward relaxation
+  SpeciesCoef<T> ut, vt; // adjoint relaxation: K transposed
+  T b00, b01, b10, b11;  // chemotactic source a = u * B * j_v
+  T r_u, a_uv, b_v;      // kinetics
+};
+
+struct Geometry {
+  int nx, ny, pitch;
+  int masked;            // 1: use the link mask (walls, obstacles, non-periodic)
+  size_t plane;          // ny * pitch elements
+  const uint16_t* link;  // link mask [ny][pitch] when masked, else null
+};
+
+// Link mask: bit 0 = node solid, bit i (1..8) = node x - e_i solid
+// (outside a non-periodic domain counts as solid).
+void launch_build_link(const Geometry& g, int periodic, const uint8_t* mask,
+                       uint16_t* link_out, hipStream_t s);
+
+template <typename T>
+struct FwdLaunch {
+  const T* src;      // post-collision state of step n-1, or null (first)
+  T* dst;            // post-collision state of step n, or null (no write)
+  const T* u0;       // initial fields (first step only)
+  const T* v0;
+  const T* ctrl;     // control c(x)
+  T* rec;            // record slot [3][plane] (u, j_vx, j_vy) or null
+};
+
+template <typename T>
+void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
+                         const FwdLaunch<T>& a, hipStream_t s);
+
+// Terminal streaming: state (may be null), u^N, v^N (may be null).
+template <typename T>
+void launch_finalize(const Geometry& g, const T* src, T* state, T* uN, T* vN,
+                     hipStream_t s);
+
+template <typename T>
+struct AdjLaunch {
+  const T* src;      // adjoint state of step n+1, or null (terminal seed)
+  T* dst;            // adjoint state of step n, or null (last step)
+  const T* seed_u;   // terminal condition (first step only)
+  const T* seed_v;   // may be null (= 0)
+  const T* rec;      // record slot of step n
+  double* g;         // gradient accumulator
+  T* adj_u0;         // dJ/du0 (last step only, may be null)
+  T* adj_v0;
+  int first;         // 1: step N-1 (reads seeds, initialises g)
+  int last;          // 1: step 0 and adj_u0/adj_v0 requested
+};
+
+template <typename T>
+void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
+                         const AdjLaunch<T>& a, hipStream_t s);
+
+// Deterministic two-pass reductions in double.
+// Result slots (double): [0] sum 1/2 (uN-ut)^2, [1] sum alpha/2 c^2,
+// [2] sum E^2, [3] max |E|, [4] count of non-finite values.
+constexpr int kRedSlots = 5;
+constexpr int kRedBlocks = 1024;
+
+template <typename T>
+void launch_cost_grad(const Geometry& g, const T* uN,
+                      const T* ut, const T* ctrl, const double* gacc,
+                      T* seed, T* grad, double alpha, double* partials,
+                      double* result, hipStream_t s);
+
+template <typename T>
+void launch_gd_step(const Geometry& g, T* ctrl,
+                    const T* grad, double zeta, double lo, double hi,
+                    double* partials, double* result, hipStream_t s);
+
+void launch_count_fluid(const Geometry& g, double* partials, double* result,
+                        hipStream_t s);
+
+}  // namespace mrt

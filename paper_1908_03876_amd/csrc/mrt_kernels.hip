@@ -1,0 +1,705 @@
+// gfx950 kernels of the two-species D2Q9 MRT chemotaxis step, its exact
+// discrete adjoint (AMRT) and the cost / gradient / update reductions.
+//
+// Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
+// BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
+// Section 3.2.1 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
+//
+// Design (memory-bound stencil, no MFMA):
+//  * One thread per lattice node, 256-thread blocks along x; every
+//    population is read once and written once per step in SoA planes, so
+//    each wavefront issues 18 coalesced 256-byte loads and 18 stores.
+//  * The kernel stores post-collision states and pulls: node x gathers
+//    phi*_i(x - e_i) (or its own phi*_opp(i) when x - e_i is solid, halfway
+//    bounce-back).  Collision runs in registers in moment space; M0^-1 is
+//    applied as M0^T with the row norms folded into the rates.
+//  * The adjoint is a gather too: nu_i(x) = lambda_i(x + e_i), or
+//    lambda_opp(i)(x) when x + e_i is solid (exact transpose of the pull).
+//  * Work-group order is remapped so that each of the 8 XCDs walks a
+//    contiguous band of rows (its L2 keeps the shifted-row and edge lines).
+//  * Reductions: wave shuffles (64 lanes), LDS across waves, one partial per
+//    block, then a single-block pass in fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mrt_internal.h"
+
+namespace mrt {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+// D2Q9 opposite directions: e3 = -e1, e4 = -e2, e7 = -e5, e8 = -e6.
+__device__ __forceinline__ constexpr int opp(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
+
+// Linear work-group id -> tile id such that XCD k (ids = k mod 8) owns the
+// contiguous tile range [k*n/8, (k+1)*n/8).
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+  const int per = n / kXcds, rem = n % kXcds;
+  const int xcd = id % kXcds, k = id / kXcds;
+  // the first `rem` XCDs own per+1 tiles
+  const int base = xcd * per + (xcd < rem ? xcd : rem);
+  return base + k;
+}
+
+struct NodeIdx {
+  int x, y;
+  int xm, xp;        // x - 1, x + 1 with periodic wrap
+  size_t r0, rm, rp; // row offsets of y, y - 1, y + 1 with wrap
+};
+
+__device__ __forceinline__ bool node_of_block(const Geometry& g, NodeIdx& n) {
+  const int nbx = (g.nx + kBlock - 1) / kBlock;
+  const int ntiles = nbx * g.ny;
+  const int id = blockIdx.x;
+  if (id >= ntiles) return false;
+  // each XCD owns ntiles/8 (+1) tiles; the id -> tile map is a bijection
+  // on [0, ntiles) because ids are dealt round-robin to XCDs.
+  const int t = xcd_tile(id, ntiles);
+  n.y = t / nbx;
+  n.x = (t % nbx) * kBlock + threadIdx.x;
+  if (n.x >= g.nx) return false;
+  n.xm = n.x == 0 ? g.nx - 1 : n.x - 1;
+  n.xp = n.x + 1 == g.nx ? 0 : n.x + 1;
+  const int ym = n.y == 0 ? g.ny - 1 : n.y - 1;
+  const int yp = n.y + 1 == g.ny ? 0 : n.y + 1;
+  n.r0 = size_t(n.y) * g.pitch;
+  n.rm = size_t(ym) * g.pitch;
+  n.rp = size_t(yp) * g.pitch;
+  return true;
+}
+
+// Offset (within a plane) of node x - e_i for i = 0..8.
+__device__ __forceinline__ size_t pull_off(const NodeIdx& n, int i) {
+  switch (i) {
+    case 0: return n.r0 + n.x;
+    case 1: return n.r0 + n.xm;   // e1 = (1,0)
+    case 2: return n.rm + n.x;    // e2 = (0,1)
+    case 3: return n.r0 + n.xp;   // e3 = (-1,0)
+    case 4: return n.rp + n.x;    // e4 = (0,-1)
+    case 5: return n.rm + n.xm;   // e5 = (1,1)
+    case 6: return n.rm + n.xp;   // e6 = (-1,1)
+    case 7: return n.rp + n.xp;   // e7 = (-1,-1)
+    default: return n.rp + n.xm;  // e8 = (1,-1)
+  }
+}
+
+// Offset of node x + e_i = x - e_opp(i).
+__device__ __forceinline__ size_t push_off(const NodeIdx& n, int i) {
+  return pull_off(n, opp(i));
+}
+
+// Relaxation in moment space: f <- f - M0^-1 Pi (M0 f - m_eq(theta)).
+// With theta = 0 and the K block transposed this is f <- f - C^T f
+// (C^T = M0^-1 Pi^T M0 since Pi only couples moments of equal row norm),
+// without the conserved zeroth-moment part.  Returns the scaled amounts
+// (a1, a2) of the e and epsilon moments for the adjoint equilibrium term.
+template <typename T>
+__device__ __forceinline__ void relax(T f[9], T theta,
+                                      const SpeciesCoef<T>& c, T& a1o,
+                                      T& a2o) {
+  const T sa = f[1] + f[2] + f[3] + f[4];
+  const T sd = f[5] + f[6] + f[7] + f[8];
+  const T m1 = T(-4) * f[0] - sa + T(2) * sd;       // e
+  const T m2 = T(4) * f[0] - T(2) * sa + sd;        // epsilon
+  const T dx = f[5] - f[6] - f[7] + f[8];
+  const T dy = f[5] + f[6] - f[7] - f[8];
+  const T m3 = f[1] - f[3] + dx;                    // j_x
+  const T m4 = T(-2) * (f[1] - f[3]) + dx;          // q_x
+  const T m5 = f[2] - f[4] + dy;                    // j_y
+  const T m6 = T(-2) * (f[2] - f[4]) + dy;          // q_y
+  const T m7 = f[1] - f[2] + f[3] - f[4];           // p_xx
+  const T m8 = f[5] - f[6] + f[7] - f[8];           // p_xy
+  const T a1 = c.s1 * (m1 - c.e_eq * theta);
+  const T a2 = c.s2 * (m2 - c.eps_eq * theta);
+  const T a3 = c.k00 * m3 + c.k01 * m5;
+  const T a5 = c.k10 * m3 + c.k11 * m5;
+  const T a4 = c.s3 * m4;
+  const T a6 = c.s4 * m6;
+  const T a7 = c.s5 * m7;
+  const T a8 = c.s6 * m8;
+  const T b = T(2) * a1 + a2;
+  const T h = -a1 - T(2) * a2;
+  f[0] -= T(4) * (a2 - a1);
+  f[1] -= h + a3 - T(2) * a4 + a7;
+  f[2] -= h + a5 - T(2) * a6 - a7;
+  f[3] -= h - a3 + T(2) * a4 + a7;
+  f[4] -= h - a5 + T(2) * a6 - a7;
+  f[5] -= b + a3 + a4 + a5 + a6 + a8;
+  f[6] -= b - a3 - a4 + a5 + a6 - a8;
+  f[7] -= b - a3 - a4 - a5 - a6 + a8;
+  f[8] -= b + a3 + a4 - a5 - a6 - a8;
+  a1o = a1;
+  a2o = a2;
+}
+
+// -------------------------------------------------------------- link mask
+
+__global__ void build_link_kernel(Geometry g, int periodic,
+                                  const uint8_t* __restrict__ mask,
+                                  uint16_t* __restrict__ link) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  uint16_t bits = 0;
+  for (int i = 0; i < 9; ++i) {
+    int xs = x - ex[i], ys = y - ey[i];
+    bool solid;
+    if (xs < 0 || ys < 0 || xs >= g.nx || ys >= g.ny) {
+      if (!periodic) {
+        solid = true;
+      } else {
+        xs = (xs + g.nx) % g.nx;
+        ys = (ys + g.ny) % g.ny;
+        solid = mask && mask[size_t(ys) * g.pitch + xs];
+      }
+    } else {
+      solid = mask && mask[size_t(ys) * g.pitch + xs];
+    }
+    if (solid) bits |= uint16_t(1u << i);
+  }
+  link[size_t(y) * g.pitch + x] = bits;
+}
+
+// --------------------------------------------------------------- forward
+
+template <typename T, bool MASKED, bool FIRST, bool RECORD, bool WRITE>
+__global__ __launch_bounds__(kBlock) void forward_step_kernel(
+    Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ u0, const T* __restrict__ v0,
+    const T* __restrict__ ctrl, T* __restrict__ rec) {
+  const uint16_t* __restrict__ link = g.link;
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = 0;
+  if (MASKED) {
+    lm = link[idx];
+    if (lm & 1u) return;  // solid node: no populations
+  }
+  T fu[9], fv[9];
+  if (FIRST) {
+    // equilibrium initialisation phi_i = w_i Theta_0 (phieq, zero flux)
+    const T a = u0[idx], b = v0[idx];
+    fu[0] = m.u.w_rest * a;
+    fv[0] = m.v.w_rest * b;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      fu[i] = m.u.w_axis * a;
+      fv[i] = m.v.w_axis * b;
+    }
+#pragma unroll
+    for (int i = 5; i < 9; ++i) {
+      fu[i] = m.u.w_diag * a;
+      fv[i] = m.v.w_diag * b;
+    }
+  } else {
+    const T* su = src;
+    const T* sv = src + 9 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      size_t o = pull_off(n, i);
+      size_t pi = size_t(i) * g.plane;
+      if (MASKED && ((lm >> i) & 1u)) {
+        o = idx;
+        pi = size_t(opp(i)) * g.plane;
+      }
+      fu[i] = su[pi + o];
+      fv[i] = sv[pi + o];
+    }
+  }
+  // macroscopic values (UGS) and the first moment of v
+  T u = T(0), v = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    u += fu[i];
+    v += fv[i];
+  }
+  const T jx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
+  const T jy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
+  if (RECORD) {
+    rec[idx] = u;
+    rec[g.plane + idx] = jx;
+    rec[2 * g.plane + idx] = jy;
+  }
+  // chemotactic source: A_u1 grad v = u * B * j_v with the local gradient
+  // grad v = -K_v j_v / (tau d_v Cs^2)
+  const T ax = u * (m.b00 * jx + m.b01 * jy);
+  const T ay = u * (m.b10 * jx + m.b11 * jy);
+  const T phu = m.r_u * u * (T(1) - u);
+  const T phv = m.a_uv * u - m.b_v * v + ctrl[idx];
+  T t1, t2;
+  relax(fu, u, m.u, t1, t2);
+  relax(fv, v, m.v, t1, t2);
+  // sources tau S_i + tau w_i Phi (S, PhiS), tau = 1, 1/Cs^2 = 3
+  const T p9 = phu * T(1.0 / 9.0), p36 = phu * T(1.0 / 36.0);
+  const T x3 = ax * T(1.0 / 3.0), y3 = ay * T(1.0 / 3.0);
+  const T x12 = ax * T(1.0 / 12.0), y12 = ay * T(1.0 / 12.0);
+  fu[0] += phu * T(4.0 / 9.0);
+  fu[1] += p9 + x3;
+  fu[2] += p9 + y3;
+  fu[3] += p9 - x3;
+  fu[4] += p9 - y3;
+  fu[5] += p36 + x12 + y12;
+  fu[6] += p36 - x12 + y12;
+  fu[7] += p36 - x12 - y12;
+  fu[8] += p36 + x12 - y12;
+  const T q9 = phv * T(1.0 / 9.0), q36 = phv * T(1.0 / 36.0);
+  fv[0] += phv * T(4.0 / 9.0);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) fv[i] += q9;
+#pragma unroll
+  for (int i = 5; i < 9; ++i) fv[i] += q36;
+  if (WRITE) {
+    T* du = dst;
+    T* dv = dst + 9 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      du[size_t(i) * g.plane + idx] = fu[i];
+      dv[size_t(i) * g.plane + idx] = fv[i];
+    }
+  }
+}
+
+template <typename T, bool MASKED>
+__global__ __launch_bounds__(kBlock) void finalize_kernel(
+    Geometry g, const T* __restrict__ src, T* __restrict__ state,
+    T* __restrict__ uN, T* __restrict__ vN) {
+  const uint16_t* __restrict__ link = g.link;
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = MASKED ? link[idx] : 0u;
+  T fu[9], fv[9];
+  if (MASKED && (lm & 1u)) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fu[i] = fv[i] = T(0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      size_t o = pull_off(n, i);
+      size_t pi = size_t(i) * g.plane;
+      if (MASKED && ((lm >> i) & 1u)) {
+        o = idx;
+        pi = size_t(opp(i)) * g.plane;
+      }
+      fu[i] = src[pi + o];
+      fv[i] = src[9 * g.plane + pi + o];
+    }
+  }
+  T u = T(0), v = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    u += fu[i];
+    v += fv[i];
+  }
+  if (uN) uN[idx] = u;
+  if (vN) vN[idx] = v;
+  if (state) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      state[size_t(i) * g.plane + idx] = fu[i];
+      state[size_t(9 + i) * g.plane + idx] = fv[i];
+    }
+  }
+}
+
+// --------------------------------------------------------------- adjoint
+
+template <typename T, bool MASKED, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
+    Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ seed_u, const T* __restrict__ seed_v,
+    const T* __restrict__ rec, double* __restrict__ gacc,
+    T* __restrict__ adj_u0, T* __restrict__ adj_v0) {
+  const uint16_t* __restrict__ link = g.link;
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = 0;
+  if (MASKED) {
+    lm = link[idx];
+    if (lm & 1u) {
+      if (FIRST) gacc[idx] = 0.0;
+      if (LAST) {
+        if (adj_u0) adj_u0[idx] = T(0);
+        if (adj_v0) adj_v0[idx] = T(0);
+      }
+      return;
+    }
+  }
+  // reverse streaming: nu_i(x) = lambda_i(x + e_i), or lambda_opp(i)(x)
+  // when x + e_i is solid (bit opp(i) of the link mask).
+  T nu[9], nv[9];
+  if (FIRST) {
+    // terminal condition lambda_i^N = seed for every i (psi(T) = dI0/dphi)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      size_t o = push_off(n, i);
+      if (MASKED && ((lm >> opp(i)) & 1u)) o = idx;
+      nu[i] = seed_u[o];
+      nv[i] = seed_v ? seed_v[o] : T(0);
+    }
+  } else {
+    const T* su = src;
+    const T* sv = src + 9 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      size_t o = push_off(n, i);
+      size_t pi = size_t(i) * g.plane;
+      if (MASKED && ((lm >> opp(i)) & 1u)) {
+        o = idx;
+        pi = size_t(opp(i)) * g.plane;
+      }
+      nu[i] = su[pi + o];
+      nv[i] = sv[pi + o];
+    }
+  }
+  // weighted sums: sigma = w . nu, p = (tau/Cs^2) sum_i w_i nu_u,i e_i
+  const T su_ = T(4.0 / 9.0) * nu[0] +
+                T(1.0 / 9.0) * (nu[1] + nu[2] + nu[3] + nu[4]) +
+                T(1.0 / 36.0) * (nu[5] + nu[6] + nu[7] + nu[8]);
+  const T sv_ = T(4.0 / 9.0) * nv[0] +
+                T(1.0 / 9.0) * (nv[1] + nv[2] + nv[3] + nv[4]) +
+                T(1.0 / 36.0) * (nv[5] + nv[6] + nv[7] + nv[8]);
+  const T px = T(1.0 / 3.0) * (nu[1] - nu[3]) +
+               T(1.0 / 12.0) * (nu[5] - nu[6] - nu[7] + nu[8]);
+  const T py = T(1.0 / 3.0) * (nu[2] - nu[4]) +
+               T(1.0 / 12.0) * (nu[5] + nu[6] - nu[7] - nu[8]);
+  // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i
+  if (FIRST)
+    gacc[idx] = double(sv_);
+  else
+    gacc[idx] += double(sv_);
+  // recorded forward quantities of step n
+  const T u = rec[idx];
+  const T jx = rec[g.plane + idx];
+  const T jy = rec[2 * g.plane + idx];
+  const T bjx = m.b00 * jx + m.b01 * jy;
+  const T bjy = m.b10 * jx + m.b11 * jy;
+  // transposed sources: d(tau S_u + tau Phi_u)/dphi_u is rank one along 1,
+  // d(tau S_u)/dphi_v = (tau/Cs^2) diag(w) E u B E^T, dPhi_v/dphi = (a, -b).
+  const T cu = su_ * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
+               sv_ * m.a_uv;
+  const T cv = -sv_ * m.b_v;
+  const T qx = u * (m.b00 * px + m.b10 * py);
+  const T qy = u * (m.b01 * px + m.b11 * py);
+  // adjoint collision: nu - C^T nu + 1 * weq^T C^T nu  (AEDs with O = 1 weq^T)
+  T a1, a2;
+  relax(nu, T(0), m.ut, a1, a2);
+  const T wu = m.u.e_eq * a1 + m.u.eps_eq * a2 + cu;
+  relax(nv, T(0), m.vt, a1, a2);
+  const T wv = m.v.e_eq * a1 + m.v.eps_eq * a2 + cv;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    nu[i] += wu;
+    nv[i] += wv;
+  }
+  nv[1] += qx;
+  nv[2] += qy;
+  nv[3] -= qx;
+  nv[4] -= qy;
+  nv[5] += qx + qy;
+  nv[6] += qy - qx;
+  nv[7] -= qx + qy;
+  nv[8] += qx - qy;
+  if (LAST) {
+    // transpose of phi_i^0 = w_i Theta_0
+    if (adj_u0)
+      adj_u0[idx] = m.u.w_rest * nu[0] +
+                    m.u.w_axis * (nu[1] + nu[2] + nu[3] + nu[4]) +
+                    m.u.w_diag * (nu[5] + nu[6] + nu[7] + nu[8]);
+    if (adj_v0)
+      adj_v0[idx] = m.v.w_rest * nv[0] +
+                    m.v.w_axis * (nv[1] + nv[2] + nv[3] + nv[4]) +
+                    m.v.w_diag * (nv[5] + nv[6] + nv[7] + nv[8]);
+  } else if (dst) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      dst[size_t(i) * g.plane + idx] = nu[i];
+      dst[size_t(9 + i) * g.plane + idx] = nv[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Block reduction of kRedSlots values (slot 3 is a max, the others sums);
+// lane 0 of the block writes the block partial.
+__device__ void block_reduce_store(double vals[kRedSlots], double* out) {
+  __shared__ double lds[kRedSlots][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) {
+    double r = (k == 3) ? wave_max(vals[k]) : wave_sum(vals[k]);
+    if (lane == 0) lds[k][wave] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kRedSlots; ++k) {
+      double r = lds[k][0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        r = (k == 3) ? fmax(r, lds[k][w]) : r + lds[k][w];
+      out[k] = r;
+    }
+  }
+}
+
+__device__ __forceinline__ bool is_fluid(const uint16_t* link, size_t idx) {
+  return link == nullptr || !(link[idx] & 1u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cost_grad_kernel(
+    Geometry g, const T* __restrict__ uN, const T* __restrict__ ut, const T* __restrict__ ctrl,
+    const double* __restrict__ gacc, T* __restrict__ seed, T* __restrict__ grad,
+    double alpha, double* __restrict__ partials) {
+  const uint16_t* link = g.link;
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t y = k / g.nx, x = k % g.nx;
+    const size_t idx = y * g.pitch + x;
+    const bool fl = is_fluid(link, idx);
+    double d = 0.0, cc = 0.0, e = 0.0;
+    if (fl) {
+      d = double(uN[idx]) - double(ut[idx]);
+      cc = double(ctrl[idx]);
+      acc[0] += 0.5 * d * d;
+      acc[1] += 0.5 * alpha * cc * cc;
+      if (!isfinite(d) || !isfinite(cc)) acc[4] += 1.0;
+    }
+    if (seed) seed[idx] = fl ? T(d) : T(0);
+    if (gacc) {
+      if (fl) {
+        e = gacc[idx] + alpha * cc;
+        acc[2] += e * e;
+        acc[3] = fmax(acc[3], fabs(e));
+        if (!isfinite(e)) acc[4] += 1.0;
+      }
+      grad[idx] = fl ? T(e) : T(0);
+    }
+  }
+  block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_reduce_kernel(
+    const double* __restrict__ partials, int nblocks,
+    double* __restrict__ result) {
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kRedSlots; ++k) {
+      double v = partials[size_t(b) * kRedSlots + k];
+      acc[k] = (k == 3) ? fmax(acc[k], v) : acc[k] + v;
+    }
+  }
+  block_reduce_store(acc, result);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void grad_max_kernel(
+    Geometry g, const T* __restrict__ grad, double* __restrict__ partials) {
+  const uint16_t* link = g.link;
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t y = k / g.nx, x = k % g.nx;
+    const size_t idx = y * g.pitch + x;
+    if (is_fluid(link, idx)) {
+      const double e = double(grad[idx]);
+      acc[3] = fmax(acc[3], fabs(e));
+      if (!isfinite(e)) acc[4] += 1.0;
+    }
+  }
+  block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
+}
+
+// zeta > 0: fixed step; zeta <= 0: heuristic min(1, 1/||E||_inf) from the
+// reduced maximum in result[3] (written by grad_max_kernel on the device).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gd_update_kernel(
+    Geometry g, T* __restrict__ ctrl, const T* __restrict__ grad, double zeta,
+    double lo, double hi, double* __restrict__ result) {
+  const uint16_t* link = g.link;
+  double z = zeta;
+  if (z <= 0.0) {
+    const double emax = result[3];
+    z = emax > 0.0 ? fmin(1.0, 1.0 / emax) : 1.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) result[kRedSlots] = z;
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t y = k / g.nx, x = k % g.nx;
+    const size_t idx = y * g.pitch + x;
+    if (!is_fluid(link, idx)) continue;
+    double c = double(ctrl[idx]) - z * double(grad[idx]);
+    c = fmin(fmax(c, lo), hi);
+    ctrl[idx] = T(c);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void count_fluid_kernel(
+    Geometry g, double* __restrict__ partials) {
+  const uint16_t* link = g.link;
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t y = k / g.nx, x = k % g.nx;
+    if (is_fluid(link, y * g.pitch + x)) acc[0] += 1.0;
+  }
+  block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
+}
+
+int stencil_blocks(const Geometry& g) {
+  return ((g.nx + kBlock - 1) / kBlock) * g.ny;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launchers
+
+void launch_build_link(const Geometry& g, int periodic, const uint8_t* mask,
+                       uint16_t* link_out, hipStream_t s) {
+  dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
+  hipLaunchKernelGGL(build_link_kernel, grid, dim3(kBlock), 0, s, g, periodic,
+                     mask, link_out);
+}
+
+template <typename T>
+void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
+                         const FwdLaunch<T>& a, hipStream_t s) {
+  const bool first = a.src == nullptr;
+  const bool rec = a.rec != nullptr;
+  const bool wr = a.dst != nullptr;
+  const int nb = stencil_blocks(g);
+#define MRT_FWD(M, F, R, W)                                                  \
+  hipLaunchKernelGGL((forward_step_kernel<T, M, F, R, W>), dim3(nb),         \
+                     dim3(kBlock), 0, s, g, m, a.src, a.dst, a.u0, a.v0,     \
+                     a.ctrl, a.rec)
+#define MRT_FWD_W(M, F, R) \
+  if (wr) MRT_FWD(M, F, R, true); else MRT_FWD(M, F, R, false)
+#define MRT_FWD_R(M, F) \
+  if (rec) { MRT_FWD_W(M, F, true); } else { MRT_FWD_W(M, F, false); }
+#define MRT_FWD_F(M) \
+  if (first) { MRT_FWD_R(M, true); } else { MRT_FWD_R(M, false); }
+  if (g.masked) {
+    MRT_FWD_F(true);
+  } else {
+    MRT_FWD_F(false);
+  }
+#undef MRT_FWD_F
+#undef MRT_FWD_R
+#undef MRT_FWD_W
+#undef MRT_FWD
+}
+
+template <typename T>
+void launch_finalize(const Geometry& g, const T* src, T* state, T* uN, T* vN,
+                     hipStream_t s) {
+  const int nb = stencil_blocks(g);
+  if (g.masked)
+    hipLaunchKernelGGL((finalize_kernel<T, true>), dim3(nb), dim3(kBlock), 0,
+                       s, g, src, state, uN, vN);
+  else
+    hipLaunchKernelGGL((finalize_kernel<T, false>), dim3(nb), dim3(kBlock), 0,
+                       s, g, src, state, uN, vN);
+}
+
+template <typename T>
+void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
+                         const AdjLaunch<T>& a, hipStream_t s) {
+  const int nb = stencil_blocks(g);
+#define MRT_ADJ(M, F, L)                                                     \
+  hipLaunchKernelGGL((adjoint_step_kernel<T, M, F, L>), dim3(nb),            \
+                     dim3(kBlock), 0, s, g, m, a.src, a.dst, a.seed_u,       \
+                     a.seed_v, a.rec, a.g, a.adj_u0, a.adj_v0)
+#define MRT_ADJ_L(M, F) \
+  if (a.last) { MRT_ADJ(M, F, true); } else { MRT_ADJ(M, F, false); }
+#define MRT_ADJ_F(M) \
+  if (a.first) { MRT_ADJ_L(M, true); } else { MRT_ADJ_L(M, false); }
+  if (g.masked) {
+    MRT_ADJ_F(true);
+  } else {
+    MRT_ADJ_F(false);
+  }
+#undef MRT_ADJ_F
+#undef MRT_ADJ_L
+#undef MRT_ADJ
+}
+
+template <typename T>
+void launch_cost_grad(const Geometry& g, const T* uN, const T* ut,
+                      const T* ctrl, const double* gacc, T* seed, T* grad,
+                      double alpha, double* partials, double* result,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((cost_grad_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0,
+                     s, g, uN, ut, ctrl, gacc, seed, grad, alpha,
+                     partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
+                     partials, kRedBlocks, result);
+}
+
+template <typename T>
+void launch_gd_step(const Geometry& g, T* ctrl, const T* grad, double zeta,
+                    double lo, double hi, double* partials, double* result,
+                    hipStream_t s) {
+  if (zeta <= 0.0) {
+    hipLaunchKernelGGL((grad_max_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0,
+                       s, g, grad, partials);
+    hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
+                       partials, kRedBlocks, result);
+  }
+  hipLaunchKernelGGL((gd_update_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0,
+                     s, g, ctrl, grad, zeta, lo, hi, result);
+}
+
+void launch_count_fluid(const Geometry& g, double* partials, double* result,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(count_fluid_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s,
+                     g, partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
+                     partials, kRedBlocks, result);
+}
+
+#define MRT_INSTANTIATE(T)                                                   \
+  template void launch_forward_step<T>(const Geometry&, const ModelCoef<T>&, \
+                                       const FwdLaunch<T>&, hipStream_t);    \
+  template void launch_finalize<T>(const Geometry&, const T*, T*, T*, T*,    \
+                                   hipStream_t);                             \
+  template void launch_adjoint_step<T>(const Geometry&, const ModelCoef<T>&, \
+                                       const AdjLaunch<T>&, hipStream_t);    \
+  template void launch_cost_grad<T>(const Geometry&, const T*, const T*,    \
+                                    const T*, const double*, T*, T*, double, \
+                                    double*, double*, hipStream_t);          \
+  template void launch_gd_step<T>(const Geometry&, T*, const T*, double,     \
+                                  double, double, double*, double*,          \
+                                  hipStream_t);
+MRT_INSTANTIATE(float)
+MRT_INSTANTIATE(double)
+#undef MRT_INSTANTIATE
+
+}  // namespace mrt
