@@ -81,6 +81,9 @@ def main():
                     help="auto | store | K (checkpoint every K steps)")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="steps of the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 1 GiB buffer 3 times with a "
+                         "plain device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
@@ -189,6 +192,16 @@ def main():
     it.close()
     del dp
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+        del a, b
+        torch.cuda.empty_cache()
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: oracle {args.L}^2 x {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(args.L, args.cpu_steps)

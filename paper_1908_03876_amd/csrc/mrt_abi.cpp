@@ -230,6 +230,7 @@ struct mrt_tape {
   std::vector<void*> ckpt;  // ckpt[s] (s >= 1): post-collision state of step sK-1
   void* rec = nullptr;      // record slots [K][3][plane]
   uint16_t* link = nullptr;
+  uint32_t* wflag = nullptr;
   double* partials = nullptr;
   double* result = nullptr;
   double* host = nullptr;   // pinned
@@ -271,9 +272,11 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
     L.K = ckpt_every;
     L.nseg = (g.nsteps + ckpt_every - 1) / ckpt_every;
   }
-  const bool masked = g.mask != nullptr || !g.periodic;
+  const bool masked = g.mask != nullptr;
   size_t t = 2 * L.state_bytes;  // forward ping-pong
-  if (masked) t += L.plane * sizeof(uint16_t);
+  if (masked)
+    t += L.plane * sizeof(uint16_t) +
+         size_t(g.ny) * ((g.nx + 63) / 64) * sizeof(uint32_t);
   t += (size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double);
   if (L.mode > 0) {
     t += 2 * L.state_bytes;                          // adjoint ping-pong
@@ -287,7 +290,7 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
 int check_tape(const mrt_problem* p, const mrt_tape* t) {
   if (!t) return fail(MRT_EINVAL, "tape is NULL");
   const mrt_grid& g = p->grid;
-  const int masked = (g.mask != nullptr || !g.periodic) ? 1 : 0;
+  const int masked = g.mask != nullptr ? 1 : 0;
   if (g.nx != t->nx || g.ny != t->ny || g.pitch != t->pitch ||
       g.nsteps != t->nsteps || g.dtype != t->dtype ||
       g.periodic != t->periodic || masked != t->masked)
@@ -304,9 +307,12 @@ mrt::Geometry geometry(const mrt_tape* t) {
   g.nx = t->nx;
   g.ny = t->ny;
   g.pitch = t->pitch;
+  g.periodic = t->periodic;
   g.masked = t->masked;
   g.plane = t->plane;
   g.link = t->masked ? t->link : nullptr;
+  g.wflag = t->masked ? t->wflag : nullptr;
+  g.nsx = (t->nx + 63) / 64;
   return g;
 }
 
@@ -331,8 +337,8 @@ template <typename T>
 int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
                       const mrt::Geometry& g, int n0, int n1, const T* src,
                       const T* u0, const T* v0, const T* ctrl, bool record,
-                      bool write_ckpt, bool skip_last_write, int kind,
-                      hipStream_t s, const T** last) {
+                      bool write_ckpt, int kind, hipStream_t s,
+                      const T** last) {
   SpanGuard span(kind, s);
   const int seg = n0 / t->K;
   for (int n = n0; n < n1; ++n) {
@@ -345,7 +351,6 @@ int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
     T* dst = static_cast<T*>(t->buf[n & 1]);
     if (write_ckpt && t->mode == 2 && (n + 1) % t->K == 0 && n + 1 < t->nsteps)
       dst = static_cast<T*>(t->ckpt[(n + 1) / t->K]);
-    if (skip_last_write && n + 1 == n1) dst = nullptr;
     a.dst = dst;
     mrt::launch_forward_step<T>(g, m, a, s);
     span.count();
@@ -376,12 +381,12 @@ int forward_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
   const int rec_start = adj ? last_seg * t->K : N;
   if (rec_start > 0) {
     rc = run_forward_steps<T>(t, m, g, 0, rec_start, nullptr, tu0, tv0, tc,
-                              false, true, false, 0, s, &cur);
+                              false, true, 0, s, &cur);
     if (rc) return rc;
   }
   if (rec_start < N) {
     rc = run_forward_steps<T>(t, m, g, rec_start, N, cur, tu0, tv0, tc, true,
-                              true, false, 0, s, &cur);
+                              true, 0, s, &cur);
     if (rc) return rc;
   }
   mrt::launch_finalize<T>(g, cur, static_cast<T*>(state), static_cast<T*>(uN),
@@ -415,7 +420,7 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
       const T* src = seg == 0 ? nullptr : static_cast<const T*>(t->ckpt[seg]);
       const T* dummy = nullptr;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true,
-                                    false, true, 2, s, &dummy);
+                                    false, 2, s, &dummy);
       if (rc) return rc;
     }
     SpanGuard span(1, s);
@@ -515,7 +520,7 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   t->nsteps = g.nsteps;
   t->dtype = g.dtype;
   t->periodic = g.periodic;
-  t->masked = (g.mask != nullptr || !g.periodic) ? 1 : 0;
+  t->masked = g.mask != nullptr ? 1 : 0;
   t->mode = L.mode;
   t->K = L.K;
   t->nseg = L.nseg;
@@ -541,6 +546,9 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   rc = alloc(L.state_bytes, &t->buf[0]);
   if (!rc) rc = alloc(L.state_bytes, &t->buf[1]);
   if (!rc && t->masked) rc = alloc(L.plane * sizeof(uint16_t), (void**)&t->link);
+  if (!rc && t->masked)
+    rc = alloc(size_t(g.ny) * ((g.nx + 63) / 64) * sizeof(uint32_t),
+               (void**)&t->wflag);
   if (!rc)
     rc = alloc((size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double),
                (void**)&t->partials);
@@ -560,7 +568,8 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   t->result = t->partials + size_t(mrt::kRedBlocks) * mrt::kRedSlots;
   const mrt::Geometry geo = geometry(t);
   hipStream_t s = nullptr;
-  if (t->masked) mrt::launch_build_link(geo, g.periodic, g.mask, t->link, s);
+  if (t->masked)
+    mrt::launch_build_link(geo, g.periodic, g.mask, t->link, t->wflag, s);
   mrt::launch_count_fluid(geo, t->partials, t->result, s);
   rc = last_launch_error();
   if (!rc) rc = read_result(t, s, 1);

@@ -33,20 +33,25 @@ struct ModelCoef {
 
 struct Geometry {
   int nx, ny, pitch;
-  int masked;            // 1: use the link mask (walls, obstacles, non-periodic)
+  int periodic;          // 1: periodic wrap; 0: walls at the lattice edge
+  int masked;            // 1: solid nodes given by a mask (link mask in use)
   size_t plane;          // ny * pitch elements
   const uint16_t* link;  // link mask [ny][pitch] when masked, else null
+  const uint32_t* wflag; // [ny][nsx]: 1 if a 64-node row segment touches a
+                         // solid node (itself or a neighbour), when masked
+  int nsx;               // 64-node segments per row, ceil(nx / 64)
 };
 
-// Link mask: bit 0 = node solid, bit i (1..8) = node x - e_i solid
-// (outside a non-periodic domain counts as solid).
+// Link mask: bit 0 = node solid, bit i (1..8) = node x - e_i solid (wrapped
+// when periodic; outside a non-periodic lattice is handled from the node
+// coordinates, not by the mask).
 void launch_build_link(const Geometry& g, int periodic, const uint8_t* mask,
-                       uint16_t* link_out, hipStream_t s);
+                       uint16_t* link_out, uint32_t* wflag_out, hipStream_t s);
 
 template <typename T>
 struct FwdLaunch {
   const T* src;      // post-collision state of step n-1, or null (first)
-  T* dst;            // post-collision state of step n, or null (no write)
+  T* dst;            // post-collision state of step n (with wall slots)
   const T* u0;       // initial fields (first step only)
   const T* v0;
   const T* ctrl;     // control c(x)

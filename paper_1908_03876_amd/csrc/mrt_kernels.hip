@@ -17,6 +17,12 @@
 //    lambda_opp(i)(x) when x + e_i is solid (exact transpose of the pull).
 //  * Work-group order is remapped so that each of the 8 XCDs walks a
 //    contiguous band of rows (its L2 keeps the shifted-row and edge lines).
+//  * State planes and the trajectory record are streamed with non-temporal
+//    stores (and non-temporal loads in the adjoint): they are touched once
+//    per sweep and would only evict the link mask, control and gradient.
+//  * Walls cost no test in the pull: a node whose population streams into
+//    a solid neighbour also parks it in that neighbour's (otherwise unused)
+//    slot of the opposite plane, where the next pull finds it.
 //  * Reductions: wave shuffles (64 lanes), LDS across waves, one partial per
 //    block, then a single-block pass in fixed order (deterministic).
 #include <hip/hip_runtime.h>
@@ -50,6 +56,8 @@ struct NodeIdx {
   int x, y;
   int xm, xp;        // x - 1, x + 1 with periodic wrap
   size_t r0, rm, rp; // row offsets of y, y - 1, y + 1 with wrap
+  bool ex0, ex1;     // x == 0, x == nx - 1
+  bool ey0, ey1;     // y == 0, y == ny - 1
 };
 
 __device__ __forceinline__ bool node_of_block(const Geometry& g, NodeIdx& n) {
@@ -63,17 +71,37 @@ __device__ __forceinline__ bool node_of_block(const Geometry& g, NodeIdx& n) {
   n.y = t / nbx;
   n.x = (t % nbx) * kBlock + threadIdx.x;
   if (n.x >= g.nx) return false;
-  n.xm = n.x == 0 ? g.nx - 1 : n.x - 1;
-  n.xp = n.x + 1 == g.nx ? 0 : n.x + 1;
-  const int ym = n.y == 0 ? g.ny - 1 : n.y - 1;
-  const int yp = n.y + 1 == g.ny ? 0 : n.y + 1;
+  n.ex0 = n.x == 0;
+  n.ex1 = n.x + 1 == g.nx;
+  n.ey0 = n.y == 0;
+  n.ey1 = n.y + 1 == g.ny;
+  n.xm = n.ex0 ? g.nx - 1 : n.x - 1;
+  n.xp = n.ex1 ? 0 : n.x + 1;
+  const int ym = n.ey0 ? g.ny - 1 : n.y - 1;
+  const int yp = n.ey1 ? 0 : n.y + 1;
   n.r0 = size_t(n.y) * g.pitch;
   n.rm = size_t(ym) * g.pitch;
   n.rp = size_t(yp) * g.pitch;
   return true;
 }
 
-// Offset (within a plane) of node x - e_i for i = 0..8.
+// Per-wavefront wall flag (64 consecutive nodes of a row, one scalar load):
+// 0 = the nodes and their neighbours are all fluid, 1 = mixed, 2 = all
+// nodes solid.  Flag-0 wavefronts never read the link mask; in mixed ones
+// the link load is independent of the population loads, so it adds no
+// latency to them.
+__device__ __forceinline__ unsigned wave_flag(const Geometry& g,
+                                              const NodeIdx& n) {
+  const int seg = __builtin_amdgcn_readfirstlane(n.y * g.nsx + (n.x >> 6));
+  return g.wflag[seg];
+}
+
+__device__ __forceinline__ unsigned link_of(const Geometry& g, unsigned flag,
+                                            size_t idx) {
+  return flag ? unsigned(g.link[idx]) : 0u;
+}
+
+// Offset (within a plane) of node x - e_i for i = 0..8 (periodic wrap).
 __device__ __forceinline__ size_t pull_off(const NodeIdx& n, int i) {
   switch (i) {
     case 0: return n.r0 + n.x;
@@ -91,6 +119,49 @@ __device__ __forceinline__ size_t pull_off(const NodeIdx& n, int i) {
 // Offset of node x + e_i = x - e_opp(i).
 __device__ __forceinline__ size_t push_off(const NodeIdx& n, int i) {
   return pull_off(n, opp(i));
+}
+
+// Is x - e_i outside the lattice (meaningful for non-periodic lattices)?
+__device__ __forceinline__ bool pull_outside(const NodeIdx& n, int i) {
+  switch (i) {
+    case 0: return false;
+    case 1: return n.ex0;
+    case 2: return n.ey0;
+    case 3: return n.ex1;
+    case 4: return n.ey1;
+    case 5: return n.ex0 || n.ey0;
+    case 6: return n.ex1 || n.ey0;
+    case 7: return n.ex1 || n.ey1;
+    default: return n.ex0 || n.ey1;
+  }
+}
+
+// Is x + e_i outside the lattice?
+__device__ __forceinline__ bool push_outside(const NodeIdx& n, int i) {
+  return pull_outside(n, opp(i));
+}
+
+// Source of the population that node x pulls in direction i: plane i at
+// x - e_i.  A solid in-domain neighbour needs no test: its slot holds the
+// reflected population written by the previous step's wall stores.  Only
+// at the edge of a non-periodic lattice does the node take its own
+// opposite population (halfway bounce-back).
+template <bool PERIODIC>
+__device__ __forceinline__ size_t pull_src(const NodeIdx& n, int i,
+                                           size_t plane) {
+  if (!PERIODIC && pull_outside(n, i))
+    return size_t(opp(i)) * plane + n.r0 + n.x;
+  return size_t(i) * plane + pull_off(n, i);
+}
+
+// Adjoint gather source: plane i at x + e_i (transpose of the pull), or the
+// node's own opposite value at the edge of a non-periodic lattice.
+template <bool PERIODIC>
+__device__ __forceinline__ size_t gather_src(const NodeIdx& n, int i,
+                                             size_t plane) {
+  if (!PERIODIC && push_outside(n, i))
+    return size_t(opp(i)) * plane + n.r0 + n.x;
+  return size_t(i) * plane + push_off(n, i);
 }
 
 // Relaxation in moment space: f <- f - M0^-1 Pi (M0 f - m_eq(theta)).
@@ -139,9 +210,13 @@ __device__ __forceinline__ void relax(T f[9], T theta,
 
 // -------------------------------------------------------------- link mask
 
+// bit 0: node solid; bit i (1..8): x - e_i is a solid node of the lattice
+// (wrapped when periodic; outside a non-periodic lattice is not a node and
+// is handled from the coordinates).
 __global__ void build_link_kernel(Geometry g, int periodic,
                                   const uint8_t* __restrict__ mask,
-                                  uint16_t* __restrict__ link) {
+                                  uint16_t* __restrict__ link,
+                                  uint32_t* __restrict__ wflag) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
@@ -150,38 +225,38 @@ __global__ void build_link_kernel(Geometry g, int periodic,
   uint16_t bits = 0;
   for (int i = 0; i < 9; ++i) {
     int xs = x - ex[i], ys = y - ey[i];
-    bool solid;
-    if (xs < 0 || ys < 0 || xs >= g.nx || ys >= g.ny) {
-      if (!periodic) {
-        solid = true;
-      } else {
-        xs = (xs + g.nx) % g.nx;
-        ys = (ys + g.ny) % g.ny;
-        solid = mask && mask[size_t(ys) * g.pitch + xs];
-      }
-    } else {
-      solid = mask && mask[size_t(ys) * g.pitch + xs];
-    }
-    if (solid) bits |= uint16_t(1u << i);
+    const bool out = xs < 0 || ys < 0 || xs >= g.nx || ys >= g.ny;
+    if (out && !periodic) continue;
+    xs = (xs + g.nx) % g.nx;
+    ys = (ys + g.ny) % g.ny;
+    if (mask[size_t(ys) * g.pitch + xs]) bits |= uint16_t(1u << i);
   }
   link[size_t(y) * g.pitch + x] = bits;
+  // blocks are 256 wide along x, so each wavefront is one 64-node segment
+  const unsigned long long any = __ballot(bits != 0);
+  const unsigned long long fluid = __ballot((bits & 1u) == 0);
+  if ((threadIdx.x & 63) == 0)
+    wflag[size_t(y) * g.nsx + (x >> 6)] = fluid == 0ull ? 2u : (any != 0ull);
 }
 
 // --------------------------------------------------------------- forward
 
-template <typename T, bool MASKED, bool FIRST, bool RECORD, bool WRITE>
+// Recording is a run-time flag (rec != null), not a template parameter: the
+// recorded and the plain steps then run the same machine code, so a
+// checkpointed recomputation reproduces the recorded trajectory bit for bit.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
 __global__ __launch_bounds__(kBlock) void forward_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ u0, const T* __restrict__ v0,
     const T* __restrict__ ctrl, T* __restrict__ rec) {
-  const uint16_t* __restrict__ link = g.link;
   NodeIdx n;
   if (!node_of_block(g, n)) return;
   const size_t idx = n.r0 + n.x;
-  unsigned lm = 0;
+  unsigned flag = 0, lm = 0;
   if (MASKED) {
-    lm = link[idx];
-    if (lm & 1u) return;  // solid node: no populations
+    flag = wave_flag(g, n);
+    if (flag == 2u) return;  // wavefront inside a solid region
+    lm = link_of(g, flag, idx);
   }
   T fu[9], fv[9];
   if (FIRST) {
@@ -200,18 +275,12 @@ __global__ __launch_bounds__(kBlock) void forward_step_kernel(
       fv[i] = m.v.w_diag * b;
     }
   } else {
-    const T* su = src;
     const T* sv = src + 9 * g.plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      size_t o = pull_off(n, i);
-      size_t pi = size_t(i) * g.plane;
-      if (MASKED && ((lm >> i) & 1u)) {
-        o = idx;
-        pi = size_t(opp(i)) * g.plane;
-      }
-      fu[i] = su[pi + o];
-      fv[i] = sv[pi + o];
+      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
+      fu[i] = src[o];
+      fv[i] = sv[o];
     }
   }
   // macroscopic values (UGS) and the first moment of v
@@ -223,10 +292,11 @@ __global__ __launch_bounds__(kBlock) void forward_step_kernel(
   }
   const T jx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
   const T jy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
-  if (RECORD) {
-    rec[idx] = u;
-    rec[g.plane + idx] = jx;
-    rec[2 * g.plane + idx] = jy;
+  if (rec != nullptr && !(MASKED && (lm & 1u))) {
+    // the record is read back only by the adjoint sweep, much later
+    __builtin_nontemporal_store(u, &rec[idx]);
+    __builtin_nontemporal_store(jx, &rec[g.plane + idx]);
+    __builtin_nontemporal_store(jy, &rec[2 * g.plane + idx]);
   }
   // chemotactic source: A_u1 grad v = u * B * j_v with the local gradient
   // grad v = -K_v j_v / (tau d_v Cs^2)
@@ -256,41 +326,50 @@ __global__ __launch_bounds__(kBlock) void forward_step_kernel(
   for (int i = 1; i < 5; ++i) fv[i] += q9;
 #pragma unroll
   for (int i = 5; i < 9; ++i) fv[i] += q36;
-  if (WRITE) {
-    T* du = dst;
-    T* dv = dst + 9 * g.plane;
+  // solid nodes of mixed wavefronts computed on slot contents they do not
+  // own; they store nothing (their slots hold the neighbours' wall stores)
+  if (MASKED && (lm & 1u)) return;
+  // streaming (non-temporal) stores: the state does not fit the caches and
+  // is next read one whole sweep later
+  T* dv = dst + 9 * g.plane;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      du[size_t(i) * g.plane + idx] = fu[i];
-      dv[size_t(i) * g.plane + idx] = fv[i];
+  for (int i = 0; i < 9; ++i) {
+    __builtin_nontemporal_store(fu[i], &dst[size_t(i) * g.plane + idx]);
+    __builtin_nontemporal_store(fv[i], &dv[size_t(i) * g.plane + idx]);
+  }
+  if (MASKED && (lm & 0x1FEu)) {
+    // wall stores: a population phi*_i streaming into the solid node
+    // x + e_i is reflected; park it in that node's slot of plane opp(i),
+    // where the next step's pull in direction opp(i) at x reads it.
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if ((lm >> opp(i)) & 1u) {
+        const size_t o = size_t(opp(i)) * g.plane + push_off(n, i);
+        dst[o] = fu[i];
+        dv[o] = fv[i];
+      }
     }
   }
 }
 
-template <typename T, bool MASKED>
+template <typename T, bool PERIODIC, bool MASKED>
 __global__ __launch_bounds__(kBlock) void finalize_kernel(
     Geometry g, const T* __restrict__ src, T* __restrict__ state,
     T* __restrict__ uN, T* __restrict__ vN) {
-  const uint16_t* __restrict__ link = g.link;
   NodeIdx n;
   if (!node_of_block(g, n)) return;
   const size_t idx = n.r0 + n.x;
-  unsigned lm = MASKED ? link[idx] : 0u;
+  const bool solid = MASKED && (link_of(g, wave_flag(g, n), idx) & 1u);
   T fu[9], fv[9];
-  if (MASKED && (lm & 1u)) {
+  if (solid) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) fu[i] = fv[i] = T(0);
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      size_t o = pull_off(n, i);
-      size_t pi = size_t(i) * g.plane;
-      if (MASKED && ((lm >> i) & 1u)) {
-        o = idx;
-        pi = size_t(opp(i)) * g.plane;
-      }
-      fu[i] = src[pi + o];
-      fv[i] = src[9 * g.plane + pi + o];
+      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
+      fu[i] = src[o];
+      fv[i] = src[9 * g.plane + o];
     }
   }
   T u = T(0), v = T(0);
@@ -312,53 +391,55 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(
 
 // --------------------------------------------------------------- adjoint
 
-template <typename T, bool MASKED, bool FIRST, bool LAST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ seed_u, const T* __restrict__ seed_v,
     const T* __restrict__ rec, double* __restrict__ gacc,
     T* __restrict__ adj_u0, T* __restrict__ adj_v0) {
-  const uint16_t* __restrict__ link = g.link;
   NodeIdx n;
   if (!node_of_block(g, n)) return;
   const size_t idx = n.r0 + n.x;
   unsigned lm = 0;
   if (MASKED) {
-    lm = link[idx];
-    if (lm & 1u) {
-      if (FIRST) gacc[idx] = 0.0;
-      if (LAST) {
-        if (adj_u0) adj_u0[idx] = T(0);
-        if (adj_v0) adj_v0[idx] = T(0);
+    const unsigned flag = wave_flag(g, n);
+    if (FIRST || LAST) {
+      // single steps: resolve solid nodes up front, they own outputs
+      lm = g.link[idx];
+      if (lm & 1u) {
+        if (FIRST) gacc[idx] = 0.0;
+        if (LAST) {
+          if (adj_u0) adj_u0[idx] = T(0);
+          if (adj_v0) adj_v0[idx] = T(0);
+        }
+        return;
       }
-      return;
+    } else {
+      if (flag == 2u) return;  // wavefront inside a solid region
+      lm = link_of(g, flag, idx);
     }
   }
   // reverse streaming: nu_i(x) = lambda_i(x + e_i), or lambda_opp(i)(x)
-  // when x + e_i is solid (bit opp(i) of the link mask).
+  // when x + e_i is a wall (exact transpose of the pull with bounce-back)
   T nu[9], nv[9];
   if (FIRST) {
-    // terminal condition lambda_i^N = seed for every i (psi(T) = dI0/dphi)
+    // terminal condition lambda_i^N = seed for every i (psi(T) = dI0/dphi);
+    // the seed fields carry no wall slots, so walls are tested here
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      size_t o = push_off(n, i);
-      if (MASKED && ((lm >> opp(i)) & 1u)) o = idx;
+      const bool wall = (!PERIODIC && push_outside(n, i)) ||
+                        (MASKED && ((lm >> opp(i)) & 1u));
+      const size_t o = wall ? idx : push_off(n, i);
       nu[i] = seed_u[o];
       nv[i] = seed_v ? seed_v[o] : T(0);
     }
   } else {
-    const T* su = src;
     const T* sv = src + 9 * g.plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      size_t o = push_off(n, i);
-      size_t pi = size_t(i) * g.plane;
-      if (MASKED && ((lm >> opp(i)) & 1u)) {
-        o = idx;
-        pi = size_t(opp(i)) * g.plane;
-      }
-      nu[i] = su[pi + o];
-      nv[i] = sv[pi + o];
+      const size_t o = gather_src<PERIODIC>(n, i, g.plane);
+      nu[i] = __builtin_nontemporal_load(&src[o]);
+      nv[i] = __builtin_nontemporal_load(&sv[o]);
     }
   }
   // weighted sums: sigma = w . nu, p = (tau/Cs^2) sum_i w_i nu_u,i e_i
@@ -372,15 +453,18 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
                T(1.0 / 12.0) * (nu[5] - nu[6] - nu[7] + nu[8]);
   const T py = T(1.0 / 3.0) * (nu[2] - nu[4]) +
                T(1.0 / 12.0) * (nu[5] + nu[6] - nu[7] - nu[8]);
+  // solid nodes of mixed wavefronts gathered slots they do not own; they
+  // update nothing
+  if (MASKED && (lm & 1u)) return;
   // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i
   if (FIRST)
     gacc[idx] = double(sv_);
   else
     gacc[idx] += double(sv_);
   // recorded forward quantities of step n
-  const T u = rec[idx];
-  const T jx = rec[g.plane + idx];
-  const T jy = rec[2 * g.plane + idx];
+  const T u = __builtin_nontemporal_load(&rec[idx]);
+  const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
+  const T jy = __builtin_nontemporal_load(&rec[2 * g.plane + idx]);
   const T bjx = m.b00 * jx + m.b01 * jy;
   const T bjy = m.b10 * jx + m.b11 * jy;
   // transposed sources: d(tau S_u + tau Phi_u)/dphi_u is rank one along 1,
@@ -420,10 +504,23 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
                     m.v.w_axis * (nv[1] + nv[2] + nv[3] + nv[4]) +
                     m.v.w_diag * (nv[5] + nv[6] + nv[7] + nv[8]);
   } else if (dst) {
+    T* dv = dst + 9 * g.plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      dst[size_t(i) * g.plane + idx] = nu[i];
-      dst[size_t(9 + i) * g.plane + idx] = nv[i];
+      __builtin_nontemporal_store(nu[i], &dst[size_t(i) * g.plane + idx]);
+      __builtin_nontemporal_store(nv[i], &dv[size_t(i) * g.plane + idx]);
+    }
+    if (MASKED && (lm & 0x1FEu)) {
+      // wall stores of the adjoint: the next gather in direction i at x
+      // reads plane i at the solid node x + e_i and must find lambda_opp(i)(x)
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        if ((lm >> opp(i)) & 1u) {
+          const size_t o = size_t(i) * g.plane + push_off(n, i);
+          dst[o] = nu[opp(i)];
+          dv[o] = nv[opp(i)];
+        }
+      }
     }
   }
 }
@@ -583,37 +680,29 @@ int stencil_blocks(const Geometry& g) {
 // ----------------------------------------------------------- launchers
 
 void launch_build_link(const Geometry& g, int periodic, const uint8_t* mask,
-                       uint16_t* link_out, hipStream_t s) {
+                       uint16_t* link_out, uint32_t* wflag_out, hipStream_t s) {
   dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
   hipLaunchKernelGGL(build_link_kernel, grid, dim3(kBlock), 0, s, g, periodic,
-                     mask, link_out);
+                     mask, link_out, wflag_out);
 }
 
 template <typename T>
 void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
                          const FwdLaunch<T>& a, hipStream_t s) {
   const bool first = a.src == nullptr;
-  const bool rec = a.rec != nullptr;
-  const bool wr = a.dst != nullptr;
   const int nb = stencil_blocks(g);
-#define MRT_FWD(M, F, R, W)                                                  \
-  hipLaunchKernelGGL((forward_step_kernel<T, M, F, R, W>), dim3(nb),         \
+#define MRT_FWD(P, M, F)                                                     \
+  hipLaunchKernelGGL((forward_step_kernel<T, P, M, F>), dim3(nb),            \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.u0, a.v0,     \
                      a.ctrl, a.rec)
-#define MRT_FWD_W(M, F, R) \
-  if (wr) MRT_FWD(M, F, R, true); else MRT_FWD(M, F, R, false)
-#define MRT_FWD_R(M, F) \
-  if (rec) { MRT_FWD_W(M, F, true); } else { MRT_FWD_W(M, F, false); }
-#define MRT_FWD_F(M) \
-  if (first) { MRT_FWD_R(M, true); } else { MRT_FWD_R(M, false); }
-  if (g.masked) {
-    MRT_FWD_F(true);
+#define MRT_FWD_F(P, M) \
+  if (first) { MRT_FWD(P, M, true); } else { MRT_FWD(P, M, false); }
+  if (g.periodic) {
+    if (g.masked) { MRT_FWD_F(true, true); } else { MRT_FWD_F(true, false); }
   } else {
-    MRT_FWD_F(false);
+    if (g.masked) { MRT_FWD_F(false, true); } else { MRT_FWD_F(false, false); }
   }
 #undef MRT_FWD_F
-#undef MRT_FWD_R
-#undef MRT_FWD_W
 #undef MRT_FWD
 }
 
@@ -621,30 +710,33 @@ template <typename T>
 void launch_finalize(const Geometry& g, const T* src, T* state, T* uN, T* vN,
                      hipStream_t s) {
   const int nb = stencil_blocks(g);
-  if (g.masked)
-    hipLaunchKernelGGL((finalize_kernel<T, true>), dim3(nb), dim3(kBlock), 0,
-                       s, g, src, state, uN, vN);
-  else
-    hipLaunchKernelGGL((finalize_kernel<T, false>), dim3(nb), dim3(kBlock), 0,
-                       s, g, src, state, uN, vN);
+#define MRT_FIN(P, M)                                                        \
+  hipLaunchKernelGGL((finalize_kernel<T, P, M>), dim3(nb), dim3(kBlock), 0,  \
+                     s, g, src, state, uN, vN)
+  if (g.periodic) {
+    if (g.masked) MRT_FIN(true, true); else MRT_FIN(true, false);
+  } else {
+    if (g.masked) MRT_FIN(false, true); else MRT_FIN(false, false);
+  }
+#undef MRT_FIN
 }
 
 template <typename T>
 void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
                          const AdjLaunch<T>& a, hipStream_t s) {
   const int nb = stencil_blocks(g);
-#define MRT_ADJ(M, F, L)                                                     \
-  hipLaunchKernelGGL((adjoint_step_kernel<T, M, F, L>), dim3(nb),            \
+#define MRT_ADJ(P, M, F, L)                                                  \
+  hipLaunchKernelGGL((adjoint_step_kernel<T, P, M, F, L>), dim3(nb),         \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.seed_u,       \
                      a.seed_v, a.rec, a.g, a.adj_u0, a.adj_v0)
-#define MRT_ADJ_L(M, F) \
-  if (a.last) { MRT_ADJ(M, F, true); } else { MRT_ADJ(M, F, false); }
-#define MRT_ADJ_F(M) \
-  if (a.first) { MRT_ADJ_L(M, true); } else { MRT_ADJ_L(M, false); }
-  if (g.masked) {
-    MRT_ADJ_F(true);
+#define MRT_ADJ_L(P, M, F) \
+  if (a.last) { MRT_ADJ(P, M, F, true); } else { MRT_ADJ(P, M, F, false); }
+#define MRT_ADJ_F(P, M) \
+  if (a.first) { MRT_ADJ_L(P, M, true); } else { MRT_ADJ_L(P, M, false); }
+  if (g.periodic) {
+    if (g.masked) { MRT_ADJ_F(true, true); } else { MRT_ADJ_F(true, false); }
   } else {
-    MRT_ADJ_F(false);
+    if (g.masked) { MRT_ADJ_F(false, true); } else { MRT_ADJ_F(false, false); }
   }
 #undef MRT_ADJ_F
 #undef MRT_ADJ_L
