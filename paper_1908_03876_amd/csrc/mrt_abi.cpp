@@ -237,6 +237,7 @@ struct mrt_tape {
   int64_t n_fluid = 0;
   // last forward
   bool fwd_done = false;
+  int rec_seg = -1;         // segment whose (u, j_v) record the slots hold
   const void* f_u0 = nullptr;
   const void* f_v0 = nullptr;
   const void* f_ctrl = nullptr;
@@ -394,6 +395,7 @@ int forward_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
   rc = last_launch_error();
   if (rc) return rc;
   t->fwd_done = true;
+  t->rec_seg = adj ? last_seg : -1;
   t->f_u0 = u0;
   t->f_v0 = v0;
   t->f_ctrl = control;
@@ -415,13 +417,16 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
   const T* asrc = nullptr;
   for (int seg = t->nseg - 1; seg >= 0; --seg) {
     const int n0 = seg * K, n1 = std::min(N, n0 + K);
-    if (seg != t->nseg - 1) {
+    if (t->rec_seg != seg) {
       // recompute the segment from its checkpoint, recording u and j_v
+      // (also the last one when an earlier sweep overwrote its record)
       const T* src = seg == 0 ? nullptr : static_cast<const T*>(t->ckpt[seg]);
       const T* dummy = nullptr;
+      t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true,
                                     false, 2, s, &dummy);
       if (rc) return rc;
+      t->rec_seg = seg;
     }
     SpanGuard span(1, s);
     for (int n = n1 - 1; n >= n0; --n) {

@@ -137,6 +137,36 @@ def test_checkpointed_equals_store_all_bitwise():
         assert np.array_equal(ck["uN"], full["uN"]), K
 
 
+def test_repeated_adjoint_on_one_forward():
+    """Several adjoint sweeps after one forward (different seeds) are each
+    exact, also when the tape is checkpointed and the first sweep's
+    recomputation overwrote the recorded last segment."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver import DeviceProblem, Tape
+    p = I.with_control_bump(I.cfg2_small(L=128, nsteps=60), amp=3.0)
+    p = p.copy(r_u=0.05, a_uv=0.05, b_v=0.05)
+    rng = np.random.default_rng(9)
+    f = p.fluid
+    seeds = [(rng.standard_normal((p.ny, p.nx)) * f, rng.standard_normal((p.ny, p.nx)) * f)
+             for _ in range(3)]
+    refs = [O.adjoint(p, a, b) for a, b in seeds]
+    for K in (-1, 7, 25):
+        dp = DeviceProblem(p, dtype=torch.float64)
+        t = Tape(dp, K)
+        abi.mrt_forward(dp.struct, t.handle, dp.u0, dp.v0, dp.control)
+        for (a, b), (g, gu0, gv0) in zip(seeds, refs):
+            gacc = dp.empty_field(torch.float64)
+            au0, av0 = dp.empty_field(), dp.empty_field()
+            abi.amrt_adjoint(dp.struct, t.handle, dp.u0, dp.v0, dp.control,
+                             dp.field(a), dp.field(b), gacc, au0, av0)
+            torch.cuda.synchronize()
+            assert rel_l2(dp.host(gacc), g, f) <= 1e-12, K
+            assert rel_l2(dp.host(au0), gu0, f) <= 1e-12, K
+            assert rel_l2(dp.host(av0), gv0, f) <= 1e-12, K
+        t.close()
+
+
 def test_deterministic_rerun():
     """Reductions have a fixed order and kernels no races: reruns are
     bitwise identical."""
