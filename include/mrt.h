@@ -205,6 +205,85 @@ int mrt_timing_reset(void);
 int mrt_timing_read(int32_t kind, double* ms /* host */,
                     int64_t* launches /* host */);
 
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent control problems of uneven size advanced
+ * together.  Each gradient iteration (forward, cost and seed, AMRT sweep,
+ * gradient and norms, gradient step, for every instance; Section 3.2.1's
+ * discrete optimisation loop) runs the forward pass and the adjoint pass as
+ * one persistent launch each, with a grid barrier between time steps, and
+ * can be captured once in a HIP graph and replayed.  Problems must be
+ * periodic, unmasked and square with pitch == nx, and share dtype and
+ * nsteps; chi, tensors, rates, reactions and alpha may differ.  The batch
+ * owns every field of every instance (instance-major, [L][L] each).
+ * ---------------------------------------------------------------------- */
+
+typedef struct mrt_batch mrt_batch;
+
+enum {
+  MRT_FIELD_U0 = 0,
+  MRT_FIELD_V0 = 1,
+  MRT_FIELD_CONTROL = 2,
+  MRT_FIELD_TARGET = 3,
+  MRT_FIELD_UN = 4,
+  MRT_FIELD_VN = 5,
+  MRT_FIELD_GRAD = 6
+};
+
+/* Launch shape of the persistent kernels: tiles of tile_w x (256/tile_w)
+ * nodes (tile_w 64, 128 or 256) and blocks_per_cu resident work-groups per
+ * compute unit (1..max_blocks_per_cu, the occupancy limit, so that every
+ * work-group of a persistent launch is resident). */
+typedef struct mrt_batch_tiles {
+  int32_t tile_w;
+  int32_t blocks_per_cu;
+  int32_t max_blocks_per_cu; /* output only */
+  int32_t reserved;
+  double ms_per_step;        /* output of mrt_batch_tune */
+} mrt_batch_tiles;
+
+/* ckpt_every: segment length of the checkpointed record (<= 0 or >= nsteps:
+ * record every step).  MRT_ENOMEM if mem_budget > 0 is exceeded. */
+int mrt_batch_create(const mrt_problem* problems, int32_t count,
+                     int32_t ckpt_every, size_t mem_budget, mrt_batch** out);
+void mrt_batch_destroy(mrt_batch* b);
+
+/* Device pointer of field `which` of instance k ([L][L], grid dtype). */
+int mrt_batch_field(mrt_batch* b, int32_t k, int32_t which, void** ptr);
+
+/* Device-to-device copy of field `which` of instance k from (to_batch = 1)
+ * or to (to_batch = 0) the caller's buffer `data` ([L][L]).  Asynchronous. */
+int mrt_batch_copy(mrt_batch* b, int32_t k, int32_t which, int32_t to_batch,
+                   void* data, void* stream);
+
+int mrt_batch_set_tiles(mrt_batch* b, const mrt_batch_tiles* tiles);
+int mrt_batch_get_tiles(mrt_batch* b, mrt_batch_tiles* tiles /* host */);
+
+/* Autotuner: times a `steps`-step forward pass for every tile width and
+ * power-of-two residency, keeps the fastest and returns it.  Synchronises
+ * `stream`; overwrites the forward work buffers (not the fields). */
+int mrt_batch_tune(mrt_batch* b, int32_t steps, mrt_batch_tiles* best /* host */,
+                   void* stream);
+
+/* Limit of a grid-barrier wait (default 2 s).  A wait beyond it aborts the
+ * persistent launch (it always terminates) and mrt_batch_scalars reports
+ * MRT_EHIP.  Exists so that the failure path can be exercised. */
+int mrt_batch_set_timeout(mrt_batch* b, double seconds);
+
+/* One gradient iteration for every instance: controls are updated in place
+ * with zeta (<= 0: per-instance min(1, 1/||E_k||_inf)).  use_graph = 1
+ * captures the iteration in a HIP graph on first use (and after a change of
+ * zeta or tiles) and replays it.  Asynchronous on `stream`. */
+int mrt_batch_iteration(mrt_batch* b, double zeta, int32_t use_graph,
+                        void* stream);
+
+/* Per-instance scalars of the last iteration (out[count], host): J and its
+ * parts at the control before the update, gradient norms, and the step
+ * used (zeta_used[count], NULL ok).  Synchronises `stream`; MRT_EHIP if a
+ * grid barrier timed out, MRT_ENONFINITE if a value is not finite. */
+int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

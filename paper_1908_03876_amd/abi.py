@@ -58,10 +58,23 @@ class mrt_tape_info(ctypes.Structure):
                 ("n_fluid", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
 
 
+class mrt_batch_tiles(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("max_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_double)]
+
+
+MRT_FIELD_U0, MRT_FIELD_V0, MRT_FIELD_CONTROL, MRT_FIELD_TARGET = 0, 1, 2, 3
+MRT_FIELD_UN, MRT_FIELD_VN, MRT_FIELD_GRAD = 4, 5, 6
+
 EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
            "cost_gradient", "gd_step", "mrt_last_error", "mrt_timing_enable",
-           "mrt_timing_reset", "mrt_timing_read"]
+           "mrt_timing_reset", "mrt_timing_read",
+           "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
+           "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
+           "mrt_batch_tune", "mrt_batch_set_timeout", "mrt_batch_iteration",
+           "mrt_batch_scalars"]
 
 
 def _load():
@@ -89,6 +102,20 @@ def _load():
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
     L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
+    T = ctypes.POINTER(mrt_batch_tiles)
+    L.mrt_batch_create.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
+                                   ctypes.POINTER(vp)]
+    L.mrt_batch_destroy.argtypes = [vp]
+    L.mrt_batch_destroy.restype = None
+    L.mrt_batch_field.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.mrt_batch_copy.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    L.mrt_batch_set_tiles.argtypes = [vp, T]
+    L.mrt_batch_get_tiles.argtypes = [vp, T]
+    L.mrt_batch_tune.argtypes = [vp, ctypes.c_int32, T, vp]
+    L.mrt_batch_set_timeout.argtypes = [vp, ctypes.c_double]
+    L.mrt_batch_iteration.argtypes = [vp, ctypes.c_double, ctypes.c_int32, vp]
+    L.mrt_batch_scalars.argtypes = [vp, ctypes.POINTER(mrt_scalars),
+                                    ctypes.POINTER(ctypes.c_double), vp]
     return L
 
 
@@ -192,3 +219,66 @@ def mrt_timing_read(kind: int):
     n = ctypes.c_int64()
     _check(lib.mrt_timing_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+# ------------------------------------------------------------- batched form
+
+def mrt_batch_create(problems, ckpt_every: int = 0, mem_budget: int = 0):
+    arr = (mrt_problem * len(problems))(*problems)
+    h = ctypes.c_void_p()
+    _check(lib.mrt_batch_create(arr, len(problems), int(ckpt_every), int(mem_budget),
+                                ctypes.byref(h)))
+    return h
+
+
+def mrt_batch_destroy(batch) -> None:
+    lib.mrt_batch_destroy(batch)
+
+
+def mrt_batch_field(batch, k: int, which: int) -> int:
+    p = ctypes.c_void_p()
+    _check(lib.mrt_batch_field(batch, int(k), int(which), ctypes.byref(p)))
+    return p.value
+
+
+def mrt_batch_copy(batch, k: int, which: int, to_batch: bool, data, stream=None) -> None:
+    _check(lib.mrt_batch_copy(batch, int(k), int(which), 1 if to_batch else 0,
+                              _ptr(data), _stream(stream)))
+
+
+def mrt_batch_set_tiles(batch, tile_w: int, blocks_per_cu: int) -> None:
+    t = mrt_batch_tiles(tile_w=int(tile_w), blocks_per_cu=int(blocks_per_cu))
+    _check(lib.mrt_batch_set_tiles(batch, ctypes.byref(t)))
+
+
+def mrt_batch_get_tiles(batch) -> dict:
+    t = mrt_batch_tiles()
+    _check(lib.mrt_batch_get_tiles(batch, ctypes.byref(t)))
+    return {"tile_w": t.tile_w, "blocks_per_cu": t.blocks_per_cu,
+            "max_blocks_per_cu": t.max_blocks_per_cu}
+
+
+def mrt_batch_tune(batch, steps: int = 20, stream=None) -> dict:
+    t = mrt_batch_tiles()
+    _check(lib.mrt_batch_tune(batch, int(steps), ctypes.byref(t), _stream(stream)))
+    return {"tile_w": t.tile_w, "blocks_per_cu": t.blocks_per_cu,
+            "max_blocks_per_cu": t.max_blocks_per_cu, "ms_per_step": t.ms_per_step}
+
+
+def mrt_batch_set_timeout(batch, seconds: float) -> None:
+    _check(lib.mrt_batch_set_timeout(batch, float(seconds)))
+
+
+def mrt_batch_iteration(batch, zeta: float = 0.0, use_graph: bool = True,
+                        stream=None) -> None:
+    _check(lib.mrt_batch_iteration(batch, float(zeta), 1 if use_graph else 0,
+                                   _stream(stream)))
+
+
+def mrt_batch_scalars(batch, count: int, stream=None):
+    out = (mrt_scalars * count)()
+    z = (ctypes.c_double * count)()
+    _check(lib.mrt_batch_scalars(batch, out, z, _stream(stream)))
+    return [{"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
+             "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid,
+             "zeta": z[i]} for i, s in enumerate(out)]

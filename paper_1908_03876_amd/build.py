@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmrt.so")
 
-SOURCES = ["mrt_kernels.hip", "mrt_abi.cpp"]
+SOURCES = ["mrt_kernels.hip", "batch_kernels.hip", "mrt_abi.cpp", "mrt_batch.cpp"]
 
 
 def hipcc() -> str:

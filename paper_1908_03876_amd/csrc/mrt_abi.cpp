@@ -219,6 +219,19 @@ struct SpanGuard {
 
 }  // namespace
 
+namespace mrt {
+namespace host {
+int validate(const mrt_problem* p) { return ::validate(p); }
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+template <typename T>
+ModelCoef<T> model_coef(const mrt_problem* p) {
+  return ::model_coef<T>(p);
+}
+template ModelCoef<float> model_coef<float>(const mrt_problem*);
+template ModelCoef<double> model_coef<double>(const mrt_problem*);
+}  // namespace host
+}  // namespace mrt
+
 // ------------------------------------------------------------------ tape
 
 struct mrt_tape {

@@ -105,4 +105,15 @@ void launch_gd_step(const Geometry& g, T* ctrl,
 void launch_count_fluid(const Geometry& g, double* partials, double* result,
                         hipStream_t s);
 
+// Host helpers of the runtime (mrt_abi.cpp), shared with the batch runtime.
+}  // namespace mrt
+
+struct mrt_problem;
+namespace mrt {
+namespace host {
+int validate(const mrt_problem* p);        // MRT_OK or MRT_EINVAL, sets the error
+int set_error(int code, const char* msg);  // records a message, returns code
+template <typename T>
+ModelCoef<T> model_coef(const mrt_problem* p);
+}  // namespace host
 }  // namespace mrt

@@ -29,184 +29,13 @@
 
 #include <cmath>
 
+#include "mrt_device.h"
 #include "mrt_internal.h"
 
 namespace mrt {
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;
-
-// D2Q9 opposite directions: e3 = -e1, e4 = -e2, e7 = -e5, e8 = -e6.
-__device__ __forceinline__ constexpr int opp(int i) {
-  return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
-}
-
-// Linear work-group id -> tile id such that XCD k (ids = k mod 8) owns the
-// contiguous tile range [k*n/8, (k+1)*n/8).
-__device__ __forceinline__ int xcd_tile(int id, int n) {
-  const int per = n / kXcds, rem = n % kXcds;
-  const int xcd = id % kXcds, k = id / kXcds;
-  // the first `rem` XCDs own per+1 tiles
-  const int base = xcd * per + (xcd < rem ? xcd : rem);
-  return base + k;
-}
-
-struct NodeIdx {
-  int x, y;
-  int xm, xp;        // x - 1, x + 1 with periodic wrap
-  size_t r0, rm, rp; // row offsets of y, y - 1, y + 1 with wrap
-  bool ex0, ex1;     // x == 0, x == nx - 1
-  bool ey0, ey1;     // y == 0, y == ny - 1
-};
-
-__device__ __forceinline__ bool node_of_block(const Geometry& g, NodeIdx& n) {
-  const int nbx = (g.nx + kBlock - 1) / kBlock;
-  const int ntiles = nbx * g.ny;
-  const int id = blockIdx.x;
-  if (id >= ntiles) return false;
-  // each XCD owns ntiles/8 (+1) tiles; the id -> tile map is a bijection
-  // on [0, ntiles) because ids are dealt round-robin to XCDs.
-  const int t = xcd_tile(id, ntiles);
-  n.y = t / nbx;
-  n.x = (t % nbx) * kBlock + threadIdx.x;
-  if (n.x >= g.nx) return false;
-  n.ex0 = n.x == 0;
-  n.ex1 = n.x + 1 == g.nx;
-  n.ey0 = n.y == 0;
-  n.ey1 = n.y + 1 == g.ny;
-  n.xm = n.ex0 ? g.nx - 1 : n.x - 1;
-  n.xp = n.ex1 ? 0 : n.x + 1;
-  const int ym = n.ey0 ? g.ny - 1 : n.y - 1;
-  const int yp = n.ey1 ? 0 : n.y + 1;
-  n.r0 = size_t(n.y) * g.pitch;
-  n.rm = size_t(ym) * g.pitch;
-  n.rp = size_t(yp) * g.pitch;
-  return true;
-}
-
-// Per-wavefront wall flag (64 consecutive nodes of a row, one scalar load):
-// 0 = the nodes and their neighbours are all fluid, 1 = mixed, 2 = all
-// nodes solid.  Flag-0 wavefronts never read the link mask; in mixed ones
-// the link load is independent of the population loads, so it adds no
-// latency to them.
-__device__ __forceinline__ unsigned wave_flag(const Geometry& g,
-                                              const NodeIdx& n) {
-  const int seg = __builtin_amdgcn_readfirstlane(n.y * g.nsx + (n.x >> 6));
-  return g.wflag[seg];
-}
-
-__device__ __forceinline__ unsigned link_of(const Geometry& g, unsigned flag,
-                                            size_t idx) {
-  return flag ? unsigned(g.link[idx]) : 0u;
-}
-
-// Offset (within a plane) of node x - e_i for i = 0..8 (periodic wrap).
-__device__ __forceinline__ size_t pull_off(const NodeIdx& n, int i) {
-  switch (i) {
-    case 0: return n.r0 + n.x;
-    case 1: return n.r0 + n.xm;   // e1 = (1,0)
-    case 2: return n.rm + n.x;    // e2 = (0,1)
-    case 3: return n.r0 + n.xp;   // e3 = (-1,0)
-    case 4: return n.rp + n.x;    // e4 = (0,-1)
-    case 5: return n.rm + n.xm;   // e5 = (1,1)
-    case 6: return n.rm + n.xp;   // e6 = (-1,1)
-    case 7: return n.rp + n.xp;   // e7 = (-1,-1)
-    default: return n.rp + n.xm;  // e8 = (1,-1)
-  }
-}
-
-// Offset of node x + e_i = x - e_opp(i).
-__device__ __forceinline__ size_t push_off(const NodeIdx& n, int i) {
-  return pull_off(n, opp(i));
-}
-
-// Is x - e_i outside the lattice (meaningful for non-periodic lattices)?
-__device__ __forceinline__ bool pull_outside(const NodeIdx& n, int i) {
-  switch (i) {
-    case 0: return false;
-    case 1: return n.ex0;
-    case 2: return n.ey0;
-    case 3: return n.ex1;
-    case 4: return n.ey1;
-    case 5: return n.ex0 || n.ey0;
-    case 6: return n.ex1 || n.ey0;
-    case 7: return n.ex1 || n.ey1;
-    default: return n.ex0 || n.ey1;
-  }
-}
-
-// Is x + e_i outside the lattice?
-__device__ __forceinline__ bool push_outside(const NodeIdx& n, int i) {
-  return pull_outside(n, opp(i));
-}
-
-// Source of the population that node x pulls in direction i: plane i at
-// x - e_i.  A solid in-domain neighbour needs no test: its slot holds the
-// reflected population written by the previous step's wall stores.  Only
-// at the edge of a non-periodic lattice does the node take its own
-// opposite population (halfway bounce-back).
-template <bool PERIODIC>
-__device__ __forceinline__ size_t pull_src(const NodeIdx& n, int i,
-                                           size_t plane) {
-  if (!PERIODIC && pull_outside(n, i))
-    return size_t(opp(i)) * plane + n.r0 + n.x;
-  return size_t(i) * plane + pull_off(n, i);
-}
-
-// Adjoint gather source: plane i at x + e_i (transpose of the pull), or the
-// node's own opposite value at the edge of a non-periodic lattice.
-template <bool PERIODIC>
-__device__ __forceinline__ size_t gather_src(const NodeIdx& n, int i,
-                                             size_t plane) {
-  if (!PERIODIC && push_outside(n, i))
-    return size_t(opp(i)) * plane + n.r0 + n.x;
-  return size_t(i) * plane + push_off(n, i);
-}
-
-// Relaxation in moment space: f <- f - M0^-1 Pi (M0 f - m_eq(theta)).
-// With theta = 0 and the K block transposed this is f <- f - C^T f
-// (C^T = M0^-1 Pi^T M0 since Pi only couples moments of equal row norm),
-// without the conserved zeroth-moment part.  Returns the scaled amounts
-// (a1, a2) of the e and epsilon moments for the adjoint equilibrium term.
-template <typename T>
-__device__ __forceinline__ void relax(T f[9], T theta,
-                                      const SpeciesCoef<T>& c, T& a1o,
-                                      T& a2o) {
-  const T sa = f[1] + f[2] + f[3] + f[4];
-  const T sd = f[5] + f[6] + f[7] + f[8];
-  const T m1 = T(-4) * f[0] - sa + T(2) * sd;       // e
-  const T m2 = T(4) * f[0] - T(2) * sa + sd;        // epsilon
-  const T dx = f[5] - f[6] - f[7] + f[8];
-  const T dy = f[5] + f[6] - f[7] - f[8];
-  const T m3 = f[1] - f[3] + dx;                    // j_x
-  const T m4 = T(-2) * (f[1] - f[3]) + dx;          // q_x
-  const T m5 = f[2] - f[4] + dy;                    // j_y
-  const T m6 = T(-2) * (f[2] - f[4]) + dy;          // q_y
-  const T m7 = f[1] - f[2] + f[3] - f[4];           // p_xx
-  const T m8 = f[5] - f[6] + f[7] - f[8];           // p_xy
-  const T a1 = c.s1 * (m1 - c.e_eq * theta);
-  const T a2 = c.s2 * (m2 - c.eps_eq * theta);
-  const T a3 = c.k00 * m3 + c.k01 * m5;
-  const T a5 = c.k10 * m3 + c.k11 * m5;
-  const T a4 = c.s3 * m4;
-  const T a6 = c.s4 * m6;
-  const T a7 = c.s5 * m7;
-  const T a8 = c.s6 * m8;
-  const T b = T(2) * a1 + a2;
-  const T h = -a1 - T(2) * a2;
-  f[0] -= T(4) * (a2 - a1);
-  f[1] -= h + a3 - T(2) * a4 + a7;
-  f[2] -= h + a5 - T(2) * a6 - a7;
-  f[3] -= h - a3 + T(2) * a4 + a7;
-  f[4] -= h - a5 + T(2) * a6 - a7;
-  f[5] -= b + a3 + a4 + a5 + a6 + a8;
-  f[6] -= b - a3 - a4 + a5 + a6 - a8;
-  f[7] -= b - a3 - a4 - a5 - a6 + a8;
-  f[8] -= b + a3 + a4 - a5 - a6 - a8;
-  a1o = a1;
-  a2o = a2;
-}
+using namespace dev;
 
 // -------------------------------------------------------------- link mask
 
@@ -239,11 +68,6 @@ __global__ void build_link_kernel(Geometry g, int periodic,
     wflag[size_t(y) * g.nsx + (x >> 6)] = fluid == 0ull ? 2u : (any != 0ull);
 }
 
-// --------------------------------------------------------------- forward
-
-// Recording is a run-time flag (rec != null), not a template parameter: the
-// recorded and the plain steps then run the same machine code, so a
-// checkpointed recomputation reproduces the recorded trajectory bit for bit.
 template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
 __global__ __launch_bounds__(kBlock) void forward_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
@@ -251,105 +75,7 @@ __global__ __launch_bounds__(kBlock) void forward_step_kernel(
     const T* __restrict__ ctrl, T* __restrict__ rec) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  const size_t idx = n.r0 + n.x;
-  unsigned flag = 0, lm = 0;
-  if (MASKED) {
-    flag = wave_flag(g, n);
-    if (flag == 2u) return;  // wavefront inside a solid region
-    lm = link_of(g, flag, idx);
-  }
-  T fu[9], fv[9];
-  if (FIRST) {
-    // equilibrium initialisation phi_i = w_i Theta_0 (phieq, zero flux)
-    const T a = u0[idx], b = v0[idx];
-    fu[0] = m.u.w_rest * a;
-    fv[0] = m.v.w_rest * b;
-#pragma unroll
-    for (int i = 1; i < 5; ++i) {
-      fu[i] = m.u.w_axis * a;
-      fv[i] = m.v.w_axis * b;
-    }
-#pragma unroll
-    for (int i = 5; i < 9; ++i) {
-      fu[i] = m.u.w_diag * a;
-      fv[i] = m.v.w_diag * b;
-    }
-  } else {
-    const T* sv = src + 9 * g.plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
-      fu[i] = src[o];
-      fv[i] = sv[o];
-    }
-  }
-  // macroscopic values (UGS) and the first moment of v
-  T u = T(0), v = T(0);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    u += fu[i];
-    v += fv[i];
-  }
-  const T jx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
-  const T jy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
-  if (rec != nullptr && !(MASKED && (lm & 1u))) {
-    // the record is read back only by the adjoint sweep, much later
-    __builtin_nontemporal_store(u, &rec[idx]);
-    __builtin_nontemporal_store(jx, &rec[g.plane + idx]);
-    __builtin_nontemporal_store(jy, &rec[2 * g.plane + idx]);
-  }
-  // chemotactic source: A_u1 grad v = u * B * j_v with the local gradient
-  // grad v = -K_v j_v / (tau d_v Cs^2)
-  const T ax = u * (m.b00 * jx + m.b01 * jy);
-  const T ay = u * (m.b10 * jx + m.b11 * jy);
-  const T phu = m.r_u * u * (T(1) - u);
-  const T phv = m.a_uv * u - m.b_v * v + ctrl[idx];
-  T t1, t2;
-  relax(fu, u, m.u, t1, t2);
-  relax(fv, v, m.v, t1, t2);
-  // sources tau S_i + tau w_i Phi (S, PhiS), tau = 1, 1/Cs^2 = 3
-  const T p9 = phu * T(1.0 / 9.0), p36 = phu * T(1.0 / 36.0);
-  const T x3 = ax * T(1.0 / 3.0), y3 = ay * T(1.0 / 3.0);
-  const T x12 = ax * T(1.0 / 12.0), y12 = ay * T(1.0 / 12.0);
-  fu[0] += phu * T(4.0 / 9.0);
-  fu[1] += p9 + x3;
-  fu[2] += p9 + y3;
-  fu[3] += p9 - x3;
-  fu[4] += p9 - y3;
-  fu[5] += p36 + x12 + y12;
-  fu[6] += p36 - x12 + y12;
-  fu[7] += p36 - x12 - y12;
-  fu[8] += p36 + x12 - y12;
-  const T q9 = phv * T(1.0 / 9.0), q36 = phv * T(1.0 / 36.0);
-  fv[0] += phv * T(4.0 / 9.0);
-#pragma unroll
-  for (int i = 1; i < 5; ++i) fv[i] += q9;
-#pragma unroll
-  for (int i = 5; i < 9; ++i) fv[i] += q36;
-  // solid nodes of mixed wavefronts computed on slot contents they do not
-  // own; they store nothing (their slots hold the neighbours' wall stores)
-  if (MASKED && (lm & 1u)) return;
-  // streaming (non-temporal) stores: the state does not fit the caches and
-  // is next read one whole sweep later
-  T* dv = dst + 9 * g.plane;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    __builtin_nontemporal_store(fu[i], &dst[size_t(i) * g.plane + idx]);
-    __builtin_nontemporal_store(fv[i], &dv[size_t(i) * g.plane + idx]);
-  }
-  if (MASKED && (lm & 0x1FEu)) {
-    // wall stores: a population phi*_i streaming into the solid node
-    // x + e_i is reflected; park it in that node's slot of plane opp(i),
-    // where the next step's pull in direction opp(i) at x reads it.
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      if ((lm >> opp(i)) & 1u) {
-        const size_t o = size_t(opp(i)) * g.plane + push_off(n, i);
-        dst[o] = fu[i];
-        dv[o] = fv[i];
-      }
-    }
-  }
+  forward_node<T, PERIODIC, MASKED, FIRST>(g, n, m, src, dst, u0, v0, ctrl, rec);
 }
 
 template <typename T, bool PERIODIC, bool MASKED>
@@ -358,38 +84,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(
     T* __restrict__ uN, T* __restrict__ vN) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  const size_t idx = n.r0 + n.x;
-  const bool solid = MASKED && (link_of(g, wave_flag(g, n), idx) & 1u);
-  T fu[9], fv[9];
-  if (solid) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fu[i] = fv[i] = T(0);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
-      fu[i] = src[o];
-      fv[i] = src[9 * g.plane + o];
-    }
-  }
-  T u = T(0), v = T(0);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    u += fu[i];
-    v += fv[i];
-  }
-  if (uN) uN[idx] = u;
-  if (vN) vN[idx] = v;
-  if (state) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      state[size_t(i) * g.plane + idx] = fu[i];
-      state[size_t(9 + i) * g.plane + idx] = fv[i];
-    }
-  }
+  finalize_node<T, PERIODIC, MASKED>(g, n, src, state, uN, vN);
 }
-
-// --------------------------------------------------------------- adjoint
 
 template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
@@ -399,166 +95,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     T* __restrict__ adj_u0, T* __restrict__ adj_v0) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  const size_t idx = n.r0 + n.x;
-  unsigned lm = 0;
-  if (MASKED) {
-    const unsigned flag = wave_flag(g, n);
-    if (FIRST || LAST) {
-      // single steps: resolve solid nodes up front, they own outputs
-      lm = g.link[idx];
-      if (lm & 1u) {
-        if (FIRST) gacc[idx] = 0.0;
-        if (LAST) {
-          if (adj_u0) adj_u0[idx] = T(0);
-          if (adj_v0) adj_v0[idx] = T(0);
-        }
-        return;
-      }
-    } else {
-      if (flag == 2u) return;  // wavefront inside a solid region
-      lm = link_of(g, flag, idx);
-    }
-  }
-  // reverse streaming: nu_i(x) = lambda_i(x + e_i), or lambda_opp(i)(x)
-  // when x + e_i is a wall (exact transpose of the pull with bounce-back)
-  T nu[9], nv[9];
-  if (FIRST) {
-    // terminal condition lambda_i^N = seed for every i (psi(T) = dI0/dphi);
-    // the seed fields carry no wall slots, so walls are tested here
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const bool wall = (!PERIODIC && push_outside(n, i)) ||
-                        (MASKED && ((lm >> opp(i)) & 1u));
-      const size_t o = wall ? idx : push_off(n, i);
-      nu[i] = seed_u[o];
-      nv[i] = seed_v ? seed_v[o] : T(0);
-    }
-  } else {
-    const T* sv = src + 9 * g.plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const size_t o = gather_src<PERIODIC>(n, i, g.plane);
-      nu[i] = __builtin_nontemporal_load(&src[o]);
-      nv[i] = __builtin_nontemporal_load(&sv[o]);
-    }
-  }
-  // weighted sums: sigma = w . nu, p = (tau/Cs^2) sum_i w_i nu_u,i e_i
-  const T su_ = T(4.0 / 9.0) * nu[0] +
-                T(1.0 / 9.0) * (nu[1] + nu[2] + nu[3] + nu[4]) +
-                T(1.0 / 36.0) * (nu[5] + nu[6] + nu[7] + nu[8]);
-  const T sv_ = T(4.0 / 9.0) * nv[0] +
-                T(1.0 / 9.0) * (nv[1] + nv[2] + nv[3] + nv[4]) +
-                T(1.0 / 36.0) * (nv[5] + nv[6] + nv[7] + nv[8]);
-  const T px = T(1.0 / 3.0) * (nu[1] - nu[3]) +
-               T(1.0 / 12.0) * (nu[5] - nu[6] - nu[7] + nu[8]);
-  const T py = T(1.0 / 3.0) * (nu[2] - nu[4]) +
-               T(1.0 / 12.0) * (nu[5] + nu[6] - nu[7] - nu[8]);
-  // solid nodes of mixed wavefronts gathered slots they do not own; they
-  // update nothing
-  if (MASKED && (lm & 1u)) return;
-  // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i
-  if (FIRST)
-    gacc[idx] = double(sv_);
-  else
-    gacc[idx] += double(sv_);
-  // recorded forward quantities of step n
-  const T u = __builtin_nontemporal_load(&rec[idx]);
-  const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
-  const T jy = __builtin_nontemporal_load(&rec[2 * g.plane + idx]);
-  const T bjx = m.b00 * jx + m.b01 * jy;
-  const T bjy = m.b10 * jx + m.b11 * jy;
-  // transposed sources: d(tau S_u + tau Phi_u)/dphi_u is rank one along 1,
-  // d(tau S_u)/dphi_v = (tau/Cs^2) diag(w) E u B E^T, dPhi_v/dphi = (a, -b).
-  const T cu = su_ * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
-               sv_ * m.a_uv;
-  const T cv = -sv_ * m.b_v;
-  const T qx = u * (m.b00 * px + m.b10 * py);
-  const T qy = u * (m.b01 * px + m.b11 * py);
-  // adjoint collision: nu - C^T nu + 1 * weq^T C^T nu  (AEDs with O = 1 weq^T)
-  T a1, a2;
-  relax(nu, T(0), m.ut, a1, a2);
-  const T wu = m.u.e_eq * a1 + m.u.eps_eq * a2 + cu;
-  relax(nv, T(0), m.vt, a1, a2);
-  const T wv = m.v.e_eq * a1 + m.v.eps_eq * a2 + cv;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    nu[i] += wu;
-    nv[i] += wv;
-  }
-  nv[1] += qx;
-  nv[2] += qy;
-  nv[3] -= qx;
-  nv[4] -= qy;
-  nv[5] += qx + qy;
-  nv[6] += qy - qx;
-  nv[7] -= qx + qy;
-  nv[8] += qx - qy;
-  if (LAST) {
-    // transpose of phi_i^0 = w_i Theta_0
-    if (adj_u0)
-      adj_u0[idx] = m.u.w_rest * nu[0] +
-                    m.u.w_axis * (nu[1] + nu[2] + nu[3] + nu[4]) +
-                    m.u.w_diag * (nu[5] + nu[6] + nu[7] + nu[8]);
-    if (adj_v0)
-      adj_v0[idx] = m.v.w_rest * nv[0] +
-                    m.v.w_axis * (nv[1] + nv[2] + nv[3] + nv[4]) +
-                    m.v.w_diag * (nv[5] + nv[6] + nv[7] + nv[8]);
-  } else if (dst) {
-    T* dv = dst + 9 * g.plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      __builtin_nontemporal_store(nu[i], &dst[size_t(i) * g.plane + idx]);
-      __builtin_nontemporal_store(nv[i], &dv[size_t(i) * g.plane + idx]);
-    }
-    if (MASKED && (lm & 0x1FEu)) {
-      // wall stores of the adjoint: the next gather in direction i at x
-      // reads plane i at the solid node x + e_i and must find lambda_opp(i)(x)
-#pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        if ((lm >> opp(i)) & 1u) {
-          const size_t o = size_t(i) * g.plane + push_off(n, i);
-          dst[o] = nu[opp(i)];
-          dv[o] = nv[opp(i)];
-        }
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------ reductions
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  return v;
-}
-
-// Block reduction of kRedSlots values (slot 3 is a max, the others sums);
-// lane 0 of the block writes the block partial.
-__device__ void block_reduce_store(double vals[kRedSlots], double* out) {
-  __shared__ double lds[kRedSlots][kBlock / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kRedSlots; ++k) {
-    double r = (k == 3) ? wave_max(vals[k]) : wave_sum(vals[k]);
-    if (lane == 0) lds[k][wave] = r;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kRedSlots; ++k) {
-      double r = lds[k][0];
-      for (int w = 1; w < kBlock / 64; ++w)
-        r = (k == 3) ? fmax(r, lds[k][w]) : r + lds[k][w];
-      out[k] = r;
-    }
-  }
+  adjoint_node<T, PERIODIC, MASKED, FIRST, LAST>(g, n, m, src, dst, seed_u, seed_v, rec, gacc, adj_u0, adj_v0);
 }
 
 __device__ __forceinline__ bool is_fluid(const uint16_t* link, size_t idx) {
