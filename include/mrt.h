@@ -242,8 +242,9 @@ typedef struct mrt_batch_tiles {
   double ms_per_step;        /* output of mrt_batch_tune */
 } mrt_batch_tiles;
 
-/* ckpt_every: segment length of the checkpointed record (<= 0 or >= nsteps:
- * record every step).  MRT_ENOMEM if mem_budget > 0 is exceeded. */
+/* ckpt_every: segment length of the checkpointed record (0 or >= nsteps:
+ * record every step; < 0: forward solves only, mrt_batch_forward, no
+ * adjoint buffers).  MRT_ENOMEM if mem_budget > 0 is exceeded. */
 int mrt_batch_create(const mrt_problem* problems, int32_t count,
                      int32_t ckpt_every, size_t mem_budget, mrt_batch** out);
 void mrt_batch_destroy(mrt_batch* b);
@@ -283,6 +284,73 @@ int mrt_batch_iteration(mrt_batch* b, double zeta, int32_t use_graph,
  * grid barrier timed out, MRT_ENONFINITE if a value is not finite. */
 int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,
                       void* stream);
+
+/* Forward solves only (no record, no adjoint) of every instance from its
+ * current u0, v0, control: writes the MRT_FIELD_UN / MRT_FIELD_VN fields.
+ * One persistent launch plus the terminal streaming.  Asynchronous. */
+int mrt_batch_forward(mrt_batch* b, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Convolutional surrogate of the control-to-state map c -> u(T) - u_base:
+ * four periodic 3x3 convolution layers (1 -> 32 -> 32 -> 32 -> 1 channels,
+ * tanh between them), BF16 weights with FP32 accumulation and FP32 master
+ * weights trained with Adam.  A layer computes z = oscale (W * (iscale x)
+ * + b); the first layer uses iscale = in_scale, the last oscale = out_scale.
+ * Fields are float [B][H][W] (periodic).  It proposes warm starts and step
+ * sizes for the optimisation loop; MRT solves verify what it proposes.
+ * ---------------------------------------------------------------------- */
+
+typedef struct mrt_srg mrt_srg;
+
+int mrt_srg_create(int32_t channels /* 32 */, int32_t max_batch, int32_t max_h,
+                   int32_t max_w, float in_scale, float out_scale, mrt_srg** out);
+void mrt_srg_destroy(mrt_srg* s);
+
+/* Device pointer and element count of a parameter of layer 0..3: kind 0
+ * FP32 master weights [cout][cin][3][3], 1 biases [cout], 2 weight
+ * gradients, 3 bias gradients (of the last backward / training step). */
+int mrt_srg_param(mrt_srg* s, int32_t layer, int32_t kind, void** ptr,
+                  int64_t* count /* host, NULL ok */);
+
+/* Device-to-device copy of a parameter (kinds as above) from (to_srg = 1)
+ * or to (to_srg = 0) the caller's float buffer.  Asynchronous. */
+int mrt_srg_copy_param(mrt_srg* s, int32_t layer, int32_t kind, int32_t to_srg,
+                       void* data, void* stream);
+
+/* After writing the FP32 masters: refresh the BF16 copies and reset the
+ * Adam moments.  Asynchronous. */
+int mrt_srg_sync(mrt_srg* s, void* stream);
+
+/* y = surrogate(x) for B fields of H x W.  Asynchronous. */
+int mrt_srg_forward(mrt_srg* s, const float* x, float* y, int32_t B, int32_t H,
+                    int32_t W, void* stream);
+
+/* Backward of the last mrt_srg_forward on x from dy = dL/dy: dx = dL/dx
+ * (NULL: not computed) and, if weight_grads, the parameter gradients.
+ * Asynchronous. */
+int mrt_srg_backward(mrt_srg* s, const float* x, const float* dy, float* dx,
+                     int32_t weight_grads, int32_t B, int32_t H, int32_t W,
+                     void* stream);
+
+/* Mean squared error of surrogate(x) against target over the interior
+ * (border pixels excluded).  Synchronises `stream`. */
+int mrt_srg_loss(mrt_srg* s, const float* x, const float* target, int32_t B,
+                 int32_t H, int32_t W, int32_t border, double* loss /* host */,
+                 void* stream);
+
+/* One Adam step (b1 = 0.9, b2 = 0.999) on the interior MSE of a batch.
+ * loss (host) NULL: asynchronous; else synchronises and returns the loss
+ * before the step. */
+int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target,
+                       int32_t B, int32_t H, int32_t W, int32_t border,
+                       float lr, double* loss /* host, NULL ok */, void* stream);
+
+/* Periodic crops: out[i] = h x w window at (oy[i], ox[i]) of the L x L field
+ * src[idx[i]] (idx, oy, ox: device int32 arrays of n entries).
+ * Asynchronous. */
+int mrt_srg_gather(const float* src, int32_t L, const int32_t* idx,
+                   const int32_t* oy, const int32_t* ox, float* out, int32_t n,
+                   int32_t h, int32_t w, void* stream);
 
 #ifdef __cplusplus
 }

@@ -74,7 +74,11 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
            "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
            "mrt_batch_tune", "mrt_batch_set_timeout", "mrt_batch_iteration",
-           "mrt_batch_scalars"]
+           "mrt_batch_scalars", "mrt_batch_forward",
+           "mrt_srg_create", "mrt_srg_destroy", "mrt_srg_param", "mrt_srg_copy_param",
+           "mrt_srg_sync",
+           "mrt_srg_forward", "mrt_srg_backward", "mrt_srg_loss",
+           "mrt_srg_train_step", "mrt_srg_gather"]
 
 
 def _load():
@@ -116,6 +120,20 @@ def _load():
     L.mrt_batch_iteration.argtypes = [vp, ctypes.c_double, ctypes.c_int32, vp]
     L.mrt_batch_scalars.argtypes = [vp, ctypes.POINTER(mrt_scalars),
                                     ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_batch_forward.argtypes = [vp, vp]
+    i32, f32 = ctypes.c_int32, ctypes.c_float
+    L.mrt_srg_create.argtypes = [i32, i32, i32, i32, f32, f32, ctypes.POINTER(vp)]
+    L.mrt_srg_destroy.argtypes = [vp]
+    L.mrt_srg_destroy.restype = None
+    L.mrt_srg_param.argtypes = [vp, i32, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64)]
+    L.mrt_srg_copy_param.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.mrt_srg_sync.argtypes = [vp, vp]
+    L.mrt_srg_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+    L.mrt_srg_backward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, vp]
+    L.mrt_srg_loss.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_srg_train_step.argtypes = [vp, vp, vp, i32, i32, i32, i32, f32,
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_srg_gather.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, i32, vp]
     return L
 
 
@@ -282,3 +300,66 @@ def mrt_batch_scalars(batch, count: int, stream=None):
     return [{"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
              "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid,
              "zeta": z[i]} for i, s in enumerate(out)]
+
+
+def mrt_batch_forward(batch, stream=None) -> None:
+    _check(lib.mrt_batch_forward(batch, _stream(stream)))
+
+
+# --------------------------------------------------------------- surrogate
+
+def mrt_srg_create(channels: int, max_batch: int, max_h: int, max_w: int,
+                   in_scale: float, out_scale: float):
+    h = ctypes.c_void_p()
+    _check(lib.mrt_srg_create(int(channels), int(max_batch), int(max_h), int(max_w),
+                              float(in_scale), float(out_scale), ctypes.byref(h)))
+    return h
+
+
+def mrt_srg_destroy(s) -> None:
+    lib.mrt_srg_destroy(s)
+
+
+def mrt_srg_param(s, layer: int, kind: int):
+    p = ctypes.c_void_p()
+    n = ctypes.c_int64()
+    _check(lib.mrt_srg_param(s, int(layer), int(kind), ctypes.byref(p), ctypes.byref(n)))
+    return p.value, n.value
+
+
+def mrt_srg_copy_param(s, layer: int, kind: int, to_srg: bool, data, stream=None) -> None:
+    _check(lib.mrt_srg_copy_param(s, int(layer), int(kind), 1 if to_srg else 0, _ptr(data),
+                                  _stream(stream)))
+
+
+def mrt_srg_sync(s, stream=None) -> None:
+    _check(lib.mrt_srg_sync(s, _stream(stream)))
+
+
+def mrt_srg_forward(s, x, y, B, H, W, stream=None) -> None:
+    _check(lib.mrt_srg_forward(s, _ptr(x), _ptr(y), int(B), int(H), int(W), _stream(stream)))
+
+
+def mrt_srg_backward(s, x, dy, dx, weight_grads, B, H, W, stream=None) -> None:
+    _check(lib.mrt_srg_backward(s, _ptr(x), _ptr(dy), _ptr(dx), 1 if weight_grads else 0,
+                                int(B), int(H), int(W), _stream(stream)))
+
+
+def mrt_srg_loss(s, x, target, B, H, W, border, stream=None) -> float:
+    v = ctypes.c_double()
+    _check(lib.mrt_srg_loss(s, _ptr(x), _ptr(target), int(B), int(H), int(W), int(border),
+                            ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def mrt_srg_train_step(s, x, target, B, H, W, border, lr, want_loss=False, stream=None):
+    v = ctypes.c_double()
+    _check(lib.mrt_srg_train_step(s, _ptr(x), _ptr(target), int(B), int(H), int(W),
+                                  int(border), float(lr),
+                                  ctypes.byref(v) if want_loss else None, _stream(stream)))
+    return v.value if want_loss else None
+
+
+def mrt_srg_gather(src, L, idx, oy, ox, out, n, h, w, stream=None) -> None:
+    _check(lib.mrt_srg_gather(_ptr(src), int(L), _ptr(idx), _ptr(oy), _ptr(ox), _ptr(out),
+                              int(n), int(h), int(w), _stream(stream)))

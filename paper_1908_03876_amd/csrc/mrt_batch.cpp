@@ -222,7 +222,11 @@ int mrt_batch_create(const mrt_problem* problems, int32_t count,
     for (size_t w : {64, 128, 256}) most = std::max(most, ((Lk + w - 1) / w) * ((Lk + 256 / w - 1) / (256 / w)));
     ntile_max += most;
   }
-  if (ckpt_every <= 0 || ckpt_every >= b->N) {
+  if (ckpt_every < 0) {  // forward solves only: no adjoint buffers, no record
+    b->mode = 0;
+    b->K = b->N;
+    b->nseg = 1;
+  } else if (ckpt_every == 0 || ckpt_every >= b->N) {
     b->mode = 1;
     b->K = b->N;
     b->nseg = 1;
@@ -232,8 +236,10 @@ int mrt_batch_create(const mrt_problem* problems, int32_t count,
     b->nseg = (b->N + ckpt_every - 1) / ckpt_every;
   }
   const size_t state = 18 * b->F * b->elem;
-  const size_t total = 8 * b->F * b->elem + b->F * 8 + 4 * state +
-                       size_t(b->nseg - 1) * state + size_t(b->K) * 3 * b->F * b->elem;
+  const bool adj = b->mode > 0;
+  const size_t total = 8 * b->F * b->elem + b->F * 8 + (adj ? 4 : 2) * state +
+                       size_t(b->nseg - 1) * state +
+                       (adj ? size_t(b->K) * 3 * b->F * b->elem : 0);
   if (mem_budget > 0 && total > mem_budget) {
     delete b;
     return err(MRT_ENOMEM, "batch needs " + std::to_string(total) + " bytes, over the budget");
@@ -253,9 +259,9 @@ int mrt_batch_create(const mrt_problem* problems, int32_t count,
   if (!rc) rc = alloc(8 * b->F * b->elem, (void**)&b->fields);
   if (!rc) rc = alloc(b->F * sizeof(double), (void**)&b->gacc);
   for (int i = 0; i < 2 && !rc; ++i) rc = alloc(state, &b->buf[i]);
-  for (int i = 0; i < 2 && !rc; ++i) rc = alloc(state, &b->abuf[i]);
+  for (int i = 0; i < 2 && !rc && adj; ++i) rc = alloc(state, &b->abuf[i]);
   if (!rc && b->nseg > 1) rc = alloc(size_t(b->nseg - 1) * state, &b->ckpt);
-  if (!rc) rc = alloc(size_t(b->K) * 3 * b->F * b->elem, &b->rec);
+  if (!rc && adj) rc = alloc(size_t(b->K) * 3 * b->F * b->elem, &b->rec);
   if (!rc) rc = alloc(size_t(count) * sizeof(mrt::ModelCoef<double>), &b->coef);
   if (!rc) rc = alloc(count * sizeof(int), (void**)&b->dL);
   if (!rc) rc = alloc(count * sizeof(size_t), (void**)&b->dfoff);
@@ -450,6 +456,7 @@ int mrt_batch_iteration(mrt_batch* b, double zeta, int32_t use_graph,
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
     return err(MRT_ESTATE, "batch belongs to another device");
+  if (b->mode == 0) return err(MRT_ESTATE, "batch was created for forward solves only");
   hipStream_t cs = static_cast<hipStream_t>(stream);
   if (!use_graph) {
     int rc = enqueue(b, zeta, cs);
@@ -483,6 +490,25 @@ int mrt_batch_iteration(mrt_batch* b, double zeta, int32_t use_graph,
   HIP_OK(hipStreamWaitEvent(cs, b->ev_out, 0));
   b->iterated = true;
   return MRT_OK;
+}
+
+int mrt_batch_forward(mrt_batch* b, void* stream) {
+  if (!b) return err(MRT_EINVAL, "batch is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int bf = persistent_blocks(b, b->max_bpc_f);
+  const int bs = std::min(b->ntiles, 4096);
+  if (b->dtype == MRT_F64) {
+    BatchArgs<double> a = make_args<double>(b);
+    a.mode = 0; a.K = a.N; a.nseg = 1;
+    mrt::launch_batch_forward<double>(a, bf, s);
+    mrt::launch_batch_finalize<double>(a, static_cast<const double*>(b->buf[(b->N - 1) & 1]), bs, s);
+  } else {
+    BatchArgs<float> a = make_args<float>(b);
+    a.mode = 0; a.K = a.N; a.nseg = 1;
+    mrt::launch_batch_forward<float>(a, bf, s);
+    mrt::launch_batch_finalize<float>(a, static_cast<const float*>(b->buf[(b->N - 1) & 1]), bs, s);
+  }
+  return launch_error();
 }
 
 int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,

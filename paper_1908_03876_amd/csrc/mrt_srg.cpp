@@ -1,0 +1,285 @@
+// Runtime of the convolutional surrogate: parameter storage (FP32 masters,
+// BF16 compute copies, Adam moments), the four-layer forward and backward
+// sequence, the training step and input gradients.  See include/mrt.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "mrt.h"
+#include "mrt_internal.h"
+#include "srg_internal.h"
+
+namespace {
+
+constexpr int kC = 32;  // hidden channels
+
+int err(int code, const std::string& m) { return mrt::host::set_error(code, m.c_str()); }
+
+#define HIP_OK(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return err(MRT_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Layer {
+  int cin = 0, cout = 0;
+  float* w = nullptr;      // FP32 master [cout][cin][9]
+  uint16_t* wb = nullptr;  // BF16 compute copy
+  float* b = nullptr;      // [cout]
+  float* dw = nullptr;
+  float* db = nullptr;
+  float* mw = nullptr;
+  float* vw = nullptr;
+  float* mb = nullptr;
+  float* vb = nullptr;
+  int nw() const { return cin * cout * 9; }
+};
+
+}  // namespace
+
+struct mrt_srg {
+  int max_batch = 0, max_h = 0, max_w = 0;
+  float s_in = 1.f, s_out = 1.f;
+  Layer L[4];
+  float* act[3] = {nullptr, nullptr, nullptr};
+  float* g[2] = {nullptr, nullptr};
+  float* dout = nullptr;
+  double* partials = nullptr;
+  double* loss_dev = nullptr;
+  double* host = nullptr;
+  int64_t step = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int check_shape(const mrt_srg* s, int B, int H, int W) {
+  if (B < 1 || H < 3 || W < 3 || B > s->max_batch || size_t(H) * W > size_t(s->max_h) * s->max_w)
+    return err(MRT_EINVAL, "batch or size outside what the surrogate was created for");
+  return MRT_OK;
+}
+
+int launch_err() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRT_OK
+                         : err(MRT_EHIP, std::string("launch failed: ") + hipGetErrorString(e));
+}
+
+void forward(mrt_srg* s, const float* x, float* y, int B, int H, int W, hipStream_t st) {
+  mrt::launch_conv_fwd<1, kC>(x, s->L[0].wb, s->L[0].b, s->act[0], B, H, W, s->s_in, 1.f, true, st);
+  mrt::launch_conv_fwd<kC, kC>(s->act[0], s->L[1].wb, s->L[1].b, s->act[1], B, H, W, 1.f, 1.f, true, st);
+  mrt::launch_conv_fwd<kC, kC>(s->act[1], s->L[2].wb, s->L[2].b, s->act[2], B, H, W, 1.f, 1.f, true, st);
+  mrt::launch_conv_fwd<kC, 1>(s->act[2], s->L[3].wb, s->L[3].b, y, B, H, W, 1.f, s->s_out, false, st);
+}
+
+// Backward through the layers of the last forward on x, from dy = dL/dy.
+void backward(mrt_srg* s, const float* x, const float* dy, float* dx, bool wgrads, int B,
+              int H, int W, hipStream_t st) {
+  const size_t n = size_t(B) * kC * H * W;
+  float* g0 = s->g[0];
+  float* g1 = s->g[1];
+  auto dw = [&](int l) { return wgrads ? s->L[l].dw : nullptr; };
+  auto db = [&](int l) { return wgrads ? s->L[l].db : nullptr; };
+  mrt::launch_conv_bwd<kC, 1>(dy, s->act[2], s->L[3].wb, g0, dw(3), db(3), B, H, W, 1.f, s->s_out, st);
+  mrt::launch_tanh_bwd(s->act[2], g0, g0, n, st);
+  mrt::launch_conv_bwd<kC, kC>(g0, s->act[1], s->L[2].wb, g1, dw(2), db(2), B, H, W, 1.f, 1.f, st);
+  mrt::launch_tanh_bwd(s->act[1], g1, g1, n, st);
+  mrt::launch_conv_bwd<kC, kC>(g1, s->act[0], s->L[1].wb, g0, dw(1), db(1), B, H, W, 1.f, 1.f, st);
+  mrt::launch_tanh_bwd(s->act[0], g0, g0, n, st);
+  mrt::launch_conv_bwd<1, kC>(g0, x, s->L[0].wb, dx, dw(0), db(0), B, H, W, s->s_in, 1.f, st);
+}
+
+void free_srg(mrt_srg* s) {
+  if (!s) return;
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->host) (void)hipHostFree(s->host);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t max_w,
+                   float in_scale, float out_scale, mrt_srg** out) {
+  if (!out) return err(MRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (channels != kC) return err(MRT_EINVAL, "the surrogate has 32 hidden channels");
+  if (max_batch < 1 || max_h < 3 || max_w < 3) return err(MRT_EINVAL, "invalid sizes");
+  if (!(std::isfinite(in_scale) && std::isfinite(out_scale)))
+    return err(MRT_EINVAL, "non-finite scales");
+  mrt_srg* s = new mrt_srg();
+  s->max_batch = max_batch;
+  s->max_h = max_h;
+  s->max_w = max_w;
+  s->s_in = in_scale;
+  s->s_out = out_scale;
+  const int cin[4] = {1, kC, kC, kC}, cout[4] = {kC, kC, kC, 1};
+  int rc = MRT_OK;
+  auto alloc = [&](size_t bytes, void** p) -> int {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return err(MRT_ENOMEM, "hipMalloc failed");
+    }
+    s->allocs.push_back(*p);
+    return hipMemset(*p, 0, bytes) == hipSuccess ? MRT_OK : err(MRT_EHIP, "hipMemset failed");
+  };
+  for (int l = 0; l < 4 && !rc; ++l) {
+    Layer& y = s->L[l];
+    y.cin = cin[l];
+    y.cout = cout[l];
+    const size_t nw = size_t(y.nw()) * 4, nb = size_t(y.cout) * 4;
+    rc = alloc(nw, (void**)&y.w);
+    if (!rc) rc = alloc(nw / 2, (void**)&y.wb);
+    if (!rc) rc = alloc(nb, (void**)&y.b);
+    if (!rc) rc = alloc(nw, (void**)&y.dw);
+    if (!rc) rc = alloc(nb, (void**)&y.db);
+    if (!rc) rc = alloc(nw, (void**)&y.mw);
+    if (!rc) rc = alloc(nw, (void**)&y.vw);
+    if (!rc) rc = alloc(nb, (void**)&y.mb);
+    if (!rc) rc = alloc(nb, (void**)&y.vb);
+  }
+  const size_t hwb = size_t(max_batch) * max_h * max_w;
+  for (int i = 0; i < 3 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->act[i]);
+  for (int i = 0; i < 2 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->g[i]);
+  if (!rc) rc = alloc(hwb * 4, (void**)&s->dout);
+  if (!rc) rc = alloc((size_t(mrt::mse_partials_needed(max_batch, max_h, max_w)) + 8) * 8,
+                      (void**)&s->partials);
+  if (!rc) rc = alloc(64, (void**)&s->loss_dev);
+  if (!rc && hipHostMalloc((void**)&s->host, 64) != hipSuccess) rc = err(MRT_ENOMEM, "pinned");
+  if (rc) {
+    free_srg(s);
+    return rc;
+  }
+  *out = s;
+  return MRT_OK;
+}
+
+void mrt_srg_destroy(mrt_srg* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_srg(s);
+}
+
+int mrt_srg_param(mrt_srg* s, int32_t layer, int32_t kind, void** ptr, int64_t* count) {
+  if (!s || !ptr || layer < 0 || layer > 3 || kind < 0 || kind > 3)
+    return err(MRT_EINVAL, "invalid parameter query");
+  Layer& y = s->L[layer];
+  float* p[4] = {y.w, y.b, y.dw, y.db};
+  const int64_t n[4] = {y.nw(), y.cout, y.nw(), y.cout};
+  *ptr = p[kind];
+  if (count) *count = n[kind];
+  return MRT_OK;
+}
+
+int mrt_srg_copy_param(mrt_srg* s, int32_t layer, int32_t kind, int32_t to_srg,
+                       void* data, void* stream) {
+  void* p = nullptr;
+  int64_t n = 0;
+  int rc = mrt_srg_param(s, layer, kind, &p, &n);
+  if (rc) return rc;
+  if (!data) return err(MRT_EINVAL, "data is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (to_srg)
+    HIP_OK(hipMemcpyAsync(p, data, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+  else
+    HIP_OK(hipMemcpyAsync(data, p, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+  return MRT_OK;
+}
+
+int mrt_srg_sync(mrt_srg* s, void* stream) {
+  if (!s) return err(MRT_EINVAL, "surrogate is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int l = 0; l < 4; ++l) {
+    Layer& y = s->L[l];
+    mrt::launch_to_bf16(y.w, y.wb, y.nw(), st);
+    HIP_OK(hipMemsetAsync(y.mw, 0, size_t(y.nw()) * 4, st));
+    HIP_OK(hipMemsetAsync(y.vw, 0, size_t(y.nw()) * 4, st));
+    HIP_OK(hipMemsetAsync(y.mb, 0, size_t(y.cout) * 4, st));
+    HIP_OK(hipMemsetAsync(y.vb, 0, size_t(y.cout) * 4, st));
+  }
+  s->step = 0;
+  return launch_err();
+}
+
+int mrt_srg_forward(mrt_srg* s, const float* x, float* y, int32_t B, int32_t H, int32_t W,
+                    void* stream) {
+  if (!s || !x || !y) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, B, H, W);
+  if (rc) return rc;
+  forward(s, x, y, B, H, W, static_cast<hipStream_t>(stream));
+  return launch_err();
+}
+
+int mrt_srg_backward(mrt_srg* s, const float* x, const float* dy, float* dx,
+                     int32_t weight_grads, int32_t B, int32_t H, int32_t W, void* stream) {
+  if (!s || !x || !dy) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, B, H, W);
+  if (rc) return rc;
+  backward(s, x, dy, dx, weight_grads != 0, B, H, W, static_cast<hipStream_t>(stream));
+  return launch_err();
+}
+
+int mrt_srg_loss(mrt_srg* s, const float* x, const float* target, int32_t B, int32_t H,
+                 int32_t W, int32_t border, double* loss, void* stream) {
+  if (!s || !x || !target || !loss) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, B, H, W);
+  if (rc) return rc;
+  if (border < 0 || 2 * border >= H || 2 * border >= W) return err(MRT_EINVAL, "bad border");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  forward(s, x, s->dout, B, H, W, st);
+  mrt::launch_mse(s->dout, target, nullptr, s->partials, s->loss_dev, B, H, W, border, st);
+  rc = launch_err();
+  if (rc) return rc;
+  HIP_OK(hipMemcpyAsync(s->host, s->loss_dev, 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *loss = s->host[0];
+  return std::isfinite(*loss) ? MRT_OK : err(MRT_ENONFINITE, "non-finite loss");
+}
+
+int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target, int32_t B,
+                       int32_t H, int32_t W, int32_t border, float lr, double* loss,
+                       void* stream) {
+  if (!s || !x || !target) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, B, H, W);
+  if (rc) return rc;
+  if (border < 0 || 2 * border >= H || 2 * border >= W) return err(MRT_EINVAL, "bad border");
+  if (!(lr > 0.f)) return err(MRT_EINVAL, "lr must be > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* pred = s->dout;  // prediction, then overwritten by dL/dpred
+  forward(s, x, pred, B, H, W, st);
+  mrt::launch_mse(pred, target, pred, s->partials, s->loss_dev, B, H, W, border, st);
+  backward(s, x, pred, nullptr, true, B, H, W, st);
+  s->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - std::pow(b1, float(s->step)), c2 = 1.f - std::pow(b2, float(s->step));
+  for (int l = 0; l < 4; ++l) {
+    Layer& y = s->L[l];
+    mrt::launch_adam(y.w, y.wb, y.dw, y.mw, y.vw, y.nw(), lr, b1, b2, eps, c1, c2, st);
+    mrt::launch_adam(y.b, nullptr, y.db, y.mb, y.vb, y.cout, lr, b1, b2, eps, c1, c2, st);
+  }
+  rc = launch_err();
+  if (rc) return rc;
+  if (loss) {
+    HIP_OK(hipMemcpyAsync(s->host, s->loss_dev, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *loss = s->host[0];
+    if (!std::isfinite(*loss)) return err(MRT_ENONFINITE, "non-finite loss");
+  }
+  return MRT_OK;
+}
+
+int mrt_srg_gather(const float* src, int32_t L, const int32_t* idx, const int32_t* oy,
+                   const int32_t* ox, float* out, int32_t n, int32_t h, int32_t w,
+                   void* stream) {
+  if (!src || !idx || !oy || !ox || !out || L < 1 || n < 1 || h < 1 || w < 1 || h > L || w > L)
+    return err(MRT_EINVAL, "invalid crop request");
+  mrt::launch_gather_crops(src, L, idx, oy, ox, out, n, h, w, static_cast<hipStream_t>(stream));
+  return launch_err();
+}
+
+}  // extern "C"
