@@ -70,6 +70,99 @@ def cpu_baseline(L: int, steps: int):
                       f"anisotropic workload, {steps} steps ({dt:.1f} s)"}
 
 
+def bench_batched(args):
+    """96 independent periodic problems, L in {128..1024} (seeded), N = 2000
+    (or --nsteps if given below 2000), per-instance chi and tensors:
+    graph-replayed gradient iterations of the batched persistent engine."""
+    import torch
+    from paper_1908_03876_amd import inputs as I
+    from paper_1908_03876_amd.batched import Batch
+    N = min(args.nsteps, 2000)
+    ps = I.cfg4(seed=4, n=96, nsteps=N)
+    sites = sum(p.nx * p.ny for p in ps)
+    K = max(1, int(round((N * 6) ** 0.5)))
+    log(f"[bench] batched: 96 instances, {sites} sites, N={N}, ckpt every {K}")
+    b = Batch(ps, dtype=torch.float32, ckpt_every=K)
+    best = b.tune(steps=10)
+    log(f"[bench] autotuner: {best}")
+    for w in range(max(args.warmup, 1)):
+        b.iterate(use_graph=True)
+        b.scalars()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    js = []
+    for k in range(args.steps):
+        b.iterate(use_graph=True)
+        js.append(sum(s["J"] for s in b.scalars()))
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    # per site-step bytes (FP32, periodic, no mask): forward 18+18 planes +
+    # control, with the record on the recomputed/last segment, adjoint 18+18
+    # planes + 3 record loads + FP64 gradient read-modify-write
+    fwd_b, rec_b, adj_b = 36 * 4 + 4, 36 * 4 + 4 + 12, 36 * 4 + 12 + 16
+    bytes_it = sites * (N * fwd_b + N * rec_b + N * adj_b)
+    out = {"metric": "batched coupled MRT+AMRT MLUPS (96 uneven instances)",
+           "value": round(sites * N / (ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+           "ms_per_iteration": round(ms, 1), "iterations": args.steps,
+           "instances": 96, "sites": sites, "nsteps": N, "ckpt_every": K,
+           "tiles": best, "algorithmic_GBps_per_iteration": round(bytes_it / (ms / 1e3) / 1e9, 1),
+           "hbm_frac": round(bytes_it / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "J_sum_history": [round(x, 4) for x in js]}
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_surrogate(args):
+    """Surrogate-assisted vs plain loop: MRT-generated training pairs on
+    256^2 (N = 1000), crop training, then both loops on 256^2 and 1024^2
+    problems with reachable (hidden-control) targets."""
+    import torch
+    from paper_1908_03876_amd import surrogate as SG
+    N, L = 1000, 256
+    n_pairs = int(os.environ.get("MRT_SRG_PAIRS", "20000"))
+    t0 = time.perf_counter()
+    data = SG.generate_pairs(n_pairs, L, N, seed=5, per_launch=96)
+    t_gen = time.perf_counter() - t0
+    log(f"[bench] {n_pairs} pairs generated in {t_gen:.1f} s")
+    var = float((data["responses"] ** 2).mean())
+    srg = SG.Surrogate(17, 1024, 1024, seed=0)
+    t0 = time.perf_counter()
+    hist = srg.train(data["controls"][:-64], data["responses"][:-64], steps=3000,
+                     batch=64, crop=64, border=4, lr=2e-3, seed=1, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    held = srg.loss(data["controls"][-64:-48], data["responses"][-64:-48])
+    log(f"[bench] trained in {t_train:.1f} s: loss {hist} held-out {held:.3e} (var {var:.3e})")
+    res = {"metric": "surrogate-assisted vs plain loop wall time to the plain loop's "
+                     "cost within 1e-3", "pairs": n_pairs, "pair_gen_s": round(t_gen, 1),
+           "train_s": round(t_train, 1), "train_loss": hist, "heldout_mse": held,
+           "response_var": var, "problems": []}
+    for size in (256, 1024):
+        prob, _ = SG.hidden_target_problem(size, N, seed=9 + size, amax=2.0)
+        base = data["u_base"][0, 0].item()
+        ub = torch.full((size, size), base, dtype=torch.float32, device="cuda")
+        cp = SG.ControlProblem(prob)
+        plain = SG.optimize_plain(cp, iters=args.steps if args.steps < 20 else 10)
+        cp.close()
+        cp = SG.ControlProblem(prob)
+        asst = SG.optimize_assisted(cp, srg, ub, plain["J"] * (1 + 1e-3), max_iters=30)
+        cp.close()
+        row = {"L": size, "plain_J": plain["J"], "plain_s": round(plain["time"], 3),
+               "plain_solves": plain["forwards"] + plain["adjoints"],
+               "assisted_J": asst["J"], "assisted_s": round(asst["time"], 3),
+               "assisted_solves": asst["forwards"] + asst["adjoints"],
+               "accepted": asst["accepted"], "fallbacks": asst["fallbacks"],
+               "speedup": round(plain["time"] / max(asst["time"], 1e-9), 2)}
+        log(f"[bench] {row}")
+        res["problems"].append(row)
+    srg.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +174,11 @@ def main():
                     help="auto | store | K (checkpoint every K steps)")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="steps of the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--workload", default="masked",
+                    choices=["masked", "batched", "surrogate"],
+                    help="masked: the 2048^2 masked anisotropic workload (the "
+                         "reported line); batched: 96 uneven periodic instances; "
+                         "surrogate: CNN-assisted vs plain loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
                          "plain device copy (reference for HBM byte counters)")
@@ -91,6 +189,10 @@ def main():
                           "decomposition), not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     import torch
     from paper_1908_03876_amd import abi
     from paper_1908_03876_amd import inputs as I

@@ -35,7 +35,6 @@ struct BatchArgs {
   const double* alpha;       // [count] control penalty
   int N, K, nseg, mode;      // steps, segment length, segments, tape mode
   int rec_seg;               // segment held by the record (adjoint pass)
-  int sync_after;            // barrier after the last step of a loop
   size_t state_elems;        // 18 * F: one batched distribution state
   size_t rec_elems;          // 3 * F: one record slot
   T* buf[2];                 // forward ping-pong

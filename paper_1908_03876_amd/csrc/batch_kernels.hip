@@ -86,11 +86,11 @@ __device__ __forceinline__ bool tile_node(const BatchTile& tl, int tile_w,
   return true;
 }
 
-// Not inlined: every call site (recorded or not, forward or recomputation)
-// then runs the same compiled body, so a recomputed segment reproduces the
-// recorded one bit for bit.
+// Recording is a run-time pointer here as in the single-lattice kernels:
+// no call site is specialised on it, so the recorded forward and the
+// recomputation compute identical values.
 template <typename T, bool FIRST>
-__device__ __noinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
+__device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     T* rec) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const BatchTile tl = a.tiles[t];
@@ -106,7 +106,7 @@ __device__ __noinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T*
 }
 
 template <typename T, bool FIRST>
-__device__ __noinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
+__device__ __forceinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     const T* rec) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const BatchTile tl = a.tiles[t];
@@ -130,37 +130,31 @@ __device__ __forceinline__ T* fwd_dst(const BatchArgs<T>& a, int n, bool ckpt) {
   return a.buf[n & 1];
 }
 
+// Forward steps [n0, n1): step n reads src (or the initial fields when
+// n == 0), writes fwd_dst and, from step rec0 on, the record slot n - rec0.
+// A barrier follows every step except the last one of the launch.
 template <typename T>
-__device__ void forward_steps(const BatchArgs<T>& a, int n0, int n1,
-                              const T* src, bool record, bool ckpt,
+__device__ void forward_steps(const BatchArgs<T>& a, int n0, int n1, int rec0,
+                              const T* src, bool ckpt, bool sync_last,
                               unsigned nblocks, bool* alive) {
-  const int seg = n0 / a.K;
   for (int n = n0; n < n1 && *alive; ++n) {
     T* dst = fwd_dst(a, n, ckpt);
-    T* rec = record ? a.rec + size_t(n - seg * a.K) * a.rec_elems : nullptr;
+    T* rec = n >= rec0 ? a.rec + size_t(n - rec0) * a.rec_elems : nullptr;
     if (n == 0)
       forward_sweep_tiles<T, true>(a, nullptr, dst, rec);
     else
       forward_sweep_tiles<T, false>(a, src, dst, rec);
     src = dst;
-    if (n + 1 < n1 || a.sync_after) *alive = grid_sync(a.barrier, nblocks, a.timeout);
+    if (n + 1 < n1 || sync_last) *alive = grid_sync(a.barrier, nblocks, a.timeout);
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
   bool alive = true;
-  const unsigned nb = gridDim.x;
   // record the last segment (it is the first one the adjoint needs)
-  const int rec_start = a.mode > 0 ? (a.nseg - 1) * a.K : a.N;
-  const T* src = nullptr;
-  if (rec_start > 0) {
-    BatchArgs<T> b = a;
-    b.sync_after = 1;
-    forward_steps<T>(b, 0, rec_start, nullptr, false, true, nb, &alive);
-    src = fwd_dst(a, rec_start - 1, true);
-  }
-  if (rec_start < a.N && alive) forward_steps<T>(a, rec_start, a.N, src, true, true, nb, &alive);
+  const int rec0 = a.mode > 0 ? (a.nseg - 1) * a.K : a.N;
+  forward_steps<T>(a, 0, a.N, rec0, nullptr, true, false, gridDim.x, &alive);
 }
 
 template <typename T>
@@ -172,9 +166,7 @@ __global__ __launch_bounds__(256) void batch_adjoint_kernel(BatchArgs<T> a) {
     const int n0 = seg * a.K, n1 = min(a.N, n0 + a.K);
     if (seg != a.rec_seg) {
       const T* src = seg == 0 ? nullptr : a.ckpt + size_t(seg - 1) * a.state_elems;
-      BatchArgs<T> b = a;
-      b.sync_after = 1;
-      forward_steps<T>(b, n0, n1, src, true, false, nb, &alive);
+      forward_steps<T>(a, n0, n1, n0, src, false, true, nb, &alive);
     }
     for (int n = n1 - 1; n >= n0 && alive; --n) {
       T* dst = n == 0 ? nullptr : a.abuf[n & 1];

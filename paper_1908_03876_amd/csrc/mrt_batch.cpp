@@ -88,7 +88,6 @@ BatchArgs<T> make_args(mrt_batch* b) {
   a.nseg = b->nseg;
   a.mode = b->mode;
   a.rec_seg = b->nseg - 1;
-  a.sync_after = 0;
   a.state_elems = 18 * b->F;
   a.rec_elems = 3 * b->F;
   a.buf[0] = static_cast<T*>(b->buf[0]);

@@ -57,7 +57,9 @@ struct mrt_srg {
 namespace {
 
 int check_shape(const mrt_srg* s, int B, int H, int W) {
-  if (B < 1 || H < 3 || W < 3 || B > s->max_batch || size_t(H) * W > size_t(s->max_h) * s->max_w)
+  // work buffers hold max_batch * max_h * max_w pixels
+  if (B < 1 || H < 3 || W < 3 ||
+      size_t(B) * H * W > size_t(s->max_batch) * s->max_h * s->max_w)
     return err(MRT_EINVAL, "batch or size outside what the surrogate was created for");
   return MRT_OK;
 }
