@@ -28,8 +28,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1908_03876_amd", "csrc", "mrt_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+# sources the single-lattice step kernels are compiled from: HBM counters
+# taken on other sources are stale
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1908_03876_amd", "csrc", f)
+               for f in ("mrt_kernels.hip", "mrt_device.h", "mrt_internal.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 
 
 def log(msg):
@@ -37,8 +40,30 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, L: int):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary (`key = value` lines), or None when it is absent, taken on
+    another workload size, or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if "=" in line:
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash() or kv.get("L") != str(L):
+        return None
+    v = kv.get(kernel + ".hbm_bytes_per_launch")
+    return int(v) if v is not None else None
 
 
 def bytes_per_site(elem: int):
@@ -172,7 +197,7 @@ def main():
     ap.add_argument("--nsteps", type=int, default=4000, help="time steps per solve")
     ap.add_argument("--ckpt", default="auto",
                     help="auto | store | K (checkpoint every K steps)")
-    ap.add_argument("--cpu-steps", type=int, default=6,
+    ap.add_argument("--cpu-steps", type=int, default=20,
                     help="steps of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--workload", default="masked",
                     choices=["masked", "batched", "surrogate"],
@@ -254,16 +279,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k][0])
     _, avg_ms, lbytes = kern[dom]
     achieved = lbytes / (avg_ms / 1e3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            ent = tr.get("kernels", {}).get(dom)
-            if ent and tr.get("kernel_source_sha256_16") == kernel_hash() \
-                    and tr.get("workload", {}).get("L") == args.L:
-                traffic = ent["hbm_bytes_per_launch"]
-        except Exception:
-            traffic = None
+    traffic = read_traffic(dom, args.L)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "kernel": dom,
