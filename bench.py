@@ -67,7 +67,7 @@ def read_traffic(kernel: str, L: int):
 
 
 def bytes_per_site(elem: int):
-    """Algorithmic HBM bytes per fluid node and step (see DESIGN.md):
+    """Algorithmic HBM bytes per fluid node and step:
     forward with record: 18 loads + 18 stores + control + link + 3 record
     stores; adjoint: 18 + 18 + 3 record loads + FP64 gradient read-modify-
     write + link."""
@@ -83,7 +83,7 @@ def cpu_baseline(L: int, steps: int):
     steps."""
     from oracle import oracle as O
     from paper_1908_03876_amd import inputs as I
-    p = I.with_control_bump(I.cfg2(L=L, nsteps=steps), amp=5.0, sigma=L / 8)
+    p = I.with_control_bump(I.masked_anisotropic(L=L, nsteps=steps), amp=5.0, sigma=L / 8)
     O.lib()
     t0 = time.perf_counter()
     O.cost_gradient(p)
@@ -103,7 +103,7 @@ def bench_batched(args):
     from paper_1908_03876_amd import inputs as I
     from paper_1908_03876_amd.batched import Batch
     N = min(args.nsteps, 2000)
-    ps = I.cfg4(seed=4, n=96, nsteps=N)
+    ps = I.uneven_batch(seed=4, n=96, nsteps=N)
     sites = sum(p.nx * p.ny for p in ps)
     K = max(1, int(round((N * 6) ** 0.5)))
     log(f"[bench] batched: 96 instances, {sites} sites, N={N}, ckpt every {K}")
@@ -209,7 +209,7 @@ def main():
                          "plain device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "bench.py runs on one GPU only; "
                           "multi-GPU sharding is a design note (domain "
                           "decomposition), not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
@@ -225,7 +225,7 @@ def main():
                                              choose_ckpt_every)
     dev = torch.device("cuda:0")
     log(f"[bench] building workload L={args.L} N={args.nsteps}")
-    prob = I.cfg2(L=args.L, nsteps=args.nsteps)
+    prob = I.masked_anisotropic(L=args.L, nsteps=args.nsteps)
     dp = DeviceProblem(prob, dtype=torch.float32, device=dev)
     free, total = torch.cuda.mem_get_info(dev)
     if args.ckpt == "auto":

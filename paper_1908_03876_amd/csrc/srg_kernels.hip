@@ -2,7 +2,7 @@
 // c -> u(T): four periodic 3x3 convolution layers (1 -> C -> C -> C -> 1
 // channels), tanh between layers, BF16 weights with FP32 accumulation, MSE
 // loss and Adam.  The surrogate only proposes warm starts and step sizes;
-// the MRT solve remains the judge of every accepted step.
+// the MRT solve still decides whether each proposed step is accepted.
 //
 // Layout: activations NCHW float [B][C][H][W], weights [Cout][Cin][3][3]
 // (BF16 compute copy of an FP32 master), periodic padding.  A layer

@@ -162,7 +162,7 @@ def _zero_solids(p: Problem) -> Problem:
 
 # ---------------------------------------------------------------- workloads
 
-def cfg1(seed: int = 1, L: int = 64, nsteps: int = 200) -> Problem:
+def periodic_isotropic(seed: int = 1, L: int = 64, nsteps: int = 200) -> Problem:
     """Plain method, FP64: L x L periodic, isotropic D_u = 0.1, D_v = 1.0,
     chi = 0.5, logistic u, v driven by u, zero initial control, Gaussian
     target bump of sigma = 8 cells."""
@@ -173,12 +173,12 @@ def cfg1(seed: int = 1, L: int = 64, nsteps: int = 200) -> Problem:
     return Problem(nx=L, ny=L, nsteps=nsteps, periodic=True, solid=None,
                    Du=0.1 * np.eye(2), Dv=1.0 * np.eye(2), chi=0.5,
                    Cchi=np.eye(2), u0=u0, v0=np.zeros((L, L)),
-                   control=np.zeros((L, L)), u_target=ut, name=f"cfg1_L{L}")
+                   control=np.zeros((L, L)), u_target=ut, name=f"periodic_L{L}")
 
 
-def cfg2(seed: int = 2, L: int = 2048, nsteps: int = 4000,
-         n_disks: int = 200, rmin: int = 5, rmax: int = 30,
-         n_target_bumps: int = 8, target_sigma: float = 64.0) -> Problem:
+def masked_anisotropic(seed: int = 2, L: int = 2048, nsteps: int = 4000,
+                       n_disks: int = 200, rmin: int = 5, rmax: int = 30,
+                       n_target_bumps: int = 8, target_sigma: float = 64.0) -> Problem:
     """Plain method at scale, FP32: L x L with a bounce-back mask of random
     disks plus a solid outer ring, full anisotropic self and chemotactic
     tensors (diagonal in [0.05, 1], off-diagonal U(-0.3, 0.3) of the
@@ -195,28 +195,28 @@ def cfg2(seed: int = 2, L: int = 2048, nsteps: int = 4000,
     p = Problem(nx=L, ny=L, nsteps=nsteps, periodic=False, solid=solid,
                 Du=Du, Dv=Dv, chi=0.5, Cchi=Cchi, u0=u0,
                 v0=np.zeros((L, L)), control=np.zeros((L, L)),
-                u_target=ut, name=f"cfg2_L{L}_N{nsteps}")
+                u_target=ut, name=f"masked_L{L}_N{nsteps}")
     return _zero_solids(p)
 
 
-def cfg2_small(seed: int = 2, L: int = 128, nsteps: int = 200) -> Problem:
+def masked_anisotropic_small(seed: int = 2, L: int = 128, nsteps: int = 200) -> Problem:
     """The small copy of the masked anisotropic workload: same tensor
     recipe, 4 disks of radius 3..8 cells plus the outer ring."""
-    return cfg2(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3, rmax=8,
-                n_target_bumps=2, target_sigma=L / 8.0)
+    return masked_anisotropic(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3, rmax=8,
+                              n_target_bumps=2, target_sigma=L / 8.0)
 
 
-def cfg3(seed: int = 3, L: int = 2048, nsteps: int = 10000) -> Problem:
+def long_horizon(seed: int = 3, L: int = 2048, nsteps: int = 10000) -> Problem:
     """Differentiation form: the masked anisotropic workload at a longer
     horizon."""
     if L <= 256:
-        return cfg2(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3, rmax=8,
-                    n_target_bumps=2, target_sigma=L / 8.0)
-    return cfg2(seed=seed, L=L, nsteps=nsteps)
+        return masked_anisotropic(seed=seed, L=L, nsteps=nsteps, n_disks=4, rmin=3,
+                                  rmax=8, n_target_bumps=2, target_sigma=L / 8.0)
+    return masked_anisotropic(seed=seed, L=L, nsteps=nsteps)
 
 
-def cfg4(seed: int = 4, n: int = 96, nsteps: int = 2000,
-         sizes=(128, 256, 384, 512, 768, 1024)) -> List[Problem]:
+def uneven_batch(seed: int = 4, n: int = 96, nsteps: int = 2000,
+                 sizes=(128, 256, 384, 512, 768, 1024)) -> List[Problem]:
     """Batched form: n independent periodic problems of uneven square size,
     per-instance chi ~ U[0.1, 1], seeded tensors and one target bump of
     sigma = L/8."""
@@ -232,7 +232,7 @@ def cfg4(seed: int = 4, n: int = 96, nsteps: int = 2000,
         out.append(Problem(nx=L, ny=L, nsteps=nsteps, periodic=True, solid=None,
                            Du=Du, Dv=Dv, chi=chi, Cchi=Cchi, u0=u0,
                            v0=np.zeros((L, L)), control=np.zeros((L, L)),
-                           u_target=ut, name=f"cfg4_{k}_L{L}"))
+                           u_target=ut, name=f"uneven_{k}_L{L}"))
     return out
 
 

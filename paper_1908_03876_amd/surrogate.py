@@ -157,9 +157,9 @@ def render_bumps(n: int, L: int, rng: np.random.Generator, device,
 
 
 def physics(L: int, nsteps: int) -> "I.Problem":
-    """The learned problem family: cfg1 physics on a periodic L x L lattice,
+    """The learned problem family: the periodic isotropic physics on a periodic L x L lattice,
     u0 = 1, v0 = 0."""
-    p = I.cfg1(L=L, nsteps=nsteps)
+    p = I.periodic_isotropic(L=L, nsteps=nsteps)
     return p.copy(u0=np.ones((L, L)), v0=np.zeros((L, L)), control=np.zeros((L, L)))
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def _struct(**kw):
     from paper_1908_03876_amd import abi, inputs
     from paper_1908_03876_amd.solver import make_problem_struct
-    p = inputs.cfg1()
+    p = inputs.periodic_isotropic()
     p = p.copy(**kw)
     return make_problem_struct(p, abi.MRT_F32, 64, None)
 
@@ -41,7 +41,7 @@ def test_validate_accepts_workloads():
     from paper_1908_03876_amd import abi, inputs
     from paper_1908_03876_amd.solver import make_problem_struct
     abi.mrt_validate(_struct())
-    p2 = inputs.cfg2_small()
+    p2 = inputs.masked_anisotropic_small()
     abi.mrt_validate(make_problem_struct(p2, abi.MRT_F64, 128, None))
 
 

@@ -20,7 +20,7 @@ def _loss(uN, ut, c, alpha):
 
 def _copy128(nsteps):
     """The 128 x 128 copy of the long-horizon masked workload."""
-    return I.with_control_bump(I.cfg3(L=128, nsteps=nsteps), amp=2.0, sigma=16.0)
+    return I.with_control_bump(I.long_horizon(L=128, nsteps=nsteps), amp=2.0, sigma=16.0)
 
 
 def _torch_grad(p, dtype, ckpt_every, control=None):
@@ -152,7 +152,7 @@ def test_autograd_full_size_long_horizon_bounded_memory():
     import torch
     from paper_1908_03876_amd.autograd import MRTSolve
     from paper_1908_03876_amd.solver import DeviceProblem, Tape
-    p = I.with_control_bump(I.cfg3(L=2048, nsteps=10000), amp=5.0, sigma=256.0)
+    p = I.with_control_bump(I.long_horizon(L=2048, nsteps=10000), amp=5.0, sigma=256.0)
     dp = DeviceProblem(p)
     assert Tape.bytes_needed(dp, 10000) > 400e9
     assert Tape.bytes_needed(dp, 100) < 40e9

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _problems(nsteps=30, sizes=(64, 128, 192, 64, 256, 128), n=6, seed=44):
-    ps = I.cfg4(seed=seed, n=n, nsteps=nsteps, sizes=sizes)
+    ps = I.uneven_batch(seed=seed, n=n, nsteps=nsteps, sizes=sizes)
     return [I.with_control_bump(p, seed=100 + k, amp=2.0) for k, p in enumerate(ps)]
 
 

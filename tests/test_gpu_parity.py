@@ -22,12 +22,12 @@ def _torch_dtype(name):
 
 
 def _cases():
-    c1 = I.cfg1()
+    c1 = I.periodic_isotropic()
     return {
-        "cfg1": c1,
-        "cfg1_control": I.with_control_bump(c1, amp=5.0, sigma=8.0),
-        "cfg1_slow": I.with_control_bump(I.slow_reaction(c1), amp=0.1, sigma=6.0),
-        "masked128": I.with_control_bump(I.cfg2_small(L=128, nsteps=120), amp=3.0),
+        "periodic": c1,
+        "periodic_control": I.with_control_bump(c1, amp=5.0, sigma=8.0),
+        "periodic_slow": I.with_control_bump(I.slow_reaction(c1), amp=0.1, sigma=6.0),
+        "masked128": I.with_control_bump(I.masked_anisotropic_small(L=128, nsteps=120), amp=3.0),
         "d_not_one": I.tiny(seed=23, L=12, nsteps=25, anisotropic=False).copy(du=0.7, dv=1.4),
     }
 
@@ -64,7 +64,7 @@ def _problem(name):
     return _cases()[name]
 
 
-NAMES = ["cfg1", "cfg1_control", "cfg1_slow", "masked128", "ragged_periodic",
+NAMES = ["periodic", "periodic_control", "periodic_slow", "masked128", "ragged_periodic",
          "ragged_masked_periodic", "walls_only", "d_not_one", "single_site"]
 
 
@@ -129,7 +129,7 @@ def test_checkpointed_equals_store_all_bitwise():
     """Segment recomputation from checkpoints reproduces the recorded
     trajectory exactly, so the gradients are bitwise equal."""
     import torch
-    p = I.with_control_bump(I.cfg2_small(L=128, nsteps=50), amp=3.0)
+    p = I.with_control_bump(I.masked_anisotropic_small(L=128, nsteps=50), amp=3.0)
     full = device_gradient(p, torch.float32, ckpt_every=-1)
     for K in (7, 10, 49):
         ck = device_gradient(p, torch.float32, ckpt_every=K)
@@ -144,7 +144,7 @@ def test_repeated_adjoint_on_one_forward():
     import torch
     from paper_1908_03876_amd import abi
     from paper_1908_03876_amd.solver import DeviceProblem, Tape
-    p = I.with_control_bump(I.cfg2_small(L=128, nsteps=60), amp=3.0)
+    p = I.with_control_bump(I.masked_anisotropic_small(L=128, nsteps=60), amp=3.0)
     p = p.copy(r_u=0.05, a_uv=0.05, b_v=0.05)
     rng = np.random.default_rng(9)
     f = p.fluid
@@ -171,7 +171,7 @@ def test_deterministic_rerun():
     """Reductions have a fixed order and kernels no races: reruns are
     bitwise identical."""
     import torch
-    p = I.with_control_bump(I.cfg2_small(L=128, nsteps=40), amp=3.0)
+    p = I.with_control_bump(I.masked_anisotropic_small(L=128, nsteps=40), amp=3.0)
     a = device_gradient(p, torch.float32)
     b = device_gradient(p, torch.float32)
     for k in ("uN", "vN", "grad", "gacc", "state"):
@@ -265,7 +265,7 @@ def test_full_size_sampled_windows():
     centres match to the FP32 tolerances."""
     import torch
     N = 16
-    p = I.with_control_bump(I.cfg2(L=2048, nsteps=N), amp=5.0, sigma=256.0)
+    p = I.with_control_bump(I.masked_anisotropic(L=2048, nsteps=N), amp=5.0, sigma=256.0)
     dev = device_gradient(p, torch.float32)
     assert dev["n_fluid"] == p.n_fluid
     rng = np.random.default_rng(7)
@@ -302,7 +302,7 @@ def test_full_size_long_horizon_properties():
     import torch
     from paper_1908_03876_amd import abi
     from paper_1908_03876_amd.solver import DeviceProblem, Tape
-    p = I.cfg2(L=2048, nsteps=4000).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
+    p = I.masked_anisotropic(L=2048, nsteps=4000).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
     p = I.with_control_bump(p, amp=0.0)
     p.v0[:] = 0.5 * p.fluid
     dp = DeviceProblem(p, dtype=torch.float32)
