@@ -276,6 +276,28 @@ def test_tlm_adjoint_dot_product(k):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+def test_tlm_adjoint_dot_product_nonsymmetric_tensors():
+    """The same identity with non-symmetric diffusion tensors (positive
+    definite symmetric part).  Then K and the collision matrix
+    C = M0^-1 Pi M0 are not symmetric, so the adjoint collision must use
+    C^T (C^T = M0^-1 Pi^T M0, (CAE)); with symmetric tensors C^T = C and a
+    transposition mistake would go unseen."""
+    p = _cases()[0]
+    p = p.copy(Du=p.Du + np.array([[0.0, 0.12], [-0.12, 0.0]]),
+               Dv=p.Dv + np.array([[0.0, -0.2], [0.2, 0.0]]))
+    rng = np.random.default_rng(20)
+    f = p.fluid
+    a = rng.standard_normal((p.ny, p.nx)) * f
+    dc = rng.standard_normal((p.ny, p.nx)) * f
+    _, _, C, _ = O.species_ops(p.Du, p.du, p.su)
+    assert np.abs(C - C.T).max() > 1e-3
+    duN, _ = O.tlm(p, dc=dc)
+    g, _, _ = O.adjoint(p, a, None)
+    lhs = (a * duN).sum()
+    rhs = (g * dc).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
 def test_tlm_against_complex_step_free_fd():
     """The TLM itself against central differences of u^N (eps = 1e-6)."""
     p = _cases()[0]
