@@ -102,7 +102,7 @@ def bench_batched(args):
     import torch
     from paper_1908_03876_amd import inputs as I
     from paper_1908_03876_amd.batched import Batch
-    N = min(args.nsteps, 2000)
+    N = min(args.nsteps or 2000, 2000)
     ps = I.uneven_batch(seed=4, n=96, nsteps=N)
     sites = sum(p.nx * p.ny for p in ps)
     K = max(1, int(round((N * 6) ** 0.5)))
@@ -138,6 +138,79 @@ def bench_batched(args):
            "hbm_frac": round(bytes_it / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
            "J_sum_history": [round(x, 4) for x in js]}
     b.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_autograd(args):
+    """Differentiation form: the 2048^2 masked anisotropic problem at
+    N = 10000, FP32, with the AMRT sweep as the backward of a
+    torch.autograd.Function and checkpoints every 100 steps.  One step is
+    forward, loss, loss.backward() (recomputing each segment from its
+    checkpoint) and the gradient-descent update."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd import inputs as I
+    from paper_1908_03876_amd.autograd import MRTSolve
+    N = args.nsteps or 10000
+    K = 100 if args.ckpt == "auto" else int(args.ckpt)
+    p = I.with_control_bump(I.long_horizon(L=args.L, nsteps=N), amp=5.0, sigma=args.L / 8)
+    log(f"[bench] autograd: {args.L}^2 N={N} checkpoints every {K}")
+    s = MRTSolve(p, dtype=torch.float32, ckpt_every=K)
+    info = s.tape.info
+    n_fluid = s.tape.n_fluid
+    dev = torch.device("cuda:0")
+    c = torch.tensor(p.control, dtype=torch.float32, device=dev, requires_grad=True)
+    ut = torch.tensor(p.u_target, dtype=torch.float32, device=dev)
+    fl = torch.tensor(p.fluid, dtype=torch.float32, device=dev)
+
+    def one():
+        uN, _ = s(c)
+        loss = 0.5 * (((uN - ut) * fl) ** 2).sum() + 0.5 * p.alpha * (c * c).sum()
+        loss.backward()
+        with torch.no_grad():
+            g = c.grad
+            c.sub_(min(1.0, 1.0 / float(g.abs().max())) * g)
+            c.grad = None
+        return float(loss)
+
+    hist = [one() for _ in range(max(args.warmup, 1))]
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    abi.mrt_timing_reset()
+    abi.mrt_timing_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        hist.append(one())
+        log(f"[bench] iter {k}: loss {hist[-1]:.6g}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    abi.mrt_timing_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    f_ms, f_n = abi.mrt_timing_read(abi.TIMING_FORWARD)
+    a_ms, a_n = abi.mrt_timing_read(abi.TIMING_ADJOINT)
+    r_ms, r_n = abi.mrt_timing_read(abi.TIMING_RECOMPUTE)
+    b_fwd, b_adj, b_norec = bytes_per_site(4)
+    n_solid = p.nx * p.ny - n_fluid
+    # forward without record, recomputation with record, adjoint
+    bytes_it = N * (n_fluid * (b_norec + b_fwd + b_adj) + 3 * 2 * n_solid)
+    out = {"metric": "autograd MRT+AMRT MLUPS (forward + checkpointed backward)",
+           "value": round(n_fluid * N / (ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+           "s_per_iteration": round(ms / 1e3, 3), "iterations": args.steps,
+           "config": {"workload": f"masked anisotropic chemotaxis control, {p.nx}x{p.ny}, "
+                                  f"N={N} steps, AMRT as autograd backward",
+                      "fluid_nodes": n_fluid, "ckpt_every": int(info.ckpt_every),
+                      "segments": int(info.n_segments),
+                      "tape_gib": round(info.device_bytes / 2**30, 2),
+                      "store_all_would_need_gib": round(
+                          (N * 12 * p.nx * p.ny) / 2**30, 1)},
+           "forward_mlups": round(n_fluid * f_n / (f_ms / 1e3) / 1e6, 1) if f_ms else None,
+           "recompute_mlups": round(n_fluid * r_n / (r_ms / 1e3) / 1e6, 1) if r_ms else None,
+           "adjoint_mlups": round(n_fluid * a_n / (a_ms / 1e3) / 1e6, 1) if a_ms else None,
+           "algorithmic_GBps_per_iteration": round(bytes_it / (ms / 1e3) / 1e9, 1),
+           "hbm_frac": round(bytes_it / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "torch_peak_gib": round(torch.cuda.max_memory_allocated(dev) / 2**30, 2),
+           "loss_history": [round(x, 4) for x in hist]}
+    s.close()
     print(json.dumps(out), flush=True)
 
 
@@ -194,15 +267,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed gradient iterations")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=2048)
-    ap.add_argument("--nsteps", type=int, default=4000, help="time steps per solve")
+    ap.add_argument("--nsteps", type=int, default=None,
+                    help="time steps per solve (default: 4000 masked, 10000 "
+                         "autograd, 2000 batched)")
     ap.add_argument("--ckpt", default="auto",
                     help="auto | store | K (checkpoint every K steps)")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="steps of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--workload", default="masked",
-                    choices=["masked", "batched", "surrogate"],
+                    choices=["masked", "autograd", "batched", "surrogate"],
                     help="masked: the 2048^2 masked anisotropic workload (the "
-                         "reported line); batched: 96 uneven periodic instances; "
+                         "reported line); autograd: the same problem at N = 10000 "
+                         "through torch.autograd with checkpoints; batched: 96 "
+                         "uneven periodic instances; "
                          "surrogate: CNN-assisted vs plain loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
@@ -218,6 +295,10 @@ def main():
         return bench_batched(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "autograd":
+        return bench_autograd(args)
+    if args.nsteps is None:
+        args.nsteps = 4000
     import torch
     from paper_1908_03876_amd import abi
     from paper_1908_03876_amd import inputs as I

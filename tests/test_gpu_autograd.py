@@ -173,6 +173,20 @@ def test_autograd_full_size_long_horizon_bounded_memory():
     assert np.array_equal(grads[0], grads[1])
 
 
+def test_autograd_checkpointed_matches_oracle_2000_steps():
+    """The 128 x 128 copy at N = 2000 with checkpoints every 100 steps (20
+    recomputed segments): FP32 gradient from loss.backward() against the
+    FP64 oracle gradient."""
+    import torch
+    p = _copy128(2000)
+    ref = O.cost_gradient(p)
+    out = _torch_grad(p, torch.float32, ckpt_every=100)
+    assert out["solver"].tape.info.n_segments == 20
+    assert rel_l2(out["grad"], ref["grad"], p.fluid) <= 1e-4
+    assert abs(out["loss"] - ref["J"]) <= 1e-5 * ref["J"]
+    out["solver"].close()
+
+
 @pytest.mark.skipif(os.environ.get("MRT_LONG_ORACLE") != "1",
                     reason="FP64 oracle at 10000 steps on 128x128 takes ~2 min "
                            "and ~24 GB of host memory; set MRT_LONG_ORACLE=1")
