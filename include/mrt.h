@@ -348,11 +348,42 @@ int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target,
                        float lr, double* loss /* host, NULL ok */, void* stream);
 
 /* Periodic crops: out[i] = h x w window at (oy[i], ox[i]) of the L x L field
- * src[idx[i]] (idx, oy, ox: device int32 arrays of n entries).
- * Asynchronous. */
+ * src[idx[i]] (idx, oy, ox: device int32 arrays of n entries), minus the
+ * same window of the L x L field `sub` when sub is not NULL (training
+ * targets u(T) - u_base).  Asynchronous. */
 int mrt_srg_gather(const float* src, int32_t L, const int32_t* idx,
-                   const int32_t* oy, const int32_t* ox, float* out, int32_t n,
-                   int32_t h, int32_t w, void* stream);
+                   const int32_t* oy, const int32_t* ox, const float* sub,
+                   float* out, int32_t n, int32_t h, int32_t w, void* stream);
+
+/* Surrogate cost of B <= 32 candidate controls x_b [B][H][W] of one control
+ * problem (classicJ with u(T) replaced by u_base + surrogate(x_b)):
+ *   J_b = 1/2 sum (u_base + S(x_b) - u_target)^2 + alpha/2 sum x_b^2,
+ * u_base and u_target [H][W], sums in double.  J (host, B entries) NULL:
+ * asynchronous, else synchronises and fills it.  dx (NULL: not computed)
+ * receives dJ_b/dx_b = S'(x_b)^T (u_base + S(x_b) - u_target) + alpha x_b.
+ * MRT_ENONFINITE if a J_b is not finite. */
+int mrt_srg_objective(mrt_srg* s, const float* x, const float* u_base,
+                      const float* u_target, double alpha, int32_t B, int32_t H,
+                      int32_t W, double* J /* host, NULL ok */, float* dx,
+                      void* stream);
+
+/* Surrogate-scored step sizes of a gradient step (Section 2.4: the step
+ * zeta_k of c - zeta E; the surrogate stands in for the exact line
+ * minimisation (LM)): J[k] = the surrogate cost above of c - lambdas[k] E
+ * for k < n <= 32 (lambdas and J on the host; n * H * W within the
+ * surrogate's work buffers).  Synchronises the stream. */
+int mrt_srg_score_steps(mrt_srg* s, const float* c, const float* E,
+                        const double* lambdas /* host */, int32_t n,
+                        const float* u_base, const float* u_target, double alpha,
+                        int32_t H, int32_t W, double* J /* host */, void* stream);
+
+/* Warm start of the control: `iters` Adam steps (b1 = 0.9, b2 = 0.999,
+ * eps = 1e-8, learning rate lr) on the surrogate cost of the single field
+ * c [H][W] (H * W <= max_h * max_w), starting from the values c holds.
+ * Asynchronous; c is updated in place. */
+int mrt_srg_warm_start(mrt_srg* s, const float* u_base, const float* u_target,
+                       double alpha, int32_t H, int32_t W, int32_t iters, float lr,
+                       float* c, void* stream);
 
 #ifdef __cplusplus
 }

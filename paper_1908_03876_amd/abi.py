@@ -78,7 +78,8 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_srg_create", "mrt_srg_destroy", "mrt_srg_param", "mrt_srg_copy_param",
            "mrt_srg_sync",
            "mrt_srg_forward", "mrt_srg_backward", "mrt_srg_loss",
-           "mrt_srg_train_step", "mrt_srg_gather"]
+           "mrt_srg_train_step", "mrt_srg_gather", "mrt_srg_objective",
+           "mrt_srg_score_steps", "mrt_srg_warm_start"]
 
 
 def _load():
@@ -133,7 +134,13 @@ def _load():
     L.mrt_srg_loss.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.mrt_srg_train_step.argtypes = [vp, vp, vp, i32, i32, i32, i32, f32,
                                      ctypes.POINTER(ctypes.c_double), vp]
-    L.mrt_srg_gather.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, i32, vp]
+    L.mrt_srg_gather.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, i32, i32, vp]
+    dbl = ctypes.c_double
+    L.mrt_srg_objective.argtypes = [vp, vp, vp, vp, dbl, i32, i32, i32,
+                                    ctypes.POINTER(dbl), vp, vp]
+    L.mrt_srg_score_steps.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), i32, vp, vp, dbl,
+                                      i32, i32, ctypes.POINTER(dbl), vp]
+    L.mrt_srg_warm_start.argtypes = [vp, vp, vp, dbl, i32, i32, i32, f32, vp, vp]
     return L
 
 
@@ -360,6 +367,32 @@ def mrt_srg_train_step(s, x, target, B, H, W, border, lr, want_loss=False, strea
     return v.value if want_loss else None
 
 
-def mrt_srg_gather(src, L, idx, oy, ox, out, n, h, w, stream=None) -> None:
-    _check(lib.mrt_srg_gather(_ptr(src), int(L), _ptr(idx), _ptr(oy), _ptr(ox), _ptr(out),
-                              int(n), int(h), int(w), _stream(stream)))
+def mrt_srg_gather(src, L, idx, oy, ox, out, n, h, w, sub=None, stream=None) -> None:
+    _check(lib.mrt_srg_gather(_ptr(src), int(L), _ptr(idx), _ptr(oy), _ptr(ox), _ptr(sub),
+                              _ptr(out), int(n), int(h), int(w), _stream(stream)))
+
+
+def mrt_srg_objective(s, x, u_base, u_target, alpha, B, H, W, want_J=True, dx=None,
+                      stream=None):
+    """Per-field surrogate costs (list of B floats, or None) and, into dx,
+    their input gradients."""
+    J = (ctypes.c_double * int(B))()
+    _check(lib.mrt_srg_objective(s, _ptr(x), _ptr(u_base), _ptr(u_target), float(alpha),
+                                 int(B), int(H), int(W), J if want_J else None, _ptr(dx),
+                                 _stream(stream)))
+    return list(J) if want_J else None
+
+
+def mrt_srg_score_steps(s, c, E, lambdas, u_base, u_target, alpha, H, W, stream=None):
+    n = len(lambdas)
+    lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
+    J = (ctypes.c_double * n)()
+    _check(lib.mrt_srg_score_steps(s, _ptr(c), _ptr(E), lam, int(n), _ptr(u_base),
+                                   _ptr(u_target), float(alpha), int(H), int(W), J,
+                                   _stream(stream)))
+    return list(J)
+
+
+def mrt_srg_warm_start(s, u_base, u_target, alpha, H, W, iters, lr, c, stream=None) -> None:
+    _check(lib.mrt_srg_warm_start(s, _ptr(u_base), _ptr(u_target), float(alpha), int(H),
+                                  int(W), int(iters), float(lr), _ptr(c), _stream(stream)))

@@ -47,9 +47,14 @@ struct mrt_srg {
   float* act[3] = {nullptr, nullptr, nullptr};
   float* g[2] = {nullptr, nullptr};
   float* dout = nullptr;
+  float* xbuf = nullptr;    // step candidates [n][H][W]
+  float* wm = nullptr;      // warm start: Adam moments and input gradient,
+  float* wv = nullptr;      // max_h * max_w each
+  float* wg = nullptr;
   double* partials = nullptr;
   double* loss_dev = nullptr;
-  double* host = nullptr;
+  double* obj_dev = nullptr;  // per-field objectives [kSrgMaxSteps]
+  double* host = nullptr;     // pinned [kSrgMaxSteps + 8]
   int64_t step = 0;
   std::vector<void*> allocs;
 };
@@ -92,6 +97,29 @@ void backward(mrt_srg* s, const float* x, const float* dy, float* dx, bool wgrad
   mrt::launch_conv_bwd<kC, kC>(g1, s->act[0], s->L[1].wb, g0, dw(1), db(1), B, H, W, 1.f, 1.f, st);
   mrt::launch_tanh_bwd(s->act[0], g0, g0, n, st);
   mrt::launch_conv_bwd<1, kC>(g0, x, s->L[0].wb, dx, dw(0), db(0), B, H, W, s->s_in, 1.f, st);
+}
+
+// Surrogate cost of B fields x (and, when dx is given, its gradient
+// S'(x)^T r + alpha x) into s->obj_dev[0..B).
+void objective(mrt_srg* s, const float* x, const float* ub, const float* ut, float alpha,
+               int B, int H, int W, float* dx, hipStream_t st) {
+  float* y = s->dout;
+  forward(s, x, y, B, H, W, st);
+  mrt::launch_objective(y, ub, ut, x, s->partials, s->obj_dev, B, H, W, alpha, st);
+  if (dx) {
+    backward(s, x, y, dx, false, B, H, W, st);
+    mrt::launch_axpy(dx, x, alpha, size_t(B) * H * W, st);
+  }
+}
+
+int read_objectives(mrt_srg* s, int n, double* J, hipStream_t st) {
+  HIP_OK(hipMemcpyAsync(s->host, s->obj_dev, size_t(n) * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i) {
+    J[i] = s->host[i];
+    if (!std::isfinite(J[i])) return err(MRT_ENONFINITE, "non-finite surrogate cost");
+  }
+  return MRT_OK;
 }
 
 void free_srg(mrt_srg* s) {
@@ -149,10 +177,19 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
   for (int i = 0; i < 3 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->act[i]);
   for (int i = 0; i < 2 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->g[i]);
   if (!rc) rc = alloc(hwb * 4, (void**)&s->dout);
-  if (!rc) rc = alloc((size_t(mrt::mse_partials_needed(max_batch, max_h, max_w)) + 8) * 8,
+  if (!rc) rc = alloc(hwb * 4, (void**)&s->xbuf);
+  const size_t hw1 = size_t(max_h) * max_w;
+  if (!rc) rc = alloc(hw1 * 4, (void**)&s->wm);
+  if (!rc) rc = alloc(hw1 * 4, (void**)&s->wv);
+  if (!rc) rc = alloc(hw1 * 4, (void**)&s->wg);
+  // MSE: one partial per 256 pixels; objectives: per field, rounded up
+  if (!rc) rc = alloc((size_t(mrt::mse_partials_needed(max_batch, max_h, max_w)) +
+                       mrt::kSrgMaxSteps + 8) * 8,
                       (void**)&s->partials);
   if (!rc) rc = alloc(64, (void**)&s->loss_dev);
-  if (!rc && hipHostMalloc((void**)&s->host, 64) != hipSuccess) rc = err(MRT_ENOMEM, "pinned");
+  if (!rc) rc = alloc(mrt::kSrgMaxSteps * 8, (void**)&s->obj_dev);
+  if (!rc && hipHostMalloc((void**)&s->host, (mrt::kSrgMaxSteps + 8) * 8) != hipSuccess)
+    rc = err(MRT_ENOMEM, "pinned");
   if (rc) {
     free_srg(s);
     return rc;
@@ -276,11 +313,73 @@ int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target, int32_t 
 }
 
 int mrt_srg_gather(const float* src, int32_t L, const int32_t* idx, const int32_t* oy,
-                   const int32_t* ox, float* out, int32_t n, int32_t h, int32_t w,
-                   void* stream) {
+                   const int32_t* ox, const float* sub, float* out, int32_t n, int32_t h,
+                   int32_t w, void* stream) {
   if (!src || !idx || !oy || !ox || !out || L < 1 || n < 1 || h < 1 || w < 1 || h > L || w > L)
     return err(MRT_EINVAL, "invalid crop request");
-  mrt::launch_gather_crops(src, L, idx, oy, ox, out, n, h, w, static_cast<hipStream_t>(stream));
+  mrt::launch_gather_crops(src, L, idx, oy, ox, sub, out, n, h, w,
+                           static_cast<hipStream_t>(stream));
+  return launch_err();
+}
+
+int mrt_srg_objective(mrt_srg* s, const float* x, const float* u_base, const float* u_target,
+                      double alpha, int32_t B, int32_t H, int32_t W, double* J, float* dx,
+                      void* stream) {
+  if (!s || !x || !u_base || !u_target) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, B, H, W);
+  if (rc) return rc;
+  if (B > mrt::kSrgMaxSteps) return err(MRT_EINVAL, "at most 32 fields per objective call");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return err(MRT_EINVAL, "alpha must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  objective(s, x, u_base, u_target, float(alpha), B, H, W, dx, st);
+  rc = launch_err();
+  if (rc || !J) return rc;
+  return read_objectives(s, B, J, st);
+}
+
+int mrt_srg_score_steps(mrt_srg* s, const float* c, const float* E, const double* lambdas,
+                        int32_t n, const float* u_base, const float* u_target, double alpha,
+                        int32_t H, int32_t W, double* J, void* stream) {
+  if (!s || !c || !E || !lambdas || !u_base || !u_target || !J)
+    return err(MRT_EINVAL, "NULL argument");
+  if (n < 1 || n > mrt::kSrgMaxSteps) return err(MRT_EINVAL, "1..32 step candidates");
+  int rc = check_shape(s, n, H, W);
+  if (rc) return rc;
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return err(MRT_EINVAL, "alpha must be >= 0");
+  mrt::SrgSteps lam{};
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(lambdas[k])) return err(MRT_EINVAL, "non-finite step size");
+    lam.v[k] = float(lambdas[k]);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t hw = size_t(H) * W;
+  mrt::launch_candidates(c, E, lam, n, hw, s->xbuf, st);
+  objective(s, s->xbuf, u_base, u_target, float(alpha), n, H, W, nullptr, st);
+  rc = launch_err();
+  if (rc) return rc;
+  return read_objectives(s, n, J, st);
+}
+
+int mrt_srg_warm_start(mrt_srg* s, const float* u_base, const float* u_target, double alpha,
+                       int32_t H, int32_t W, int32_t iters, float lr, float* c,
+                       void* stream) {
+  if (!s || !u_base || !u_target || !c) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, 1, H, W);
+  if (rc) return rc;
+  if (size_t(H) * W > size_t(s->max_h) * s->max_w)
+    return err(MRT_EINVAL, "warm start field larger than max_h x max_w");
+  if (iters < 0 || !(lr > 0.f)) return err(MRT_EINVAL, "iters >= 0 and lr > 0 required");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return err(MRT_EINVAL, "alpha must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t hw = size_t(H) * W;
+  HIP_OK(hipMemsetAsync(s->wm, 0, hw * 4, st));
+  HIP_OK(hipMemsetAsync(s->wv, 0, hw * 4, st));
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int k = 1; k <= iters; ++k) {
+    objective(s, c, u_base, u_target, float(alpha), 1, H, W, s->wg, st);
+    const float c1 = 1.f - std::pow(b1, float(k)), c2 = 1.f - std::pow(b2, float(k));
+    mrt::launch_adam(c, nullptr, s->wg, s->wm, s->wv, int(hw), lr, b1, b2, eps, c1, c2, st);
+  }
   return launch_err();
 }
 

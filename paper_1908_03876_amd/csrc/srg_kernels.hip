@@ -231,18 +231,88 @@ __global__ __launch_bounds__(kB) void to_bf16_kernel(const float* __restrict__ w
   if (i < n) wb[i] = f32_to_bf16(w[i]);
 }
 
-// Periodic crops: out[i] = src[idx[i]] shifted by (oy[i], ox[i]), size h x w.
+// Periodic crops: out[i] = src[idx[i]] shifted by (oy[i], ox[i]), size h x w,
+// minus the same window of the L x L field `sub` when given.
 __global__ __launch_bounds__(kB) void gather_crops_kernel(
     const float* __restrict__ src, int L, const int* __restrict__ idx,
-    const int* __restrict__ oy, const int* __restrict__ ox, float* __restrict__ out,
-    int n, int h, int w) {
+    const int* __restrict__ oy, const int* __restrict__ ox,
+    const float* __restrict__ sub, float* __restrict__ out, int n, int h, int w) {
   const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
   const size_t hw = size_t(h) * w;
   if (p >= size_t(n) * hw) return;
   const int i = int(p / hw);
   const int r = int(p % hw);
   const int y = (r / w + oy[i]) % L, x = (r % w + ox[i]) % L;
-  out[p] = src[size_t(idx[i]) * L * L + size_t(y) * L + x];
+  const size_t q = size_t(y) * L + x;
+  float v = src[size_t(idx[i]) * L * L + q];
+  if (sub) v -= sub[q];
+  out[p] = v;
+}
+
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double part[kB / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kB / 64; ++i) r += part[i];
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+// Surrogate cost of B candidate controls x_b (one field each):
+//   r_b = u_base + y_b - u_target   (written over y, same index)
+//   J_b = 1/2 sum r_b^2 + alpha/2 sum x_b^2
+// Block (blockIdx.x, b) writes its FP64 partial to partials[b][blockIdx.x].
+__global__ __launch_bounds__(kB) void objective_kernel(float* y, const float* __restrict__ ub,
+                                                       const float* __restrict__ ut,
+                                                       const float* __restrict__ x,
+                                                       double* __restrict__ partials, int hw,
+                                                       float alpha) {
+  const int b = blockIdx.y;
+  const int p = blockIdx.x * kB + threadIdx.x;
+  double acc = 0.0;
+  if (p < hw) {
+    const size_t q = size_t(b) * hw + p;
+    const float d = ub[p] + y[q] - ut[p];
+    y[q] = d;
+    const float xv = x[q];
+    acc = 0.5 * double(d) * double(d) + 0.5 * double(alpha) * double(xv) * double(xv);
+  }
+  const double s = block_sum_d(acc);
+  if (threadIdx.x == 0) partials[size_t(b) * gridDim.x + blockIdx.x] = s;
+}
+
+// out[b] = sum of row b of partials [B][n], fixed order.
+__global__ __launch_bounds__(kB) void rows_sum_kernel(const double* __restrict__ partials,
+                                                      int n, double* __restrict__ out) {
+  const double* row = partials + size_t(blockIdx.x) * n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kB) s += row[i];
+  s = block_sum_d(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// dx += alpha * x
+__global__ __launch_bounds__(kB) void axpy_kernel(float* __restrict__ dx,
+                                                  const float* __restrict__ x, float alpha,
+                                                  size_t n) {
+  const size_t i = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (i < n) dx[i] += alpha * x[i];
+}
+
+// Step candidates X_k = c - lambda_k E (k < n).
+__global__ __launch_bounds__(kB) void candidates_kernel(const float* __restrict__ c,
+                                                        const float* __restrict__ E,
+                                                        SrgSteps lam, int n, size_t hw,
+                                                        float* __restrict__ X) {
+  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (p >= size_t(n) * hw) return;
+  const int k = int(p / hw);
+  const size_t q = p % hw;
+  X[p] = c[q] - lam.v[k] * E[q];
 }
 
 int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
@@ -298,9 +368,31 @@ void launch_to_bf16(const float* w, uint16_t* wb, int n, hipStream_t s) {
 }
 
 void launch_gather_crops(const float* src, int L, const int* idx, const int* oy, const int* ox,
-                         float* out, int n, int h, int w, hipStream_t s) {
+                         const float* sub, float* out, int n, int h, int w, hipStream_t s) {
   hipLaunchKernelGGL(gather_crops_kernel, dim3(blocks_for(size_t(n) * h * w)), dim3(kB), 0, s,
-                     src, L, idx, oy, ox, out, n, h, w);
+                     src, L, idx, oy, ox, sub, out, n, h, w);
+}
+
+int objective_partials_needed(int B, int H, int W) { return B * blocks_for(size_t(H) * W); }
+
+void launch_objective(float* y, const float* ub, const float* ut, const float* x,
+                      double* partials, double* out, int B, int H, int W, float alpha,
+                      hipStream_t s) {
+  const int hw = H * W;
+  const int nb = blocks_for(size_t(hw));
+  hipLaunchKernelGGL(objective_kernel, dim3(nb, B), dim3(kB), 0, s, y, ub, ut, x, partials, hw,
+                     alpha);
+  hipLaunchKernelGGL(rows_sum_kernel, dim3(B), dim3(kB), 0, s, partials, nb, out);
+}
+
+void launch_axpy(float* dx, const float* x, float alpha, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, dx, x, alpha, n);
+}
+
+void launch_candidates(const float* c, const float* E, const SrgSteps& lam, int n, size_t hw,
+                       float* X, hipStream_t s) {
+  hipLaunchKernelGGL(candidates_kernel, dim3(blocks_for(size_t(n) * hw)), dim3(kB), 0, s, c, E,
+                     lam, n, hw, X);
 }
 
 #define MRT_SRG_INST(CI, CO)                                                            \

@@ -92,16 +92,58 @@ class Surrogate:
         abi.mrt_srg_backward(self.handle, x, dy.contiguous(), dx, False, B, H, W)
         return dx
 
-    def loss(self, x: torch.Tensor, y: torch.Tensor, border: int = 0) -> float:
+    def loss(self, x: torch.Tensor, y: torch.Tensor, border: int = 0,
+             sub: Optional[torch.Tensor] = None) -> float:
+        """Interior MSE of the surrogate on x against y (minus the field sub
+        when given, the same for every sample)."""
+        x = x.contiguous()
         B, H, W = x.shape
-        return abi.mrt_srg_loss(self.handle, x.contiguous(), y.contiguous(), B, H, W, border)
+        if sub is not None:
+            assert H == W, "baseline subtraction needs square fields"
+            t = torch.empty_like(x)
+            idx = torch.arange(B, dtype=torch.int32, device=self.device)
+            zero = torch.zeros(B, dtype=torch.int32, device=self.device)
+            abi.mrt_srg_gather(y.contiguous(), H, idx, zero, zero, t, B, H, W,
+                               sub=sub.contiguous())
+            y = t
+        return abi.mrt_srg_loss(self.handle, x, y.contiguous(), B, H, W, border)
+
+    # -- use in the optimisation loop
+    def objective(self, x: torch.Tensor, u_base, u_target, alpha: float, grad: bool = False):
+        """Surrogate costs 1/2 |u_base + S(x_b) - u_t|^2 + alpha/2 |x_b|^2 of
+        the fields x_b, and their input gradients when grad is set."""
+        x = x.contiguous()
+        B, H, W = x.shape
+        dx = torch.empty_like(x) if grad else None
+        J = abi.mrt_srg_objective(self.handle, x, u_base.contiguous(), u_target.contiguous(),
+                                  alpha, B, H, W, want_J=True, dx=dx)
+        return (J, dx) if grad else J
+
+    def score_steps(self, c, E, lambdas, u_base, u_target, alpha: float) -> List[float]:
+        """Surrogate costs of the controls c - lambda_k E."""
+        H, W = c.shape
+        return abi.mrt_srg_score_steps(self.handle, c.contiguous(), E.contiguous(), lambdas,
+                                       u_base.contiguous(), u_target.contiguous(), alpha, H, W)
+
+    def warm_start(self, u_base, u_target, alpha: float, iters: int = 300, lr: float = 0.05,
+                   c0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Control minimising the surrogate cost (Adam on the control, the
+        gradients through the network), from c0 (default 0)."""
+        H, W = u_target.shape
+        c = torch.zeros((H, W), dtype=torch.float32, device=self.device) if c0 is None \
+            else c0.clone().contiguous()
+        abi.mrt_srg_warm_start(self.handle, u_base.contiguous(), u_target.contiguous(), alpha,
+                               H, W, iters, lr, c)
+        return c
 
     # -- training
     def train(self, controls: torch.Tensor, responses: torch.Tensor, steps: int,
               batch: int = 32, crop: int = 64, border: int = 4, lr: float = 2e-3,
-              seed: int = 0, log_every: int = 100) -> List[float]:
+              seed: int = 0, log_every: int = 100,
+              u_base: Optional[torch.Tensor] = None) -> List[float]:
         """Adam on random periodic crops of (control, response) pairs, cosine
-        learning-rate decay.  Returns the logged training losses."""
+        learning-rate decay; the targets are the responses minus u_base when
+        given.  Returns the logged training losses."""
         n, L, _ = controls.shape
         rng = np.random.default_rng(seed)
         x = torch.empty((batch, crop, crop), dtype=torch.float32, device=self.device)
@@ -112,7 +154,7 @@ class Surrogate:
             oy = torch.tensor(rng.integers(0, L, batch), dtype=torch.int32, device=self.device)
             ox = torch.tensor(rng.integers(0, L, batch), dtype=torch.int32, device=self.device)
             abi.mrt_srg_gather(controls, L, idx, oy, ox, x, batch, crop, crop)
-            abi.mrt_srg_gather(responses, L, idx, oy, ox, y, batch, crop, crop)
+            abi.mrt_srg_gather(responses, L, idx, oy, ox, y, batch, crop, crop, sub=u_base)
             lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
             want = (s % log_every == 0) or s == steps - 1
             loss = abi.mrt_srg_train_step(self.handle, x, y, batch, crop, crop, border,
@@ -165,8 +207,9 @@ def physics(L: int, nsteps: int) -> "I.Problem":
 
 def generate_pairs(n: int, L: int, nsteps: int, seed: int, per_launch: int = 96,
                    device="cuda:0", smax: float = 32.0) -> Dict[str, torch.Tensor]:
-    """(control, u(T) - u_base) pairs from forward MRT solves of the batched
-    engine (one persistent launch per group of `per_launch` controls)."""
+    """(control, u(T)) pairs from forward MRT solves of the batched engine
+    (one persistent launch per group of `per_launch` controls), and the
+    uncontrolled u(T) = u_base.  The network learns u(T) - u_base."""
     dev = torch.device(device)
     rng = np.random.default_rng(seed)
     base = physics(L, nsteps)
@@ -185,7 +228,6 @@ def generate_pairs(n: int, L: int, nsteps: int, seed: int, per_launch: int = 96,
         for k in range(cnt):
             abi.mrt_batch_copy(b.handle, k, abi.MRT_FIELD_UN, False, responses[s + k])
     torch.cuda.synchronize(dev)
-    responses -= u_base[None]
     b.close()
     return {"controls": controls, "responses": responses, "u_base": u_base}
 
@@ -201,6 +243,7 @@ class ControlProblem:
         self.it = GradientIteration(self.dp, ckpt_every=-1)
         self.ftape = Tape(self.dp, 0)
         self.uN = self.dp.empty_field()
+        self.trial = self.dp.empty_field()
         self.n_forward = 0
         self.n_adjoint = 0
         assert self.dp.pitch == self.dp.nx, "square lattices with nx a multiple of 64"
@@ -212,11 +255,22 @@ class ControlProblem:
         self.n_forward += 1
         return r["J"]
 
+    def step(self, c: torch.Tensor, E: torch.Tensor, lam: float) -> None:
+        """c <- c - lam E in place (gd_step with a given step size)."""
+        abi.gd_step(self.dp.struct, self.ftape.handle, c, E, zeta=lam, want_zeta=False)
+
+    def trial_cost(self, c: torch.Tensor, E: torch.Tensor, lam: float) -> float:
+        """J(c - lam E), one MRT forward."""
+        self.trial.copy_(c)
+        self.step(self.trial, E, lam)
+        return self.cost(self.trial)
+
     def gradient(self, c: torch.Tensor):
+        """J, E = grad J, ||E||_inf and ||E||_2 at c (one MRT + AMRT)."""
         r = self.it.gradient(control=c)
         self.n_forward += 1
         self.n_adjoint += 1
-        return r["J"], self.it.grad.clone(), r["grad_inf"]
+        return r["J"], self.it.grad.clone(), r["grad_inf"], r["grad_l2"]
 
     def close(self):
         self.it.close()
@@ -231,7 +285,7 @@ def line_search(cp: ControlProblem, c, E, J0, lam0, max_expand=20, golden=6):
 
     def J(lam):
         if lam not in f:
-            f[lam] = cp.cost(c - lam * E)
+            f[lam] = cp.trial_cost(c, E, lam)
         return f[lam]
 
     a, b = 0.0, lam0
@@ -269,30 +323,15 @@ def optimize_plain(cp: ControlProblem, iters: int, c0=None) -> dict:
     hist = []
     J = None
     for _ in range(iters):
-        J, E, einf = cp.gradient(c)
+        J, E, einf, _ = cp.gradient(c)
         hist.append(J)
         lam, Jn = line_search(cp, c, E, J, min(1.0, 1.0 / max(einf, 1e-300)))
-        c = c - lam * E
+        cp.step(c, E, lam)
         J = Jn
     hist.append(J)
     torch.cuda.synchronize()
     return {"J": J, "hist": hist, "control": c, "time": time.perf_counter() - t0,
             "forwards": cp.n_forward, "adjoints": cp.n_adjoint}
-
-
-def warm_start(srg: Surrogate, u_target, u_base, alpha, iters=300, lr=0.05):
-    """Control minimising the surrogate cost 1/2 |u_base + S(c) - u_t|^2 +
-    alpha/2 |c|^2 (Adam on the control, gradients through the network)."""
-    c = torch.zeros_like(u_target)[None]
-    m = torch.zeros_like(c)
-    v = torch.zeros_like(c)
-    for k in range(1, iters + 1):
-        r = u_base + srg.forward(c) - u_target
-        g = srg.input_grad(c, r) + alpha * c
-        m.mul_(0.9).add_(0.1 * g)
-        v.mul_(0.999).add_(0.001 * g * g)
-        c = c - lr * (m / (1 - 0.9 ** k)) / (torch.sqrt(v / (1 - 0.999 ** k)) + 1e-8)
-    return c[0]
 
 
 def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: float,
@@ -307,29 +346,28 @@ def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: floa
     nx = cp.dp.nx
     ut = cp.dp.u_target[:, :nx]
     alpha = cp.prob.alpha
-    c = warm_start(srg, ut, u_base, alpha, iters=warm_iters)
+    c = srg.warm_start(u_base, ut, alpha, iters=warm_iters)
     J = cp.cost(c)
     hist = [J]
     accepted = fallbacks = 0
     for _ in range(max_iters):
         if J <= target_J:
             break
-        J, E, einf = cp.gradient(c)
+        J, E, einf, e2 = cp.gradient(c)
         lam0 = min(1.0, 1.0 / max(einf, 1e-300))
-        lams = lam0 * (2.0 ** np.arange(-2, n_cand - 2))
-        X = torch.stack([c - float(l) * E for l in lams] + [c])
-        S = srg.forward(X)
-        pj = 0.5 * ((u_base[None] + S - ut[None]) ** 2).sum(dim=(1, 2)) \
-            + 0.5 * alpha * (X ** 2).sum(dim=(1, 2))
-        pred = (pj[:-1] - pj[-1]).double().cpu().numpy() + J
-        lam = float(lams[int(np.argmin(pred))])
-        Jn = cp.cost(c - lam * E)
-        if Jn <= J - 1e-4 * lam * float((E * E).sum()):
+        lams = [lam0 * 2.0 ** k for k in range(-2, n_cand - 2)]
+        # surrogate costs of the candidates and of c itself (lambda = 0):
+        # the predicted change is added to the true J
+        pj = srg.score_steps(c, E, lams + [0.0], u_base, ut, alpha)
+        pred = [pj[k] - pj[-1] + J for k in range(n_cand)]
+        lam = lams[int(np.argmin(pred))]
+        Jn = cp.trial_cost(c, E, lam)
+        if Jn <= J - 1e-4 * lam * e2 * e2:
             accepted += 1
         else:
             fallbacks += 1
             lam, Jn = line_search(cp, c, E, J, lam0)
-        c = c - lam * E
+        cp.step(c, E, lam)
         J = Jn
         hist.append(J)
     torch.cuda.synchronize()
