@@ -5,6 +5,13 @@ Network: x -> tanh(conv1(s_in x)) -> tanh(conv2) -> tanh(conv3) -> s_out conv4,
 each conv a periodic 3x3 correlation z[b,o,y,x] = sum_{c,dy,dx} w[o,c,dy+1,dx+1]
 x[b,c,y+dy,x+dx] + bias[o].  Loss: mean squared error over the interior.
 Gradients by the chain rule written out layer by layer.
+
+Precision model (bf16=True), the storage precision of the device kernels:
+the three hidden activations are rounded to bfloat16 after the tanh, and
+the gradients with respect to the hidden pre-activations (after the
+factor 1 - a^2) are rounded to bfloat16; the input, the output, dL/dy and
+all sums stay in full precision here.  Weights are passed in already
+rounded.
 """
 from __future__ import annotations
 
@@ -42,12 +49,13 @@ def conv_backward(dz, x, w, iscale=1.0, oscale=1.0):
     return dx, dw, db
 
 
-def forward(params, x, s_in, s_out):
+def forward(params, x, s_in, s_out, bf16=False):
     """params: list of 4 (w, b).  Returns output and the activations."""
+    r = bf16_round if bf16 else (lambda a: a)
     a0 = x[:, None]
-    a1 = np.tanh(conv(a0, *params[0], iscale=s_in))
-    a2 = np.tanh(conv(a1, *params[1]))
-    a3 = np.tanh(conv(a2, *params[2]))
+    a1 = r(np.tanh(conv(a0, *params[0], iscale=s_in)))
+    a2 = r(np.tanh(conv(a1, *params[1])))
+    a3 = r(np.tanh(conv(a2, *params[2])))
     y = conv(a3, *params[3], oscale=s_out)
     return y[:, 0], (a0, a1, a2, a3)
 
@@ -61,21 +69,21 @@ def mse(pred, target, border):
     return (d * d).sum() / n, 2.0 * d / n
 
 
-def backward(params, acts, dy, s_in, s_out):
+def backward(params, acts, dy, s_in, s_out, bf16=False):
     """dL/dx and [(dL/dw, dL/db)] for the layers given dL/dy."""
+    r = bf16_round if bf16 else (lambda a: a)
     a0, a1, a2, a3 = acts
     grads = [None] * 4
     g = dy[:, None]
-    d3, grads[3] = None, None
     dx3, dw, db = conv_backward(g, a3, params[3][0], oscale=s_out)
     grads[3] = (dw, db)
-    g = dx3 * (1 - a3 * a3)
+    g = r(dx3 * (1 - a3 * a3))
     dx2, dw, db = conv_backward(g, a2, params[2][0])
     grads[2] = (dw, db)
-    g = dx2 * (1 - a2 * a2)
+    g = r(dx2 * (1 - a2 * a2))
     dx1, dw, db = conv_backward(g, a1, params[1][0])
     grads[1] = (dw, db)
-    g = dx1 * (1 - a1 * a1)
+    g = r(dx1 * (1 - a1 * a1))
     dx0, dw, db = conv_backward(g, a0, params[0][0], iscale=s_in)
     grads[0] = (dw, db)
     return dx0[:, 0], grads

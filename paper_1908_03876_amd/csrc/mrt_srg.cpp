@@ -27,7 +27,9 @@ int err(int code, const std::string& m) { return mrt::host::set_error(code, m.c_
 struct Layer {
   int cin = 0, cout = 0;
   float* w = nullptr;      // FP32 master [cout][cin][9]
-  uint16_t* wb = nullptr;  // BF16 compute copy
+  uint16_t* wb = nullptr;  // BF16 compute copy [cout][cin][9] (one-channel layers)
+  uint16_t* wf = nullptr;  // MFMA fragments, forward and transposed (32 x 32 layers)
+  uint16_t* wt = nullptr;
   float* b = nullptr;      // [cout]
   float* dw = nullptr;
   float* db = nullptr;
@@ -44,8 +46,10 @@ struct mrt_srg {
   int max_batch = 0, max_h = 0, max_w = 0;
   float s_in = 1.f, s_out = 1.f;
   Layer L[4];
-  float* act[3] = {nullptr, nullptr, nullptr};
-  float* g[2] = {nullptr, nullptr};
+  uint16_t* act[3] = {nullptr, nullptr, nullptr};  // BF16 [B][H][W][32]
+  uint16_t* g[2] = {nullptr, nullptr};             // BF16 [B][H][W][32]
+  float* wpart = nullptr;                          // weight-gradient partials
+  double* tpart = nullptr;
   float* dout = nullptr;
   float* xbuf = nullptr;    // step candidates [n][H][W]
   float* wm = nullptr;      // warm start: Adam moments and input gradient,
@@ -76,27 +80,46 @@ int launch_err() {
 }
 
 void forward(mrt_srg* s, const float* x, float* y, int B, int H, int W, hipStream_t st) {
-  mrt::launch_conv_fwd<1, kC>(x, s->L[0].wb, s->L[0].b, s->act[0], B, H, W, s->s_in, 1.f, true, st);
-  mrt::launch_conv_fwd<kC, kC>(s->act[0], s->L[1].wb, s->L[1].b, s->act[1], B, H, W, 1.f, 1.f, true, st);
-  mrt::launch_conv_fwd<kC, kC>(s->act[1], s->L[2].wb, s->L[2].b, s->act[2], B, H, W, 1.f, 1.f, true, st);
-  mrt::launch_conv_fwd<kC, 1>(s->act[2], s->L[3].wb, s->L[3].b, y, B, H, W, 1.f, s->s_out, false, st);
+  mrt::launch_srg_l0_fwd(x, s->L[0].wb, s->L[0].b, s->act[0], B, H, W, s->s_in, st);
+  mrt::launch_srg_c32_fwd(s->act[0], s->L[1].wf, s->L[1].b, s->act[1], B, H, W, st);
+  mrt::launch_srg_c32_fwd(s->act[1], s->L[2].wf, s->L[2].b, s->act[2], B, H, W, st);
+  mrt::launch_srg_l3_fwd(s->act[2], s->L[3].wb, s->L[3].b, y, B, H, W, s->s_out, st);
 }
 
 // Backward through the layers of the last forward on x, from dy = dL/dy.
 void backward(mrt_srg* s, const float* x, const float* dy, float* dx, bool wgrads, int B,
               int H, int W, hipStream_t st) {
-  const size_t n = size_t(B) * kC * H * W;
-  float* g0 = s->g[0];
-  float* g1 = s->g[1];
-  auto dw = [&](int l) { return wgrads ? s->L[l].dw : nullptr; };
-  auto db = [&](int l) { return wgrads ? s->L[l].db : nullptr; };
-  mrt::launch_conv_bwd<kC, 1>(dy, s->act[2], s->L[3].wb, g0, dw(3), db(3), B, H, W, 1.f, s->s_out, st);
-  mrt::launch_tanh_bwd(s->act[2], g0, g0, n, st);
-  mrt::launch_conv_bwd<kC, kC>(g0, s->act[1], s->L[2].wb, g1, dw(2), db(2), B, H, W, 1.f, 1.f, st);
-  mrt::launch_tanh_bwd(s->act[1], g1, g1, n, st);
-  mrt::launch_conv_bwd<kC, kC>(g1, s->act[0], s->L[1].wb, g0, dw(1), db(1), B, H, W, 1.f, 1.f, st);
-  mrt::launch_tanh_bwd(s->act[0], g0, g0, n, st);
-  mrt::launch_conv_bwd<1, kC>(g0, x, s->L[0].wb, dx, dw(0), db(0), B, H, W, s->s_in, 1.f, st);
+  uint16_t* g0 = s->g[0];
+  uint16_t* g1 = s->g[1];
+  // layer 3 (32 -> 1): dz2 with the tanh of layer 2 folded in
+  mrt::launch_srg_l3_bwd_data(dy, s->L[3].wb, s->act[2], g0, B, H, W, s->s_out, st);
+  if (wgrads)
+    mrt::launch_srg_thin_wgrad(s->act[2], dy, -1, s->tpart, B, H, W, s->s_out, s->s_out, 0,
+                               s->L[3].dw, s->L[3].db, st);
+  // layer 2 (32 -> 32)
+  if (wgrads)
+    mrt::launch_srg_c32_bwd_weight(g0, s->act[1], s->wpart, s->L[2].dw, s->L[2].db, B, H, W, st);
+  mrt::launch_srg_c32_bwd_data(g0, s->L[2].wt, s->act[1], g1, B, H, W, st);
+  // layer 1 (32 -> 32)
+  if (wgrads)
+    mrt::launch_srg_c32_bwd_weight(g1, s->act[0], s->wpart, s->L[1].dw, s->L[1].db, B, H, W, st);
+  mrt::launch_srg_c32_bwd_data(g1, s->L[1].wt, s->act[0], g0, B, H, W, st);
+  // layer 0 (1 -> 32)
+  if (dx) mrt::launch_srg_l0_bwd_data(g0, s->L[0].wb, dx, B, H, W, s->s_in, st);
+  if (wgrads)
+    mrt::launch_srg_thin_wgrad(g0, x, 1, s->tpart, B, H, W, s->s_in, 1.f, 1, s->L[0].dw,
+                               s->L[0].db, st);
+}
+
+// BF16 compute copies of the FP32 masters.
+void refresh_weights(mrt_srg* s, hipStream_t st) {
+  for (int l = 0; l < 4; ++l) {
+    Layer& y = s->L[l];
+    if (y.wf)
+      mrt::launch_srg_pack(y.w, y.wf, y.wt, st);
+    else
+      mrt::launch_to_bf16(y.w, y.wb, y.nw(), st);
+  }
 }
 
 // Surrogate cost of B fields x (and, when dx is given, its gradient
@@ -164,7 +187,12 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
     y.cout = cout[l];
     const size_t nw = size_t(y.nw()) * 4, nb = size_t(y.cout) * 4;
     rc = alloc(nw, (void**)&y.w);
-    if (!rc) rc = alloc(nw / 2, (void**)&y.wb);
+    if (y.cin == kC && y.cout == kC) {
+      if (!rc) rc = alloc(nw / 2, (void**)&y.wf);
+      if (!rc) rc = alloc(nw / 2, (void**)&y.wt);
+    } else if (!rc) {
+      rc = alloc(nw / 2, (void**)&y.wb);
+    }
     if (!rc) rc = alloc(nb, (void**)&y.b);
     if (!rc) rc = alloc(nw, (void**)&y.dw);
     if (!rc) rc = alloc(nb, (void**)&y.db);
@@ -174,8 +202,10 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
     if (!rc) rc = alloc(nb, (void**)&y.vb);
   }
   const size_t hwb = size_t(max_batch) * max_h * max_w;
-  for (int i = 0; i < 3 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->act[i]);
-  for (int i = 0; i < 2 && !rc; ++i) rc = alloc(hwb * kC * 4, (void**)&s->g[i]);
+  for (int i = 0; i < 3 && !rc; ++i) rc = alloc(hwb * kC * 2, (void**)&s->act[i]);
+  for (int i = 0; i < 2 && !rc; ++i) rc = alloc(hwb * kC * 2, (void**)&s->g[i]);
+  if (!rc) rc = alloc(size_t(mrt::kSrgWBlocks) * 4 * mrt::kSrgWPart * 4, (void**)&s->wpart);
+  if (!rc) rc = alloc(mrt::kSrgThinPartDoubles * 8, (void**)&s->tpart);
   if (!rc) rc = alloc(hwb * 4, (void**)&s->dout);
   if (!rc) rc = alloc(hwb * 4, (void**)&s->xbuf);
   const size_t hw1 = size_t(max_h) * max_w;
@@ -233,9 +263,9 @@ int mrt_srg_copy_param(mrt_srg* s, int32_t layer, int32_t kind, int32_t to_srg,
 int mrt_srg_sync(mrt_srg* s, void* stream) {
   if (!s) return err(MRT_EINVAL, "surrogate is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  refresh_weights(s, st);
   for (int l = 0; l < 4; ++l) {
     Layer& y = s->L[l];
-    mrt::launch_to_bf16(y.w, y.wb, y.nw(), st);
     HIP_OK(hipMemsetAsync(y.mw, 0, size_t(y.nw()) * 4, st));
     HIP_OK(hipMemsetAsync(y.vw, 0, size_t(y.nw()) * 4, st));
     HIP_OK(hipMemsetAsync(y.mb, 0, size_t(y.cout) * 4, st));
@@ -300,6 +330,7 @@ int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target, int32_t 
     Layer& y = s->L[l];
     mrt::launch_adam(y.w, y.wb, y.dw, y.mw, y.vw, y.nw(), lr, b1, b2, eps, c1, c2, st);
     mrt::launch_adam(y.b, nullptr, y.db, y.mb, y.vb, y.cout, lr, b1, b2, eps, c1, c2, st);
+    if (y.wf) mrt::launch_srg_pack(y.w, y.wf, y.wt, st);
   }
   rc = launch_err();
   if (rc) return rc;

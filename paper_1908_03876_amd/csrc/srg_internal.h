@@ -9,15 +9,35 @@
 
 namespace mrt {
 
-template <int CIN, int COUT>
-void launch_conv_fwd(const float* x, const uint16_t* w, const float* b, float* y,
-                     int B, int H, int W, float iscale, float oscale, bool act,
-                     hipStream_t s);
-template <int CIN, int COUT>
-void launch_conv_bwd(const float* dz, const float* x, const uint16_t* w, float* dx,
-                     float* dw, float* db, int B, int H, int W, float iscale,
-                     float oscale, hipStream_t s);
-void launch_tanh_bwd(const float* y, const float* dy, float* dz, size_t n, hipStream_t s);
+// Sizes of the reduction scratch of the weight gradients.
+constexpr int kSrgWPart = 32 * 32 * 9 + 32;  // one wavefront partial: dW, db
+constexpr int kSrgWBlocks = 256;             // max blocks of the MFMA weight gradient
+constexpr int kSrgThinBlocks = 256;          // max blocks per tap of the thin ones
+constexpr size_t kSrgThinPartDoubles = size_t(11) * kSrgThinBlocks * 32 + kSrgThinBlocks;
+
+// Hidden activations and gradients are BF16 channels-last [B][H][W][32].
+void launch_srg_l0_fwd(const float* x, const uint16_t* w, const float* b, uint16_t* out, int B,
+                       int H, int W, float iscale, hipStream_t s);
+void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, int B, int H,
+                            int W, float iscale, hipStream_t s);
+void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, float* y, int B,
+                       int H, int W, float oscale, hipStream_t s);
+void launch_srg_l3_bwd_data(const float* dy, const uint16_t* w, const uint16_t* a, uint16_t* dz,
+                            int B, int H, int W, float oscale, hipStream_t s);
+// dw[c][t] = scale sum_p F[p][c] S[p + sgn off(t)]; db per channel
+// (bscale sum F) or single (bscale sum S).
+void launch_srg_thin_wgrad(const uint16_t* F, const float* S, int sgn, double* part, int B,
+                           int H, int W, float scale, float bscale, int bias_per_channel,
+                           float* dw, float* db, hipStream_t s);
+// MFMA weight fragments (forward and transposed) of a 32 x 32 layer.
+void launch_srg_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t s);
+void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, uint16_t* out,
+                        int B, int H, int W, hipStream_t s);
+void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
+                             uint16_t* dzprev, int B, int H, int W, hipStream_t s);
+// part: kSrgWBlocks * 4 * kSrgWPart floats
+void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* part, float* dw,
+                               float* db, int B, int H, int W, hipStream_t s);
 void launch_mse(const float* pred, const float* t, float* dpred, double* partials,
                 double* out, int B, int H, int W, int border, hipStream_t s);
 int mse_partials_needed(int B, int H, int W);

@@ -1,13 +1,25 @@
 // Kernels of the convolutional surrogate of the control-to-state map
 // c -> u(T): four periodic 3x3 convolution layers (1 -> C -> C -> C -> 1
-// channels), tanh between layers, BF16 weights with FP32 accumulation, MSE
-// loss and Adam.  The surrogate only proposes warm starts and step sizes;
-// the MRT solve still decides whether each proposed step is accepted.
+// channels, C = 32), tanh between layers, BF16 weights with FP32
+// accumulation, MSE loss and Adam.  The surrogate only proposes warm starts
+// and step sizes; the MRT solve still decides whether each proposed step is
+// accepted.
 //
-// Layout: activations NCHW float [B][C][H][W], weights [Cout][Cin][3][3]
-// (BF16 compute copy of an FP32 master), periodic padding.  A layer
-// computes z = oscale * (W * (iscale * x) + b).
-#include <hip/hip_bf16.h>
+// Layout: the input x and the output y are float [B][H][W]; the hidden
+// activations and the gradients with respect to the hidden pre-activations
+// are BF16 channels-last [B][H][W][32] (64 bytes per pixel), rounded to
+// nearest even after the tanh (forward) or after the factor 1 - a^2
+// (backward).  Master weights are FP32 [Cout][Cin][3][3]; compute copies
+// are BF16.  Periodic padding.  A layer computes
+// z = oscale * (W * (iscale * x) + b).
+//
+// The two 32 -> 32 layers are implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16): per tap t the 32 x 32 weight matrix W_t
+// multiplies the 32 channels of the 16 pixels of a tile, giving an output
+// of channels x pixels whose lanes hold 4 consecutive channels of one pixel
+// (8-byte channels-last stores).  Each wavefront keeps the 18 weight
+// fragments (9 taps x 2 channel blocks) in registers and walks many tiles.
+// The one-channel first and last layers stay on the vector ALU.
 #include <hip/hip_runtime.h>
 
 #include "srg_internal.h"
@@ -16,6 +28,13 @@ namespace mrt {
 namespace {
 
 constexpr int kB = 256;
+constexpr int kC = 32;
+constexpr int kWaves = kB / 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(uint32_t(h) << 16);
@@ -33,89 +52,454 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-// Forward: one thread per output pixel, all COUT channels in registers;
-// the layer's weights are staged once per block in LDS as FP32.
-template <int CIN, int COUT, bool TANH>
-__global__ __launch_bounds__(kB) void conv_fwd_kernel(
-    const float* __restrict__ x, const uint16_t* __restrict__ w,
-    const float* __restrict__ bias, float* __restrict__ y, int B, int H, int W,
-    float iscale, float oscale) {
-  __shared__ float sw[COUT * CIN * 9];
-  for (int i = threadIdx.x; i < COUT * CIN * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+__device__ __forceinline__ size_t pix(int bh, int W, int x) { return size_t(bh) * W + x; }
+
+// 8 channels (16 bytes) of a channels-last BF16 field as an MFMA fragment.
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+// unpack 2 BF16 of a 32-bit word
+__device__ __forceinline__ float lo16(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi16(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// ------------------------------------------------ first layer (1 -> 32)
+
+// One thread per pixel: a0 = bf16(tanh(b + W0 * (s_in x))), 32 channels.
+__global__ __launch_bounds__(kB) void l0_fwd_kernel(const float* __restrict__ x,
+                                                    const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias,
+                                                    uint16_t* __restrict__ out, int B, int H,
+                                                    int W, float iscale) {
+  __shared__ float sw[kC * 9];
+  __shared__ float sb[kC];
+  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+  if (threadIdx.x < kC) sb[threadIdx.x] = bias[threadIdx.x];
   __syncthreads();
   const size_t hw = size_t(H) * W;
   const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
   if (p >= size_t(B) * hw) return;
-  const int b = int(p / hw);
-  const int r = int(p % hw);
-  const int py = r / W, px = r % W;
-  float acc[COUT];
+  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
+  float v[9];
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) acc[co] = bias[co];
-  const float* xb = x + size_t(b) * CIN * hw;
-  for (int ci = 0; ci < CIN; ++ci) {
-    const float* xc = xb + size_t(ci) * hw;
+  for (int t = 0; t < 9; ++t)
+    v[t] = iscale * x[size_t(b) * hw + size_t(wrap(py + t / 3 - 1, H)) * W +
+                      wrap(px + t % 3 - 1, W)];
+  uint32_t pk[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float z0 = sb[2 * k], z1 = sb[2 * k + 1];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
-      const float v = iscale * xc[size_t(yy) * W + xx];
-#pragma unroll
-      for (int co = 0; co < COUT; ++co) acc[co] += sw[(co * CIN + ci) * 9 + t] * v;
+      z0 += sw[(2 * k) * 9 + t] * v[t];
+      z1 += sw[(2 * k + 1) * 9 + t] * v[t];
     }
+    pk[k] = uint32_t(f32_to_bf16(tanhf(z0))) | (uint32_t(f32_to_bf16(tanhf(z1))) << 16);
   }
-  float* yb = y + size_t(b) * COUT * hw + r;
+  u32x4* o = reinterpret_cast<u32x4*>(out + p * kC);
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) {
-    float z = oscale * acc[co];
-    if (TANH) z = tanhf(z);
-    yb[size_t(co) * hw] = z;
-  }
+  for (int k = 0; k < 4; ++k) o[k] = u32x4{pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]};
 }
 
-// dz = dy * (1 - y^2) for a tanh output y (in place on dy allowed).
-__global__ __launch_bounds__(kB) void tanh_bwd_kernel(const float* __restrict__ y,
-                                                     const float* dy, float* dz,
-                                                     size_t n) {
-  const size_t i = size_t(blockIdx.x) * kB + threadIdx.x;
-  if (i >= n) return;
-  const float t = y[i];
-  dz[i] = dy[i] * (1.0f - t * t);
-}
-
-// Backward data: dx[b][ci][p] = iscale * oscale *
-//   sum_co sum_t W[co][ci][t] dz[b][co][p - off(t)].
-template <int CIN, int COUT>
-__global__ __launch_bounds__(kB) void conv_bwd_data_kernel(
-    const float* __restrict__ dz, const uint16_t* __restrict__ w,
-    float* __restrict__ dx, int B, int H, int W, float iscale, float oscale) {
-  __shared__ float sw[COUT * CIN * 9];
-  for (int i = threadIdx.x; i < COUT * CIN * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+// dx[p] = s_in * sum_t sum_co W0[co][t] dz0[p - off(t)][co]
+__global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restrict__ dz,
+                                                         const uint16_t* __restrict__ w,
+                                                         float* __restrict__ dx, int B, int H,
+                                                         int W, float iscale) {
+  __shared__ float sw[kC * 9];
+  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
   __syncthreads();
   const size_t hw = size_t(H) * W;
   const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
   if (p >= size_t(B) * hw) return;
-  const int b = int(p / hw);
-  const int r = int(p % hw);
-  const int py = r / W, px = r % W;
-  float acc[CIN];
+  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
+  float acc = 0.f;
 #pragma unroll
-  for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
-  const float* db = dz + size_t(b) * COUT * hw;
-  for (int co = 0; co < COUT; ++co) {
-    const float* dc = db + size_t(co) * hw;
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrap(py - (t / 3 - 1), H), xx = wrap(px - (t % 3 - 1), W);
+    const u32x4* g = reinterpret_cast<const u32x4*>(dz + (size_t(b) * hw + size_t(yy) * W + xx) * kC);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      // output pixel q = p - off(t) used input pixel p through tap t
-      const int yy = wrap(py - (t / 3 - 1), H), xx = wrap(px - (t % 3 - 1), W);
-      const float g = dc[size_t(yy) * W + xx];
+    for (int k = 0; k < 4; ++k) {
+      const u32x4 q = g[k];
 #pragma unroll
-      for (int ci = 0; ci < CIN; ++ci) acc[ci] += sw[(co * CIN + ci) * 9 + t] * g;
+      for (int e = 0; e < 4; ++e) {
+        const int co = 8 * k + 2 * e;
+        acc += sw[co * 9 + t] * lo16(q[e]) + sw[(co + 1) * 9 + t] * hi16(q[e]);
+      }
     }
   }
-  float* xb = dx + size_t(b) * CIN * hw + r;
-  const float s = iscale * oscale;
+  dx[p] = iscale * acc;
+}
+
+// ------------------------------------------------- last layer (32 -> 1)
+
+// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci])
+__global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__ a,
+                                                    const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias,
+                                                    float* __restrict__ y, int B, int H, int W,
+                                                    float oscale) {
+  __shared__ float sw[kC * 9];
+  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+  __syncthreads();
+  const size_t hw = size_t(H) * W;
+  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (p >= size_t(B) * hw) return;
+  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
+  float acc = bias[0];
 #pragma unroll
-  for (int ci = 0; ci < CIN; ++ci) xb[size_t(ci) * hw] = s * acc[ci];
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
+    const u32x4* s = reinterpret_cast<const u32x4*>(a + (size_t(b) * hw + size_t(yy) * W + xx) * kC);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const u32x4 q = s[k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ci = 8 * k + 2 * e;
+        acc += sw[ci * 9 + t] * lo16(q[e]) + sw[(ci + 1) * 9 + t] * hi16(q[e]);
+      }
+    }
+  }
+  y[p] = oscale * acc;
+}
+
+// dz2[p][ci] = bf16((s_out sum_t W3[ci][t] dy[p - off(t)]) (1 - a2[p][ci]^2))
+__global__ __launch_bounds__(kB) void l3_bwd_data_kernel(const float* __restrict__ dy,
+                                                         const uint16_t* __restrict__ w,
+                                                         const uint16_t* __restrict__ a,
+                                                         uint16_t* __restrict__ dz, int B, int H,
+                                                         int W, float oscale) {
+  __shared__ float sw[kC * 9];
+  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+  __syncthreads();
+  const size_t hw = size_t(H) * W;
+  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (p >= size_t(B) * hw) return;
+  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
+  float g[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+    g[t] = oscale * dy[size_t(b) * hw + size_t(wrap(py - (t / 3 - 1), H)) * W +
+                       wrap(px - (t % 3 - 1), W)];
+  const u32x4* ap = reinterpret_cast<const u32x4*>(a + p * kC);
+  u32x4* o = reinterpret_cast<u32x4*>(dz + p * kC);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const u32x4 q = ap[k];
+    u32x4 res;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ci = 8 * k + 2 * e;
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        s0 += sw[ci * 9 + t] * g[t];
+        s1 += sw[(ci + 1) * 9 + t] * g[t];
+      }
+      const float a0 = lo16(q[e]), a1 = hi16(q[e]);
+      res[e] = uint32_t(f32_to_bf16(s0 * (1.f - a0 * a0))) |
+               (uint32_t(f32_to_bf16(s1 * (1.f - a1 * a1))) << 16);
+    }
+    o[k] = res;
+  }
+}
+
+// Weight gradients of a one-channel layer from a 32-channel field F and a
+// one-channel field S:  out[c][t] = sum_p F[p][c] S[p + sgn off(t)], with
+// block (blockIdx.x, t = blockIdx.y) partials [9][nblk][32], and for t = 0
+// also the channel sums sum_p F[p][c] ([nblk][32]) and sum_p S[p] ([nblk]).
+__global__ __launch_bounds__(kB) void thin_wgrad_kernel(const uint16_t* __restrict__ F,
+                                                        const float* __restrict__ S, int sgn,
+                                                        double* __restrict__ part, int B, int H,
+                                                        int W) {
+  const int t = blockIdx.y, nblk = gridDim.x;
+  const int dy = sgn * (t / 3 - 1), dx = sgn * (t % 3 - 1);
+  const size_t hw = size_t(H) * W, n = size_t(B) * hw;
+  float acc[kC], fs[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) acc[c] = fs[c] = 0.f;
+  float ss = 0.f;
+  for (size_t p = size_t(blockIdx.x) * kB + threadIdx.x; p < n; p += size_t(nblk) * kB) {
+    const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
+    const float sv = S[size_t(b) * hw + size_t(wrap(py + dy, H)) * W + wrap(px + dx, W)];
+    const u32x4* fp = reinterpret_cast<const u32x4*>(F + p * kC);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const u32x4 q = fp[k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 8 * k + 2 * e;
+        const float f0 = lo16(q[e]), f1 = hi16(q[e]);
+        acc[c] += f0 * sv;
+        acc[c + 1] += f1 * sv;
+        fs[c] += f0;
+        fs[c + 1] += f1;
+      }
+    }
+    ss += S[p];
+  }
+  __shared__ double red[kWaves][2 * kC + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = 0; c < 2 * kC + 1; ++c) {
+    double v = c < kC ? double(acc[c]) : (c < 2 * kC ? double(fs[c - kC]) : double(ss));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kC + 1) {
+    const int c = threadIdx.x;
+    double v = 0.0;
+    for (int k = 0; k < kWaves; ++k) v += red[k][c];
+    if (c < kC)
+      part[(size_t(t) * nblk + blockIdx.x) * kC + c] = v;
+    else if (t == 0 && c < 2 * kC)
+      part[(size_t(9) * nblk + blockIdx.x) * kC + (c - kC)] = v;
+    else if (t == 0)
+      part[size_t(10) * nblk * kC + blockIdx.x] = v;
+  }
+}
+
+// Finish of thin_wgrad: dw[c][t] = scale * sum_blk part[t][blk][c] (layout
+// of the masters, [Cout][Cin][9] with one of them 1); bias gradients either
+// per channel (db[c] = bscale * sum of F) or one value (db[0] = bscale *
+// sum of S).
+__global__ __launch_bounds__(kB) void thin_wgrad_finish_kernel(const double* __restrict__ part,
+                                                               int nblk, float scale,
+                                                               float bscale, int bias_per_channel,
+                                                               float* __restrict__ dw,
+                                                               float* __restrict__ db) {
+  for (int i = threadIdx.x; i < kC * 9; i += kB) {
+    const int c = i / 9, t = i % 9;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[(size_t(t) * nblk + k) * kC + c];
+    dw[i] = float(scale * s);
+  }
+  const int i = threadIdx.x;
+  if (bias_per_channel && i < kC) {
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[(size_t(9) * nblk + k) * kC + i];
+    db[i] = float(bscale * s);
+  }
+  if (!bias_per_channel && i == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[size_t(10) * nblk * kC + k];
+    db[0] = float(bscale * s);
+  }
+}
+
+// ------------------------------------------- 32 -> 32 layers on MFMA
+
+// Weight fragments for the matrix cores, from the FP32 masters [32][32][9]:
+//   fwd[t][mb][lane][j] = W[co = 16 mb + lane % 16][ci = 8 (lane / 16) + j][t]
+//   bwd[t][mb][lane][j] = W[co = 8 (lane / 16) + j][ci = 16 mb + lane % 16][t]
+// (A operands of D = W_t X and D = W_t^T G).
+__global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restrict__ w,
+                                                          uint16_t* __restrict__ fwd,
+                                                          uint16_t* __restrict__ bwd) {
+  const int i = blockIdx.x * kB + threadIdx.x;  // over 9 * 2 * 64 * 8
+  if (i >= 9 * 2 * 64 * 8) return;
+  const int j = i & 7, lane = (i >> 3) & 63, mb = (i >> 9) & 1, t = i >> 10;
+  const int a = 16 * mb + (lane & 15), b = 8 * (lane >> 4) + j;
+  fwd[i] = f32_to_bf16(w[(a * kC + b) * 9 + t]);
+  bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
+}
+
+// Forward of a hidden layer: out = bf16(tanh(b + sum_t W_t in[p + off(t)])).
+// Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).
+__global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict__ in,
+                                                     const uint16_t* __restrict__ wf,
+                                                     const float* __restrict__ bias,
+                                                     uint16_t* __restrict__ out, int B, int H,
+                                                     int W) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
+  bf16x8 a[9][2];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) a[t][mb] = load8(wf + ((t * 2 + mb) * 64 + lane) * 8);
+  float bv[2][4];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[mb][j] = bias[16 * mb + 4 * q + j];
+  const int tpr = (W + 15) >> 4;
+  const int ntiles = B * H * tpr;
+  for (int tile = wid; tile < ntiles; tile += nw) {
+    const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
+    const int b = bh / H, y = bh - b * H;
+    const int px = x0 + c16;
+    const int pl = px < W ? px : W - 1;  // ragged tile: any valid pixel
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = wrap(y + t / 3 - 1, H), xx = wrap(pl + t % 3 - 1, W);
+      const bf16x8 xv = load8(in + pix(b * H + yy, W, xx) * kC + 8 * q);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], xv, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], xv, acc1, 0, 0, 0);
+    }
+    if (px < W) {
+      uint16_t* o = out + pix(bh, W, px) * kC + 4 * q;
+      u32x2 r0, r1;
+      r0[0] = uint32_t(f32_to_bf16(tanhf(acc0[0] + bv[0][0]))) |
+              (uint32_t(f32_to_bf16(tanhf(acc0[1] + bv[0][1]))) << 16);
+      r0[1] = uint32_t(f32_to_bf16(tanhf(acc0[2] + bv[0][2]))) |
+              (uint32_t(f32_to_bf16(tanhf(acc0[3] + bv[0][3]))) << 16);
+      r1[0] = uint32_t(f32_to_bf16(tanhf(acc1[0] + bv[1][0]))) |
+              (uint32_t(f32_to_bf16(tanhf(acc1[1] + bv[1][1]))) << 16);
+      r1[1] = uint32_t(f32_to_bf16(tanhf(acc1[2] + bv[1][2]))) |
+              (uint32_t(f32_to_bf16(tanhf(acc1[3] + bv[1][3]))) << 16);
+      *reinterpret_cast<u32x2*>(o) = r0;
+      *reinterpret_cast<u32x2*>(o + 16) = r1;
+    }
+  }
+}
+
+// Backward data of a hidden layer with the previous tanh folded in:
+// dz_prev[p][ci] = bf16((sum_t W_t^T dz[p - off(t)])[ci] (1 - a_prev[p][ci]^2)).
+__global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __restrict__ dz,
+                                                          const uint16_t* __restrict__ wt,
+                                                          const uint16_t* __restrict__ aprev,
+                                                          uint16_t* __restrict__ dzprev, int B,
+                                                          int H, int W) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
+  bf16x8 a[9][2];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) a[t][mb] = load8(wt + ((t * 2 + mb) * 64 + lane) * 8);
+  const int tpr = (W + 15) >> 4;
+  const int ntiles = B * H * tpr;
+  for (int tile = wid; tile < ntiles; tile += nw) {
+    const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
+    const int b = bh / H, y = bh - b * H;
+    const int px = x0 + c16;
+    const int pl = px < W ? px : W - 1;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = wrap(y - (t / 3 - 1), H), xx = wrap(pl - (t % 3 - 1), W);
+      const bf16x8 gv = load8(dz + pix(b * H + yy, W, xx) * kC + 8 * q);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], gv, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], gv, acc1, 0, 0, 0);
+    }
+    if (px < W) {
+      const size_t o = pix(bh, W, px) * kC + 4 * q;
+      const u32x2 p0 = *reinterpret_cast<const u32x2*>(aprev + o);
+      const u32x2 p1 = *reinterpret_cast<const u32x2*>(aprev + o + 16);
+      float av[2][4] = {{lo16(p0[0]), hi16(p0[0]), lo16(p0[1]), hi16(p0[1])},
+                        {lo16(p1[0]), hi16(p1[0]), lo16(p1[1]), hi16(p1[1])}};
+      float gv[2][4] = {{acc0[0], acc0[1], acc0[2], acc0[3]},
+                        {acc1[0], acc1[1], acc1[2], acc1[3]}};
+      u32x2 r[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float g0 = gv[mb][2 * h] * (1.f - av[mb][2 * h] * av[mb][2 * h]);
+          const float g1 = gv[mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
+          r[mb][h] = uint32_t(f32_to_bf16(g0)) | (uint32_t(f32_to_bf16(g1)) << 16);
+        }
+      *reinterpret_cast<u32x2*>(dzprev + o) = r[0];
+      *reinterpret_cast<u32x2*>(dzprev + o + 16) = r[1];
+    }
+  }
+}
+
+// Weight gradients of a hidden layer on the matrix cores:
+//   dW[co][ci][t] = sum_p dz[p][co] a[p + off(t)][ci],  db[co] = sum_p dz[p][co]
+// over chunks of 32 pixels of a row (the MFMA K dimension); each wavefront
+// accumulates all 9 x 2 x 2 output fragments over its chunks and writes
+// one partial [kSrgWPart] (weights in master layout, then biases).
+__global__ __launch_bounds__(kB) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
+                                                            const uint16_t* __restrict__ a,
+                                                            float* __restrict__ part, int B,
+                                                            int H, int W) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
+  f32x4 acc[9][2][2];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc[t][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbs[2] = {0.f, 0.f};
+  const int cpr = (W + 31) >> 5;
+  const int nchunks = B * H * cpr;
+  for (int ch = wid; ch < nchunks; ch += nw) {
+    const int bh = ch / cpr, x0 = (ch - bh * cpr) * 32;
+    const int b = bh / H, y = bh - b * H;
+    // A[m = co][k = pixel]: dz of the 8 pixels 8q..8q+7 of the chunk
+    bf16x8 af[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int px = x0 + 8 * q + j;
+      const bool in = px < W;
+      const size_t o = pix(bh, W, in ? px : 0) * kC + c16;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const uint16_t v = in ? dz[o + 16 * mb] : uint16_t(0);
+        af[mb][j] = __builtin_bit_cast(__bf16, v);
+        dbs[mb] += bf16_to_f32(v);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = wrap(y + t / 3 - 1, H);
+      bf16x8 bf[2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int px = x0 + 8 * q + j;
+        const int xx = wrap((px < W ? px : W - 1) + t % 3 - 1, W);
+        const size_t o = pix(b * H + yy, W, xx) * kC + c16;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) bf[nb][j] = __builtin_bit_cast(__bf16, a[o + 16 * nb]);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[t][mb][nb] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf[nb], acc[t][mb][nb], 0, 0, 0);
+    }
+  }
+  float* P = part + size_t(wid) * kSrgWPart;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int co = 16 * mb + 4 * q + j, ci = 16 * nb + c16;
+          P[(co * kC + ci) * 9 + t] = acc[t][mb][nb][j];
+        }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    float s = dbs[mb];
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (q == 0) P[kC * kC * 9 + 16 * mb + c16] = s;
+  }
+}
+
+// dw[i] = sum over the nw wavefront partials (fixed order), i < kSrgWPart.
+__global__ __launch_bounds__(kB) void wpart_sum_kernel(const float* __restrict__ part, int nw,
+                                                       float* __restrict__ dw,
+                                                       float* __restrict__ db) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= kSrgWPart) return;
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += part[size_t(k) * kSrgWPart + i];
+  if (i < kC * kC * 9)
+    dw[i] = float(s);
+  else
+    db[i - kC * kC * 9] = float(s);
 }
 
 __device__ __forceinline__ float block_sum(float v) {
@@ -129,41 +513,6 @@ __device__ __forceinline__ float block_sum(float v) {
     for (int i = 0; i < kB / 64; ++i) r += part[i];
   __syncthreads();
   return r;  // valid in thread 0
-}
-
-// Backward weights: block (co, ci) sums over all pixels in fixed order:
-// dW[co][ci][t] = oscale * iscale * sum_p dz[b][co][p] x[b][ci][p + off(t)],
-// and for ci == 0 also db[co] = oscale * sum_p dz[b][co][p].
-template <int CIN, int COUT>
-__global__ __launch_bounds__(kB) void conv_bwd_weight_kernel(
-    const float* __restrict__ dz, const float* __restrict__ x,
-    float* __restrict__ dw, float* __restrict__ dbias, int B, int H, int W,
-    float iscale, float oscale) {
-  const int co = blockIdx.x / CIN, ci = blockIdx.x % CIN;
-  const size_t hw = size_t(H) * W;
-  float acc[10];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) acc[t] = 0.f;
-  for (size_t p = threadIdx.x; p < size_t(B) * hw; p += kB) {
-    const int b = int(p / hw);
-    const int r = int(p % hw);
-    const int py = r / W, px = r % W;
-    const float g = dz[(size_t(b) * COUT + co) * hw + r];
-    const float* xc = x + (size_t(b) * CIN + ci) * hw;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
-      acc[t] += g * xc[size_t(yy) * W + xx];
-    }
-    acc[9] += g;
-  }
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const float s = block_sum(acc[t]);
-    if (threadIdx.x == 0) dw[(co * CIN + ci) * 9 + t] = oscale * iscale * s;
-  }
-  const float s = block_sum(acc[9]);
-  if (threadIdx.x == 0 && ci == 0) dbias[co] = oscale * s;
 }
 
 // MSE over the interior (a border of `border` pixels excluded):
@@ -317,33 +666,79 @@ __global__ __launch_bounds__(kB) void candidates_kernel(const float* __restrict_
 
 int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
 
+
+int blocks_for_pixels(int B, int H, int W) { return blocks_for(size_t(B) * H * W); }
+
+// wavefronts of the MFMA kernels: enough to fill the chip, each walking
+// many tiles so that its weight fragments are loaded once
+int mfma_blocks(int nitems) {
+  const int want = (nitems + kWaves - 1) / kWaves;
+  return want < 512 ? (want > 0 ? want : 1) : 512;
+}
+
 }  // namespace
 
-template <int CIN, int COUT>
-void launch_conv_fwd(const float* x, const uint16_t* w, const float* b, float* y,
-                     int B, int H, int W, float is, float os, bool act, hipStream_t s) {
-  const int nb = blocks_for(size_t(B) * H * W);
-  if (act)
-    hipLaunchKernelGGL((conv_fwd_kernel<CIN, COUT, true>), dim3(nb), dim3(kB), 0, s, x, w, b,
-                       y, B, H, W, is, os);
-  else
-    hipLaunchKernelGGL((conv_fwd_kernel<CIN, COUT, false>), dim3(nb), dim3(kB), 0, s, x, w, b,
-                       y, B, H, W, is, os);
+void launch_srg_l0_fwd(const float* x, const uint16_t* w, const float* b, uint16_t* out, int B,
+                       int H, int W, float iscale, hipStream_t s) {
+  hipLaunchKernelGGL(l0_fwd_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, x, w, b,
+                     out, B, H, W, iscale);
 }
 
-template <int CIN, int COUT>
-void launch_conv_bwd(const float* dz, const float* x, const uint16_t* w, float* dx, float* dw,
-                     float* db, int B, int H, int W, float is, float os, hipStream_t s) {
-  if (dw)
-    hipLaunchKernelGGL((conv_bwd_weight_kernel<CIN, COUT>), dim3(CIN * COUT), dim3(kB), 0, s,
-                       dz, x, dw, db, B, H, W, is, os);
-  if (dx)
-    hipLaunchKernelGGL((conv_bwd_data_kernel<CIN, COUT>), dim3(blocks_for(size_t(B) * H * W)),
-                       dim3(kB), 0, s, dz, w, dx, B, H, W, is, os);
+void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, int B, int H,
+                            int W, float iscale, hipStream_t s) {
+  hipLaunchKernelGGL(l0_bwd_data_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, dz,
+                     w, dx, B, H, W, iscale);
 }
 
-void launch_tanh_bwd(const float* y, const float* dy, float* dz, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(tanh_bwd_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, y, dy, dz, n);
+void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, float* y, int B,
+                       int H, int W, float oscale, hipStream_t s) {
+  hipLaunchKernelGGL(l3_fwd_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, a, w, b,
+                     y, B, H, W, oscale);
+}
+
+void launch_srg_l3_bwd_data(const float* dy, const uint16_t* w, const uint16_t* a, uint16_t* dz,
+                            int B, int H, int W, float oscale, hipStream_t s) {
+  hipLaunchKernelGGL(l3_bwd_data_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, dy,
+                     w, a, dz, B, H, W, oscale);
+}
+
+void launch_srg_thin_wgrad(const uint16_t* F, const float* S, int sgn, double* part, int B,
+                           int H, int W, float scale, float bscale, int bias_per_channel,
+                           float* dw, float* db, hipStream_t s) {
+  int nblk = blocks_for_pixels(B, H, W);
+  if (nblk > kSrgThinBlocks) nblk = kSrgThinBlocks;
+  hipLaunchKernelGGL(thin_wgrad_kernel, dim3(nblk, 9), dim3(kB), 0, s, F, S, sgn, part, B, H, W);
+  hipLaunchKernelGGL(thin_wgrad_finish_kernel, dim3(1), dim3(kB), 0, s, part, nblk, scale,
+                     bscale, bias_per_channel, dw, db);
+}
+
+void launch_srg_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t s) {
+  hipLaunchKernelGGL(pack_weights_kernel, dim3((9 * 2 * 64 * 8 + kB - 1) / kB), dim3(kB), 0, s,
+                     w, fwd, bwd);
+}
+
+void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, uint16_t* out,
+                        int B, int H, int W, hipStream_t s) {
+  const int ntiles = B * H * ((W + 15) / 16);
+  hipLaunchKernelGGL(c32_fwd_kernel, dim3(mfma_blocks(ntiles)), dim3(kB), 0, s, in, wf, b, out,
+                     B, H, W);
+}
+
+void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
+                             uint16_t* dzprev, int B, int H, int W, hipStream_t s) {
+  const int ntiles = B * H * ((W + 15) / 16);
+  hipLaunchKernelGGL(c32_bwd_data_kernel, dim3(mfma_blocks(ntiles)), dim3(kB), 0, s, dz, wt,
+                     aprev, dzprev, B, H, W);
+}
+
+void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* part, float* dw,
+                               float* db, int B, int H, int W, hipStream_t s) {
+  const int nchunks = B * H * ((W + 31) / 32);
+  int nb = (nchunks + kWaves - 1) / kWaves;
+  if (nb > kSrgWBlocks) nb = kSrgWBlocks;
+  hipLaunchKernelGGL(c32_bwd_weight_kernel, dim3(nb), dim3(kB), 0, s, dz, a, part, B, H, W);
+  hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + kB - 1) / kB), dim3(kB), 0, s, part,
+                     nb * kWaves, dw, db);
 }
 
 void launch_mse(const float* pred, const float* t, float* dpred, double* partials,
@@ -395,16 +790,5 @@ void launch_candidates(const float* c, const float* E, const SrgSteps& lam, int 
                      lam, n, hw, X);
 }
 
-#define MRT_SRG_INST(CI, CO)                                                            \
-  template void launch_conv_fwd<CI, CO>(const float*, const uint16_t*, const float*,   \
-                                        float*, int, int, int, float, float, bool,     \
-                                        hipStream_t);                                  \
-  template void launch_conv_bwd<CI, CO>(const float*, const float*, const uint16_t*,   \
-                                        float*, float*, float*, int, int, int, float,  \
-                                        float, hipStream_t);
-MRT_SRG_INST(1, 32)
-MRT_SRG_INST(32, 32)
-MRT_SRG_INST(32, 1)
-#undef MRT_SRG_INST
 
 }  // namespace mrt
