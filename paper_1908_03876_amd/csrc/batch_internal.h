@@ -12,13 +12,28 @@
 namespace mrt {
 
 // One work tile: tile_w x (256 / tile_w) nodes of instance k at (x0, y0).
+// One tile of the sweep: instance k, its first row and column, and the
+// instance's size and field offset (so that a tile needs one table load).
 struct BatchTile {
-  int k, y0, x0, pad;
+  int k, y0, x0, L;
+  unsigned long long fo;
+  unsigned long long pad;
 };
 
-// Grid barrier state (device memory): arrival count, generation, abort flag.
+// Two-level grid barrier, each word on its own 128-byte line: blocks arrive
+// at the counter of their group (block id mod 8, the XCD they run on), the
+// last arriver of a group at the top counter; the last group flips the
+// generation the waiting blocks poll.  `abort` is the sticky time-out flag.
+constexpr int kBarrierGroups = 8;
+struct BarrierLine {
+  unsigned v;
+  unsigned pad[31];
+};
 struct BarrierState {
-  unsigned count, gen, abort, pad;
+  BarrierLine group[kBarrierGroups];
+  BarrierLine top;
+  BarrierLine gen;
+  BarrierLine abort;
 };
 
 // Per-instance reduction slots: [0] J_track, [1] J_reg, [2] sum E^2,

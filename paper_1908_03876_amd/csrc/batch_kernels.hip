@@ -22,39 +22,62 @@ namespace {
 
 using namespace dev;
 
+// Grid barrier of the persistent kernels.  __syncthreads() has completed
+// the block's stores into its XCD's L2 before thread 0 arrives; the last
+// arriver of each XCD group then releases that L2 once (agent-scope
+// fence), the waiting blocks poll with plain atomic loads, and each block
+// acquires once after the generation has moved on.  A wall-clock limit
+// turns a barrier that never completes into a sticky abort flag.
 __device__ __forceinline__ bool grid_sync(BarrierState* bs, unsigned nblocks,
                                           unsigned long long timeout) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    if (__hip_atomic_load(&bs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (__hip_atomic_load(&bs->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       ok = 0;
     } else {
-      __threadfence();  // release this block's stores to every XCD
       const unsigned gen =
-          __hip_atomic_load(&bs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived = __hip_atomic_fetch_add(
-          &bs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == nblocks - 1) {
-        __hip_atomic_store(&bs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&bs->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
+          __hip_atomic_load(&bs->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned ngroups = nblocks < unsigned(kBarrierGroups) ? nblocks : kBarrierGroups;
+      const unsigned grp = blockIdx.x % kBarrierGroups;
+      const unsigned gsize = (nblocks - grp + kBarrierGroups - 1) / kBarrierGroups;
+      bool last = false;
+      const unsigned arrived = __hip_atomic_fetch_add(&bs->group[grp].v, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == gsize - 1) {
+        // last of its group: every member's stores are in this L2; publish
+        // them, reset the group counter, arrive at the top
+        __hip_atomic_store(&bs->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned top = __hip_atomic_fetch_add(&bs->top.v, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (top == ngroups - 1) {
+          __hip_atomic_store(&bs->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&bs->gen.v, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          last = true;
+        }
+      }
+      if (!last) {
         const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&bs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(&bs->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
           __builtin_amdgcn_s_sleep(2);
+          // the clock and the abort flag are checked at the first poll and
+          // then every 32 polls
+          if ((spins++ & 31u) != 0u) continue;
           if (wall_clock64() - t0 > timeout) {
-            __hip_atomic_store(&bs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bs->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = 0;
             break;
           }
-          if (__hip_atomic_load(&bs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          if (__hip_atomic_load(&bs->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             ok = 0;
             break;
           }
         }
       }
-      __threadfence();  // acquire the other blocks' stores
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other XCDs' stores
     }
   }
   __syncthreads();
@@ -89,19 +112,60 @@ __device__ __forceinline__ bool tile_node(const BatchTile& tl, int tile_w,
 // Recording is a run-time pointer here as in the single-lattice kernels:
 // no call site is specialised on it, so the recorded forward and the
 // recomputation compute identical values.
+// Node of tile t for this thread: instance offset, geometry, coefficients.
+template <typename T>
+struct TileNode {
+  bool ok;
+  size_t fo;
+  Geometry g;
+  NodeIdx n;
+  int k;
+};
+
+template <typename T>
+__device__ __forceinline__ TileNode<T> tile_of(const BatchArgs<T>& a, int t) {
+  TileNode<T> r;
+  const BatchTile tl = a.tiles[t];
+  r.k = __builtin_amdgcn_readfirstlane(tl.k);
+  r.g = inst_geom(__builtin_amdgcn_readfirstlane(tl.L));
+  r.ok = tile_node(tl, a.tile_w, r.g, r.n);
+  r.fo = size_t(tl.fo);
+  return r;
+}
+
+// Forward sweep over this block's tiles, two at a time: both tiles' loads
+// are issued before either collision, so one tile's loads are in flight
+// while the other is computed.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     T* rec) {
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const BatchTile tl = a.tiles[t];
-    const int k = __builtin_amdgcn_readfirstlane(tl.k);
-    const Geometry g = inst_geom(a.L[k]);
-    NodeIdx n;
-    if (!tile_node(tl, a.tile_w, g, n)) continue;
-    const size_t fo = a.foff[k];
-    forward_node<T, true, false, FIRST>(
-        g, n, a.coef[k], src ? src + 18 * fo : nullptr, dst + 18 * fo,
-        a.u0 + fo, a.v0 + fo, a.ctrl + fo, rec ? rec + 3 * fo : nullptr);
+#ifdef MRT_CONTIG
+  const int per = (a.ntiles + gridDim.x - 1) / gridDim.x;
+  const int t0 = blockIdx.x * per, t1 = min(a.ntiles, t0 + per);
+  for (int t = t0; t < t1; t += 2) {
+    const TileNode<T> A = tile_of(a, t);
+    const bool hasB = t + 1 < t1;
+    const TileNode<T> B = tile_of(a, hasB ? t + 1 : t);
+#else
+  const int nb = gridDim.x;
+  for (int t = blockIdx.x; t < a.ntiles; t += 2 * nb) {
+    const TileNode<T> A = tile_of(a, t);
+    const bool hasB = t + nb < a.ntiles;
+    const TileNode<T> B = tile_of(a, hasB ? t + nb : t);
+#endif
+    T fa[9], ga[9], ca = T(0), fb[9], gb[9], cb = T(0);
+    if (A.ok)
+      forward_gather<T, true, FIRST>(A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
+                                     a.u0 + A.fo, a.v0 + A.fo, a.ctrl + A.fo, fa, ga, ca);
+    if (hasB && B.ok)
+      forward_gather<T, true, FIRST>(B.g, B.n, a.coef[B.k], src ? src + 18 * B.fo : nullptr,
+                                     a.u0 + B.fo, a.v0 + B.fo, a.ctrl + B.fo, fb, gb, cb);
+    if (A.ok)
+      forward_collide_store<T, false>(A.g, A.n, a.coef[A.k], fa, ga, ca, dst + 18 * A.fo,
+                                      rec ? rec + 3 * A.fo : nullptr, 0u);
+    if (hasB && B.ok)
+      forward_collide_store<T, false>(B.g, B.n, a.coef[B.k], fb, gb, cb, dst + 18 * B.fo,
+                                      rec ? rec + 3 * B.fo : nullptr, 0u);
   }
 }
 
@@ -111,10 +175,10 @@ __device__ __forceinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const BatchTile tl = a.tiles[t];
     const int k = __builtin_amdgcn_readfirstlane(tl.k);
-    const Geometry g = inst_geom(a.L[k]);
+    const Geometry g = inst_geom(__builtin_amdgcn_readfirstlane(tl.L));
     NodeIdx n;
     if (!tile_node(tl, a.tile_w, g, n)) continue;
-    const size_t fo = a.foff[k];
+    const size_t fo = size_t(tl.fo);
     adjoint_node<T, true, false, FIRST, false>(
         g, n, a.coef[k], src ? src + 18 * fo : nullptr,
         dst ? dst + 18 * fo : nullptr, a.seed_u + fo, nullptr, rec + 3 * fo,
@@ -271,10 +335,10 @@ __global__ __launch_bounds__(256) void batch_gd_kernel(BatchArgs<T> a, double ze
 
 __global__ void barrier_reset_kernel(BarrierState* bs) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    bs->count = 0u;
-    bs->gen = 0u;
-    bs->abort = 0u;
-    bs->pad = 0u;
+    for (int g = 0; g < kBarrierGroups; ++g) bs->group[g].v = 0u;
+    bs->top.v = 0u;
+    bs->gen.v = 0u;
+    bs->abort.v = 0u;
   }
 }
 

@@ -119,7 +119,8 @@ int build_tiles(mrt_batch* b, int tile_w) {
   for (int k = 0; k < b->count; ++k) {
     beg[k] = int(t.size());
     for (int y = 0; y < b->L[k]; y += tile_h)
-      for (int x = 0; x < b->L[k]; x += tile_w) t.push_back({k, y, x, 0});
+      for (int x = 0; x < b->L[k]; x += tile_w)
+        t.push_back({k, y, x, b->L[k], (unsigned long long)b->foff[k], 0ull});
   }
   beg[b->count] = int(t.size());
   if (t.size() > b->tile_cap) return err(MRT_EINVAL, "tile table overflow");
@@ -429,9 +430,9 @@ int mrt_batch_tune(mrt_batch* b, int32_t steps, mrt_batch_tiles* best,
   b->bpc = best_b;
   // the tuning passes ran the real kernels on the batch buffers: the barrier
   // must not have tripped
-  HIP_OK(hipMemcpy(b->host, b->barrier, sizeof(mrt::BarrierState), hipMemcpyDeviceToHost));
-  const mrt::BarrierState* bs = reinterpret_cast<const mrt::BarrierState*>(b->host);
-  if (bs->abort) return err(MRT_EHIP, "grid barrier timed out during tuning");
+  unsigned* ab = reinterpret_cast<unsigned*>(b->host);
+  HIP_OK(hipMemcpy(ab, &b->barrier->abort.v, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (*ab) return err(MRT_EHIP, "grid barrier timed out during tuning");
   if (best) {
     best->tile_w = best_w;
     best->blocks_per_cu = best_b;
@@ -518,11 +519,10 @@ int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,
   const size_t n = size_t(b->count) * mrt::kBatchSlots;
   HIP_OK(hipMemcpyAsync(b->host, b->res_cost, n * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(b->host + n, b->res_grad, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(b->host + 2 * n, b->barrier, sizeof(mrt::BarrierState),
-                        hipMemcpyDeviceToHost, s));
+  unsigned* ab = reinterpret_cast<unsigned*>(b->host + 2 * n);
+  HIP_OK(hipMemcpyAsync(ab, &b->barrier->abort.v, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  const mrt::BarrierState* bs = reinterpret_cast<const mrt::BarrierState*>(b->host + 2 * n);
-  if (bs->abort)
+  if (*ab)
     return err(MRT_EHIP, "grid barrier timed out: work-groups were not all resident");
   bool finite = true;
   for (int k = 0; k < b->count; ++k) {

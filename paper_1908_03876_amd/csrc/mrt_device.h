@@ -199,24 +199,18 @@ __device__ __forceinline__ void relax(T f[9], T theta,
 
 // --------------------------------------------------------------- forward
 
-// Recording is a run-time flag (rec != null), not a template parameter: the
-// recorded and the plain steps then run the same machine code, so a
-// checkpointed recomputation reproduces the recorded trajectory bit for bit.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
-__device__ __forceinline__ void forward_node(
-    const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
-    const T* __restrict__ u0, const T* __restrict__ v0,
-    const T* __restrict__ ctrl, T* __restrict__ rec) {
+// Pre-collision populations of node n: the pull from src (with wall slots),
+// or the equilibrium initialisation phi_i = w_i Theta_0 (phieq, zero flux)
+// on the first step.  Also returns the node's control value, so that every
+// load of a node update can be issued before any of its stores.
+template <typename T, bool PERIODIC, bool FIRST>
+__device__ __forceinline__ void forward_gather(const Geometry& g, const NodeIdx& n,
+                                               const ModelCoef<T>& m, const T* __restrict__ src,
+                                               const T* __restrict__ u0, const T* __restrict__ v0,
+                                               const T* __restrict__ ctrl, T fu[9], T fv[9],
+                                               T& c) {
   const size_t idx = n.r0 + n.x;
-  unsigned flag = 0, lm = 0;
-  if (MASKED) {
-    flag = wave_flag(g, n);
-    if (flag == 2u) return;  // wavefront inside a solid region
-    lm = link_of(g, flag, idx);
-  }
-  T fu[9], fv[9];
   if (FIRST) {
-    // equilibrium initialisation phi_i = w_i Theta_0 (phieq, zero flux)
     const T a = u0[idx], b = v0[idx];
     fu[0] = m.u.w_rest * a;
     fv[0] = m.v.w_rest * b;
@@ -239,6 +233,18 @@ __device__ __forceinline__ void forward_node(
       fv[i] = sv[o];
     }
   }
+  c = ctrl[idx];
+}
+
+// Collision of the gathered node values and the stores: record (u, j_v),
+// post-collision state with non-temporal stores, wall slots.  `lm` is the
+// node's link word (0 without a mask).
+template <typename T, bool MASKED>
+__device__ __forceinline__ void forward_collide_store(const Geometry& g, const NodeIdx& n,
+                                                      const ModelCoef<T>& m, T fu[9], T fv[9],
+                                                      T c, T* __restrict__ dst,
+                                                      T* __restrict__ rec, unsigned lm) {
+  const size_t idx = n.r0 + n.x;
   // macroscopic values (UGS) and the first moment of v
   T u = T(0), v = T(0);
 #pragma unroll
@@ -259,7 +265,7 @@ __device__ __forceinline__ void forward_node(
   const T ax = u * (m.b00 * jx + m.b01 * jy);
   const T ay = u * (m.b10 * jx + m.b11 * jy);
   const T phu = m.r_u * u * (T(1) - u);
-  const T phv = m.a_uv * u - m.b_v * v + ctrl[idx];
+  const T phv = m.a_uv * u - m.b_v * v + c;
   T t1, t2;
   relax(fu, u, m.u, t1, t2);
   relax(fv, v, m.v, t1, t2);
@@ -308,6 +314,25 @@ __device__ __forceinline__ void forward_node(
   }
 }
 
+// One forward step (eq:LBE with S, PhiS, MF, MC) at node n.  Recording is a
+// run-time flag (rec != null), not a template parameter: the recorded and
+// the plain steps then run the same machine code, so a checkpointed
+// recomputation reproduces the recorded trajectory bit for bit.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+__device__ __forceinline__ void forward_node(
+    const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ u0, const T* __restrict__ v0,
+    const T* __restrict__ ctrl, T* __restrict__ rec) {
+  unsigned lm = 0;
+  if (MASKED) {
+    const unsigned flag = wave_flag(g, n);
+    if (flag == 2u) return;  // wavefront inside a solid region
+    lm = link_of(g, flag, n.r0 + n.x);
+  }
+  T fu[9], fv[9], c;
+  forward_gather<T, PERIODIC, FIRST>(g, n, m, src, u0, v0, ctrl, fu, fv, c);
+  forward_collide_store<T, MASKED>(g, n, m, fu, fv, c, dst, rec, lm);
+}
 
 template <typename T, bool PERIODIC, bool MASKED>
 __device__ __forceinline__ void finalize_node(
