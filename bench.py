@@ -4,7 +4,7 @@ one MI355X.
 Workload (masked anisotropic chemotaxis at scale, FP32): 2048 x 2048 lattice
 with a bounce-back mask of 200 random disks (radius 5-30) plus a solid outer
 ring, full anisotropic self and chemotactic tensors, N = 4000 time steps per
-solve.  One timed step = one gradient iteration of Section 3.2.1: forward MRT
+solve.  One timed step = one gradient iteration of Section 3.2: forward MRT
 solve recording the adjoint tape, cost and adjoint seed, AMRT reverse sweep,
 gradient and norms, gradient step on the control.  Inputs are seeded and
 resident in HBM before timing starts.
@@ -214,6 +214,55 @@ def bench_autograd(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lma(args):
+    """Gradient iterations on the 2048^2 masked anisotropic problem (N = 4000,
+    FP32, store-all) with two step rules from the same start: the heuristic
+    zeta = min(1, 1/||E||_inf) and the linearised line minimisation (LMA),
+    which costs one tangent-linear solve per iteration."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd import inputs as I
+    from paper_1908_03876_amd.solver import DeviceProblem, GradientIteration
+    N = args.nsteps or 4000
+    prob = I.masked_anisotropic(L=args.L, nsteps=N)
+    res = {"metric": "J after k gradient iterations: heuristic step vs LMA step "
+                     "(one tangent-linear solve per iteration)",
+           "config": {"workload": f"masked anisotropic chemotaxis control, {args.L}x{args.L}, "
+                                  f"N={N}, FP32, store-all tape"}}
+    for rule in ("heuristic", "lma"):
+        dp = DeviceProblem(prob, dtype=torch.float32)
+        it = GradientIteration(dp, ckpt_every=N)
+        hist, zetas = [], []
+        it.step() if rule == "heuristic" else it.step_lma()  # warm-up iteration
+        dp.control.copy_(dp.field(prob.control))
+        torch.cuda.synchronize()
+        abi.mrt_timing_reset()
+        abi.mrt_timing_enable(True)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r = it.step() if rule == "heuristic" else it.step_lma()
+            hist.append(r["J"])
+            zetas.append(r["zeta"])
+            log(f"[bench] {rule} iter {k}: J={r['J']:.6g} zeta={r['zeta']:.4g}")
+        r = it.gradient()
+        hist.append(r["J"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        abi.mrt_timing_enable(False)
+        t_ms, t_n = abi.mrt_timing_read(abi.TIMING_TLM)
+        res[rule] = {"s_per_iteration": round(dt, 4), "J_history": [round(x, 4) for x in hist],
+                     "zeta": [float(f"{z:.5g}") for z in zetas]}
+        if rule == "lma" and t_n:
+            res[rule]["tlm_mlups"] = round(it.tape.n_fluid * t_n / (t_ms / 1e3) / 1e6, 1)
+        it.close()
+        del dp
+        torch.cuda.empty_cache()
+    j0 = res["heuristic"]["J_history"][0]
+    res["J_decrease_ratio_lma_over_heuristic"] = round(
+        (j0 - res["lma"]["J_history"][-1]) / max(j0 - res["heuristic"]["J_history"][-1], 1e-300), 1)
+    print(json.dumps(res), flush=True)
+
+
 def bench_surrogate(args):
     """Surrogate-assisted vs plain loop: MRT-generated training pairs on
     256^2 (N = 1000), crop training, then both loops on 256^2 and 1024^2
@@ -278,11 +327,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="steps of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--workload", default="masked",
-                    choices=["masked", "autograd", "batched", "surrogate"],
+                    choices=["masked", "autograd", "batched", "surrogate", "lma"],
                     help="masked: the 2048^2 masked anisotropic workload (the "
                          "reported line); autograd: the same problem at N = 10000 "
                          "through torch.autograd with checkpoints; batched: 96 "
-                         "uneven periodic instances; "
+                         "uneven periodic instances; lma: heuristic vs LMA step "
+                         "sizes on the masked problem; "
                          "surrogate: CNN-assisted vs plain loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
@@ -300,6 +350,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "autograd":
         return bench_autograd(args)
+    if args.workload == "lma":
+        return bench_lma(args)
     if args.nsteps is None:
         args.nsteps = 4000
     import torch

@@ -183,7 +183,7 @@ int cost_gradient(const mrt_problem* p, mrt_tape* t, const void* uN,
                   const double* grad_accum, void* seed_out, void* grad_out,
                   mrt_scalars* out /* host */, void* stream);
 
-/* Gradient step (Section 2.3, Step 5): control <- clamp(control - zeta *
+/* Gradient step (Section 2.4, Step 5): control <- clamp(control - zeta *
  * grad, lo, hi) on fluid nodes.  zeta <= 0 selects the heuristic step
  * zeta = min(1, 1/||grad||_inf) (Remark after Step 6), computed on the
  * device.  lo/hi = -/+INFINITY for no box constraint.  If zeta_used is not
@@ -192,11 +192,39 @@ int gd_step(const mrt_problem* p, mrt_tape* t, void* control,
             const void* grad, double zeta, double lo, double hi,
             double* zeta_used /* host, NULL ok */, void* stream);
 
+/* Tangent-linear model (sensitivity LBE, LIBEG-V; Section 2.4 uses it in
+ * the linearised line minimisation LMA): the derivative of (u^N, v^N) of the
+ * last mrt_forward on this tape in the direction (dc, du0, dv0), each NULL =
+ * 0.  It applies, step by step, the Jacobian of the collision at the
+ * recorded forward state (the record (u, j_v) of every step, re-recorded
+ * segment by segment from the checkpoints in checkpointed mode) followed by
+ * the streaming with bounce-back, from the equilibrium of (du0, dv0).
+ * u0, v0, control must be the buffers of that forward call.  Writes duN
+ * and/or dvN [ny][pitch] (0 on solids).  Uses the tape's adjoint buffers:
+ * do not overlap with amrt_adjoint on the same tape.  MRT_ESTATE if the
+ * tape has no record or no forward ran.  Asynchronous. */
+int mrt_tlm(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
+            const void* control, const void* dc, const void* du0,
+            const void* dv0, void* duN, void* dvN, void* stream);
+
+/* out = sum over the fluid nodes of x * y, accumulated in double in a fixed
+ * order (x, y: [ny][pitch] of the grid's dtype).  The inner product of
+ * the line searches and conjugate-gradient rules of Section 2.4.
+ * Synchronises `stream`; MRT_ENONFINITE if the result is not finite. */
+int mrt_dot(const mrt_problem* p, mrt_tape* t, const void* x, const void* y,
+            double* out /* host */, void* stream);
+
+/* y <- a x + b y on the fluid nodes, 0 on the solid ones (search
+ * directions and control updates of Section 2.4).  Asynchronous. */
+int mrt_axpby(const mrt_problem* p, mrt_tape* t, const void* x, void* y,
+              double a, double b, void* stream);
+
 /* Thread-local text of the last error. */
 const char* mrt_last_error(void);
 
 /* Kernel timing with HIP events recorded on the caller's stream around the
- * step loops.  kind: 0 forward steps, 1 adjoint steps, 2 recompute steps.
+ * step loops.  kind: 0 forward steps, 1 adjoint steps, 2 recompute steps,
+ * 3 tangent-linear steps.
  * mrt_timing_read synchronises on the recorded events and returns the
  * summed milliseconds and the number of kernel launches since the last
  * reset. */
@@ -209,7 +237,7 @@ int mrt_timing_read(int32_t kind, double* ms /* host */,
 /* ------------------------------------------------------------------------
  * Batched form: many independent control problems of uneven size advanced
  * together.  Each gradient iteration (forward, cost and seed, AMRT sweep,
- * gradient and norms, gradient step, for every instance; Section 3.2.1's
+ * gradient and norms, gradient step, for every instance; Section 3.2's
  * discrete optimisation loop) runs the forward pass and the adjoint pass as
  * one persistent launch each, with a grid barrier between time steps, and
  * can be captured once in a HIP graph and replayed.  Problems must be

@@ -40,7 +40,7 @@
 //     psi(T) = dI0/dphi; gradient (gradientLattice): sum over steps of
 //     sum_i psi_v,i dF_v,i/dc with dF_v,i/dc = tau w_i.
 //   * Sensitivity LBE (LIBEG-V) as a forward-mode linearisation (TLM).
-//   * Gradient step (Section 2.3, Step 5 and the heuristic step
+//   * Gradient step (Section 2.4, Step 5 and the heuristic step
 //     zeta = min(1, 1/||E||_inf)).
 #include <cmath>
 #include <complex>

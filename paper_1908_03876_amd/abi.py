@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmrt.so")
 
 MRT_OK, MRT_EINVAL, MRT_ENOMEM, MRT_EHIP, MRT_ENONFINITE, MRT_ESTATE = 0, -1, -2, -3, -4, -5
 MRT_F32, MRT_F64 = 0, 1
-TIMING_FORWARD, TIMING_ADJOINT, TIMING_RECOMPUTE = 0, 1, 2
+TIMING_FORWARD, TIMING_ADJOINT, TIMING_RECOMPUTE, TIMING_TLM = 0, 1, 2, 3
 
 
 class MrtError(RuntimeError):
@@ -70,7 +70,7 @@ MRT_FIELD_UN, MRT_FIELD_VN, MRT_FIELD_GRAD = 4, 5, 6
 EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
            "cost_gradient", "gd_step", "mrt_last_error", "mrt_timing_enable",
-           "mrt_timing_reset", "mrt_timing_read",
+           "mrt_timing_reset", "mrt_timing_read", "mrt_tlm", "mrt_dot", "mrt_axpby",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
            "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
            "mrt_batch_tune", "mrt_batch_set_timeout", "mrt_batch_iteration",
@@ -103,6 +103,9 @@ def _load():
                                 ctypes.POINTER(mrt_scalars), vp]
     L.gd_step.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_tlm.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mrt_dot.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_axpby.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
     L.mrt_last_error.restype = ctypes.c_char_p
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
     L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -229,6 +232,24 @@ def gd_step(p, tape, control, grad, zeta=0.0, lo=-math.inf, hi=math.inf,
                        float(zeta), float(lo), float(hi),
                        ctypes.byref(z) if want_zeta else None, _stream(stream)))
     return z.value if want_zeta else None
+
+
+def mrt_tlm(p, tape, u0, v0, control, dc=None, du0=None, dv0=None, duN=None, dvN=None,
+            stream=None) -> None:
+    _check(lib.mrt_tlm(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control), _ptr(dc),
+                       _ptr(du0), _ptr(dv0), _ptr(duN), _ptr(dvN), _stream(stream)))
+
+
+def mrt_dot(p, tape, x, y, stream=None) -> float:
+    v = ctypes.c_double()
+    _check(lib.mrt_dot(ctypes.byref(p), tape, _ptr(x), _ptr(y), ctypes.byref(v),
+                       _stream(stream)))
+    return v.value
+
+
+def mrt_axpby(p, tape, x, y, a: float, b: float, stream=None) -> None:
+    _check(lib.mrt_axpby(ctypes.byref(p), tape, _ptr(x), _ptr(y), float(a), float(b),
+                         _stream(stream)))
 
 
 def mrt_timing_enable(on: bool) -> None:

@@ -181,8 +181,8 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   std::vector<TimedSpan> pending;
-  double ms[3] = {0, 0, 0};
-  int64_t launches[3] = {0, 0, 0};
+  double ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
 };
 
 Timing& timing() {
@@ -464,6 +464,51 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
   return MRT_OK;
 }
 
+// Tangent-linear sweep: segments in forward order, each re-recorded from
+// its checkpoint when the record slots hold another one, then the TLM
+// steps of the segment into the adjoint ping-pong buffers.
+template <typename T>
+int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
+             const void* control, const void* dc, const void* du0, const void* dv0,
+             void* duN, void* dvN, hipStream_t s) {
+  const mrt::ModelCoef<T> m = model_coef<T>(p);
+  const mrt::Geometry g = geometry(t);
+  const int N = t->nsteps, K = t->K;
+  const T* tu0 = static_cast<const T*>(u0);
+  const T* tv0 = static_cast<const T*>(v0);
+  const T* tc = static_cast<const T*>(control);
+  const T* dsrc = nullptr;
+  for (int seg = 0; seg < t->nseg; ++seg) {
+    const int n0 = seg * K, n1 = std::min(N, n0 + K);
+    if (t->rec_seg != seg) {
+      const T* src = seg == 0 ? nullptr : static_cast<const T*>(t->ckpt[seg]);
+      const T* dummy = nullptr;
+      t->rec_seg = -1;
+      int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true, false, 2, s,
+                                    &dummy);
+      if (rc) return rc;
+      t->rec_seg = seg;
+    }
+    SpanGuard span(3, s);
+    for (int n = n0; n < n1; ++n) {
+      mrt::TlmLaunch<T> a;
+      a.src = dsrc;
+      a.dst = static_cast<T*>(t->abuf[n & 1]);
+      a.du0 = static_cast<const T*>(du0);
+      a.dv0 = static_cast<const T*>(dv0);
+      a.dc = static_cast<const T*>(dc);
+      a.rec = slot<T>(t, n - n0);
+      mrt::launch_tlm_step<T>(g, m, a, s);
+      span.count();
+      int rc = last_launch_error();
+      if (rc) return rc;
+      dsrc = a.dst;
+    }
+  }
+  mrt::launch_finalize<T>(g, dsrc, nullptr, static_cast<T*>(duN), static_cast<T*>(dvN), s);
+  return last_launch_error();
+}
+
 int read_result(mrt_tape* t, hipStream_t s, int n) {
   HIP_TRY(hipMemcpyAsync(t->host, t->result, sizeof(double) * n,
                          hipMemcpyDeviceToHost, s));
@@ -705,6 +750,67 @@ int gd_step(const mrt_problem* p, mrt_tape* t, void* control, const void* grad,
   return MRT_OK;
 }
 
+int mrt_tlm(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
+            const void* control, const void* dc, const void* du0, const void* dv0,
+            void* duN, void* dvN, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (t->mode == 0) return fail(MRT_ESTATE, "tape was created without a record");
+  if (!t->fwd_done) return fail(MRT_ESTATE, "no forward solve recorded on this tape");
+  if (u0 != t->f_u0 || v0 != t->f_v0 || control != t->f_ctrl)
+    return fail(MRT_ESTATE, "u0/v0/control differ from the recorded forward");
+  if (!duN && !dvN) return fail(MRT_EINVAL, "duN or dvN required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->grid.dtype == MRT_F64
+             ? tlm_impl<double>(p, t, u0, v0, control, dc, du0, dv0, duN, dvN, s)
+             : tlm_impl<float>(p, t, u0, v0, control, dc, du0, dv0, duN, dvN, s);
+}
+
+int mrt_dot(const mrt_problem* p, mrt_tape* t, const void* x, const void* y, double* out,
+            void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!x || !y || !out) return fail(MRT_EINVAL, "x, y and out required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const mrt::Geometry g = geometry(t);
+  if (p->grid.dtype == MRT_F64)
+    mrt::launch_dot<double>(g, static_cast<const double*>(x), static_cast<const double*>(y),
+                            t->partials, t->result, s);
+  else
+    mrt::launch_dot<float>(g, static_cast<const float*>(x), static_cast<const float*>(y),
+                           t->partials, t->result, s);
+  rc = last_launch_error();
+  if (rc) return rc;
+  rc = read_result(t, s, mrt::kRedSlots);
+  if (rc) return rc;
+  *out = t->host[0];
+  if (t->host[4] != 0.0 || !std::isfinite(*out))
+    return fail(MRT_ENONFINITE, "non-finite dot product");
+  return MRT_OK;
+}
+
+int mrt_axpby(const mrt_problem* p, mrt_tape* t, const void* x, void* y, double a, double b,
+              void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!x || !y) return fail(MRT_EINVAL, "x and y required");
+  if (!std::isfinite(a) || !std::isfinite(b)) return fail(MRT_EINVAL, "non-finite a or b");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const mrt::Geometry g = geometry(t);
+  if (p->grid.dtype == MRT_F64)
+    mrt::launch_axpby<double>(g, static_cast<const double*>(x), static_cast<double*>(y), a, b,
+                              s);
+  else
+    mrt::launch_axpby<float>(g, static_cast<const float*>(x), static_cast<float*>(y), a, b, s);
+  return last_launch_error();
+}
+
 const char* mrt_last_error(void) { return g_err.c_str(); }
 
 int mrt_timing_enable(int32_t on) {
@@ -723,7 +829,7 @@ int mrt_timing_reset(void) {
     (void)hipEventDestroy(sp.b);
   }
   t.pending.clear();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     t.ms[k] = 0.0;
     t.launches[k] = 0;
   }
@@ -731,7 +837,7 @@ int mrt_timing_reset(void) {
 }
 
 int mrt_timing_read(int32_t kind, double* ms, int64_t* launches) {
-  if (kind < 0 || kind > 2) return fail(MRT_EINVAL, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(MRT_EINVAL, "kind must be 0, 1, 2 or 3");
   Timing& t = timing();
   std::lock_guard<std::mutex> lk(t.mu);
   for (auto& sp : t.pending) {

@@ -4,7 +4,7 @@
 //
 // Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
 // BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
-// Section 3.2.1 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
+// Section 3.2 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -236,9 +236,62 @@ __device__ __forceinline__ void forward_gather(const Geometry& g, const NodeIdx&
   c = ctrl[idx];
 }
 
+// Sources tau S_i + tau w_i Phi (S, PhiS) with tau = 1, 1/Cs^2 = 3: the
+// chemotactic flux (ax, ay) and the kinetics phu on the u populations, phv
+// on the v populations.
+template <typename T>
+__device__ __forceinline__ void add_sources(T fu[9], T fv[9], T phu, T ax, T ay, T phv) {
+  const T p9 = phu * T(1.0 / 9.0), p36 = phu * T(1.0 / 36.0);
+  const T x3 = ax * T(1.0 / 3.0), y3 = ay * T(1.0 / 3.0);
+  const T x12 = ax * T(1.0 / 12.0), y12 = ay * T(1.0 / 12.0);
+  fu[0] += phu * T(4.0 / 9.0);
+  fu[1] += p9 + x3;
+  fu[2] += p9 + y3;
+  fu[3] += p9 - x3;
+  fu[4] += p9 - y3;
+  fu[5] += p36 + x12 + y12;
+  fu[6] += p36 - x12 + y12;
+  fu[7] += p36 - x12 - y12;
+  fu[8] += p36 + x12 - y12;
+  const T q9 = phv * T(1.0 / 9.0), q36 = phv * T(1.0 / 36.0);
+  fv[0] += phv * T(4.0 / 9.0);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) fv[i] += q9;
+#pragma unroll
+  for (int i = 5; i < 9; ++i) fv[i] += q36;
+}
+
+// Post-collision state of a fluid node: non-temporal stores (the state does
+// not fit the caches and is next read one whole sweep later) and the wall
+// slots: a population phi*_i streaming into the solid node x + e_i is
+// reflected; it is parked in that node's slot of plane opp(i), where the
+// next step's pull in direction opp(i) at x reads it.
+template <typename T, bool MASKED>
+__device__ __forceinline__ void store_state(const Geometry& g, const NodeIdx& n,
+                                            const T fu[9], const T fv[9],
+                                            T* __restrict__ dst, unsigned lm) {
+  const size_t idx = n.r0 + n.x;
+  T* dv = dst + 9 * g.plane;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    __builtin_nontemporal_store(fu[i], &dst[size_t(i) * g.plane + idx]);
+    __builtin_nontemporal_store(fv[i], &dv[size_t(i) * g.plane + idx]);
+  }
+  if (MASKED && (lm & 0x1FEu)) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if ((lm >> opp(i)) & 1u) {
+        const size_t o = size_t(opp(i)) * g.plane + push_off(n, i);
+        dst[o] = fu[i];
+        dv[o] = fv[i];
+      }
+    }
+  }
+}
+
 // Collision of the gathered node values and the stores: record (u, j_v),
-// post-collision state with non-temporal stores, wall slots.  `lm` is the
-// node's link word (0 without a mask).
+// post-collision state, wall slots.  `lm` is the node's link word (0
+// without a mask).
 template <typename T, bool MASKED>
 __device__ __forceinline__ void forward_collide_store(const Geometry& g, const NodeIdx& n,
                                                       const ModelCoef<T>& m, T fu[9], T fv[9],
@@ -269,49 +322,47 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
   T t1, t2;
   relax(fu, u, m.u, t1, t2);
   relax(fv, v, m.v, t1, t2);
-  // sources tau S_i + tau w_i Phi (S, PhiS), tau = 1, 1/Cs^2 = 3
-  const T p9 = phu * T(1.0 / 9.0), p36 = phu * T(1.0 / 36.0);
-  const T x3 = ax * T(1.0 / 3.0), y3 = ay * T(1.0 / 3.0);
-  const T x12 = ax * T(1.0 / 12.0), y12 = ay * T(1.0 / 12.0);
-  fu[0] += phu * T(4.0 / 9.0);
-  fu[1] += p9 + x3;
-  fu[2] += p9 + y3;
-  fu[3] += p9 - x3;
-  fu[4] += p9 - y3;
-  fu[5] += p36 + x12 + y12;
-  fu[6] += p36 - x12 + y12;
-  fu[7] += p36 - x12 - y12;
-  fu[8] += p36 + x12 - y12;
-  const T q9 = phv * T(1.0 / 9.0), q36 = phv * T(1.0 / 36.0);
-  fv[0] += phv * T(4.0 / 9.0);
-#pragma unroll
-  for (int i = 1; i < 5; ++i) fv[i] += q9;
-#pragma unroll
-  for (int i = 5; i < 9; ++i) fv[i] += q36;
+  add_sources(fu, fv, phu, ax, ay, phv);
   // solid nodes of mixed wavefronts computed on slot contents they do not
   // own; they store nothing (their slots hold the neighbours' wall stores)
   if (MASKED && (lm & 1u)) return;
-  // streaming (non-temporal) stores: the state does not fit the caches and
-  // is next read one whole sweep later
-  T* dv = dst + 9 * g.plane;
+  store_state<T, MASKED>(g, n, fu, fv, dst, lm);
+}
+
+// Tangent-linear step (sensitivity LBE, LIBEG-V) at a node: the derivative
+// of the collision of forward step n applied to the gathered perturbation
+// (fu, fv), with the recorded pre-collision u and j_v of that step and the
+// control perturbation dc.  The relaxation is linear (relax with theta =
+// the perturbed density); the sources give
+//   d(u B j_v) = du B j_v + u B dj_v,   dPhi_u = r_u (1 - 2u) du,
+//   dPhi_v = a_uv du - b_v dv + dc.
+template <typename T, bool MASKED>
+__device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeIdx& n,
+                                                  const ModelCoef<T>& m, T fu[9], T fv[9],
+                                                  T dc, const T* __restrict__ rec,
+                                                  T* __restrict__ dst, unsigned lm) {
+  const size_t idx = n.r0 + n.x;
+  const T u = __builtin_nontemporal_load(&rec[idx]);
+  const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
+  const T jy = __builtin_nontemporal_load(&rec[2 * g.plane + idx]);
+  T du = T(0), dv = T(0);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    __builtin_nontemporal_store(fu[i], &dst[size_t(i) * g.plane + idx]);
-    __builtin_nontemporal_store(fv[i], &dv[size_t(i) * g.plane + idx]);
+    du += fu[i];
+    dv += fv[i];
   }
-  if (MASKED && (lm & 0x1FEu)) {
-    // wall stores: a population phi*_i streaming into the solid node
-    // x + e_i is reflected; park it in that node's slot of plane opp(i),
-    // where the next step's pull in direction opp(i) at x reads it.
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      if ((lm >> opp(i)) & 1u) {
-        const size_t o = size_t(opp(i)) * g.plane + push_off(n, i);
-        dst[o] = fu[i];
-        dv[o] = fv[i];
-      }
-    }
-  }
+  const T djx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
+  const T djy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
+  const T dax = du * (m.b00 * jx + m.b01 * jy) + u * (m.b00 * djx + m.b01 * djy);
+  const T day = du * (m.b10 * jx + m.b11 * jy) + u * (m.b10 * djx + m.b11 * djy);
+  const T dphu = m.r_u * (T(1) - T(2) * u) * du;
+  const T dphv = m.a_uv * du - m.b_v * dv + dc;
+  T t1, t2;
+  relax(fu, du, m.u, t1, t2);
+  relax(fv, dv, m.v, t1, t2);
+  add_sources(fu, fv, dphu, dax, day, dphv);
+  if (MASKED && (lm & 1u)) return;
+  store_state<T, MASKED>(g, n, fu, fv, dst, lm);
 }
 
 // One forward step (eq:LBE with S, PhiS, MF, MC) at node n.  Recording is a

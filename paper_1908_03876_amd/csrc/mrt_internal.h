@@ -85,6 +85,29 @@ template <typename T>
 void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
                          const AdjLaunch<T>& a, hipStream_t s);
 
+template <typename T>
+struct TlmLaunch {
+  const T* src;      // perturbation of step n-1 (post-collision), or null (n = 0)
+  T* dst;            // perturbation after step n (with wall slots)
+  const T* du0;      // initial perturbations (n = 0 only; null = 0)
+  const T* dv0;
+  const T* dc;       // control perturbation (null = 0)
+  const T* rec;      // record slot of step n (forward u, j_vx, j_vy)
+};
+
+template <typename T>
+void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T>& a,
+                     hipStream_t s);
+
+// result[0] = sum over fluid nodes of x * y (double), result[4] = number of
+// non-finite products.
+template <typename T>
+void launch_dot(const Geometry& g, const T* x, const T* y, double* partials, double* result,
+                hipStream_t s);
+// y <- a x + b y on fluid nodes, 0 on solid nodes.
+template <typename T>
+void launch_axpby(const Geometry& g, const T* x, T* y, double a, double b, hipStream_t s);
+
 // Deterministic two-pass reductions in double.
 // Result slots (double): [0] sum 1/2 (uN-ut)^2, [1] sum alpha/2 c^2,
 // [2] sum E^2, [3] max |E|, [4] count of non-finite values.

@@ -3,7 +3,7 @@
 //
 // Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
 // BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
-// Section 3.2.1 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
+// Section 3.2 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
 //
 // Design (memory-bound stencil, no MFMA):
 //  * One thread per lattice node, 256-thread blocks along x; every
@@ -96,6 +96,51 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
   NodeIdx n;
   if (!node_of_block(g, n)) return;
   adjoint_node<T, PERIODIC, MASKED, FIRST, LAST>(g, n, m, src, dst, seed_u, seed_v, rec, gacc, adj_u0, adj_v0);
+}
+
+// Tangent-linear step of step n: pulls the perturbation (or, for n = 0,
+// the equilibrium of (du0, dv0)), linearised collision at the recorded
+// (u, j_v) of step n, streaming stores as the forward.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+__global__ __launch_bounds__(kBlock) void tlm_step_kernel(
+    Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ du0, const T* __restrict__ dv0, const T* __restrict__ dc,
+    const T* __restrict__ rec) {
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = 0;
+  if (MASKED) {
+    const unsigned flag = wave_flag(g, n);
+    if (flag == 2u) return;  // wavefront inside a solid region
+    lm = link_of(g, flag, idx);
+  }
+  T fu[9], fv[9];
+  if (FIRST) {
+    const T a = du0 ? du0[idx] : T(0), b = dv0 ? dv0[idx] : T(0);
+    fu[0] = m.u.w_rest * a;
+    fv[0] = m.v.w_rest * b;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      fu[i] = m.u.w_axis * a;
+      fv[i] = m.v.w_axis * b;
+    }
+#pragma unroll
+    for (int i = 5; i < 9; ++i) {
+      fu[i] = m.u.w_diag * a;
+      fv[i] = m.v.w_diag * b;
+    }
+  } else {
+    const T* sv = src + 9 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
+      fu[i] = src[o];
+      fv[i] = sv[o];
+    }
+  }
+  const T c = dc ? dc[idx] : T(0);
+  tlm_collide_store<T, MASKED>(g, n, m, fu, fv, c, rec, dst, lm);
 }
 
 __device__ __forceinline__ bool is_fluid(const uint16_t* link, size_t idx) {
@@ -192,6 +237,43 @@ __global__ __launch_bounds__(kBlock) void gd_update_kernel(
     double c = double(ctrl[idx]) - z * double(grad[idx]);
     c = fmin(fmax(c, lo), hi);
     ctrl[idx] = T(c);
+  }
+}
+
+// Partial sums of x . y over the fluid nodes (slot 0), non-finite count
+// (slot 4).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dot_kernel(Geometry g, const T* __restrict__ x,
+                                                     const T* __restrict__ y,
+                                                     double* __restrict__ partials) {
+  const uint16_t* link = g.link;
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t yy = k / g.nx, xx = k % g.nx;
+    const size_t idx = yy * g.pitch + xx;
+    if (is_fluid(link, idx)) {
+      const double v = double(x[idx]) * double(y[idx]);
+      acc[0] += v;
+      if (!isfinite(v)) acc[4] += 1.0;
+    }
+  }
+  block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
+}
+
+// y <- a x + b y on the fluid nodes, 0 on the solid ones.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void axpby_kernel(Geometry g, const T* __restrict__ x,
+                                                       T* __restrict__ y, double a,
+                                                       double b) {
+  const uint16_t* link = g.link;
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t yy = k / g.nx, xx = k % g.nx;
+    const size_t idx = yy * g.pitch + xx;
+    y[idx] = is_fluid(link, idx) ? T(a * double(x[idx]) + b * double(y[idx])) : T(0);
   }
 }
 
@@ -306,6 +388,39 @@ void launch_gd_step(const Geometry& g, T* ctrl, const T* grad, double zeta,
                      s, g, ctrl, grad, zeta, lo, hi, result);
 }
 
+template <typename T>
+void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T>& a,
+                     hipStream_t s) {
+  const bool first = a.src == nullptr;
+  const int nb = stencil_blocks(g);
+#define MRT_TLM(P, M, F)                                                     \
+  hipLaunchKernelGGL((tlm_step_kernel<T, P, M, F>), dim3(nb), dim3(kBlock),  \
+                     0, s, g, m, a.src, a.dst, a.du0, a.dv0, a.dc, a.rec)
+#define MRT_TLM_F(P, M) \
+  if (first) { MRT_TLM(P, M, true); } else { MRT_TLM(P, M, false); }
+  if (g.periodic) {
+    if (g.masked) { MRT_TLM_F(true, true); } else { MRT_TLM_F(true, false); }
+  } else {
+    if (g.masked) { MRT_TLM_F(false, true); } else { MRT_TLM_F(false, false); }
+  }
+#undef MRT_TLM_F
+#undef MRT_TLM
+}
+
+template <typename T>
+void launch_dot(const Geometry& g, const T* x, const T* y, double* partials, double* result,
+                hipStream_t s) {
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0, s, g, x, y,
+                     partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s, partials, kRedBlocks,
+                     result);
+}
+
+template <typename T>
+void launch_axpby(const Geometry& g, const T* x, T* y, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL((axpby_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0, s, g, x, y, a, b);
+}
+
 void launch_count_fluid(const Geometry& g, double* partials, double* result,
                         hipStream_t s) {
   hipLaunchKernelGGL(count_fluid_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s,
@@ -326,7 +441,13 @@ void launch_count_fluid(const Geometry& g, double* partials, double* result,
                                     double*, double*, hipStream_t);          \
   template void launch_gd_step<T>(const Geometry&, T*, const T*, double,     \
                                   double, double, double*, double*,          \
-                                  hipStream_t);
+                                  hipStream_t);                              \
+  template void launch_tlm_step<T>(const Geometry&, const ModelCoef<T>&,     \
+                                   const TlmLaunch<T>&, hipStream_t);        \
+  template void launch_dot<T>(const Geometry&, const T*, const T*, double*,  \
+                              double*, hipStream_t);                         \
+  template void launch_axpby<T>(const Geometry&, const T*, T*, double,       \
+                                double, hipStream_t);
 MRT_INSTANTIATE(float)
 MRT_INSTANTIATE(double)
 #undef MRT_INSTANTIATE

@@ -1,5 +1,5 @@
 """Device-resident problems, tapes and the gradient-descent loop on top of
-the C-ABI (Section 3.2.1, discrete optimisation algorithm: forward N steps,
+the C-ABI (Section 3.2, discrete optimisation algorithm: forward N steps,
 adjoint N..0, gradient, update, repeat).
 
 Fields live in HBM as [ny, pitch] torch tensors (pitch = nx rounded up to 64
@@ -155,7 +155,7 @@ def choose_ckpt_every(dp: DeviceProblem, budget_bytes: int) -> int:
 
 
 class GradientIteration:
-    """One discrete gradient of J(c) and the update (Section 3.2.1):
+    """One discrete gradient of J(c) and the update (Section 3.2):
     forward -> cost & seed -> AMRT adjoint -> gradient & norms -> gd_step."""
 
     def __init__(self, dp: DeviceProblem, ckpt_every: int = -1,
@@ -203,6 +203,43 @@ class GradientIteration:
         r["zeta"] = abi.gd_step(self.dp.struct, self.tape.handle,
                                 self.dp.control, self.grad, zeta, lo, hi,
                                 want_zeta=want_zeta, stream=stream)
+        return r
+
+    def tlm(self, dc=None, du0=None, dv0=None, control=None, stream=None):
+        """Tangent-linear response (du^N, dv^N) of the last forward on this
+        iteration's tape to the perturbation (dc, du0, dv0)."""
+        dp = self.dp
+        c = dp.control if control is None else control
+        if not hasattr(self, "duN"):
+            self.duN = dp.empty_field()
+            self.dvN = dp.empty_field()
+        abi.mrt_tlm(dp.struct, self.tape.handle, dp.u0, dp.v0, c, dc, du0, dv0,
+                    self.duN, self.dvN, stream)
+        return self.duN, self.dvN
+
+    def lma_zeta(self, control=None, stream=None) -> float:
+        """Step of the linearised line minimisation (LMA, Section 2.4) for the
+        quadratic cost, after gradient(): with P = F'(c) E from the
+        tangent-linear model,
+            zeta = (<u^N - u_t, P> + alpha <c, E>) / (<P, P> + alpha <E, E>)."""
+        dp = self.dp
+        c = dp.control if control is None else control
+        P, _ = self.tlm(dc=self.grad, control=c, stream=stream)
+        t = self.tape.handle
+        num = abi.mrt_dot(dp.struct, t, self.seed, P, stream) + \
+            dp.prob.alpha * abi.mrt_dot(dp.struct, t, c, self.grad, stream)
+        den = abi.mrt_dot(dp.struct, t, P, P, stream) + \
+            dp.prob.alpha * abi.mrt_dot(dp.struct, t, self.grad, self.grad, stream)
+        return num / den
+
+    def step_lma(self, lo: float = -math.inf, hi: float = math.inf, stream=None) -> dict:
+        """One gradient iteration with the LMA step size (one extra
+        tangent-linear solve instead of a line search)."""
+        r = self.gradient(stream=stream)
+        z = self.lma_zeta(stream=stream)
+        abi.gd_step(self.dp.struct, self.tape.handle, self.dp.control, self.grad, z, lo, hi,
+                    want_zeta=False, stream=stream)
+        r["zeta"] = z
         return r
 
     def close(self):
