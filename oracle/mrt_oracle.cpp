@@ -316,6 +316,33 @@ void init_equilibrium(const OrcProblem& p, const Ops& ops, const T* u0,
   }
 }
 
+// Push streaming along e_i with halfway bounce-back of both species:
+// phi_i(x + e_i) = post_i(x), or phi_opp(i)(x) = post_i(x) when x + e_i is
+// solid (or outside a non-periodic lattice).
+template <typename T>
+void stream_push(const OrcProblem& p, const Ops& ops, const T* post, T* fnew) {
+  const int nc = p.nx * p.ny;
+  for (int k = 0; k < 2 * Q * nc; ++k) fnew[k] = T(0);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p.ny; ++y)
+    for (int x = 0; x < p.nx; ++x) {
+      int cell = y * p.nx + x;
+      if (p.solid && p.solid[cell]) continue;
+      for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < Q; ++i) {
+          // Streaming into neighbours would race between rows under OpenMP
+          // only if two sources targeted one slot; each (target, i) has a
+          // unique source, so the writes are disjoint.
+          int nb = neighbour(p, x, y, i, +1);
+          T val = post[(s * Q + i) * nc + cell];
+          if (nb >= 0)
+            fnew[(s * Q + i) * nc + nb] = val;
+          else
+            fnew[(s * Q + ops.opp[i]) * nc + cell] = val;
+        }
+    }
+}
+
 // One step: collide every fluid node, then push-stream along e_i with
 // halfway bounce-back (eq:LBE): phi_i(x + e_i, t+1) = phi*_i(x), or
 // phi_opp(i)(x, t+1) = phi*_i(x) when x + e_i is solid.
@@ -336,25 +363,82 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
       collide(p, ops, loc, ctrl ? ctrl[cell] : T(0), out);
       for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = out[k];
     }
-  for (int k = 0; k < 2 * Q * nc; ++k) fnew[k] = T(0);
-#pragma omp parallel for schedule(static)
-  for (int y = 0; y < p.ny; ++y)
-    for (int x = 0; x < p.nx; ++x) {
-      int cell = y * p.nx + x;
-      if (p.solid && p.solid[cell]) continue;
-      for (int s = 0; s < 2; ++s)
-        for (int i = 0; i < Q; ++i) {
-          // Streaming into neighbours would race between rows under OpenMP
-          // only if two sources targeted one slot; each (target, i) has a
-          // unique source, so the writes are disjoint.
-          int nb = neighbour(p, x, y, i, +1);
-          T val = post[(s * Q + i) * nc + cell];
-          if (nb >= 0)
-            fnew[(s * Q + i) * nc + nb] = val;
-          else
-            fnew[(s * Q + ops.opp[i]) * nc + cell] = val;
-        }
+  stream_push(p, ops, post, fnew);
+}
+
+// ------------------------------------------------- continuous adjoint
+
+// Collision of the continuous-adjoint system (FVM-PF-Adj-K for the
+// two-species instance) solved by the same MRT scheme in reversed time
+// s = T - t (Section 3.2.1).  With p the adjoint of u and q that of v:
+//   p_s = div(D_u grad p) + chi (C grad v) . grad p + r_u (1 - 2u) p + a_uv q
+//   q_s = div(D_v grad q) - b_v q - div(chi u C^T grad p)
+// p relaxes like u (K_u, weq_u) and q like v.  The gradients come from the
+// first moments as in the forward: grad v = -K_v j_v / (tau d_v Cs^2) from
+// the forward populations fw at this time, grad p = -K_u j_p / (tau d_u Cs^2)
+// from the adjoint populations.  The cross-diffusion of q by p enters as the
+// flux source a_q = K_v (chi u C^T grad p) / tau, the other terms as scalar
+// sources.  phi: pre-collision [p (Q), q (Q)]; out: post-collision.
+void cadj_collide(const OrcProblem& p, const Ops& ops, const double* fw, const double* phi,
+                  double* out) {
+  double u = 0, jvx = 0, jvy = 0;
+  for (int i = 0; i < Q; ++i) {
+    u += fw[i];
+    jvx += EX[i] * fw[Q + i];
+    jvy += EY[i] * fw[Q + i];
+  }
+  const double* fp = phi;
+  const double* fq = phi + Q;
+  double P = 0, Qv = 0, jpx = 0, jpy = 0;
+  for (int i = 0; i < Q; ++i) {
+    P += fp[i];
+    Qv += fq[i];
+    jpx += EX[i] * fp[i];
+    jpy += EY[i] * fp[i];
+  }
+  const double* Kv = ops.v.K;
+  const double* Ku = ops.u.K;
+  const double gvx = -(Kv[0] * jvx + Kv[1] * jvy) / (TAU * p.v.d * CS2);
+  const double gvy = -(Kv[2] * jvx + Kv[3] * jvy) / (TAU * p.v.d * CS2);
+  const double gpx = -(Ku[0] * jpx + Ku[1] * jpy) / (TAU * p.u.d * CS2);
+  const double gpy = -(Ku[2] * jpx + Ku[3] * jpy) / (TAU * p.u.d * CS2);
+  const double cgx = p.Cchi[0] * gvx + p.Cchi[1] * gvy;
+  const double cgy = p.Cchi[2] * gvx + p.Cchi[3] * gvy;
+  const double Phi_p = p.r_u * (1.0 - 2.0 * u) * P + p.a_uv * Qv + p.chi * (cgx * gpx + cgy * gpy);
+  const double Phi_q = -p.b_v * Qv;
+  // chi u C^T grad p, then K_v / tau
+  const double fx = p.chi * u * (p.Cchi[0] * gpx + p.Cchi[2] * gpy);
+  const double fy = p.chi * u * (p.Cchi[1] * gpx + p.Cchi[3] * gpy);
+  const double aqx = (Kv[0] * fx + Kv[1] * fy) / TAU;
+  const double aqy = (Kv[2] * fx + Kv[3] * fy) / TAU;
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesOps& so = s == 0 ? ops.u : ops.v;
+    const double* f = s == 0 ? fp : fq;
+    const double theta = s == 0 ? P : Qv;
+    const double Phi = s == 0 ? Phi_p : Phi_q;
+    double m[Q], meq[Q], mcol[Q], feq[Q];
+    for (int i = 0; i < Q; ++i) feq[i] = so.weq[i] * theta;
+    for (int r = 0; r < Q; ++r) {
+      m[r] = 0;
+      meq[r] = 0;
+      for (int i = 0; i < Q; ++i) {
+        m[r] += M0[r][i] * f[i];
+        meq[r] += M0[r][i] * feq[i];
+      }
     }
+    for (int r = 0; r < Q; ++r) {
+      double acc = 0;
+      for (int k = 0; k < Q; ++k) acc += so.Pi[r * Q + k] * (m[k] - meq[k]);
+      mcol[r] = m[r] - acc;
+    }
+    for (int i = 0; i < Q; ++i) {
+      double back = 0;
+      for (int r = 0; r < Q; ++r) back += ops.Minv[i * Q + r] * mcol[r];
+      double S = 0;
+      if (s == 1) S = WGT[i] * (EX[i] * aqx + EY[i] * aqy) / CS2;
+      out[s * Q + i] = back + TAU * S + TAU * WGT[i] * Phi;
+    }
+  }
 }
 
 // Jacobian of the local sources R = tau S + tau Phi of both species with
@@ -788,6 +872,52 @@ int orc_cost_gradient(const OrcProblem* p, int nsteps, const double* u0,
   for (size_t cell = 0; cell < nc; ++cell)
     grad[cell] = (p->solid && p->solid[cell]) ? 0.0 : grad[cell] + p->alpha * c[cell];
   if (uN_out) std::memcpy(uN_out, uN.data(), sizeof(double) * nc);
+  return 0;
+}
+
+// Continuous-adjoint gradient: the forward trajectory, then the system of
+// cadj_collide in reversed time from p = seed_u (equilibrium populations),
+// q = 0, with streaming and bounce-back as the forward; reversed step k
+// uses the forward state of step N-1-k.  g[cell] = tau sum_k q^k (the
+// pre-collision q of each reversed step), the time integral of q in the
+// gradient (DJRW) of a control entering Phi_v.
+int orc_cadjoint(const OrcProblem* p, int nsteps, const double* u0, const double* v0,
+                 const double* c, const double* seed_u, double* g) {
+  Ops ops;
+  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  const size_t nc = size_t(p->nx) * p->ny;
+  std::vector<double> f, traj;
+  run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
+  std::vector<double> d(2 * Q * nc, 0.0), post(2 * Q * nc), dnew(2 * Q * nc);
+  for (size_t cell = 0; cell < nc; ++cell) {
+    g[cell] = 0.0;
+    if (p->solid && p->solid[cell]) continue;
+    for (int i = 0; i < Q; ++i) d[(0 * Q + i) * nc + cell] = ops.u.weq[i] * seed_u[cell];
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    const double* fn = traj.data() + size_t(nsteps - 1 - k) * 2 * Q * nc;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const int cell = y * p->nx + x;
+        if (p->solid && p->solid[cell]) {
+          for (int q = 0; q < 2 * Q; ++q) post[q * nc + cell] = 0.0;
+          continue;
+        }
+        double fw[2 * Q], loc[2 * Q], out[2 * Q];
+        for (int q = 0; q < 2 * Q; ++q) {
+          fw[q] = fn[q * nc + cell];
+          loc[q] = d[q * nc + cell];
+        }
+        double qv = 0.0;
+        for (int i = 0; i < Q; ++i) qv += loc[Q + i];
+        g[cell] += TAU * qv;
+        cadj_collide(*p, ops, fw, loc, out);
+        for (int q = 0; q < 2 * Q; ++q) post[q * nc + cell] = out[q];
+      }
+    stream_push(*p, ops, post.data(), dnew.data());
+    d.swap(dnew);
+  }
   return 0;
 }
 

@@ -71,6 +71,7 @@ def lib():
                                             ctypes.c_double, dp, dp, dp]
         L.orc_cost_gradient.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp,
                                         dp, dp, dp, dp]
+        L.orc_cadjoint.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp]
         L.orc_gd_step.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
         L.orc_gd_step.restype = ctypes.c_double
@@ -252,6 +253,28 @@ def cost_gradient(p, nsteps=None, control=None, control_on_u=False):
                                    ctypes.byref(jr), _dp(uN)))
     return {"J": J.value, "J_track": jt.value, "J_reg": jr.value,
             "grad": grad, "uN": uN}
+
+
+def cadjoint(p, seed_u, nsteps=None, control=None):
+    """Continuous-adjoint part of the gradient: tau * sum over the reversed
+    steps of q (the adjoint of v), [ny, nx]."""
+    n = p.nsteps if nsteps is None else nsteps
+    pr = _Prob(p, False)
+    c = _f64(p.control if control is None else control)
+    g = np.zeros((p.ny, p.nx))
+    _check(lib().orc_cadjoint(pr.ptr, n, _dp(_f64(p.u0)), _dp(_f64(p.v0)), _dp(c),
+                              _dp(_f64(seed_u)), _dp(g)))
+    return g
+
+
+def cost_gradient_continuous(p, nsteps=None, control=None):
+    """J and the continuous-adjoint gradient tau sum q + alpha c (0 on solids)."""
+    c = p.control if control is None else control
+    fwd = forward(p, nsteps=nsteps, control=c)
+    f = p.fluid
+    seed = (fwd["uN"] - p.u_target) * f
+    g = cadjoint(p, seed, nsteps=nsteps, control=c)
+    return {"J": cost(p, fwd["uN"], control=c)[0], "grad": (g + p.alpha * c) * f}
 
 
 def gd_step(control, grad, zeta=0.0, lo=-np.inf, hi=np.inf):

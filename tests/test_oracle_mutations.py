@@ -43,6 +43,15 @@ MUTANTS = [
      "fnew[(s * Q + i) * nc + cell] = val;"),
     ("adjoint streaming without the wall reflection",
      ": lam[(s * Q + ops.opp[i]) * nc + cell];", ": lam[(s * Q + i) * nc + cell];"),
+    ("continuous adjoint: sign of the advection term",
+     "p.chi * (cgx * gpx + cgy * gpy);", "-p.chi * (cgx * gpx + cgy * gpy);"),
+    ("continuous adjoint: C instead of C^T in the cross-diffusion",
+     "const double fx = p.chi * u * (p.Cchi[0] * gpx + p.Cchi[2] * gpy);",
+     "const double fx = p.chi * u * (p.Cchi[0] * gpx + p.Cchi[1] * gpy);"),
+    ("continuous adjoint: dropped coupling a_uv q",
+     "p.r_u * (1.0 - 2.0 * u) * P + p.a_uv * Qv +", "p.r_u * (1.0 - 2.0 * u) * P +"),
+    ("continuous adjoint: forward state of the wrong step",
+     "traj.data() + size_t(nsteps - 1 - k) * 2 * Q * nc;", "traj.data() + size_t(k) * 2 * Q * nc;"),
     ("dropped half in the penalty",
      "jr += 0.5 * p->alpha * c[cell] * c[cell];", "jr += p->alpha * c[cell] * c[cell];"),
 ]
