@@ -285,6 +285,48 @@ def bench_lma(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_cadjoint(args):
+    """The continuous-adjoint gradient (Section 3.2.1) against the exact
+    discrete AMRT gradient on the 2048^2 masked problem (N = 4000, FP32,
+    store-all): time per gradient and the relative difference."""
+    import torch
+    import numpy as np
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd import inputs as I
+    from paper_1908_03876_amd.solver import DeviceProblem, GradientIteration
+    N = args.nsteps or 4000
+    prob = I.with_control_bump(I.masked_anisotropic(L=args.L, nsteps=N), amp=5.0,
+                               sigma=args.L / 8)
+    dp = DeviceProblem(prob, dtype=torch.float32)
+    it = GradientIteration(dp, ckpt_every=N)
+    out = {"metric": "continuous-adjoint vs discrete AMRT gradient",
+           "config": {"workload": f"masked anisotropic chemotaxis control, {args.L}x{args.L}, "
+                                  f"N={N}, FP32, store-all tape"}}
+    grads = {}
+    for name, fn in (("discrete", it.gradient), ("continuous", it.gradient_continuous)):
+        fn()
+        torch.cuda.synchronize()
+        abi.mrt_timing_reset()
+        abi.mrt_timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        abi.mrt_timing_enable(False)
+        kind = abi.TIMING_ADJOINT if name == "discrete" else abi.TIMING_CADJ
+        ms, n = abi.mrt_timing_read(kind)
+        grads[name] = dp.host(it.grad)
+        out[name] = {"s_per_gradient": round(dt, 4),
+                     "sweep_mlups": round(it.tape.n_fluid * n / (ms / 1e3) / 1e6, 1)}
+    f = prob.fluid
+    d, c = grads["discrete"][f], grads["continuous"][f]
+    out["rel_l2_difference"] = float(f"{np.linalg.norm(c - d) / np.linalg.norm(d):.4e}")
+    out["correlation"] = round(float(np.corrcoef(d, c)[0, 1]), 6)
+    it.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_surrogate(args):
     """Surrogate-assisted vs plain loop: MRT-generated training pairs on
     256^2 (N = 1000), crop training, then both loops on 256^2 and 1024^2
@@ -349,12 +391,14 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="steps of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--workload", default="masked",
-                    choices=["masked", "autograd", "batched", "surrogate", "lma"],
+                    choices=["masked", "autograd", "batched", "surrogate", "lma",
+                             "cadjoint"],
                     help="masked: the 2048^2 masked anisotropic workload (the "
                          "reported line); autograd: the same problem at N = 10000 "
                          "through torch.autograd with checkpoints; batched: 96 "
                          "uneven periodic instances; lma: heuristic vs LMA step "
-                         "sizes on the masked problem; "
+                         "sizes on the masked problem; cadjoint: continuous vs "
+                         "discrete adjoint gradient; "
                          "surrogate: CNN-assisted vs plain loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
@@ -374,6 +418,8 @@ def main():
         return bench_autograd(args)
     if args.workload == "lma":
         return bench_lma(args)
+    if args.workload == "cadjoint":
+        return bench_cadjoint(args)
     if args.nsteps is None:
         args.nsteps = 4000
     import torch

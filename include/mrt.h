@@ -207,6 +207,23 @@ int mrt_tlm(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
             const void* control, const void* dc, const void* du0,
             const void* dv0, void* duN, void* dvN, void* stream);
 
+/* Continuous-adjoint variant of the gradient (Section 3.2.1): the continuous
+ * adjoint system (FVM-PF-Adj-K) of the two-species problem, reversed in
+ * time s = T - t and solved by the same MRT scheme, with p (adjoint of u)
+ * and q (adjoint of v):
+ *   p_s = div(D_u grad p) + chi (Cchi grad v) . grad p + r_u (1 - 2u) p + a_uv q
+ *   q_s = div(D_v grad q) - b_v q - div(chi u Cchi^T grad p)
+ * from p = seed_u, q = 0, with the forward state of the last mrt_forward on
+ * this tape (re-recorded per segment when checkpointed) and bounce-back
+ * walls.  Writes grad_accum[ny][pitch] (double) = tau sum over the
+ * reversed steps of q (0 on solids); cost_gradient phase 2 then adds
+ * alpha * control, as after amrt_adjoint.  It approximates the exact
+ * discrete gradient of amrt_adjoint to the discretisation error.  Uses the
+ * tape's adjoint buffers.  Asynchronous. */
+int mrt_cadjoint(const mrt_problem* p, mrt_tape* t, const void* u0,
+                 const void* v0, const void* control, const void* seed_u,
+                 double* grad_accum, void* stream);
+
 /* out = sum over the fluid nodes of x * y, accumulated in double in a fixed
  * order (x, y: [ny][pitch] of the grid's dtype).  The inner product of
  * the line searches and conjugate-gradient rules of Section 2.4.
@@ -224,7 +241,7 @@ const char* mrt_last_error(void);
 
 /* Kernel timing with HIP events recorded on the caller's stream around the
  * step loops.  kind: 0 forward steps, 1 adjoint steps, 2 recompute steps,
- * 3 tangent-linear steps.
+ * 3 tangent-linear steps, 4 continuous-adjoint steps.
  * mrt_timing_read synchronises on the recorded events and returns the
  * summed milliseconds and the number of kernel launches since the last
  * reset. */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmrt.so")
 
 MRT_OK, MRT_EINVAL, MRT_ENOMEM, MRT_EHIP, MRT_ENONFINITE, MRT_ESTATE = 0, -1, -2, -3, -4, -5
 MRT_F32, MRT_F64 = 0, 1
-TIMING_FORWARD, TIMING_ADJOINT, TIMING_RECOMPUTE, TIMING_TLM = 0, 1, 2, 3
+TIMING_FORWARD, TIMING_ADJOINT, TIMING_RECOMPUTE, TIMING_TLM, TIMING_CADJ = 0, 1, 2, 3, 4
 
 
 class MrtError(RuntimeError):
@@ -71,6 +71,7 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
            "cost_gradient", "gd_step", "mrt_last_error", "mrt_timing_enable",
            "mrt_timing_reset", "mrt_timing_read", "mrt_tlm", "mrt_dot", "mrt_axpby",
+           "mrt_cadjoint",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
            "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
            "mrt_batch_tune", "mrt_batch_set_timeout", "mrt_batch_iteration",
@@ -105,6 +106,7 @@ def _load():
                           ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
     L.mrt_tlm.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.mrt_dot.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_cadjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     L.mrt_axpby.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
     L.mrt_last_error.restype = ctypes.c_char_p
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
@@ -238,6 +240,11 @@ def mrt_tlm(p, tape, u0, v0, control, dc=None, du0=None, dv0=None, duN=None, dvN
             stream=None) -> None:
     _check(lib.mrt_tlm(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control), _ptr(dc),
                        _ptr(du0), _ptr(dv0), _ptr(duN), _ptr(dvN), _stream(stream)))
+
+
+def mrt_cadjoint(p, tape, u0, v0, control, seed_u, grad_accum, stream=None) -> None:
+    _check(lib.mrt_cadjoint(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control),
+                            _ptr(seed_u), _ptr(grad_accum), _stream(stream)))
 
 
 def mrt_dot(p, tape, x, y, stream=None) -> float:

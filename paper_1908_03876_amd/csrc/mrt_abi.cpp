@@ -181,8 +181,8 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   std::vector<TimedSpan> pending;
-  double ms[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  int64_t launches[5] = {0, 0, 0, 0, 0};
 };
 
 Timing& timing() {
@@ -227,6 +227,44 @@ template <typename T>
 ModelCoef<T> model_coef(const mrt_problem* p) {
   return ::model_coef<T>(p);
 }
+template <typename T>
+CadjCoef<T> cadj_coef(const mrt_problem* p) {
+  // grad Theta = G_Theta j with G_Theta = -K_Theta / (tau d_Theta Cs^2)
+  double Ku[4], Kv[4], Gu[4], Gv[4];
+  k_block(p->u, Ku);
+  k_block(p->v, Kv);
+  for (int k = 0; k < 4; ++k) {
+    Gu[k] = -Ku[k] / (kTau * p->u.d * kCs2);
+    Gv[k] = -Kv[k] / (kTau * p->v.d * kCs2);
+  }
+  auto mul = [](const double* a, const double* b, double* c) {
+    c[0] = a[0] * b[0] + a[1] * b[2];
+    c[1] = a[0] * b[1] + a[1] * b[3];
+    c[2] = a[2] * b[0] + a[3] * b[2];
+    c[3] = a[2] * b[1] + a[3] * b[3];
+  };
+  const double chiC[4] = {p->chi * p->Cchi[0], p->chi * p->Cchi[1], p->chi * p->Cchi[2],
+                          p->chi * p->Cchi[3]};
+  const double GuT[4] = {Gu[0], Gu[2], Gu[1], Gu[3]};
+  const double chiCT[4] = {chiC[0], chiC[2], chiC[1], chiC[3]};
+  double t[4], M[4], Bq[4];
+  mul(GuT, chiC, t);  // M = G_u^T (chi C) G_v
+  mul(t, Gv, M);
+  mul(Kv, chiCT, t);  // Bq = K_v (chi C^T) G_u / tau
+  mul(t, Gu, Bq);
+  CadjCoef<T> c;
+  c.m00 = T(M[0]);
+  c.m01 = T(M[1]);
+  c.m10 = T(M[2]);
+  c.m11 = T(M[3]);
+  c.q00 = T(Bq[0] / kTau);
+  c.q01 = T(Bq[1] / kTau);
+  c.q10 = T(Bq[2] / kTau);
+  c.q11 = T(Bq[3] / kTau);
+  return c;
+}
+template CadjCoef<float> cadj_coef<float>(const mrt_problem*);
+template CadjCoef<double> cadj_coef<double>(const mrt_problem*);
 template ModelCoef<float> model_coef<float>(const mrt_problem*);
 template ModelCoef<double> model_coef<double>(const mrt_problem*);
 }  // namespace host
@@ -509,6 +547,49 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
   return last_launch_error();
 }
 
+// Continuous-adjoint sweep: reversed steps k = 0..N-1 use the forward
+// record of step N-1-k, so segments run in reverse as in the AMRT sweep.
+template <typename T>
+int cadjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
+                  const void* control, const void* seed_u, double* gacc, hipStream_t s) {
+  const mrt::ModelCoef<T> m = model_coef<T>(p);
+  const mrt::CadjCoef<T> cc = mrt::host::cadj_coef<T>(p);
+  const mrt::Geometry g = geometry(t);
+  const int N = t->nsteps, K = t->K;
+  const T* tu0 = static_cast<const T*>(u0);
+  const T* tv0 = static_cast<const T*>(v0);
+  const T* tc = static_cast<const T*>(control);
+  const T* src = nullptr;
+  for (int seg = t->nseg - 1; seg >= 0; --seg) {
+    const int n0 = seg * K, n1 = std::min(N, n0 + K);
+    if (t->rec_seg != seg) {
+      const T* cs = seg == 0 ? nullptr : static_cast<const T*>(t->ckpt[seg]);
+      const T* dummy = nullptr;
+      t->rec_seg = -1;
+      int rc = run_forward_steps<T>(t, m, g, n0, n1, cs, tu0, tv0, tc, true, false, 2, s,
+                                    &dummy);
+      if (rc) return rc;
+      t->rec_seg = seg;
+    }
+    SpanGuard span(4, s);
+    for (int n = n1 - 1; n >= n0; --n) {
+      mrt::CadjLaunch<T> a;
+      a.src = src;
+      a.dst = static_cast<T*>(t->abuf[n & 1]);
+      a.seed_u = static_cast<const T*>(seed_u);
+      a.rec = slot<T>(t, n - n0);
+      a.g = gacc;
+      a.first = n == N - 1;
+      mrt::launch_cadj_step<T>(g, m, cc, a, s);
+      span.count();
+      int rc = last_launch_error();
+      if (rc) return rc;
+      src = a.dst;
+    }
+  }
+  return MRT_OK;
+}
+
 int read_result(mrt_tape* t, hipStream_t s, int n) {
   HIP_TRY(hipMemcpyAsync(t->host, t->result, sizeof(double) * n,
                          hipMemcpyDeviceToHost, s));
@@ -768,6 +849,23 @@ int mrt_tlm(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
              : tlm_impl<float>(p, t, u0, v0, control, dc, du0, dv0, duN, dvN, s);
 }
 
+int mrt_cadjoint(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
+                 const void* control, const void* seed_u, double* grad_accum, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (t->mode == 0) return fail(MRT_ESTATE, "tape was created without a record");
+  if (!t->fwd_done) return fail(MRT_ESTATE, "no forward solve recorded on this tape");
+  if (u0 != t->f_u0 || v0 != t->f_v0 || control != t->f_ctrl)
+    return fail(MRT_ESTATE, "u0/v0/control differ from the recorded forward");
+  if (!seed_u || !grad_accum) return fail(MRT_EINVAL, "seed_u and grad_accum required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->grid.dtype == MRT_F64
+             ? cadjoint_impl<double>(p, t, u0, v0, control, seed_u, grad_accum, s)
+             : cadjoint_impl<float>(p, t, u0, v0, control, seed_u, grad_accum, s);
+}
+
 int mrt_dot(const mrt_problem* p, mrt_tape* t, const void* x, const void* y, double* out,
             void* stream) {
   int rc = validate(p);
@@ -829,7 +927,7 @@ int mrt_timing_reset(void) {
     (void)hipEventDestroy(sp.b);
   }
   t.pending.clear();
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     t.ms[k] = 0.0;
     t.launches[k] = 0;
   }
@@ -837,7 +935,7 @@ int mrt_timing_reset(void) {
 }
 
 int mrt_timing_read(int32_t kind, double* ms, int64_t* launches) {
-  if (kind < 0 || kind > 3) return fail(MRT_EINVAL, "kind must be 0, 1, 2 or 3");
+  if (kind < 0 || kind > 4) return fail(MRT_EINVAL, "kind must be 0..4");
   Timing& t = timing();
   std::lock_guard<std::mutex> lk(t.mu);
   for (auto& sp : t.pending) {

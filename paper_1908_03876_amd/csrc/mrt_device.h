@@ -365,6 +365,64 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
   store_state<T, MASKED>(g, n, fu, fv, dst, lm);
 }
 
+// Continuous-adjoint step (Section 3.2.1: the continuous adjoint system of
+// the two-species instance solved by the MRT scheme in reversed time) at a
+// node, from the gathered adjoint populations (fp of p, fq of q) and the
+// recorded forward u, j_v at this time:
+//   p_s = div(D_u grad p) + chi (C grad v).grad p + r_u (1 - 2u) p + a_uv q
+//   q_s = div(D_v grad q) - b_v q - div(chi u C^T grad p)
+// p relaxes like u and q like v; the advection and the couplings are
+// scalar sources, the cross-diffusion of q a flux source, as the
+// chemotaxis of u in the forward.  Accumulates g += tau q (pre-collision).
+template <typename T, bool MASKED, bool FIRST>
+__device__ __forceinline__ void cadj_collide_store(const Geometry& g, const NodeIdx& n,
+                                                   const ModelCoef<T>& m, const CadjCoef<T>& cc,
+                                                   T fp[9], T fq[9], const T* __restrict__ rec,
+                                                   T* __restrict__ dst, double* __restrict__ gacc,
+                                                   unsigned lm) {
+  const size_t idx = n.r0 + n.x;
+  const T u = __builtin_nontemporal_load(&rec[idx]);
+  const T jvx = __builtin_nontemporal_load(&rec[g.plane + idx]);
+  const T jvy = __builtin_nontemporal_load(&rec[2 * g.plane + idx]);
+  T P = T(0), Qv = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    P += fp[i];
+    Qv += fq[i];
+  }
+  const T jpx = fp[1] - fp[3] + fp[5] - fp[6] - fp[7] + fp[8];
+  const T jpy = fp[2] - fp[4] + fp[5] + fp[6] - fp[7] - fp[8];
+  const bool solid = MASKED && (lm & 1u);
+  if (!solid) {
+    if (FIRST)
+      gacc[idx] = double(Qv);
+    else
+      gacc[idx] += double(Qv);
+  }
+  const T adv = jpx * (cc.m00 * jvx + cc.m01 * jvy) + jpy * (cc.m10 * jvx + cc.m11 * jvy);
+  const T php = m.r_u * (T(1) - T(2) * u) * P + m.a_uv * Qv + adv;
+  const T phq = -m.b_v * Qv;
+  const T aqx = u * (cc.q00 * jpx + cc.q01 * jpy);
+  const T aqy = u * (cc.q10 * jpx + cc.q11 * jpy);
+  T t1, t2;
+  relax(fp, P, m.u, t1, t2);
+  relax(fq, Qv, m.v, t1, t2);
+  add_sources(fp, fq, php, T(0), T(0), phq);
+  // flux source of q: 3 w_i e_i . a_q
+  const T x3 = aqx * T(1.0 / 3.0), y3 = aqy * T(1.0 / 3.0);
+  const T x12 = aqx * T(1.0 / 12.0), y12 = aqy * T(1.0 / 12.0);
+  fq[1] += x3;
+  fq[2] += y3;
+  fq[3] -= x3;
+  fq[4] -= y3;
+  fq[5] += x12 + y12;
+  fq[6] += y12 - x12;
+  fq[7] -= x12 + y12;
+  fq[8] += x12 - y12;
+  if (solid) return;
+  store_state<T, MASKED>(g, n, fp, fq, dst, lm);
+}
+
 // One forward step (eq:LBE with S, PhiS, MF, MC) at node n.  Recording is a
 // run-time flag (rec != null), not a template parameter: the recorded and
 // the plain steps then run the same machine code, so a checkpointed

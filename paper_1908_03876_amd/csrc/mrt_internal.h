@@ -85,6 +85,29 @@ template <typename T>
 void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
                          const AdjLaunch<T>& a, hipStream_t s);
 
+// Coefficients of the continuous-adjoint system (p adjoint of u, q of v):
+// advection chi (C grad v) . grad p = j_p^T M j_v and the cross-diffusion
+// flux of q, a_q = u Bq j_p, with grad Theta = -K_Theta j / (tau d Cs^2).
+template <typename T>
+struct CadjCoef {
+  T m00, m01, m10, m11;
+  T q00, q01, q10, q11;
+};
+
+template <typename T>
+struct CadjLaunch {
+  const T* src;      // continuous-adjoint state of the previous reversed step, or null
+  T* dst;            // state after this reversed step (with wall slots)
+  const T* seed_u;   // p at s = 0 (first reversed step only)
+  const T* rec;      // record slot of the forward step at this time
+  double* g;         // time integral of q
+  int first;         // 1: first reversed step (initialises g)
+};
+
+template <typename T>
+void launch_cadj_step(const Geometry& g, const ModelCoef<T>& m, const CadjCoef<T>& cc,
+                      const CadjLaunch<T>& a, hipStream_t s);
+
 template <typename T>
 struct TlmLaunch {
   const T* src;      // perturbation of step n-1 (post-collision), or null (n = 0)
@@ -138,5 +161,7 @@ int validate(const mrt_problem* p);        // MRT_OK or MRT_EINVAL, sets the err
 int set_error(int code, const char* msg);  // records a message, returns code
 template <typename T>
 ModelCoef<T> model_coef(const mrt_problem* p);
+template <typename T>
+CadjCoef<T> cadj_coef(const mrt_problem* p);
 }  // namespace host
 }  // namespace mrt

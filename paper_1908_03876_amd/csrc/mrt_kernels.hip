@@ -143,6 +143,53 @@ __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
   tlm_collide_store<T, MASKED>(g, n, m, fu, fv, c, rec, dst, lm);
 }
 
+// Continuous-adjoint step: pulls the adjoint populations (or, for the first
+// reversed step, p = seed_u at equilibrium and q = 0), then
+// cadj_collide_store with the record of the forward step at this time.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+__global__ __launch_bounds__(kBlock) void cadj_step_kernel(
+    Geometry g, ModelCoef<T> m, CadjCoef<T> cc, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ seed_u, const T* __restrict__ rec, double* __restrict__ gacc) {
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = 0;
+  if (MASKED) {
+    if (FIRST) {
+      // the first step owns g on every node, solid ones included
+      lm = g.link[idx];
+      if (lm & 1u) {
+        gacc[idx] = 0.0;
+        return;
+      }
+    } else {
+      const unsigned flag = wave_flag(g, n);
+      if (flag == 2u) return;  // wavefront inside a solid region
+      lm = link_of(g, flag, idx);
+    }
+  }
+  T fp[9], fq[9];
+  if (FIRST) {
+    const T a = seed_u[idx];
+    fp[0] = m.u.w_rest * a;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) fp[i] = m.u.w_axis * a;
+#pragma unroll
+    for (int i = 5; i < 9; ++i) fp[i] = m.u.w_diag * a;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fq[i] = T(0);
+  } else {
+    const T* sq = src + 9 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const size_t o = pull_src<PERIODIC>(n, i, g.plane);
+      fp[i] = src[o];
+      fq[i] = sq[o];
+    }
+  }
+  cadj_collide_store<T, MASKED, FIRST>(g, n, m, cc, fp, fq, rec, dst, gacc, lm);
+}
+
 __device__ __forceinline__ bool is_fluid(const uint16_t* link, size_t idx) {
   return link == nullptr || !(link[idx] & 1u);
 }
@@ -408,6 +455,24 @@ void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T
 }
 
 template <typename T>
+void launch_cadj_step(const Geometry& g, const ModelCoef<T>& m, const CadjCoef<T>& cc,
+                      const CadjLaunch<T>& a, hipStream_t s) {
+  const int nb = stencil_blocks(g);
+#define MRT_CADJ(P, M, F)                                                       \
+  hipLaunchKernelGGL((cadj_step_kernel<T, P, M, F>), dim3(nb), dim3(kBlock), 0,  \
+                     s, g, m, cc, a.src, a.dst, a.seed_u, a.rec, a.g)
+#define MRT_CADJ_F(P, M) \
+  if (a.first) { MRT_CADJ(P, M, true); } else { MRT_CADJ(P, M, false); }
+  if (g.periodic) {
+    if (g.masked) { MRT_CADJ_F(true, true); } else { MRT_CADJ_F(true, false); }
+  } else {
+    if (g.masked) { MRT_CADJ_F(false, true); } else { MRT_CADJ_F(false, false); }
+  }
+#undef MRT_CADJ_F
+#undef MRT_CADJ
+}
+
+template <typename T>
 void launch_dot(const Geometry& g, const T* x, const T* y, double* partials, double* result,
                 hipStream_t s) {
   hipLaunchKernelGGL((dot_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0, s, g, x, y,
@@ -442,6 +507,9 @@ void launch_count_fluid(const Geometry& g, double* partials, double* result,
   template void launch_gd_step<T>(const Geometry&, T*, const T*, double,     \
                                   double, double, double*, double*,          \
                                   hipStream_t);                              \
+  template void launch_cadj_step<T>(const Geometry&, const ModelCoef<T>&,    \
+                                    const CadjCoef<T>&, const CadjLaunch<T>&, \
+                                    hipStream_t);                             \
   template void launch_tlm_step<T>(const Geometry&, const ModelCoef<T>&,     \
                                    const TlmLaunch<T>&, hipStream_t);        \
   template void launch_dot<T>(const Geometry&, const T*, const T*, double*,  \

@@ -196,6 +196,22 @@ class GradientIteration:
         r2["J"], r2["J_track"], r2["J_reg"] = r1["J"], r1["J_track"], r1["J_reg"]
         return r2
 
+    def gradient_continuous(self, control=None, stream=None) -> dict:
+        """As gradient(), with the continuous-adjoint sweep (Section 3.2.1)
+        in place of the AMRT: an approximation of the discrete gradient."""
+        dp = self.dp
+        c = dp.control if control is None else control
+        self.forward(c, stream)
+        r1 = abi.cost_gradient(dp.struct, self.tape.handle, self.uN,
+                               dp.u_target, c, None, self.seed, None, stream)
+        abi.mrt_cadjoint(dp.struct, self.tape.handle, dp.u0, dp.v0, c, self.seed,
+                         self.gacc, stream)
+        r2 = abi.cost_gradient(dp.struct, self.tape.handle, self.uN,
+                               dp.u_target, c, self.gacc, None, self.grad,
+                               stream)
+        r2["J"], r2["J_track"], r2["J_reg"] = r1["J"], r1["J_track"], r1["J_reg"]
+        return r2
+
     def step(self, zeta: float = 0.0, lo: float = -math.inf,
              hi: float = math.inf, stream=None, want_zeta: bool = True) -> dict:
         """One iteration of the gradient algorithm on dp.control (in place)."""
