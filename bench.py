@@ -4,7 +4,7 @@ one MI355X.
 Workload (masked anisotropic chemotaxis at scale, FP32): 2048 x 2048 lattice
 with a bounce-back mask of 200 random disks (radius 5-30) plus a solid outer
 ring, full anisotropic self and chemotactic tensors, N = 4000 time steps per
-solve.  One timed step = one gradient iteration of Section 3.2: forward MRT
+solve.  One timed step = one gradient iteration of Section 3.2.1: forward MRT
 solve recording the adjoint tape, cost and adjoint seed, AMRT reverse sweep,
 gradient and norms, gradient step on the control.  Inputs are seeded and
 resident in HBM before timing starts.
@@ -286,7 +286,7 @@ def bench_lma(args):
 
 
 def bench_cadjoint(args):
-    """The continuous-adjoint gradient (Section 3.2.1) against the exact
+    """The continuous-adjoint gradient (Section 3.2.2) against the exact
     discrete AMRT gradient on the 2048^2 masked problem (N = 4000, FP32,
     store-all): time per gradient and the relative difference."""
     import torch

@@ -207,7 +207,7 @@ int mrt_tlm(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
             const void* control, const void* dc, const void* du0,
             const void* dv0, void* duN, void* dvN, void* stream);
 
-/* Continuous-adjoint variant of the gradient (Section 3.2.1): the continuous
+/* Continuous-adjoint variant of the gradient (Section 3.2.2): the continuous
  * adjoint system (FVM-PF-Adj-K) of the two-species problem, reversed in
  * time s = T - t and solved by the same MRT scheme, with p (adjoint of u)
  * and q (adjoint of v):
@@ -254,7 +254,7 @@ int mrt_timing_read(int32_t kind, double* ms /* host */,
 /* ------------------------------------------------------------------------
  * Batched form: many independent control problems of uneven size advanced
  * together.  Each gradient iteration (forward, cost and seed, AMRT sweep,
- * gradient and norms, gradient step, for every instance; Section 3.2's
+ * gradient and norms, gradient step, for every instance; Section 3.2.1's
  * discrete optimisation loop) runs the forward pass and the adjoint pass as
  * one persistent launch each, with a grid barrier between time steps, and
  * can be captured once in a HIP graph and replayed.  Problems must be

@@ -370,7 +370,7 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
 
 // Collision of the continuous-adjoint system (FVM-PF-Adj-K for the
 // two-species instance) solved by the same MRT scheme in reversed time
-// s = T - t (Section 3.2.1).  With p the adjoint of u and q that of v:
+// s = T - t (Section 3.2.2).  With p the adjoint of u and q that of v:
 //   p_s = div(D_u grad p) + chi (C grad v) . grad p + r_u (1 - 2u) p + a_uv q
 //   q_s = div(D_v grad q) - b_v q - div(chi u C^T grad p)
 // p relaxes like u (K_u, weq_u) and q like v.  The gradients come from the

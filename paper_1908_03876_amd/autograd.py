@@ -1,5 +1,5 @@
 """The MRT solve as a differentiable torch operation whose backward is the
-AMRT sweep (Section 3.2: the discrete adjoint gives the exact gradient of
+AMRT sweep (Section 3.2.1: the discrete adjoint gives the exact gradient of
 any functional of the final state; Theorem 3, gradientLattice).
 
     solver = MRTSolve(problem, ckpt_every=100)

@@ -1,5 +1,5 @@
 """Batched form: many independent control problems of uneven size, one
-gradient iteration for all of them per call (Section 3.2's optimisation
+gradient iteration for all of them per call (Section 3.2.1's optimisation
 loop, instance by instance), with the forward and adjoint passes as single
 persistent launches, the iteration captured in a HIP graph and the launch
 shape chosen by the library's autotuner.  This module only marshals data in

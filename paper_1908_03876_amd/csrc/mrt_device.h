@@ -4,7 +4,7 @@
 //
 // Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
 // BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
-// Section 3.2 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
+// Section 3.2.1 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -365,7 +365,7 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
   store_state<T, MASKED>(g, n, fu, fv, dst, lm);
 }
 
-// Continuous-adjoint step (Section 3.2.1: the continuous adjoint system of
+// Continuous-adjoint step (Section 3.2.2: the continuous adjoint system of
 // the two-species instance solved by the MRT scheme in reversed time) at a
 // node, from the gathered adjoint populations (fp of p, fq of q) and the
 // recorded forward u, j_v at this time:

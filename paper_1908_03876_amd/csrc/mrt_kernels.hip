@@ -3,7 +3,7 @@
 //
 // Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
 // BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
-// Section 3.2 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
+// Section 3.2.1 (LIBEG, CAE, AEDs, RFS1, CAEL, gradientLattice).
 //
 // Design (memory-bound stencil, no MFMA):
 //  * One thread per lattice node, 256-thread blocks along x; every

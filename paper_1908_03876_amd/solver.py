@@ -1,5 +1,5 @@
 """Device-resident problems, tapes and the gradient-descent loop on top of
-the C-ABI (Section 3.2, discrete optimisation algorithm: forward N steps,
+the C-ABI (Section 3.2.1, discrete optimisation algorithm: forward N steps,
 adjoint N..0, gradient, update, repeat).
 
 Fields live in HBM as [ny, pitch] torch tensors (pitch = nx rounded up to 64
@@ -155,7 +155,7 @@ def choose_ckpt_every(dp: DeviceProblem, budget_bytes: int) -> int:
 
 
 class GradientIteration:
-    """One discrete gradient of J(c) and the update (Section 3.2):
+    """One discrete gradient of J(c) and the update (Section 3.2.1):
     forward -> cost & seed -> AMRT adjoint -> gradient & norms -> gd_step."""
 
     def __init__(self, dp: DeviceProblem, ckpt_every: int = -1,
@@ -197,7 +197,7 @@ class GradientIteration:
         return r2
 
     def gradient_continuous(self, control=None, stream=None) -> dict:
-        """As gradient(), with the continuous-adjoint sweep (Section 3.2.1)
+        """As gradient(), with the continuous-adjoint sweep (Section 3.2.2)
         in place of the AMRT: an approximation of the discrete gradient."""
         dp = self.dp
         c = dp.control if control is None else control

@@ -1,6 +1,6 @@
 """Learned form: a convolutional surrogate of the control-to-state map,
 trained on pairs the MRT solver itself generates, proposing warm starts and
-line-search steps to the adjoint-based gradient loop (Section 3.2), while
+line-search steps to the adjoint-based gradient loop (Section 3.2.1), while
 every accepted step is verified by a true MRT solve.
 
 The paper's conclusion suggests pairing the method with a reduced-order

@@ -1,6 +1,6 @@
 """Batched form: uneven-size instances advanced by persistent launches,
 graph-captured iterations and autotuned launch shapes, each instance checked
-against the oracle's gradient iteration (Section 3.2)."""
+against the oracle's gradient iteration (Section 3.2.1)."""
 import numpy as np
 import pytest
 

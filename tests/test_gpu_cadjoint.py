@@ -1,4 +1,4 @@
-"""Continuous-adjoint gradient on the device (Section 3.2.1: the continuous
+"""Continuous-adjoint gradient on the device (Section 3.2.2: the continuous
 adjoint system solved by the MRT scheme in reversed time) against the FP64
 oracle's implementation of the same scheme, and its relation to the exact
 discrete (AMRT) gradient at full size."""

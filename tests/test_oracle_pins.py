@@ -485,7 +485,7 @@ def _smooth_problem(L, N0=40):
 
 
 def test_continuous_adjoint_converges_to_discrete_gradient():
-    """Section 3.2.1: the continuous adjoint system solved by the MRT scheme
+    """Section 3.2.2: the continuous adjoint system solved by the MRT scheme
     in reversed time gives a gradient that differs from the exact discrete
     (AMRT) gradient by the discretisation error: second order under
     diffusive scaling (the difference drops 4x per halving of h)."""
