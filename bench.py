@@ -327,6 +327,61 @@ def bench_cadjoint(args):
     print(json.dumps(out), flush=True)
 
 
+# FLOP per pixel of the surrogate: the two 32 -> 32 layers (2 * 9 * 32 * 32
+# each, on the matrix cores) and the one-channel first and last layers
+# (2 * 9 * 32 each, vector ALU)
+SRG_C32_FLOP = 2 * 9 * 32 * 32
+SRG_THIN_FLOP = 2 * 9 * 32
+
+
+def bench_srg_kernels(args):
+    """Throughput of the surrogate's kernels in its two uses: training steps
+    on 64 crops of 64 x 64 (forward, backward with weight gradients, Adam)
+    and candidate scoring on 17 fields of 1024 x 1024 (forward only)."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.surrogate import Surrogate
+    dev = torch.device("cuda:0")
+    srg = Surrogate(17, 1024, 1024, seed=0)
+    g = torch.Generator(device=dev).manual_seed(0)
+    out = {"metric": "surrogate network throughput (BF16 MFMA, FP32 accumulation)"}
+    # scoring: forward of 17 fields of 1024^2
+    x = torch.randn((17, 1024, 1024), generator=g, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        abi.mrt_srg_forward(srg.handle, x, y, 17, 1024, 1024)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = max(args.steps, 1)
+    for _ in range(reps):
+        abi.mrt_srg_forward(srg.handle, x, y, 17, 1024, 1024)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pix = 17 * 1024 * 1024
+    flop = pix * (2 * SRG_C32_FLOP + 2 * SRG_THIN_FLOP)
+    out["forward_17x1024x1024"] = {"ms": round(ms, 3), "TFLOP_s": round(flop / ms / 1e9, 1)}
+    # training steps: 64 crops of 64 x 64
+    xb = torch.randn((64, 64, 64), generator=g, device=dev)
+    tb = 0.01 * torch.randn((64, 64, 64), generator=g, device=dev)
+    for _ in range(3):
+        abi.mrt_srg_train_step(srg.handle, xb, tb, 64, 64, 64, 4, 1e-4)
+    e0.record()
+    reps_t = 50 * reps
+    for _ in range(reps_t):
+        abi.mrt_srg_train_step(srg.handle, xb, tb, 64, 64, 64, 4, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_t = e0.elapsed_time(e1) / reps_t
+    pix_t = 64 * 64 * 64
+    # forward + backward data + weight gradients
+    flop_t = pix_t * 3 * (2 * SRG_C32_FLOP + 2 * SRG_THIN_FLOP)
+    out["train_step_64x64x64"] = {"ms": round(ms_t, 3), "TFLOP_s": round(flop_t / ms_t / 1e9, 1)}
+    out["peak_bf16_dense_TFLOP_s"] = 2500.0
+    srg.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_surrogate(args):
     """Surrogate-assisted vs plain loop: MRT-generated training pairs on
     256^2 (N = 1000), crop training, then both loops on 256^2 and 1024^2
@@ -392,13 +447,14 @@ def main():
                     help="steps of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--workload", default="masked",
                     choices=["masked", "autograd", "batched", "surrogate", "lma",
-                             "cadjoint"],
+                             "cadjoint", "srg-kernels"],
                     help="masked: the 2048^2 masked anisotropic workload (the "
                          "reported line); autograd: the same problem at N = 10000 "
                          "through torch.autograd with checkpoints; batched: 96 "
                          "uneven periodic instances; lma: heuristic vs LMA step "
                          "sizes on the masked problem; cadjoint: continuous vs "
-                         "discrete adjoint gradient; "
+                         "discrete adjoint gradient; srg-kernels: surrogate "
+                         "network throughput; "
                          "surrogate: CNN-assisted vs plain loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
@@ -420,6 +476,8 @@ def main():
         return bench_lma(args)
     if args.workload == "cadjoint":
         return bench_cadjoint(args)
+    if args.workload == "srg-kernels":
+        return bench_srg_kernels(args)
     if args.nsteps is None:
         args.nsteps = 4000
     import torch

@@ -204,7 +204,7 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
   const size_t hwb = size_t(max_batch) * max_h * max_w;
   for (int i = 0; i < 3 && !rc; ++i) rc = alloc(hwb * kC * 2, (void**)&s->act[i]);
   for (int i = 0; i < 2 && !rc; ++i) rc = alloc(hwb * kC * 2, (void**)&s->g[i]);
-  if (!rc) rc = alloc(size_t(mrt::kSrgWBlocks) * 4 * mrt::kSrgWPart * 4, (void**)&s->wpart);
+  if (!rc) rc = alloc(size_t(mrt::kSrgWBlocks) * mrt::kSrgWPart * 4, (void**)&s->wpart);
   if (!rc) rc = alloc(mrt::kSrgThinPartDoubles * 8, (void**)&s->tpart);
   if (!rc) rc = alloc(hwb * 4, (void**)&s->dout);
   if (!rc) rc = alloc(hwb * 4, (void**)&s->xbuf);

@@ -10,9 +10,9 @@
 namespace mrt {
 
 // Sizes of the reduction scratch of the weight gradients.
-constexpr int kSrgWPart = 32 * 32 * 9 + 32;  // one wavefront partial: dW, db
+constexpr int kSrgWPart = 32 * 32 * 9 + 32;  // one block partial: dW, db
 constexpr int kSrgWBlocks = 256;             // max blocks of the MFMA weight gradient
-constexpr int kSrgThinBlocks = 256;          // max blocks per tap of the thin ones
+constexpr int kSrgThinBlocks = 1024;         // max blocks of the thin ones
 constexpr size_t kSrgThinPartDoubles = size_t(11) * kSrgThinBlocks * 32 + kSrgThinBlocks;
 
 // Hidden activations and gradients are BF16 channels-last [B][H][W][32].
@@ -35,7 +35,7 @@ void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, 
                         int B, int H, int W, hipStream_t s);
 void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
                              uint16_t* dzprev, int B, int H, int W, hipStream_t s);
-// part: kSrgWBlocks * 4 * kSrgWPart floats
+// part: kSrgWBlocks * kSrgWPart floats
 void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* part, float* dw,
                                float* db, int B, int H, int W, hipStream_t s);
 void launch_mse(const float* pred, const float* t, float* dpred, double* partials,

@@ -63,6 +63,19 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
 __device__ __forceinline__ float lo16(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float hi16(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double part[kB / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kB / 64; ++i) r += part[i];
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
 // ------------------------------------------------ first layer (1 -> 32)
 
 // One thread per pixel: a0 = bf16(tanh(b + W0 * (s_in x))), 32 channels.
@@ -206,86 +219,100 @@ __global__ __launch_bounds__(kB) void l3_bwd_data_kernel(const float* __restrict
 }
 
 // Weight gradients of a one-channel layer from a 32-channel field F and a
-// one-channel field S:  out[c][t] = sum_p F[p][c] S[p + sgn off(t)], with
-// block (blockIdx.x, t = blockIdx.y) partials [9][nblk][32], and for t = 0
-// also the channel sums sum_p F[p][c] ([nblk][32]) and sum_p S[p] ([nblk]).
+// one-channel field S:  out[c][t] = sum_p F[p][c] S[p + sgn off(t)], all nine
+// taps in one pass over F.  Lane = (pixel pp = lane / 8 of the wavefront's 8
+// pixels, channel quad cq = lane % 8); each lane keeps 9 x 4 products, the 4
+// channel sums and (cq = 0) the sum of S.  Block partials: [9][nblk][32]
+// products, [nblk][32] channel sums of F (slot 9), [nblk] sums of S.
 __global__ __launch_bounds__(kB) void thin_wgrad_kernel(const uint16_t* __restrict__ F,
                                                         const float* __restrict__ S, int sgn,
                                                         double* __restrict__ part, int B, int H,
                                                         int W) {
-  const int t = blockIdx.y, nblk = gridDim.x;
-  const int dy = sgn * (t / 3 - 1), dx = sgn * (t % 3 - 1);
+  const int nblk = gridDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pp = lane >> 3, cq = lane & 7;
   const size_t hw = size_t(H) * W, n = size_t(B) * hw;
-  float acc[kC], fs[kC];
+  float acc[9][4], fs[4] = {0.f, 0.f, 0.f, 0.f}, ss = 0.f;
 #pragma unroll
-  for (int c = 0; c < kC; ++c) acc[c] = fs[c] = 0.f;
-  float ss = 0.f;
-  for (size_t p = size_t(blockIdx.x) * kB + threadIdx.x; p < n; p += size_t(nblk) * kB) {
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[t][j] = 0.f;
+  for (size_t p = (size_t(blockIdx.x) * kWaves + wv) * 8 + pp; p < n;
+       p += size_t(nblk) * kWaves * 8) {
     const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
-    const float sv = S[size_t(b) * hw + size_t(wrap(py + dy, H)) * W + wrap(px + dx, W)];
-    const u32x4* fp = reinterpret_cast<const u32x4*>(F + p * kC);
+    const u32x2 q = *reinterpret_cast<const u32x2*>(F + p * kC + 4 * cq);
+    const float f[4] = {lo16(q[0]), hi16(q[0]), lo16(q[1]), hi16(q[1])};
+    const float* Sb = S + size_t(b) * hw;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const u32x4 q = fp[k];
+    for (int t = 0; t < 9; ++t) {
+      const float sv = Sb[size_t(wrap(py + sgn * (t / 3 - 1), H)) * W + wrap(px + sgn * (t % 3 - 1), W)];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 8 * k + 2 * e;
-        const float f0 = lo16(q[e]), f1 = hi16(q[e]);
-        acc[c] += f0 * sv;
-        acc[c + 1] += f1 * sv;
-        fs[c] += f0;
-        fs[c + 1] += f1;
-      }
+      for (int j = 0; j < 4; ++j) acc[t][j] += f[j] * sv;
+      if (t == 4 && cq == 0) ss += sv;
     }
-    ss += S[p];
-  }
-  __shared__ double red[kWaves][2 * kC + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int c = 0; c < 2 * kC + 1; ++c) {
-    double v = c < kC ? double(acc[c]) : (c < 2 * kC ? double(fs[c - kC]) : double(ss));
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][c] = v;
+    for (int j = 0; j < 4; ++j) fs[j] += f[j];
+  }
+  // lanes of one channel quad: xor 8, 16, 32; then the waves in LDS
+  constexpr int kV = 9 * 4 + 4 + 1;
+  __shared__ float red[kWaves][8][kV];
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    float v = k < 36 ? acc[k / 4][k % 4] : (k < 40 ? fs[k - 36] : ss);
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (pp == 0) red[wv][cq][k] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 2 * kC + 1) {
-    const int c = threadIdx.x;
+  // 9 x 32 products, 32 channel sums, 1 sum of S
+  for (int i = threadIdx.x; i < 9 * kC + kC + 1; i += kB) {
     double v = 0.0;
-    for (int k = 0; k < kWaves; ++k) v += red[k][c];
-    if (c < kC)
+    if (i < 9 * kC) {
+      const int t = i / kC, c = i % kC;
+      for (int k = 0; k < kWaves; ++k) v += double(red[k][c / 4][t * 4 + c % 4]);
       part[(size_t(t) * nblk + blockIdx.x) * kC + c] = v;
-    else if (t == 0 && c < 2 * kC)
-      part[(size_t(9) * nblk + blockIdx.x) * kC + (c - kC)] = v;
-    else if (t == 0)
+    } else if (i < 10 * kC) {
+      const int c = i - 9 * kC;
+      for (int k = 0; k < kWaves; ++k) v += double(red[k][c / 4][36 + c % 4]);
+      part[(size_t(9) * nblk + blockIdx.x) * kC + c] = v;
+    } else {
+      for (int k = 0; k < kWaves; ++k) v += double(red[k][0][40]);
       part[size_t(10) * nblk * kC + blockIdx.x] = v;
+    }
   }
 }
 
-// Finish of thin_wgrad: dw[c][t] = scale * sum_blk part[t][blk][c] (layout
-// of the masters, [Cout][Cin][9] with one of them 1); bias gradients either
-// per channel (db[c] = bscale * sum of F) or one value (db[0] = bscale *
-// sum of S).
+// Finish of thin_wgrad, one block per output: dw[c * 9 + t] = scale *
+// sum_blk part[t][blk][c] (master layout [Cout][Cin][9] with one of them 1),
+// then either 32 per-channel bias gradients (bscale * sum of F) or one
+// (bscale * sum of S).  Fixed summation order.
 __global__ __launch_bounds__(kB) void thin_wgrad_finish_kernel(const double* __restrict__ part,
                                                                int nblk, float scale,
                                                                float bscale, int bias_per_channel,
                                                                float* __restrict__ dw,
                                                                float* __restrict__ db) {
-  for (int i = threadIdx.x; i < kC * 9; i += kB) {
-    const int c = i / 9, t = i % 9;
-    double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t(t) * nblk + k) * kC + c];
-    dw[i] = float(scale * s);
+  const int o = blockIdx.x;
+  const double* src;
+  size_t stride;
+  if (o < 9 * kC) {
+    const int c = o / 9, t = o % 9;
+    src = part + size_t(t) * nblk * kC + c;
+    stride = kC;
+  } else if (bias_per_channel) {
+    src = part + size_t(9) * nblk * kC + (o - 9 * kC);
+    stride = kC;
+  } else {
+    src = part + size_t(10) * nblk * kC;
+    stride = 1;
   }
-  const int i = threadIdx.x;
-  if (bias_per_channel && i < kC) {
-    double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t(9) * nblk + k) * kC + i];
-    db[i] = float(bscale * s);
-  }
-  if (!bias_per_channel && i == 0) {
-    double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[size_t(10) * nblk * kC + k];
-    db[0] = float(bscale * s);
+  double v = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kB) v += src[size_t(k) * stride];
+  v = block_sum_d(v);
+  if (threadIdx.x == 0) {
+    if (o < 9 * kC)
+      dw[o] = float(scale * v);
+    else
+      db[o - 9 * kC] = float(bscale * v);
   }
 }
 
@@ -412,8 +439,9 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
 // Weight gradients of a hidden layer on the matrix cores:
 //   dW[co][ci][t] = sum_p dz[p][co] a[p + off(t)][ci],  db[co] = sum_p dz[p][co]
 // over chunks of 32 pixels of a row (the MFMA K dimension); each wavefront
-// accumulates all 9 x 2 x 2 output fragments over its chunks and writes
-// one partial [kSrgWPart] (weights in master layout, then biases).
+// accumulates all 9 x 2 x 2 output fragments over its chunks, the block's
+// wavefronts are summed in LDS in a fixed order, and the block writes one
+// partial [kSrgWPart] (weights in master layout, then biases).
 __global__ __launch_bounds__(kB) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
                                                             const uint16_t* __restrict__ a,
                                                             float* __restrict__ part, int B,
@@ -467,39 +495,71 @@ __global__ __launch_bounds__(kB) void c32_bwd_weight_kernel(const uint16_t* __re
               __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf[nb], acc[t][mb][nb], 0, 0, 0);
     }
   }
-  float* P = part + size_t(wid) * kSrgWPart;
-#pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int co = 16 * mb + 4 * q + j, ci = 16 * nb + c16;
-          P[(co * kC + ci) * 9 + t] = acc[t][mb][nb][j];
-        }
+  __shared__ float red[kSrgWPart];
+  const int wv = threadIdx.x >> 6;
+  float db2[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
-    float s = dbs[mb];
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    if (q == 0) P[kC * kC * 9 + 16 * mb + c16] = s;
+    float v = dbs[mb];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    db2[mb] = v;
   }
+  for (int k = 0; k < kWaves; ++k) {
+    if (wv == k) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int co = 16 * mb + 4 * q + j, ci = 16 * nb + c16;
+              float& r = red[(co * kC + ci) * 9 + t];
+              r = k == 0 ? acc[t][mb][nb][j] : r + acc[t][mb][nb][j];
+            }
+      if (q == 0)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          float& r = red[kC * kC * 9 + 16 * mb + c16];
+          r = k == 0 ? db2[mb] : r + db2[mb];
+        }
+    }
+    __syncthreads();
+  }
+  float* P = part + size_t(blockIdx.x) * kSrgWPart;
+  for (int i = threadIdx.x; i < kSrgWPart; i += kB) P[i] = red[i];
 }
 
-// dw[i] = sum over the nw wavefront partials (fixed order), i < kSrgWPart.
-__global__ __launch_bounds__(kB) void wpart_sum_kernel(const float* __restrict__ part, int nw,
+// dw[i] = sum over the np block partials, i < kSrgWPart: 64 outputs per
+// block, four slices of the partials per output (each in a fixed order),
+// combined in a fixed order.
+__global__ __launch_bounds__(kB) void wpart_sum_kernel(const float* __restrict__ part, int np,
                                                        float* __restrict__ dw,
                                                        float* __restrict__ db) {
-  const int i = blockIdx.x * kB + threadIdx.x;
-  if (i >= kSrgWPart) return;
-  double s = 0.0;
-  for (int k = 0; k < nw; ++k) s += part[size_t(k) * kSrgWPart + i];
-  if (i < kC * kC * 9)
-    dw[i] = float(s);
-  else
-    db[i - kC * kC * 9] = float(s);
+  const int o = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + o;
+  __shared__ double red[kWaves][64];
+  double s0 = 0.0, s1 = 0.0;
+  if (i < kSrgWPart) {
+    int k = sl;
+    for (; k + kWaves < np; k += 2 * kWaves) {
+      s0 += part[size_t(k) * kSrgWPart + i];
+      s1 += part[size_t(k + kWaves) * kSrgWPart + i];
+    }
+    if (k < np) s0 += part[size_t(k) * kSrgWPart + i];
+  }
+  red[sl][o] = s0 + s1;
+  __syncthreads();
+  if (sl == 0 && i < kSrgWPart) {
+    double s = 0.0;
+    for (int k = 0; k < kWaves; ++k) s += red[k][o];
+    if (i < kC * kC * 9)
+      dw[i] = float(s);
+    else
+      db[i - kC * kC * 9] = float(s);
+  }
 }
 
 __device__ __forceinline__ float block_sum(float v) {
@@ -598,19 +658,6 @@ __global__ __launch_bounds__(kB) void gather_crops_kernel(
   out[p] = v;
 }
 
-__device__ __forceinline__ double block_sum_d(double v) {
-  __shared__ double part[kB / 64];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kB / 64; ++i) r += part[i];
-  __syncthreads();
-  return r;  // valid in thread 0
-}
-
 // Surrogate cost of B candidate controls x_b (one field each):
 //   r_b = u_base + y_b - u_target   (written over y, same index)
 //   J_b = 1/2 sum r_b^2 + alpha/2 sum x_b^2
@@ -705,10 +752,12 @@ void launch_srg_l3_bwd_data(const float* dy, const uint16_t* w, const uint16_t* 
 void launch_srg_thin_wgrad(const uint16_t* F, const float* S, int sgn, double* part, int B,
                            int H, int W, float scale, float bscale, int bias_per_channel,
                            float* dw, float* db, hipStream_t s) {
-  int nblk = blocks_for_pixels(B, H, W);
-  if (nblk > kSrgThinBlocks) nblk = kSrgThinBlocks;
-  hipLaunchKernelGGL(thin_wgrad_kernel, dim3(nblk, 9), dim3(kB), 0, s, F, S, sgn, part, B, H, W);
-  hipLaunchKernelGGL(thin_wgrad_finish_kernel, dim3(1), dim3(kB), 0, s, part, nblk, scale,
+  const size_t n = size_t(B) * H * W;
+  size_t want = (n + kWaves * 8 - 1) / (kWaves * 8);
+  const int nblk = int(want < size_t(kSrgThinBlocks) ? want : size_t(kSrgThinBlocks));
+  hipLaunchKernelGGL(thin_wgrad_kernel, dim3(nblk), dim3(kB), 0, s, F, S, sgn, part, B, H, W);
+  const int nout = 9 * kC + (bias_per_channel ? kC : 1);
+  hipLaunchKernelGGL(thin_wgrad_finish_kernel, dim3(nout), dim3(kB), 0, s, part, nblk, scale,
                      bscale, bias_per_channel, dw, db);
 }
 
@@ -737,8 +786,8 @@ void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* par
   int nb = (nchunks + kWaves - 1) / kWaves;
   if (nb > kSrgWBlocks) nb = kSrgWBlocks;
   hipLaunchKernelGGL(c32_bwd_weight_kernel, dim3(nb), dim3(kB), 0, s, dz, a, part, B, H, W);
-  hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + kB - 1) / kB), dim3(kB), 0, s, part,
-                     nb * kWaves, dw, db);
+  hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + 63) / 64), dim3(kB), 0, s, part, nb,
+                     dw, db);
 }
 
 void launch_mse(const float* pred, const float* t, float* dpred, double* partials,
