@@ -139,20 +139,11 @@ __device__ __forceinline__ TileNode<T> tile_of(const BatchArgs<T>& a, int t) {
 template <typename T, bool FIRST>
 __device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     T* rec) {
-#ifdef MRT_CONTIG
-  const int per = (a.ntiles + gridDim.x - 1) / gridDim.x;
-  const int t0 = blockIdx.x * per, t1 = min(a.ntiles, t0 + per);
-  for (int t = t0; t < t1; t += 2) {
-    const TileNode<T> A = tile_of(a, t);
-    const bool hasB = t + 1 < t1;
-    const TileNode<T> B = tile_of(a, hasB ? t + 1 : t);
-#else
   const int nb = gridDim.x;
   for (int t = blockIdx.x; t < a.ntiles; t += 2 * nb) {
     const TileNode<T> A = tile_of(a, t);
     const bool hasB = t + nb < a.ntiles;
     const TileNode<T> B = tile_of(a, hasB ? t + nb : t);
-#endif
     T fa[9], ga[9], ca = T(0), fb[9], gb[9], cb = T(0);
     if (A.ok)
       forward_gather<T, true, FIRST>(A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,

@@ -162,6 +162,8 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
   *out = nullptr;
   if (channels != kC) return err(MRT_EINVAL, "the surrogate has 32 hidden channels");
   if (max_batch < 1 || max_h < 3 || max_w < 3) return err(MRT_EINVAL, "invalid sizes");
+  if (size_t(max_batch) * size_t(max_h) * size_t(max_w) > (size_t(1) << 28))
+    return err(MRT_EINVAL, "at most 2^28 pixels (batch x height x width)");
   if (!(std::isfinite(in_scale) && std::isfinite(out_scale)))
     return err(MRT_EINVAL, "non-finite scales");
   mrt_srg* s = new mrt_srg();

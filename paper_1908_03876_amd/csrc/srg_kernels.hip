@@ -48,6 +48,29 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 
+// Two floats rounded to nearest even and packed (low half = a): the
+// hardware conversion.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = {__bf16(a), __bf16(b)};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// Hyperbolic tangent in a few instructions: tanh x = s (1 - 2 / (e^{2|x|} + 1))
+// with s = sign x, from the hardware base-2 exponential and reciprocal; for
+// |x| < 1/16, where that form cancels, the odd Taylor series to x^7
+// (truncation below 3e-13).  About 1e-7 absolute error, far below the BF16
+// spacing of the stored activations.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float ax = fabsf(x);
+  const float e = __builtin_amdgcn_exp2f(ax * 2.8853900817779268f);  // 2 log2(e)
+  const float big = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+  const float x2 = x * x;
+  const float small =
+      ax * (1.f + x2 * (-0.33333333333f + x2 * (0.13333333333f - x2 * 0.053968253968f)));
+  return copysignf(ax < 0.0625f ? small : big, x);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
@@ -107,7 +130,7 @@ __global__ __launch_bounds__(kB) void l0_fwd_kernel(const float* __restrict__ x,
       z0 += sw[(2 * k) * 9 + t] * v[t];
       z1 += sw[(2 * k + 1) * 9 + t] * v[t];
     }
-    pk[k] = uint32_t(f32_to_bf16(tanhf(z0))) | (uint32_t(f32_to_bf16(tanhf(z1))) << 16);
+    pk[k] = pack_bf16(tanh_fast(z0), tanh_fast(z1));
   }
   u32x4* o = reinterpret_cast<u32x4*>(out + p * kC);
 #pragma unroll
@@ -146,7 +169,9 @@ __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restr
 
 // ------------------------------------------------- last layer (32 -> 1)
 
-// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci])
+// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]): four lanes
+// per pixel, each summing eight channels (one 16-byte load per tap), then
+// combined across the four lanes; grid-strided.
 __global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__ a,
                                                     const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias,
@@ -155,26 +180,29 @@ __global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__
   __shared__ float sw[kC * 9];
   for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
   __syncthreads();
-  const size_t hw = size_t(H) * W;
-  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
-  if (p >= size_t(B) * hw) return;
-  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
-  float acc = bias[0];
+  const int hw = H * W, n = B * hw;
+  const int cg = threadIdx.x & 3;
+  const float b0 = bias[0];
+  // the four lanes of a pixel share every iteration (the stride is a
+  // multiple of 4), so they reach the shuffles together
+  for (int p = (blockIdx.x * kB + threadIdx.x) >> 2; p < n; p += (gridDim.x * kB) >> 2) {
+    const int b = p / hw, r = p - b * hw, py = r / W, px = r - py * W;
+    float acc = 0.f;
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
-    const u32x4* s = reinterpret_cast<const u32x4*>(a + (size_t(b) * hw + size_t(yy) * W + xx) * kC);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const u32x4 q = s[k];
+    for (int t = 0; t < 9; ++t) {
+      const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
+      const u32x4 q = *reinterpret_cast<const u32x4*>(
+          a + (size_t(b * H + yy) * W + xx) * kC + 8 * cg);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int ci = 8 * k + 2 * e;
+        const int ci = 8 * cg + 2 * e;
         acc += sw[ci * 9 + t] * lo16(q[e]) + sw[(ci + 1) * 9 + t] * hi16(q[e]);
       }
     }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (cg == 0) y[p] = oscale * (b0 + acc);
   }
-  y[p] = oscale * acc;
 }
 
 // dz2[p][ci] = bf16((s_out sum_t W3[ci][t] dy[p - off(t)]) (1 - a2[p][ci]^2))
@@ -211,8 +239,7 @@ __global__ __launch_bounds__(kB) void l3_bwd_data_kernel(const float* __restrict
         s1 += sw[(ci + 1) * 9 + t] * g[t];
       }
       const float a0 = lo16(q[e]), a1 = hi16(q[e]);
-      res[e] = uint32_t(f32_to_bf16(s0 * (1.f - a0 * a0))) |
-               (uint32_t(f32_to_bf16(s1 * (1.f - a1 * a1))) << 16);
+      res[e] = pack_bf16(s0 * (1.f - a0 * a0), s1 * (1.f - a1 * a1));
     }
     o[k] = res;
   }
@@ -333,6 +360,23 @@ __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restric
   bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
 }
 
+// The nine taps p + sgn off(t) of a 16-pixel tile of one row, lane = (channel
+// group q, pixel c16), as MFMA B fragments.  A ragged tile's lanes past the
+// row end read the last pixel instead (their results are not stored).
+template <int SGN>
+__device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, int tile, int tpr,
+                                          int H, int W, int q, int c16, bf16x8 (&v)[9]) {
+  const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
+  const int b = bh / H, y = bh - b * H;
+  const int px = x0 + c16;
+  const int pl = px < W ? px : W - 1;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrap(y + SGN * (t / 3 - 1), H), xx = wrap(pl + SGN * (t % 3 - 1), W);
+    v[t] = load8(src + pix(b * H + yy, W, xx) * kC + 8 * q);
+  }
+}
+
 // Forward of a hidden layer: out = bf16(tanh(b + sum_t W_t in[p + off(t)])).
 // Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).
 __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict__ in,
@@ -355,29 +399,22 @@ __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict_
   const int tpr = (W + 15) >> 4;
   const int ntiles = B * H * tpr;
   for (int tile = wid; tile < ntiles; tile += nw) {
-    const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
-    const int b = bh / H, y = bh - b * H;
-    const int px = x0 + c16;
-    const int pl = px < W ? px : W - 1;  // ragged tile: any valid pixel
+    bf16x8 cur[9];
+    load_taps<1>(in, tile, tpr, H, W, q, c16, cur);
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(y + t / 3 - 1, H), xx = wrap(pl + t % 3 - 1, W);
-      const bf16x8 xv = load8(in + pix(b * H + yy, W, xx) * kC + 8 * q);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], xv, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], xv, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], cur[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], cur[t], acc1, 0, 0, 0);
     }
+    const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
     if (px < W) {
       uint16_t* o = out + pix(bh, W, px) * kC + 4 * q;
       u32x2 r0, r1;
-      r0[0] = uint32_t(f32_to_bf16(tanhf(acc0[0] + bv[0][0]))) |
-              (uint32_t(f32_to_bf16(tanhf(acc0[1] + bv[0][1]))) << 16);
-      r0[1] = uint32_t(f32_to_bf16(tanhf(acc0[2] + bv[0][2]))) |
-              (uint32_t(f32_to_bf16(tanhf(acc0[3] + bv[0][3]))) << 16);
-      r1[0] = uint32_t(f32_to_bf16(tanhf(acc1[0] + bv[1][0]))) |
-              (uint32_t(f32_to_bf16(tanhf(acc1[1] + bv[1][1]))) << 16);
-      r1[1] = uint32_t(f32_to_bf16(tanhf(acc1[2] + bv[1][2]))) |
-              (uint32_t(f32_to_bf16(tanhf(acc1[3] + bv[1][3]))) << 16);
+      r0[0] = pack_bf16(tanh_fast(acc0[0] + bv[0][0]), tanh_fast(acc0[1] + bv[0][1]));
+      r0[1] = pack_bf16(tanh_fast(acc0[2] + bv[0][2]), tanh_fast(acc0[3] + bv[0][3]));
+      r1[0] = pack_bf16(tanh_fast(acc1[0] + bv[1][0]), tanh_fast(acc1[1] + bv[1][1]));
+      r1[1] = pack_bf16(tanh_fast(acc1[2] + bv[1][2]), tanh_fast(acc1[3] + bv[1][3]));
       *reinterpret_cast<u32x2*>(o) = r0;
       *reinterpret_cast<u32x2*>(o + 16) = r1;
     }
@@ -401,18 +438,15 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
   const int tpr = (W + 15) >> 4;
   const int ntiles = B * H * tpr;
   for (int tile = wid; tile < ntiles; tile += nw) {
-    const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
-    const int b = bh / H, y = bh - b * H;
-    const int px = x0 + c16;
-    const int pl = px < W ? px : W - 1;
+    bf16x8 cur[9];
+    load_taps<-1>(dz, tile, tpr, H, W, q, c16, cur);
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(y - (t / 3 - 1), H), xx = wrap(pl - (t % 3 - 1), W);
-      const bf16x8 gv = load8(dz + pix(b * H + yy, W, xx) * kC + 8 * q);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], gv, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], gv, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], cur[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], cur[t], acc1, 0, 0, 0);
     }
+    const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
     if (px < W) {
       const size_t o = pix(bh, W, px) * kC + 4 * q;
       const u32x2 p0 = *reinterpret_cast<const u32x2*>(aprev + o);
@@ -428,7 +462,7 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
         for (int h = 0; h < 2; ++h) {
           const float g0 = gv[mb][2 * h] * (1.f - av[mb][2 * h] * av[mb][2 * h]);
           const float g1 = gv[mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
-          r[mb][h] = uint32_t(f32_to_bf16(g0)) | (uint32_t(f32_to_bf16(g1)) << 16);
+          r[mb][h] = pack_bf16(g0, g1);
         }
       *reinterpret_cast<u32x2*>(dzprev + o) = r[0];
       *reinterpret_cast<u32x2*>(dzprev + o + 16) = r[1];
@@ -716,11 +750,12 @@ int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
 
 int blocks_for_pixels(int B, int H, int W) { return blocks_for(size_t(B) * H * W); }
 
+
 // wavefronts of the MFMA kernels: enough to fill the chip, each walking
 // many tiles so that its weight fragments are loaded once
 int mfma_blocks(int nitems) {
   const int want = (nitems + kWaves - 1) / kWaves;
-  return want < 512 ? (want > 0 ? want : 1) : 512;
+  return want < 1024 ? (want > 0 ? want : 1) : 1024;
 }
 
 }  // namespace
@@ -739,7 +774,8 @@ void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, in
 
 void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, float* y, int B,
                        int H, int W, float oscale, hipStream_t s) {
-  hipLaunchKernelGGL(l3_fwd_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, a, w, b,
+  const int nb = blocks_for(size_t(4) * B * H * W);
+  hipLaunchKernelGGL(l3_fwd_kernel, dim3(nb < 2048 ? nb : 2048), dim3(kB), 0, s, a, w, b,
                      y, B, H, W, oscale);
 }
 
