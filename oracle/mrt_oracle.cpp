@@ -142,6 +142,7 @@ struct OrcProblem {
   double r_u, a_uv, b_v;
   double alpha;
   int control_on_u;  // 0: control enters Phi_v (default); 1: enters Phi_u
+  int source_order;  // 1: tau F_i; 2: plus (tau^2/2) dF_i/dt (kappa_t = 1, kappa_x = 0)
 };
 
 }  // extern "C"
@@ -233,8 +234,14 @@ inline int neighbour(const OrcProblem& p, int x, int y, int i, int sign) {
 
 // Local collision at one fluid node (eq:LBE with (S), (PhiS), (MF), (MC)).
 // phi: pre-collision [2][Q] (species u then v); out: post-collision [2][Q].
+// Second-order source (eq:LBEG with kappa_t = 1, kappa_x = 0): when Fprev
+// holds Phi_u, Phi_v of the previous step at this node, the term
+// (tau^2/2) dF_i/dt is taken by the explicit characteristic difference
+// (F_i(t) - F_i(t - tau)) / tau of the Remark after (eq:LBEG).  Fnow (if
+// given) receives Phi_u, Phi_v of this step.
 template <typename T>
-void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out) {
+void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
+             const T* Fprev = nullptr, T* Fnow = nullptr) {
   const T* fu = phi;
   const T* fv = phi + Q;
   // (UGS): macroscopic values; first moment of v.
@@ -267,6 +274,10 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out) {
     Phi_u += c;
   else
     Phi_v += c;
+  if (Fnow) {
+    Fnow[0] = Phi_u;
+    Fnow[1] = Phi_v;
+  }
   for (int s = 0; s < 2; ++s) {
     const SpeciesOps& so = s == 0 ? ops.u : ops.v;
     const T* f = s == 0 ? fu : fv;
@@ -297,7 +308,9 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out) {
       if (s == 0) S = WGT[i] * (double(EX[i]) * ax + double(EY[i]) * ay) / CS2;
       // (PhiS) with V = 0.
       T PhiI = WGT[i] * Phi;
-      out[s * Q + i] = back + TAU * S + TAU * PhiI;
+      T second = 0;
+      if (Fprev) second = (TAU * TAU / 2.0) * (PhiI - WGT[i] * Fprev[s]) / TAU;
+      out[s * Q + i] = back + TAU * S + TAU * PhiI + second;
     }
   }
 }
@@ -346,10 +359,15 @@ void stream_push(const OrcProblem& p, const Ops& ops, const T* post, T* fnew) {
 // One step: collide every fluid node, then push-stream along e_i with
 // halfway bounce-back (eq:LBE): phi_i(x + e_i, t+1) = phi*_i(x), or
 // phi_opp(i)(x, t+1) = phi*_i(x) when x + e_i is solid.
+// With source_order 2, F [2][ncell] holds Phi_u, Phi_v of the previous
+// step on entry and those of this step on exit; at the first step (first =
+// true) there is no previous value and the difference term is taken as
+// zero (F_i(-tau) = F_i(0)).
 template <typename T>
 void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
-          T* post, T* fnew) {
+          T* post, T* fnew, T* F = nullptr, bool first = true) {
   const int nc = p.nx * p.ny;
+  const bool second = p.source_order == 2 && F != nullptr;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p.ny; ++y)
     for (int x = 0; x < p.nx; ++x) {
@@ -360,7 +378,17 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
       }
       T loc[2 * Q], out[2 * Q];
       for (int k = 0; k < 2 * Q; ++k) loc[k] = f[k * nc + cell];
-      collide(p, ops, loc, ctrl ? ctrl[cell] : T(0), out);
+      T prev[2], now[2];
+      if (second) {
+        prev[0] = F[cell];
+        prev[1] = F[nc + cell];
+      }
+      collide(p, ops, loc, ctrl ? ctrl[cell] : T(0), out,
+              second && !first ? prev : nullptr, second ? now : nullptr);
+      if (second) {
+        F[cell] = now[0];
+        F[nc + cell] = now[1];
+      }
       for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = out[k];
     }
   stream_push(p, ops, post, fnew);
@@ -446,7 +474,7 @@ void cadj_collide(const OrcProblem& p, const Ops& ops, const double* fw, const d
 // column = input (s',j)), assembled from the partial derivatives of each
 // term of (S) and (PhiS).
 void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
-                     double* dR) {
+                     double* dR, bool with_phi = true) {
   const double* fu = phi;
   const double* fv = phi + Q;
   double u = 0, jx = 0, jy = 0;
@@ -482,6 +510,7 @@ void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
       double dS = wi * u * (ex * (Au[0] * dgx + Au[1] * dgy) +
                             ey * (Au[2] * dgx + Au[3] * dgy)) / CS2;
       dR[(0 * Q + i) * N2 + (1 * Q + j)] += TAU * dS;
+      if (!with_phi) continue;
       // Phi_u = r_u u (1-u): dPhi_u,i/dphi_u,j = w_i r_u (1 - 2u)
       dR[(0 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.r_u * (1.0 - 2.0 * u);
       // Phi_v = a u - b v + c
@@ -505,9 +534,9 @@ void relaxation_jacobian(const SpeciesOps& so, double* Jr) {
 // Full local Jacobian of the collision map: block-diagonal relaxation part
 // plus the source part.
 void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
-                    double* Jac) {
+                    double* Jac, bool with_phi = true) {
   const int N2 = 2 * Q;
-  source_jacobian(p, ops, phi, Jac);
+  source_jacobian(p, ops, phi, Jac, with_phi);
   for (int s = 0; s < 2; ++s) {
     double Jr[Q * Q];
     relaxation_jacobian(s == 0 ? ops.u : ops.v, Jr);
@@ -521,11 +550,22 @@ void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
 //   lambda_i = nu_i - [Lambda* (nu - psi_eq)]_i + R~_i,
 //   Lambda* (nu - psi_eq) = Lambda* nu - O Lambda* nu,
 //   R~_i = sum_k nu_k dR_k/dphi_i  (R = tau S + tau Phi over both species).
+//
+// With rho given (source_order 2), the kinetics part of R is left out of
+// dR and enters as sum_s rho_s dPhi_s/dphi_i instead, rho_s being the
+// adjoint of the node's Phi_s of this step.
 void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
-                   const double* nu, double* lam) {
+                   const double* nu, double* lam, const double* rho = nullptr) {
   const int N2 = 2 * Q;
   double dR[N2 * N2];
-  source_jacobian(p, ops, phi, dR);
+  source_jacobian(p, ops, phi, dR, rho == nullptr);
+  double dphi[2] = {0.0, 0.0};  // sum_s rho_s dPhi_s / dTheta_{s'}
+  if (rho) {
+    double u = 0.0;
+    for (int i = 0; i < Q; ++i) u += phi[i];
+    dphi[0] = rho[0] * p.r_u * (1.0 - 2.0 * u) + rho[1] * p.a_uv;
+    dphi[1] = -rho[1] * p.b_v;
+  }
   for (int s = 0; s < 2; ++s) {
     const SpeciesOps& so = s == 0 ? ops.u : ops.v;
     const double* n = nu + s * Q;
@@ -539,7 +579,7 @@ void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
       for (int j = 0; j < Q; ++j) OLn += so.weq[j] * Ln[j];
       double Rt = 0.0;
       for (int k = 0; k < N2; ++k) Rt += nu[k] * dR[k * N2 + (s * Q + i)];
-      lam[s * Q + i] = n[i] - (Ln[i] - OLn) + Rt;
+      lam[s * Q + i] = n[i] - (Ln[i] - OLn) + Rt + dphi[s];
     }
   }
 }
@@ -550,12 +590,13 @@ void run_forward(const OrcProblem& p, const Ops& ops, int nsteps,
   const size_t nc = size_t(p.nx) * p.ny;
   f.assign(2 * Q * nc, 0.0);
   std::vector<double> post(2 * Q * nc), fnew(2 * Q * nc);
+  std::vector<double> F(2 * nc, 0.0);
   init_equilibrium(p, ops, u0, v0, f.data());
   if (traj) traj->assign(size_t(nsteps) * 2 * Q * nc, 0.0);
   for (int n = 0; n < nsteps; ++n) {
     if (traj) std::memcpy(traj->data() + size_t(n) * 2 * Q * nc, f.data(),
                           sizeof(double) * 2 * Q * nc);
-    step(p, ops, f.data(), c, post.data(), fnew.data());
+    step(p, ops, f.data(), c, post.data(), fnew.data(), F.data(), n == 0);
     f.swap(fnew);
   }
 }
@@ -622,7 +663,7 @@ int orc_forward(const OrcProblem* p, int nsteps, const double* u0,
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
-  std::vector<double> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc);
+  std::vector<double> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc), F(2 * nc, 0.0);
   init_equilibrium(*p, ops, u0, v0, f.data());
   for (int n = 0; n < nsteps; ++n) {
     if (traj_u || traj_j)
@@ -639,7 +680,7 @@ int orc_forward(const OrcProblem* p, int nsteps, const double* u0,
           traj_j[(size_t(n) * 2 + 1) * nc + cell] = jy;
         }
       }
-    step<double>(*p, ops, f.data(), c, post.data(), fnew.data());
+    step<double>(*p, ops, f.data(), c, post.data(), fnew.data(), F.data(), n == 0);
     f.swap(fnew);
   }
   for (size_t cell = 0; cell < nc; ++cell) {
@@ -695,6 +736,12 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   }
   for (size_t cell = 0; cell < nc; ++cell) g[cell] = 0.0;
   const int cs = p->control_on_u ? 0 : 1;
+  // source_order 2: the state of the scheme also holds F(t - tau), i.e.
+  // Phi_u, Phi_v of the previous step; mu [2][ncell] is its adjoint (the
+  // adjoint of the Phi stored by step n, read by step n + 1; 0 after the
+  // last step, which nothing reads).
+  const bool so2 = p->source_order == 2;
+  std::vector<double> mu(so2 ? 2 * nc : 0, 0.0);
   for (int n = nsteps - 1; n >= 0; --n) {
     // Adjoint streaming along -e_i (transpose of push + bounce-back):
     // nu_i(x) = lambda_i(x + e_i) if x + e_i is fluid, else lambda_opp(i)(x).
@@ -722,11 +769,27 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
           loc[k] = fn[k * nc + cell];
           nl[k] = nu[k * nc + cell];
         }
-        // (gradientLattice): dF_Theta,i/dc = tau w_i.
-        double gc = 0.0;
-        for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * TAU * WGT[i];
-        g[cell] += gc;
-        local_adjoint(*p, ops, loc, nl, out);
+        if (!so2) {
+          // (gradientLattice): dF_Theta,i/dc = tau w_i.
+          double gc = 0.0;
+          for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * TAU * WGT[i];
+          g[cell] += gc;
+          local_adjoint(*p, ops, loc, nl, out);
+        } else {
+          // out_i = ... + tau w_i Phi + (tau/2) w_i (Phi - F_prev) (n >= 1):
+          // d out_i / d Phi = (tau + tau/2) w_i, d out_i / d F_prev =
+          // -(tau/2) w_i; Phi of this step is also stored for step n + 1.
+          double sig[2] = {0.0, 0.0}, rho[2];
+          for (int q = 0; q < 2; ++q)
+            for (int i = 0; i < Q; ++i) sig[q] += nl[q * Q + i] * WGT[i];
+          const double kdir = TAU + (n >= 1 ? TAU / 2.0 : 0.0);
+          for (int q = 0; q < 2; ++q) {
+            rho[q] = kdir * sig[q] + mu[q * nc + cell];
+            mu[q * nc + cell] = n >= 1 ? -(TAU / 2.0) * sig[q] : 0.0;
+          }
+          g[cell] += rho[cs];  // dPhi_cs / dc = 1
+          local_adjoint(*p, ops, loc, nl, out, rho);
+        }
         for (int k = 0; k < 2 * Q; ++k) lam[k * nc + cell] = out[k];
       }
   }
@@ -764,6 +827,10 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
   }
   const int cs = p->control_on_u ? 0 : 1;
   const int N2 = 2 * Q;
+  // source_order 2: dF [2][ncell] is the perturbation of the stored Phi of
+  // the previous step.
+  const bool so2 = p->source_order == 2;
+  std::vector<double> dF(so2 ? 2 * nc : 0, 0.0);
   for (int n = 0; n < nsteps; ++n) {
     const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
 #pragma omp parallel for schedule(static)
@@ -776,15 +843,37 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
         }
         double loc[N2], Jac[N2 * N2];
         for (int k = 0; k < N2; ++k) loc[k] = fn[k * nc + cell];
-        local_jacobian(*p, ops, loc, Jac);
+        local_jacobian(*p, ops, loc, Jac, !so2);
         for (int r = 0; r < N2; ++r) {
           double acc = 0.0;
           for (int k = 0; k < N2; ++k) acc += Jac[r * N2 + k] * d[k * nc + cell];
           dpost[r * nc + cell] = acc;
         }
-        if (dc)
-          for (int i = 0; i < Q; ++i)
-            dpost[(cs * Q + i) * nc + cell] += TAU * WGT[i] * dc[cell];
+        if (!so2) {
+          if (dc)
+            for (int i = 0; i < Q; ++i)
+              dpost[(cs * Q + i) * nc + cell] += TAU * WGT[i] * dc[cell];
+        } else {
+          // perturbation of Phi_u, Phi_v (with the control) of this step
+          double u = 0.0, du = 0.0, dv = 0.0;
+          for (int i = 0; i < Q; ++i) {
+            u += loc[i];
+            du += d[(0 * Q + i) * nc + cell];
+            dv += d[(1 * Q + i) * nc + cell];
+          }
+          const double dcc = dc ? dc[cell] : 0.0;
+          double dphi[2];
+          dphi[0] = p->r_u * (1.0 - 2.0 * u) * du + (cs == 0 ? dcc : 0.0);
+          dphi[1] = p->a_uv * du - p->b_v * dv + (cs == 1 ? dcc : 0.0);
+          for (int q = 0; q < 2; ++q) {
+            for (int i = 0; i < Q; ++i) {
+              double add = TAU * WGT[i] * dphi[q];
+              if (n >= 1) add += (TAU / 2.0) * WGT[i] * (dphi[q] - dF[q * nc + cell]);
+              dpost[(q * Q + i) * nc + cell] += add;
+            }
+            dF[q * nc + cell] = dphi[q];
+          }
+        }
       }
     std::fill(dnew.begin(), dnew.end(), 0.0);
     for (int y = 0; y < p->ny; ++y)
@@ -833,9 +922,10 @@ int orc_cost_complex_step(const OrcProblem* p, int nsteps, const double* u0,
     cv0[k] = v0[k];
     cc[k] = cd(c[k], h * dc[k]);
   }
+  std::vector<cd> F(2 * nc);
   init_equilibrium<cd>(*p, ops, cu0.data(), cv0.data(), f.data());
   for (int n = 0; n < nsteps; ++n) {
-    step<cd>(*p, ops, f.data(), cc.data(), post.data(), fnew.data());
+    step<cd>(*p, ops, f.data(), cc.data(), post.data(), fnew.data(), F.data(), n == 0);
     f.swap(fnew);
   }
   cd J = 0.0;

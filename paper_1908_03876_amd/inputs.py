@@ -49,6 +49,7 @@ class Problem:
     v0: np.ndarray = None        # [ny, nx]
     control: np.ndarray = None   # [ny, nx], initial guess of c
     u_target: np.ndarray = None  # [ny, nx]
+    source_order: int = 1        # 1: tau w_i Phi; 2: plus (tau^2/2) d/dt of it
     name: str = ""
 
     @property

@@ -54,6 +54,16 @@ MUTANTS = [
      "traj.data() + size_t(nsteps - 1 - k) * 2 * Q * nc;", "traj.data() + size_t(k) * 2 * Q * nc;"),
     ("dropped half in the penalty",
      "jr += 0.5 * p->alpha * c[cell] * c[cell];", "jr += p->alpha * c[cell] * c[cell];"),
+    ("second-order source: sign of the previous step",
+     "(PhiI - WGT[i] * Fprev[s])", "(PhiI + WGT[i] * Fprev[s])"),
+    ("second-order source: zero history at the first step",
+     "second && !first ? prev : nullptr", "second ? prev : nullptr"),
+    ("second-order adjoint: direct coefficient without the difference term",
+     "const double kdir = TAU + (n >= 1 ? TAU / 2.0 : 0.0);", "const double kdir = TAU;"),
+    ("second-order adjoint: lag adjoint not carried",
+     "rho[q] = kdir * sig[q] + mu[q * nc + cell];", "rho[q] = kdir * sig[q];"),
+    ("second-order TLM: previous perturbation dropped",
+     "(dphi[q] - dF[q * nc + cell])", "(dphi[q])"),
 ]
 
 

@@ -505,3 +505,119 @@ def test_continuous_adjoint_without_chemotaxis_is_penalty_only():
     p = I.tiny(L=8, nsteps=10, seed=5).copy(chi=0.0)
     g = O.cost_gradient_continuous(p)["grad"]
     np.testing.assert_allclose(g, p.alpha * p.control * p.fluid, rtol=0, atol=1e-17)
+
+
+# ------------------------------------- second-order source term (eq:LBEG)
+
+def _single_site(r_u=0.7, a_uv=0.3, b_v=0.45, c=0.15, u0=0.3, v0=0.2, nsteps=7,
+                 source_order=2):
+    one = np.ones((1, 1))
+    return I.Problem(nx=1, ny=1, nsteps=nsteps, periodic=True, solid=None,
+                     Du=np.array([[0.3, 0.1], [0.1, 0.2]]), Dv=0.5 * np.eye(2), chi=0.8,
+                     Cchi=np.eye(2), r_u=r_u, a_uv=a_uv, b_v=b_v, alpha=0.01,
+                     u0=u0 * one, v0=v0 * one, control=c * one, u_target=0.9 * one,
+                     source_order=source_order)
+
+
+def test_second_order_source_single_site_is_adams_bashforth():
+    """(eq:LBEG) with kappa_t = 1, kappa_x = 0 and the explicit characteristic
+    difference of the Remark after it: on one periodic site streaming is the
+    identity and the populations sum to
+    Theta' = Theta + tau Phi^n + (tau/2)(Phi^n - Phi^{n-1}), the two-step
+    Adams-Bashforth rule (with Phi^{-1} = Phi^0 at the first step).  With the
+    control on u, dJ/dc follows from the tangent of that scalar recurrence."""
+    p = _single_site()
+    u, v, c = 0.3, 0.2, 0.15
+    pu = pv = None
+    for _ in range(7):
+        fu, fv = 0.7 * u * (1 - u), 0.3 * u - 0.45 * v + c
+        lu = fu if pu is None else pu
+        lv = fv if pv is None else pv
+        u, v, pu, pv = u + fu + 0.5 * (fu - lu), v + fv + 0.5 * (fv - lv), fu, fv
+    r = O.forward(p)
+    assert abs(r["uN"][0, 0] - u) < 1e-15 and abs(r["vN"][0, 0] - v) < 1e-15
+    # control on u: Phi_u = r u (1 - u) + c; tangent recurrence with dc = 1
+    us, du, dfp = [0.3], 0.0, None
+    for n in range(7):
+        un = us[-1]
+        df = 0.7 * (1 - 2 * un) * du + 1.0
+        dl = df if dfp is None else dfp
+        fu = 0.7 * un * (1 - un) + c
+        fl = fu if n == 0 else 0.7 * us[-2] * (1 - us[-2]) + c
+        us.append(un + fu + 0.5 * (fu - fl))
+        du, dfp = du + df + 0.5 * (df - dl), df
+    g = O.cost_gradient(p, control_on_u=True)
+    assert abs(g["grad"][0, 0] - ((us[-1] - 0.9) * du + 0.01 * c)) < 1e-14
+
+
+@pytest.mark.parametrize("order,ratio", [(1, 2.0), (2, 4.0)])
+def test_source_order_sets_the_time_accuracy_of_the_kinetics(order, ratio):
+    """The second-order term is what makes the kinetics O(tau^2) accurate
+    (Chapman-Enskog balance with kappa_t = 1, Section 3.1): on one site the
+    logistic u' = r u (1 - u) has the closed form
+    u(t) = 1 / (1 + (1/u0 - 1) exp(-r t)); halving r tau at a fixed r t
+    divides the error at r t = 4 by about 2 (first order) or 4 (second)."""
+    errs = []
+    for r_u, n in ((0.05, 80), (0.025, 160), (0.0125, 320)):
+        p = _single_site(r_u=r_u, a_uv=0.0, b_v=0.0, c=0.0, u0=0.1, nsteps=n,
+                         source_order=order)
+        exact = 1.0 / (1.0 + 9.0 * np.exp(-4.0))
+        errs.append(abs(O.forward(p)["uN"][0, 0] - exact))
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 0.9 * ratio < e0 / e1 < 1.1 * ratio
+
+
+def test_second_order_constant_source_equals_first_order():
+    """A source that does not change in time (no kinetics, static control)
+    makes the difference term vanish: the second-order scheme equals the
+    first-order one, forward exactly and gradient to rounding."""
+    p = I.tiny(L=8, nsteps=12, seed=6, masked=True).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
+    a = O.forward(p)
+    b = O.forward(p.copy(source_order=2))
+    assert np.array_equal(a["uN"], b["uN"]) and np.array_equal(a["vN"], b["vN"])
+    ga = O.cost_gradient(p)["grad"]
+    gb = O.cost_gradient(p.copy(source_order=2))["grad"]
+    assert np.abs(ga - gb).max() <= 1e-13 * np.abs(ga).max()
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_second_order_gradient_complex_step(k):
+    """The adjoint of the second-order scheme (the stored Phi of the
+    previous step is part of the state, its adjoint carried backwards) is
+    the exact derivative of J: complex step, h = 1e-20."""
+    p = _cases()[k].copy(source_order=2)
+    g = O.cost_gradient(p)["grad"]
+    for seed in (1, 2):
+        h = I.random_direction(p, seed)
+        _, dj = O.cost_complex_step(p, h)
+        assert abs((g * h).sum() - dj) <= 1e-12 * max(abs(dj), 1e-300)
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_second_order_tlm_adjoint_dot_product(k):
+    """Sensitivity equations of the second-order scheme against its adjoint:
+    <a, du^N> + <b, dv^N> = <g, dc> + <dJ/du0, du0> + <dJ/dv0, dv0>."""
+    p = _cases()[k].copy(source_order=2)
+    rng = np.random.default_rng(30 + k)
+    f = p.fluid
+    a, b, dc, du0, dv0 = (rng.standard_normal((p.ny, p.nx)) * f for _ in range(5))
+    duN, dvN = O.tlm(p, dc=dc, du0=du0, dv0=dv0)
+    g, gu0, gv0 = O.adjoint(p, a, b)
+    lhs = (a * duN).sum() + (b * dvN).sum()
+    rhs = (g * dc).sum() + (gu0 * du0).sum() + (gv0 * dv0).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_second_order_tlm_against_differences():
+    """The second-order TLM against central differences of u^N and v^N."""
+    p = _cases()[1].copy(source_order=2)
+    rng = np.random.default_rng(33)
+    f = p.fluid
+    dc, du0 = rng.standard_normal((p.ny, p.nx)) * f, rng.standard_normal((p.ny, p.nx)) * f
+    duN, dvN = O.tlm(p, dc=dc, du0=du0)
+    eps = 1e-6
+    rp = O.forward(p, control=p.control + eps * dc, u0=p.u0 + eps * du0)
+    rm = O.forward(p, control=p.control - eps * dc, u0=p.u0 - eps * du0)
+    for d, key in ((duN, "uN"), (dvN, "vN")):
+        fd = (rp[key] - rm[key]) / (2 * eps)
+        assert np.linalg.norm(d - fd) <= 1e-7 * np.linalg.norm(fd)
