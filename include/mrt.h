@@ -95,6 +95,17 @@ typedef struct mrt_problem {
   double a_uv;     /* Phi_v = a_uv u - b_v v + c */
   double b_v;
   double alpha;    /* control penalty weight, >= 0 */
+  /* Source term of the LBE (eq:LBEG): 0 or 1 = tau F_i (first order, the
+   * default); 2 = tau F_i + (tau^2/2) dF_i/dt, i.e. kappa_t = 1 and
+   * kappa_x = 0, with the time derivative taken by the explicit
+   * characteristic difference (F_i(t) - F_i(t - tau)) / tau of the Remark
+   * after (eq:LBEG) and F_i(-tau) = F_i(0).  Order 2 adds the previous
+   * step's kinetics to the scheme's state (two planes, carried by the tape
+   * and its checkpoints).  It is a two-step (Adams-Bashforth-like) rule:
+   * stable for slow kinetics, unstable when tau dPhi/dTheta reaches -1.
+   * The batched engine accepts order 0 or 1 only. */
+  int32_t source_order;
+  int32_t reserved;  /* must be 0 */
 } mrt_problem;
 
 /* Reduced scalars returned by cost_gradient (host struct). */

@@ -43,7 +43,8 @@ class mrt_problem(ctypes.Structure):
     _fields_ = [("grid", mrt_grid), ("u", mrt_species), ("v", mrt_species),
                 ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 4),
                 ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
-                ("b_v", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("b_v", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("source_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mrt_scalars(ctypes.Structure):

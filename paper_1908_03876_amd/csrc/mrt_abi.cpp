@@ -107,6 +107,9 @@ int validate(const mrt_problem* p) {
   if (!finite_all(sc, 8) || !std::isfinite(p->alpha))
     return fail(MRT_EINVAL, "non-finite model coefficient");
   if (p->alpha < 0.0) return fail(MRT_EINVAL, "alpha < 0");
+  if (p->source_order < 0 || p->source_order > 2)
+    return fail(MRT_EINVAL, "source_order %d: must be 0, 1 or 2", p->source_order);
+  if (p->reserved != 0) return fail(MRT_EINVAL, "problem.reserved must be 0");
   return MRT_OK;
 }
 
@@ -275,10 +278,17 @@ template ModelCoef<double> model_coef<double>(const mrt_problem*);
 struct mrt_tape {
   int nx, ny, pitch, nsteps, dtype, periodic, masked, device;
   int mode, K, nseg;
+  int so2;                  // second-order source term (source_order 2)
   size_t plane, elem, state_bytes, rec_slot_bytes, total_bytes;
   void* buf[2] = {nullptr, nullptr};
   void* abuf[2] = {nullptr, nullptr};
   std::vector<void*> ckpt;  // ckpt[s] (s >= 1): post-collision state of step sK-1
+  // so2: kinetics of the previous step [2][plane] (forward), its adjoint or
+  // its perturbation (adjoint and tangent sweeps), and per checkpoint the
+  // kinetics stored by step sK-1
+  void* lag = nullptr;
+  void* alag = nullptr;
+  std::vector<void*> ckpt_lag;
   void* rec = nullptr;      // record slots [K][3][plane]
   uint16_t* link = nullptr;
   uint32_t* wflag = nullptr;
@@ -301,7 +311,7 @@ size_t elem_size(int dtype) { return dtype == MRT_F64 ? 8 : 4; }
 
 struct Layout {
   int mode, K, nseg;
-  size_t plane, elem, state_bytes, rec_slot_bytes, total;
+  size_t plane, elem, state_bytes, rec_slot_bytes, lag_bytes, total;
 };
 
 Layout plan(const mrt_problem* p, int ckpt_every) {
@@ -311,6 +321,7 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
   L.elem = elem_size(g.dtype);
   L.state_bytes = 18 * L.plane * L.elem;
   L.rec_slot_bytes = 3 * L.plane * L.elem;
+  L.lag_bytes = p->source_order == 2 ? 2 * L.plane * L.elem : 0;
   if (ckpt_every <= 0) {
     L.mode = 0;
     L.K = g.nsteps;
@@ -325,14 +336,14 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
     L.nseg = (g.nsteps + ckpt_every - 1) / ckpt_every;
   }
   const bool masked = g.mask != nullptr;
-  size_t t = 2 * L.state_bytes;  // forward ping-pong
+  size_t t = 2 * L.state_bytes + L.lag_bytes;  // forward ping-pong, lag
   if (masked)
     t += L.plane * sizeof(uint16_t) +
          size_t(g.ny) * ((g.nx + 63) / 64) * sizeof(uint32_t);
   t += (size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double);
   if (L.mode > 0) {
-    t += 2 * L.state_bytes;                          // adjoint ping-pong
-    t += size_t(L.nseg - 1) * L.state_bytes;          // checkpoints
+    t += 2 * L.state_bytes + L.lag_bytes;            // adjoint ping-pong, lag
+    t += size_t(L.nseg - 1) * (L.state_bytes + L.lag_bytes);  // checkpoints
     t += size_t(L.K) * L.rec_slot_bytes;              // record slots
   }
   L.total = t;
@@ -347,6 +358,8 @@ int check_tape(const mrt_problem* p, const mrt_tape* t) {
       g.nsteps != t->nsteps || g.dtype != t->dtype ||
       g.periodic != t->periodic || masked != t->masked)
     return fail(MRT_ESTATE, "tape was created for another grid");
+  if ((p->source_order == 2 ? 1 : 0) != t->so2)
+    return fail(MRT_ESTATE, "tape was created for another source order");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
     return fail(MRT_ESTATE, "tape belongs to device %d, current is %d",
@@ -385,14 +398,22 @@ int last_launch_error() {
 // The output of step n goes to ckpt[(n+1)/K] when that step closes a
 // segment (checkpointed mode, forward pass), else to a ping-pong buffer.
 // Returns the buffer holding the last written state through *last.
+//
+// Second-order source: the kinetics of the previous step live in t->lag;
+// a step that closes a segment also saves them beside its checkpoint, and
+// a recomputation that starts from checkpoint `seg` (restore_lag) first
+// restores them.
 template <typename T>
 int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
                       const mrt::Geometry& g, int n0, int n1, const T* src,
                       const T* u0, const T* v0, const T* ctrl, bool record,
                       bool write_ckpt, int kind, hipStream_t s,
-                      const T** last) {
+                      const T** last, bool restore_lag = false) {
   SpanGuard span(kind, s);
   const int seg = n0 / t->K;
+  if (t->so2 && restore_lag && n0 > 0)
+    HIP_TRY(hipMemcpyAsync(t->lag, t->ckpt_lag[seg], 2 * t->plane * t->elem,
+                           hipMemcpyDeviceToDevice, s));
   for (int n = n0; n < n1; ++n) {
     mrt::FwdLaunch<T> a;
     a.src = src;
@@ -400,14 +421,18 @@ int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
     a.v0 = v0;
     a.ctrl = ctrl;
     a.rec = record ? slot<T>(t, n - seg * t->K) : nullptr;
+    a.lag = t->so2 ? static_cast<T*>(t->lag) : nullptr;
     T* dst = static_cast<T*>(t->buf[n & 1]);
-    if (write_ckpt && t->mode == 2 && (n + 1) % t->K == 0 && n + 1 < t->nsteps)
-      dst = static_cast<T*>(t->ckpt[(n + 1) / t->K]);
+    const bool closes = write_ckpt && t->mode == 2 && (n + 1) % t->K == 0 && n + 1 < t->nsteps;
+    if (closes) dst = static_cast<T*>(t->ckpt[(n + 1) / t->K]);
     a.dst = dst;
     mrt::launch_forward_step<T>(g, m, a, s);
     span.count();
     int rc = last_launch_error();
     if (rc) return rc;
+    if (closes && t->so2)
+      HIP_TRY(hipMemcpyAsync(t->ckpt_lag[(n + 1) / t->K], t->lag, 2 * t->plane * t->elem,
+                             hipMemcpyDeviceToDevice, s));
     src = dst;
   }
   *last = src;
@@ -475,7 +500,7 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
       const T* dummy = nullptr;
       t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true,
-                                    false, 2, s, &dummy);
+                                    false, 2, s, &dummy, true);
       if (rc) return rc;
       t->rec_seg = seg;
     }
@@ -492,6 +517,8 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
       a.g = gacc;
       a.adj_u0 = static_cast<T*>(adj_u0);
       a.adj_v0 = static_cast<T*>(adj_v0);
+      a.mu = t->so2 ? static_cast<T*>(t->alag) : nullptr;
+      a.step0 = n == 0 ? 1 : 0;
       mrt::launch_adjoint_step<T>(g, m, a, s);
       span.count();
       int rc = last_launch_error();
@@ -523,7 +550,7 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
       const T* dummy = nullptr;
       t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true, false, 2, s,
-                                    &dummy);
+                                    &dummy, true);
       if (rc) return rc;
       t->rec_seg = seg;
     }
@@ -536,6 +563,7 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
       a.dv0 = static_cast<const T*>(dv0);
       a.dc = static_cast<const T*>(dc);
       a.rec = slot<T>(t, n - n0);
+      a.dlag = t->so2 ? static_cast<T*>(t->alag) : nullptr;
       mrt::launch_tlm_step<T>(g, m, a, s);
       span.count();
       int rc = last_launch_error();
@@ -567,7 +595,7 @@ int cadjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void*
       const T* dummy = nullptr;
       t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, cs, tu0, tv0, tc, true, false, 2, s,
-                                    &dummy);
+                                    &dummy, true);
       if (rc) return rc;
       t->rec_seg = seg;
     }
@@ -668,6 +696,7 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   t->mode = L.mode;
   t->K = L.K;
   t->nseg = L.nseg;
+  t->so2 = p->source_order == 2 ? 1 : 0;
   t->plane = L.plane;
   t->elem = L.elem;
   t->state_bytes = L.state_bytes;
@@ -689,6 +718,7 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   }
   rc = alloc(L.state_bytes, &t->buf[0]);
   if (!rc) rc = alloc(L.state_bytes, &t->buf[1]);
+  if (!rc && t->so2) rc = alloc(L.lag_bytes, &t->lag);
   if (!rc && t->masked) rc = alloc(L.plane * sizeof(uint16_t), (void**)&t->link);
   if (!rc && t->masked)
     rc = alloc(size_t(g.ny) * ((g.nx + 63) / 64) * sizeof(uint32_t),
@@ -701,6 +731,9 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
     if (!rc) rc = alloc(L.state_bytes, &t->abuf[1]);
     t->ckpt.assign(L.nseg, nullptr);
     for (int k = 1; k < L.nseg && !rc; ++k) rc = alloc(L.state_bytes, &t->ckpt[k]);
+    if (!rc && t->so2) rc = alloc(L.lag_bytes, &t->alag);
+    t->ckpt_lag.assign(L.nseg, nullptr);
+    for (int k = 1; t->so2 && k < L.nseg && !rc; ++k) rc = alloc(L.lag_bytes, &t->ckpt_lag[k]);
     if (!rc) rc = alloc(size_t(L.K) * L.rec_slot_bytes, &t->rec);
   }
   if (!rc && hipHostMalloc((void**)&t->host, 16 * sizeof(double)) != hipSuccess)

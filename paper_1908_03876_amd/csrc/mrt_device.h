@@ -292,11 +292,21 @@ __device__ __forceinline__ void store_state(const Geometry& g, const NodeIdx& n,
 // Collision of the gathered node values and the stores: record (u, j_v),
 // post-collision state, wall slots.  `lm` is the node's link word (0
 // without a mask).
-template <typename T, bool MASKED>
+//
+// LAG: second-order source term of (eq:LBEG) with kappa_t = 1, kappa_x = 0
+// by the explicit characteristic difference: tau F + (tau/2)(F - F_prev)
+// = tau (3/2 F - 1/2 F_prev) per population.  lag [2][plane] holds the
+// kinetics r_u u (1-u), a_uv u - b_v v of the previous step at this node
+// (the static control cancels in the difference) and is overwritten with
+// this step's; at the first step there is no previous value and the
+// difference is zero.
+template <typename T, bool MASKED, bool LAG = false>
 __device__ __forceinline__ void forward_collide_store(const Geometry& g, const NodeIdx& n,
                                                       const ModelCoef<T>& m, T fu[9], T fv[9],
                                                       T c, T* __restrict__ dst,
-                                                      T* __restrict__ rec, unsigned lm) {
+                                                      T* __restrict__ rec, unsigned lm,
+                                                      T* __restrict__ lag = nullptr,
+                                                      bool first = false) {
   const size_t idx = n.r0 + n.x;
   // macroscopic values (UGS) and the first moment of v
   T u = T(0), v = T(0);
@@ -317,8 +327,22 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
   // grad v = -K_v j_v / (tau d_v Cs^2)
   const T ax = u * (m.b00 * jx + m.b01 * jy);
   const T ay = u * (m.b10 * jx + m.b11 * jy);
-  const T phu = m.r_u * u * (T(1) - u);
-  const T phv = m.a_uv * u - m.b_v * v + c;
+  const T ru = m.r_u * u * (T(1) - u);
+  const T rv = m.a_uv * u - m.b_v * v;
+  T phu, phv;
+  if (LAG) {
+    const T lu = first ? ru : lag[idx];
+    const T lv = first ? rv : lag[g.plane + idx];
+    phu = T(1.5) * ru - T(0.5) * lu;
+    phv = T(1.5) * rv - T(0.5) * lv + c;
+    if (!(MASKED && (lm & 1u))) {
+      lag[idx] = ru;
+      lag[g.plane + idx] = rv;
+    }
+  } else {
+    phu = ru;
+    phv = rv + c;
+  }
   T t1, t2;
   relax(fu, u, m.u, t1, t2);
   relax(fv, v, m.v, t1, t2);
@@ -336,11 +360,15 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
 // the perturbed density); the sources give
 //   d(u B j_v) = du B j_v + u B dj_v,   dPhi_u = r_u (1 - 2u) du,
 //   dPhi_v = a_uv du - b_v dv + dc.
-template <typename T, bool MASKED>
+// LAG: the second-order source as in the forward, on the perturbed
+// kinetics; dlag [2][plane] carries their previous-step values.
+template <typename T, bool MASKED, bool LAG = false>
 __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeIdx& n,
                                                   const ModelCoef<T>& m, T fu[9], T fv[9],
                                                   T dc, const T* __restrict__ rec,
-                                                  T* __restrict__ dst, unsigned lm) {
+                                                  T* __restrict__ dst, unsigned lm,
+                                                  T* __restrict__ dlag = nullptr,
+                                                  bool first = false) {
   const size_t idx = n.r0 + n.x;
   const T u = __builtin_nontemporal_load(&rec[idx]);
   const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
@@ -355,8 +383,22 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
   const T djy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
   const T dax = du * (m.b00 * jx + m.b01 * jy) + u * (m.b00 * djx + m.b01 * djy);
   const T day = du * (m.b10 * jx + m.b11 * jy) + u * (m.b10 * djx + m.b11 * djy);
-  const T dphu = m.r_u * (T(1) - T(2) * u) * du;
-  const T dphv = m.a_uv * du - m.b_v * dv + dc;
+  const T dru = m.r_u * (T(1) - T(2) * u) * du;
+  const T drv = m.a_uv * du - m.b_v * dv;
+  T dphu, dphv;
+  if (LAG) {
+    const T lu = first ? dru : dlag[idx];
+    const T lv = first ? drv : dlag[g.plane + idx];
+    dphu = T(1.5) * dru - T(0.5) * lu;
+    dphv = T(1.5) * drv - T(0.5) * lv + dc;
+    if (!(MASKED && (lm & 1u))) {
+      dlag[idx] = dru;
+      dlag[g.plane + idx] = drv;
+    }
+  } else {
+    dphu = dru;
+    dphv = drv + dc;
+  }
   T t1, t2;
   relax(fu, du, m.u, t1, t2);
   relax(fv, dv, m.v, t1, t2);
@@ -427,11 +469,11 @@ __device__ __forceinline__ void cadj_collide_store(const Geometry& g, const Node
 // run-time flag (rec != null), not a template parameter: the recorded and
 // the plain steps then run the same machine code, so a checkpointed
 // recomputation reproduces the recorded trajectory bit for bit.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG = false>
 __device__ __forceinline__ void forward_node(
     const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ u0, const T* __restrict__ v0,
-    const T* __restrict__ ctrl, T* __restrict__ rec) {
+    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag = nullptr) {
   unsigned lm = 0;
   if (MASKED) {
     const unsigned flag = wave_flag(g, n);
@@ -440,7 +482,7 @@ __device__ __forceinline__ void forward_node(
   }
   T fu[9], fv[9], c;
   forward_gather<T, PERIODIC, FIRST>(g, n, m, src, u0, v0, ctrl, fu, fv, c);
-  forward_collide_store<T, MASKED>(g, n, m, fu, fv, c, dst, rec, lm);
+  forward_collide_store<T, MASKED, LAG>(g, n, m, fu, fv, c, dst, rec, lm, lag, FIRST);
 }
 
 template <typename T, bool PERIODIC, bool MASKED>
@@ -480,12 +522,21 @@ __device__ __forceinline__ void finalize_node(
 
 // --------------------------------------------------------------- adjoint
 
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST>
+// LAG: adjoint of the second-order source.  The scheme's state then also
+// holds the previous step's kinetics F_prev; mu [2][plane] is the adjoint
+// of the kinetics this step stores for the next one.  With sigma = w . nu
+// per species, the adjoint of this step's kinetics is rho = 3/2 sigma + mu
+// (sigma + mu at step 0, where F_prev = F), and the new mu = -1/2 sigma.
+// FIRST (step N-1) reads no mu: nothing reads the last stored kinetics.
+// step0 marks step 0 (a run-time flag: LAST is set only when dJ/du0,
+// dJ/dv0 are requested).
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, bool LAG = false>
 __device__ __forceinline__ void adjoint_node(
     const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ seed_u, const T* __restrict__ seed_v,
     const T* __restrict__ rec, double* __restrict__ gacc,
-    T* __restrict__ adj_u0, T* __restrict__ adj_v0) {
+    T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu = nullptr,
+    bool step0 = false) {
   const size_t idx = n.r0 + n.x;
   unsigned lm = 0;
   if (MASKED) {
@@ -556,9 +607,23 @@ __device__ __forceinline__ void adjoint_node(
   const T bjy = m.b10 * jx + m.b11 * jy;
   // transposed sources: d(tau S_u + tau Phi_u)/dphi_u is rank one along 1,
   // d(tau S_u)/dphi_v = (tau/Cs^2) diag(w) E u B E^T, dPhi_v/dphi = (a, -b).
-  const T cu = su_ * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
-               sv_ * m.a_uv;
-  const T cv = -sv_ * m.b_v;
+  T rho_u = su_, rho_v = sv_;
+  if (LAG) {
+    const T mu_u = FIRST ? T(0) : mu[idx];
+    const T mu_v = FIRST ? T(0) : mu[g.plane + idx];
+    if (step0) {
+      rho_u = su_ + mu_u;
+      rho_v = sv_ + mu_v;
+    } else {
+      rho_u = T(1.5) * su_ + mu_u;
+      rho_v = T(1.5) * sv_ + mu_v;
+      mu[idx] = T(-0.5) * su_;
+      mu[g.plane + idx] = T(-0.5) * sv_;
+    }
+  }
+  const T cu = rho_u * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
+               rho_v * m.a_uv;
+  const T cv = -rho_v * m.b_v;
   const T qx = u * (m.b00 * px + m.b10 * py);
   const T qy = u * (m.b01 * px + m.b11 * py);
   // adjoint collision: nu - C^T nu + 1 * weq^T C^T nu  (AEDs with O = 1 weq^T)

@@ -56,6 +56,8 @@ struct FwdLaunch {
   const T* v0;
   const T* ctrl;     // control c(x)
   T* rec;            // record slot [3][plane] (u, j_vx, j_vy) or null
+  T* lag;            // second-order source: kinetics of the previous step
+                     // [2][plane], overwritten with this step's; null = first order
 };
 
 template <typename T>
@@ -79,6 +81,9 @@ struct AdjLaunch {
   T* adj_v0;
   int first;         // 1: step N-1 (reads seeds, initialises g)
   int last;          // 1: step 0 and adj_u0/adj_v0 requested
+  T* mu;             // second-order source: adjoint of the stored kinetics
+                     // [2][plane]; null = first order
+  int step0;         // 1: step 0 (used with mu)
 };
 
 template <typename T>
@@ -116,6 +121,8 @@ struct TlmLaunch {
   const T* dv0;
   const T* dc;       // control perturbation (null = 0)
   const T* rec;      // record slot of step n (forward u, j_vx, j_vy)
+  T* dlag;           // second-order source: perturbed kinetics of the
+                     // previous step [2][plane]; null = first order
 };
 
 template <typename T>

@@ -68,14 +68,14 @@ __global__ void build_link_kernel(Geometry g, int periodic,
     wflag[size_t(y) * g.nsx + (x >> 6)] = fluid == 0ull ? 2u : (any != 0ull);
 }
 
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG>
 __global__ __launch_bounds__(kBlock) void forward_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ u0, const T* __restrict__ v0,
-    const T* __restrict__ ctrl, T* __restrict__ rec) {
+    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  forward_node<T, PERIODIC, MASKED, FIRST>(g, n, m, src, dst, u0, v0, ctrl, rec);
+  forward_node<T, PERIODIC, MASKED, FIRST, LAG>(g, n, m, src, dst, u0, v0, ctrl, rec, lag);
 }
 
 template <typename T, bool PERIODIC, bool MASKED>
@@ -87,25 +87,26 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(
   finalize_node<T, PERIODIC, MASKED>(g, n, src, state, uN, vN);
 }
 
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, bool LAG>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ seed_u, const T* __restrict__ seed_v,
     const T* __restrict__ rec, double* __restrict__ gacc,
-    T* __restrict__ adj_u0, T* __restrict__ adj_v0) {
+    T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu, int step0) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  adjoint_node<T, PERIODIC, MASKED, FIRST, LAST>(g, n, m, src, dst, seed_u, seed_v, rec, gacc, adj_u0, adj_v0);
+  adjoint_node<T, PERIODIC, MASKED, FIRST, LAST, LAG>(g, n, m, src, dst, seed_u, seed_v, rec,
+                                                      gacc, adj_u0, adj_v0, mu, step0 != 0);
 }
 
 // Tangent-linear step of step n: pulls the perturbation (or, for n = 0,
 // the equilibrium of (du0, dv0)), linearised collision at the recorded
 // (u, j_v) of step n, streaming stores as the forward.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG>
 __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ du0, const T* __restrict__ dv0, const T* __restrict__ dc,
-    const T* __restrict__ rec) {
+    const T* __restrict__ rec, T* __restrict__ dlag) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
   const size_t idx = n.r0 + n.x;
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
     }
   }
   const T c = dc ? dc[idx] : T(0);
-  tlm_collide_store<T, MASKED>(g, n, m, fu, fv, c, rec, dst, lm);
+  tlm_collide_store<T, MASKED, LAG>(g, n, m, fu, fv, c, rec, dst, lm, dlag, FIRST);
 }
 
 // Continuous-adjoint step: pulls the adjoint populations (or, for the first
@@ -357,10 +358,12 @@ void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
                          const FwdLaunch<T>& a, hipStream_t s) {
   const bool first = a.src == nullptr;
   const int nb = stencil_blocks(g);
-#define MRT_FWD(P, M, F)                                                     \
-  hipLaunchKernelGGL((forward_step_kernel<T, P, M, F>), dim3(nb),            \
+#define MRT_FWD2(P, M, F, LG)                                                \
+  hipLaunchKernelGGL((forward_step_kernel<T, P, M, F, LG>), dim3(nb),        \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.u0, a.v0,     \
-                     a.ctrl, a.rec)
+                     a.ctrl, a.rec, a.lag)
+#define MRT_FWD(P, M, F) \
+  if (a.lag) { MRT_FWD2(P, M, F, true); } else { MRT_FWD2(P, M, F, false); }
 #define MRT_FWD_F(P, M) \
   if (first) { MRT_FWD(P, M, true); } else { MRT_FWD(P, M, false); }
   if (g.periodic) {
@@ -370,6 +373,7 @@ void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
   }
 #undef MRT_FWD_F
 #undef MRT_FWD
+#undef MRT_FWD2
 }
 
 template <typename T>
@@ -391,10 +395,13 @@ template <typename T>
 void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
                          const AdjLaunch<T>& a, hipStream_t s) {
   const int nb = stencil_blocks(g);
-#define MRT_ADJ(P, M, F, L)                                                  \
-  hipLaunchKernelGGL((adjoint_step_kernel<T, P, M, F, L>), dim3(nb),         \
+#define MRT_ADJ2(P, M, F, L, LG)                                             \
+  hipLaunchKernelGGL((adjoint_step_kernel<T, P, M, F, L, LG>), dim3(nb),     \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.seed_u,       \
-                     a.seed_v, a.rec, a.g, a.adj_u0, a.adj_v0)
+                     a.seed_v, a.rec, a.g, a.adj_u0, a.adj_v0, a.mu,         \
+                     a.step0)
+#define MRT_ADJ(P, M, F, L) \
+  if (a.mu) { MRT_ADJ2(P, M, F, L, true); } else { MRT_ADJ2(P, M, F, L, false); }
 #define MRT_ADJ_L(P, M, F) \
   if (a.last) { MRT_ADJ(P, M, F, true); } else { MRT_ADJ(P, M, F, false); }
 #define MRT_ADJ_F(P, M) \
@@ -407,6 +414,7 @@ void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
 #undef MRT_ADJ_F
 #undef MRT_ADJ_L
 #undef MRT_ADJ
+#undef MRT_ADJ2
 }
 
 template <typename T>
@@ -440,9 +448,12 @@ void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T
                      hipStream_t s) {
   const bool first = a.src == nullptr;
   const int nb = stencil_blocks(g);
-#define MRT_TLM(P, M, F)                                                     \
-  hipLaunchKernelGGL((tlm_step_kernel<T, P, M, F>), dim3(nb), dim3(kBlock),  \
-                     0, s, g, m, a.src, a.dst, a.du0, a.dv0, a.dc, a.rec)
+#define MRT_TLM2(P, M, F, LG)                                                \
+  hipLaunchKernelGGL((tlm_step_kernel<T, P, M, F, LG>), dim3(nb),            \
+                     dim3(kBlock), 0, s, g, m, a.src, a.dst, a.du0, a.dv0,   \
+                     a.dc, a.rec, a.dlag)
+#define MRT_TLM(P, M, F) \
+  if (a.dlag) { MRT_TLM2(P, M, F, true); } else { MRT_TLM2(P, M, F, false); }
 #define MRT_TLM_F(P, M) \
   if (first) { MRT_TLM(P, M, true); } else { MRT_TLM(P, M, false); }
   if (g.periodic) {
@@ -452,6 +463,7 @@ void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T
   }
 #undef MRT_TLM_F
 #undef MRT_TLM
+#undef MRT_TLM2
 }
 
 template <typename T>

@@ -42,6 +42,8 @@ def make_problem_struct(prob, dtype_code: int, pitch: int,
     p.Cchi[:] = [float(x) for x in np.asarray(prob.Cchi, dtype=np.float64).ravel()]
     p.r_u, p.a_uv, p.b_v = float(prob.r_u), float(prob.a_uv), float(prob.b_v)
     p.alpha = float(prob.alpha)
+    p.source_order = int(getattr(prob, "source_order", 1))
+    p.reserved = 0
     return p
 
 

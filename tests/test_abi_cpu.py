@@ -66,6 +66,8 @@ def test_validate_rejects_bad_grid(field, value):
     dict(sv=np.array([1, 1, 1, 1, 1, 1, 0.0])),
     dict(alpha=-1.0),
     dict(chi=math.nan),
+    dict(source_order=3),
+    dict(source_order=-1),
 ])
 def test_validate_rejects_bad_model(kw):
     from paper_1908_03876_amd import abi
@@ -89,3 +91,26 @@ def test_tape_bytes_layout():
     assert ck - fwd == 2 * state + 3 * state + 50 * 3 * plane
     with pytest.raises(abi.MrtError):
         abi.mrt_tape_bytes(_struct(nsteps=0), 0)
+
+
+def test_tape_bytes_layout_second_order_source():
+    """The second-order source adds the previous step's kinetics (2 planes)
+    to the forward state, to the adjoint/tangent state and to every
+    checkpoint."""
+    from paper_1908_03876_amd import abi
+    s1 = _struct(nsteps=200)
+    s2 = _struct(nsteps=200, source_order=2)
+    abi.mrt_validate(s2)
+    lag = 2 * 64 * 64 * 4
+    assert abi.mrt_tape_bytes(s2, 0) - abi.mrt_tape_bytes(s1, 0) == lag
+    assert abi.mrt_tape_bytes(s2, 200) - abi.mrt_tape_bytes(s1, 200) == 2 * lag
+    assert abi.mrt_tape_bytes(s2, 50) - abi.mrt_tape_bytes(s1, 50) == 2 * lag + 3 * lag
+
+
+def test_validate_rejects_reserved_problem_field():
+    from paper_1908_03876_amd import abi
+    s = _struct()
+    s.reserved = 1
+    with pytest.raises(abi.MrtError) as e:
+        abi.mrt_validate(s)
+    assert e.value.code == abi.MRT_EINVAL
