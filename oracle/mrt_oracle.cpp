@@ -142,7 +142,11 @@ struct OrcProblem {
   double r_u, a_uv, b_v;
   double alpha;
   int control_on_u;  // 0: control enters Phi_v (default); 1: enters Phi_u
-  int source_order;  // 1: tau F_i; 2: plus (tau^2/2) dF_i/dt (kappa_t = 1, kappa_x = 0)
+  // Source term of (eq:LBEG): 0 or 1: tau F_i; 2: plus (tau^2/2) dF_i/dt
+  // by the explicit characteristic difference (kappa_t = 1, kappa_x = 0);
+  // 3: plus (tau^2/2)(d/dt + e_i.grad) F_i by the implicit characteristic
+  // difference (kappa_t = kappa_x = 1).
+  int source_term;
 };
 
 }  // extern "C"
@@ -239,9 +243,13 @@ inline int neighbour(const OrcProblem& p, int x, int y, int i, int sign) {
 // (tau^2/2) dF_i/dt is taken by the explicit characteristic difference
 // (F_i(t) - F_i(t - tau)) / tau of the Remark after (eq:LBEG).  Fnow (if
 // given) receives Phi_u, Phi_v of this step.
+// With `implicit` (kappa_t = kappa_x = 1, implicit characteristic
+// difference (F_i(x + e_i tau, t + tau) - F_i(x, t)) / tau), only the
+// explicit half -(tau/2) F_i(x, t) is added here; the other half belongs to
+// the arrival node and is added by implicit_node after streaming.
 template <typename T>
 void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
-             const T* Fprev = nullptr, T* Fnow = nullptr) {
+             const T* Fprev = nullptr, T* Fnow = nullptr, bool implicit = false) {
   const T* fu = phi;
   const T* fv = phi + Q;
   // (UGS): macroscopic values; first moment of v.
@@ -310,6 +318,7 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
       T PhiI = WGT[i] * Phi;
       T second = 0;
       if (Fprev) second = (TAU * TAU / 2.0) * (PhiI - WGT[i] * Fprev[s]) / TAU;
+      if (implicit) second = -(TAU * TAU / 2.0) * PhiI / TAU;
       out[s * Q + i] = back + TAU * S + TAU * PhiI + second;
     }
   }
@@ -356,10 +365,48 @@ void stream_push(const OrcProblem& p, const Ops& ops, const T* post, T* fnew) {
     }
 }
 
+// Implicit half of the characteristic difference at a fluid node y: the
+// populations R_i streamed into y give phi_i = R_i + (tau/2) w_i Phi(Theta)
+// with Theta = sum_i phi_i, so Theta - (tau/2) Phi(Theta) = sum_i R_i, a
+// 2 x 2 nonlinear system (Phi_u depends on u, Phi_v on u and v) solved by
+// Newton's method; then phi_i follows.  ph: [2][Q], R in, phi out.
+template <typename T>
+void implicit_node(const OrcProblem& p, T* ph, T c) {
+  const double h = TAU / 2.0;
+  const T cu = p.control_on_u ? c : T(0), cv = p.control_on_u ? T(0) : c;
+  T Ru = 0, Rv = 0;
+  for (int i = 0; i < Q; ++i) {
+    Ru += ph[i];
+    Rv += ph[Q + i];
+  }
+  T u = Ru, v = Rv;
+  int extra = 0;
+  for (int it = 0; it < 100 && extra < 3; ++it) {
+    const T fu = u - Ru - h * (p.r_u * u * (1.0 - u) + cu);
+    const T fv = v - Rv - h * (p.a_uv * u - p.b_v * v + cv);
+    // Jacobian [[1 - h r (1 - 2u), 0], [-h a, 1 + h b]]
+    const T j11 = 1.0 - h * p.r_u * (1.0 - 2.0 * u);
+    const T j22 = 1.0 + h * p.b_v;
+    const T du = fu / j11;
+    const T dv = (fv + h * p.a_uv * du) / j22;
+    u -= du;
+    v -= dv;
+    if (std::abs(du) <= 1e-15 * (1.0 + std::abs(u)) &&
+        std::abs(dv) <= 1e-15 * (1.0 + std::abs(v)))
+      ++extra;  // converged; a few more iterations settle the last bits
+  }
+  const T Phi_u = p.r_u * u * (1.0 - u) + cu;
+  const T Phi_v = p.a_uv * u - p.b_v * v + cv;
+  for (int i = 0; i < Q; ++i) {
+    ph[i] += h * WGT[i] * Phi_u;
+    ph[Q + i] += h * WGT[i] * Phi_v;
+  }
+}
+
 // One step: collide every fluid node, then push-stream along e_i with
 // halfway bounce-back (eq:LBE): phi_i(x + e_i, t+1) = phi*_i(x), or
 // phi_opp(i)(x, t+1) = phi*_i(x) when x + e_i is solid.
-// With source_order 2, F [2][ncell] holds Phi_u, Phi_v of the previous
+// With source_term 2, F [2][ncell] holds Phi_u, Phi_v of the previous
 // step on entry and those of this step on exit; at the first step (first =
 // true) there is no previous value and the difference term is taken as
 // zero (F_i(-tau) = F_i(0)).
@@ -367,7 +414,8 @@ template <typename T>
 void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
           T* post, T* fnew, T* F = nullptr, bool first = true) {
   const int nc = p.nx * p.ny;
-  const bool second = p.source_order == 2 && F != nullptr;
+  const bool second = p.source_term == 2 && F != nullptr;
+  const bool implicit = p.source_term == 3;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p.ny; ++y)
     for (int x = 0; x < p.nx; ++x) {
@@ -384,7 +432,7 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
         prev[1] = F[nc + cell];
       }
       collide(p, ops, loc, ctrl ? ctrl[cell] : T(0), out,
-              second && !first ? prev : nullptr, second ? now : nullptr);
+              second && !first ? prev : nullptr, second ? now : nullptr, implicit);
       if (second) {
         F[cell] = now[0];
         F[nc + cell] = now[1];
@@ -392,6 +440,16 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
       for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = out[k];
     }
   stream_push(p, ops, post, fnew);
+  if (implicit) {
+#pragma omp parallel for schedule(static)
+    for (int cell = 0; cell < nc; ++cell) {
+      if (p.solid && p.solid[cell]) continue;
+      T ph[2 * Q];
+      for (int k = 0; k < 2 * Q; ++k) ph[k] = fnew[k * nc + cell];
+      implicit_node(p, ph, ctrl ? ctrl[cell] : T(0));
+      for (int k = 0; k < 2 * Q; ++k) fnew[k * nc + cell] = ph[k];
+    }
+  }
 }
 
 // ------------------------------------------------- continuous adjoint
@@ -474,7 +532,7 @@ void cadj_collide(const OrcProblem& p, const Ops& ops, const double* fw, const d
 // column = input (s',j)), assembled from the partial derivatives of each
 // term of (S) and (PhiS).
 void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
-                     double* dR, bool with_phi = true) {
+                     double* dR, double phi_scale = 1.0) {
   const double* fu = phi;
   const double* fv = phi + Q;
   double u = 0, jx = 0, jy = 0;
@@ -510,12 +568,11 @@ void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
       double dS = wi * u * (ex * (Au[0] * dgx + Au[1] * dgy) +
                             ey * (Au[2] * dgx + Au[3] * dgy)) / CS2;
       dR[(0 * Q + i) * N2 + (1 * Q + j)] += TAU * dS;
-      if (!with_phi) continue;
       // Phi_u = r_u u (1-u): dPhi_u,i/dphi_u,j = w_i r_u (1 - 2u)
-      dR[(0 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.r_u * (1.0 - 2.0 * u);
+      dR[(0 * Q + i) * N2 + (0 * Q + j)] += phi_scale * TAU * wi * p.r_u * (1.0 - 2.0 * u);
       // Phi_v = a u - b v + c
-      dR[(1 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.a_uv;
-      dR[(1 * Q + i) * N2 + (1 * Q + j)] += TAU * wi * (-p.b_v);
+      dR[(1 * Q + i) * N2 + (0 * Q + j)] += phi_scale * TAU * wi * p.a_uv;
+      dR[(1 * Q + i) * N2 + (1 * Q + j)] += phi_scale * TAU * wi * (-p.b_v);
     }
   }
 }
@@ -534,9 +591,9 @@ void relaxation_jacobian(const SpeciesOps& so, double* Jr) {
 // Full local Jacobian of the collision map: block-diagonal relaxation part
 // plus the source part.
 void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
-                    double* Jac, bool with_phi = true) {
+                    double* Jac, double phi_scale = 1.0) {
   const int N2 = 2 * Q;
-  source_jacobian(p, ops, phi, Jac, with_phi);
+  source_jacobian(p, ops, phi, Jac, phi_scale);
   for (int s = 0; s < 2; ++s) {
     double Jr[Q * Q];
     relaxation_jacobian(s == 0 ? ops.u : ops.v, Jr);
@@ -551,14 +608,15 @@ void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
 //   Lambda* (nu - psi_eq) = Lambda* nu - O Lambda* nu,
 //   R~_i = sum_k nu_k dR_k/dphi_i  (R = tau S + tau Phi over both species).
 //
-// With rho given (source_order 2), the kinetics part of R is left out of
+// With rho given (source_term 2), the kinetics part of R is left out of
 // dR and enters as sum_s rho_s dPhi_s/dphi_i instead, rho_s being the
 // adjoint of the node's Phi_s of this step.
 void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
-                   const double* nu, double* lam, const double* rho = nullptr) {
+                   const double* nu, double* lam, const double* rho = nullptr,
+                   double phi_scale = 1.0) {
   const int N2 = 2 * Q;
   double dR[N2 * N2];
-  source_jacobian(p, ops, phi, dR, rho == nullptr);
+  source_jacobian(p, ops, phi, dR, rho == nullptr ? phi_scale : 0.0);
   double dphi[2] = {0.0, 0.0};  // sum_s rho_s dPhi_s / dTheta_{s'}
   if (rho) {
     double u = 0.0;
@@ -581,6 +639,53 @@ void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
       for (int k = 0; k < N2; ++k) Rt += nu[k] * dR[k * N2 + (s * Q + i)];
       lam[s * Q + i] = n[i] - (Ln[i] - OLn) + Rt + dphi[s];
     }
+  }
+}
+
+// Transpose of implicit_node at a node whose solved state is ph (the
+// arrival populations of the step): with lam the adjoint of the output
+// populations, sigma_s = w . lam_s, J = dPhi/dTheta and
+// M = I - (tau/2) J (the Jacobian of the node equation), the adjoint of the
+// streamed sum is Sbar = M^-T (tau/2) J^T sigma and lam_s,i += Sbar_s.
+// The control enters Phi directly and through Theta; its gradient
+// contribution is (tau/2)(sigma + Sbar) of the controlled species.
+void implicit_node_adjoint(const OrcProblem& p, const double* ph, double* lam, double* gc) {
+  const double h = TAU / 2.0;
+  double u = 0.0, su = 0.0, sv = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    u += ph[i];
+    su += WGT[i] * lam[i];
+    sv += WGT[i] * lam[Q + i];
+  }
+  const double tu = h * (su * p.r_u * (1.0 - 2.0 * u) + sv * p.a_uv);
+  const double tv = h * (-p.b_v * sv);
+  const double Sv = tv / (1.0 + h * p.b_v);
+  const double Su = (tu + h * p.a_uv * Sv) / (1.0 - h * p.r_u * (1.0 - 2.0 * u));
+  for (int i = 0; i < Q; ++i) {
+    lam[i] += Su;
+    lam[Q + i] += Sv;
+  }
+  *gc = p.control_on_u ? h * (su + Su) : h * (sv + Sv);
+}
+
+// Tangent of implicit_node: d (in: the perturbation of the streamed
+// populations, out: of the solved ones) at a node whose solved state is ph.
+void implicit_node_tangent(const OrcProblem& p, const double* ph, double dc, double* d) {
+  const double h = TAU / 2.0;
+  double u = 0.0, dRu = 0.0, dRv = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    u += ph[i];
+    dRu += d[i];
+    dRv += d[Q + i];
+  }
+  const double dcu = p.control_on_u ? dc : 0.0, dcv = p.control_on_u ? 0.0 : dc;
+  const double du = (dRu + h * dcu) / (1.0 - h * p.r_u * (1.0 - 2.0 * u));
+  const double dv = (dRv + h * dcv + h * p.a_uv * du) / (1.0 + h * p.b_v);
+  const double dPu = p.r_u * (1.0 - 2.0 * u) * du + dcu;
+  const double dPv = p.a_uv * du - p.b_v * dv + dcv;
+  for (int i = 0; i < Q; ++i) {
+    d[i] += h * WGT[i] * dPu;
+    d[Q + i] += h * WGT[i] * dPv;
   }
 }
 
@@ -736,13 +841,31 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   }
   for (size_t cell = 0; cell < nc; ++cell) g[cell] = 0.0;
   const int cs = p->control_on_u ? 0 : 1;
-  // source_order 2: the state of the scheme also holds F(t - tau), i.e.
+  // source_term 2: the state of the scheme also holds F(t - tau), i.e.
   // Phi_u, Phi_v of the previous step; mu [2][ncell] is its adjoint (the
   // adjoint of the Phi stored by step n, read by step n + 1; 0 after the
   // last step, which nothing reads).
-  const bool so2 = p->source_order == 2;
+  const bool so2 = p->source_term == 2;
   std::vector<double> mu(so2 ? 2 * nc : 0, 0.0);
+  // source_term 3: each step ends with the implicit node solve at the
+  // arrival nodes, whose transpose comes first
+  const bool implicit = p->source_term == 3;
   for (int n = nsteps - 1; n >= 0; --n) {
+    if (implicit) {
+      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * 2 * Q * nc : f.data();
+#pragma omp parallel for schedule(static)
+      for (int cell = 0; cell < int(nc); ++cell) {
+        if (p->solid && p->solid[cell]) continue;
+        double ph[2 * Q], lm[2 * Q], gc;
+        for (int k = 0; k < 2 * Q; ++k) {
+          ph[k] = fa[k * nc + cell];
+          lm[k] = lam[k * nc + cell];
+        }
+        implicit_node_adjoint(*p, ph, lm, &gc);
+        for (int k = 0; k < 2 * Q; ++k) lam[k * nc + cell] = lm[k];
+        g[cell] += gc;
+      }
+    }
     // Adjoint streaming along -e_i (transpose of push + bounce-back):
     // nu_i(x) = lambda_i(x + e_i) if x + e_i is fluid, else lambda_opp(i)(x).
 #pragma omp parallel for schedule(static)
@@ -770,11 +893,13 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
           nl[k] = nu[k * nc + cell];
         }
         if (!so2) {
-          // (gradientLattice): dF_Theta,i/dc = tau w_i.
+          // (gradientLattice): dF_Theta,i/dc = tau w_i (tau/2 for the
+          // explicit half of the implicit characteristic difference).
+          const double kphi = implicit ? 0.5 : 1.0;
           double gc = 0.0;
-          for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * TAU * WGT[i];
+          for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * kphi * TAU * WGT[i];
           g[cell] += gc;
-          local_adjoint(*p, ops, loc, nl, out);
+          local_adjoint(*p, ops, loc, nl, out, nullptr, kphi);
         } else {
           // out_i = ... + tau w_i Phi + (tau/2) w_i (Phi - F_prev) (n >= 1):
           // d out_i / d Phi = (tau + tau/2) w_i, d out_i / d F_prev =
@@ -827,10 +952,11 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
   }
   const int cs = p->control_on_u ? 0 : 1;
   const int N2 = 2 * Q;
-  // source_order 2: dF [2][ncell] is the perturbation of the stored Phi of
+  // source_term 2: dF [2][ncell] is the perturbation of the stored Phi of
   // the previous step.
-  const bool so2 = p->source_order == 2;
+  const bool so2 = p->source_term == 2;
   std::vector<double> dF(so2 ? 2 * nc : 0, 0.0);
+  const bool implicit = p->source_term == 3;
   for (int n = 0; n < nsteps; ++n) {
     const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
 #pragma omp parallel for schedule(static)
@@ -843,16 +969,17 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
         }
         double loc[N2], Jac[N2 * N2];
         for (int k = 0; k < N2; ++k) loc[k] = fn[k * nc + cell];
-        local_jacobian(*p, ops, loc, Jac, !so2);
+        local_jacobian(*p, ops, loc, Jac, so2 ? 0.0 : (implicit ? 0.5 : 1.0));
         for (int r = 0; r < N2; ++r) {
           double acc = 0.0;
           for (int k = 0; k < N2; ++k) acc += Jac[r * N2 + k] * d[k * nc + cell];
           dpost[r * nc + cell] = acc;
         }
         if (!so2) {
+          const double kphi = implicit ? 0.5 : 1.0;
           if (dc)
             for (int i = 0; i < Q; ++i)
-              dpost[(cs * Q + i) * nc + cell] += TAU * WGT[i] * dc[cell];
+              dpost[(cs * Q + i) * nc + cell] += kphi * TAU * WGT[i] * dc[cell];
         } else {
           // perturbation of Phi_u, Phi_v (with the control) of this step
           double u = 0.0, du = 0.0, dv = 0.0;
@@ -890,6 +1017,19 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
               dnew[(s * Q + ops.opp[i]) * nc + cell] = val;
           }
       }
+    if (implicit) {
+      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * 2 * Q * nc : f.data();
+      for (size_t cell = 0; cell < nc; ++cell) {
+        if (p->solid && p->solid[cell]) continue;
+        double ph[N2], dl[N2];
+        for (int k = 0; k < N2; ++k) {
+          ph[k] = fa[k * nc + cell];
+          dl[k] = dnew[k * nc + cell];
+        }
+        implicit_node_tangent(*p, ph, dc ? dc[cell] : 0.0, dl);
+        for (int k = 0; k < N2; ++k) dnew[k * nc + cell] = dl[k];
+      }
+    }
     d.swap(dnew);
   }
   for (size_t cell = 0; cell < nc; ++cell) {

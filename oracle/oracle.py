@@ -44,7 +44,7 @@ class OrcProblem(ctypes.Structure):
                 ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 4),
                 ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
                 ("b_v", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("control_on_u", ctypes.c_int), ("source_order", ctypes.c_int)]
+                ("control_on_u", ctypes.c_int), ("source_term", ctypes.c_int)]
 
 
 _lib = None
@@ -115,7 +115,7 @@ class _Prob:
         s.r_u, s.a_uv, s.b_v = float(p.r_u), float(p.a_uv), float(p.b_v)
         s.alpha = float(p.alpha)
         s.control_on_u = 1 if control_on_u else 0
-        s.source_order = int(getattr(p, "source_order", 1))
+        s.source_term = int(getattr(p, "source_term", 1))
         self.s = s
 
     @property

@@ -49,7 +49,10 @@ class Problem:
     v0: np.ndarray = None        # [ny, nx]
     control: np.ndarray = None   # [ny, nx], initial guess of c
     u_target: np.ndarray = None  # [ny, nx]
-    source_order: int = 1        # 1: tau w_i Phi; 2: plus (tau^2/2) d/dt of it
+    source_term: int = 1        # 1: tau w_i Phi; 2: plus (tau^2/2) dF/dt by the
+                                 # explicit characteristic difference (kappa_x = 0);
+                                 # 3: plus (tau^2/2)(d/dt + e.grad) F by the
+                                 # implicit one (kappa_x = 1)
     name: str = ""
 
     @property

@@ -64,6 +64,17 @@ MUTANTS = [
      "rho[q] = kdir * sig[q] + mu[q * nc + cell];", "rho[q] = kdir * sig[q];"),
     ("second-order TLM: previous perturbation dropped",
      "(dphi[q] - dF[q * nc + cell])", "(dphi[q])"),
+    ("implicit source: sign of the arrival half",
+     "ph[Q + i] += h * WGT[i] * Phi_v;", "ph[Q + i] -= h * WGT[i] * Phi_v;"),
+    ("implicit source: departure half dropped",
+     "if (implicit) second = -(TAU * TAU / 2.0) * PhiI / TAU;", "if (implicit) second = 0;"),
+    ("implicit adjoint: coupling of the node equation dropped",
+     "const double Su = (tu + h * p.a_uv * Sv) /", "const double Su = (tu) /"),
+    ("implicit adjoint: control through the node solve dropped",
+     "*gc = p.control_on_u ? h * (su + Su) : h * (sv + Sv);",
+     "*gc = p.control_on_u ? h * (su + Su) : h * sv;"),
+    ("implicit tangent: control missing in the node solve",
+     "const double dv = (dRv + h * dcv + h * p.a_uv * du)", "const double dv = (dRv + h * p.a_uv * du)"),
 ]
 
 

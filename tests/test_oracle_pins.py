@@ -510,13 +510,13 @@ def test_continuous_adjoint_without_chemotaxis_is_penalty_only():
 # ------------------------------------- second-order source term (eq:LBEG)
 
 def _single_site(r_u=0.7, a_uv=0.3, b_v=0.45, c=0.15, u0=0.3, v0=0.2, nsteps=7,
-                 source_order=2):
+                 source_term=2):
     one = np.ones((1, 1))
     return I.Problem(nx=1, ny=1, nsteps=nsteps, periodic=True, solid=None,
                      Du=np.array([[0.3, 0.1], [0.1, 0.2]]), Dv=0.5 * np.eye(2), chi=0.8,
                      Cchi=np.eye(2), r_u=r_u, a_uv=a_uv, b_v=b_v, alpha=0.01,
                      u0=u0 * one, v0=v0 * one, control=c * one, u_target=0.9 * one,
-                     source_order=source_order)
+                     source_term=source_term)
 
 
 def test_second_order_source_single_site_is_adams_bashforth():
@@ -550,17 +550,18 @@ def test_second_order_source_single_site_is_adams_bashforth():
     assert abs(g["grad"][0, 0] - ((us[-1] - 0.9) * du + 0.01 * c)) < 1e-14
 
 
-@pytest.mark.parametrize("order,ratio", [(1, 2.0), (2, 4.0)])
-def test_source_order_sets_the_time_accuracy_of_the_kinetics(order, ratio):
+@pytest.mark.parametrize("term,ratio", [(1, 2.0), (2, 4.0), (3, 4.0)])
+def test_source_term_sets_the_time_accuracy_of_the_kinetics(term, ratio):
     """The second-order term is what makes the kinetics O(tau^2) accurate
     (Chapman-Enskog balance with kappa_t = 1, Section 3.1): on one site the
     logistic u' = r u (1 - u) has the closed form
     u(t) = 1 / (1 + (1/u0 - 1) exp(-r t)); halving r tau at a fixed r t
-    divides the error at r t = 4 by about 2 (first order) or 4 (second)."""
+    divides the error at r t = 4 by about 2 (first order) or 4 (second
+    order, explicit or implicit characteristic difference)."""
     errs = []
     for r_u, n in ((0.05, 80), (0.025, 160), (0.0125, 320)):
         p = _single_site(r_u=r_u, a_uv=0.0, b_v=0.0, c=0.0, u0=0.1, nsteps=n,
-                         source_order=order)
+                         source_term=term)
         exact = 1.0 / (1.0 + 9.0 * np.exp(-4.0))
         errs.append(abs(O.forward(p)["uN"][0, 0] - exact))
     for e0, e1 in zip(errs, errs[1:]):
@@ -573,10 +574,10 @@ def test_second_order_constant_source_equals_first_order():
     first-order one, forward exactly and gradient to rounding."""
     p = I.tiny(L=8, nsteps=12, seed=6, masked=True).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
     a = O.forward(p)
-    b = O.forward(p.copy(source_order=2))
+    b = O.forward(p.copy(source_term=2))
     assert np.array_equal(a["uN"], b["uN"]) and np.array_equal(a["vN"], b["vN"])
     ga = O.cost_gradient(p)["grad"]
-    gb = O.cost_gradient(p.copy(source_order=2))["grad"]
+    gb = O.cost_gradient(p.copy(source_term=2))["grad"]
     assert np.abs(ga - gb).max() <= 1e-13 * np.abs(ga).max()
 
 
@@ -585,7 +586,7 @@ def test_second_order_gradient_complex_step(k):
     """The adjoint of the second-order scheme (the stored Phi of the
     previous step is part of the state, its adjoint carried backwards) is
     the exact derivative of J: complex step, h = 1e-20."""
-    p = _cases()[k].copy(source_order=2)
+    p = _cases()[k].copy(source_term=2)
     g = O.cost_gradient(p)["grad"]
     for seed in (1, 2):
         h = I.random_direction(p, seed)
@@ -597,7 +598,7 @@ def test_second_order_gradient_complex_step(k):
 def test_second_order_tlm_adjoint_dot_product(k):
     """Sensitivity equations of the second-order scheme against its adjoint:
     <a, du^N> + <b, dv^N> = <g, dc> + <dJ/du0, du0> + <dJ/dv0, dv0>."""
-    p = _cases()[k].copy(source_order=2)
+    p = _cases()[k].copy(source_term=2)
     rng = np.random.default_rng(30 + k)
     f = p.fluid
     a, b, dc, du0, dv0 = (rng.standard_normal((p.ny, p.nx)) * f for _ in range(5))
@@ -610,7 +611,7 @@ def test_second_order_tlm_adjoint_dot_product(k):
 
 def test_second_order_tlm_against_differences():
     """The second-order TLM against central differences of u^N and v^N."""
-    p = _cases()[1].copy(source_order=2)
+    p = _cases()[1].copy(source_term=2)
     rng = np.random.default_rng(33)
     f = p.fluid
     dc, du0 = rng.standard_normal((p.ny, p.nx)) * f, rng.standard_normal((p.ny, p.nx)) * f
@@ -618,6 +619,112 @@ def test_second_order_tlm_against_differences():
     eps = 1e-6
     rp = O.forward(p, control=p.control + eps * dc, u0=p.u0 + eps * du0)
     rm = O.forward(p, control=p.control - eps * dc, u0=p.u0 - eps * du0)
+    for d, key in ((duN, "uN"), (dvN, "vN")):
+        fd = (rp[key] - rm[key]) / (2 * eps)
+        assert np.linalg.norm(d - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+def test_implicit_source_single_site_is_the_trapezoidal_rule():
+    """(eq:LBEG) with kappa_t = kappa_x = 1 and the implicit characteristic
+    difference (F_i(x + e_i tau, t + tau) - F_i(x, t)) / tau (Remark after
+    (eq:LBEG)): on one periodic site the populations sum to
+    Theta' = Theta + (tau/2)(Phi(Theta) + Phi(Theta')), the trapezoidal
+    rule, whose implicit stage is solved here in closed form (quadratic for
+    u, linear for v); with the control on u, dJ/dc follows from its
+    tangent."""
+    import math
+    h = 0.5
+    u, v = 0.3, 0.2
+    for _ in range(7):
+        ru = u + h * 0.7 * u * (1 - u)
+        A, B = h * 0.7, 1 - h * 0.7
+        un = (-B + math.sqrt(B * B + 4 * A * ru)) / (2 * A)
+        v = (v + h * (0.3 * u - 0.45 * v + 0.15) + h * (0.3 * un + 0.15)) / (1 + h * 0.45)
+        u = un
+    p = _single_site(source_term=3)
+    r = O.forward(p)
+    assert abs(r["uN"][0, 0] - u) < 2e-15 and abs(r["vN"][0, 0] - v) < 2e-15
+    # control on u: u' = u + h (F(u) + F(u')), F = r u (1 - u) + c; tangent
+    # du' (1 - h r (1 - 2u')) = du (1 + h r (1 - 2u)) + 2 h dc
+    rr, c = 0.7, 0.15
+    us = [0.3]
+    for _ in range(7):
+        x = us[-1]
+        rhs = x + h * (rr * x * (1 - x) + c) + h * c
+        A, B = h * rr, 1 - h * rr
+        us.append((-B + math.sqrt(B * B + 4 * A * rhs)) / (2 * A))
+    du = 0.0
+    for n in range(7):
+        du = (du * (1 + h * rr * (1 - 2 * us[n])) + 2 * h) / (1 - h * rr * (1 - 2 * us[n + 1]))
+    g = O.cost_gradient(p, control_on_u=True)
+    assert abs(g["grad"][0, 0] - ((us[-1] - 0.9) * du + 0.01 * c)) < 1e-14
+
+
+def test_implicit_source_is_stable_where_the_explicit_one_is_not():
+    """At the workloads' kinetics rates (tau dPhi/dTheta = -1 at the fixed
+    point u = 1, v = (a + c)/b) the trapezoidal rule is A-stable and settles
+    on the fixed point, while the two-step explicit rule has a root at -1
+    and does not."""
+    q = dict(r_u=1.0, a_uv=1.0, b_v=1.0, c=0.15, u0=0.3, v0=0.2, nsteps=400)
+    imp = O.forward(_single_site(source_term=3, **q))
+    exp = O.forward(_single_site(source_term=2, **q))
+    assert abs(imp["uN"][0, 0] - 1.0) < 1e-12 and abs(imp["vN"][0, 0] - 1.15) < 1e-12
+    assert abs(exp["vN"][0, 0] - 1.15) > 1e-2
+
+
+def test_implicit_uniform_source_equals_first_order():
+    """A source constant in time and space (no kinetics, a uniform control)
+    makes the two halves of the characteristic difference cancel: the
+    implicit scheme equals the first-order one.  A control that varies in
+    space does not cancel (the e_i . grad part of the term), which the
+    second case checks."""
+    p = I.tiny(L=8, nsteps=12, seed=6, masked=True).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
+    p = p.copy(control=0.4 * p.fluid)
+    a = O.forward(p)
+    b = O.forward(p.copy(source_term=3))
+    for k in ("uN", "vN"):
+        assert np.abs(a[k] - b[k]).max() <= 1e-13 * np.abs(a[k]).max()
+    q = p.copy(control=p.control * (1.0 + 0.5 * np.arange(p.nx)[None, :] / p.nx))
+    a = O.forward(q)
+    b = O.forward(q.copy(source_term=3))
+    assert np.abs(a["vN"] - b["vN"]).max() > 1e-4
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_implicit_gradient_complex_step(k):
+    """The adjoint of the implicit scheme (transpose of the node solve, then
+    of streaming and of the explicit half) against the complex-step
+    derivative (the node solve runs in complex arithmetic)."""
+    p = _cases()[k].copy(source_term=3)
+    g = O.cost_gradient(p)["grad"]
+    for seed in (1, 2):
+        h = I.random_direction(p, seed)
+        _, dj = O.cost_complex_step(p, h)
+        assert abs((g * h).sum() - dj) <= 1e-12 * max(abs(dj), 1e-300)
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_implicit_tlm_adjoint_dot_product(k):
+    p = _cases()[k].copy(source_term=3)
+    rng = np.random.default_rng(40 + k)
+    f = p.fluid
+    a, b, dc, du0, dv0 = (rng.standard_normal((p.ny, p.nx)) * f for _ in range(5))
+    duN, dvN = O.tlm(p, dc=dc, du0=du0, dv0=dv0)
+    g, gu0, gv0 = O.adjoint(p, a, b)
+    lhs = (a * duN).sum() + (b * dvN).sum()
+    rhs = (g * dc).sum() + (gu0 * du0).sum() + (gv0 * dv0).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_implicit_tlm_against_differences():
+    p = _cases()[1].copy(source_term=3)
+    rng = np.random.default_rng(43)
+    f = p.fluid
+    dc, dv0 = rng.standard_normal((p.ny, p.nx)) * f, rng.standard_normal((p.ny, p.nx)) * f
+    duN, dvN = O.tlm(p, dc=dc, dv0=dv0)
+    eps = 1e-6
+    rp = O.forward(p, control=p.control + eps * dc, v0=p.v0 + eps * dv0)
+    rm = O.forward(p, control=p.control - eps * dc, v0=p.v0 - eps * dv0)
     for d, key in ((duN, "uN"), (dvN, "vN")):
         fd = (rp[key] - rm[key]) / (2 * eps)
         assert np.linalg.norm(d - fd) <= 1e-7 * np.linalg.norm(fd)
