@@ -95,17 +95,38 @@ def test_source_texts_present_once():
         assert src.count(old) == 1, label
 
 
-@pytest.mark.parametrize("label,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_fails_a_pin(tmp_path, label, old, new):
-    _copy_tree(str(tmp_path))
-    path = os.path.join(str(tmp_path), "oracle", "mrt_oracle.cpp")
+def _run_mutant(base, k):
+    """Plant mutant k in a private copy under base and run the pins there;
+    returns (exit code, tail of the output)."""
+    label, old, new = MUTANTS[k]
+    d = os.path.join(base, f"m{k}")
+    os.makedirs(d)
+    _copy_tree(d)
+    path = os.path.join(d, "oracle", "mrt_oracle.cpp")
     src = open(path).read()
-    assert src.count(old) == 1
+    if src.count(old) != 1:
+        return -1, f"{label}: source text not found once"
     open(path, "w").write(src.replace(old, new))
-    env = dict(os.environ, OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "4"))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=str(tmp_path), env=env,
-                       capture_output=True, text=True, timeout=300)
-    tail = (r.stdout + r.stderr)[-400:]
+                        "tests/test_oracle_pins.py"], cwd=d, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return r.returncode, (r.stdout + r.stderr)[-400:]
+
+
+@pytest.fixture(scope="module")
+def mutant_results(tmp_path_factory):
+    """All mutants at once, several copies building and testing in
+    parallel (each is an independent compiler and pytest process)."""
+    from concurrent.futures import ThreadPoolExecutor
+    base = str(tmp_path_factory.mktemp("mutants"))
+    workers = max(1, min(8, (os.cpu_count() or 2)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda k: _run_mutant(base, k), range(len(MUTANTS))))
+
+
+@pytest.mark.parametrize("k", range(len(MUTANTS)), ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_fails_a_pin(mutant_results, k):
+    rc, tail = mutant_results[k]
     # exit code 1: tests ran and at least one failed (not a build error)
-    assert r.returncode == 1 and "failed" in tail, f"{label}: pins did not catch it\n{tail}"
+    assert rc == 1 and "failed" in tail, f"{MUTANTS[k][0]}: pins did not catch it\n{tail}"
