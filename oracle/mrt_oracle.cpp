@@ -1,5 +1,6 @@
-// Plain FP64 CPU oracle for the coupled two-species D2Q9 MRT lattice
-// Boltzmann scheme, its exact discrete adjoint (AMRT) and the cost gradient.
+// Plain FP64 CPU oracle for the coupled two- or three-species D2Q9 MRT
+// lattice Boltzmann scheme, its exact discrete adjoint (AMRT) and the cost
+// gradient.
 //
 // TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
 // baseline leg of the benchmark may load this library.  It shares no code,
@@ -29,8 +30,14 @@
 //     pre-collision first moment of v.
 //   * Reaction source (PhiS) with V = 0: Phi_Theta,i = w_i Phi_Theta,
 //     Phi_u = r_u u (1-u), Phi_v = a_uv u - b_v v + c(x) (control on v).
-//   * The second-order source term (tau^2/2)(kappa_t d/dt + ...) of (eq:LBE)
-//     is not included (first-order source reading).
+//   * Third species (optional, attraction-repulsion example (ARC)): a
+//     repulsive signal w with Phi_w = a_w u - b_w w + s_w and the second
+//     cross-diffusion of u, D_u2 = chi_w u C_w (chi_w < 0 repels), whose
+//     source A_u2 grad w joins S_u with grad w read from j_w like grad v.
+//   * The second-order source term (tau^2/2)(kappa_t d/dt + kappa_x e.grad)
+//     of (eq:LBEG): by the explicit or the implicit characteristic
+//     difference of the Remark after (eq:LBEG) (source_term 2 or 3, two
+//     species), else omitted (source_term 1).
 //   * One step = collision (MC) in moment space (MF), then streaming along
 //     e_i (eq:LBE); halfway bounce-back on solid cells and, when the lattice
 //     is not periodic, outside the domain.
@@ -51,6 +58,7 @@
 namespace {
 
 constexpr int Q = 9;
+constexpr int NSX = 3;  // at most three species
 constexpr double TAU = 1.0;
 constexpr double CS2 = 1.0 / 3.0;
 
@@ -147,6 +155,13 @@ struct OrcProblem {
   // 3: plus (tau^2/2)(d/dt + e_i.grad) F_i by the implicit characteristic
   // difference (kappa_t = kappa_x = 1).
   int source_term;
+  // Species count: 2 (u, v) or 3 (u, v, w; first-order source term only).
+  int nspecies;
+  OrcSpecies w;
+  double chi_w;      // D_u2 = chi_w u C_w
+  double Cw[4];
+  double a_w, b_w, s_w;
+  const double* w0;  // initial w [ny*nx] (NULL = 0)
 };
 
 }  // extern "C"
@@ -163,9 +178,15 @@ struct SpeciesOps {
 
 struct Ops {
   double Minv[Q * Q];
-  SpeciesOps u, v;
+  SpeciesOps u, v, w;
   int opp[Q];
 };
+
+inline int nspec(const OrcProblem& p) { return p.nspecies == 3 ? 3 : 2; }
+
+inline const SpeciesOps& sops(const Ops& ops, int s) {
+  return s == 0 ? ops.u : (s == 1 ? ops.v : ops.w);
+}
 
 void k_from_D(const OrcSpecies& s, double K[4]) {
   // K^-1 = D/(d Cs^2 tau) + I/2  (from D = d Cs^2 tau (K^-1 - I/2)).
@@ -211,8 +232,10 @@ void build_species(const OrcSpecies& s, const double* Minv, SpeciesOps& o) {
 
 bool build_ops(const OrcProblem& p, Ops& ops) {
   if (!invert(Q, &M0[0][0], ops.Minv)) return false;
+  if (p.nspecies == 3 && p.source_term > 1) return false;  // not defined here
   build_species(p.u, ops.Minv, ops.u);
   build_species(p.v, ops.Minv, ops.v);
+  build_species(p.nspecies == 3 ? p.w : p.v, ops.Minv, ops.w);
   for (int i = 0; i < Q; ++i) ops.opp[i] = opposite(i);
   return true;
 }
@@ -237,7 +260,7 @@ inline int neighbour(const OrcProblem& p, int x, int y, int i, int sign) {
 // ------------------------------------------------------------------ forward
 
 // Local collision at one fluid node (eq:LBE with (S), (PhiS), (MF), (MC)).
-// phi: pre-collision [2][Q] (species u then v); out: post-collision [2][Q].
+// phi: pre-collision [NS][Q] (species u, v, then w); out: post-collision.
 // Second-order source (eq:LBEG with kappa_t = 1, kappa_x = 0): when Fprev
 // holds Phi_u, Phi_v of the previous step at this node, the term
 // (tau^2/2) dF_i/dt is taken by the explicit characteristic difference
@@ -250,6 +273,7 @@ inline int neighbour(const OrcProblem& p, int x, int y, int i, int sign) {
 template <typename T>
 void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
              const T* Fprev = nullptr, T* Fnow = nullptr, bool implicit = false) {
+  const int NS = nspec(p);
   const T* fu = phi;
   const T* fv = phi + Q;
   // (UGS): macroscopic values; first moment of v.
@@ -275,6 +299,29 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
   A[3] = (Ku[2] * D1[1] + Ku[3] * D1[3]) / TAU;
   T ax = A[0] * gvx + A[1] * gvy;
   T ay = A[2] * gvx + A[3] * gvy;
+  // Third species: grad w from j_w, D_u2 = chi_w u C_w, A_u2 = K_u D_u2 / tau.
+  T wv = 0, Phi_w = 0;
+  if (NS == 3) {
+    const T* fw = phi + 2 * Q;
+    T kx = 0, ky = 0;
+    for (int i = 0; i < Q; ++i) {
+      wv += fw[i];
+      kx += double(EX[i]) * fw[i];
+      ky += double(EY[i]) * fw[i];
+    }
+    const double* Kw = ops.w.K;
+    T gwx = -(Kw[0] * kx + Kw[1] * ky) / (TAU * p.w.d * CS2);
+    T gwy = -(Kw[2] * kx + Kw[3] * ky) / (TAU * p.w.d * CS2);
+    T D2[4], A2[4];
+    for (int k = 0; k < 4; ++k) D2[k] = p.chi_w * u * p.Cw[k];
+    A2[0] = (Ku[0] * D2[0] + Ku[1] * D2[2]) / TAU;
+    A2[1] = (Ku[0] * D2[1] + Ku[1] * D2[3]) / TAU;
+    A2[2] = (Ku[2] * D2[0] + Ku[3] * D2[2]) / TAU;
+    A2[3] = (Ku[2] * D2[1] + Ku[3] * D2[3]) / TAU;
+    ax += A2[0] * gwx + A2[1] * gwy;
+    ay += A2[2] * gwx + A2[3] * gwy;
+    Phi_w = p.a_w * u - p.b_w * wv + p.s_w;
+  }
   // Kinetics.
   T Phi_u = p.r_u * u * (1.0 - u);
   T Phi_v = p.a_uv * u - p.b_v * v;
@@ -286,11 +333,11 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
     Fnow[0] = Phi_u;
     Fnow[1] = Phi_v;
   }
-  for (int s = 0; s < 2; ++s) {
-    const SpeciesOps& so = s == 0 ? ops.u : ops.v;
-    const T* f = s == 0 ? fu : fv;
-    T theta = s == 0 ? u : v;
-    T Phi = s == 0 ? Phi_u : Phi_v;
+  for (int s = 0; s < NS; ++s) {
+    const SpeciesOps& so = sops(ops, s);
+    const T* f = phi + s * Q;
+    T theta = s == 0 ? u : (s == 1 ? v : wv);
+    T Phi = s == 0 ? Phi_u : (s == 1 ? Phi_v : Phi_w);
     // (MF): m = M F, m_eq = M F_eq.
     T feq[Q], m[Q], meq[Q], mcol[Q];
     for (int i = 0; i < Q; ++i) feq[i] = so.weq[i] * theta;
@@ -317,7 +364,7 @@ void collide(const OrcProblem& p, const Ops& ops, const T* phi, T c, T* out,
       // (PhiS) with V = 0.
       T PhiI = WGT[i] * Phi;
       T second = 0;
-      if (Fprev) second = (TAU * TAU / 2.0) * (PhiI - WGT[i] * Fprev[s]) / TAU;
+      if (Fprev && s < 2) second = (TAU * TAU / 2.0) * (PhiI - WGT[i] * Fprev[s]) / TAU;
       if (implicit) second = -(TAU * TAU / 2.0) * PhiI / TAU;
       out[s * Q + i] = back + TAU * S + TAU * PhiI + second;
     }
@@ -334,6 +381,9 @@ void init_equilibrium(const OrcProblem& p, const Ops& ops, const T* u0,
     for (int i = 0; i < Q; ++i) {
       f[(0 * Q + i) * nc + cell] = sol ? T(0) : ops.u.weq[i] * u0[cell];
       f[(1 * Q + i) * nc + cell] = sol ? T(0) : ops.v.weq[i] * v0[cell];
+      if (nspec(p) == 3)
+        f[(2 * Q + i) * nc + cell] =
+            sol || !p.w0 ? T(0) : T(ops.w.weq[i] * p.w0[cell]);
     }
   }
 }
@@ -344,13 +394,14 @@ void init_equilibrium(const OrcProblem& p, const Ops& ops, const T* u0,
 template <typename T>
 void stream_push(const OrcProblem& p, const Ops& ops, const T* post, T* fnew) {
   const int nc = p.nx * p.ny;
-  for (int k = 0; k < 2 * Q * nc; ++k) fnew[k] = T(0);
+  const int NS = nspec(p);
+  for (int k = 0; k < NS * Q * nc; ++k) fnew[k] = T(0);
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p.ny; ++y)
     for (int x = 0; x < p.nx; ++x) {
       int cell = y * p.nx + x;
       if (p.solid && p.solid[cell]) continue;
-      for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < NS; ++s)
         for (int i = 0; i < Q; ++i) {
           // Streaming into neighbours would race between rows under OpenMP
           // only if two sources targeted one slot; each (target, i) has a
@@ -414,6 +465,7 @@ template <typename T>
 void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
           T* post, T* fnew, T* F = nullptr, bool first = true) {
   const int nc = p.nx * p.ny;
+  const int NQ = nspec(p) * Q;
   const bool second = p.source_term == 2 && F != nullptr;
   const bool implicit = p.source_term == 3;
 #pragma omp parallel for schedule(static)
@@ -421,11 +473,11 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
     for (int x = 0; x < p.nx; ++x) {
       int cell = y * p.nx + x;
       if (p.solid && p.solid[cell]) {
-        for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = T(0);
+        for (int k = 0; k < NQ; ++k) post[k * nc + cell] = T(0);
         continue;
       }
-      T loc[2 * Q], out[2 * Q];
-      for (int k = 0; k < 2 * Q; ++k) loc[k] = f[k * nc + cell];
+      T loc[NSX * Q], out[NSX * Q];
+      for (int k = 0; k < NQ; ++k) loc[k] = f[k * nc + cell];
       T prev[2], now[2];
       if (second) {
         prev[0] = F[cell];
@@ -437,7 +489,7 @@ void step(const OrcProblem& p, const Ops& ops, const T* f, const T* ctrl,
         F[cell] = now[0];
         F[nc + cell] = now[1];
       }
-      for (int k = 0; k < 2 * Q; ++k) post[k * nc + cell] = out[k];
+      for (int k = 0; k < NQ; ++k) post[k * nc + cell] = out[k];
     }
   stream_push(p, ops, post, fnew);
   if (implicit) {
@@ -527,8 +579,8 @@ void cadj_collide(const OrcProblem& p, const Ops& ops, const double* fw, const d
   }
 }
 
-// Jacobian of the local sources R = tau S + tau Phi of both species with
-// respect to the pre-collision node value (18 x 18, row = output (s,i),
+// Jacobian of the local sources R = tau S + tau Phi of all species with
+// respect to the pre-collision node value (NS Q x NS Q, row = output (s,i),
 // column = input (s',j)), assembled from the partial derivatives of each
 // term of (S) and (PhiS).
 void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
@@ -541,7 +593,8 @@ void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
     jx += EX[i] * fv[i];
     jy += EY[i] * fv[i];
   }
-  const int N2 = 2 * Q;
+  const int NS = nspec(p);
+  const int N2 = NS * Q;
   for (int k = 0; k < N2 * N2; ++k) dR[k] = 0.0;
   const double* Kv = ops.v.K;
   const double* Ku = ops.u.K;
@@ -553,12 +606,28 @@ void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
   Au[1] = p.chi * (Ku[0] * p.Cchi[1] + Ku[1] * p.Cchi[3]) / TAU;
   Au[2] = p.chi * (Ku[2] * p.Cchi[0] + Ku[3] * p.Cchi[2]) / TAU;
   Au[3] = p.chi * (Ku[2] * p.Cchi[1] + Ku[3] * p.Cchi[3]) / TAU;
+  // third species: A_u2 / u = K_u chi_w C_w / tau and grad w from j_w
+  double Aw[4] = {0, 0, 0, 0}, gwx = 0, gwy = 0;
+  const double* Kw = ops.w.K;
+  if (NS == 3) {
+    double kx = 0, ky = 0;
+    for (int i = 0; i < Q; ++i) {
+      kx += EX[i] * phi[2 * Q + i];
+      ky += EY[i] * phi[2 * Q + i];
+    }
+    gwx = -(Kw[0] * kx + Kw[1] * ky) / (TAU * p.w.d * CS2);
+    gwy = -(Kw[2] * kx + Kw[3] * ky) / (TAU * p.w.d * CS2);
+    Aw[0] = p.chi_w * (Ku[0] * p.Cw[0] + Ku[1] * p.Cw[2]) / TAU;
+    Aw[1] = p.chi_w * (Ku[0] * p.Cw[1] + Ku[1] * p.Cw[3]) / TAU;
+    Aw[2] = p.chi_w * (Ku[2] * p.Cw[0] + Ku[3] * p.Cw[2]) / TAU;
+    Aw[3] = p.chi_w * (Ku[2] * p.Cw[1] + Ku[3] * p.Cw[3]) / TAU;
+  }
   for (int i = 0; i < Q; ++i) {
     double wi = WGT[i];
     double ex = EX[i], ey = EY[i];
-    // dS_u,i/dphi_u,j = w_i e_i.(Au grad v)/Cs^2 (through u = sum phi_u)
-    double dSdu = wi * (ex * (Au[0] * gvx + Au[1] * gvy) +
-                        ey * (Au[2] * gvx + Au[3] * gvy)) / CS2;
+    // dS_u,i/dphi_u,j = w_i e_i.(Au grad v + Aw grad w)/Cs^2 (through u)
+    double dSdu = wi * (ex * (Au[0] * gvx + Au[1] * gvy + Aw[0] * gwx + Aw[1] * gwy) +
+                        ey * (Au[2] * gvx + Au[3] * gvy + Aw[2] * gwx + Aw[3] * gwy)) / CS2;
     for (int j = 0; j < Q; ++j) {
       dR[(0 * Q + i) * N2 + (0 * Q + j)] += TAU * dSdu;
       // dS_u,i/dphi_v,j = w_i e_i.(u Au dgradv/dphi_v,j)/Cs^2 with
@@ -573,6 +642,17 @@ void source_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
       // Phi_v = a u - b v + c
       dR[(1 * Q + i) * N2 + (0 * Q + j)] += phi_scale * TAU * wi * p.a_uv;
       dR[(1 * Q + i) * N2 + (1 * Q + j)] += phi_scale * TAU * wi * (-p.b_v);
+      if (NS == 3) {
+        // dS_u,i/dphi_w,j through grad w = -K_w j_w / (tau d_w Cs^2)
+        double hx = -(Kw[0] * EX[j] + Kw[1] * EY[j]) / (TAU * p.w.d * CS2);
+        double hy = -(Kw[2] * EX[j] + Kw[3] * EY[j]) / (TAU * p.w.d * CS2);
+        double dSw = wi * u * (ex * (Aw[0] * hx + Aw[1] * hy) +
+                               ey * (Aw[2] * hx + Aw[3] * hy)) / CS2;
+        dR[(0 * Q + i) * N2 + (2 * Q + j)] += TAU * dSw;
+        // Phi_w = a_w u - b_w w + s_w
+        dR[(2 * Q + i) * N2 + (0 * Q + j)] += TAU * wi * p.a_w;
+        dR[(2 * Q + i) * N2 + (2 * Q + j)] += TAU * wi * (-p.b_w);
+      }
     }
   }
 }
@@ -592,11 +672,12 @@ void relaxation_jacobian(const SpeciesOps& so, double* Jr) {
 // plus the source part.
 void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
                     double* Jac, double phi_scale = 1.0) {
-  const int N2 = 2 * Q;
+  const int NS = nspec(p);
+  const int N2 = NS * Q;
   source_jacobian(p, ops, phi, Jac, phi_scale);
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < NS; ++s) {
     double Jr[Q * Q];
-    relaxation_jacobian(s == 0 ? ops.u : ops.v, Jr);
+    relaxation_jacobian(sops(ops, s), Jr);
     for (int i = 0; i < Q; ++i)
       for (int j = 0; j < Q; ++j) Jac[(s * Q + i) * N2 + (s * Q + j)] += Jr[i * Q + j];
   }
@@ -614,18 +695,19 @@ void local_jacobian(const OrcProblem& p, const Ops& ops, const double* phi,
 void local_adjoint(const OrcProblem& p, const Ops& ops, const double* phi,
                    const double* nu, double* lam, const double* rho = nullptr,
                    double phi_scale = 1.0) {
-  const int N2 = 2 * Q;
-  double dR[N2 * N2];
+  const int NS = nspec(p);
+  const int N2 = NS * Q;
+  double dR[NSX * Q * NSX * Q];
   source_jacobian(p, ops, phi, dR, rho == nullptr ? phi_scale : 0.0);
-  double dphi[2] = {0.0, 0.0};  // sum_s rho_s dPhi_s / dTheta_{s'}
+  double dphi[NSX] = {0.0, 0.0, 0.0};  // sum_s rho_s dPhi_s / dTheta_{s'}
   if (rho) {
     double u = 0.0;
     for (int i = 0; i < Q; ++i) u += phi[i];
     dphi[0] = rho[0] * p.r_u * (1.0 - 2.0 * u) + rho[1] * p.a_uv;
     dphi[1] = -rho[1] * p.b_v;
   }
-  for (int s = 0; s < 2; ++s) {
-    const SpeciesOps& so = s == 0 ? ops.u : ops.v;
+  for (int s = 0; s < NS; ++s) {
+    const SpeciesOps& so = sops(ops, s);
     const double* n = nu + s * Q;
     double Ln[Q];  // Lambda* nu = C^T nu
     for (int i = 0; i < Q; ++i) {
@@ -693,14 +775,15 @@ void run_forward(const OrcProblem& p, const Ops& ops, int nsteps,
                  const double* u0, const double* v0, const double* c,
                  std::vector<double>& f, std::vector<double>* traj) {
   const size_t nc = size_t(p.nx) * p.ny;
-  f.assign(2 * Q * nc, 0.0);
-  std::vector<double> post(2 * Q * nc), fnew(2 * Q * nc);
+  const size_t NQ = size_t(nspec(p)) * Q;
+  f.assign(NQ * nc, 0.0);
+  std::vector<double> post(NQ * nc), fnew(NQ * nc);
   std::vector<double> F(2 * nc, 0.0);
   init_equilibrium(p, ops, u0, v0, f.data());
-  if (traj) traj->assign(size_t(nsteps) * 2 * Q * nc, 0.0);
+  if (traj) traj->assign(size_t(nsteps) * NQ * nc, 0.0);
   for (int n = 0; n < nsteps; ++n) {
-    if (traj) std::memcpy(traj->data() + size_t(n) * 2 * Q * nc, f.data(),
-                          sizeof(double) * 2 * Q * nc);
+    if (traj) std::memcpy(traj->data() + size_t(n) * NQ * nc, f.data(),
+                          sizeof(double) * NQ * nc);
     step(p, ops, f.data(), c, post.data(), fnew.data(), F.data(), n == 0);
     f.swap(fnew);
   }
@@ -735,7 +818,7 @@ int orc_species_ops(const OrcSpecies* s, double* K, double* Pi, double* C,
   return 0;
 }
 
-// One local collision: phi[18] pre-collision -> out[18] post-collision.
+// One local collision: phi[NS*9] pre-collision -> out[NS*9] post-collision.
 int orc_collide(const OrcProblem* p, const double* phi, double c, double* out) {
   Ops ops;
   if (!build_ops(*p, ops)) return -1;
@@ -758,17 +841,18 @@ int orc_local_adjoint(const OrcProblem* p, const double* phi, const double* nu,
   return 0;
 }
 
-// Forward solve: N steps from the equilibrium of (u0, v0).  Outputs u^N and
-// v^N (after the last streaming) and optionally the full distribution state
-// state[2][9][ny][nx] and the per-step pre-collision trajectory of u and j_v
-// (traj_u[N][ny*nx], traj_j[N][2][ny*nx]).
+// Forward solve: N steps from the equilibrium of (u0, v0) (and w0).
+// Outputs u^N and v^N (after the last streaming) and optionally the full
+// distribution state state[NS][9][ny][nx] and the per-step pre-collision
+// trajectory of u and j_v (traj_u[N][ny*nx], traj_j[N][2][ny*nx]).
 int orc_forward(const OrcProblem* p, int nsteps, const double* u0,
                 const double* v0, const double* c, double* uN, double* vN,
                 double* state, double* traj_u, double* traj_j) {
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
-  std::vector<double> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc), F(2 * nc, 0.0);
+  const size_t NQ = size_t(nspec(*p)) * Q;
+  std::vector<double> f(NQ * nc), post(NQ * nc), fnew(NQ * nc), F(2 * nc, 0.0);
   init_equilibrium(*p, ops, u0, v0, f.data());
   for (int n = 0; n < nsteps; ++n) {
     if (traj_u || traj_j)
@@ -797,7 +881,7 @@ int orc_forward(const OrcProblem* p, int nsteps, const double* u0,
     if (uN) uN[cell] = u;
     if (vN) vN[cell] = v;
   }
-  if (state) std::memcpy(state, f.data(), sizeof(double) * 2 * Q * nc);
+  if (state) std::memcpy(state, f.data(), sizeof(double) * NQ * nc);
   return 0;
 }
 
@@ -829,9 +913,11 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
+  const int NS = nspec(*p);
+  const size_t NQ = size_t(NS) * Q;
   std::vector<double> f, traj;
   run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
-  std::vector<double> lam(2 * Q * nc, 0.0), nu(2 * Q * nc, 0.0);
+  std::vector<double> lam(NQ * nc, 0.0), nu(NQ * nc, 0.0);
   for (size_t cell = 0; cell < nc; ++cell) {
     if (p->solid && p->solid[cell]) continue;
     for (int i = 0; i < Q; ++i) {
@@ -852,7 +938,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   const bool implicit = p->source_term == 3;
   for (int n = nsteps - 1; n >= 0; --n) {
     if (implicit) {
-      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * 2 * Q * nc : f.data();
+      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * NQ * nc : f.data();
 #pragma omp parallel for schedule(static)
       for (int cell = 0; cell < int(nc); ++cell) {
         if (p->solid && p->solid[cell]) continue;
@@ -873,7 +959,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
       for (int x = 0; x < p->nx; ++x) {
         int cell = y * p->nx + x;
         if (p->solid && p->solid[cell]) continue;
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < NS; ++s)
           for (int i = 0; i < Q; ++i) {
             int nb = neighbour(*p, x, y, i, +1);
             nu[(s * Q + i) * nc + cell] =
@@ -881,14 +967,14 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
                         : lam[(s * Q + ops.opp[i]) * nc + cell];
           }
       }
-    const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
+    const double* fn = traj.data() + size_t(n) * NQ * nc;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         int cell = y * p->nx + x;
         if (p->solid && p->solid[cell]) continue;
-        double loc[2 * Q], nl[2 * Q], out[2 * Q];
-        for (int k = 0; k < 2 * Q; ++k) {
+        double loc[NSX * Q], nl[NSX * Q], out[NSX * Q];
+        for (int k = 0; k < int(NQ); ++k) {
           loc[k] = fn[k * nc + cell];
           nl[k] = nu[k * nc + cell];
         }
@@ -915,7 +1001,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
           g[cell] += rho[cs];  // dPhi_cs / dc = 1
           local_adjoint(*p, ops, loc, nl, out, rho);
         }
-        for (int k = 0; k < 2 * Q; ++k) lam[k * nc + cell] = out[k];
+        for (int k = 0; k < int(NQ); ++k) lam[k * nc + cell] = out[k];
       }
   }
   // Transpose of the equilibrium initialisation phi_i^0 = weq_i Theta_0.
@@ -940,9 +1026,11 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
+  const int NS = nspec(*p);
+  const size_t NQ = size_t(NS) * Q;
   std::vector<double> f, traj;
   run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
-  std::vector<double> d(2 * Q * nc, 0.0), dpost(2 * Q * nc), dnew(2 * Q * nc);
+  std::vector<double> d(NQ * nc, 0.0), dpost(NQ * nc), dnew(NQ * nc);
   for (size_t cell = 0; cell < nc; ++cell) {
     if (p->solid && p->solid[cell]) continue;
     for (int i = 0; i < Q; ++i) {
@@ -951,14 +1039,14 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
     }
   }
   const int cs = p->control_on_u ? 0 : 1;
-  const int N2 = 2 * Q;
+  const int N2 = int(NQ);
   // source_term 2: dF [2][ncell] is the perturbation of the stored Phi of
   // the previous step.
   const bool so2 = p->source_term == 2;
   std::vector<double> dF(so2 ? 2 * nc : 0, 0.0);
   const bool implicit = p->source_term == 3;
   for (int n = 0; n < nsteps; ++n) {
-    const double* fn = traj.data() + size_t(n) * 2 * Q * nc;
+    const double* fn = traj.data() + size_t(n) * NQ * nc;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
@@ -967,7 +1055,7 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
           for (int k = 0; k < N2; ++k) dpost[k * nc + cell] = 0.0;
           continue;
         }
-        double loc[N2], Jac[N2 * N2];
+        double loc[NSX * Q], Jac[NSX * Q * NSX * Q];
         for (int k = 0; k < N2; ++k) loc[k] = fn[k * nc + cell];
         local_jacobian(*p, ops, loc, Jac, so2 ? 0.0 : (implicit ? 0.5 : 1.0));
         for (int r = 0; r < N2; ++r) {
@@ -1007,7 +1095,7 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
       for (int x = 0; x < p->nx; ++x) {
         int cell = y * p->nx + x;
         if (p->solid && p->solid[cell]) continue;
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < NS; ++s)
           for (int i = 0; i < Q; ++i) {
             int nb = neighbour(*p, x, y, i, +1);
             double val = dpost[(s * Q + i) * nc + cell];
@@ -1018,10 +1106,10 @@ int orc_tlm(const OrcProblem* p, int nsteps, const double* u0,
           }
       }
     if (implicit) {
-      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * 2 * Q * nc : f.data();
+      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * NQ * nc : f.data();
       for (size_t cell = 0; cell < nc; ++cell) {
         if (p->solid && p->solid[cell]) continue;
-        double ph[N2], dl[N2];
+        double ph[NSX * Q], dl[NSX * Q];
         for (int k = 0; k < N2; ++k) {
           ph[k] = fa[k * nc + cell];
           dl[k] = dnew[k * nc + cell];
@@ -1055,7 +1143,8 @@ int orc_cost_complex_step(const OrcProblem* p, int nsteps, const double* u0,
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
-  std::vector<cd> f(2 * Q * nc), post(2 * Q * nc), fnew(2 * Q * nc);
+  const size_t NQ = size_t(nspec(*p)) * Q;
+  std::vector<cd> f(NQ * nc), post(NQ * nc), fnew(NQ * nc);
   std::vector<cd> cu0(nc), cv0(nc), cc(nc);
   for (size_t k = 0; k < nc; ++k) {
     cu0[k] = u0[k];
@@ -1114,7 +1203,7 @@ int orc_cost_gradient(const OrcProblem* p, int nsteps, const double* u0,
 int orc_cadjoint(const OrcProblem* p, int nsteps, const double* u0, const double* v0,
                  const double* c, const double* seed_u, double* g) {
   Ops ops;
-  if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  if (!build_ops(*p, ops) || nsteps < 0 || nspec(*p) != 2) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
   std::vector<double> f, traj;
   run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);

@@ -44,7 +44,11 @@ class OrcProblem(ctypes.Structure):
                 ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 4),
                 ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
                 ("b_v", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("control_on_u", ctypes.c_int), ("source_term", ctypes.c_int)]
+                ("control_on_u", ctypes.c_int), ("source_term", ctypes.c_int),
+                ("nspecies", ctypes.c_int), ("w", OrcSpecies),
+                ("chi_w", ctypes.c_double), ("Cw", ctypes.c_double * 4),
+                ("a_w", ctypes.c_double), ("b_w", ctypes.c_double),
+                ("s_w", ctypes.c_double), ("w0", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -116,6 +120,16 @@ class _Prob:
         s.alpha = float(p.alpha)
         s.control_on_u = 1 if control_on_u else 0
         s.source_term = int(getattr(p, "source_term", 1))
+        s.nspecies = int(getattr(p, "nspecies", 2))
+        self.w0 = None
+        if s.nspecies == 3:
+            s.w = _species(p.Dw, p.dw, p.sw)
+            s.chi_w = float(p.chi_w)
+            s.Cw[:] = [float(x) for x in np.asarray(p.Cw).ravel()]
+            s.a_w, s.b_w, s.s_w = float(p.a_w), float(p.b_w), float(p.s_w)
+            if p.w0 is not None:
+                self.w0 = np.ascontiguousarray(p.w0, dtype=np.float64)
+                s.w0 = self.w0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.s = s
 
     @property
@@ -176,8 +190,10 @@ def forward(p, nsteps=None, control=None, u0=None, v0=None, want_state=False,
     v0 = _f64(p.v0 if v0 is None else v0)
     c = _f64(p.control if control is None else control)
     shp = (p.ny, p.nx)
+    ns = int(getattr(p, "nspecies", 2))
+    want_state = want_state or ns == 3
     uN = np.zeros(shp); vN = np.zeros(shp)
-    state = np.zeros((2, 9) + shp) if want_state else None
+    state = np.zeros((ns, 9) + shp) if want_state else None
     tu = np.zeros((n,) + shp) if want_traj else None
     tj = np.zeros((n, 2) + shp) if want_traj else None
     _check(lib().orc_forward(pr.ptr, n, _dp(u0), _dp(v0), _dp(c), _dp(uN), _dp(vN),
@@ -185,6 +201,8 @@ def forward(p, nsteps=None, control=None, u0=None, v0=None, want_state=False,
     out = {"uN": uN, "vN": vN}
     if want_state:
         out["state"] = state
+    if ns == 3:
+        out["wN"] = state[2].sum(axis=0)
     if want_traj:
         out["traj_u"], out["traj_j"] = tu, tj
     return out

@@ -49,6 +49,18 @@ class Problem:
     v0: np.ndarray = None        # [ny, nx]
     control: np.ndarray = None   # [ny, nx], initial guess of c
     u_target: np.ndarray = None  # [ny, nx]
+    # third species (attraction-repulsion example): a repulsive signal w,
+    # Phi_w = a_w u - b_w w + s_w, cross-diffusion of u D_u2 = chi_w u C_w
+    nspecies: int = 2
+    Dw: np.ndarray = None
+    dw: float = 1.0
+    sw: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(7))
+    chi_w: float = 0.0
+    Cw: np.ndarray = None
+    a_w: float = 0.0
+    b_w: float = 0.0
+    s_w: float = 0.0
+    w0: np.ndarray = None        # [ny, nx]
     source_term: int = 1        # 1: tau w_i Phi; 2: plus (tau^2/2) dF/dt by the
                                  # explicit characteristic difference (kappa_x = 0);
                                  # 3: plus (tau^2/2)(d/dt + e.grad) F by the
@@ -68,7 +80,7 @@ class Problem:
     def copy(self, **changes) -> "Problem":
         p = dataclasses.replace(self, **changes)
         for f in ("solid", "Du", "Dv", "Cchi", "su", "sv", "u0", "v0",
-                  "control", "u_target"):
+                  "control", "u_target", "Dw", "sw", "Cw", "w0"):
             val = getattr(p, f)
             if isinstance(val, np.ndarray) and f not in changes:
                 setattr(p, f, val.copy())
@@ -255,6 +267,17 @@ def with_control_bump(p: Problem, seed: int = 11, amp: float = 5.0,
 def slow_reaction(p: Problem, rate: float = 0.01) -> Problem:
     """Copy of p with slow kinetics r_u = a_uv = b_v = rate."""
     return p.copy(r_u=rate, a_uv=rate, b_v=rate)
+
+
+def with_repellent(p: Problem, seed: int = 21, chi_w: float = -0.4) -> Problem:
+    """Copy of p with a third species w, a repulsive chemical signal
+    (attraction-repulsion example): seeded SPD D_w and C_w (recipe of the
+    other tensors), chi_w < 0, Phi_w = 0.5 u - 0.8 w + 0.05, non-unit
+    relaxation rates, w0 ~ 0.2 U(0, 1) on fluid nodes."""
+    rng = np.random.default_rng(seed)
+    w0 = 0.2 * rng.uniform(0, 1, size=(p.ny, p.nx)) * p.fluid
+    return p.copy(nspecies=3, Dw=random_spd(rng), dw=1.0, sw=rng.uniform(0.8, 1.6, size=7),
+                  chi_w=chi_w, Cw=random_spd(rng), a_w=0.5, b_w=0.8, s_w=0.05, w0=w0)
 
 
 def random_direction(p: Problem, seed: int) -> np.ndarray:

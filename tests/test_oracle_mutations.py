@@ -75,6 +75,17 @@ MUTANTS = [
      "*gc = p.control_on_u ? h * (su + Su) : h * sv;"),
     ("implicit tangent: control missing in the node solve",
      "const double dv = (dRv + h * dcv + h * p.a_uv * du)", "const double dv = (dRv + h * p.a_uv * du)"),
+    ("third species: repulsion with the attraction tensor",
+     "D2[k] = p.chi_w * u * p.Cw[k];", "D2[k] = p.chi_w * u * p.Cchi[k];"),
+    ("third species: decay sign in Phi_w",
+     "Phi_w = p.a_w * u - p.b_w * wv + p.s_w;", "Phi_w = p.a_w * u + p.b_w * wv + p.s_w;"),
+    ("third species: adjoint gradient of w with K_v",
+     "double hx = -(Kw[0] * EX[j] + Kw[1] * EY[j])", "double hx = -(Kv[0] * EX[j] + Kv[1] * EY[j])"),
+    ("third species: decay dropped from the source Jacobian",
+     "dR[(2 * Q + i) * N2 + (2 * Q + j)] += TAU * wi * (-p.b_w);", ""),
+    ("third species: w not streamed",
+     "for (int s = 0; s < NS; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming",
+     "for (int s = 0; s < 2; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming"),
 ]
 
 

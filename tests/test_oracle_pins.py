@@ -728,3 +728,86 @@ def test_implicit_tlm_against_differences():
     for d, key in ((duN, "uN"), (dvN, "vN")):
         fd = (rp[key] - rm[key]) / (2 * eps)
         assert np.linalg.norm(d - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+# ------------------------- third species: attraction-repulsion, (ARC)
+
+def _three(k):
+    return I.with_repellent(_cases()[k], seed=50 + k)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_three_species_mass_conservation(masked):
+    """(TF0) for all three species with both chemotactic fluxes active and
+    no kinetics."""
+    p = _three(1 if masked else 0).copy(r_u=0.0, a_uv=0.0, b_v=0.0, a_w=0.0, b_w=0.0,
+                                        s_w=0.0, control=0.0 * _cases()[0].control)
+    f = p.fluid
+    r = O.forward(p.copy(nsteps=40))
+    for key, init in (("uN", p.u0), ("vN", p.v0), ("wN", p.w0)):
+        assert abs(r[key][f].sum() / init[f].sum() - 1) < 1e-13
+
+
+def test_three_species_single_site_closed_form():
+    """One periodic site: three decoupled kinetic recurrences."""
+    one = np.ones((1, 1))
+    p = _single_site(source_term=1).copy(nspecies=3, Dw=0.4 * np.eye(2), dw=1.0,
+                                          chi_w=-0.5, Cw=np.eye(2), a_w=0.35, b_w=0.6,
+                                          s_w=0.07, w0=0.25 * one)
+    u, v, w, c = 0.3, 0.2, 0.25, 0.15
+    for _ in range(7):
+        u, v, w = (u + 0.7 * u * (1 - u), v + 0.3 * u - 0.45 * v + c,
+                   w + 0.35 * u - 0.6 * w + 0.07)
+    r = O.forward(p)
+    assert max(abs(r["uN"][0, 0] - u), abs(r["vN"][0, 0] - v), abs(r["wN"][0, 0] - w)) < 1e-15
+
+
+def test_repellent_path_mirrors_the_attractant_path():
+    """With no attraction (chi = 0) the repellent w drives u through the
+    same lattice operations the attractant v drives it through in the
+    two-species scheme: w's tensors, rates, kinetics and initial field,
+    moved into v's places of a two-species problem (w's constant source as
+    a uniform control), give the same u^N, and v^N equal to w^N."""
+    p = _three(1).copy(chi=0.0)
+    q = _cases()[1].copy(chi=p.chi_w, Cchi=p.Cw, Dv=p.Dw, dv=p.dw, sv=p.sw, a_uv=p.a_w,
+                         b_v=p.b_w, v0=p.w0, control=p.s_w * p.fluid)
+    a = O.forward(p)
+    b = O.forward(q)
+    assert np.abs(a["uN"] - b["uN"]).max() <= 1e-14 * np.abs(b["uN"]).max()
+    assert np.abs(a["wN"] - b["vN"]).max() <= 1e-14 * np.abs(b["vN"]).max()
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_three_species_gradient_complex_step(k):
+    """The AMRT of the three-species scheme (control on v, which reaches u
+    through attraction while w repels) against the complex step."""
+    p = _three(k)
+    g = O.cost_gradient(p)["grad"]
+    for seed in (1, 2):
+        h = I.random_direction(p, seed)
+        _, dj = O.cost_complex_step(p, h)
+        assert abs((g * h).sum() - dj) <= 1e-12 * max(abs(dj), 1e-300)
+
+
+@pytest.mark.parametrize("k", range(2))
+def test_three_species_tlm_adjoint_dot_product(k):
+    p = _three(k)
+    rng = np.random.default_rng(60 + k)
+    f = p.fluid
+    a, b, dc, du0, dv0 = (rng.standard_normal((p.ny, p.nx)) * f for _ in range(5))
+    duN, dvN = O.tlm(p, dc=dc, du0=du0, dv0=dv0)
+    g, gu0, gv0 = O.adjoint(p, a, b)
+    lhs = (a * duN).sum() + (b * dvN).sum()
+    rhs = (g * dc).sum() + (gu0 * du0).sum() + (gv0 * dv0).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_three_species_tlm_against_differences():
+    p = _three(1)
+    dc = I.random_direction(p, 7)
+    duN, _ = O.tlm(p, dc=dc)
+    eps = 1e-6
+    up = O.forward(p, control=p.control + eps * dc)["uN"]
+    um = O.forward(p, control=p.control - eps * dc)["uN"]
+    fd = (up - um) / (2 * eps)
+    assert np.linalg.norm(duN - fd) <= 1e-7 * np.linalg.norm(fd)
