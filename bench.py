@@ -66,14 +66,20 @@ def read_traffic(kernel: str, L: int):
     return int(v) if v is not None else None
 
 
-def bytes_per_site(elem: int):
+def bytes_per_site(elem: int, source_term: int = 1, nspecies: int = 2):
     """Algorithmic HBM bytes per fluid node and step:
-    forward with record: 18 loads + 18 stores + control + link + 3 record
-    stores; adjoint: 18 + 18 + 3 record loads + FP64 gradient read-modify-
-    write + link."""
-    fwd = 36 * elem + elem + 2 + 3 * elem
-    adj = 36 * elem + 3 * elem + 16 + 2
-    fwd_norec = 36 * elem + elem + 2
+    forward with record: 9 NS loads + 9 NS stores + control + link + record
+    stores (u, j_v; and j_w with three species); adjoint: 9 NS + 9 NS + the
+    record loads + FP64 gradient read-modify-write + link.  The explicit
+    second-order source term adds a read and a write of two planes (the
+    previous step's kinetics, or their adjoint) to both; the implicit one
+    adds no traffic (the node solve is arithmetic)."""
+    lag = 4 * elem if source_term == 2 else 0
+    pops = 18 * nspecies * elem
+    rec = (5 if nspecies == 3 else 3) * elem
+    fwd = pops + elem + 2 + rec + lag
+    adj = pops + rec + 16 + 2 + lag
+    fwd_norec = pops + elem + 2 + lag
     return fwd, adj, fwd_norec
 
 
@@ -456,6 +462,17 @@ def main():
                          "discrete adjoint gradient; srg-kernels: surrogate "
                          "network throughput; "
                          "surrogate: CNN-assisted vs plain loop")
+    ap.add_argument("--source-term", type=int, default=1, choices=[1, 2, 3],
+                    help="masked workload: 1 first-order source term; 2 second "
+                         "order by the explicit characteristic difference (a "
+                         "two-step rule that needs slower kinetics: the kinetics "
+                         "rates are then 0.1); 3 second order by the implicit "
+                         "characteristic difference (stable at the workload's "
+                         "rates)")
+    ap.add_argument("--species", type=int, default=2, choices=[2, 3],
+                    help="masked workload: 3 adds the repulsive signal w of the "
+                         "attraction-repulsion example (seeded tensors, "
+                         "chi_w = -0.4)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times with a "
                          "plain device copy (reference for HBM byte counters)")
@@ -488,6 +505,12 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] building workload L={args.L} N={args.nsteps}")
     prob = I.masked_anisotropic(L=args.L, nsteps=args.nsteps)
+    if args.source_term == 2:
+        prob = I.slow_reaction(prob, 0.1).copy(source_term=2)
+    elif args.source_term == 3:
+        prob = prob.copy(source_term=3)
+    if args.species == 3:
+        prob = I.with_repellent(prob)
     dp = DeviceProblem(prob, dtype=torch.float32, device=dev)
     free, total = torch.cuda.mem_get_info(dev)
     if args.ckpt == "auto":
@@ -527,7 +550,7 @@ def main():
     value = n_fluid * dp.nsteps / (ms_step / 1e3) / 1e6
 
     elem = 4
-    b_fwd, b_adj, b_norec = bytes_per_site(elem)
+    b_fwd, b_adj, b_norec = bytes_per_site(elem, args.source_term, args.species)
     n_solid = dp.nx * dp.ny - n_fluid
     # per-launch algorithmic bytes (solid nodes only read their link entry)
     launch_bytes_adj = n_fluid * b_adj + 2 * n_solid
@@ -541,7 +564,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k][0])
     _, avg_ms, lbytes = kern[dom]
     achieved = lbytes / (avg_ms / 1e3) / 1e9
-    traffic = read_traffic(dom, args.L)
+    traffic = (read_traffic(dom, args.L)
+               if args.source_term == 1 and args.species == 2 else None)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "kernel": dom,
@@ -556,8 +580,16 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded disks, tensors, targets)",
         "config": {"workload": f"masked anisotropic chemotaxis control, {dp.nx}x{dp.ny} "
-                               f"D2Q9 two-species MRT, 200 disks + wall ring, N={dp.nsteps} "
-                               f"steps per solve, gradient-descent iterations",
+                               f"D2Q9 {'three' if args.species == 3 else 'two'}-species MRT, "
+                               f"200 disks + wall ring, N={dp.nsteps} "
+                               f"steps per solve, gradient-descent iterations"
+                               + {1: "", 2: ", second-order source term (explicit "
+                                           "characteristic difference), kinetics rates 0.1",
+                                  3: ", second-order source term (implicit characteristic "
+                                     "difference)"}[args.source_term]
+                               + (", three species (repulsive signal w)"
+                                  if args.species == 3 else ""),
+                   "source_term": args.source_term, "species": args.species,
                    "L": dp.nx, "nsteps": dp.nsteps, "fluid_nodes": n_fluid,
                    "tape": mode, "ckpt_every": int(info.ckpt_every),
                    "tape_gib": round(info.device_bytes / 2**30, 2),

@@ -104,8 +104,19 @@ typedef struct mrt_problem {
    * and its checkpoints).  It is a two-step (Adams-Bashforth-like) rule:
    * stable for slow kinetics, unstable when tau dPhi/dTheta reaches -1.
    * The batched engine accepts order 0 or 1 only. */
-  int32_t source_order;
-  int32_t reserved;  /* must be 0 */
+  int32_t source_term;
+  /* Species: 0 or 2 = u and v; 3 adds a repulsive chemical signal w (the
+   * attraction-repulsion example (ARC)): Phi_w = a_w u - b_w w + s_w and a
+   * second cross-diffusion of u, D_{u,2} = chi_w u C_w (chi_w < 0 repels),
+   * whose gradient is read from the first moment of w as that of v.  The
+   * state is then [3][9][ny][pitch]; the second-order source terms, the
+   * continuous adjoint and the batched engine take two species only. */
+  int32_t nspecies;
+  mrt_species w;
+  double chi_w;
+  double Cw[4];      /* row-major 2x2 shape of the repulsive tensor */
+  double a_w, b_w, s_w;
+  const void* w0;    /* device [ny][pitch] initial w, grid dtype; NULL = 0 */
 } mrt_problem;
 
 /* Reduced scalars returned by cost_gradient (host struct). */

@@ -44,7 +44,11 @@ class mrt_problem(ctypes.Structure):
                 ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 4),
                 ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
                 ("b_v", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("source_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("source_term", ctypes.c_int32), ("nspecies", ctypes.c_int32),
+                ("w", mrt_species), ("chi_w", ctypes.c_double),
+                ("Cw", ctypes.c_double * 4), ("a_w", ctypes.c_double),
+                ("b_w", ctypes.c_double), ("s_w", ctypes.c_double),
+                ("w0", ctypes.c_void_p)]
 
 
 class mrt_scalars(ctypes.Structure):

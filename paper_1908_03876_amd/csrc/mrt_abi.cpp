@@ -107,9 +107,23 @@ int validate(const mrt_problem* p) {
   if (!finite_all(sc, 8) || !std::isfinite(p->alpha))
     return fail(MRT_EINVAL, "non-finite model coefficient");
   if (p->alpha < 0.0) return fail(MRT_EINVAL, "alpha < 0");
-  if (p->source_order < 0 || p->source_order > 2)
-    return fail(MRT_EINVAL, "source_order %d: must be 0, 1 or 2", p->source_order);
-  if (p->reserved != 0) return fail(MRT_EINVAL, "problem.reserved must be 0");
+  if (p->source_term < 0 || p->source_term > 3)
+    return fail(MRT_EINVAL, "source_term %d: must be 0, 1, 2 or 3", p->source_term);
+  if (p->source_term == 3 && !(0.5 * p->r_u < 1.0 && 0.5 * p->b_v > -1.0))
+    return fail(MRT_EINVAL,
+                "implicit source term needs tau r_u / 2 < 1 and tau b_v / 2 > -1 "
+                "(a solvable node equation)");
+  if (p->nspecies != 0 && p->nspecies != 2 && p->nspecies != 3)
+    return fail(MRT_EINVAL, "nspecies %d: must be 0, 2 or 3", p->nspecies);
+  if (p->nspecies == 3) {
+    if (p->source_term > 1)
+      return fail(MRT_EINVAL, "three species take the first-order source term only");
+    rc = check_species(p->w, "w");
+    if (rc) return rc;
+    const double wc[8] = {p->chi_w, p->Cw[0], p->Cw[1], p->Cw[2], p->Cw[3],
+                          p->a_w, p->b_w, p->s_w};
+    if (!finite_all(wc, 8)) return fail(MRT_EINVAL, "non-finite coefficient of w");
+  }
   return MRT_OK;
 }
 
@@ -143,7 +157,7 @@ mrt::SpeciesCoef<T> species_coef(const mrt_species& s, bool transpose_k) {
 
 template <typename T>
 mrt::ModelCoef<T> model_coef(const mrt_problem* p) {
-  mrt::ModelCoef<T> m;
+  mrt::ModelCoef<T> m{};
   m.u = species_coef<T>(p->u, false);
   m.v = species_coef<T>(p->v, false);
   m.ut = species_coef<T>(p->u, true);
@@ -169,6 +183,30 @@ mrt::ModelCoef<T> model_coef(const mrt_problem* p) {
   m.r_u = T(p->r_u);
   m.a_uv = T(p->a_uv);
   m.b_v = T(p->b_v);
+  if (p->nspecies == 3) {
+    // A_u2 grad w = (K_u chi_w u C_w / tau) (-K_w j_w / (tau d_w Cs^2))
+    //             = u * Bw * j_w
+    double Kw[4], KW[4], Bw[4];
+    k_block(p->w, Kw);
+    KW[0] = Ku[0] * p->Cw[0] + Ku[1] * p->Cw[2];
+    KW[1] = Ku[0] * p->Cw[1] + Ku[1] * p->Cw[3];
+    KW[2] = Ku[2] * p->Cw[0] + Ku[3] * p->Cw[2];
+    KW[3] = Ku[2] * p->Cw[1] + Ku[3] * p->Cw[3];
+    const double fw = -p->chi_w / (kTau * kTau * p->w.d * kCs2);
+    Bw[0] = fw * (KW[0] * Kw[0] + KW[1] * Kw[2]);
+    Bw[1] = fw * (KW[0] * Kw[1] + KW[1] * Kw[3]);
+    Bw[2] = fw * (KW[2] * Kw[0] + KW[3] * Kw[2]);
+    Bw[3] = fw * (KW[2] * Kw[1] + KW[3] * Kw[3]);
+    m.w = species_coef<T>(p->w, false);
+    m.wt = species_coef<T>(p->w, true);
+    m.bw00 = T(Bw[0]);
+    m.bw01 = T(Bw[1]);
+    m.bw10 = T(Bw[2]);
+    m.bw11 = T(Bw[3]);
+    m.a_w = T(p->a_w);
+    m.b_w = T(p->b_w);
+    m.s_w = T(p->s_w);
+  }
   return m;
 }
 
@@ -278,7 +316,9 @@ template ModelCoef<double> model_coef<double>(const mrt_problem*);
 struct mrt_tape {
   int nx, ny, pitch, nsteps, dtype, periodic, masked, device;
   int mode, K, nseg;
-  int so2;                  // second-order source term (source_order 2)
+  int ns;                   // species: 2 or 3
+  int so2;                  // explicit second-order source term (source_term 2)
+  int impl;                 // implicit second-order source term (source_term 3)
   size_t plane, elem, state_bytes, rec_slot_bytes, total_bytes;
   void* buf[2] = {nullptr, nullptr};
   void* abuf[2] = {nullptr, nullptr};
@@ -289,6 +329,8 @@ struct mrt_tape {
   void* lag = nullptr;
   void* alag = nullptr;
   std::vector<void*> ckpt_lag;
+  // impl: adjoint seeds of the last state's sums [2][plane]
+  void* tseed = nullptr;
   void* rec = nullptr;      // record slots [K][3][plane]
   uint16_t* link = nullptr;
   uint32_t* wflag = nullptr;
@@ -311,7 +353,7 @@ size_t elem_size(int dtype) { return dtype == MRT_F64 ? 8 : 4; }
 
 struct Layout {
   int mode, K, nseg;
-  size_t plane, elem, state_bytes, rec_slot_bytes, lag_bytes, total;
+  size_t plane, elem, state_bytes, rec_slot_bytes, lag_bytes, tseed_bytes, total;
 };
 
 Layout plan(const mrt_problem* p, int ckpt_every) {
@@ -319,9 +361,11 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
   const mrt_grid& g = p->grid;
   L.plane = size_t(g.ny) * size_t(g.pitch);
   L.elem = elem_size(g.dtype);
-  L.state_bytes = 18 * L.plane * L.elem;
-  L.rec_slot_bytes = 3 * L.plane * L.elem;
-  L.lag_bytes = p->source_order == 2 ? 2 * L.plane * L.elem : 0;
+  const int ns = p->nspecies == 3 ? 3 : 2;
+  L.state_bytes = size_t(9 * ns) * L.plane * L.elem;
+  L.rec_slot_bytes = size_t(ns == 3 ? 5 : 3) * L.plane * L.elem;
+  L.lag_bytes = p->source_term == 2 ? 2 * L.plane * L.elem : 0;
+  L.tseed_bytes = p->source_term == 3 ? 2 * L.plane * L.elem : 0;
   if (ckpt_every <= 0) {
     L.mode = 0;
     L.K = g.nsteps;
@@ -342,7 +386,7 @@ Layout plan(const mrt_problem* p, int ckpt_every) {
          size_t(g.ny) * ((g.nx + 63) / 64) * sizeof(uint32_t);
   t += (size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double);
   if (L.mode > 0) {
-    t += 2 * L.state_bytes + L.lag_bytes;            // adjoint ping-pong, lag
+    t += 2 * L.state_bytes + L.lag_bytes + L.tseed_bytes;  // adjoint ping-pong, lag, seeds
     t += size_t(L.nseg - 1) * (L.state_bytes + L.lag_bytes);  // checkpoints
     t += size_t(L.K) * L.rec_slot_bytes;              // record slots
   }
@@ -358,8 +402,10 @@ int check_tape(const mrt_problem* p, const mrt_tape* t) {
       g.nsteps != t->nsteps || g.dtype != t->dtype ||
       g.periodic != t->periodic || masked != t->masked)
     return fail(MRT_ESTATE, "tape was created for another grid");
-  if ((p->source_order == 2 ? 1 : 0) != t->so2)
-    return fail(MRT_ESTATE, "tape was created for another source order");
+  if ((p->source_term == 2 ? 1 : 0) != t->so2 || (p->source_term == 3 ? 1 : 0) != t->impl)
+    return fail(MRT_ESTATE, "tape was created for another source term");
+  if ((p->nspecies == 3 ? 3 : 2) != t->ns)
+    return fail(MRT_ESTATE, "tape was created for another number of species");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
     return fail(MRT_ESTATE, "tape belongs to device %d, current is %d",
@@ -408,7 +454,7 @@ int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
                       const mrt::Geometry& g, int n0, int n1, const T* src,
                       const T* u0, const T* v0, const T* ctrl, bool record,
                       bool write_ckpt, int kind, hipStream_t s,
-                      const T** last, bool restore_lag = false) {
+                      const T** last, bool restore_lag = false, const T* w0 = nullptr) {
   SpanGuard span(kind, s);
   const int seg = n0 / t->K;
   if (t->so2 && restore_lag && n0 > 0)
@@ -421,7 +467,9 @@ int run_forward_steps(mrt_tape* t, const mrt::ModelCoef<T>& m,
     a.v0 = v0;
     a.ctrl = ctrl;
     a.rec = record ? slot<T>(t, n - seg * t->K) : nullptr;
+    a.variant = t->ns == 3 ? 4 : (t->so2 ? 2 : (t->impl ? 3 : 1));
     a.lag = t->so2 ? static_cast<T*>(t->lag) : nullptr;
+    a.w0 = w0;
     T* dst = static_cast<T*>(t->buf[n & 1]);
     const bool closes = write_ckpt && t->mode == 2 && (n + 1) % t->K == 0 && n + 1 < t->nsteps;
     if (closes) dst = static_cast<T*>(t->ckpt[(n + 1) / t->K]);
@@ -456,18 +504,19 @@ int forward_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
   int rc;
   // segments before the last: no record; the last one records the tape
   const int rec_start = adj ? last_seg * t->K : N;
+  const T* tw0 = static_cast<const T*>(p->nspecies == 3 ? p->w0 : nullptr);
   if (rec_start > 0) {
     rc = run_forward_steps<T>(t, m, g, 0, rec_start, nullptr, tu0, tv0, tc,
-                              false, true, 0, s, &cur);
+                              false, true, 0, s, &cur, false, tw0);
     if (rc) return rc;
   }
   if (rec_start < N) {
     rc = run_forward_steps<T>(t, m, g, rec_start, N, cur, tu0, tv0, tc, true,
-                              true, 0, s, &cur);
+                              true, 0, s, &cur, false, tw0);
     if (rc) return rc;
   }
   mrt::launch_finalize<T>(g, cur, static_cast<T*>(state), static_cast<T*>(uN),
-                          static_cast<T*>(vN), s);
+                          static_cast<T*>(vN), s, t->impl ? &m : nullptr, tc, t->ns == 3);
   rc = last_launch_error();
   if (rc) return rc;
   t->fwd_done = true;
@@ -500,9 +549,25 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
       const T* dummy = nullptr;
       t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true,
-                                    false, 2, s, &dummy, true);
+                                    false, 2, s, &dummy, true,
+                                    static_cast<const T*>(p->nspecies == 3 ? p->w0 : nullptr));
       if (rc) return rc;
       t->rec_seg = seg;
+    }
+    const T* su = static_cast<const T*>(seed_u);
+    const T* sv = static_cast<const T*>(seed_v);
+    if (t->impl && seg == t->nseg - 1) {
+      // the cost sees Theta^N, a function of the sums of the last state,
+      // which buf[(N-1) & 1] holds (the last step never closes a segment,
+      // and the last segment was the most recent one run or recomputed)
+      T* tu = static_cast<T*>(t->tseed);
+      T* tv = tu + t->plane;
+      mrt::launch_implicit_terminal<T>(g, m, static_cast<const T*>(t->buf[(N - 1) & 1]), tc,
+                                       su, sv, tu, tv, gacc, s);
+      int rc = last_launch_error();
+      if (rc) return rc;
+      su = tu;
+      sv = tv;
     }
     SpanGuard span(1, s);
     for (int n = n1 - 1; n >= n0; --n) {
@@ -511,8 +576,9 @@ int adjoint_impl(const mrt_problem* p, mrt_tape* t, const void* u0,
       a.first = n == N - 1;
       a.last = (n == 0 && want0) ? 1 : 0;
       a.dst = n == 0 ? nullptr : static_cast<T*>(t->abuf[n & 1]);
-      a.seed_u = static_cast<const T*>(seed_u);
-      a.seed_v = static_cast<const T*>(seed_v);
+      a.seed_u = su;
+      a.seed_v = sv;
+      a.variant = t->ns == 3 ? 4 : (t->so2 ? 2 : (t->impl ? 3 : 1));
       a.rec = slot<T>(t, n - n0);
       a.g = gacc;
       a.adj_u0 = static_cast<T*>(adj_u0);
@@ -550,7 +616,8 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
       const T* dummy = nullptr;
       t->rec_seg = -1;
       int rc = run_forward_steps<T>(t, m, g, n0, n1, src, tu0, tv0, tc, true, false, 2, s,
-                                    &dummy, true);
+                                    &dummy, true,
+                                    static_cast<const T*>(p->nspecies == 3 ? p->w0 : nullptr));
       if (rc) return rc;
       t->rec_seg = seg;
     }
@@ -563,6 +630,7 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
       a.dv0 = static_cast<const T*>(dv0);
       a.dc = static_cast<const T*>(dc);
       a.rec = slot<T>(t, n - n0);
+      a.variant = t->ns == 3 ? 4 : (t->so2 ? 2 : (t->impl ? 3 : 1));
       a.dlag = t->so2 ? static_cast<T*>(t->alag) : nullptr;
       mrt::launch_tlm_step<T>(g, m, a, s);
       span.count();
@@ -571,7 +639,13 @@ int tlm_impl(const mrt_problem* p, mrt_tape* t, const void* u0, const void* v0,
       dsrc = a.dst;
     }
   }
-  mrt::launch_finalize<T>(g, dsrc, nullptr, static_cast<T*>(duN), static_cast<T*>(dvN), s);
+  if (t->impl)
+    // the last segment ran last, so buf[(N-1) & 1] holds the forward's last state
+    mrt::launch_implicit_tlm_final<T>(g, m, static_cast<const T*>(t->buf[(N - 1) & 1]), dsrc,
+                                      tc, static_cast<const T*>(dc), static_cast<T*>(duN),
+                                      static_cast<T*>(dvN), s);
+  else
+    mrt::launch_finalize<T>(g, dsrc, nullptr, static_cast<T*>(duN), static_cast<T*>(dvN), s);
   return last_launch_error();
 }
 
@@ -696,7 +770,9 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
   t->mode = L.mode;
   t->K = L.K;
   t->nseg = L.nseg;
-  t->so2 = p->source_order == 2 ? 1 : 0;
+  t->ns = p->nspecies == 3 ? 3 : 2;
+  t->so2 = p->source_term == 2 ? 1 : 0;
+  t->impl = p->source_term == 3 ? 1 : 0;
   t->plane = L.plane;
   t->elem = L.elem;
   t->state_bytes = L.state_bytes;
@@ -732,6 +808,7 @@ int mrt_tape_create(const mrt_problem* p, int32_t ckpt_every,
     t->ckpt.assign(L.nseg, nullptr);
     for (int k = 1; k < L.nseg && !rc; ++k) rc = alloc(L.state_bytes, &t->ckpt[k]);
     if (!rc && t->so2) rc = alloc(L.lag_bytes, &t->alag);
+    if (!rc && t->impl) rc = alloc(L.tseed_bytes, &t->tseed);
     t->ckpt_lag.assign(L.nseg, nullptr);
     for (int k = 1; t->so2 && k < L.nseg && !rc; ++k) rc = alloc(L.lag_bytes, &t->ckpt_lag[k]);
     if (!rc) rc = alloc(size_t(L.K) * L.rec_slot_bytes, &t->rec);
@@ -893,6 +970,7 @@ int mrt_cadjoint(const mrt_problem* p, mrt_tape* t, const void* u0, const void* 
   if (u0 != t->f_u0 || v0 != t->f_v0 || control != t->f_ctrl)
     return fail(MRT_ESTATE, "u0/v0/control differ from the recorded forward");
   if (!seed_u || !grad_accum) return fail(MRT_EINVAL, "seed_u and grad_accum required");
+  if (t->ns == 3) return fail(MRT_EINVAL, "the continuous adjoint takes two species only");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return p->grid.dtype == MRT_F64
              ? cadjoint_impl<double>(p, t, u0, v0, control, seed_u, grad_accum, s)

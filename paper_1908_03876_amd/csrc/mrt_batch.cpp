@@ -205,8 +205,10 @@ int mrt_batch_create(const mrt_problem* problems, int32_t count,
       return err(MRT_EINVAL, "batched problems must be periodic, unmasked, square, pitch == nx");
     if (g.dtype != g0.dtype || g.nsteps != g0.nsteps)
       return err(MRT_EINVAL, "batched problems must share dtype and nsteps");
-    if (p->source_order == 2)
+    if (p->source_term > 1)
       return err(MRT_EINVAL, "the batched engine runs the first-order source term only");
+    if (p->nspecies == 3)
+      return err(MRT_EINVAL, "the batched engine runs two species only");
   }
   mrt_batch* b = new mrt_batch();
   b->count = count;

@@ -1,6 +1,6 @@
-// Per-node device code of the two-species D2Q9 MRT step and of its exact
-// discrete adjoint (AMRT), shared by the single-lattice kernels and the
-// batched persistent kernels.
+// Per-node device code of the two- and three-species D2Q9 MRT step and of
+// its exact discrete adjoint (AMRT), shared by the single-lattice kernels
+// and the batched persistent kernels.
 //
 // Method: arXiv:1908.03876, Section 3.1 (eq:LBE, S, PhiS, MF, MC, phieq,
 // BC11, the relaxation matrix Pi and D = d Cs^2 tau (K^-1 - I/2)) and
@@ -289,6 +289,76 @@ __device__ __forceinline__ void store_state(const Geometry& g, const NodeIdx& n,
   }
 }
 
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+
+// Implicit characteristic difference of the second-order source (eq:LBEG
+// with kappa_t = kappa_x = 1): the scheme carries g = phi - (tau/2) w Phi,
+// and Theta solves Theta - (tau/2) Phi(Theta) = G = sum_i g_i at each node:
+// u from (tau r_u / 2) u^2 + (1 - tau r_u / 2) u - G_u = 0 (the root that
+// tends to G_u as r_u -> 0, written without cancellation; tau r_u < 2),
+// then v from the linear equation (a_uv u - b_v v + c enters at weight 1/2).
+template <typename T>
+__device__ __forceinline__ void implicit_solve(const ModelCoef<T>& m, T Gu, T Gv, T c, T& u,
+                                               T& v) {
+  const T hr = T(0.5) * m.r_u;
+  const T bq = T(1) - hr;
+  u = T(2) * Gu / (bq + dsqrt(bq * bq + T(4) * hr * Gu));
+  v = (Gv + T(0.5) * (m.a_uv * u + c)) / (T(1) + T(0.5) * m.b_v);
+}
+
+// Scheme variants: the source term of (eq:LBEG) for two species, 1 first
+// order (tau F_i), 2 explicit characteristic difference (kappa_t = 1,
+// kappa_x = 0), 3 implicit characteristic difference (kappa_t = kappa_x =
+// 1); 4 three species (u, v and a repulsive signal w, first-order source).
+constexpr int kVarFirst = 1, kVarExplicit = 2, kVarImplicit = 3, kVarThree = 4;
+
+// Third species of a node: its pull from planes 18..26 of src (with wall
+// slots), or w_i w0 at the first step.
+template <typename T, bool PERIODIC, bool FIRST>
+__device__ __forceinline__ void gather_w(const Geometry& g, const NodeIdx& n,
+                                         const ModelCoef<T>& m, const T* __restrict__ src,
+                                         const T* __restrict__ w0, T fw[9]) {
+  if (FIRST) {
+    const T a = w0 ? w0[n.r0 + n.x] : T(0);
+    fw[0] = m.w.w_rest * a;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) fw[i] = m.w.w_axis * a;
+#pragma unroll
+    for (int i = 5; i < 9; ++i) fw[i] = m.w.w_diag * a;
+  } else {
+    const T* sw = src + 18 * g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fw[i] = sw[pull_src<PERIODIC>(n, i, g.plane)];
+  }
+}
+
+// Stores of the third species' post-collision values (planes 18..26 of
+// dst) with their wall slots, as store_state does for u and v.
+template <typename T, bool MASKED>
+__device__ __forceinline__ void store_w(const Geometry& g, const NodeIdx& n, const T fw[9],
+                                        T* __restrict__ dst, unsigned lm) {
+  const size_t idx = n.r0 + n.x;
+  T* dw = dst + 18 * g.plane;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(fw[i], &dw[size_t(i) * g.plane + idx]);
+  if (MASKED && (lm & 0x1FEu)) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      if ((lm >> opp(i)) & 1u) dw[size_t(opp(i)) * g.plane + push_off(n, i)] = fw[i];
+  }
+}
+
+// Kinetics source tau w_i Phi on one species' populations.
+template <typename T>
+__device__ __forceinline__ void add_kinetics(T f[9], T ph) {
+  f[0] += ph * T(4.0 / 9.0);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) f[i] += ph * T(1.0 / 9.0);
+#pragma unroll
+  for (int i = 5; i < 9; ++i) f[i] += ph * T(1.0 / 36.0);
+}
+
 // Collision of the gathered node values and the stores: record (u, j_v),
 // post-collision state, wall slots.  `lm` is the node's link word (0
 // without a mask).
@@ -300,13 +370,29 @@ __device__ __forceinline__ void store_state(const Geometry& g, const NodeIdx& n,
 // (the static control cancels in the difference) and is overwritten with
 // this step's; at the first step there is no previous value and the
 // difference is zero.
-template <typename T, bool MASKED, bool LAG = false>
+//
+// kVarImplicit: the gathered values are g (phi at the first step, which
+// starts from phi^0 = w~ Theta_0); Theta comes from implicit_solve, phi =
+// g + (tau/2) w Phi, and the stored post-collision value is
+// g* = relax(phi) + tau S + (tau/2) w Phi: the departure half of the
+// difference, -(tau/2) F_i(x, t), plus the arrival half, which the next
+// step's node solve takes at x + e_i.  The first moment of g equals that of
+// phi (sum_i w_i e_i = 0).
+//
+// kVarThree: fw holds the third species; the record gains j_w (planes 3
+// and 4), the chemotactic flux of u gains u Bw j_w (the repulsion
+// A_u2 grad w with grad w = -K_w j_w / (tau d_w Cs^2)), and w relaxes with
+// its own rates and receives Phi_w = a_w u - b_w w + s_w.
+template <typename T, bool MASKED, int VAR = kVarFirst>
 __device__ __forceinline__ void forward_collide_store(const Geometry& g, const NodeIdx& n,
                                                       const ModelCoef<T>& m, T fu[9], T fv[9],
                                                       T c, T* __restrict__ dst,
                                                       T* __restrict__ rec, unsigned lm,
                                                       T* __restrict__ lag = nullptr,
-                                                      bool first = false) {
+                                                      bool first = false,
+                                                      T* __restrict__ fw = nullptr) {
+  constexpr bool W3 = VAR == kVarThree;
+  constexpr bool LAG = VAR == kVarExplicit;
   const size_t idx = n.r0 + n.x;
   // macroscopic values (UGS) and the first moment of v
   T u = T(0), v = T(0);
@@ -317,16 +403,38 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
   }
   const T jx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
   const T jy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
+  if (VAR == kVarImplicit && !first) {
+    const T Gu = u, Gv = v;
+    implicit_solve(m, Gu, Gv, c, u, v);
+    const T hu = T(0.5) * m.r_u * u * (T(1) - u);
+    const T hv = T(0.5) * (m.a_uv * u - m.b_v * v + c);
+    add_sources(fu, fv, hu, T(0), T(0), hv);  // phi = g + (tau/2) w Phi
+  }
+  T wv = T(0), kx = T(0), ky = T(0);
+  if (W3) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) wv += fw[i];
+    kx = fw[1] - fw[3] + fw[5] - fw[6] - fw[7] + fw[8];
+    ky = fw[2] - fw[4] + fw[5] + fw[6] - fw[7] - fw[8];
+  }
   if (rec != nullptr && !(MASKED && (lm & 1u))) {
     // the record is read back only by the adjoint sweep, much later
     __builtin_nontemporal_store(u, &rec[idx]);
     __builtin_nontemporal_store(jx, &rec[g.plane + idx]);
     __builtin_nontemporal_store(jy, &rec[2 * g.plane + idx]);
+    if (W3) {
+      __builtin_nontemporal_store(kx, &rec[3 * g.plane + idx]);
+      __builtin_nontemporal_store(ky, &rec[4 * g.plane + idx]);
+    }
   }
   // chemotactic source: A_u1 grad v = u * B * j_v with the local gradient
   // grad v = -K_v j_v / (tau d_v Cs^2)
-  const T ax = u * (m.b00 * jx + m.b01 * jy);
-  const T ay = u * (m.b10 * jx + m.b11 * jy);
+  T ax = u * (m.b00 * jx + m.b01 * jy);
+  T ay = u * (m.b10 * jx + m.b11 * jy);
+  if (W3) {
+    ax += u * (m.bw00 * kx + m.bw01 * ky);
+    ay += u * (m.bw10 * kx + m.bw11 * ky);
+  }
   const T ru = m.r_u * u * (T(1) - u);
   const T rv = m.a_uv * u - m.b_v * v;
   T phu, phv;
@@ -339,6 +447,9 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
       lag[idx] = ru;
       lag[g.plane + idx] = rv;
     }
+  } else if (VAR == kVarImplicit) {
+    phu = T(0.5) * ru;
+    phv = T(0.5) * (rv + c);
   } else {
     phu = ru;
     phv = rv + c;
@@ -347,10 +458,15 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
   relax(fu, u, m.u, t1, t2);
   relax(fv, v, m.v, t1, t2);
   add_sources(fu, fv, phu, ax, ay, phv);
+  if (W3) {
+    relax(fw, wv, m.w, t1, t2);
+    add_kinetics(fw, m.a_w * u - m.b_w * wv + m.s_w);
+  }
   // solid nodes of mixed wavefronts computed on slot contents they do not
   // own; they store nothing (their slots hold the neighbours' wall stores)
   if (MASKED && (lm & 1u)) return;
   store_state<T, MASKED>(g, n, fu, fv, dst, lm);
+  if (W3) store_w<T, MASKED>(g, n, fw, dst, lm);
 }
 
 // Tangent-linear step (sensitivity LBE, LIBEG-V) at a node: the derivative
@@ -362,13 +478,23 @@ __device__ __forceinline__ void forward_collide_store(const Geometry& g, const N
 //   dPhi_v = a_uv du - b_v dv + dc.
 // LAG: the second-order source as in the forward, on the perturbed
 // kinetics; dlag [2][plane] carries their previous-step values.
-template <typename T, bool MASKED, bool LAG = false>
+// kVarImplicit: the perturbation of g; the node equation linearised at the
+// recorded u gives du = dG_u / (1 - (tau/2) r_u (1 - 2u)) and
+// dv = (dG_v + (tau/2)(a_uv du + dc)) / (1 + (tau/2) b_v) (none at the first
+// step, whose input is dphi^0).
+// kVarThree: fw holds the perturbation of the third species;
+// d(u Bw j_w) = du Bw j_w + u Bw dj_w with j_w recorded, and
+// dPhi_w = a_w du - b_w dw.
+template <typename T, bool MASKED, int VAR = kVarFirst>
 __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeIdx& n,
                                                   const ModelCoef<T>& m, T fu[9], T fv[9],
                                                   T dc, const T* __restrict__ rec,
                                                   T* __restrict__ dst, unsigned lm,
                                                   T* __restrict__ dlag = nullptr,
-                                                  bool first = false) {
+                                                  bool first = false,
+                                                  T* __restrict__ fw = nullptr) {
+  constexpr bool LAG = VAR == kVarExplicit;
+  constexpr bool W3 = VAR == kVarThree;
   const size_t idx = n.r0 + n.x;
   const T u = __builtin_nontemporal_load(&rec[idx]);
   const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
@@ -379,10 +505,28 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
     du += fu[i];
     dv += fv[i];
   }
+  if (VAR == kVarImplicit && !first) {
+    du = du / (T(1) - T(0.5) * m.r_u * (T(1) - T(2) * u));
+    dv = (dv + T(0.5) * (m.a_uv * du + dc)) / (T(1) + T(0.5) * m.b_v);
+    const T hu = T(0.5) * m.r_u * (T(1) - T(2) * u) * du;
+    const T hv = T(0.5) * (m.a_uv * du - m.b_v * dv + dc);
+    add_sources(fu, fv, hu, T(0), T(0), hv);  // dphi = dg + (tau/2) w dPhi
+  }
   const T djx = fv[1] - fv[3] + fv[5] - fv[6] - fv[7] + fv[8];
   const T djy = fv[2] - fv[4] + fv[5] + fv[6] - fv[7] - fv[8];
-  const T dax = du * (m.b00 * jx + m.b01 * jy) + u * (m.b00 * djx + m.b01 * djy);
-  const T day = du * (m.b10 * jx + m.b11 * jy) + u * (m.b10 * djx + m.b11 * djy);
+  T dax = du * (m.b00 * jx + m.b01 * jy) + u * (m.b00 * djx + m.b01 * djy);
+  T day = du * (m.b10 * jx + m.b11 * jy) + u * (m.b10 * djx + m.b11 * djy);
+  T dw = T(0);
+  if (W3) {
+    const T kx = __builtin_nontemporal_load(&rec[3 * g.plane + idx]);
+    const T ky = __builtin_nontemporal_load(&rec[4 * g.plane + idx]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dw += fw[i];
+    const T dkx = fw[1] - fw[3] + fw[5] - fw[6] - fw[7] + fw[8];
+    const T dky = fw[2] - fw[4] + fw[5] + fw[6] - fw[7] - fw[8];
+    dax += du * (m.bw00 * kx + m.bw01 * ky) + u * (m.bw00 * dkx + m.bw01 * dky);
+    day += du * (m.bw10 * kx + m.bw11 * ky) + u * (m.bw10 * dkx + m.bw11 * dky);
+  }
   const T dru = m.r_u * (T(1) - T(2) * u) * du;
   const T drv = m.a_uv * du - m.b_v * dv;
   T dphu, dphv;
@@ -395,6 +539,9 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
       dlag[idx] = dru;
       dlag[g.plane + idx] = drv;
     }
+  } else if (VAR == kVarImplicit) {
+    dphu = T(0.5) * dru;
+    dphv = T(0.5) * (drv + dc);
   } else {
     dphu = dru;
     dphv = drv + dc;
@@ -403,8 +550,13 @@ __device__ __forceinline__ void tlm_collide_store(const Geometry& g, const NodeI
   relax(fu, du, m.u, t1, t2);
   relax(fv, dv, m.v, t1, t2);
   add_sources(fu, fv, dphu, dax, day, dphv);
+  if (W3) {
+    relax(fw, dw, m.w, t1, t2);
+    add_kinetics(fw, m.a_w * du - m.b_w * dw);
+  }
   if (MASKED && (lm & 1u)) return;
   store_state<T, MASKED>(g, n, fu, fv, dst, lm);
+  if (W3) store_w<T, MASKED>(g, n, fw, dst, lm);
 }
 
 // Continuous-adjoint step (Section 3.2.2: the continuous adjoint system of
@@ -469,11 +621,12 @@ __device__ __forceinline__ void cadj_collide_store(const Geometry& g, const Node
 // run-time flag (rec != null), not a template parameter: the recorded and
 // the plain steps then run the same machine code, so a checkpointed
 // recomputation reproduces the recorded trajectory bit for bit.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG = false>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, int VAR = kVarFirst>
 __device__ __forceinline__ void forward_node(
     const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ u0, const T* __restrict__ v0,
-    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag = nullptr) {
+    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag = nullptr,
+    const T* __restrict__ w0 = nullptr) {
   unsigned lm = 0;
   if (MASKED) {
     const unsigned flag = wave_flag(g, n);
@@ -482,13 +635,24 @@ __device__ __forceinline__ void forward_node(
   }
   T fu[9], fv[9], c;
   forward_gather<T, PERIODIC, FIRST>(g, n, m, src, u0, v0, ctrl, fu, fv, c);
-  forward_collide_store<T, MASKED, LAG>(g, n, m, fu, fv, c, dst, rec, lm, lag, FIRST);
+  if (VAR == kVarThree) {
+    T fw[9];
+    gather_w<T, PERIODIC, FIRST>(g, n, m, src, w0, fw);
+    forward_collide_store<T, MASKED, VAR>(g, n, m, fu, fv, c, dst, rec, lm, lag, FIRST, fw);
+  } else {
+    forward_collide_store<T, MASKED, VAR>(g, n, m, fu, fv, c, dst, rec, lm, lag, FIRST);
+  }
 }
 
-template <typename T, bool PERIODIC, bool MASKED>
+// Terminal streaming: the state after the last step and its sums.  IMPL
+// (implicit characteristic difference): the streamed values are g; Theta^N
+// comes from the node solve and the state is phi^N = g + (tau/2) w Phi.
+// W3: the third species' populations are also streamed into the state.
+template <typename T, bool PERIODIC, bool MASKED, bool IMPL = false, bool W3 = false>
 __device__ __forceinline__ void finalize_node(
     const Geometry& g, const NodeIdx& n, const T* __restrict__ src, T* __restrict__ state,
-    T* __restrict__ uN, T* __restrict__ vN) {
+    T* __restrict__ uN, T* __restrict__ vN, const ModelCoef<T>* m = nullptr,
+    const T* __restrict__ ctrl = nullptr) {
   const size_t idx = n.r0 + n.x;
   const bool solid = MASKED && (link_of(g, wave_flag(g, n), idx) & 1u);
   T fu[9], fv[9];
@@ -509,6 +673,13 @@ __device__ __forceinline__ void finalize_node(
     u += fu[i];
     v += fv[i];
   }
+  if (IMPL && !solid) {
+    const T c = ctrl[idx];
+    const T Gu = u, Gv = v;
+    implicit_solve(*m, Gu, Gv, c, u, v);
+    add_sources(fu, fv, T(0.5) * m->r_u * u * (T(1) - u), T(0), T(0),
+                T(0.5) * (m->a_uv * u - m->b_v * v + c));
+  }
   if (uN) uN[idx] = u;
   if (vN) vN[idx] = v;
   if (state) {
@@ -516,6 +687,12 @@ __device__ __forceinline__ void finalize_node(
     for (int i = 0; i < 9; ++i) {
       state[size_t(i) * g.plane + idx] = fu[i];
       state[size_t(9 + i) * g.plane + idx] = fv[i];
+    }
+    if (W3) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        state[size_t(18 + i) * g.plane + idx] =
+            solid ? T(0) : src[18 * g.plane + pull_src<PERIODIC>(n, i, g.plane)];
     }
   }
 }
@@ -530,7 +707,21 @@ __device__ __forceinline__ void finalize_node(
 // FIRST (step N-1) reads no mu: nothing reads the last stored kinetics.
 // step0 marks step 0 (a run-time flag: LAST is set only when dJ/du0,
 // dJ/dv0 are requested).
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, bool LAG = false>
+//
+// kVarImplicit: the adjoint of g.  With A the relaxation (phi -> phi -
+// C (phi - w~ Theta)), a step maps g to g* = A g + (tau/2)(A w + w) Phi +
+// tau S with Theta from the node equation, so the sensitivity to Phi_s is
+// kappa_s = (tau/2)(w . A^T nu_s + sigma_s); through the linearised node
+// solve (alpha = 1 / (1 - (tau/2) r_u (1 - 2u)), beta = 1 / (1 +
+// (tau/2) b_v)) the sums G_s receive Gbar_v = beta vbar and Gbar_u =
+// alpha (ubar + (tau/2) a_uv beta vbar), and the control kappa_v beta.  At
+// step 0 the input is phi^0 itself: kappa_s = (tau/2) sigma_s, no solve.
+//
+// kVarThree: the adjoint of w as well (planes 18..26; zero at the terminal
+// step, the cost not depending on w): sigma_w enters u's source through
+// a_w, w's own through -b_w; the repulsive flux u Bw j_w adds
+// p . (Bw j_w) to u's and e_i . (u Bw^T p) to w's.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, int VAR = kVarFirst>
 __device__ __forceinline__ void adjoint_node(
     const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ seed_u, const T* __restrict__ seed_v,
@@ -580,6 +771,19 @@ __device__ __forceinline__ void adjoint_node(
       nv[i] = __builtin_nontemporal_load(&sv[o]);
     }
   }
+  constexpr bool W3 = VAR == kVarThree;
+  T nw[9];
+  if (W3) {
+    if (FIRST) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nw[i] = T(0);
+    } else {
+      const T* sw = src + 18 * g.plane;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        nw[i] = __builtin_nontemporal_load(&sw[gather_src<PERIODIC>(n, i, g.plane)]);
+    }
+  }
   // weighted sums: sigma = w . nu, p = (tau/Cs^2) sum_i w_i nu_u,i e_i
   const T su_ = T(4.0 / 9.0) * nu[0] +
                 T(1.0 / 9.0) * (nu[1] + nu[2] + nu[3] + nu[4]) +
@@ -594,11 +798,16 @@ __device__ __forceinline__ void adjoint_node(
   // solid nodes of mixed wavefronts gathered slots they do not own; they
   // update nothing
   if (MASKED && (lm & 1u)) return;
-  // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i
-  if (FIRST)
-    gacc[idx] = double(sv_);
-  else
-    gacc[idx] += double(sv_);
+  constexpr bool LAG = VAR == kVarExplicit;
+  constexpr bool IMPL = VAR == kVarImplicit;
+  // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i (the implicit
+  // form adds its share below)
+  if (!IMPL) {
+    if (FIRST)
+      gacc[idx] = double(sv_);
+    else
+      gacc[idx] += double(sv_);
+  }
   // recorded forward quantities of step n
   const T u = __builtin_nontemporal_load(&rec[idx]);
   const T jx = __builtin_nontemporal_load(&rec[g.plane + idx]);
@@ -621,17 +830,72 @@ __device__ __forceinline__ void adjoint_node(
       mu[g.plane + idx] = T(-0.5) * sv_;
     }
   }
-  const T cu = rho_u * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
-               rho_v * m.a_uv;
-  const T cv = -rho_v * m.b_v;
   const T qx = u * (m.b00 * px + m.b10 * py);
   const T qy = u * (m.b01 * px + m.b11 * py);
-  // adjoint collision: nu - C^T nu + 1 * weq^T C^T nu  (AEDs with O = 1 weq^T)
-  T a1, a2;
-  relax(nu, T(0), m.ut, a1, a2);
-  const T wu = m.u.e_eq * a1 + m.u.eps_eq * a2 + cu;
-  relax(nv, T(0), m.vt, a1, a2);
-  const T wv = m.v.e_eq * a1 + m.v.eps_eq * a2 + cv;
+  T wu, wv;
+  if (!IMPL) {
+    T cu = rho_u * m.r_u * (T(1) - T(2) * u) + px * bjx + py * bjy +
+           rho_v * m.a_uv;
+    const T cv = -rho_v * m.b_v;
+    if (W3) {
+      const T kx = __builtin_nontemporal_load(&rec[3 * g.plane + idx]);
+      const T ky = __builtin_nontemporal_load(&rec[4 * g.plane + idx]);
+      const T sw_ = T(4.0 / 9.0) * nw[0] + T(1.0 / 9.0) * (nw[1] + nw[2] + nw[3] + nw[4]) +
+                    T(1.0 / 36.0) * (nw[5] + nw[6] + nw[7] + nw[8]);
+      cu += px * (m.bw00 * kx + m.bw01 * ky) + py * (m.bw10 * kx + m.bw11 * ky) +
+            sw_ * m.a_w;
+      T a1, a2;
+      relax(nw, T(0), m.wt, a1, a2);
+      const T ww = m.w.e_eq * a1 + m.w.eps_eq * a2 - sw_ * m.b_w;
+      const T rx = u * (m.bw00 * px + m.bw10 * py);
+      const T ry = u * (m.bw01 * px + m.bw11 * py);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nw[i] += ww;
+      nw[1] += rx;
+      nw[2] += ry;
+      nw[3] -= rx;
+      nw[4] -= ry;
+      nw[5] += rx + ry;
+      nw[6] += ry - rx;
+      nw[7] -= rx + ry;
+      nw[8] += rx - ry;
+    }
+    // adjoint collision: nu - C^T nu + 1 * weq^T C^T nu  (AEDs with O = 1 weq^T)
+    T a1, a2;
+    relax(nu, T(0), m.ut, a1, a2);
+    wu = m.u.e_eq * a1 + m.u.eps_eq * a2 + cu;
+    relax(nv, T(0), m.vt, a1, a2);
+    wv = m.v.e_eq * a1 + m.v.eps_eq * a2 + cv;
+  } else {
+    T a1, a2;
+    relax(nu, T(0), m.ut, a1, a2);
+    const T eu = m.u.e_eq * a1 + m.u.eps_eq * a2;
+    relax(nv, T(0), m.vt, a1, a2);
+    const T ev = m.v.e_eq * a1 + m.v.eps_eq * a2;
+    T ku = T(0.5) * su_, kv = T(0.5) * sv_;
+    if (!step0) {
+      // w . A^T nu = w . (relaxed nu) + e (sum_i w_i = 1)
+      const T tu = T(4.0 / 9.0) * nu[0] + T(1.0 / 9.0) * (nu[1] + nu[2] + nu[3] + nu[4]) +
+                   T(1.0 / 36.0) * (nu[5] + nu[6] + nu[7] + nu[8]) + eu;
+      const T tv = T(4.0 / 9.0) * nv[0] + T(1.0 / 9.0) * (nv[1] + nv[2] + nv[3] + nv[4]) +
+                   T(1.0 / 36.0) * (nv[5] + nv[6] + nv[7] + nv[8]) + ev;
+      ku = T(0.5) * (tu + su_);
+      kv = T(0.5) * (tv + sv_);
+    }
+    const T ubar = ku * m.r_u * (T(1) - T(2) * u) + kv * m.a_uv + px * bjx + py * bjy;
+    const T vbar = -kv * m.b_v;
+    T gu = ubar, gv = vbar, gc = kv;
+    if (!step0) {
+      const T beta = T(1) / (T(1) + T(0.5) * m.b_v);
+      const T alpha = T(1) / (T(1) - T(0.5) * m.r_u * (T(1) - T(2) * u));
+      gv = beta * vbar;
+      gu = alpha * (ubar + T(0.5) * m.a_uv * gv);
+      gc = kv * beta;
+    }
+    gacc[idx] += double(gc);  // initialised by the terminal transform
+    wu = eu + gu;
+    wv = ev + gv;
+  }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     nu[i] += wu;
@@ -662,6 +926,12 @@ __device__ __forceinline__ void adjoint_node(
       __builtin_nontemporal_store(nu[i], &dst[size_t(i) * g.plane + idx]);
       __builtin_nontemporal_store(nv[i], &dv[size_t(i) * g.plane + idx]);
     }
+    if (W3) {
+      T* dw = dst + 18 * g.plane;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        __builtin_nontemporal_store(nw[i], &dw[size_t(i) * g.plane + idx]);
+    }
     if (MASKED && (lm & 0x1FEu)) {
       // wall stores of the adjoint: the next gather in direction i at x
       // reads plane i at the solid node x + e_i and must find lambda_opp(i)(x)
@@ -671,6 +941,7 @@ __device__ __forceinline__ void adjoint_node(
           const size_t o = size_t(i) * g.plane + push_off(n, i);
           dst[o] = nu[opp(i)];
           dv[o] = nv[opp(i)];
+          if (W3) dst[18 * g.plane + o] = nw[opp(i)];
         }
       }
     }

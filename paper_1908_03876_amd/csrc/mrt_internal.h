@@ -29,6 +29,10 @@ struct ModelCoef {
   SpeciesCoef<T> ut, vt; // adjoint relaxation: K transposed
   T b00, b01, b10, b11;  // chemotactic source a = u * B * j_v
   T r_u, a_uv, b_v;      // kinetics
+  // third species (three-species problems only)
+  SpeciesCoef<T> w, wt;
+  T bw00, bw01, bw10, bw11;  // repulsive source a += u * Bw * j_w
+  T a_w, b_w, s_w;           // Phi_w = a_w u - b_w w + s_w
 };
 
 struct Geometry {
@@ -56,18 +60,38 @@ struct FwdLaunch {
   const T* v0;
   const T* ctrl;     // control c(x)
   T* rec;            // record slot [3][plane] (u, j_vx, j_vy) or null
-  T* lag;            // second-order source: kinetics of the previous step
-                     // [2][plane], overwritten with this step's; null = first order
+  int variant;       // scheme variant: 1 first-order source, 2 explicit,
+                     // 3 implicit characteristic difference, 4 three species
+  T* lag;            // variant 2: kinetics of the previous step [2][plane],
+                     // overwritten with this step's
+  const T* w0;       // variant 4: initial w (first step only; null = 0)
 };
 
 template <typename T>
 void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
                          const FwdLaunch<T>& a, hipStream_t s);
 
-// Terminal streaming: state (may be null), u^N, v^N (may be null).
+// Terminal streaming: state (may be null), u^N, v^N (may be null).  With m
+// given (implicit characteristic difference), Theta^N comes from the node
+// solve with the control ctrl and the state is phi^N.
 template <typename T>
 void launch_finalize(const Geometry& g, const T* src, T* state, T* uN, T* vN,
-                     hipStream_t s);
+                     hipStream_t s, const ModelCoef<T>* m = nullptr,
+                     const T* ctrl = nullptr, bool three = false);
+
+// Implicit characteristic difference: adjoint seeds of the sums G^N from
+// (dJ/du^N, dJ/dv^N) (seed_v may be null), initialising the gradient
+// accumulator with the control's share in v^N; and the tangent of Theta^N
+// from that of G^N (fsrc: the forward's last post-collision state, dsrc:
+// the tangent's).
+template <typename T>
+void launch_implicit_terminal(const Geometry& g, const ModelCoef<T>& m, const T* src,
+                              const T* ctrl, const T* seed_u, const T* seed_v, T* out_u,
+                              T* out_v, double* gacc, hipStream_t s);
+template <typename T>
+void launch_implicit_tlm_final(const Geometry& g, const ModelCoef<T>& m, const T* fsrc,
+                               const T* dsrc, const T* ctrl, const T* dc, T* duN, T* dvN,
+                               hipStream_t s);
 
 template <typename T>
 struct AdjLaunch {
@@ -81,9 +105,9 @@ struct AdjLaunch {
   T* adj_v0;
   int first;         // 1: step N-1 (reads seeds, initialises g)
   int last;          // 1: step 0 and adj_u0/adj_v0 requested
-  T* mu;             // second-order source: adjoint of the stored kinetics
-                     // [2][plane]; null = first order
-  int step0;         // 1: step 0 (used with mu)
+  int variant;       // scheme variant (as FwdLaunch)
+  T* mu;             // variant 2: adjoint of the stored kinetics [2][plane]
+  int step0;         // 1: step 0
 };
 
 template <typename T>
@@ -121,8 +145,9 @@ struct TlmLaunch {
   const T* dv0;
   const T* dc;       // control perturbation (null = 0)
   const T* rec;      // record slot of step n (forward u, j_vx, j_vy)
-  T* dlag;           // second-order source: perturbed kinetics of the
-                     // previous step [2][plane]; null = first order
+  int variant;       // scheme variant (as FwdLaunch)
+  T* dlag;           // variant 2: perturbed kinetics of the previous step
+                     // [2][plane]
 };
 
 template <typename T>

@@ -68,26 +68,103 @@ __global__ void build_link_kernel(Geometry g, int periodic,
     wflag[size_t(y) * g.nsx + (x >> 6)] = fluid == 0ull ? 2u : (any != 0ull);
 }
 
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, int VAR>
 __global__ __launch_bounds__(kBlock) void forward_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ u0, const T* __restrict__ v0,
-    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag) {
+    const T* __restrict__ ctrl, T* __restrict__ rec, T* __restrict__ lag,
+    const T* __restrict__ w0) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  forward_node<T, PERIODIC, MASKED, FIRST, LAG>(g, n, m, src, dst, u0, v0, ctrl, rec, lag);
+  forward_node<T, PERIODIC, MASKED, FIRST, VAR>(g, n, m, src, dst, u0, v0, ctrl, rec, lag, w0);
 }
 
-template <typename T, bool PERIODIC, bool MASKED>
+template <typename T, bool PERIODIC, bool MASKED, bool IMPL, bool W3>
 __global__ __launch_bounds__(kBlock) void finalize_kernel(
-    Geometry g, const T* __restrict__ src, T* __restrict__ state,
-    T* __restrict__ uN, T* __restrict__ vN) {
+    Geometry g, ModelCoef<T> m, const T* __restrict__ src, const T* __restrict__ ctrl,
+    T* __restrict__ state, T* __restrict__ uN, T* __restrict__ vN) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  finalize_node<T, PERIODIC, MASKED>(g, n, src, state, uN, vN);
+  finalize_node<T, PERIODIC, MASKED, IMPL, W3>(g, n, src, state, uN, vN, &m, ctrl);
 }
 
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, bool LAG>
+// Pull of the populations streamed into node n after the last step (zeros
+// on solid nodes) and their sums G.
+template <typename T, bool PERIODIC, bool MASKED>
+__device__ __forceinline__ bool pull_sums(const Geometry& g, const NodeIdx& n,
+                                          const T* __restrict__ src, T& Gu, T& Gv) {
+  const size_t idx = n.r0 + n.x;
+  if (MASKED && (link_of(g, wave_flag(g, n), idx) & 1u)) return false;
+  Gu = T(0);
+  Gv = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const size_t o = pull_src<PERIODIC>(n, i, g.plane);
+    Gu += src[o];
+    Gv += src[9 * g.plane + o];
+  }
+  return true;
+}
+
+// Implicit characteristic difference, terminal condition of the adjoint:
+// the cost sees Theta^N, a function of the sums G^N of the last state, so
+// the seeds (dJ/du^N, dJ/dv^N) = (a, b) become the adjoint of G^N:
+// beta b and alpha (a + (tau/2) a_uv beta b), with alpha and beta of the
+// node equation at u^N.  v^N also depends on the control (weight tau/2 in
+// the node equation): the gradient accumulator starts at (tau/2) beta b.
+// Zero on solid nodes.
+template <typename T, bool PERIODIC, bool MASKED>
+__global__ __launch_bounds__(kBlock) void implicit_terminal_kernel(
+    Geometry g, ModelCoef<T> m, const T* __restrict__ src, const T* __restrict__ ctrl,
+    const T* __restrict__ seed_u, const T* __restrict__ seed_v, T* __restrict__ out_u,
+    T* __restrict__ out_v, double* __restrict__ gacc) {
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  T Gu, Gv;
+  if (!pull_sums<T, PERIODIC, MASKED>(g, n, src, Gu, Gv)) {
+    out_u[idx] = T(0);
+    out_v[idx] = T(0);
+    gacc[idx] = 0.0;
+    return;
+  }
+  T u, v;
+  implicit_solve(m, Gu, Gv, ctrl[idx], u, v);
+  const T alpha = T(1) / (T(1) - T(0.5) * m.r_u * (T(1) - T(2) * u));
+  const T beta = T(1) / (T(1) + T(0.5) * m.b_v);
+  const T b = seed_v ? seed_v[idx] : T(0);
+  out_v[idx] = beta * b;
+  out_u[idx] = alpha * (seed_u[idx] + T(0.5) * m.a_uv * beta * b);
+  gacc[idx] = double(T(0.5) * beta * b);
+}
+
+// Implicit characteristic difference, end of the tangent sweep: the
+// perturbation of Theta^N from that of G^N (node equation linearised at the
+// forward's u^N, with the control perturbation).
+template <typename T, bool PERIODIC, bool MASKED>
+__global__ __launch_bounds__(kBlock) void implicit_tlm_final_kernel(
+    Geometry g, ModelCoef<T> m, const T* __restrict__ fsrc, const T* __restrict__ dsrc,
+    const T* __restrict__ ctrl, const T* __restrict__ dc, T* __restrict__ duN,
+    T* __restrict__ dvN) {
+  NodeIdx n;
+  if (!node_of_block(g, n)) return;
+  const size_t idx = n.r0 + n.x;
+  T Gu, Gv, dGu, dGv;
+  if (!pull_sums<T, PERIODIC, MASKED>(g, n, fsrc, Gu, Gv)) {
+    if (duN) duN[idx] = T(0);
+    if (dvN) dvN[idx] = T(0);
+    return;
+  }
+  pull_sums<T, PERIODIC, MASKED>(g, n, dsrc, dGu, dGv);
+  T u, v;
+  implicit_solve(m, Gu, Gv, ctrl[idx], u, v);
+  const T du = dGu / (T(1) - T(0.5) * m.r_u * (T(1) - T(2) * u));
+  const T dcc = dc ? dc[idx] : T(0);
+  if (duN) duN[idx] = du;
+  if (dvN) dvN[idx] = (dGv + T(0.5) * (m.a_uv * du + dcc)) / (T(1) + T(0.5) * m.b_v);
+}
+
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, int VAR>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ seed_u, const T* __restrict__ seed_v,
@@ -95,14 +172,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu, int step0) {
   NodeIdx n;
   if (!node_of_block(g, n)) return;
-  adjoint_node<T, PERIODIC, MASKED, FIRST, LAST, LAG>(g, n, m, src, dst, seed_u, seed_v, rec,
+  adjoint_node<T, PERIODIC, MASKED, FIRST, LAST, VAR>(g, n, m, src, dst, seed_u, seed_v, rec,
                                                       gacc, adj_u0, adj_v0, mu, step0 != 0);
 }
 
 // Tangent-linear step of step n: pulls the perturbation (or, for n = 0,
 // the equilibrium of (du0, dv0)), linearised collision at the recorded
 // (u, j_v) of step n, streaming stores as the forward.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAG>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, int VAR>
 __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
     Geometry g, ModelCoef<T> m, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ du0, const T* __restrict__ dv0, const T* __restrict__ dc,
@@ -141,7 +218,14 @@ __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
     }
   }
   const T c = dc ? dc[idx] : T(0);
-  tlm_collide_store<T, MASKED, LAG>(g, n, m, fu, fv, c, rec, dst, lm, dlag, FIRST);
+  if (VAR == kVarThree) {
+    // the third species' perturbation starts at zero (no dw0)
+    T fw[9];
+    gather_w<T, PERIODIC, FIRST>(g, n, m, src, nullptr, fw);
+    tlm_collide_store<T, MASKED, VAR>(g, n, m, fu, fv, c, rec, dst, lm, dlag, FIRST, fw);
+  } else {
+    tlm_collide_store<T, MASKED, VAR>(g, n, m, fu, fv, c, rec, dst, lm, dlag, FIRST);
+  }
 }
 
 // Continuous-adjoint step: pulls the adjoint populations (or, for the first
@@ -358,12 +442,15 @@ void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
                          const FwdLaunch<T>& a, hipStream_t s) {
   const bool first = a.src == nullptr;
   const int nb = stencil_blocks(g);
-#define MRT_FWD2(P, M, F, LG)                                                \
-  hipLaunchKernelGGL((forward_step_kernel<T, P, M, F, LG>), dim3(nb),        \
+#define MRT_FWD2(P, M, F, VR)                                                \
+  hipLaunchKernelGGL((forward_step_kernel<T, P, M, F, VR>), dim3(nb),        \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.u0, a.v0,     \
-                     a.ctrl, a.rec, a.lag)
-#define MRT_FWD(P, M, F) \
-  if (a.lag) { MRT_FWD2(P, M, F, true); } else { MRT_FWD2(P, M, F, false); }
+                     a.ctrl, a.rec, a.lag, a.w0)
+#define MRT_FWD(P, M, F)                                                     \
+  if (a.variant == kVarExplicit) { MRT_FWD2(P, M, F, kVarExplicit); }       \
+  else if (a.variant == kVarImplicit) { MRT_FWD2(P, M, F, kVarImplicit); }  \
+  else if (a.variant == kVarThree) { MRT_FWD2(P, M, F, kVarThree); }        \
+  else { MRT_FWD2(P, M, F, kVarFirst); }
 #define MRT_FWD_F(P, M) \
   if (first) { MRT_FWD(P, M, true); } else { MRT_FWD(P, M, false); }
   if (g.periodic) {
@@ -378,30 +465,74 @@ void launch_forward_step(const Geometry& g, const ModelCoef<T>& m,
 
 template <typename T>
 void launch_finalize(const Geometry& g, const T* src, T* state, T* uN, T* vN,
-                     hipStream_t s) {
+                     hipStream_t s, const ModelCoef<T>* m, const T* ctrl, bool three) {
   const int nb = stencil_blocks(g);
+  const bool impl = m != nullptr;
+  const ModelCoef<T> mc = impl ? *m : ModelCoef<T>{};
+#define MRT_FIN2(P, M, I, W)                                                 \
+  hipLaunchKernelGGL((finalize_kernel<T, P, M, I, W>), dim3(nb),             \
+                     dim3(kBlock), 0, s, g, mc, src, ctrl, state, uN, vN)
 #define MRT_FIN(P, M)                                                        \
-  hipLaunchKernelGGL((finalize_kernel<T, P, M>), dim3(nb), dim3(kBlock), 0,  \
-                     s, g, src, state, uN, vN)
+  if (impl) { MRT_FIN2(P, M, true, false); }                                 \
+  else if (three) { MRT_FIN2(P, M, false, true); }                           \
+  else { MRT_FIN2(P, M, false, false); }
   if (g.periodic) {
-    if (g.masked) MRT_FIN(true, true); else MRT_FIN(true, false);
+    if (g.masked) { MRT_FIN(true, true); } else { MRT_FIN(true, false); }
   } else {
-    if (g.masked) MRT_FIN(false, true); else MRT_FIN(false, false);
+    if (g.masked) { MRT_FIN(false, true); } else { MRT_FIN(false, false); }
   }
 #undef MRT_FIN
+#undef MRT_FIN2
+}
+
+template <typename T>
+void launch_implicit_terminal(const Geometry& g, const ModelCoef<T>& m, const T* src,
+                              const T* ctrl, const T* seed_u, const T* seed_v, T* out_u,
+                              T* out_v, double* gacc, hipStream_t s) {
+  const int nb = stencil_blocks(g);
+#define MRT_TRM(P, M)                                                        \
+  hipLaunchKernelGGL((implicit_terminal_kernel<T, P, M>), dim3(nb),          \
+                     dim3(kBlock), 0, s, g, m, src, ctrl, seed_u, seed_v,    \
+                     out_u, out_v, gacc)
+  if (g.periodic) {
+    if (g.masked) { MRT_TRM(true, true); } else { MRT_TRM(true, false); }
+  } else {
+    if (g.masked) { MRT_TRM(false, true); } else { MRT_TRM(false, false); }
+  }
+#undef MRT_TRM
+}
+
+template <typename T>
+void launch_implicit_tlm_final(const Geometry& g, const ModelCoef<T>& m, const T* fsrc,
+                               const T* dsrc, const T* ctrl, const T* dc, T* duN, T* dvN,
+                               hipStream_t s) {
+  const int nb = stencil_blocks(g);
+#define MRT_ITF(P, M)                                                        \
+  hipLaunchKernelGGL((implicit_tlm_final_kernel<T, P, M>), dim3(nb),         \
+                     dim3(kBlock), 0, s, g, m, fsrc, dsrc, ctrl, dc, duN,    \
+                     dvN)
+  if (g.periodic) {
+    if (g.masked) { MRT_ITF(true, true); } else { MRT_ITF(true, false); }
+  } else {
+    if (g.masked) { MRT_ITF(false, true); } else { MRT_ITF(false, false); }
+  }
+#undef MRT_ITF
 }
 
 template <typename T>
 void launch_adjoint_step(const Geometry& g, const ModelCoef<T>& m,
                          const AdjLaunch<T>& a, hipStream_t s) {
   const int nb = stencil_blocks(g);
-#define MRT_ADJ2(P, M, F, L, LG)                                             \
-  hipLaunchKernelGGL((adjoint_step_kernel<T, P, M, F, L, LG>), dim3(nb),     \
+#define MRT_ADJ2(P, M, F, L, VR)                                             \
+  hipLaunchKernelGGL((adjoint_step_kernel<T, P, M, F, L, VR>), dim3(nb),     \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.seed_u,       \
                      a.seed_v, a.rec, a.g, a.adj_u0, a.adj_v0, a.mu,         \
                      a.step0)
-#define MRT_ADJ(P, M, F, L) \
-  if (a.mu) { MRT_ADJ2(P, M, F, L, true); } else { MRT_ADJ2(P, M, F, L, false); }
+#define MRT_ADJ(P, M, F, L)                                                  \
+  if (a.variant == kVarExplicit) { MRT_ADJ2(P, M, F, L, kVarExplicit); }    \
+  else if (a.variant == kVarImplicit) { MRT_ADJ2(P, M, F, L, kVarImplicit); } \
+  else if (a.variant == kVarThree) { MRT_ADJ2(P, M, F, L, kVarThree); }      \
+  else { MRT_ADJ2(P, M, F, L, kVarFirst); }
 #define MRT_ADJ_L(P, M, F) \
   if (a.last) { MRT_ADJ(P, M, F, true); } else { MRT_ADJ(P, M, F, false); }
 #define MRT_ADJ_F(P, M) \
@@ -448,12 +579,15 @@ void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T
                      hipStream_t s) {
   const bool first = a.src == nullptr;
   const int nb = stencil_blocks(g);
-#define MRT_TLM2(P, M, F, LG)                                                \
-  hipLaunchKernelGGL((tlm_step_kernel<T, P, M, F, LG>), dim3(nb),            \
+#define MRT_TLM2(P, M, F, VR)                                                \
+  hipLaunchKernelGGL((tlm_step_kernel<T, P, M, F, VR>), dim3(nb),            \
                      dim3(kBlock), 0, s, g, m, a.src, a.dst, a.du0, a.dv0,   \
                      a.dc, a.rec, a.dlag)
-#define MRT_TLM(P, M, F) \
-  if (a.dlag) { MRT_TLM2(P, M, F, true); } else { MRT_TLM2(P, M, F, false); }
+#define MRT_TLM(P, M, F)                                                     \
+  if (a.variant == kVarExplicit) { MRT_TLM2(P, M, F, kVarExplicit); }       \
+  else if (a.variant == kVarImplicit) { MRT_TLM2(P, M, F, kVarImplicit); }  \
+  else if (a.variant == kVarThree) { MRT_TLM2(P, M, F, kVarThree); }        \
+  else { MRT_TLM2(P, M, F, kVarFirst); }
 #define MRT_TLM_F(P, M) \
   if (first) { MRT_TLM(P, M, true); } else { MRT_TLM(P, M, false); }
   if (g.periodic) {
@@ -510,7 +644,16 @@ void launch_count_fluid(const Geometry& g, double* partials, double* result,
   template void launch_forward_step<T>(const Geometry&, const ModelCoef<T>&, \
                                        const FwdLaunch<T>&, hipStream_t);    \
   template void launch_finalize<T>(const Geometry&, const T*, T*, T*, T*,    \
-                                   hipStream_t);                             \
+                                   hipStream_t, const ModelCoef<T>*,         \
+                                   const T*, bool);                          \
+  template void launch_implicit_terminal<T>(const Geometry&,                 \
+                                            const ModelCoef<T>&, const T*,   \
+                                            const T*, const T*, const T*,    \
+                                            T*, T*, double*, hipStream_t);   \
+  template void launch_implicit_tlm_final<T>(const Geometry&,                \
+                                             const ModelCoef<T>&, const T*,  \
+                                             const T*, const T*, const T*,   \
+                                             T*, T*, hipStream_t);           \
   template void launch_adjoint_step<T>(const Geometry&, const ModelCoef<T>&, \
                                        const AdjLaunch<T>&, hipStream_t);    \
   template void launch_cost_grad<T>(const Geometry&, const T*, const T*,    \

@@ -23,8 +23,8 @@ def padded_pitch(nx: int, align: int = 64) -> int:
 
 
 def make_problem_struct(prob, dtype_code: int, pitch: int,
-                        mask_ptr: Optional[int], nsteps: Optional[int] = None
-                        ) -> abi.mrt_problem:
+                        mask_ptr: Optional[int], nsteps: Optional[int] = None,
+                        w0_ptr: Optional[int] = None) -> abi.mrt_problem:
     p = abi.mrt_problem()
     g = p.grid
     g.nx, g.ny, g.pitch, g.q = int(prob.nx), int(prob.ny), int(pitch), 9
@@ -42,8 +42,16 @@ def make_problem_struct(prob, dtype_code: int, pitch: int,
     p.Cchi[:] = [float(x) for x in np.asarray(prob.Cchi, dtype=np.float64).ravel()]
     p.r_u, p.a_uv, p.b_v = float(prob.r_u), float(prob.a_uv), float(prob.b_v)
     p.alpha = float(prob.alpha)
-    p.source_order = int(getattr(prob, "source_order", 1))
-    p.reserved = 0
+    p.source_term = int(getattr(prob, "source_term", 1))
+    p.nspecies = int(getattr(prob, "nspecies", 2))
+    if p.nspecies == 3:
+        p.w.D[:] = [float(x) for x in np.asarray(prob.Dw, dtype=np.float64).ravel()]
+        p.w.d = float(prob.dw)
+        p.w.s[:] = [float(x) for x in np.asarray(prob.sw, dtype=np.float64).ravel()]
+        p.chi_w = float(prob.chi_w)
+        p.Cw[:] = [float(x) for x in np.asarray(prob.Cw, dtype=np.float64).ravel()]
+        p.a_w, p.b_w, p.s_w = float(prob.a_w), float(prob.b_w), float(prob.s_w)
+        p.w0 = w0_ptr
     return p
 
 
@@ -68,9 +76,12 @@ class DeviceProblem:
         self.v0 = self.field(prob.v0)
         self.control = self.field(prob.control)
         self.u_target = self.field(prob.u_target)
+        self.nspecies = int(getattr(prob, "nspecies", 2))
+        self.w0 = self.field(prob.w0) if self.nspecies == 3 else None
         self.struct = make_problem_struct(
             prob, self.code, self.pitch,
-            None if self.mask is None else self.mask.data_ptr(), self.nsteps)
+            None if self.mask is None else self.mask.data_ptr(), self.nsteps,
+            None if self.w0 is None else self.w0.data_ptr())
         abi.mrt_validate(self.struct)
 
     # -- host <-> device helpers (set-up and read-back only)
@@ -90,7 +101,7 @@ class DeviceProblem:
         return t[:, : self.nx].double().cpu().numpy()
 
     def state_tensor(self) -> torch.Tensor:
-        return torch.zeros((2, 9, self.ny, self.pitch), dtype=self.dtype,
+        return torch.zeros((self.nspecies, 9, self.ny, self.pitch), dtype=self.dtype,
                            device=self.device)
 
     def with_nsteps(self, nsteps: int) -> "DeviceProblem":
@@ -99,7 +110,8 @@ class DeviceProblem:
         q.nsteps = int(nsteps)
         q.struct = make_problem_struct(
             self.prob, self.code, self.pitch,
-            None if self.mask is None else self.mask.data_ptr(), nsteps)
+            None if self.mask is None else self.mask.data_ptr(), nsteps,
+            None if self.w0 is None else self.w0.data_ptr())
         return q
 
 

@@ -66,8 +66,9 @@ def test_validate_rejects_bad_grid(field, value):
     dict(sv=np.array([1, 1, 1, 1, 1, 1, 0.0])),
     dict(alpha=-1.0),
     dict(chi=math.nan),
-    dict(source_order=3),
-    dict(source_order=-1),
+    dict(source_term=4),
+    dict(source_term=-1),
+    dict(source_term=3, r_u=2.0),                        # node equation not solvable
 ])
 def test_validate_rejects_bad_model(kw):
     from paper_1908_03876_amd import abi
@@ -94,23 +95,54 @@ def test_tape_bytes_layout():
 
 
 def test_tape_bytes_layout_second_order_source():
-    """The second-order source adds the previous step's kinetics (2 planes)
-    to the forward state, to the adjoint/tangent state and to every
-    checkpoint."""
+    """The explicit second-order source adds the previous step's kinetics
+    (2 planes) to the forward state, to the adjoint/tangent state and to
+    every checkpoint."""
     from paper_1908_03876_amd import abi
     s1 = _struct(nsteps=200)
-    s2 = _struct(nsteps=200, source_order=2)
+    s2 = _struct(nsteps=200, source_term=2)
     abi.mrt_validate(s2)
     lag = 2 * 64 * 64 * 4
     assert abi.mrt_tape_bytes(s2, 0) - abi.mrt_tape_bytes(s1, 0) == lag
     assert abi.mrt_tape_bytes(s2, 200) - abi.mrt_tape_bytes(s1, 200) == 2 * lag
     assert abi.mrt_tape_bytes(s2, 50) - abi.mrt_tape_bytes(s1, 50) == 2 * lag + 3 * lag
+    # implicit form: two planes of terminal adjoint seeds when there is an adjoint
+    s3 = _struct(nsteps=200, source_term=3)
+    abi.mrt_validate(s3)
+    assert abi.mrt_tape_bytes(s3, 0) == abi.mrt_tape_bytes(s1, 0)
+    assert abi.mrt_tape_bytes(s3, 50) - abi.mrt_tape_bytes(s1, 50) == lag
 
 
-def test_validate_rejects_reserved_problem_field():
-    from paper_1908_03876_amd import abi
-    s = _struct()
-    s.reserved = 1
+@pytest.mark.parametrize("bad", ["nspecies", "w_rate", "w_source_term"])
+def test_validate_three_species(bad):
+    """A valid three-species problem is accepted; a bad species count, a
+    bad w relaxation rate or a second-order source term with three species
+    are not."""
+    from paper_1908_03876_amd import abi, inputs
+    from paper_1908_03876_amd.solver import make_problem_struct
+    p = inputs.with_repellent(inputs.periodic_isotropic())
+    abi.mrt_validate(make_problem_struct(p, abi.MRT_F32, 64, None))
+    if bad == "nspecies":
+        s = make_problem_struct(p, abi.MRT_F32, 64, None)
+        s.nspecies = 4
+    elif bad == "w_rate":
+        s = make_problem_struct(p.copy(sw=np.array([1, 1, 1, 2.5, 1, 1, 1.0])), abi.MRT_F32,
+                                64, None)
+    else:
+        s = make_problem_struct(p.copy(source_term=3), abi.MRT_F32, 64, None)
     with pytest.raises(abi.MrtError) as e:
         abi.mrt_validate(s)
     assert e.value.code == abi.MRT_EINVAL
+
+
+def test_tape_bytes_layout_three_species():
+    """Three species: 27 planes of state and 5 record planes (u, j_v, j_w)
+    per step."""
+    from paper_1908_03876_amd import abi, inputs
+    from paper_1908_03876_amd.solver import make_problem_struct
+    p = inputs.with_repellent(inputs.periodic_isotropic()).copy(nsteps=200)
+    s3 = make_problem_struct(p, abi.MRT_F32, 64, None)
+    plane = 64 * 64 * 4
+    fwd = abi.mrt_tape_bytes(s3, 0)
+    store = abi.mrt_tape_bytes(s3, 200)
+    assert store - fwd == 2 * 27 * plane + 200 * 5 * plane
