@@ -605,13 +605,22 @@ def main():
     del dp
     torch.cuda.empty_cache()
     if args.copy_calibration:
+        # a plain 1 GiB device copy: the reference of the byte counters, and
+        # the bandwidth the runtime's own copy reaches (HIP events)
         n = (1 << 30) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
+        best = None
         for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             b.copy_(a)
-        torch.cuda.synchronize()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
         out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+        out["copy_GBps"] = round(8 * n / (best / 1e3) / 1e9, 1)
         del a, b
         torch.cuda.empty_cache()
     if args.cpu_steps > 0:
