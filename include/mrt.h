@@ -1,8 +1,8 @@
 /*
  * mrt.h - C-ABI of the MI355X (gfx950) hot path for adjoint-based optimal
  * control of a coupled anisotropic chemotaxis system with a two-species
- * D2Q9 multiple-relaxation-time lattice Boltzmann model (MRT) and its
- * adjoint (AMRT).
+ * (optionally three-species) D2Q9 multiple-relaxation-time lattice
+ * Boltzmann model (MRT) and its adjoint (AMRT).
  *
  * Method: A. Belmiloudi, "Optimal Control for Chemotaxis Systems and
  * Adjoint-Based Optimization with Multiple-Relaxation-Time Lattice Boltzmann
@@ -24,7 +24,8 @@
  *   - Floating-point fields have the grid's dtype (MRT_F32: float,
  *     MRT_F64: double), except grad_accum, which is always double.
  *   - The distribution state is SoA: population i of species s (0 = u,
- *     1 = v) of node (x, y) is at ((s*9 + i)*ny + y)*pitch + x, with the D2Q9
+ *     1 = v, 2 = w with three species) of node (x, y) is at
+ *     ((s*9 + i)*ny + y)*pitch + x, with the D2Q9
  *     velocity order e0 = 0, e1 = (1,0), e2 = (0,1), e3 = -e1, e4 = -e2,
  *     e5 = (1,1), e6 = (-1,1), e7 = -e5, e8 = -e6 (Remark on DmQq lattices).
  *   - Solid nodes (mask = 1) carry no populations: every output is 0 there.
