@@ -313,3 +313,149 @@ def tiny(seed: int = 5, L: int = 8, nsteps: int = 10, masked: bool = False,
                 alpha=1e-2, su=su, sv=sv, u0=u0, v0=v0, control=c,
                 u_target=ut, name=f"tiny_L{L}")
     return _zero_solids(p)
+
+
+# ------------------------------------------------------------ D3Q19 problems
+
+
+@dataclasses.dataclass
+class Problem3:
+    """A control problem on a D3Q19 lattice (two species, lattice units)."""
+
+    nx: int
+    ny: int
+    nz: int
+    nsteps: int
+    periodic: bool
+    solid: Optional[np.ndarray]  # uint8 [nz, ny, nx], 1 = solid, or None
+    Du: np.ndarray               # 3x3 self-diffusion tensors
+    Dv: np.ndarray
+    chi: float
+    Cchi: np.ndarray             # 3x3 shape of the chemotactic tensor
+    r_u: float = 1.0
+    a_uv: float = 1.0
+    b_v: float = 1.0
+    alpha: float = 1e-3
+    du: float = 1.0
+    dv: float = 1.0
+    su: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(16))
+    sv: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(16))
+    u0: np.ndarray = None        # [nz, ny, nx]
+    v0: np.ndarray = None
+    control: np.ndarray = None
+    u_target: np.ndarray = None
+    name: str = ""
+
+    @property
+    def fluid(self) -> np.ndarray:
+        if self.solid is None:
+            return np.ones((self.nz, self.ny, self.nx), dtype=bool)
+        return self.solid == 0
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.fluid.sum())
+
+    def copy(self, **changes) -> "Problem3":
+        p = dataclasses.replace(self, **changes)
+        for f in ("solid", "Du", "Dv", "Cchi", "su", "sv", "u0", "v0", "control", "u_target"):
+            val = getattr(p, f)
+            if isinstance(val, np.ndarray) and f not in changes:
+                setattr(p, f, val.copy())
+        return p
+
+
+def random_spd3(rng: np.random.Generator, lo: float = 0.05, hi: float = 1.0) -> np.ndarray:
+    """3x3 SPD tensor: diagonal ~ U[lo, hi], off-diagonals r sqrt(D_ii D_jj)
+    with r ~ U(-0.3, 0.3) (unit-diagonal part diagonally dominant, so SPD)."""
+    d = rng.uniform(lo, hi, size=3)
+    r = rng.uniform(-0.3, 0.3, size=3)
+    R = np.array([[1.0, r[0], r[1]], [r[0], 1.0, r[2]], [r[1], r[2], 1.0]])
+    s = np.sqrt(d)
+    return R * np.outer(s, s)
+
+
+def _bump3(shape, rng, n, sigma, periodic=True):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros(shape)
+    for _ in range(n):
+        c = rng.uniform(0, 1, size=3) * np.array([nz, ny, nx])
+        dz, dy, dx = z - c[0], y - c[1], x - c[2]
+        if periodic:
+            dz = np.minimum(np.abs(dz), nz - np.abs(dz))
+            dy = np.minimum(np.abs(dy), ny - np.abs(dy))
+            dx = np.minimum(np.abs(dx), nx - np.abs(dx))
+        out += np.exp(-(dx * dx + dy * dy + dz * dz) / (2 * sigma * sigma))
+    return out
+
+
+def _zero_solids3(p: Problem3) -> Problem3:
+    if p.solid is not None:
+        s = p.solid != 0
+        for f in ("u0", "v0", "control", "u_target"):
+            getattr(p, f)[s] = 0.0
+    return p
+
+
+def periodic_3d(seed: int = 7, L: int = 16, nsteps: int = 30) -> Problem3:
+    """Periodic cube with seeded anisotropic tensors, a control bump and a
+    target bump; kinetics r_u = a_uv = b_v = 1."""
+    rng = np.random.default_rng(seed)
+    shp = (L, L, L)
+    u0 = 1.0 + 0.1 * rng.uniform(-1, 1, size=shp)
+    return Problem3(nx=L, ny=L, nz=L, nsteps=nsteps, periodic=True, solid=None,
+                    Du=random_spd3(rng), Dv=random_spd3(rng), chi=0.5, Cchi=random_spd3(rng),
+                    u0=u0, v0=np.zeros(shp), control=2.0 * _bump3(shp, rng, 1, L / 6),
+                    u_target=1.0 + 0.5 * _bump3(shp, rng, 1, L / 6), name=f"periodic3d_L{L}")
+
+
+def masked_3d(seed: int = 8, L: int = 24, nsteps: int = 30, n_spheres: int = None,
+              rmin: int = 2, rmax: int = 4) -> Problem3:
+    """Cube with a one-cell solid frame and seeded solid spheres (centres
+    uniform, integer radii U{rmin..rmax}); tensors, bumps and kinetics as in
+    periodic_3d."""
+    rng = np.random.default_rng(seed)
+    shp = (L, L, L)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    solid = np.zeros(shp, dtype=np.uint8)
+    solid[0], solid[-1] = 1, 1
+    solid[:, 0], solid[:, -1] = 1, 1
+    solid[:, :, 0], solid[:, :, -1] = 1, 1
+    n = n_spheres if n_spheres is not None else max(1, (L * L * L) // 4000)
+    for _ in range(n):
+        c = rng.uniform(0, L, size=3)
+        r = rng.integers(rmin, rmax + 1)
+        solid[(z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2 <= r * r] = 1
+    u0 = 1.0 + 0.1 * rng.uniform(-1, 1, size=shp)
+    p = Problem3(nx=L, ny=L, nz=L, nsteps=nsteps, periodic=False, solid=solid,
+                 Du=random_spd3(rng), Dv=random_spd3(rng), chi=0.5, Cchi=random_spd3(rng),
+                 u0=u0, v0=np.zeros(shp), control=2.0 * _bump3(shp, rng, 2, L / 8, False),
+                 u_target=1.0 + 0.5 * _bump3(shp, rng, 2, L / 8, False), name=f"masked3d_L{L}")
+    return _zero_solids3(p)
+
+
+def tiny3d(seed: int = 9, nx: int = 5, ny: int = 4, nz: int = 3, nsteps: int = 6,
+           masked: bool = False) -> Problem3:
+    """Small randomised D3Q19 instance for brute-force checks."""
+    rng = np.random.default_rng(seed)
+    shp = (nz, ny, nx)
+    solid = None
+    if masked:
+        solid = np.zeros(shp, dtype=np.uint8)
+        solid[nz // 2, ny // 2, nx // 2] = 1
+        solid[0, 0, :] = 1
+    p = Problem3(nx=nx, ny=ny, nz=nz, nsteps=nsteps, periodic=not masked, solid=solid,
+                 Du=random_spd3(rng), Dv=random_spd3(rng), chi=0.7, Cchi=random_spd3(rng),
+                 r_u=0.3, a_uv=0.4, b_v=0.2, alpha=1e-2,
+                 su=rng.uniform(0.8, 1.6, size=16), sv=rng.uniform(0.8, 1.6, size=16),
+                 u0=1.0 + 0.3 * rng.uniform(-1, 1, size=shp), v0=0.5 * rng.uniform(0, 1, size=shp),
+                 control=rng.uniform(-1, 1, size=shp), u_target=1.0 + 0.5 * rng.uniform(0, 1, size=shp),
+                 name="tiny3d")
+    return _zero_solids3(p)
+
+
+def random_direction3(p: Problem3, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((p.nz, p.ny, p.nx)) * p.fluid
+    return h / np.abs(h).max()

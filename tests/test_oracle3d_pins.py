@@ -1,0 +1,257 @@
+"""Pins of the FP64 D3Q19 oracle (TEST INFRASTRUCTURE) against what the paper
+and the mathematics fix: the printed D3Q19 velocities and weights
+(tests/golden/d3q19_paper.json), lattice isotropy, the orthogonality of the
+Gram-Schmidt moment basis, the equilibrium moments, the diffusivity of the
+mass mode (dispersion relation), conservation, a one-site closed form,
+complex-step and tangent/adjoint identities, and mirror covariance."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle3d as O3
+from paper_1908_03876_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "d3q19_paper.json")
+CS2 = 1.0 / 3.0
+
+
+def test_d3q19_tables_match_print():
+    g = json.load(open(GOLD))
+    E, w, M, Minv = O3.tables()
+    np.testing.assert_array_equal(E, np.array(g["velocities"], dtype=float))
+    np.testing.assert_allclose(w, np.array(g["weights_num"]) / g["weights_den"], atol=1e-17)
+
+
+def test_d3q19_isotropy():
+    """Sum w = 1, sum w e = 0, sum w e e = Cs^2 I and the fourth-order
+    moment Cs^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc): the conditions the
+    Chapman-Enskog analysis of Section 3.1 uses."""
+    E, w, _, _ = O3.tables()
+    I3 = np.eye(3)
+    assert abs(w.sum() - 1) < 1e-15
+    np.testing.assert_allclose(w @ E, 0, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", w, E, E), CS2 * I3, atol=1e-16)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, E, E, E, E)
+    iso = CS2 ** 2 * (np.einsum("ab,cd->abcd", I3, I3) + np.einsum("ac,bd->abcd", I3, I3)
+                      + np.einsum("ad,bc->abcd", I3, I3))
+    np.testing.assert_allclose(m4, iso, atol=1e-16)
+    # opposite pairs
+    for i in range(1, 19, 2):
+        np.testing.assert_array_equal(E[i + 1], -E[i])
+
+
+def test_d3q19_moment_basis():
+    """Rows of M are mutually orthogonal; row 0 is the density and rows
+    3, 5, 7 the flux components."""
+    E, _, M, Minv = O3.tables()
+    G = M @ M.T
+    np.testing.assert_allclose(G - np.diag(np.diag(G)), 0, atol=1e-12)
+    np.testing.assert_allclose(M[0], 1, atol=0)
+    for r, a in ((3, 0), (5, 1), (7, 2)):
+        np.testing.assert_allclose(M[r], E[:, a], atol=1e-15)
+    np.testing.assert_allclose(M @ Minv, np.eye(19), atol=1e-13)
+
+
+@pytest.mark.parametrize("d", [0.5, 1.0, 2.0])
+def test_d3q19_equilibrium_moments(d):
+    """(phieq) in 3-D: sum phi_eq = Theta, zero flux, second moment
+    d Cs^2 Theta I."""
+    E, _, _, _ = O3.tables()
+    _, _, weq = O3.species_ops(0.1 * np.eye(3), d)
+    assert abs(weq.sum() - 1) < 1e-15
+    np.testing.assert_allclose(weq @ E, 0, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", weq, E, E), d * CS2 * np.eye(3), atol=1e-15)
+
+
+def test_d3q19_mrt_reduces_to_bgk():
+    """All free rates s and K = s I (D = d Cs^2 tau (1/s - 1/2) I) give
+    C = s I."""
+    s = 1.3
+    D = CS2 * (1 / s - 0.5) * np.eye(3)
+    K, C, _ = O3.species_ops(D, 1.0, s * np.ones(16))
+    np.testing.assert_allclose(K, s * np.eye(3), atol=1e-14)
+    np.testing.assert_allclose(C, s * np.eye(19), atol=1e-13)
+
+
+def _dispersion3(D, d=1.0, s=None, h=2e-4):
+    E, _, _, _ = O3.tables()
+    _, C, weq = O3.species_ops(D, d, np.ones(16) if s is None else s)
+    A0 = np.eye(19) - C + C @ np.outer(weq, np.ones(19))
+
+    def loglam(k):
+        ev = np.linalg.eigvals(np.diag(np.exp(-1j * (E @ k))) @ A0)
+        return np.log(ev[np.argmin(np.abs(ev - 1.0))]).real
+
+    out = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            ea, eb = np.eye(3)[a] * h, np.eye(3)[b] * h
+            out[a, b] = (loglam(ea + eb) - loglam(ea - eb) - loglam(-ea + eb)
+                         + loglam(-ea - eb)) / (4 * h * h)
+    return -0.5 * out
+
+
+@pytest.mark.parametrize("d,rates", [(1.0, None), (0.7, "random")])
+def test_d3q19_dispersion_recovers_D(d, rates):
+    """D = d Cs^2 tau (K^-1 - I/2) (PC14) in 3-D: the mass mode diffuses
+    with exactly the anisotropic 3x3 tensor D."""
+    D = np.array([[0.6, 0.12, -0.05], [0.12, 0.3, 0.08], [-0.05, 0.08, 0.45]])
+    s = None if rates is None else np.random.default_rng(3).uniform(0.7, 1.5, 16)
+    np.testing.assert_allclose(_dispersion3(D, d, s), D, atol=1e-5)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_d3q19_mass_conservation(masked):
+    p = I.tiny3d(nx=7, ny=6, nz=5, nsteps=20, masked=masked).copy(r_u=0.0, a_uv=0.0, b_v=0.0)
+    p = p.copy(control=0.0 * p.control)
+    f = p.fluid
+    r = O3.forward(p)
+    assert abs(r["uN"][f].sum() / p.u0[f].sum() - 1) < 1e-13
+    assert abs(r["vN"][f].sum() / p.v0[f].sum() - 1) < 1e-13
+
+
+def test_d3q19_single_site_closed_form():
+    """1x1x1 periodic lattice: streaming is the identity, leaving the
+    kinetic recurrences."""
+    one = np.ones((1, 1, 1))
+    p = I.tiny3d(nx=1, ny=1, nz=1, nsteps=7).copy(r_u=0.7, a_uv=0.3, b_v=0.45, u0=0.3 * one,
+                                                   v0=0.2 * one, control=0.15 * one)
+    u, v = 0.3, 0.2
+    for _ in range(7):
+        u, v = u + 0.7 * u * (1 - u), v + 0.3 * u - 0.45 * v + 0.15
+    r = O3.forward(p)
+    assert abs(r["uN"].item() - u) < 1e-15 and abs(r["vN"].item() - v) < 1e-15
+
+
+def _cases3():
+    return [I.tiny3d(seed=9), I.tiny3d(seed=10, masked=True),
+            I.tiny3d(seed=11, nx=4, ny=5, nz=4).copy(du=0.7, dv=1.3)]
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_d3q19_gradient_complex_step(k):
+    p = _cases3()[k]
+    g = O3.cost_gradient(p)["grad"]
+    for seed in (1, 2):
+        h = I.random_direction3(p, seed)
+        _, dj = O3.cost_complex_step(p, h)
+        assert abs((g * h).sum() - dj) <= 1e-12 * max(abs(dj), 1e-300)
+
+
+@pytest.mark.parametrize("k", range(2))
+def test_d3q19_tlm_adjoint_dot_product(k):
+    p = _cases3()[k]
+    rng = np.random.default_rng(70 + k)
+    f = p.fluid
+    shp = (p.nz, p.ny, p.nx)
+    a, b, dc, du0, dv0 = (rng.standard_normal(shp) * f for _ in range(5))
+    duN, dvN = O3.tlm(p, dc=dc, du0=du0, dv0=dv0)
+    g, gu0, gv0 = O3.adjoint(p, a, b)
+    lhs = (a * duN).sum() + (b * dvN).sum()
+    rhs = (g * dc).sum() + (gu0 * du0).sum() + (gv0 * dv0).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_d3q19_local_jacobian_against_differences():
+    p = _cases3()[0]
+    rng = np.random.default_rng(4)
+    phi = np.concatenate([0.05 + 0.1 * rng.uniform(size=19), 0.03 + 0.05 * rng.uniform(size=19)])
+    J = O3.local_jacobian(p, phi)
+    eps = 1e-6
+    fd = np.zeros((38, 38))
+    for j in range(38):
+        e = np.zeros(38); e[j] = eps
+        fd[:, j] = (O3.collide(p, phi + e, 0.3) - O3.collide(p, phi - e, 0.3)) / (2 * eps)
+    np.testing.assert_allclose(J, fd, atol=1e-8)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_d3q19_mirror_covariance(axis):
+    """Mirroring one axis (the tensors' off-diagonal entries in that axis
+    negated) mirrors u^N and the gradient; every moment of the basis is
+    even or odd in each axis, so the free rates are unchanged."""
+    p = _cases3()[1]
+    P = np.eye(3)
+    P[2 - axis, 2 - axis] = -1.0  # array axis 0 is z, 2 is x
+    fl = lambda a: None if a is None else np.flip(a, axis=axis).copy()
+    q = p.copy(Du=P @ p.Du @ P, Dv=P @ p.Dv @ P, Cchi=P @ p.Cchi @ P, solid=fl(p.solid),
+               u0=fl(p.u0), v0=fl(p.v0), control=fl(p.control), u_target=fl(p.u_target))
+    a = O3.cost_gradient(p)
+    b = O3.cost_gradient(q)
+    np.testing.assert_allclose(b["uN"], np.flip(a["uN"], axis=axis), atol=1e-13)
+    np.testing.assert_allclose(b["grad"], np.flip(a["grad"], axis=axis), atol=1e-13)
+
+
+def _swap_xz(p):
+    """The problem with x and z exchanged: arrays transposed on axes 0, 2,
+    tensors conjugated by the exchange, and the free rates of the moments
+    that the exchange permutes (|e|^2 e_x <-> |e|^2 e_z, e_x e_y <-> e_y e_z,
+    (e_y^2 - e_z^2) e_x <-> (e_x^2 - e_y^2) e_z) swapped."""
+    P = np.array([[0.0, 0, 1], [0, 1, 0], [1, 0, 0]])
+    perm = np.arange(16)
+    for a, b in ((3, 5), (10, 11), (13, 15)):
+        perm[a], perm[b] = b, a
+    tr = lambda a: None if a is None else np.ascontiguousarray(np.transpose(a, (2, 1, 0)))
+    return p.copy(nx=p.nz, nz=p.nx, Du=P @ p.Du @ P, Dv=P @ p.Dv @ P, Cchi=P @ p.Cchi @ P,
+                  su=p.su[perm], sv=p.sv[perm], solid=tr(p.solid), u0=tr(p.u0), v0=tr(p.v0),
+                  control=tr(p.control), u_target=tr(p.u_target))
+
+
+def _exchange_symmetric_rates(s):
+    """Rates equal within each pair of moments the x<->z exchange mixes:
+    {3x^2-|e|^2, e_y^2-e_z^2} and their |e|^2 multiples span invariant
+    planes, so those rates must agree as pairs."""
+    s = s.copy()
+    s[8], s[9] = s[6], s[7]
+    return s
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_d3q19_axis_exchange_covariance(masked):
+    """Exchanging x and z maps solutions and gradients onto solutions and
+    gradients; a non-cubic box makes any x/z mix-up in streaming, the
+    chemotactic flux or the rate assignment visible."""
+    p = I.tiny3d(seed=13, nx=5, ny=4, nz=3, nsteps=6, masked=masked)
+    p = p.copy(su=_exchange_symmetric_rates(p.su), sv=_exchange_symmetric_rates(p.sv))
+    a = O3.cost_gradient(p)
+    b = O3.cost_gradient(_swap_xz(p))
+    np.testing.assert_allclose(b["uN"], np.transpose(a["uN"], (2, 1, 0)), atol=1e-13)
+    np.testing.assert_allclose(b["grad"], np.transpose(a["grad"], (2, 1, 0)), atol=1e-13)
+
+
+def _drift_ratio3(L, n):
+    """Lattice u-mode amplitude over the linearised PDE amplitude for a v
+    Fourier mode along k = 2 pi/L (1, 1, 1)."""
+    Du = 0.05 * np.eye(3)
+    Dv = np.array([[0.3, 0.05, -0.04], [0.05, 0.2, 0.06], [-0.04, 0.06, 0.25]])
+    C = np.array([[1.0, 0.2, 0.1], [0.2, 0.6, -0.15], [0.1, -0.15, 0.8]])
+    chi = 0.05
+    x = np.arange(L)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    k = 2 * np.pi / L * np.array([1.0, 1.0, 1.0])
+    phase = k[0] * X + k[1] * Y + k[2] * Z
+    zero = np.zeros((L, L, L))
+    p = I.Problem3(nx=L, ny=L, nz=L, nsteps=n, periodic=True, solid=None, Du=Du, Dv=Dv,
+                   chi=chi, Cchi=C, r_u=0.0, a_uv=0.0, b_v=0.0, u0=zero + 1.0,
+                   v0=1.0 + 0.1 * np.sin(phase), control=zero, u_target=zero)
+    du = O3.forward(p)["uN"] - 1.0
+    lu, lv = k @ Du @ k, k @ Dv @ k
+    A = chi * (k @ C @ k) * 0.1 * (np.exp(-lv * n) - np.exp(-lu * n)) / (lu - lv)
+    s, c = np.sin(phase), np.cos(phase)
+    amp = (du * s).sum() / (s * s).sum()
+    return amp / A, (du * c).sum() / (c * c).sum() / amp
+
+
+def test_d3q19_chemotactic_drift_matches_pde():
+    """Proposition 1 in 3-D: the u equation gains -div(chi u C_chi grad v).
+    Linearised about u = 1 for a decaying v mode (rate l_v = k^T D_v k), the
+    u mode amplitude is chi (k^T C k) 0.1 (e^{-l_v t} - e^{-l_u t})/(l_u - l_v).
+    The lattice agrees to within its O(k^2) error, which shrinks at about
+    second order when the wavelength grows from 16 to 24 cells."""
+    r16, _ = _drift_ratio3(16, 60)
+    r24, cos24 = _drift_ratio3(24, 60)
+    assert 0.96 < r24 < 1.01
+    assert abs(1 - r24) < 0.5 * abs(1 - r16)
+    assert abs(cos24) < 0.05

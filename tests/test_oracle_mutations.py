@@ -88,6 +88,45 @@ MUTANTS = [
      "for (int s = 0; s < 2; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming"),
 ]
 
+# the same for the D3Q19 oracle, against its own pins
+MUTANTS3 = [
+    ("D3Q19: weight of the diagonal links",
+     "(i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0)", "(i <= 6 ? 1.0 / 18.0 : 1.0 / 18.0)"),
+    ("D3Q19: Gram-Schmidt projection sign",
+     "M[k * Q + i] -= num / den * M[l * Q + i];", "M[k * Q + i] += num / den * M[l * Q + i];"),
+    ("D3Q19: K from D, half added off the diagonal",
+     "(k % 4 == 0 ? 0.5 : 0.0)", "(k % 3 == 0 ? 0.5 : 0.0)"),
+    ("D3Q19: flux block on the wrong moment",
+     "const int jr[3] = {3, 5, 7};", "const int jr[3] = {3, 5, 8};"),
+    ("D3Q19: equilibrium weight sign",
+     "(s.d - 1.0) * CS2 * (e2 - 3.0 * CS2)", "(s.d + 1.0) * CS2 * (e2 - 3.0 * CS2)"),
+    ("D3Q19: chemotactic source without its z part",
+     "double(EV[i][1]) * a[1] + double(EV[i][2]) * a[2]) /", "double(EV[i][1]) * a[1]) /"),
+    ("D3Q19: chemotactic tensor with K_v",
+     "acc += ops.u.K[a * 3 + k] * p.Cchi[k * 3 + b];", "acc += ops.v.K[a * 3 + k] * p.Cchi[k * 3 + b];"),
+    ("D3Q19: local gradient with the wrong d",
+     "local_grad(ops.v.K, p.v.d, fv, gv);\n  double A[9];\n  chem_tensor(p, ops, A);\n  T a[3];",
+     "local_grad(ops.v.K, p.u.d, fv, gv);\n  double A[9];\n  chem_tensor(p, ops, A);\n  T a[3];"),
+    ("D3Q19: dropped factor 2 in the logistic derivative",
+     "TAU * wi * p.r_u * (1.0 - 2.0 * u);", "TAU * wi * p.r_u * (1.0 - u);"),
+    ("D3Q19: transposed Jacobian in the adjoint",
+     "acc += J[r * N2 + k] * nl[r];", "acc += J[k * N2 + r] * nl[r];"),
+    ("D3Q19: bounce-back into the same direction",
+     "fnew[(s * Q + ops.opp[i]) * nc + cell] = val;", "fnew[(s * Q + i) * nc + cell] = val;"),
+    ("D3Q19: adjoint streaming without the wall reflection",
+     ": lam[(s * Q + ops.opp[i]) * nc + cell];", ": lam[(s * Q + i) * nc + cell];"),
+    ("D3Q19: gradient from the u adjoint",
+     "gc += nl[Q + i] * TAU * wgt(i);", "gc += nl[i] * TAU * wgt(i);"),
+    ("D3Q19: tangent control on u",
+     "dpost[(Q + i) * nc + cell] += TAU * wgt(i) * dc[cell];",
+     "dpost[(i) * nc + cell] += TAU * wgt(i) * dc[cell];"),
+    ("D3Q19: periodic wrap in z with ny",
+     "zn = (zn % p.nz + p.nz) % p.nz;", "zn = (zn % p.ny + p.ny) % p.ny;"),
+]
+
+CASES = ([(m, "mrt_oracle.cpp", "test_oracle_pins.py") for m in MUTANTS] +
+         [(m, "mrt3d_oracle.cpp", "test_oracle3d_pins.py") for m in MUTANTS3])
+
 
 def _copy_tree(dst):
     for d in ("oracle", "tests"):
@@ -101,26 +140,26 @@ def _copy_tree(dst):
 
 
 def test_source_texts_present_once():
-    src = open(os.path.join(ROOT, "oracle", "mrt_oracle.cpp")).read()
-    for label, old, _ in MUTANTS:
+    for (label, old, _), src_file, _ in CASES:
+        src = open(os.path.join(ROOT, "oracle", src_file)).read()
         assert src.count(old) == 1, label
 
 
 def _run_mutant(base, k):
     """Plant mutant k in a private copy under base and run the pins there;
     returns (exit code, tail of the output)."""
-    label, old, new = MUTANTS[k]
+    (label, old, new), src_file, pins = CASES[k]
     d = os.path.join(base, f"m{k}")
     os.makedirs(d)
     _copy_tree(d)
-    path = os.path.join(d, "oracle", "mrt_oracle.cpp")
+    path = os.path.join(d, "oracle", src_file)
     src = open(path).read()
     if src.count(old) != 1:
         return -1, f"{label}: source text not found once"
     open(path, "w").write(src.replace(old, new))
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=d, env=env,
+                        os.path.join("tests", pins)], cwd=d, env=env,
                        capture_output=True, text=True, timeout=600)
     return r.returncode, (r.stdout + r.stderr)[-400:]
 
@@ -133,11 +172,11 @@ def mutant_results(tmp_path_factory):
     base = str(tmp_path_factory.mktemp("mutants"))
     workers = max(1, min(8, (os.cpu_count() or 2)))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        return list(ex.map(lambda k: _run_mutant(base, k), range(len(MUTANTS))))
+        return list(ex.map(lambda k: _run_mutant(base, k), range(len(CASES))))
 
 
-@pytest.mark.parametrize("k", range(len(MUTANTS)), ids=[m[0] for m in MUTANTS])
+@pytest.mark.parametrize("k", range(len(CASES)), ids=[c[0][0] for c in CASES])
 def test_planted_mistake_fails_a_pin(mutant_results, k):
     rc, tail = mutant_results[k]
     # exit code 1: tests ran and at least one failed (not a build error)
-    assert rc == 1 and "failed" in tail, f"{MUTANTS[k][0]}: pins did not catch it\n{tail}"
+    assert rc == 1 and "failed" in tail, f"{CASES[k][0][0]}: pins did not catch it\n{tail}"
