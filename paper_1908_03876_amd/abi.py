@@ -1,4 +1,4 @@
-"""ctypes binding of the C-ABI in include/mrt.h (argument marshalling only).
+"""ctypes binding of the C-ABI in include/mrt.h and include/mrt3.h (argument marshalling only).
 
 Every function here has the name of the C entry point it calls.  Device
 memory comes from torch tensors (``data_ptr()``), streams from
@@ -69,6 +69,25 @@ class mrt_batch_tiles(ctypes.Structure):
                 ("ms_per_step", ctypes.c_double)]
 
 
+class mrt3_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("periodic", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mask", ctypes.c_void_p)]
+
+
+class mrt3_species(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double * 9), ("d", ctypes.c_double),
+                ("s", ctypes.c_double * 16)]
+
+
+class mrt3_problem(ctypes.Structure):
+    _fields_ = [("grid", mrt3_grid), ("u", mrt3_species), ("v", mrt3_species),
+                ("chi", ctypes.c_double), ("Cchi", ctypes.c_double * 9),
+                ("r_u", ctypes.c_double), ("a_uv", ctypes.c_double),
+                ("b_v", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
 MRT_FIELD_U0, MRT_FIELD_V0, MRT_FIELD_CONTROL, MRT_FIELD_TARGET = 0, 1, 2, 3
 MRT_FIELD_UN, MRT_FIELD_VN, MRT_FIELD_GRAD = 4, 5, 6
 
@@ -85,7 +104,10 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_srg_sync",
            "mrt_srg_forward", "mrt_srg_backward", "mrt_srg_loss",
            "mrt_srg_train_step", "mrt_srg_gather", "mrt_srg_objective",
-           "mrt_srg_score_steps", "mrt_srg_warm_start"]
+           "mrt_srg_score_steps", "mrt_srg_warm_start",
+           "mrt3_validate", "mrt3_tape_bytes", "mrt3_tape_create", "mrt3_tape_destroy",
+           "mrt3_tape_query", "mrt3_forward", "amrt3_adjoint", "mrt3_tlm",
+           "mrt3_cost_gradient", "mrt3_gd_step"]
 
 
 def _load():
@@ -151,6 +173,19 @@ def _load():
     L.mrt_srg_score_steps.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), i32, vp, vp, dbl,
                                       i32, i32, ctypes.POINTER(dbl), vp]
     L.mrt_srg_warm_start.argtypes = [vp, vp, vp, dbl, i32, i32, i32, f32, vp, vp]
+    P3 = ctypes.POINTER(mrt3_problem)
+    L.mrt3_validate.argtypes = [P3]
+    L.mrt3_tape_bytes.argtypes = [P3, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.mrt3_tape_create.argtypes = [P3, i32, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.mrt3_tape_destroy.argtypes = [vp]
+    L.mrt3_tape_destroy.restype = None
+    L.mrt3_tape_query.argtypes = [vp, ctypes.POINTER(mrt_tape_info)]
+    L.mrt3_forward.argtypes = [P3, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.amrt3_adjoint.argtypes = [P3, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mrt3_tlm.argtypes = [P3, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mrt3_cost_gradient.argtypes = [P3, vp, vp, vp, vp, vp, vp, vp,
+                                     ctypes.POINTER(mrt_scalars), vp]
+    L.mrt3_gd_step.argtypes = [P3, vp, vp, vp, dbl, dbl, dbl, ctypes.POINTER(dbl), vp]
     return L
 
 
@@ -429,3 +464,69 @@ def mrt_srg_score_steps(s, c, E, lambdas, u_base, u_target, alpha, H, W, stream=
 def mrt_srg_warm_start(s, u_base, u_target, alpha, H, W, iters, lr, c, stream=None) -> None:
     _check(lib.mrt_srg_warm_start(s, _ptr(u_base), _ptr(u_target), float(alpha), int(H),
                                   int(W), int(iters), float(lr), _ptr(c), _stream(stream)))
+
+
+# ----------------------------------------------------------- D3Q19 (mrt3.h)
+
+def mrt3_validate(p: mrt3_problem) -> None:
+    _check(lib.mrt3_validate(ctypes.byref(p)))
+
+
+def mrt3_tape_bytes(p: mrt3_problem, ckpt_every: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.mrt3_tape_bytes(ctypes.byref(p), int(ckpt_every), ctypes.byref(n)))
+    return n.value
+
+
+def mrt3_tape_create(p: mrt3_problem, ckpt_every: int, mem_budget: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.mrt3_tape_create(ctypes.byref(p), int(ckpt_every), int(mem_budget),
+                                ctypes.byref(h)))
+    return h
+
+
+def mrt3_tape_destroy(tape) -> None:
+    lib.mrt3_tape_destroy(tape)
+
+
+def mrt3_tape_query(tape) -> mrt_tape_info:
+    info = mrt_tape_info()
+    _check(lib.mrt3_tape_query(tape, ctypes.byref(info)))
+    return info
+
+
+def mrt3_forward(p, tape, u0, v0, control, state=None, uN=None, vN=None, stream=None) -> None:
+    _check(lib.mrt3_forward(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control),
+                            _ptr(state), _ptr(uN), _ptr(vN), _stream(stream)))
+
+
+def amrt3_adjoint(p, tape, u0, v0, control, seed_u, seed_v, grad_accum, adj_u0=None,
+                  adj_v0=None, stream=None) -> None:
+    _check(lib.amrt3_adjoint(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control),
+                             _ptr(seed_u), _ptr(seed_v), _ptr(grad_accum), _ptr(adj_u0),
+                             _ptr(adj_v0), _stream(stream)))
+
+
+def mrt3_tlm(p, tape, u0, v0, control, dc=None, du0=None, dv0=None, duN=None, dvN=None,
+             stream=None) -> None:
+    _check(lib.mrt3_tlm(ctypes.byref(p), tape, _ptr(u0), _ptr(v0), _ptr(control), _ptr(dc),
+                        _ptr(du0), _ptr(dv0), _ptr(duN), _ptr(dvN), _stream(stream)))
+
+
+def mrt3_cost_gradient(p, tape, uN, u_target, control, grad_accum=None, seed_out=None,
+                       grad_out=None, stream=None) -> dict:
+    s = mrt_scalars()
+    _check(lib.mrt3_cost_gradient(ctypes.byref(p), tape, _ptr(uN), _ptr(u_target),
+                                  _ptr(control), _ptr(grad_accum), _ptr(seed_out),
+                                  _ptr(grad_out), ctypes.byref(s), _stream(stream)))
+    return {"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
+            "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid}
+
+
+def mrt3_gd_step(p, tape, control, grad, zeta=0.0, lo=-math.inf, hi=math.inf,
+                 want_zeta=True, stream=None):
+    z = ctypes.c_double(0.0)
+    _check(lib.mrt3_gd_step(ctypes.byref(p), tape, _ptr(control), _ptr(grad), float(zeta),
+                            float(lo), float(hi), ctypes.byref(z) if want_zeta else None,
+                            _stream(stream)))
+    return z.value if want_zeta else None

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmrt.so")
 
-SOURCES = ["mrt_kernels.hip", "batch_kernels.hip", "srg_kernels.hip", "mrt_abi.cpp",
+SOURCES = ["mrt_kernels.hip", "batch_kernels.hip", "srg_kernels.hip", "mrt3_kernels.hip",
+           "mrt_abi.cpp", "mrt3_abi.cpp",
            "mrt_batch.cpp", "mrt_srg.cpp"]
 
 

@@ -264,6 +264,29 @@ namespace mrt {
 namespace host {
 int validate(const mrt_problem* p) { return ::validate(p); }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+int failf(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+void* span_begin(int kind, hipStream_t s) {
+  SpanGuard* g = new SpanGuard(kind, s);
+  if (!g->active) {
+    delete g;
+    return nullptr;
+  }
+  return g;
+}
+void span_end(void* span, int64_t launches) {
+  if (!span) return;
+  SpanGuard* g = static_cast<SpanGuard*>(span);
+  g->span.launches = launches;
+  delete g;
+}
 template <typename T>
 ModelCoef<T> model_coef(const mrt_problem* p) {
   return ::model_coef<T>(p);

@@ -411,22 +411,28 @@ def periodic_3d(seed: int = 7, L: int = 16, nsteps: int = 30) -> Problem3:
 
 
 def masked_3d(seed: int = 8, L: int = 24, nsteps: int = 30, n_spheres: int = None,
-              rmin: int = 2, rmax: int = 4) -> Problem3:
-    """Cube with a one-cell solid frame and seeded solid spheres (centres
-    uniform, integer radii U{rmin..rmax}); tensors, bumps and kinetics as in
-    periodic_3d."""
+              rmin: int = None, rmax: int = None) -> Problem3:
+    """Cube with a one-cell solid frame and seeded solid spheres (a porous
+    medium: centres uniform, integer radii U{rmin..rmax}, by default
+    max(2, L/64)..max(4, L/24) and max(3, L^3/16000) spheres, about 9% of
+    the volume at L = 256); tensors, bumps and kinetics as in periodic_3d."""
     rng = np.random.default_rng(seed)
     shp = (L, L, L)
-    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    rmin = max(2, L // 64) if rmin is None else rmin
+    rmax = max(4, L // 24) if rmax is None else rmax
     solid = np.zeros(shp, dtype=np.uint8)
     solid[0], solid[-1] = 1, 1
     solid[:, 0], solid[:, -1] = 1, 1
     solid[:, :, 0], solid[:, :, -1] = 1, 1
-    n = n_spheres if n_spheres is not None else max(1, (L * L * L) // 4000)
+    n = n_spheres if n_spheres is not None else max(3, (L * L * L) // 16000)
     for _ in range(n):
         c = rng.uniform(0, L, size=3)
-        r = rng.integers(rmin, rmax + 1)
-        solid[(z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2 <= r * r] = 1
+        r = int(rng.integers(rmin, rmax + 1))
+        lo = [max(0, int(np.floor(c[k] - r))) for k in range(3)]
+        hi = [min(L, int(np.ceil(c[k] + r)) + 1) for k in range(3)]
+        z, y, x = np.ogrid[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        ball = (z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2 <= r * r
+        solid[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] |= ball.astype(np.uint8)
     u0 = 1.0 + 0.1 * rng.uniform(-1, 1, size=shp)
     p = Problem3(nx=L, ny=L, nz=L, nsteps=nsteps, periodic=False, solid=solid,
                  Du=random_spd3(rng), Dv=random_spd3(rng), chi=0.5, Cchi=random_spd3(rng),
@@ -459,3 +465,21 @@ def random_direction3(p: Problem3, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     h = rng.standard_normal((p.nz, p.ny, p.nx)) * p.fluid
     return h / np.abs(h).max()
+
+
+def ragged_3d(seed: int, nx: int, ny: int, nz: int, nsteps: int, periodic: bool,
+              masked: bool, solid_frac: float = 0.06) -> Problem3:
+    """Box of any shape with seeded tensors, rates, kinetics and fields;
+    masked: each node solid with probability solid_frac (seeded)."""
+    rng = np.random.default_rng(seed)
+    shp = (nz, ny, nx)
+    solid = (rng.uniform(size=shp) < solid_frac).astype(np.uint8) if masked else None
+    p = Problem3(nx=nx, ny=ny, nz=nz, nsteps=nsteps, periodic=periodic, solid=solid,
+                 Du=random_spd3(rng), Dv=random_spd3(rng), chi=0.3, Cchi=random_spd3(rng),
+                 r_u=0.3, a_uv=0.4, b_v=0.2, alpha=1e-2,
+                 su=rng.uniform(0.8, 1.6, size=16), sv=rng.uniform(0.8, 1.6, size=16),
+                 u0=1.0 + 0.3 * rng.uniform(-1, 1, size=shp), v0=0.5 * rng.uniform(0, 1, size=shp),
+                 control=0.2 * rng.uniform(-1, 1, size=shp),
+                 u_target=1.0 + 0.5 * rng.uniform(0, 1, size=shp),
+                 name=f"ragged3d_{nx}x{ny}x{nz}")
+    return _zero_solids3(p)

@@ -10,13 +10,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mrt.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("mrt.h", "mrt3.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(\w+)\s*\([^;{]*\)\s*;", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(\w+)\s*\([^;{]*\)\s*;", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -24,6 +27,7 @@ def test_library_exports_every_declared_symbol():
     names = _declared()
     assert "mrt_forward" in names and "amrt_adjoint" in names
     assert "cost_gradient" in names and "gd_step" in names
+    assert "mrt3_forward" in names and "amrt3_adjoint" in names
     for n in names:
         assert hasattr(abi.lib, n), n
     assert sorted(abi.EXPORTS) == names
@@ -146,3 +150,75 @@ def test_tape_bytes_layout_three_species():
     fwd = abi.mrt_tape_bytes(s3, 0)
     store = abi.mrt_tape_bytes(s3, 200)
     assert store - fwd == 2 * 27 * plane + 200 * 5 * plane
+
+
+# ------------------------------------------------------------------ D3Q19
+
+def _struct3(**kw):
+    from paper_1908_03876_amd import abi, inputs
+    from paper_1908_03876_amd.solver3 import make_problem3_struct
+    p = inputs.tiny3d().copy(**kw)
+    return make_problem3_struct(p, abi.MRT_F32, 64, None)
+
+
+def test_validate3_accepts_workloads():
+    from paper_1908_03876_amd import abi, inputs
+    from paper_1908_03876_amd.solver3 import make_problem3_struct
+    abi.mrt3_validate(_struct3())
+    for p in (inputs.masked_3d(L=24), inputs.periodic_3d(L=16),
+              inputs.ragged_3d(1, 300, 6, 5, 10, True, True)):
+        abi.mrt3_validate(make_problem3_struct(p, abi.MRT_F64, 320, None))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("nz", 0), ("ny", 5000), ("pitch", 3), ("nsteps", 0), ("dtype", 5),
+    ("periodic", 2), ("reserved", 1)])
+def test_validate3_rejects_bad_grid(field, value):
+    from paper_1908_03876_amd import abi
+    s = _struct3()
+    setattr(s.grid, field, value)
+    with pytest.raises(abi.MrtError) as e:
+        abi.mrt3_validate(s)
+    assert e.value.code == abi.MRT_EINVAL
+
+
+def test_validate3_rejects_oversized_plane():
+    from paper_1908_03876_amd import abi
+    s = _struct3()
+    s.grid.nx, s.grid.ny, s.grid.nz, s.grid.pitch = 4096, 4096, 128, 4096
+    with pytest.raises(abi.MrtError):
+        abi.mrt3_validate(s)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(Du=-np.eye(3)), dict(Dv=np.array([[1.0, 0.5, 0], [0.4, 1.0, 0], [0, 0, 1.0]])),
+    dict(Du=np.array([[1.0, 2.0, 0], [2.0, 1.0, 0], [0, 0, 1.0]])), dict(du=0.0),
+    dict(su=np.full(16, 2.0)), dict(sv=np.r_[np.ones(15), 0.0]), dict(chi=math.nan),
+    dict(alpha=-1.0), dict(Cchi=np.full((3, 3), math.inf))])
+def test_validate3_rejects_bad_model(kw):
+    from paper_1908_03876_amd import abi
+    with pytest.raises(abi.MrtError) as e:
+        abi.mrt3_validate(_struct3(**kw))
+    assert e.value.code == abi.MRT_EINVAL
+
+
+def test_tape3_bytes_layout():
+    """Two states (38 planes each), the reduction buffers, and with the
+    adjoint two more states, K record slots of 4 planes and one state per
+    checkpoint after the first; a mask adds 4 + 2 bytes per node and the
+    per-segment flags."""
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import make_problem3_struct
+    from paper_1908_03876_amd import inputs
+    p = inputs.tiny3d(nsteps=10)
+    pitch = 64
+    plane = p.nz * p.ny * pitch
+    red = (1024 * 5 + 16) * 8
+    for code, e in ((abi.MRT_F32, 4), (abi.MRT_F64, 8)):
+        s = make_problem3_struct(p, code, pitch, None)
+        state = 38 * plane * e
+        assert abi.mrt3_tape_bytes(s, 0) == 2 * state + red
+        assert abi.mrt3_tape_bytes(s, 10) == 4 * state + red + 10 * 4 * plane * e
+        assert abi.mrt3_tape_bytes(s, 3) == 4 * state + red + 3 * state + 3 * 4 * plane * e
+        sm = make_problem3_struct(p, code, pitch, 12345)
+        assert abi.mrt3_tape_bytes(sm, 0) == 2 * state + red + plane * 6 + p.nz * p.ny * 4

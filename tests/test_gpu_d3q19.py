@@ -1,0 +1,200 @@
+"""The D3Q19 path on the device (mrt3 C-ABI) against the FP64 D3Q19 oracle:
+forward state, cost and AMRT gradient on periodic, walled, masked, ragged
+and one-node lattices; general seeds with the initial sensitivities; the
+tangent-linear model; checkpointed = store-all; the gradient step; and the
+TLM/AMRT identity at the 256^3 masked size."""
+import numpy as np
+import pytest
+
+from oracle import oracle3d as O3
+from paper_1908_03876_amd import inputs as I
+from tests.gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": (1e-12, 1e-12), "f32": (1e-5, 1e-4)}
+
+
+def _dtype(name):
+    import torch
+    return torch.float64 if name == "f64" else torch.float32
+
+
+def _problem(name):
+    if name == "tiny_periodic":
+        return I.tiny3d(seed=9)
+    if name == "tiny_walls_masked":
+        return I.tiny3d(seed=10, masked=True)
+    if name == "ragged_masked_periodic":
+        return I.ragged_3d(21, 300, 6, 5, 10, True, True)
+    if name == "ragged_walls":
+        return I.ragged_3d(22, 70, 9, 8, 12, False, False)
+    if name == "masked_spheres":
+        return I.masked_3d(seed=8, L=24, nsteps=20)
+    if name == "single_site":
+        return I.ragged_3d(23, 1, 1, 1, 7, True, False).copy(chi=0.8)
+    raise KeyError(name)
+
+
+CASES = ["tiny_periodic", "tiny_walls_masked", "ragged_masked_periodic", "ragged_walls",
+         "masked_spheres", "single_site"]
+
+
+def device_gradient3(p, dtype, ckpt_every=-1, seed_v=None, want_adj0=False):
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, Tape3
+    dp = DeviceProblem3(p, dtype=dtype)
+    tape = Tape3(dp, ckpt_every)
+    uN, vN = dp.empty_field(), dp.empty_field()
+    state = dp.state_tensor()
+    seed, grad = dp.empty_field(), dp.empty_field()
+    gacc = dp.empty_field(torch.float64)
+    c = dp.control
+    abi.mrt3_forward(dp.struct, tape.handle, dp.u0, dp.v0, c, state, uN, vN)
+    r1 = abi.mrt3_cost_gradient(dp.struct, tape.handle, uN, dp.u_target, c, None, seed, None)
+    sv = None if seed_v is None else dp.field(seed_v)
+    au0 = dp.empty_field() if want_adj0 else None
+    av0 = dp.empty_field() if want_adj0 else None
+    abi.amrt3_adjoint(dp.struct, tape.handle, dp.u0, dp.v0, c, seed, sv, gacc, au0, av0)
+    r2 = abi.mrt3_cost_gradient(dp.struct, tape.handle, uN, dp.u_target, c, gacc, None, grad)
+    torch.cuda.synchronize()
+    out = {"uN": dp.host(uN), "vN": dp.host(vN), "seed": dp.host(seed), "gacc": dp.host(gacc),
+           "grad": dp.host(grad), "J": r1["J"], "grad_inf": r2["grad_inf"],
+           "grad_l2": r2["grad_l2"], "n_fluid": r1["n_fluid"],
+           "state": state[..., : dp.nx].double().cpu().numpy(), "tape": tape.info.mode}
+    if want_adj0:
+        out["adj_u0"], out["adj_v0"] = dp.host(au0), dp.host(av0)
+    tape.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", CASES)
+def test_d3q19_forward_and_gradient_parity(name, prec):
+    p = _problem(name)
+    print(f"case {name} {prec} {p.nx}x{p.ny}x{p.nz} N={p.nsteps}", flush=True)
+    ref = O3.cost_gradient(p)
+    fwd = O3.forward(p, want_state=True)
+    f = p.fluid
+    dev = device_gradient3(p, _dtype(prec))
+    ftol, gtol = TOL[prec]
+    assert dev["n_fluid"] == int(f.sum())
+    assert rel_l2(dev["uN"], fwd["uN"], f) <= ftol
+    assert rel_l2(dev["vN"], fwd["vN"], f) <= ftol
+    assert rel_l2(dev["state"], fwd["state"]) <= ftol
+    assert abs(dev["J"] - ref["J"]) <= max(ftol, 1e-13) * abs(ref["J"]) * 10
+    assert rel_l2(dev["grad"], ref["grad"], f) <= gtol
+    gin = np.abs(ref["grad"][f]).max()
+    assert abs(dev["grad_inf"] - gin) <= gtol * gin
+    if p.solid is not None:
+        s = p.solid != 0
+        assert np.all(dev["state"][:, :, s] == 0) and np.all(dev["grad"][s] == 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_d3q19_general_seed_and_initial_sensitivity(prec):
+    p = I.ragged_3d(24, 40, 7, 6, 9, False, True)
+    rng = np.random.default_rng(5)
+    f = p.fluid
+    shp = (p.nz, p.ny, p.nx)
+    a = rng.standard_normal(shp) * f
+    b = rng.standard_normal(shp) * f
+    g, gu0, gv0 = O3.adjoint(p, a, b)
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, Tape3
+    dp = DeviceProblem3(p, dtype=_dtype(prec))
+    tape = Tape3(dp, -1)
+    abi.mrt3_forward(dp.struct, tape.handle, dp.u0, dp.v0, dp.control)
+    gacc = dp.empty_field(torch.float64)
+    au0, av0 = dp.empty_field(), dp.empty_field()
+    abi.amrt3_adjoint(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, dp.field(a),
+                      dp.field(b), gacc, au0, av0)
+    torch.cuda.synchronize()
+    tol = TOL[prec][1]
+    assert rel_l2(dp.host(gacc), g, f) <= tol
+    assert rel_l2(dp.host(au0), gu0, f) <= tol
+    assert rel_l2(dp.host(av0), gv0, f) <= tol
+    tape.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["tiny_walls_masked", "ragged_masked_periodic"])
+def test_d3q19_tlm_parity(name, prec):
+    p = _problem(name)
+    rng = np.random.default_rng(11)
+    f = p.fluid
+    shp = (p.nz, p.ny, p.nx)
+    dc, du0, dv0 = (rng.standard_normal(shp) * f for _ in range(3))
+    duN, dvN = O3.tlm(p, dc=dc, du0=du0, dv0=dv0)
+    import torch
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, GradientIteration3
+    dp = DeviceProblem3(p, dtype=_dtype(prec))
+    it = GradientIteration3(dp, ckpt_every=3)
+    it.forward()
+    d_u, d_v = it.tlm(dc=dp.field(dc), du0=dp.field(du0), dv0=dp.field(dv0))
+    torch.cuda.synchronize()
+    tol = TOL[prec][1]
+    assert rel_l2(dp.host(d_u), duN, f) <= tol
+    assert rel_l2(dp.host(d_v), dvN, f) <= tol
+    it.close()
+
+
+def test_d3q19_checkpointed_tape_equals_store_all():
+    """Recomputed segments reproduce the recorded trajectory bit for bit."""
+    import torch
+    p = _problem("masked_spheres").copy(nsteps=11)
+    a = device_gradient3(p, torch.float32, ckpt_every=-1, want_adj0=True)
+    b = device_gradient3(p, torch.float32, ckpt_every=4, want_adj0=True)
+    assert a["tape"] == 1 and b["tape"] == 2
+    for k in ("uN", "vN", "state", "gacc", "grad", "adj_u0", "adj_v0"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_d3q19_gd_step_heuristic():
+    """zeta = min(1, 1/||E||_inf) and c <- c - zeta E on fluid nodes."""
+    import torch
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, GradientIteration3
+    p = _problem("ragged_masked_periodic")
+    dp = DeviceProblem3(p, dtype=torch.float64)
+    c0 = dp.host(dp.control)
+    it = GradientIteration3(dp)
+    r = it.step()
+    torch.cuda.synchronize()
+    E = dp.host(it.grad)
+    ref = O3.cost_gradient(p)
+    assert rel_l2(E, ref["grad"], p.fluid) <= 1e-12
+    z = min(1.0, 1.0 / np.abs(E[p.fluid]).max())
+    assert abs(r["zeta"] - z) <= 1e-15 * z
+    np.testing.assert_allclose(dp.host(dp.control), (c0 - z * E) * p.fluid, atol=1e-15)
+    it.close()
+
+
+def test_d3q19_tlm_adjoint_identity_at_256():
+    """<a, du^N(dc)> = <g(a), dc> between the device TLM and the device AMRT
+    on the 256^3 masked workload (FP32, checkpointed): the discrete adjoint
+    identity at a size the oracle cannot run."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, Tape3
+    p = I.masked_3d(seed=8, L=256, nsteps=40)
+    rng = np.random.default_rng(6)
+    f = p.fluid
+    shp = (p.nz, p.ny, p.nx)
+    a = rng.standard_normal(shp, dtype=np.float32) * f
+    dc = rng.standard_normal(shp, dtype=np.float32) * f
+    dp = DeviceProblem3(p, dtype=torch.float32)
+    tape = Tape3(dp, 10)
+    at, dct = dp.field(a), dp.field(dc)
+    abi.mrt3_forward(dp.struct, tape.handle, dp.u0, dp.v0, dp.control)
+    duN = dp.empty_field()
+    abi.mrt3_tlm(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, dct, None, None, duN, None)
+    g = dp.empty_field(torch.float64)
+    abi.amrt3_adjoint(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, at, None, g)
+    torch.cuda.synchronize()
+    lhs = float((dp.host(duN) * a).sum())
+    rhs = float((dp.host(g) * dc).sum())
+    print(f"256^3: <a, duN> = {lhs:.9e}, <g, dc> = {rhs:.9e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    tape.close()
