@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "mrt3_internal.h"
+#include "mrt_host.h"
 #include "mrt_internal.h"
 
 using mrt::host::failf;

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "mrt_host.h"
 #include "mrt_internal.h"
 
 namespace {

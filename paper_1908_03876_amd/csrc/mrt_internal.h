@@ -191,13 +191,6 @@ namespace mrt {
 namespace host {
 int validate(const mrt_problem* p);        // MRT_OK or MRT_EINVAL, sets the error
 int set_error(int code, const char* msg);  // records a message, returns code
-// printf-style set_error
-int failf(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-// Timed span of a step loop for mrt_timing_read (kind 0 forward, 1
-// adjoint, 2 recomputation, 3 tangent, 4 continuous adjoint): span_begin
-// returns null when timing is off; span_end records `launches` kernels.
-void* span_begin(int kind, hipStream_t s);
-void span_end(void* span, int64_t launches);
 template <typename T>
 ModelCoef<T> model_coef(const mrt_problem* p);
 template <typename T>
