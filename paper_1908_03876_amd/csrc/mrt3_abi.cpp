@@ -102,6 +102,9 @@ int validate3(const mrt3_problem* p) {
   if (g.pitch < g.nx) return failf(MRT_EINVAL, "pitch %d < nx %d", g.pitch, g.nx);
   if (double(g.nz) * double(g.ny) * double(g.pitch) >= 2147483648.0)
     return failf(MRT_EINVAL, "nz * ny * pitch must be < 2^31");
+  if (mrt3::internal_plane(g.nx, g.ny, g.nz) >= (size_t(1) << 29))
+    return failf(MRT_EINVAL, "lattice too large: (nz + 2)(ny + 2) * roundup(nx + 1, 64) "
+                             "must be < 2^29");
   if (g.nsteps < 1) return failf(MRT_EINVAL, "nsteps %d < 1", g.nsteps);
   if (g.dtype != MRT_F32 && g.dtype != MRT_F64)
     return failf(MRT_EINVAL, "unknown dtype %d", g.dtype);
@@ -176,15 +179,19 @@ mrt3::Model3Coef<T> model_coef3(const mrt3_problem* p) {
 
 struct Layout3 {
   int mode, K, nseg;
-  size_t plane, elem, state_bytes, rec_slot_bytes, total;
+  size_t plane, planeI, elem, state_bytes, rec_slot_bytes, total;
 };
+
+// Link words are in use with a mask and on every non-periodic lattice.
+bool uses_links(const mrt3_grid& g) { return g.mask != nullptr || g.periodic == 0; }
 
 Layout3 plan3(const mrt3_problem* p, int ckpt_every) {
   Layout3 L{};
   const mrt3_grid& g = p->grid;
   L.plane = size_t(g.nz) * size_t(g.ny) * size_t(g.pitch);
+  L.planeI = mrt3::internal_plane(g.nx, g.ny, g.nz);
   L.elem = g.dtype == MRT_F64 ? 8 : 4;
-  L.state_bytes = size_t(2 * mrt3::Q) * L.plane * L.elem;
+  L.state_bytes = size_t(2 * mrt3::Q) * L.planeI * L.elem;
   L.rec_slot_bytes = 4 * L.plane * L.elem;
   if (ckpt_every <= 0) {
     L.mode = 0;
@@ -200,7 +207,7 @@ Layout3 plan3(const mrt3_problem* p, int ckpt_every) {
     L.nseg = (g.nsteps + ckpt_every - 1) / ckpt_every;
   }
   size_t t = 2 * L.state_bytes;
-  if (g.mask != nullptr)
+  if (uses_links(g))
     t += L.plane * (sizeof(uint32_t) + sizeof(uint16_t)) +
          size_t(g.nz) * g.ny * ((g.nx + 63) / 64) * sizeof(uint32_t);
   t += (size_t(mrt::kRedBlocks) * mrt::kRedSlots + 16) * sizeof(double);
@@ -217,8 +224,9 @@ Layout3 plan3(const mrt3_problem* p, int ckpt_every) {
 
 struct mrt3_tape {
   int nx, ny, nz, pitch, nsteps, dtype, periodic, masked, device;
+  int has_mask;              // a solid mask was given (masked: link words in use)
   int mode, K, nseg;
-  size_t plane, elem, state_bytes, rec_slot_bytes, total_bytes;
+  size_t plane, planeI, elem, state_bytes, rec_slot_bytes, total_bytes;
   void* buf[2] = {nullptr, nullptr};
   void* abuf[2] = {nullptr, nullptr};
   std::vector<void*> ckpt;   // ckpt[s] (s >= 1): post-collision state of step sK-1
@@ -243,10 +251,10 @@ namespace {
 int check_tape3(const mrt3_problem* p, const mrt3_tape* t) {
   if (!t) return failf(MRT_EINVAL, "tape is NULL");
   const mrt3_grid& g = p->grid;
-  const int masked = g.mask != nullptr ? 1 : 0;
+  const int has_mask = g.mask != nullptr ? 1 : 0;
   if (g.nx != t->nx || g.ny != t->ny || g.nz != t->nz || g.pitch != t->pitch ||
       g.nsteps != t->nsteps || g.dtype != t->dtype || g.periodic != t->periodic ||
-      masked != t->masked)
+      has_mask != t->has_mask)
     return failf(MRT_ESTATE, "tape was created for another grid");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
@@ -263,6 +271,8 @@ mrt3::Geometry3 geometry3(const mrt3_tape* t) {
   g.periodic = t->periodic;
   g.masked = t->masked;
   g.plane = uint32_t(t->plane);
+  g.pitchI = mrt3::internal_pitch(t->nx);
+  g.planeI = uint32_t(t->planeI);
   g.link = t->masked ? t->link : nullptr;
   g.wflag = t->masked ? t->wflag : nullptr;
   g.nsx = (t->nx + 63) / 64;
@@ -276,9 +286,9 @@ mrt::Geometry flat_geometry(const mrt3_tape* t) {
   g.ny = t->ny * t->nz;
   g.pitch = t->pitch;
   g.periodic = t->periodic;
-  g.masked = t->masked;
   g.plane = t->plane;
-  g.link = t->masked ? t->solid16 : nullptr;
+  g.masked = t->has_mask;
+  g.link = t->has_mask ? t->solid16 : nullptr;
   g.wflag = nullptr;
   g.nsx = (t->nx + 63) / 64;
   return g;
@@ -534,11 +544,13 @@ int mrt3_tape_create(const mrt3_problem* p, int32_t ckpt_every, size_t mem_budge
   t->nsteps = g.nsteps;
   t->dtype = g.dtype;
   t->periodic = g.periodic;
-  t->masked = g.mask != nullptr ? 1 : 0;
+  t->masked = uses_links(g) ? 1 : 0;
+  t->has_mask = g.mask != nullptr ? 1 : 0;
   t->mode = L.mode;
   t->K = L.K;
   t->nseg = L.nseg;
   t->plane = L.plane;
+  t->planeI = L.planeI;
   t->elem = L.elem;
   t->state_bytes = L.state_bytes;
   t->rec_slot_bytes = L.rec_slot_bytes;

@@ -115,19 +115,37 @@ struct Model3Coef {
   T r_u, a_uv, b_v;     // kinetics
 };
 
+// Fields (controls, seeds, records, outputs) use the public layout
+// [nz][ny][pitch].  The distribution buffers the library owns use an
+// internal layout with a one-node halo: node (x, y, z) at
+// ((z + 1)(ny + 2) + y + 1) pitchI + x, pitchI >= nx + 1, so that every
+// neighbour x +- e_i of a node, also outside the lattice, has a slot: the
+// padding column at x = nx (and, through the linear index, at x = -1 of
+// the next row) and the halo rows and slabs in y and z.  On a non-periodic
+// lattice the outside is solid and gets wall slots like a solid node; a
+// pull is then a uniform plane base plus one per-node offset.
 struct Geometry3 {
   int nx, ny, nz, pitch;
   int periodic;            // 1: periodic wrap; 0: walls at the lattice edge
-  int masked;              // 1: solid nodes from a mask (link words in use)
-  uint32_t plane;          // nz * ny * pitch elements (< 2^31)
+  int masked;              // 1: link words in use (a mask, or walls at the
+                           // edge of a non-periodic lattice)
+  uint32_t plane;          // public plane, nz * ny * pitch elements
+  int pitchI;              // internal row stride
+  uint32_t planeI;         // internal plane, (nz + 2)(ny + 2) pitchI elements
   const uint32_t* link;    // [nz][ny][pitch] when masked: bit 0 node solid,
-                           // bit i = node x - e_i solid (wrapped when
-                           // periodic; outside a non-periodic lattice is
-                           // handled from the coordinates)
+                           // bit i = node x - e_i solid or, on a
+                           // non-periodic lattice, outside (wrapped when
+                           // periodic)
   const uint32_t* wflag;   // [nz][ny][nsx]: 0 = a 64-node row segment and
                            // its neighbours are fluid, 1 = mixed, 2 = solid
   int nsx;                 // ceil(nx / 64)
 };
+
+// Internal row stride and plane size of a lattice.
+inline int internal_pitch(int nx) { return ((nx + 1 + 63) / 64) * 64; }
+inline size_t internal_plane(int nx, int ny, int nz) {
+  return size_t(nz + 2) * size_t(ny + 2) * size_t(internal_pitch(nx));
+}
 
 void launch_build_link3(const Geometry3& g, const uint8_t* mask, uint32_t* link,
                         uint32_t* wflag, uint16_t* solid16, hipStream_t s);
@@ -146,8 +164,8 @@ template <typename T>
 void launch_forward3(const Geometry3& g, const Model3Coef<T>& m, const Fwd3Launch<T>& a,
                      hipStream_t s);
 
-// Terminal streaming: state [2][19][plane] (may be null), u^N, v^N (may be
-// null).
+// Terminal streaming: state [2][19][plane] in the public layout (may be
+// null), u^N, v^N (may be null).
 template <typename T>
 void launch_finalize3(const Geometry3& g, const T* src, T* state, T* uN, T* vN,
                       hipStream_t s);

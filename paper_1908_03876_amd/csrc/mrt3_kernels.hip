@@ -10,11 +10,14 @@
 //
 // Design (as the D2Q9 kernels): one thread per node, 256-node row tiles
 // dealt to the 8 XCDs in contiguous bands; structure-of-arrays planes
-// [species][19][nz][ny][pitch]; pull streaming of post-collision states,
-// so each population is read once and written once per step; a population
-// streaming into a solid node is parked in that node's slot of the
-// opposite plane ("wall slot"), so the pull needs no mask test; per
-// 64-node row segment a flag lets all-fluid wavefronts skip the link word.
+// [species][19] of the haloed internal layout; pull streaming of
+// post-collision states, so each population is read once and written once
+// per step; every load is a plane base plus the node's one 32-bit offset
+// (a neighbour outside a non-periodic lattice lies in the halo); halfway
+// bounce-back reads the node's own opposite population where the link word
+// marks a wall, so no store is ever scattered and every wavefront writes
+// whole cache lines; per 64-node row segment a flag lets all-fluid
+// wavefronts skip the link word.
 #include "mrt3_internal.h"
 #include "mrt_device.h"
 
@@ -26,8 +29,18 @@ using mrt::dev::xcd_tile;
 
 struct Node3 {
   int x, y, z;
-  uint32_t idx;  // z * ny * pitch + y * pitch + x
+  uint32_t pub;  // public index (z * ny + y) * pitch + x
+  uint32_t in;   // internal index ((z + 1)(ny + 2) + y + 1) * pitchI + x
 };
+
+__device__ __forceinline__ void make_node(const Geometry3& g, int x, int y, int z, Node3& n) {
+  n.x = x;
+  n.y = y;
+  n.z = z;
+  n.pub = (uint32_t(z) * uint32_t(g.ny) + uint32_t(y)) * uint32_t(g.pitch) + uint32_t(x);
+  n.in = (uint32_t(z + 1) * uint32_t(g.ny + 2) + uint32_t(y + 1)) * uint32_t(g.pitchI) +
+         uint32_t(x);
+}
 
 __device__ __forceinline__ bool node_of_block(const Geometry3& g, Node3& n) {
   const int nbx = (g.nx + kBlock - 1) / kBlock;
@@ -38,10 +51,7 @@ __device__ __forceinline__ bool node_of_block(const Geometry3& g, Node3& n) {
   const int x = (t % nbx) * kBlock + int(threadIdx.x);
   if (x >= g.nx) return false;
   const int r = t / nbx;  // row z * ny + y
-  n.x = x;
-  n.y = r % g.ny;
-  n.z = r / g.ny;
-  n.idx = uint32_t(r) * uint32_t(g.pitch) + uint32_t(x);
+  make_node(g, x, r % g.ny, r / g.ny, n);
   return true;
 }
 
@@ -51,45 +61,87 @@ __device__ __forceinline__ unsigned wave_flag(const Geometry3& g, const Node3& n
   return g.wflag[seg];
 }
 
-// Offset of node x + (dx, dy, dz), wrapped when periodic; `out` reports a
-// node outside a non-periodic lattice (the offset is then meaningless).
+// Internal index delta of the displacement (dx, dy, dz) (wave-uniform).
+__device__ __forceinline__ int idelta(const Geometry3& g, int dx, int dy, int dz) {
+  return (dz * (g.ny + 2) + dy) * g.pitchI + dx;
+}
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Internal index of node x + (dx, dy, dz) on a periodic lattice.
+__device__ __forceinline__ uint32_t nb_in_wrapped(const Geometry3& g, const Node3& n, int dx,
+                                                  int dy, int dz) {
+  const int xx = wrap(n.x + dx, g.nx), yy = wrap(n.y + dy, g.ny), zz = wrap(n.z + dz, g.nz);
+  return (uint32_t(zz + 1) * uint32_t(g.ny + 2) + uint32_t(yy + 1)) * uint32_t(g.pitchI) +
+         uint32_t(xx);
+}
+
+// Public index of the in-lattice node x + (dx, dy, dz) (wrapped when
+// periodic).
 template <bool PERIODIC>
-__device__ __forceinline__ uint32_t nb_off(const Geometry3& g, const Node3& n, int dx, int dy,
-                                           int dz, bool& out) {
+__device__ __forceinline__ uint32_t nb_pub(const Geometry3& g, const Node3& n, int dx, int dy,
+                                           int dz) {
   int xx = n.x + dx, yy = n.y + dy, zz = n.z + dz;
   if (PERIODIC) {
-    xx = xx < 0 ? xx + g.nx : (xx >= g.nx ? xx - g.nx : xx);
-    yy = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
-    zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
-    out = false;
-  } else {
-    out = xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz;
+    xx = wrap(xx, g.nx);
+    yy = wrap(yy, g.ny);
+    zz = wrap(zz, g.nz);
   }
   return (uint32_t(zz) * uint32_t(g.ny) + uint32_t(yy)) * uint32_t(g.pitch) + uint32_t(xx);
 }
 
-// Source of the population node x pulls in direction i: plane i at x - e_i
-// (a solid neighbour's slot holds the reflected value), or the node's own
-// opposite population at the edge of a non-periodic lattice (halfway
-// bounce-back).
-template <bool PERIODIC>
-__device__ __forceinline__ size_t pull_src(const Geometry3& g, const Node3& n, int i) {
-  const Vel e = vel(i);
-  bool out;
-  const uint32_t o = nb_off<PERIODIC>(g, n, -e.x, -e.y, -e.z, out);
-  if (!PERIODIC && out) return size_t(opp(i)) * g.plane + n.idx;
-  return size_t(i) * g.plane + o;
+// Raw buffer accesses to the internal planes: a resource over one plane
+// (wave-uniform, its base shifted by the neighbour displacement) plus the
+// node's 32-bit byte offset, so that every access is one buffer
+// instruction with no per-lane 64-bit address arithmetic.  The resources
+// carry no range limit: every access is in bounds by construction (the
+// halo holds every neighbour).  Cache policy: kNT = non-temporal.
+constexpr int kNT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
 }
 
-// Adjoint gather: plane i at x + e_i (transpose of the pull), or the
-// node's own opposite value at the edge of a non-periodic lattice.
-template <bool PERIODIC>
-__device__ __forceinline__ size_t gather_src(const Geometry3& g, const Node3& n, int i) {
+template <int AUX>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, kNT);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  using U2 = unsigned __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, kNT);
+}
+
+// Population node x pulls in direction i: plane i of buf at x - e_i (the
+// halo slot outside a non-periodic lattice; a solid neighbour's value is
+// replaced by the wall read).  bo = the node's internal byte offset.
+template <typename T, bool PERIODIC, int AUX>
+__device__ __forceinline__ T pull_ld(const Geometry3& g, const Node3& n, const T* buf, int i,
+                                     uint32_t bo) {
   const Vel e = vel(i);
-  bool out;
-  const uint32_t o = nb_off<PERIODIC>(g, n, e.x, e.y, e.z, out);
-  if (!PERIODIC && out) return size_t(opp(i)) * g.plane + n.idx;
-  return size_t(i) * g.plane + o;
+  const T* pl = buf + size_t(i) * g.planeI;
+  if (PERIODIC)
+    return bload<AUX>(rsrc_of(pl), nb_in_wrapped(g, n, -e.x, -e.y, -e.z) * uint32_t(sizeof(T)),
+                      T(0));
+  return bload<AUX>(rsrc_of(pl - idelta(g, e.x, e.y, e.z)), bo, T(0));
+}
+
+// Adjoint gather: plane i of buf at x + e_i (the transpose of the pull).
+template <typename T, bool PERIODIC, int AUX>
+__device__ __forceinline__ T gather_ld(const Geometry3& g, const Node3& n, const T* buf, int i,
+                                       uint32_t bo) {
+  const Vel e = vel(i);
+  const T* pl = buf + size_t(i) * g.planeI;
+  if (PERIODIC)
+    return bload<AUX>(rsrc_of(pl), nb_in_wrapped(g, n, e.x, e.y, e.z) * uint32_t(sizeof(T)),
+                      T(0));
+  return bload<AUX>(rsrc_of(pl + idelta(g, e.x, e.y, e.z)), bo, T(0));
 }
 
 // acc (+)= r * v for a compile-time integer r (after unrolling): zero terms
@@ -236,14 +288,37 @@ __device__ __forceinline__ void add_sources(T fu[Q], T fv[Q], T phu, T ax, T ay,
   }
 }
 
+// Halfway bounce-back by own-node reads.  When the neighbour a population
+// streams from is solid (or outside a non-periodic lattice), the value is
+// the node's own opposite post-collision population of the previous step,
+// which the node stored in its own slot of the opposite plane: the pull
+// reads it there and no node ever writes into a solid node's slots.  In
+// the forward (and tangent) the wall test of direction i is bit i of the
+// link word (x - e_i solid); in the adjoint gather it is bit opp(i)
+// (x + e_i solid).  The plain pull has already been issued for every lane
+// (a solid neighbour's slot holds garbage, which is discarded here).
+template <typename T, bool ADJ>
+__device__ __forceinline__ void wall_reads(const Geometry3& g, const T* __restrict__ buf,
+                                           T f[Q], unsigned lm, uint32_t bo) {
+  T own[Q];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    own[i] = f[i];
+    if ((lm >> (ADJ ? opp(i) : i)) & 1u)
+      own[i] = bload<ADJ ? kNT : 0>(rsrc_of(buf + size_t(opp(i)) * g.planeI), bo, T(0));
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) f[i] = own[i];
+}
+
 // Pre-collision populations: the pull from src, or w~ Theta_0 at step 0.
-template <typename T, bool PERIODIC, bool FIRST>
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST>
 __device__ __forceinline__ void gather(const Geometry3& g, const Node3& n,
                                        const Model3Coef<T>& m, const T* __restrict__ src,
                                        const T* __restrict__ u0, const T* __restrict__ v0,
-                                       T fu[Q], T fv[Q]) {
+                                       T fu[Q], T fv[Q], uint32_t bo, unsigned lm) {
   if (FIRST) {
-    const T a = u0 ? u0[n.idx] : T(0), b = v0 ? v0[n.idx] : T(0);
+    const T a = u0 ? u0[n.pub] : T(0), b = v0 ? v0[n.pub] : T(0);
     fu[0] = m.u.w_rest * a;
     fv[0] = m.v.w_rest * b;
 #pragma unroll
@@ -257,40 +332,30 @@ __device__ __forceinline__ void gather(const Geometry3& g, const Node3& n,
       fv[i] = m.v.w_diag * b;
     }
   } else {
-    const T* sv = src + size_t(Q) * g.plane;
+    const T* sv = src + size_t(Q) * g.planeI;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const size_t o = pull_src<PERIODIC>(g, n, i);
-      fu[i] = src[o];
-      fv[i] = sv[o];
+      fu[i] = pull_ld<T, PERIODIC, 0>(g, n, src, i, bo);
+      fv[i] = pull_ld<T, PERIODIC, 0>(g, n, sv, i, bo);
+    }
+    if (MASKED && lm != 0u) {
+      wall_reads<T, false>(g, src, fu, lm, bo);
+      wall_reads<T, false>(g, sv, fv, lm, bo);
     }
   }
 }
 
-// Post-collision stores (non-temporal: next read a whole sweep later) and
-// the wall slots: phi*_i streaming into the solid node x + e_i is parked
-// in that node's slot of plane opp(i), which the next pull in direction
-// opp(i) at x reads.
-template <typename T, bool PERIODIC, bool MASKED>
-__device__ __forceinline__ void store_state(const Geometry3& g, const Node3& n, const T fu[Q],
-                                            const T fv[Q], T* __restrict__ dst, unsigned lm) {
-  T* dv = dst + size_t(Q) * g.plane;
+// Post-collision stores, non-temporal (next read a whole sweep later).
+// Every lane of a wavefront stores, solid nodes too (their values are never
+// read by a fluid node), so the stores always fill whole cache lines.
+template <typename T>
+__device__ __forceinline__ void store_state(const Geometry3& g, const T fu[Q], const T fv[Q],
+                                            T* __restrict__ dst, uint32_t bo) {
+  T* dv = dst + size_t(Q) * g.planeI;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    __builtin_nontemporal_store(fu[i], &dst[size_t(i) * g.plane + n.idx]);
-    __builtin_nontemporal_store(fv[i], &dv[size_t(i) * g.plane + n.idx]);
-  }
-  if (MASKED && (lm & 0x7FFFEu)) {
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if ((lm >> opp(i)) & 1u) {
-        const Vel e = vel(i);
-        bool out;
-        const size_t o = size_t(opp(i)) * g.plane + nb_off<PERIODIC>(g, n, e.x, e.y, e.z, out);
-        dst[o] = fu[i];
-        dv[o] = fv[i];
-      }
-    }
+    bstore(rsrc_of(dst + size_t(i) * g.planeI), bo, fu[i]);
+    bstore(rsrc_of(dv + size_t(i) * g.planeI), bo, fv[i]);
   }
 }
 
@@ -305,11 +370,12 @@ __global__ __launch_bounds__(kBlock) void forward3_kernel(Geometry3 g, Model3Coe
   if (MASKED) {
     const unsigned flag = wave_flag(g, n);
     if (flag == 2u) return;
-    lm = flag ? g.link[n.idx] : 0u;
+    lm = flag ? g.link[n.pub] : 0u;
   }
+  const uint32_t bo = n.in * uint32_t(sizeof(T));
   T fu[Q], fv[Q];
-  gather<T, PERIODIC, FIRST>(g, n, m, a.src, a.u0, a.v0, fu, fv);
-  const T c = a.ctrl[n.idx];
+  gather<T, PERIODIC, MASKED, FIRST>(g, n, m, a.src, a.u0, a.v0, fu, fv, bo, lm);
+  const T c = a.ctrl[n.pub];
   T u = T(0), v = T(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -320,10 +386,10 @@ __global__ __launch_bounds__(kBlock) void forward3_kernel(Geometry3 g, Model3Coe
   first_moment(fv, jx, jy, jz);
   const bool solid = MASKED && (lm & 1u);
   if (a.rec != nullptr && !solid) {
-    __builtin_nontemporal_store(u, &a.rec[n.idx]);
-    __builtin_nontemporal_store(jx, &a.rec[size_t(g.plane) + n.idx]);
-    __builtin_nontemporal_store(jy, &a.rec[2 * size_t(g.plane) + n.idx]);
-    __builtin_nontemporal_store(jz, &a.rec[3 * size_t(g.plane) + n.idx]);
+    __builtin_nontemporal_store(u, &a.rec[n.pub]);
+    __builtin_nontemporal_store(jx, &a.rec[size_t(g.plane) + n.pub]);
+    __builtin_nontemporal_store(jy, &a.rec[2 * size_t(g.plane) + n.pub]);
+    __builtin_nontemporal_store(jz, &a.rec[3 * size_t(g.plane) + n.pub]);
   }
   // A_u1 grad v = u B j_v with grad v = -K_v j_v / (tau d_v Cs^2)
   const T ax = u * (m.b[0] * jx + m.b[1] * jy + m.b[2] * jz);
@@ -335,9 +401,9 @@ __global__ __launch_bounds__(kBlock) void forward3_kernel(Geometry3 g, Model3Coe
   relax<T, false>(fu, u, m.u, t1, t2);
   relax<T, false>(fv, v, m.v, t1, t2);
   add_sources(fu, fv, phu, ax, ay, az, phv);
-  // solid nodes of mixed wavefronts computed on slots they do not own
-  if (solid) return;
-  store_state<T, PERIODIC, MASKED>(g, n, fu, fv, a.dst, lm);
+  // solid nodes of mixed wavefronts computed on values nobody reads; they
+  // store them anyway, keeping the wavefront's stores whole
+  store_state<T>(g, fu, fv, a.dst, bo);
 }
 
 template <typename T, bool PERIODIC, bool MASKED>
@@ -347,17 +413,25 @@ __global__ __launch_bounds__(kBlock) void finalize3_kernel(Geometry3 g, const T*
                                                            T* __restrict__ vN) {
   Node3 n;
   if (!node_of_block(g, n)) return;
-  const bool solid = MASKED && (g.link[n.idx] & 1u);
+  const bool solid = MASKED && (g.link[n.pub] & 1u);
+  const uint32_t bo = n.in * uint32_t(sizeof(T));
   T fu[Q], fv[Q];
   if (solid) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) fu[i] = fv[i] = T(0);
   } else {
+    const T* sv = src + size_t(Q) * g.planeI;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const size_t o = pull_src<PERIODIC>(g, n, i);
-      fu[i] = src[o];
-      fv[i] = src[size_t(Q) * g.plane + o];
+      fu[i] = pull_ld<T, PERIODIC, 0>(g, n, src, i, bo);
+      fv[i] = pull_ld<T, PERIODIC, 0>(g, n, sv, i, bo);
+    }
+    if (MASKED) {
+      const unsigned lm = g.link[n.pub];
+      if (lm != 0u) {
+        wall_reads<T, false>(g, src, fu, lm, bo);
+        wall_reads<T, false>(g, sv, fv, lm, bo);
+      }
     }
   }
   T u = T(0), v = T(0);
@@ -366,13 +440,13 @@ __global__ __launch_bounds__(kBlock) void finalize3_kernel(Geometry3 g, const T*
     u += fu[i];
     v += fv[i];
   }
-  if (uN) uN[n.idx] = u;
-  if (vN) vN[n.idx] = v;
+  if (uN) uN[n.pub] = u;
+  if (vN) vN[n.pub] = v;
   if (state) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      state[size_t(i) * g.plane + n.idx] = fu[i];
-      state[size_t(Q + i) * g.plane + n.idx] = fv[i];
+      state[size_t(i) * g.plane + n.pub] = fu[i];
+      state[size_t(Q + i) * g.plane + n.pub] = fv[i];
     }
   }
 }
@@ -392,10 +466,9 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
                                                           Adj3Launch<T> a) {
   Node3 n;
   if (!node_of_block(g, n)) return;
-  const uint32_t idx = n.idx;
+  const uint32_t idx = n.pub;
   unsigned lm = 0;
   if (MASKED) {
-    const unsigned flag = wave_flag(g, n);
     if (FIRST || LAST) {
       // single steps: solid nodes own outputs
       lm = g.link[idx];
@@ -408,33 +481,37 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
         return;
       }
     } else {
+      const unsigned flag = wave_flag(g, n);
       if (flag == 2u) return;
       lm = flag ? g.link[idx] : 0u;
     }
   }
+  const uint32_t bo = n.in * uint32_t(sizeof(T));
   T nu[Q], nv[Q];
   if (FIRST) {
-    // lambda_i^N = seed for every i; the seeds carry no wall slots
+    // lambda_i^N = seed for every i; the seeds carry no wall slots (a wall
+    // includes the outside of a non-periodic lattice)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const Vel e = vel(i);
-      bool out;
-      const uint32_t o = nb_off<PERIODIC>(g, n, e.x, e.y, e.z, out);
-      const bool wall = (!PERIODIC && out) || (MASKED && ((lm >> opp(i)) & 1u));
-      const uint32_t s = wall ? idx : o;
+      const bool wall = MASKED && ((lm >> opp(i)) & 1u);
+      const uint32_t s = wall ? idx : nb_pub<PERIODIC>(g, n, e.x, e.y, e.z);
       nu[i] = a.seed_u[s];
       nv[i] = a.seed_v ? a.seed_v[s] : T(0);
     }
   } else {
-    const T* sv = a.src + size_t(Q) * g.plane;
+    const T* sv = a.src + size_t(Q) * g.planeI;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const size_t o = gather_src<PERIODIC>(g, n, i);
-      nu[i] = __builtin_nontemporal_load(&a.src[o]);
-      nv[i] = __builtin_nontemporal_load(&sv[o]);
+      nu[i] = gather_ld<T, PERIODIC, kNT>(g, n, a.src, i, bo);
+      nv[i] = gather_ld<T, PERIODIC, kNT>(g, n, sv, i, bo);
+    }
+    if (MASKED && lm != 0u) {
+      wall_reads<T, true>(g, a.src, nu, lm, bo);
+      wall_reads<T, true>(g, sv, nv, lm, bo);
     }
   }
-  if (MASKED && (lm & 1u)) return;
+  const bool solid = MASKED && (lm & 1u);
   const T su = wsum(nu), sv = wsum(nv);
   T px, py, pz;
   first_moment(nu, px, py, pz);
@@ -445,10 +522,12 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
     py = T(1.0 / 6.0) * dya + T(1.0 / 12.0) * (py - dya);
     pz = T(1.0 / 6.0) * dza + T(1.0 / 12.0) * (pz - dza);
   }
-  if (FIRST)
-    a.g[idx] = double(sv);
-  else
-    a.g[idx] += double(sv);
+  if (!solid) {
+    if (FIRST)
+      a.g[idx] = double(sv);
+    else
+      a.g[idx] += double(sv);
+  }
   const T u = __builtin_nontemporal_load(&a.rec[idx]);
   const T jx = __builtin_nontemporal_load(&a.rec[size_t(g.plane) + idx]);
   const T jy = __builtin_nontemporal_load(&a.rec[2 * size_t(g.plane) + idx]);
@@ -496,27 +575,9 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
       a.adj_v0[idx] = m.v.w_rest * nv[0] + m.v.w_axis * ax + m.v.w_diag * dg;
     }
   } else if (a.dst) {
-    T* dst = a.dst;
-    T* dv = dst + size_t(Q) * g.plane;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      __builtin_nontemporal_store(nu[i], &dst[size_t(i) * g.plane + idx]);
-      __builtin_nontemporal_store(nv[i], &dv[size_t(i) * g.plane + idx]);
-    }
-    if (MASKED && (lm & 0x7FFFEu)) {
-      // the next gather in direction i at x reads plane i at the solid
-      // node x + e_i and must find lambda_opp(i)(x)
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        if ((lm >> opp(i)) & 1u) {
-          const Vel e = vel(i);
-          bool out;
-          const size_t o = size_t(i) * g.plane + nb_off<PERIODIC>(g, n, e.x, e.y, e.z, out);
-          dst[o] = nu[opp(i)];
-          dv[o] = nv[opp(i)];
-        }
-      }
-    }
+    // solid nodes of mixed wavefronts store values nobody reads (whole
+    // cache lines)
+    store_state<T>(g, nu, nv, a.dst, bo);
   }
 }
 
@@ -535,17 +596,18 @@ __global__ __launch_bounds__(kBlock) void tlm3_kernel(Geometry3 g, Model3Coef<T>
   if (MASKED) {
     const unsigned flag = wave_flag(g, n);
     if (flag == 2u) return;
-    lm = flag ? g.link[n.idx] : 0u;
+    lm = flag ? g.link[n.pub] : 0u;
   }
+  const uint32_t bo = n.in * uint32_t(sizeof(T));
   T fu[Q], fv[Q];
-  gather<T, PERIODIC, FIRST>(g, n, m, a.src, a.du0, a.dv0, fu, fv);
-  const T dc = a.dc ? a.dc[n.idx] : T(0);
-  const bool solid = MASKED && (lm & 1u);
-  if (solid) return;
-  const T u = __builtin_nontemporal_load(&a.rec[n.idx]);
-  const T jx = __builtin_nontemporal_load(&a.rec[size_t(g.plane) + n.idx]);
-  const T jy = __builtin_nontemporal_load(&a.rec[2 * size_t(g.plane) + n.idx]);
-  const T jz = __builtin_nontemporal_load(&a.rec[3 * size_t(g.plane) + n.idx]);
+  gather<T, PERIODIC, MASKED, FIRST>(g, n, m, a.src, a.du0, a.dv0, fu, fv, bo, lm);
+  const T dc = a.dc ? a.dc[n.pub] : T(0);
+  // solid nodes of mixed wavefronts compute on values nobody reads (their
+  // record entries are stale) and store them, keeping the stores whole
+  const T u = __builtin_nontemporal_load(&a.rec[n.pub]);
+  const T jx = __builtin_nontemporal_load(&a.rec[size_t(g.plane) + n.pub]);
+  const T jy = __builtin_nontemporal_load(&a.rec[2 * size_t(g.plane) + n.pub]);
+  const T jz = __builtin_nontemporal_load(&a.rec[3 * size_t(g.plane) + n.pub]);
   T du = T(0), dv = T(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -566,14 +628,15 @@ __global__ __launch_bounds__(kBlock) void tlm3_kernel(Geometry3 g, Model3Coef<T>
   relax<T, false>(fu, du, m.u, t1, t2);
   relax<T, false>(fv, dv, m.v, t1, t2);
   add_sources(fu, fv, phu, ax, ay, az, phv);
-  store_state<T, PERIODIC, MASKED>(g, n, fu, fv, a.dst, lm);
+  store_state<T>(g, fu, fv, a.dst, bo);
 }
 
 // ------------------------------------------------------------ link words
 
-// One thread per node: the link word (bit 0 = solid, bit i = x - e_i
-// solid), the 16-bit solid flag the reductions read, and per 64-node row
-// segment the wavefront flag.
+// One thread per node: the link word (bit 0 = solid, bit i = x - e_i solid
+// or, on a non-periodic lattice, outside), the 16-bit solid flag the
+// reductions read, and per 64-node row segment the wavefront flag.  mask
+// may be null (no solid node).
 template <bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void build_link3_kernel(Geometry3 g,
                                                              const uint8_t* __restrict__ mask,
@@ -585,24 +648,25 @@ __global__ __launch_bounds__(kBlock) void build_link3_kernel(Geometry3 g,
   const int x = (int(blockIdx.x) % nbx) * kBlock + int(threadIdx.x);
   const bool valid = r < g.ny * g.nz && x < g.nx;
   Node3 n;
-  n.x = x;
-  n.y = valid ? r % g.ny : 0;
-  n.z = valid ? r / g.ny : 0;
-  n.idx = valid ? uint32_t(r) * uint32_t(g.pitch) + uint32_t(x) : 0u;
+  make_node(g, valid ? x : 0, valid ? r % g.ny : 0, valid ? r / g.ny : 0, n);
   unsigned lw = 0;
   bool solid = true;
   if (valid) {
-    solid = mask[n.idx] != 0;
+    solid = mask != nullptr && mask[n.pub] != 0;
     lw = solid ? 1u : 0u;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const Vel e = vel(i);
-      bool out;
-      const uint32_t o = nb_off<PERIODIC>(g, n, -e.x, -e.y, -e.z, out);
-      if (!out && mask[o] != 0) lw |= 1u << i;
+      const int xx = n.x - e.x, yy = n.y - e.y, zz = n.z - e.z;
+      const bool out = xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz;
+      if (!PERIODIC && out) {
+        lw |= 1u << i;
+      } else if (mask != nullptr && mask[nb_pub<PERIODIC>(g, n, -e.x, -e.y, -e.z)] != 0) {
+        lw |= 1u << i;
+      }
     }
-    link[n.idx] = lw;
-    solid16[n.idx] = solid ? 1 : 0;
+    link[n.pub] = lw;
+    solid16[n.pub] = solid ? 1 : 0;
   }
   const uint64_t any_link = __ballot(valid && lw != 0u);
   const uint64_t any_fluid = __ballot(valid && !solid);
@@ -624,16 +688,15 @@ static dim3 grid_of(const Geometry3& g) {
 
 void launch_build_link3(const Geometry3& g, const uint8_t* mask, uint32_t* link,
                         uint32_t* wflag, uint16_t* solid16, hipStream_t s) {
-  const int nbx = (g.nx + kBlock - 1) / kBlock;
-  const dim3 grid(unsigned(nbx) * unsigned(g.ny) * unsigned(g.nz));
   if (g.periodic)
-    hipLaunchKernelGGL(build_link3_kernel<true>, grid, dim3(kBlock), 0, s, g, mask, link, wflag,
-                       solid16);
+    hipLaunchKernelGGL(build_link3_kernel<true>, grid_of(g), dim3(kBlock), 0, s, g, mask, link,
+                       wflag, solid16);
   else
-    hipLaunchKernelGGL(build_link3_kernel<false>, grid, dim3(kBlock), 0, s, g, mask, link, wflag,
-                       solid16);
+    hipLaunchKernelGGL(build_link3_kernel<false>, grid_of(g), dim3(kBlock), 0, s, g, mask, link,
+                       wflag, solid16);
 }
 
+// A non-periodic lattice always runs with link words (its edge is a wall).
 #define MRT3_DISPATCH_PM(KERNEL, ...)                                                      \
   do {                                                                                     \
     if (g.periodic) {                                                                      \
@@ -644,12 +707,8 @@ void launch_build_link3(const Geometry3& g, const uint8_t* mask, uint32_t* link,
         hipLaunchKernelGGL((KERNEL<T, true, false, ##__VA_ARGS__>), grid_of(g),            \
                            dim3(kBlock), 0, s, g, m, a);                                   \
     } else {                                                                               \
-      if (g.masked)                                                                        \
-        hipLaunchKernelGGL((KERNEL<T, false, true, ##__VA_ARGS__>), grid_of(g),            \
-                           dim3(kBlock), 0, s, g, m, a);                                   \
-      else                                                                                 \
-        hipLaunchKernelGGL((KERNEL<T, false, false, ##__VA_ARGS__>), grid_of(g),           \
-                           dim3(kBlock), 0, s, g, m, a);                                   \
+      hipLaunchKernelGGL((KERNEL<T, false, true, ##__VA_ARGS__>), grid_of(g), dim3(kBlock),  \
+                         0, s, g, m, a);                                                   \
     }                                                                                      \
   } while (0)
 
@@ -673,12 +732,8 @@ void launch_finalize3(const Geometry3& g, const T* src, T* state, T* uN, T* vN,
       hipLaunchKernelGGL((finalize3_kernel<T, true, false>), grid_of(g), dim3(kBlock), 0, s, g,
                          src, state, uN, vN);
   } else {
-    if (g.masked)
-      hipLaunchKernelGGL((finalize3_kernel<T, false, true>), grid_of(g), dim3(kBlock), 0, s, g,
-                         src, state, uN, vN);
-    else
-      hipLaunchKernelGGL((finalize3_kernel<T, false, false>), grid_of(g), dim3(kBlock), 0, s,
-                         g, src, state, uN, vN);
+    hipLaunchKernelGGL((finalize3_kernel<T, false, true>), grid_of(g), dim3(kBlock), 0, s, g,
+                       src, state, uN, vN);
   }
 }
 

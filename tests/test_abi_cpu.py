@@ -203,8 +203,9 @@ def test_validate3_rejects_bad_model(kw):
 
 
 def test_tape3_bytes_layout():
-    """Two states (38 planes each), the reduction buffers, and with the
-    adjoint two more states, K record slots of 4 planes and one state per
+    """Two states (38 planes of the haloed internal layout, (nz+2)(ny+2)
+    rows of roundup(nx+1, 64)), the reduction buffers, and with the adjoint
+    two more states, K record slots of 4 public planes and one state per
     checkpoint after the first; a mask adds 4 + 2 bytes per node and the
     per-segment flags."""
     from paper_1908_03876_amd import abi
@@ -213,12 +214,16 @@ def test_tape3_bytes_layout():
     p = inputs.tiny3d(nsteps=10)
     pitch = 64
     plane = p.nz * p.ny * pitch
+    plane_int = (p.nz + 2) * (p.ny + 2) * 64
     red = (1024 * 5 + 16) * 8
     for code, e in ((abi.MRT_F32, 4), (abi.MRT_F64, 8)):
         s = make_problem3_struct(p, code, pitch, None)
-        state = 38 * plane * e
+        state = 38 * plane_int * e
         assert abi.mrt3_tape_bytes(s, 0) == 2 * state + red
         assert abi.mrt3_tape_bytes(s, 10) == 4 * state + red + 10 * 4 * plane * e
         assert abi.mrt3_tape_bytes(s, 3) == 4 * state + red + 3 * state + 3 * 4 * plane * e
         sm = make_problem3_struct(p, code, pitch, 12345)
         assert abi.mrt3_tape_bytes(sm, 0) == 2 * state + red + plane * 6 + p.nz * p.ny * 4
+        # a non-periodic lattice uses link words even without a mask
+        sw = make_problem3_struct(p.copy(periodic=False), code, pitch, None)
+        assert abi.mrt3_tape_bytes(sw, 0) == 2 * state + red + plane * 6 + p.nz * p.ny * 4
