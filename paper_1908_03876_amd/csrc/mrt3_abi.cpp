@@ -103,7 +103,7 @@ int validate3(const mrt3_problem* p) {
   if (double(g.nz) * double(g.ny) * double(g.pitch) >= 2147483648.0)
     return failf(MRT_EINVAL, "nz * ny * pitch must be < 2^31");
   if (mrt3::internal_plane(g.nx, g.ny, g.nz) >= (size_t(1) << 29))
-    return failf(MRT_EINVAL, "lattice too large: (nz + 2)(ny + 2) * roundup(nx + 1, 64) "
+    return failf(MRT_EINVAL, "lattice too large: (nz + 2)(ny + 2) * roundup(nx, 64) "
                              "must be < 2^29");
   if (g.nsteps < 1) return failf(MRT_EINVAL, "nsteps %d < 1", g.nsteps);
   if (g.dtype != MRT_F32 && g.dtype != MRT_F64)

@@ -117,13 +117,14 @@ struct Model3Coef {
 
 // Fields (controls, seeds, records, outputs) use the public layout
 // [nz][ny][pitch].  The distribution buffers the library owns use an
-// internal layout with a one-node halo: node (x, y, z) at
-// ((z + 1)(ny + 2) + y + 1) pitchI + x, pitchI >= nx + 1, so that every
-// neighbour x +- e_i of a node, also outside the lattice, has a slot: the
-// padding column at x = nx (and, through the linear index, at x = -1 of
-// the next row) and the halo rows and slabs in y and z.  On a non-periodic
-// lattice the outside is solid and gets wall slots like a solid node; a
-// pull is then a uniform plane base plus one per-node offset.
+// internal layout with halo rows and slabs in y and z: node (x, y, z) at
+// ((z + 1)(ny + 2) + y + 1) pitchI + x, pitchI = nx rounded up to 64, so
+// that every neighbour x +- e_i of a node, also outside a non-periodic
+// lattice, is an in-bounds address (x = -1 and x = nx fall on the end and
+// the start of the adjacent rows).  Values read there for a neighbour
+// outside the lattice are discarded by the bounce-back (the link word marks
+// the outside as a wall), so a pull is a uniform plane base plus one
+// per-node offset with no edge test.
 struct Geometry3 {
   int nx, ny, nz, pitch;
   int periodic;            // 1: periodic wrap; 0: walls at the lattice edge
@@ -142,7 +143,7 @@ struct Geometry3 {
 };
 
 // Internal row stride and plane size of a lattice.
-inline int internal_pitch(int nx) { return ((nx + 1 + 63) / 64) * 64; }
+inline int internal_pitch(int nx) { return ((nx + 63) / 64) * 64; }
 inline size_t internal_plane(int nx, int ny, int nz) {
   return size_t(nz + 2) * size_t(ny + 2) * size_t(internal_pitch(nx));
 }

@@ -13,7 +13,9 @@
 // [species][19] of the haloed internal layout; pull streaming of
 // post-collision states, so each population is read once and written once
 // per step; every load is a plane base plus the node's one 32-bit offset
-// (a neighbour outside a non-periodic lattice lies in the halo); halfway
+// (a neighbour outside a non-periodic lattice is still an in-bounds address,
+// in the halo or at the end of an adjacent row, and its value is discarded
+// by the bounce-back); halfway
 // bounce-back reads the node's own opposite population where the link word
 // marks a wall, so no store is ever scattered and every wavefront writes
 // whole cache lines; per 64-node row segment a flag lets all-fluid
@@ -95,7 +97,8 @@ __device__ __forceinline__ uint32_t nb_pub(const Geometry3& g, const Node3& n, i
 // node's 32-bit byte offset, so that every access is one buffer
 // instruction with no per-lane 64-bit address arithmetic.  The resources
 // carry no range limit: every access is in bounds by construction (the
-// halo holds every neighbour).  Cache policy: kNT = non-temporal.
+// halo rows and slabs cover every neighbour).  Cache policy: kNT =
+// non-temporal.
 constexpr int kNT = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p) {
@@ -118,9 +121,9 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, d
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, kNT);
 }
 
-// Population node x pulls in direction i: plane i of buf at x - e_i (the
-// halo slot outside a non-periodic lattice; a solid neighbour's value is
-// replaced by the wall read).  bo = the node's internal byte offset.
+// Population node x pulls in direction i: plane i of buf at x - e_i (where
+// that neighbour is solid or outside a non-periodic lattice the value read
+// is replaced by the wall read).  bo = the node's internal byte offset.
 template <typename T, bool PERIODIC, int AUX>
 __device__ __forceinline__ T pull_ld(const Geometry3& g, const Node3& n, const T* buf, int i,
                                      uint32_t bo) {
@@ -269,23 +272,25 @@ __device__ __forceinline__ T wsum(const T f[Q]) {
   return T(1.0 / 3.0) * f[0] + T(1.0 / 18.0) * ax + T(1.0 / 36.0) * dg;
 }
 
-// tau S_i + tau w_i Phi (S, PhiS), tau = 1, 1/Cs^2 = 3: the chemotactic
-// flux a on the u populations with the kinetics phu, phv on v.
+// tau S_i + tau w_i Phi (S, PhiS), tau = 1, 1/Cs^2 = 3: on u the
+// chemotactic flux a and the kinetics phu; on v the kinetics phv.
 template <typename T>
-__device__ __forceinline__ void add_sources(T fu[Q], T fv[Q], T phu, T ax, T ay, T az, T phv) {
+__device__ __forceinline__ void add_sources_u(T fu[Q], T phu, T ax, T ay, T az) {
   fu[0] += phu * T(1.0 / 3.0);
-  fv[0] += phv * T(1.0 / 3.0);
 #pragma unroll
   for (int p = 0; p < 9; ++p) {
     const int i = 2 * p + 1;
-    const T w = T(wgt(i));
     const T ea = T(3.0 * wgt(i)) * edot(i, ax, ay, az);
-    const T k = phu * w;
+    const T k = phu * T(wgt(i));
     fu[i] += k + ea;
     fu[i + 1] += k - ea;
-    fv[i] += phv * w;
-    fv[i + 1] += phv * w;
   }
+}
+template <typename T>
+__device__ __forceinline__ void add_sources_v(T fv[Q], T phv) {
+  fv[0] += phv * T(1.0 / 3.0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) fv[i] += phv * T(wgt(i));
 }
 
 // Halfway bounce-back by own-node reads.  When the neighbour a population
@@ -309,6 +314,17 @@ __device__ __forceinline__ void wall_reads(const Geometry3& g, const T* __restri
   }
 #pragma unroll
   for (int i = 1; i < Q; ++i) f[i] = own[i];
+}
+
+// w~ . f (the transpose of the initialisation phi_i = w~_i Theta_0).
+template <typename T>
+__device__ __forceinline__ T shell_dot(const T f[Q], const Species3Coef<T>& c) {
+  T ax = T(0), dg = T(0);
+#pragma unroll
+  for (int i = 1; i <= 6; ++i) ax += f[i];
+#pragma unroll
+  for (int i = 7; i < Q; ++i) dg += f[i];
+  return c.w_rest * f[0] + c.w_axis * ax + c.w_diag * dg;
 }
 
 // Pre-collision populations: the pull from src, or w~ Theta_0 at step 0.
@@ -345,18 +361,16 @@ __device__ __forceinline__ void gather(const Geometry3& g, const Node3& n,
   }
 }
 
-// Post-collision stores, non-temporal (next read a whole sweep later).
-// Every lane of a wavefront stores, solid nodes too (their values are never
-// read by a fluid node), so the stores always fill whole cache lines.
+// Post-collision stores of one species (planes [0, 19) of dst),
+// non-temporal (next read a whole sweep later).  Every lane of a wavefront
+// stores, solid nodes too (their values are never read by a fluid node), so
+// the stores always fill whole cache lines.  Each species is stored as soon
+// as it is final, which frees its registers before the other one relaxes.
 template <typename T>
-__device__ __forceinline__ void store_state(const Geometry3& g, const T fu[Q], const T fv[Q],
-                                            T* __restrict__ dst, uint32_t bo) {
-  T* dv = dst + size_t(Q) * g.planeI;
+__device__ __forceinline__ void store_species(const Geometry3& g, const T f[Q],
+                                              T* __restrict__ dst, uint32_t bo) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    bstore(rsrc_of(dst + size_t(i) * g.planeI), bo, fu[i]);
-    bstore(rsrc_of(dv + size_t(i) * g.planeI), bo, fv[i]);
-  }
+  for (int i = 0; i < Q; ++i) bstore(rsrc_of(dst + size_t(i) * g.planeI), bo, f[i]);
 }
 
 // ------------------------------------------------------------ forward
@@ -397,13 +411,15 @@ __global__ __launch_bounds__(kBlock) void forward3_kernel(Geometry3 g, Model3Coe
   const T az = u * (m.b[6] * jx + m.b[7] * jy + m.b[8] * jz);
   const T phu = m.r_u * u * (T(1) - u);
   const T phv = m.a_uv * u - m.b_v * v + c;
-  T t1, t2;
-  relax<T, false>(fu, u, m.u, t1, t2);
-  relax<T, false>(fv, v, m.v, t1, t2);
-  add_sources(fu, fv, phu, ax, ay, az, phv);
-  // solid nodes of mixed wavefronts computed on values nobody reads; they
+  // solid nodes of mixed wavefronts compute on values nobody reads; they
   // store them anyway, keeping the wavefront's stores whole
-  store_state<T>(g, fu, fv, a.dst, bo);
+  T t1, t2;
+  relax<T, false>(fv, v, m.v, t1, t2);
+  add_sources_v(fv, phv);
+  store_species<T>(g, fv, a.dst + size_t(Q) * g.planeI, bo);
+  relax<T, false>(fu, u, m.u, t1, t2);
+  add_sources_u(fu, phu, ax, ay, az);
+  store_species<T>(g, fu, a.dst, bo);
 }
 
 template <typename T, bool PERIODIC, bool MASKED>
@@ -540,44 +556,35 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
   const T qx = u * (m.b[0] * px + m.b[3] * py + m.b[6] * pz);
   const T qy = u * (m.b[1] * px + m.b[4] * py + m.b[7] * pz);
   const T qz = u * (m.b[2] * px + m.b[5] * py + m.b[8] * pz);
+  // each species is finished and stored in turn (u first: its adjoint
+  // feeds p and q, computed above, and nothing else), which frees its
+  // registers before v relaxes; solid nodes of mixed wavefronts store values
+  // nobody reads (whole cache lines)
   T a1, a2;
   relax<T, true>(nu, T(0), m.u, a1, a2);
   const T wu = m.u.e_eq * a1 + m.u.eps_eq * a2 + cu;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) nu[i] += wu;
+  if (LAST) {
+    // transpose of phi_i^0 = w~_i Theta_0
+    if (a.adj_u0) a.adj_u0[idx] = shell_dot(nu, m.u);
+  } else if (a.dst) {
+    store_species<T>(g, nu, a.dst, bo);
+  }
   relax<T, true>(nv, T(0), m.v, a1, a2);
   const T wv = m.v.e_eq * a1 + m.v.eps_eq * a2 + cv;
-  nu[0] += wu;
   nv[0] += wv;
 #pragma unroll
   for (int p = 0; p < 9; ++p) {
     const int i = 2 * p + 1;
     const T eq = edot(i, qx, qy, qz);
-    nu[i] += wu;
-    nu[i + 1] += wu;
     nv[i] += wv + eq;
     nv[i + 1] += wv - eq;
   }
   if (LAST) {
-    // transpose of phi_i^0 = w~_i Theta_0
-    if (a.adj_u0) {
-      T ax = T(0), dg = T(0);
-#pragma unroll
-      for (int i = 1; i <= 6; ++i) ax += nu[i];
-#pragma unroll
-      for (int i = 7; i < Q; ++i) dg += nu[i];
-      a.adj_u0[idx] = m.u.w_rest * nu[0] + m.u.w_axis * ax + m.u.w_diag * dg;
-    }
-    if (a.adj_v0) {
-      T ax = T(0), dg = T(0);
-#pragma unroll
-      for (int i = 1; i <= 6; ++i) ax += nv[i];
-#pragma unroll
-      for (int i = 7; i < Q; ++i) dg += nv[i];
-      a.adj_v0[idx] = m.v.w_rest * nv[0] + m.v.w_axis * ax + m.v.w_diag * dg;
-    }
+    if (a.adj_v0) a.adj_v0[idx] = shell_dot(nv, m.v);
   } else if (a.dst) {
-    // solid nodes of mixed wavefronts store values nobody reads (whole
-    // cache lines)
-    store_state<T>(g, nu, nv, a.dst, bo);
+    store_species<T>(g, nv, a.dst + size_t(Q) * g.planeI, bo);
   }
 }
 
@@ -625,10 +632,12 @@ __global__ __launch_bounds__(kBlock) void tlm3_kernel(Geometry3 g, Model3Coef<T>
   const T phu = m.r_u * (T(1) - T(2) * u) * du;
   const T phv = m.a_uv * du - m.b_v * dv + dc;
   T t1, t2;
-  relax<T, false>(fu, du, m.u, t1, t2);
   relax<T, false>(fv, dv, m.v, t1, t2);
-  add_sources(fu, fv, phu, ax, ay, az, phv);
-  store_state<T>(g, fu, fv, a.dst, bo);
+  add_sources_v(fv, phv);
+  store_species<T>(g, fv, a.dst + size_t(Q) * g.planeI, bo);
+  relax<T, false>(fu, du, m.u, t1, t2);
+  add_sources_u(fu, phu, ax, ay, az);
+  store_species<T>(g, fu, a.dst, bo);
 }
 
 // ------------------------------------------------------------ link words

@@ -204,7 +204,7 @@ def test_validate3_rejects_bad_model(kw):
 
 def test_tape3_bytes_layout():
     """Two states (38 planes of the haloed internal layout, (nz+2)(ny+2)
-    rows of roundup(nx+1, 64)), the reduction buffers, and with the adjoint
+    rows of roundup(nx, 64)), the reduction buffers, and with the adjoint
     two more states, K record slots of 4 public planes and one state per
     checkpoint after the first; a mask adds 4 + 2 bytes per node and the
     per-segment flags."""
