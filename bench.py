@@ -33,34 +33,39 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1908_03876_amd", "csrc", f)
                for f in ("mrt_kernels.hip", "mrt_device.h", "mrt_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+# the same for the D3Q19 step kernels
+KERNEL3_SRCS = [os.path.join(ROOT, "paper_1908_03876_amd", "csrc", f)
+                for f in ("mrt3_kernels.hip", "mrt3_internal.h", "mrt_device.h")]
+TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "d3q19_traffic_counters.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(srcs=None) -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in (KERNEL_SRCS if srcs is None else srcs):
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, L: int):
+def read_traffic(kernel: str, L: int, path: str = None, srcs=None):
     """Calibrated HBM bytes per launch of `kernel` from the committed counter
     summary (`key = value` lines), or None when it is absent, taken on
     another workload size, or taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILE if path is None else path
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             line = line.split("#", 1)[0].strip()
             if "=" in line:
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_hash() or kv.get("L") != str(L):
+    if kv.get("kernel_source_sha256_16") != kernel_hash(srcs) or kv.get("L") != str(L):
         return None
     v = kv.get(kernel + ".hbm_bytes_per_launch")
     return int(v) if v is not None else None
@@ -438,6 +443,28 @@ def bench_surrogate(args):
     print(json.dumps(res), flush=True)
 
 
+def copy_calibration(out: dict, dev):
+    """A plain 1 GiB device copy: the reference of the byte counters, and the
+    bandwidth the runtime's own copy reaches (HIP events, best of 3)."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+    out["copy_GBps"] = round(8 * n / (best / 1e3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def bytes_per_site3(elem: int):
     """Algorithmic HBM bytes per fluid node and step on D3Q19 (two species):
     forward with record: 38 loads + 38 stores + control + record stores (u,
@@ -527,8 +554,9 @@ def bench_d3q19(args):
     dom = max(kern, key=lambda k: kern[k][0])
     avg_ms = kern[dom][1]
     achieved = launch_bytes[dom] / (avg_ms / 1e3) / 1e9
+    traffic = read_traffic(dom, L, TRAFFIC3_FILE, KERNEL3_SRCS) if info.mode == 1 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_bytes_per_launch": int(launch_bytes[dom]),
             "other_kernel": {k: {"avg_launch_ms": round(kern[k][1], 5),
@@ -558,6 +586,8 @@ def bench_d3q19(args):
     it.close()
     del dp
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        copy_calibration(out, dev)
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: D3Q19 oracle {L}^3 x 1 step")
         out["cpu_baseline"] = cpu_baseline3(L, 1)
@@ -737,24 +767,7 @@ def main():
     del dp
     torch.cuda.empty_cache()
     if args.copy_calibration:
-        # a plain 1 GiB device copy: the reference of the byte counters, and
-        # the bandwidth the runtime's own copy reaches (HIP events)
-        n = (1 << 30) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        best = None
-        for _ in range(3):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            b.copy_(a)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
-        out["copy_GBps"] = round(8 * n / (best / 1e3) / 1e9, 1)
-        del a, b
-        torch.cuda.empty_cache()
+        copy_calibration(out, dev)
     if args.cpu_steps > 0:
         log(f"[bench] cpu baseline: oracle {args.L}^2 x {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(args.L, args.cpu_steps)
