@@ -443,6 +443,15 @@ def bench_surrogate(args):
     print(json.dumps(res), flush=True)
 
 
+def traffic_rate(traffic, avg_ms):
+    """HBM GB/s from the counter bytes per launch over the measured launch
+    time, and its fraction of the peak (empty without counter figures)."""
+    if traffic is None:
+        return {}
+    gbs = traffic / (avg_ms / 1e3) / 1e9
+    return {"traffic_GBps": round(gbs, 1), "traffic_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def copy_calibration(out: dict, dev):
     """A plain 1 GiB device copy: the reference of the byte counters, and the
     bandwidth the runtime's own copy reaches (HIP events, best of 3)."""
@@ -562,6 +571,7 @@ def bench_d3q19(args):
             "other_kernel": {k: {"avg_launch_ms": round(kern[k][1], 5),
                                  "GBps": round(launch_bytes[k] / (kern[k][1] / 1e3) / 1e9, 1)}
                              for k in kern if k != dom and kern[k][0] > 0}}
+    roof.update(traffic_rate(traffic, avg_ms))
     out = {
         "metric": "coupled MRT+AMRT MLUPS (gradient iteration: forward + adjoint), "
                   "HBM GB/s fraction; s per gradient iteration",
@@ -733,6 +743,7 @@ def main():
             "traffic": traffic, "kernel": dom,
             "avg_launch_ms": round(avg_ms, 5),
             "algorithmic_bytes_per_launch": int(lbytes)}
+    roof.update(traffic_rate(traffic, avg_ms))
     out = {
         "metric": "coupled MRT+AMRT MLUPS (gradient iteration: forward + adjoint), "
                   "HBM GB/s fraction; s per gradient iteration",
