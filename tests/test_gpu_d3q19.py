@@ -198,3 +198,66 @@ def test_d3q19_tlm_adjoint_identity_at_256():
     print(f"256^3: <a, duN> = {lhs:.9e}, <g, dc> = {rhs:.9e}", flush=True)
     assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
     tape.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,ck", [(1, -1), (3, 1)])
+def test_d3q19_shortest_horizons(N, ck, prec):
+    """N = 1 (the first adjoint step is also the last: seeds, gradient and
+    the initial sensitivities in one launch) and N = 3 with a checkpoint
+    at every step (every segment recomputed from its checkpoint)."""
+    p = I.ragged_3d(25, 33, 5, 4, N, False, True)
+    rng = np.random.default_rng(8)
+    f = p.fluid
+    shp = (p.nz, p.ny, p.nx)
+    a = rng.standard_normal(shp) * f
+    b = rng.standard_normal(shp) * f
+    g, gu0, gv0 = O3.adjoint(p, a, b)
+    fwd = O3.forward(p)
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, Tape3
+    dp = DeviceProblem3(p, dtype=_dtype(prec))
+    tape = Tape3(dp, ck)
+    assert tape.info.mode == (1 if ck < 0 or ck >= N else 2)
+    uN = dp.empty_field()
+    abi.mrt3_forward(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, None, uN, None)
+    gacc = dp.empty_field(torch.float64)
+    au0, av0 = dp.empty_field(), dp.empty_field()
+    abi.amrt3_adjoint(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, dp.field(a),
+                      dp.field(b), gacc, au0, av0)
+    torch.cuda.synchronize()
+    ftol, tol = TOL[prec]
+    assert rel_l2(dp.host(uN), fwd["uN"], f) <= ftol
+    assert rel_l2(dp.host(gacc), g, f) <= tol
+    assert rel_l2(dp.host(au0), gu0, f) <= tol
+    assert rel_l2(dp.host(av0), gv0, f) <= tol
+    s = ~f
+    assert np.all(dp.host(gacc)[s] == 0) and np.all(dp.host(au0)[s] == 0)
+    tape.close()
+
+
+def test_d3q19_rejects_mismatched_calls():
+    """The tape checks the problem it was made for and the call order."""
+    import torch
+    from paper_1908_03876_amd import abi
+    from paper_1908_03876_amd.solver3 import DeviceProblem3, Tape3, make_problem3_struct
+    p = I.tiny3d(seed=9)
+    dp = DeviceProblem3(p, dtype=torch.float32)
+    tape = Tape3(dp, -1)
+    g = dp.empty_field(torch.float64)
+    with pytest.raises(abi.MrtError) as e:
+        abi.amrt3_adjoint(dp.struct, tape.handle, dp.u0, dp.v0, dp.control, dp.u0, None, g)
+    assert e.value.code == abi.MRT_ESTATE  # no forward yet
+    other = make_problem3_struct(p.copy(nsteps=p.nsteps + 1), dp.code, dp.pitch, None)
+    with pytest.raises(abi.MrtError) as e:
+        abi.mrt3_forward(other, tape.handle, dp.u0, dp.v0, dp.control)
+    assert e.value.code == abi.MRT_ESTATE
+    fwd_only = Tape3(dp, 0)
+    abi.mrt3_forward(dp.struct, fwd_only.handle, dp.u0, dp.v0, dp.control)
+    with pytest.raises(abi.MrtError) as e:
+        abi.amrt3_adjoint(dp.struct, fwd_only.handle, dp.u0, dp.v0, dp.control, dp.u0, None, g)
+    assert e.value.code == abi.MRT_ESTATE
+    torch.cuda.synchronize()
+    tape.close()
+    fwd_only.close()
