@@ -33,11 +33,16 @@ def _problem(name):
         return I.masked_3d(seed=8, L=24, nsteps=20)
     if name == "single_site":
         return I.ragged_3d(23, 1, 1, 1, 7, True, False).copy(chi=0.8)
+    if name == "nonsymmetric_chemotaxis":
+        # a non-symmetric C_chi and d != 1 for both species
+        p = I.ragged_3d(26, 19, 7, 6, 9, False, True)
+        C = np.array([[0.9, 0.3, -0.2], [-0.1, 0.6, 0.25], [0.15, -0.3, 0.7]])
+        return p.copy(Cchi=C, chi=0.6, du=0.8, dv=1.3)
     raise KeyError(name)
 
 
 CASES = ["tiny_periodic", "tiny_walls_masked", "ragged_masked_periodic", "ragged_walls",
-         "masked_spheres", "single_site"]
+         "masked_spheres", "single_site", "nonsymmetric_chemotaxis"]
 
 
 def device_gradient3(p, dtype, ckpt_every=-1, seed_v=None, want_adj0=False):

@@ -126,8 +126,9 @@ def test_d3q19_single_site_closed_form():
 
 
 def _cases3():
+    C = np.array([[0.9, 0.3, -0.2], [-0.1, 0.6, 0.25], [0.15, -0.3, 0.7]])
     return [I.tiny3d(seed=9), I.tiny3d(seed=10, masked=True),
-            I.tiny3d(seed=11, nx=4, ny=5, nz=4).copy(du=0.7, dv=1.3)]
+            I.tiny3d(seed=11, nx=4, ny=5, nz=4).copy(du=0.7, dv=1.3, Cchi=C)]
 
 
 @pytest.mark.parametrize("k", range(3))
@@ -140,7 +141,7 @@ def test_d3q19_gradient_complex_step(k):
         assert abs((g * h).sum() - dj) <= 1e-12 * max(abs(dj), 1e-300)
 
 
-@pytest.mark.parametrize("k", range(2))
+@pytest.mark.parametrize("k", range(3))
 def test_d3q19_tlm_adjoint_dot_product(k):
     p = _cases3()[k]
     rng = np.random.default_rng(70 + k)
