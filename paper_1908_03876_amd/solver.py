@@ -235,6 +235,27 @@ class GradientIteration:
                                 want_zeta=want_zeta, stream=stream)
         return r
 
+    def run(self, max_iters: int, gtol: float = 0.0, zeta: float = 0.0,
+            lo: float = -math.inf, hi: float = math.inf, stream=None) -> list:
+        """The gradient algorithm of Section 3.2.1 for at most max_iters
+        iterations, stopping before an update once ||E_k||_2 <= gtol ||E_0||_2
+        (the "gradient small enough" test; gtol = 0 runs every iteration).
+        Returns the per-iteration scalars; the last entry is the iteration
+        that met the test, if any (its gradient was computed, no step taken)."""
+        hist = []
+        g0 = None
+        for _ in range(max_iters):
+            r = self.gradient(stream=stream)
+            g0 = r["grad_l2"] if g0 is None else g0
+            if gtol > 0.0 and r["grad_l2"] <= gtol * g0:
+                r["stopped"] = True
+                hist.append(r)
+                break
+            r["zeta"] = abi.gd_step(self.dp.struct, self.tape.handle, self.dp.control,
+                                    self.grad, zeta, lo, hi, stream=stream)
+            hist.append(r)
+        return hist
+
     def tlm(self, dc=None, du0=None, dv0=None, control=None, stream=None):
         """Tangent-linear response (du^N, dv^N) of the last forward on this
         iteration's tape to the perturbation (dc, du0, dv0)."""

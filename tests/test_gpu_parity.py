@@ -320,3 +320,32 @@ def test_full_size_long_horizon_properties():
     assert abs(v[f].sum() / p.v0[f].sum() - 1.0) < 2e-5
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     tape.close()
+
+
+def test_gradient_loop_stop_test_matches_oracle():
+    """GradientIteration.run: the gradient algorithm with the stop test
+    ||E_k||_2 <= gtol ||E_0||_2 stops at the iteration the FP64 oracle's
+    own loop reaches it, with the oracle's control at that point."""
+    import torch
+    from paper_1908_03876_amd.solver import DeviceProblem, GradientIteration
+    p = I.with_control_bump(I.masked_anisotropic_small(L=48, nsteps=30), amp=3.0)
+    f = p.fluid
+    c = p.control.copy()
+    norms, controls = [], []
+    for _ in range(5):
+        r = O.cost_gradient(p.copy(control=c))
+        norms.append(np.sqrt((r["grad"][f] ** 2).sum()))
+        controls.append(c.copy())
+        c, _ = O.gd_step(c, r["grad"], 0.0, -np.inf, np.inf)
+    rel = np.array(norms) / norms[0]
+    assert np.all(np.diff(rel) < 0)
+    gtol = 0.5 * (rel[2] + rel[3])  # met first at k = 3
+    dp = DeviceProblem(p, dtype=torch.float64)
+    it = GradientIteration(dp)
+    hist = it.run(10, gtol=gtol)
+    torch.cuda.synchronize()
+    assert len(hist) == 4 and hist[-1].get("stopped") and not hist[2].get("stopped")
+    for k, h in enumerate(hist):
+        assert abs(h["grad_l2"] - norms[k]) <= 1e-10 * norms[k]
+    np.testing.assert_allclose(dp.host(dp.control)[f], controls[3][f], rtol=0, atol=1e-12)
+    it.close()
