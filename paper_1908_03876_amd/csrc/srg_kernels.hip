@@ -17,8 +17,9 @@
 // (v_mfma_f32_16x16x32_bf16): per tap t the 32 x 32 weight matrix W_t
 // multiplies the 32 channels of the 16 pixels of a tile, giving an output
 // of channels x pixels whose lanes hold 4 consecutive channels of one pixel
-// (8-byte channels-last stores).  Each wavefront keeps the 18 weight
-// fragments (9 taps x 2 channel blocks) in registers and walks many tiles.
+// (8-byte channels-last stores).  A block keeps the 18 weight fragments
+// (9 taps x 2 channel blocks) in LDS, read per MFMA, and its wavefronts
+// walk many tiles.
 // The one-channel first and last layers stay on the vector ALU.
 #include <hip/hip_runtime.h>
 
@@ -378,19 +379,20 @@ __device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, int 
 }
 
 // Forward of a hidden layer: out = bf16(tanh(b + sum_t W_t in[p + off(t)])).
-// Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).
+// Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).  The
+// 18 weight fragments (9 taps x 2 channel blocks, 18 KB) sit in LDS, read
+// per MFMA, so that a wavefront holds only its taps and accumulators and
+// eight wavefronts fit on a SIMD to hide the tap-load latency.
 __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict__ in,
                                                      const uint16_t* __restrict__ wf,
                                                      const float* __restrict__ bias,
                                                      uint16_t* __restrict__ out, int B, int H,
                                                      int W) {
+  __shared__ bf16x8 wl[18 * 64];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
-  bf16x8 a[9][2];
-#pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) a[t][mb] = load8(wf + ((t * 2 + mb) * 64 + lane) * 8);
+  for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wf + size_t(k) * 8);
+  __syncthreads();
   float bv[2][4];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -404,8 +406,12 @@ __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict_
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], cur[t], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], cur[t], acc1, 0, 0, 0);
+      const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, cur[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, cur[t], acc1, 0, 0, 0);
+      // keep the next tap's weight reads below this point: two fragments
+      // live at a time
+      __builtin_amdgcn_sched_barrier(0);
     }
     const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
     if (px < W) {
@@ -423,18 +429,17 @@ __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict_
 
 // Backward data of a hidden layer with the previous tanh folded in:
 // dz_prev[p][ci] = bf16((sum_t W_t^T dz[p - off(t)])[ci] (1 - a_prev[p][ci]^2)).
+// The transposed weight fragments sit in LDS, as in the forward.
 __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __restrict__ dz,
                                                           const uint16_t* __restrict__ wt,
                                                           const uint16_t* __restrict__ aprev,
                                                           uint16_t* __restrict__ dzprev, int B,
                                                           int H, int W) {
+  __shared__ bf16x8 wl[18 * 64];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
-  bf16x8 a[9][2];
-#pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) a[t][mb] = load8(wt + ((t * 2 + mb) * 64 + lane) * 8);
+  for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wt + size_t(k) * 8);
+  __syncthreads();
   const int tpr = (W + 15) >> 4;
   const int ntiles = B * H * tpr;
   for (int tile = wid; tile < ntiles; tile += nw) {
@@ -443,8 +448,10 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][0], cur[t], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][1], cur[t], acc1, 0, 0, 0);
+      const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, cur[t], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, cur[t], acc1, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
     if (px < W) {
@@ -805,15 +812,19 @@ void launch_srg_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t s
 void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, uint16_t* out,
                         int B, int H, int W, hipStream_t s) {
   const int ntiles = B * H * ((W + 15) / 16);
-  hipLaunchKernelGGL(c32_fwd_kernel, dim3(mfma_blocks(ntiles)), dim3(kB), 0, s, in, wf, b, out,
-                     B, H, W);
+  // up to 2048 blocks: eight wavefronts per SIMD
+  const int want = (ntiles + kWaves - 1) / kWaves;
+  const int nb = want < 2048 ? (want > 0 ? want : 1) : 2048;
+  hipLaunchKernelGGL(c32_fwd_kernel, dim3(nb), dim3(kB), 0, s, in, wf, b, out, B, H, W);
 }
 
 void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
                              uint16_t* dzprev, int B, int H, int W, hipStream_t s) {
   const int ntiles = B * H * ((W + 15) / 16);
-  hipLaunchKernelGGL(c32_bwd_data_kernel, dim3(mfma_blocks(ntiles)), dim3(kB), 0, s, dz, wt,
-                     aprev, dzprev, B, H, W);
+  const int want = (ntiles + kWaves - 1) / kWaves;
+  const int nb = want < 2048 ? (want > 0 ? want : 1) : 2048;
+  hipLaunchKernelGGL(c32_bwd_data_kernel, dim3(nb), dim3(kB), 0, s, dz, wt, aprev, dzprev, B, H,
+                     W);
 }
 
 void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* part, float* dw,
