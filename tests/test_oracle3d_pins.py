@@ -256,3 +256,25 @@ def test_d3q19_chemotactic_drift_matches_pde():
     assert 0.96 < r24 < 1.01
     assert abs(1 - r24) < 0.5 * abs(1 - r16)
     assert abs(cos24) < 0.05
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_d3q19_unit_decay_forgets_initial_v(masked):
+    """With b_v = 1 (and a unit time step) the v source of the first
+    collision is a_uv u - v + c, so the post-collision v population of an
+    equilibrium start is w~ (a_uv u0 + c): v0 drops out of the whole
+    trajectory, and the adjoint's dJ/dv0 vanishes.  With b_v != 1 it does
+    not (the contrast case)."""
+    import dataclasses
+    p = dataclasses.replace(I.tiny3d(masked=masked), b_v=1.0)
+    rng = np.random.default_rng(11)
+    v1 = 0.7 * rng.uniform(0, 1, size=p.v0.shape) * p.fluid
+    a, b = O3.forward(p), O3.forward(p, v0=v1)
+    assert np.abs(b["uN"] - a["uN"]).max() <= 1e-14
+    assert np.abs(b["vN"] - a["vN"]).max() <= 1e-14
+    seed = rng.standard_normal(p.v0.shape) * p.fluid
+    _, gu0, gv0 = O3.adjoint(p, seed, seed)
+    assert np.abs(gv0).max() <= 1e-14 * np.abs(gu0).max()
+    q = dataclasses.replace(p, b_v=0.5)
+    _, _, gv0q = O3.adjoint(q, seed, seed)
+    assert np.abs(gv0q).max() >= 1e-3 * np.abs(gu0).max()

@@ -811,3 +811,25 @@ def test_three_species_tlm_against_differences():
     um = O.forward(p, control=p.control - eps * dc)["uN"]
     fd = (up - um) / (2 * eps)
     assert np.linalg.norm(duN - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_unit_decay_forgets_initial_v(masked):
+    """With b_v = 1 (and a unit time step) the v source of the first
+    collision is a_uv u - v + c, so the post-collision v population of an
+    equilibrium start is w~ (a_uv u0 + c): v0 drops out of the whole
+    trajectory, and the adjoint's dJ/dv0 vanishes.  With b_v != 1 it does
+    not (the contrast case)."""
+    import dataclasses
+    p = dataclasses.replace(I.tiny(masked=masked), b_v=1.0)
+    rng = np.random.default_rng(11)
+    v1 = 0.7 * rng.uniform(0, 1, size=p.v0.shape) * p.fluid
+    a, b = O.forward(p), O.forward(p, v0=v1)
+    assert np.abs(b["uN"] - a["uN"]).max() <= 1e-14
+    assert np.abs(b["vN"] - a["vN"]).max() <= 1e-14
+    seed = rng.standard_normal(p.v0.shape) * p.fluid
+    _, gu0, gv0 = O.adjoint(p, seed, seed)
+    assert np.abs(gv0).max() <= 1e-14 * np.abs(gu0).max()
+    q = dataclasses.replace(p, b_v=0.5)
+    _, _, gv0q = O.adjoint(q, seed, seed)
+    assert np.abs(gv0q).max() >= 1e-3 * np.abs(gu0).max()
