@@ -22,20 +22,30 @@ import torch
 
 from . import abi
 from .solver import DeviceProblem, Tape
+from .solver3 import DeviceProblem3, Tape3
 
 
 class MRTSolve(torch.nn.Module):
-    """Differentiable map (control, u0, v0) -> (u^N, v^N) of one problem."""
+    """Differentiable map (control, u0, v0) -> (u^N, v^N) of one problem, on
+    D2Q9 (fields [ny, nx]) or, for a problem with a z extent, on D3Q19
+    (fields [nz, ny, nx])."""
 
     def __init__(self, prob, dtype=torch.float32, device="cuda:0",
                  ckpt_every: int = 100, nsteps: Optional[int] = None,
                  mem_budget: int = 0):
         super().__init__()
-        self.dp = DeviceProblem(prob, dtype=dtype, device=device, nsteps=nsteps)
-        self.tape = Tape(self.dp, ckpt_every, mem_budget)
+        self.three_d = hasattr(prob, "nz")
+        if self.three_d:
+            self.dp = DeviceProblem3(prob, dtype=dtype, device=device, nsteps=nsteps)
+            self.tape = Tape3(self.dp, ckpt_every, mem_budget)
+            self._fwd, self._adj = abi.mrt3_forward, abi.amrt3_adjoint
+        else:
+            self.dp = DeviceProblem(prob, dtype=dtype, device=device, nsteps=nsteps)
+            self.tape = Tape(self.dp, ckpt_every, mem_budget)
+            self._fwd, self._adj = abi.mrt_forward, abi.amrt_adjoint
         dp = self.dp
-        # library-side padded buffers ([ny, pitch]); the tape's record refers
-        # to the contents these held at the last forward
+        # library-side padded buffers ([(nz,) ny, pitch]); the tape's record
+        # refers to the contents these held at the last forward
         self._u0, self._v0, self._c = dp.empty_field(), dp.empty_field(), dp.empty_field()
         self._uN, self._vN = dp.empty_field(), dp.empty_field()
         self._su, self._sv = dp.empty_field(), dp.empty_field()
@@ -46,24 +56,26 @@ class MRTSolve(torch.nn.Module):
 
     @property
     def shape(self):
+        if self.three_d:
+            return (self.dp.nz, self.dp.ny, self.dp.nx)
         return (self.dp.ny, self.dp.nx)
 
     def default_inputs(self):
         nx = self.dp.nx
-        return (self.dp.control[:, :nx].clone(), self.dp.u0[:, :nx].clone(),
-                self.dp.v0[:, :nx].clone())
+        return (self.dp.control[..., :nx].clone(), self.dp.u0[..., :nx].clone(),
+                self.dp.v0[..., :nx].clone())
 
     # -- called by the autograd Function
     def _run_forward(self, control, u0, v0):
         nx = self.dp.nx
-        self._c[:, :nx].copy_(control)
-        self._u0[:, :nx].copy_(u0)
-        self._v0[:, :nx].copy_(v0)
-        abi.mrt_forward(self.dp.struct, self.tape.handle, self._u0, self._v0,
-                        self._c, None, self._uN, self._vN)
+        self._c[..., :nx].copy_(control)
+        self._u0[..., :nx].copy_(u0)
+        self._v0[..., :nx].copy_(v0)
+        self._fwd(self.dp.struct, self.tape.handle, self._u0, self._v0, self._c, None,
+                  self._uN, self._vN)
         self._generation += 1
         self._recorded = self._generation
-        return self._uN[:, :nx].clone(), self._vN[:, :nx].clone(), self._generation
+        return self._uN[..., :nx].clone(), self._vN[..., :nx].clone(), self._generation
 
     def _run_adjoint(self, generation, control, u0, v0, gu, gv, want_u0, want_v0):
         nx = self.dp.nx
@@ -73,19 +85,17 @@ class MRTSolve(torch.nn.Module):
         self._su.zero_()
         self._sv.zero_()
         if gu is not None:
-            self._su[:, :nx].copy_(gu)
+            self._su[..., :nx].copy_(gu)
         sv = None
         if gv is not None:
-            self._sv[:, :nx].copy_(gv)
+            self._sv[..., :nx].copy_(gv)
             sv = self._sv
-        abi.amrt_adjoint(self.dp.struct, self.tape.handle, self._u0, self._v0,
-                         self._c, self._su, sv, self._g,
-                         self._au0 if want_u0 else None,
-                         self._av0 if want_v0 else None)
+        self._adj(self.dp.struct, self.tape.handle, self._u0, self._v0, self._c, self._su, sv,
+                  self._g, self._au0 if want_u0 else None, self._av0 if want_v0 else None)
         dt = self.dp.dtype
-        gc = self._g[:, :nx].to(dt)
-        gu0 = self._au0[:, :nx].clone() if want_u0 else None
-        gv0 = self._av0[:, :nx].clone() if want_v0 else None
+        gc = self._g[..., :nx].to(dt)
+        gu0 = self._au0[..., :nx].clone() if want_u0 else None
+        gv0 = self._av0[..., :nx].clone() if want_v0 else None
         return gc, gu0, gv0
 
     def forward(self, control, u0=None, v0=None):
