@@ -276,6 +276,7 @@ mrt3::Geometry3 geometry3(const mrt3_tape* t) {
   g.link = t->masked ? t->link : nullptr;
   g.wflag = t->masked ? t->wflag : nullptr;
   g.nsx = (t->nx + 63) / 64;
+  g.band = mrt3::band_of(t->nx, t->ny);
   return g;
 }
 

@@ -140,12 +140,26 @@ struct Geometry3 {
   const uint32_t* wflag;   // [nz][ny][nsx]: 0 = a 64-node row segment and
                            // its neighbours are fluid, 1 = mixed, 2 = solid
   int nsx;                 // ceil(nx / 64)
+  int band;                // y-rows per band of the tile order, band_of()
 };
 
 // Internal row stride and plane size of a lattice.
 inline int internal_pitch(int nx) { return ((nx + 63) / 64) * 64; }
 inline size_t internal_plane(int nx, int ny, int nz) {
   return size_t(nz + 2) * size_t(ny + 2) * size_t(internal_pitch(nx));
+}
+
+// Height of the y-bands in which the kernels take rows z-fastest.  The 8
+// XCDs own equal contiguous ranges of tiles, so a band of ny / 8 rows is
+// one XCD's share and the rows on either side of a band edge run at the
+// same time on two XCDs.  That share is cut into equal bands when the rows
+// between z-neighbours, band * nx nodes at about 336 bytes each, would not
+// stay in an XCD's 4 MB L2 (band * nx <= 8192: 32 rows of 256 nodes).
+inline int band_of(int nx, int ny) {
+  const int share = (ny + 7) / 8;
+  const int most = nx >= 8192 ? 1 : 8192 / nx;
+  const int nb = (share + most - 1) / most;
+  return (share + nb - 1) / nb;
 }
 
 void launch_build_link3(const Geometry3& g, const uint8_t* mask, uint32_t* link,

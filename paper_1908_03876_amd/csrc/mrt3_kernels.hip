@@ -44,6 +44,30 @@ __device__ __forceinline__ void make_node(const Geometry3& g, int x, int y, int 
          uint32_t(x);
 }
 
+// Row order of the tiles: z-fastest inside bands of g.band y-rows (the
+// last band takes the remainder).  A row shares cache lines with the rows
+// at y +- 1 and z +- 1 (its pulls, and the bounce-back reads of the nodes
+// next to a wall, hit the lines its neighbours pull); in this order those
+// rows run within a band's width of blocks on the same XCD, while the lines
+// are still in its L2, where plain z-major order puts a whole (ny x nx)
+// slice between z-neighbours.
+__device__ __forceinline__ void band_row(const Geometry3& g, int r, int& y, int& z) {
+  const int b = g.band;
+  const int whole = (g.ny / b) * b;
+  int y0, h, q;
+  if (r < whole * g.nz) {
+    y0 = (r / (b * g.nz)) * b;
+    h = b;
+    q = r - y0 * g.nz;
+  } else {
+    y0 = whole;
+    h = g.ny - whole;
+    q = r - whole * g.nz;
+  }
+  z = q / h;
+  y = y0 + (q - z * h);
+}
+
 __device__ __forceinline__ bool node_of_block(const Geometry3& g, Node3& n) {
   const int nbx = (g.nx + kBlock - 1) / kBlock;
   const int ntiles = nbx * g.ny * g.nz;
@@ -52,8 +76,9 @@ __device__ __forceinline__ bool node_of_block(const Geometry3& g, Node3& n) {
   const int t = xcd_tile(id, ntiles);
   const int x = (t % nbx) * kBlock + int(threadIdx.x);
   if (x >= g.nx) return false;
-  const int r = t / nbx;  // row z * ny + y
-  make_node(g, x, r % g.ny, r / g.ny, n);
+  int y, z;
+  band_row(g, t / nbx, y, z);
+  make_node(g, x, y, z, n);
   return true;
 }
 
