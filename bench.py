@@ -88,22 +88,61 @@ def bytes_per_site(elem: int, source_term: int = 1, nspecies: int = 2):
     return fwd, adj, fwd_norec
 
 
+def _gomp():
+    """The OpenMP runtime the oracle libraries are built against (g++
+    -fopenmp links libgomp); its thread count is set here, in process."""
+    import ctypes
+    return ctypes.CDLL("libgomp.so.1")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(run, threads: int) -> float:
+    """Seconds of run() with the oracle's OpenMP pool at `threads` (0: as
+    configured), restoring the previous count afterwards."""
+    gomp = _gomp()
+    before = gomp.omp_get_max_threads()
+    if threads > 0:
+        gomp.omp_set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        run()
+        return time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(before)
+
+
 def cpu_baseline(L: int, steps: int):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
     workload: the full L x L masked problem for `steps` forward + adjoint
-    steps."""
+    steps on all configured threads, and for one step on one thread."""
     from oracle import oracle as O
     from paper_1908_03876_amd import inputs as I
-    p = I.with_control_bump(I.masked_anisotropic(L=L, nsteps=steps), amp=5.0, sigma=L / 8)
+
+    def problem(n):
+        return I.with_control_bump(I.masked_anisotropic(L=L, nsteps=n), amp=5.0, sigma=L / 8)
+    p = problem(steps)
     O.lib()
-    t0 = time.perf_counter()
-    O.cost_gradient(p)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = _gomp().omp_get_max_threads()
+    dt = _time_oracle(lambda: O.cost_gradient(p), 0)
+    p1 = problem(1)
+    dt1 = _time_oracle(lambda: O.cost_gradient(p1), 1)
     return {"value": p.n_fluid * steps / dt / 1e6, "unit": "MLUPS",
             "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle forward+adjoint gradient, {L}x{L} masked "
-                      f"anisotropic workload, {steps} steps ({dt:.1f} s)"}
+                      f"anisotropic workload, {steps} steps ({dt:.1f} s)",
+            "one_thread": {"value": p1.n_fluid / dt1 / 1e6, "unit": "MLUPS",
+                           "sample": f"the same problem, 1 step on 1 thread ({dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_batched(args):
@@ -487,21 +526,26 @@ def bytes_per_site3(elem: int):
     return fwd, adj, fwd_norec
 
 
-def cpu_baseline3(L: int, steps: int):
+def cpu_baseline3(L: int, steps: int, L1: int = 96):
     """Time the FP64 D3Q19 oracle (as it stands) on the full L^3 masked
-    problem for `steps` forward + adjoint steps."""
+    problem for `steps` forward + adjoint steps on all configured threads,
+    and on the L1^3 problem of the same recipe for one step on one thread."""
     from oracle import oracle3d as O3
     from paper_1908_03876_amd import inputs as I
     p = I.masked_3d(seed=8, L=L, nsteps=steps)
     O3.lib()
-    t0 = time.perf_counter()
-    O3.cost_gradient(p)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = _gomp().omp_get_max_threads()
+    dt = _time_oracle(lambda: O3.cost_gradient(p), 0)
+    p1 = I.masked_3d(seed=8, L=L1, nsteps=1)
+    dt1 = _time_oracle(lambda: O3.cost_gradient(p1), 1)
     return {"value": p.n_fluid * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"FP64 D3Q19 oracle forward+adjoint gradient, {L}^3 masked porous "
-                      f"workload, {steps} step(s) ({dt:.1f} s)"}
+                      f"workload, {steps} step(s) ({dt:.1f} s)",
+            "one_thread": {"value": p1.n_fluid / dt1 / 1e6, "unit": "MLUPS",
+                           "sample": f"{L1}^3 problem of the same recipe, 1 step on 1 thread "
+                                     f"({dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_d3q19(args):
