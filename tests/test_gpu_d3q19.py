@@ -38,11 +38,19 @@ def _problem(name):
         p = I.ragged_3d(26, 19, 7, 6, 9, False, True)
         C = np.array([[0.9, 0.3, -0.2], [-0.1, 0.6, 0.25], [0.15, -0.3, 0.7]])
         return p.copy(Cchi=C, chi=0.6, du=0.8, dv=1.3)
+    if name == "banded_walls":
+        # two blocks per row (nx > 256); the rows fall into y-bands of 5 with
+        # a remainder band of 2
+        return I.ragged_3d(28, 280, 37, 9, 8, False, True)
+    if name == "banded_periodic":
+        # y-bands of 9 with a remainder band of 7, periodic wrap across them
+        return I.ragged_3d(29, 64, 70, 12, 6, True, True)
     raise KeyError(name)
 
 
 CASES = ["tiny_periodic", "tiny_walls_masked", "ragged_masked_periodic", "ragged_walls",
-         "masked_spheres", "single_site", "nonsymmetric_chemotaxis"]
+         "masked_spheres", "single_site", "nonsymmetric_chemotaxis", "banded_walls",
+         "banded_periodic"]
 
 
 def device_gradient3(p, dtype, ckpt_every=-1, seed_v=None, want_adj0=False):
