@@ -371,8 +371,8 @@ int mrt_batch_forward(mrt_batch* b, void* stream);
 typedef struct mrt_srg mrt_srg;
 
 /* Work buffers hold max_batch * max_h * max_w pixels (at most 2^28, else
- * MRT_EINVAL); any call with B * H * W within that (H, W >= 3) is
- * accepted. */
+ * MRT_EINVAL); any call with B * H * W within that (H, W >= 3, W <= 2^24)
+ * is accepted. */
 int mrt_srg_create(int32_t channels /* 32 */, int32_t max_batch, int32_t max_h,
                    int32_t max_w, float in_scale, float out_scale, mrt_srg** out);
 void mrt_srg_destroy(mrt_srg* s);

@@ -70,6 +70,8 @@ int check_shape(const mrt_srg* s, int B, int H, int W) {
   if (B < 1 || H < 3 || W < 3 ||
       size_t(B) * H * W > size_t(s->max_batch) * s->max_h * s->max_w)
     return err(MRT_EINVAL, "batch or size outside what the surrogate was created for");
+  // the convolution kernels address a row of 64-byte pixels with 32-bit offsets
+  if (W > (1 << 24)) return err(MRT_EINVAL, "at most 2^24 pixels per row");
   return MRT_OK;
 }
 

@@ -53,23 +53,22 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // hardware conversion.
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-  const bf16x2 v = {__bf16(a), __bf16(b)};
-  return __builtin_bit_cast(uint32_t, v);
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
 // Hyperbolic tangent in a few instructions: tanh x = s (1 - 2 / (e^{2|x|} + 1))
-// with s = sign x, from the hardware base-2 exponential and reciprocal; for
-// |x| < 1/16, where that form cancels, the odd Taylor series to x^7
-// (truncation below 3e-13).  About 1e-7 absolute error, far below the BF16
-// spacing of the stored activations.
+// with s = sign x, from the hardware base-2 exponential and reciprocal
+// (absolute error about 1.5e-7: an ulp of each near 1); for |x| < 1e-3,
+// where that form cancels, x itself (tanh x = x (1 - x^2 / 3 + ...), off by
+// at most 3.4e-10).  Both are far below the BF16 spacing of the stored
+// activations.
 __device__ __forceinline__ float tanh_fast(float x) {
   const float ax = fabsf(x);
   const float e = __builtin_amdgcn_exp2f(ax * 2.8853900817779268f);  // 2 log2(e)
   const float big = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
-  const float x2 = x * x;
-  const float small =
-      ax * (1.f + x2 * (-0.33333333333f + x2 * (0.13333333333f - x2 * 0.053968253968f)));
-  return copysignf(ax < 0.0625f ? small : big, x);
+  return copysignf(ax < 1e-3f ? ax : big, x);
 }
 
 __device__ __forceinline__ int wrap(int i, int n) {
@@ -361,20 +360,51 @@ __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restric
   bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
 }
 
-// The nine taps p + sgn off(t) of a 16-pixel tile of one row, lane = (channel
-// group q, pixel c16), as MFMA B fragments.  A ragged tile's lanes past the
-// row end read the last pixel instead (their results are not stored).
+// A 16-pixel tile of one row: field b, row y, first pixel x0.  The tile
+// index is wave-uniform, so the decomposition runs on the scalar unit.
+struct Tile {
+  int bh, b, y, x0;
+};
+
+__device__ __forceinline__ Tile tile_at(int tile, int tpr, int H) {
+  tile = __builtin_amdgcn_readfirstlane(tile);
+  Tile t;
+  t.bh = tile / tpr;
+  t.x0 = (tile - t.bh * tpr) * 16;
+  t.b = t.bh / H;
+  t.y = t.bh - t.b * H;
+  return t;
+}
+
+// Buffer resource over row bh of a channels-last BF16 field (W pixels of
+// 64 bytes): the row base is a scalar 64-bit address, the per-lane offsets
+// within the row stay 32-bit, and an offset past the row reads 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const uint16_t* f, int bh, int W) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(f + size_t(bh) * W * kC),
+                                           (short)0, W * kC * 2, 0x00020000);
+}
+
+// The nine taps p + sgn off(t), t = 3 (dy + 1) + (dx + 1), of a 16-pixel
+// tile, lane = (channel group q, pixel c16), as MFMA B fragments: three
+// wrapped rows (scalar resources) times three wrapped columns (per-lane
+// byte offsets).  A ragged tile's lanes past the row end read the last
+// pixel instead (their results are not stored).
 template <int SGN>
-__device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, int tile, int tpr,
+__device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, const Tile& tl,
                                           int H, int W, int q, int c16, bf16x8 (&v)[9]) {
-  const int bh = tile / tpr, x0 = (tile - bh * tpr) * 16;
-  const int b = bh / H, y = bh - b * H;
-  const int px = x0 + c16;
+  const int px = tl.x0 + c16;
   const int pl = px < W ? px : W - 1;
+  uint32_t col[3];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = wrap(y + SGN * (t / 3 - 1), H), xx = wrap(pl + SGN * (t % 3 - 1), W);
-    v[t] = load8(src + pix(b * H + yy, W, xx) * kC + 8 * q);
+  for (int c = 0; c < 3; ++c)
+    col[c] = uint32_t(wrap(pl + SGN * (c - 1), W)) * uint32_t(kC * 2) + uint32_t(16 * q);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int yy = wrap(tl.y + SGN * (r - 1), H);
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(src, tl.b * H + yy, W);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      v[3 * r + c] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, col[c], 0, 0));
   }
 }
 
@@ -382,28 +412,30 @@ __device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, int 
 // Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).  The
 // 18 weight fragments (9 taps x 2 channel blocks, 18 KB) sit in LDS, read
 // per MFMA, so that a wavefront holds only its taps and accumulators and
-// eight wavefronts fit on a SIMD to hide the tap-load latency.
-__global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict__ in,
+// eight wavefronts fit on a SIMD to hide the tap-load latency.  The
+// accumulators start at the bias.
+__global__ __launch_bounds__(kB, 8) void c32_fwd_kernel(const uint16_t* __restrict__ in,
                                                      const uint16_t* __restrict__ wf,
                                                      const float* __restrict__ bias,
                                                      uint16_t* __restrict__ out, int B, int H,
                                                      int W) {
   __shared__ bf16x8 wl[18 * 64];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
-  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
   for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wf + size_t(k) * 8);
   __syncthreads();
-  float bv[2][4];
+  f32x4 bv[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) bv[mb][j] = bias[16 * mb + 4 * q + j];
   const int tpr = (W + 15) >> 4;
   const int ntiles = B * H * tpr;
+  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
   for (int tile = wid; tile < ntiles; tile += nw) {
+    const Tile tl = tile_at(tile, tpr, H);
     bf16x8 cur[9];
-    load_taps<1>(in, tile, tpr, H, W, q, c16, cur);
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    load_taps<1>(in, tl, H, W, q, c16, cur);
+    f32x4 acc0 = bv[0], acc1 = bv[1];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
@@ -413,16 +445,17 @@ __global__ __launch_bounds__(kB) void c32_fwd_kernel(const uint16_t* __restrict_
       // live at a time
       __builtin_amdgcn_sched_barrier(0);
     }
-    const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
+    const int px = tl.x0 + c16;
     if (px < W) {
-      uint16_t* o = out + pix(bh, W, px) * kC + 4 * q;
+      const __amdgpu_buffer_rsrc_t ro = row_rsrc(out, tl.bh, W);
+      const uint32_t o = uint32_t(px) * uint32_t(kC * 2) + uint32_t(8 * q);
       u32x2 r0, r1;
-      r0[0] = pack_bf16(tanh_fast(acc0[0] + bv[0][0]), tanh_fast(acc0[1] + bv[0][1]));
-      r0[1] = pack_bf16(tanh_fast(acc0[2] + bv[0][2]), tanh_fast(acc0[3] + bv[0][3]));
-      r1[0] = pack_bf16(tanh_fast(acc1[0] + bv[1][0]), tanh_fast(acc1[1] + bv[1][1]));
-      r1[1] = pack_bf16(tanh_fast(acc1[2] + bv[1][2]), tanh_fast(acc1[3] + bv[1][3]));
-      *reinterpret_cast<u32x2*>(o) = r0;
-      *reinterpret_cast<u32x2*>(o + 16) = r1;
+      r0[0] = pack_bf16(tanh_fast(acc0[0]), tanh_fast(acc0[1]));
+      r0[1] = pack_bf16(tanh_fast(acc0[2]), tanh_fast(acc0[3]));
+      r1[0] = pack_bf16(tanh_fast(acc1[0]), tanh_fast(acc1[1]));
+      r1[1] = pack_bf16(tanh_fast(acc1[2]), tanh_fast(acc1[3]));
+      __builtin_amdgcn_raw_buffer_store_b64(r0, ro, o, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(r1, ro, o + 32u, 0, 0);
     }
   }
 }
@@ -437,14 +470,15 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
                                                           int H, int W) {
   __shared__ bf16x8 wl[18 * 64];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
-  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
   for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wt + size_t(k) * 8);
   __syncthreads();
   const int tpr = (W + 15) >> 4;
   const int ntiles = B * H * tpr;
+  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
   for (int tile = wid; tile < ntiles; tile += nw) {
+    const Tile tl = tile_at(tile, tpr, H);
     bf16x8 cur[9];
-    load_taps<-1>(dz, tile, tpr, H, W, q, c16, cur);
+    load_taps<-1>(dz, tl, H, W, q, c16, cur);
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -453,11 +487,13 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
       acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, cur[t], acc1, 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
-    const int bh = tile / tpr, px = (tile - bh * tpr) * 16 + c16;
+    const int px = tl.x0 + c16;
     if (px < W) {
-      const size_t o = pix(bh, W, px) * kC + 4 * q;
-      const u32x2 p0 = *reinterpret_cast<const u32x2*>(aprev + o);
-      const u32x2 p1 = *reinterpret_cast<const u32x2*>(aprev + o + 16);
+      const __amdgpu_buffer_rsrc_t ra = row_rsrc(aprev, tl.bh, W);
+      const __amdgpu_buffer_rsrc_t rd = row_rsrc(dzprev, tl.bh, W);
+      const uint32_t o = uint32_t(px) * uint32_t(kC * 2) + uint32_t(8 * q);
+      const u32x2 p0 = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, o, 0, 0));
+      const u32x2 p1 = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, o + 32u, 0, 0));
       float av[2][4] = {{lo16(p0[0]), hi16(p0[0]), lo16(p0[1]), hi16(p0[1])},
                         {lo16(p1[0]), hi16(p1[0]), lo16(p1[1]), hi16(p1[1])}};
       float gv[2][4] = {{acc0[0], acc0[1], acc0[2], acc0[3]},
@@ -471,8 +507,8 @@ __global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __rest
           const float g1 = gv[mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
           r[mb][h] = pack_bf16(g0, g1);
         }
-      *reinterpret_cast<u32x2*>(dzprev + o) = r[0];
-      *reinterpret_cast<u32x2*>(dzprev + o + 16) = r[1];
+      __builtin_amdgcn_raw_buffer_store_b64(r[0], rd, o, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(r[1], rd, o + 32u, 0, 0);
     }
   }
 }
@@ -758,11 +794,12 @@ int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
 int blocks_for_pixels(int B, int H, int W) { return blocks_for(size_t(B) * H * W); }
 
 
-// wavefronts of the MFMA kernels: enough to fill the chip, each walking
-// many tiles so that its weight fragments are loaded once
-int mfma_blocks(int nitems) {
-  const int want = (nitems + kWaves - 1) / kWaves;
-  return want < 1024 ? (want > 0 ? want : 1) : 1024;
+// blocks of the MFMA kernels: up to 2048 (eight wavefronts per SIMD), each
+// wavefront walking many tiles so that the block loads its weight
+// fragments into LDS once
+int mfma_blocks(int ntiles) {
+  const int want = (ntiles + kWaves - 1) / kWaves;
+  return want < 2048 ? (want > 0 ? want : 1) : 2048;
 }
 
 }  // namespace
@@ -811,18 +848,13 @@ void launch_srg_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t s
 
 void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, uint16_t* out,
                         int B, int H, int W, hipStream_t s) {
-  const int ntiles = B * H * ((W + 15) / 16);
-  // up to 2048 blocks: eight wavefronts per SIMD
-  const int want = (ntiles + kWaves - 1) / kWaves;
-  const int nb = want < 2048 ? (want > 0 ? want : 1) : 2048;
+  const int nb = mfma_blocks(B * H * ((W + 15) / 16));
   hipLaunchKernelGGL(c32_fwd_kernel, dim3(nb), dim3(kB), 0, s, in, wf, b, out, B, H, W);
 }
 
 void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
                              uint16_t* dzprev, int B, int H, int W, hipStream_t s) {
-  const int ntiles = B * H * ((W + 15) / 16);
-  const int want = (ntiles + kWaves - 1) / kWaves;
-  const int nb = want < 2048 ? (want > 0 ? want : 1) : 2048;
+  const int nb = mfma_blocks(B * H * ((W + 15) / 16));
   hipLaunchKernelGGL(c32_bwd_data_kernel, dim3(nb), dim3(kB), 0, s, dz, wt, aprev, dzprev, B, H,
                      W);
 }
