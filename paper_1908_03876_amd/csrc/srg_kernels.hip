@@ -170,15 +170,21 @@ __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restr
 // ------------------------------------------------- last layer (32 -> 1)
 
 // y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]): four lanes
-// per pixel, each summing eight channels (one 16-byte load per tap), then
-// combined across the four lanes; grid-strided.
+// per pixel, each summing eight channels (one 16-byte load per tap, all nine
+// in flight) as four two-channel dot products of BF16 pairs (exact
+// products, FP32 sums), then combined across the four lanes; grid-strided.
 __global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__ a,
                                                     const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias,
                                                     float* __restrict__ y, int B, int H, int W,
                                                     float oscale) {
-  __shared__ float sw[kC * 9];
-  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  // (W3[2j][t], W3[2j+1][t]) as BF16 pairs, [t][j]
+  __shared__ __attribute__((aligned(16))) uint32_t wp[9 * 16];
+  for (int i = threadIdx.x; i < 9 * 16; i += kB) {
+    const int t = i / 16, j = i - 16 * t;
+    wp[i] = uint32_t(w[(2 * j) * 9 + t]) | (uint32_t(w[(2 * j + 1) * 9 + t]) << 16);
+  }
   __syncthreads();
   const int hw = H * W, n = B * hw;
   const int cg = threadIdx.x & 3;
@@ -187,16 +193,24 @@ __global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__
   // multiple of 4), so they reach the shuffles together
   for (int p = (blockIdx.x * kB + threadIdx.x) >> 2; p < n; p += (gridDim.x * kB) >> 2) {
     const int b = p / hw, r = p - b * hw, py = r / W, px = r - py * W;
-    float acc = 0.f;
+    u32x4 q[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
-      const u32x4 q = *reinterpret_cast<const u32x4*>(
-          a + (size_t(b * H + yy) * W + xx) * kC + 8 * cg);
+      q[t] = *reinterpret_cast<const u32x4*>(a + (size_t(b * H + yy) * W + xx) * kC + 8 * cg);
+    }
+    // all nine tap loads in flight before the first sum
+    __builtin_amdgcn_sched_barrier(0);
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + 4 * cg]);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int ci = 8 * cg + 2 * e;
-        acc += sw[ci * 9 + t] * lo16(q[e]) + sw[(ci + 1) * 9 + t] * hi16(q[e]);
+        // through scalars: a bit cast of a vector element itself reads element 0
+        const uint32_t qe = q[t][e], we = wq[e];
+        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, qe),
+                                              __builtin_bit_cast(bf16x2, we), acc, false);
       }
     }
     acc += __shfl_xor(acc, 1, 64);
