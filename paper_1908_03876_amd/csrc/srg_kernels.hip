@@ -18,8 +18,8 @@
 // multiplies the 32 channels of the 16 pixels of a tile, giving an output
 // of channels x pixels whose lanes hold 4 consecutive channels of one pixel
 // (8-byte channels-last stores).  A block keeps the 18 weight fragments
-// (9 taps x 2 channel blocks) in LDS, read per MFMA, and its wavefronts
-// walk many tiles.
+// (9 taps x 2 channel blocks) in LDS, read per MFMA, and walks many tiles;
+// the forward stages its input patches in LDS as well.
 // The one-channel first and last layers stay on the vector ALU.
 #include <hip/hip_runtime.h>
 
@@ -423,53 +423,112 @@ __device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, cons
 }
 
 // Forward of a hidden layer: out = bf16(tanh(b + sum_t W_t in[p + off(t)])).
-// Tiles of 16 pixels of one row; lane = (channel group q, pixel c16).  The
-// 18 weight fragments (9 taps x 2 channel blocks, 18 KB) sit in LDS, read
-// per MFMA, so that a wavefront holds only its taps and accumulators and
-// eight wavefronts fit on a SIMD to hide the tap-load latency.  The
-// accumulators start at the bias.
-__global__ __launch_bounds__(kB, 8) void c32_fwd_kernel(const uint16_t* __restrict__ in,
+// A block takes patches of kPR rows x 64 pixels.  It stages the patch with
+// its one-pixel halo, (kPR + 2) rows x 66 pixels of 64 bytes (periodic
+// wrap), in LDS once, so that every input pixel crosses the vector memory
+// unit once per patch instead of once per tap; wavefront w then computes
+// the 16-pixel column w of all kPR rows, lane = (channel group q, pixel
+// c16), reading each weight fragment once per tap for the kPR rows.  The
+// 16-byte quarter `part` of staged pixel px sits in slot (part + px / 2) % 4
+// of the pixel, so that the eight lanes served together (eight pixels, one
+// quarter each) fall on distinct banks.  The accumulators start at the bias.
+constexpr int kPR = 4;                      // output rows per patch
+constexpr int kSW = 66;                     // staged pixels per row
+constexpr int kStage = (kPR + 2) * kSW * 4; // 16-byte chunks staged
+
+__device__ __forceinline__ uint32_t stage_off(int r, int px, int part) {
+  return uint32_t((r * kSW + px) * 64 + (((part + (px >> 1)) & 3) << 4));
+}
+
+__global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restrict__ in,
                                                      const uint16_t* __restrict__ wf,
                                                      const float* __restrict__ bias,
                                                      uint16_t* __restrict__ out, int B, int H,
                                                      int W) {
   __shared__ bf16x8 wl[18 * 64];
+  __shared__ __attribute__((aligned(16))) unsigned char st[kStage * 16];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wf + size_t(k) * 8);
-  __syncthreads();
   f32x4 bv[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) bv[mb][j] = bias[16 * mb + 4 * q + j];
-  const int tpr = (W + 15) >> 4;
-  const int ntiles = B * H * tpr;
-  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
-  for (int tile = wid; tile < ntiles; tile += nw) {
-    const Tile tl = tile_at(tile, tpr, H);
-    bf16x8 cur[9];
-    load_taps<1>(in, tl, H, W, q, c16, cur);
-    f32x4 acc0 = bv[0], acc1 = bv[1];
+  const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
+  const int npatch = B * pr * pc;
+  // column offsets (bytes) of this lane's three x taps in a staged row
+  uint32_t colo[3];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) colo[dx] = stage_off(0, 16 * wv + c16 + dx, q);
+  // each thread stages up to kChunks 16-byte chunks of a patch; the next
+  // patch's chunks are loaded into registers while the current one computes
+  constexpr int kChunks = (kStage + kB - 1) / kB;
+  bf16x8 pre[kChunks];
+  auto fetch = [&](int patch) {
+    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = int(threadIdx.x) + k * kB;
+      if (c < kStage) {
+        const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
+        int yy = y0 - 1 + r;
+        yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+        int xx = x0 - 1 + px;
+        // x = -1 and x = W wrap; staged pixels further out feed no output
+        xx = xx < 0 ? xx + W : (xx >= W ? (xx - W < W ? xx - W : W - 1) : xx);
+        pre[k] = load8(in + pix(b * H + yy, W, xx) * kC + 8 * part);
+      }
+    }
+  };
+  if (int(blockIdx.x) < npatch) fetch(blockIdx.x);
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+    __syncthreads();  // the previous patch's reads of st are done (and wl is written)
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = int(threadIdx.x) + k * kB;
+      if (c < kStage) {
+        const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
+        *reinterpret_cast<bf16x8*>(st + stage_off(r, px, part)) = pre[k];
+      }
+    }
+    __syncthreads();
+    if (patch + int(gridDim.x) < npatch) fetch(patch + gridDim.x);
+    f32x4 acc[kPR][2];
+#pragma unroll
+    for (int j = 0; j < kPR; ++j) {
+      acc[j][0] = bv[0];
+      acc[j][1] = bv[1];
+    }
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
       const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, cur[t], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, cur[t], acc1, 0, 0, 0);
-      // keep the next tap's weight reads below this point: two fragments
-      // live at a time
-      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < kPR; ++j) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+            st + colo[dx] + uint32_t((j + dy) * kSW * 64));
+        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, v, acc[j][0], 0, 0, 0);
+        acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, v, acc[j][1], 0, 0, 0);
+      }
     }
-    const int px = tl.x0 + c16;
-    if (px < W) {
-      const __amdgpu_buffer_rsrc_t ro = row_rsrc(out, tl.bh, W);
-      const uint32_t o = uint32_t(px) * uint32_t(kC * 2) + uint32_t(8 * q);
-      u32x2 r0, r1;
-      r0[0] = pack_bf16(tanh_fast(acc0[0]), tanh_fast(acc0[1]));
-      r0[1] = pack_bf16(tanh_fast(acc0[2]), tanh_fast(acc0[3]));
-      r1[0] = pack_bf16(tanh_fast(acc1[0]), tanh_fast(acc1[1]));
-      r1[1] = pack_bf16(tanh_fast(acc1[2]), tanh_fast(acc1[3]));
-      __builtin_amdgcn_raw_buffer_store_b64(r0, ro, o, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b64(r1, ro, o + 32u, 0, 0);
+    const int px = x0 + 16 * wv + c16;
+#pragma unroll
+    for (int j = 0; j < kPR; ++j) {
+      const int y = y0 + j;
+      if (y < H && px < W) {
+        uint16_t* o = out + pix(b * H + y, W, px) * kC + 4 * q;
+        u32x2 r0, r1;
+        r0[0] = pack_bf16(tanh_fast(acc[j][0][0]), tanh_fast(acc[j][0][1]));
+        r0[1] = pack_bf16(tanh_fast(acc[j][0][2]), tanh_fast(acc[j][0][3]));
+        r1[0] = pack_bf16(tanh_fast(acc[j][1][0]), tanh_fast(acc[j][1][1]));
+        r1[1] = pack_bf16(tanh_fast(acc[j][1][2]), tanh_fast(acc[j][1][3]));
+        *reinterpret_cast<u32x2*>(o) = r0;
+        *reinterpret_cast<u32x2*>(o + 16) = r1;
+      }
     }
   }
 }
@@ -862,7 +921,12 @@ void launch_srg_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t s
 
 void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, uint16_t* out,
                         int B, int H, int W, hipStream_t s) {
-  const int nb = mfma_blocks(B * H * ((W + 15) / 16));
+  // patches of kPR rows x 64 pixels; as many blocks as the LDS of the 256
+  // CUs holds (160 KB each)
+  const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
+  const int lds = 18 * 64 * 16 + kStage * 16;
+  const int most = 256 * (160 * 1024 / lds);
+  const int nb = np < most ? (np > 0 ? np : 1) : most;
   hipLaunchKernelGGL(c32_fwd_kernel, dim3(nb), dim3(kB), 0, s, in, wf, b, out, B, H, W);
 }
 
