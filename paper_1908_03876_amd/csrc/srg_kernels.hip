@@ -169,11 +169,62 @@ __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restr
 
 // ------------------------------------------------- last layer (32 -> 1)
 
-// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]): four lanes
-// per pixel, each summing eight channels (one 16-byte load per tap, all nine
-// in flight) as four two-channel dot products of BF16 pairs (exact
-// products, FP32 sums), then combined across the four lanes; grid-strided.
-__global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__ a,
+// Patches of kPR rows x 64 pixels, staged in LDS with their one-pixel halo
+// ((kPR + 2) rows x 66 pixels of 64 bytes, periodic wrap) so that every
+// input pixel crosses the vector memory unit once per patch instead of
+// once per tap.  The 16-byte quarter `part` of staged pixel px sits in slot
+// (part + px / 2) % 4 of the pixel, so that eight consecutive pixels read
+// at the same quarter fall on distinct banks.
+constexpr int kPR = 4;                      // output rows per patch
+constexpr int kSW = 66;                     // staged pixels per row
+constexpr int kStage = (kPR + 2) * kSW * 4; // 16-byte chunks staged
+static_assert(kPR == kWaves, "the 32 -> 1 layer maps one wavefront to each patch row");
+
+__device__ __forceinline__ uint32_t stage_off(int r, int px, int part) {
+  return uint32_t((r * kSW + px) * 64 + (((part + (px >> 1)) & 3) << 4));
+}
+
+// Stage the patch's chunks this thread owns into registers (the caller
+// writes them to LDS once the previous patch is done).
+template <int NCH>
+__device__ __forceinline__ void fetch_patch(const uint16_t* __restrict__ in, int patch, int pr,
+                                            int pc, int H, int W, u32x4 (&pre)[NCH]) {
+  const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+  const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    const int c = int(threadIdx.x) + k * kB;
+    if (c < kStage) {
+      const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
+      int yy = y0 - 1 + r;
+      yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+      int xx = x0 - 1 + px;
+      // x = -1 and x = W wrap; staged pixels further out feed no output
+      xx = xx < 0 ? xx + W : (xx >= W ? (xx - W < W ? xx - W : W - 1) : xx);
+      pre[k] = *reinterpret_cast<const u32x4*>(in + pix(b * H + yy, W, xx) * kC + 8 * part);
+    }
+  }
+}
+
+template <int NCH>
+__device__ __forceinline__ void store_patch(unsigned char* st, const u32x4 (&pre)[NCH]) {
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    const int c = int(threadIdx.x) + k * kB;
+    if (c < kStage) {
+      const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
+      *reinterpret_cast<u32x4*>(st + stage_off(r, px, part)) = pre[k];
+    }
+  }
+}
+
+constexpr int kChunks = (kStage + kB - 1) / kB;
+
+// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]): one thread
+// per output pixel of a staged patch (wavefront = patch row), the 32
+// channels of each tap summed as 16 two-channel dot products of BF16 pairs
+// (exact products, FP32 sums) with the weight pairs read as LDS broadcasts.
+__global__ __launch_bounds__(kB, 4) void l3_fwd_kernel(const uint16_t* __restrict__ a,
                                                     const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias,
                                                     float* __restrict__ y, int B, int H, int W,
@@ -181,41 +232,51 @@ __global__ __launch_bounds__(kB) void l3_fwd_kernel(const uint16_t* __restrict__
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   // (W3[2j][t], W3[2j+1][t]) as BF16 pairs, [t][j]
   __shared__ __attribute__((aligned(16))) uint32_t wp[9 * 16];
+  __shared__ __attribute__((aligned(16))) unsigned char st[kStage * 16];
   for (int i = threadIdx.x; i < 9 * 16; i += kB) {
     const int t = i / 16, j = i - 16 * t;
     wp[i] = uint32_t(w[(2 * j) * 9 + t]) | (uint32_t(w[(2 * j + 1) * 9 + t]) << 16);
   }
-  __syncthreads();
-  const int hw = H * W, n = B * hw;
-  const int cg = threadIdx.x & 3;
   const float b0 = bias[0];
-  // the four lanes of a pixel share every iteration (the stride is a
-  // multiple of 4), so they reach the shuffles together
-  for (int p = (blockIdx.x * kB + threadIdx.x) >> 2; p < n; p += (gridDim.x * kB) >> 2) {
-    const int b = p / hw, r = p - b * hw, py = r / W, px = r - py * W;
-    u32x4 q[9];
+  const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
+  const int npatch = B * pr * pc;
+  const int row = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), col = threadIdx.x & 63;
+  // byte offsets of this lane's three x taps (each quarter) in a staged row
+  uint32_t colo[3][4];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(py + t / 3 - 1, H), xx = wrap(px + t % 3 - 1, W);
-      q[t] = *reinterpret_cast<const u32x4*>(a + (size_t(b * H + yy) * W + xx) * kC + 8 * cg);
-    }
-    // all nine tap loads in flight before the first sum
-    __builtin_amdgcn_sched_barrier(0);
+  for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+    for (int part = 0; part < 4; ++part) colo[dx][part] = stage_off(0, col + dx, part);
+  const uint32_t rowo = uint32_t(row * kSW * 64);
+  u32x4 pre[kChunks];
+  if (int(blockIdx.x) < npatch) fetch_patch(a, blockIdx.x, pr, pc, H, W, pre);
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+    __syncthreads();  // the previous patch's reads of st are done (and wp is written)
+    store_patch(st, pre);
+    __syncthreads();
+    if (patch + int(gridDim.x) < npatch) fetch_patch(a, patch + gridDim.x, pr, pc, H, W, pre);
     float acc = 0.f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + 4 * cg]);
+      const int dy = t / 3, dx = t % 3;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // through scalars: a bit cast of a vector element itself reads element 0
-        const uint32_t qe = q[t][e], we = wq[e];
-        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, qe),
-                                              __builtin_bit_cast(bf16x2, we), acc, false);
+      for (int part = 0; part < 4; ++part) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(st + rowo + colo[dx][part] +
+                                                        uint32_t(dy * kSW * 64));
+        const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + 4 * part]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // through scalars: a bit cast of a vector element itself reads element 0
+          const uint32_t ve = v[e], we = wq[e];
+          acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, ve),
+                                                __builtin_bit_cast(bf16x2, we), acc, false);
+        }
       }
     }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    if (cg == 0) y[p] = oscale * (b0 + acc);
+    const int yo = y0 + row, xo = x0 + col;
+    if (yo < H && xo < W) y[pix(b * H + yo, W, xo)] = oscale * (b0 + acc);
   }
 }
 
@@ -423,23 +484,11 @@ __device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, cons
 }
 
 // Forward of a hidden layer: out = bf16(tanh(b + sum_t W_t in[p + off(t)])).
-// A block takes patches of kPR rows x 64 pixels.  It stages the patch with
-// its one-pixel halo, (kPR + 2) rows x 66 pixels of 64 bytes (periodic
-// wrap), in LDS once, so that every input pixel crosses the vector memory
-// unit once per patch instead of once per tap; wavefront w then computes
-// the 16-pixel column w of all kPR rows, lane = (channel group q, pixel
-// c16), reading each weight fragment once per tap for the kPR rows.  The
-// 16-byte quarter `part` of staged pixel px sits in slot (part + px / 2) % 4
-// of the pixel, so that the eight lanes served together (eight pixels, one
-// quarter each) fall on distinct banks.  The accumulators start at the bias.
-constexpr int kPR = 4;                      // output rows per patch
-constexpr int kSW = 66;                     // staged pixels per row
-constexpr int kStage = (kPR + 2) * kSW * 4; // 16-byte chunks staged
-
-__device__ __forceinline__ uint32_t stage_off(int r, int px, int part) {
-  return uint32_t((r * kSW + px) * 64 + (((part + (px >> 1)) & 3) << 4));
-}
-
+// A block walks staged patches (above), loading the next patch into
+// registers while the current one computes; wavefront w computes the
+// 16-pixel column w of all kPR rows, lane = (channel group q, pixel c16),
+// reading each weight fragment once per tap for the kPR rows.  The
+// accumulators start at the bias.
 __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restrict__ in,
                                                      const uint16_t* __restrict__ wf,
                                                      const float* __restrict__ bias,
@@ -461,42 +510,17 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
   uint32_t colo[3];
 #pragma unroll
   for (int dx = 0; dx < 3; ++dx) colo[dx] = stage_off(0, 16 * wv + c16 + dx, q);
-  // each thread stages up to kChunks 16-byte chunks of a patch; the next
-  // patch's chunks are loaded into registers while the current one computes
-  constexpr int kChunks = (kStage + kB - 1) / kB;
-  bf16x8 pre[kChunks];
-  auto fetch = [&](int patch) {
-    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
-    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
-#pragma unroll
-    for (int k = 0; k < kChunks; ++k) {
-      const int c = int(threadIdx.x) + k * kB;
-      if (c < kStage) {
-        const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
-        int yy = y0 - 1 + r;
-        yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
-        int xx = x0 - 1 + px;
-        // x = -1 and x = W wrap; staged pixels further out feed no output
-        xx = xx < 0 ? xx + W : (xx >= W ? (xx - W < W ? xx - W : W - 1) : xx);
-        pre[k] = load8(in + pix(b * H + yy, W, xx) * kC + 8 * part);
-      }
-    }
-  };
-  if (int(blockIdx.x) < npatch) fetch(blockIdx.x);
+  // the next patch's chunks are loaded into registers while the current
+  // one computes
+  u32x4 pre[kChunks];
+  if (int(blockIdx.x) < npatch) fetch_patch(in, blockIdx.x, pr, pc, H, W, pre);
   for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
     const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
     const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
     __syncthreads();  // the previous patch's reads of st are done (and wl is written)
-#pragma unroll
-    for (int k = 0; k < kChunks; ++k) {
-      const int c = int(threadIdx.x) + k * kB;
-      if (c < kStage) {
-        const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
-        *reinterpret_cast<bf16x8*>(st + stage_off(r, px, part)) = pre[k];
-      }
-    }
+    store_patch(st, pre);
     __syncthreads();
-    if (patch + int(gridDim.x) < npatch) fetch(patch + gridDim.x);
+    if (patch + int(gridDim.x) < npatch) fetch_patch(in, patch + gridDim.x, pr, pc, H, W, pre);
     f32x4 acc[kPR][2];
 #pragma unroll
     for (int j = 0; j < kPR; ++j) {
@@ -891,8 +915,11 @@ void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, in
 
 void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, float* y, int B,
                        int H, int W, float oscale, hipStream_t s) {
-  const int nb = blocks_for(size_t(4) * B * H * W);
-  hipLaunchKernelGGL(l3_fwd_kernel, dim3(nb < 2048 ? nb : 2048), dim3(kB), 0, s, a, w, b,
+  // patches of kPR rows x 64 pixels; four blocks per CU (the kernel is
+  // built for four wavefronts per SIMD, and four stages fit in 160 KB)
+  const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
+  const int nb = np < 1024 ? (np > 0 ? np : 1) : 1024;
+  hipLaunchKernelGGL(l3_fwd_kernel, dim3(nb), dim3(kB), 0, s, a, w, b,
                      y, B, H, W, oscale);
 }
 
