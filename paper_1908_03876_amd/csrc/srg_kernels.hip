@@ -435,51 +435,23 @@ __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restric
   bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
 }
 
-// A 16-pixel tile of one row: field b, row y, first pixel x0.  The tile
-// index is wave-uniform, so the decomposition runs on the scalar unit.
-struct Tile {
-  int bh, b, y, x0;
-};
-
-__device__ __forceinline__ Tile tile_at(int tile, int tpr, int H) {
-  tile = __builtin_amdgcn_readfirstlane(tile);
-  Tile t;
-  t.bh = tile / tpr;
-  t.x0 = (tile - t.bh * tpr) * 16;
-  t.b = t.bh / H;
-  t.y = t.bh - t.b * H;
-  return t;
-}
-
-// Buffer resource over row bh of a channels-last BF16 field (W pixels of
-// 64 bytes): the row base is a scalar 64-bit address, the per-lane offsets
-// within the row stay 32-bit, and an offset past the row reads 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const uint16_t* f, int bh, int W) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(f + size_t(bh) * W * kC),
-                                           (short)0, W * kC * 2, 0x00020000);
-}
-
-// The nine taps p + sgn off(t), t = 3 (dy + 1) + (dx + 1), of a 16-pixel
-// tile, lane = (channel group q, pixel c16), as MFMA B fragments: three
-// wrapped rows (scalar resources) times three wrapped columns (per-lane
-// byte offsets).  A ragged tile's lanes past the row end read the last
-// pixel instead (their results are not stored).
+// The 18 MFMAs per tile of a staged patch for the kPR rows of wavefront
+// column wv: tap t = 3 dy + dx reads the staged pixel at p + sgn off(t).
 template <int SGN>
-__device__ __forceinline__ void load_taps(const uint16_t* __restrict__ src, const Tile& tl,
-                                          int H, int W, int q, int c16, bf16x8 (&v)[9]) {
-  const int px = tl.x0 + c16;
-  const int pl = px < W ? px : W - 1;
-  uint32_t col[3];
+__device__ __forceinline__ void staged_taps(const unsigned char* st, const bf16x8* wl,
+                                            const uint32_t (&colo)[3], int lane,
+                                            f32x4 (&acc)[kPR][2]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    col[c] = uint32_t(wrap(pl + SGN * (c - 1), W)) * uint32_t(kC * 2) + uint32_t(16 * q);
+  for (int t = 0; t < 9; ++t) {
+    const int dy = SGN > 0 ? t / 3 : 2 - t / 3, dx = SGN > 0 ? t % 3 : 2 - t % 3;
+    const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    const int yy = wrap(tl.y + SGN * (r - 1), H);
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc(src, tl.b * H + yy, W);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      v[3 * r + c] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, col[c], 0, 0));
+    for (int j = 0; j < kPR; ++j) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+          st + colo[dx] + uint32_t((j + dy) * kSW * 64));
+      acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, v, acc[j][0], 0, 0, 0);
+      acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, v, acc[j][1], 0, 0, 0);
+    }
   }
 }
 
@@ -527,18 +499,7 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
       acc[j][0] = bv[0];
       acc[j][1] = bv[1];
     }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int dy = t / 3, dx = t % 3;
-      const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
-#pragma unroll
-      for (int j = 0; j < kPR; ++j) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(
-            st + colo[dx] + uint32_t((j + dy) * kSW * 64));
-        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, v, acc[j][0], 0, 0, 0);
-        acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, v, acc[j][1], 0, 0, 0);
-      }
-    }
+    staged_taps<1>(st, wl, colo, lane, acc);
     const int px = x0 + 16 * wv + c16;
 #pragma unroll
     for (int j = 0; j < kPR; ++j) {
@@ -558,54 +519,62 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
 }
 
 // Backward data of a hidden layer with the previous tanh folded in:
-// dz_prev[p][ci] = bf16((sum_t W_t^T dz[p - off(t)])[ci] (1 - a_prev[p][ci]^2)).
-// The transposed weight fragments sit in LDS, as in the forward.
-__global__ __launch_bounds__(kB) void c32_bwd_data_kernel(const uint16_t* __restrict__ dz,
-                                                          const uint16_t* __restrict__ wt,
-                                                          const uint16_t* __restrict__ aprev,
-                                                          uint16_t* __restrict__ dzprev, int B,
-                                                          int H, int W) {
+// dz_prev[p][ci] = bf16((sum_t W_t^T dz[p - off(t)])[ci] (1 - a_prev[p][ci]^2)),
+// on the staged, prefetched patches of the forward with the transposed
+// weight fragments in LDS.
+__global__ __launch_bounds__(kB, 3) void c32_bwd_data_kernel(const uint16_t* __restrict__ dz,
+                                                             const uint16_t* __restrict__ wt,
+                                                             const uint16_t* __restrict__ aprev,
+                                                             uint16_t* __restrict__ dzprev,
+                                                             int B, int H, int W) {
   __shared__ bf16x8 wl[18 * 64];
+  __shared__ __attribute__((aligned(16))) unsigned char st[kStage * 16];
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   for (int k = threadIdx.x; k < 18 * 64; k += kB) wl[k] = load8(wt + size_t(k) * 8);
-  __syncthreads();
-  const int tpr = (W + 15) >> 4;
-  const int ntiles = B * H * tpr;
-  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
-  for (int tile = wid; tile < ntiles; tile += nw) {
-    const Tile tl = tile_at(tile, tpr, H);
-    bf16x8 cur[9];
-    load_taps<-1>(dz, tl, H, W, q, c16, cur);
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
+  const int npatch = B * pr * pc;
+  uint32_t colo[3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const bf16x8 w0 = wl[(t * 2) * 64 + lane], w1 = wl[(t * 2 + 1) * 64 + lane];
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, cur[t], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, cur[t], acc1, 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
+  for (int dx = 0; dx < 3; ++dx) colo[dx] = stage_off(0, 16 * wv + c16 + dx, q);
+  u32x4 pre[kChunks];
+  if (int(blockIdx.x) < npatch) fetch_patch(dz, blockIdx.x, pr, pc, H, W, pre);
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+    __syncthreads();  // the previous patch's reads of st are done (and wl is written)
+    store_patch(st, pre);
+    __syncthreads();
+    if (patch + int(gridDim.x) < npatch) fetch_patch(dz, patch + gridDim.x, pr, pc, H, W, pre);
+    f32x4 acc[kPR][2];
+#pragma unroll
+    for (int j = 0; j < kPR; ++j) {
+      acc[j][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc[j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    const int px = tl.x0 + c16;
-    if (px < W) {
-      const __amdgpu_buffer_rsrc_t ra = row_rsrc(aprev, tl.bh, W);
-      const __amdgpu_buffer_rsrc_t rd = row_rsrc(dzprev, tl.bh, W);
-      const uint32_t o = uint32_t(px) * uint32_t(kC * 2) + uint32_t(8 * q);
-      const u32x2 p0 = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, o, 0, 0));
-      const u32x2 p1 = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, o + 32u, 0, 0));
-      float av[2][4] = {{lo16(p0[0]), hi16(p0[0]), lo16(p0[1]), hi16(p0[1])},
-                        {lo16(p1[0]), hi16(p1[0]), lo16(p1[1]), hi16(p1[1])}};
-      float gv[2][4] = {{acc0[0], acc0[1], acc0[2], acc0[3]},
-                        {acc1[0], acc1[1], acc1[2], acc1[3]}};
-      u32x2 r[2];
+    staged_taps<-1>(st, wl, colo, lane, acc);
+    const int px = x0 + 16 * wv + c16;
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+    for (int j = 0; j < kPR; ++j) {
+      const int y = y0 + j;
+      if (y < H && px < W) {
+        const size_t o = pix(b * H + y, W, px) * kC + 4 * q;
+        const u32x2 p0 = *reinterpret_cast<const u32x2*>(aprev + o);
+        const u32x2 p1 = *reinterpret_cast<const u32x2*>(aprev + o + 16);
+        const float av[2][4] = {{lo16(p0[0]), hi16(p0[0]), lo16(p0[1]), hi16(p0[1])},
+                                {lo16(p1[0]), hi16(p1[0]), lo16(p1[1]), hi16(p1[1])}};
+        u32x2 r[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const float g0 = gv[mb][2 * h] * (1.f - av[mb][2 * h] * av[mb][2 * h]);
-          const float g1 = gv[mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
-          r[mb][h] = pack_bf16(g0, g1);
-        }
-      __builtin_amdgcn_raw_buffer_store_b64(r[0], rd, o, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b64(r[1], rd, o + 32u, 0, 0);
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float g0 = acc[j][mb][2 * h] * (1.f - av[mb][2 * h] * av[mb][2 * h]);
+            const float g1 = acc[j][mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
+            r[mb][h] = pack_bf16(g0, g1);
+          }
+        *reinterpret_cast<u32x2*>(dzprev + o) = r[0];
+        *reinterpret_cast<u32x2*>(dzprev + o + 16) = r[1];
+      }
     }
   }
 }
@@ -891,14 +860,6 @@ int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
 int blocks_for_pixels(int B, int H, int W) { return blocks_for(size_t(B) * H * W); }
 
 
-// blocks of the MFMA kernels: up to 2048 (eight wavefronts per SIMD), each
-// wavefront walking many tiles so that the block loads its weight
-// fragments into LDS once
-int mfma_blocks(int ntiles) {
-  const int want = (ntiles + kWaves - 1) / kWaves;
-  return want < 2048 ? (want > 0 ? want : 1) : 2048;
-}
-
 }  // namespace
 
 void launch_srg_l0_fwd(const float* x, const uint16_t* w, const float* b, uint16_t* out, int B,
@@ -959,7 +920,9 @@ void launch_srg_c32_fwd(const uint16_t* in, const uint16_t* wf, const float* b, 
 
 void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint16_t* aprev,
                              uint16_t* dzprev, int B, int H, int W, hipStream_t s) {
-  const int nb = mfma_blocks(B * H * ((W + 15) / 16));
+  // staged patches as in the forward, three blocks per CU
+  const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
+  const int nb = np < 768 ? (np > 0 ? np : 1) : 768;
   hipLaunchKernelGGL(c32_bwd_data_kernel, dim3(nb), dim3(kB), 0, s, dz, wt, aprev, dzprev, B, H,
                      W);
 }
