@@ -92,8 +92,10 @@ class MRTSolve(torch.nn.Module):
             sv = self._sv
         self._adj(self.dp.struct, self.tape.handle, self._u0, self._v0, self._c, self._su, sv,
                   self._g, self._au0 if want_u0 else None, self._av0 if want_v0 else None)
-        dt = self.dp.dtype
-        gc = self._g[..., :nx].to(dt)
+        # a copy, never a view: in FP64 .to() would return the solver's own
+        # buffer, which the next backward overwrites (and which autograd may
+        # keep as .grad and accumulate into)
+        gc = self._g[..., :nx].to(self.dp.dtype, copy=True)
         gu0 = self._au0[..., :nx].clone() if want_u0 else None
         gv0 = self._av0[..., :nx].clone() if want_v0 else None
         return gc, gu0, gv0

@@ -106,6 +106,37 @@ def test_autograd_second_forward_before_backward():
     s.close()
 
 
+def test_autograd_gradient_is_a_copy_not_the_solver_buffer():
+    """FP64, a loss in which the control enters only through the solve: the
+    gradient autograd stores is a tensor of its own, so a second backward
+    after zero_grad(set_to_none=False) gives the same gradient (not twice
+    it), and a backward without zeroing accumulates exactly once more."""
+    import torch
+    from paper_1908_03876_amd.autograd import MRTSolve
+    p = _copy128(40)
+    s = MRTSolve(p, dtype=torch.float64, ckpt_every=16)
+    c = torch.tensor(p.control, dtype=torch.float64, device="cuda", requires_grad=True)
+    ut = torch.tensor(p.u_target, dtype=torch.float64, device="cuda")
+    fl = torch.tensor(p.fluid, device="cuda")
+
+    def backward_once():
+        uN, _ = s(c)
+        (0.5 * (((uN - ut) * fl) ** 2).sum()).backward()
+
+    backward_once()
+    g1 = c.grad.clone()
+    assert c.grad.data_ptr() != s._g.data_ptr()
+    assert g1.abs().max() > 0
+    c.grad.zero_()
+    backward_once()
+    assert torch.equal(c.grad, g1)
+    backward_once()
+    assert torch.equal(c.grad, 2.0 * g1)
+    ref = O.cost_gradient(p.copy(alpha=0.0))
+    assert rel_l2(g1.cpu().numpy(), ref["grad"], p.fluid) <= 1e-12
+    s.close()
+
+
 def test_autograd_initial_state_gradient():
     """Gradients w.r.t. u0 and v0 through the equilibrium initialisation,
     against the oracle's adjoint."""
