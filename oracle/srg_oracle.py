@@ -11,7 +11,17 @@ the three hidden activations are rounded to bfloat16 after the tanh, and
 the gradients with respect to the hidden pre-activations (after the
 factor 1 - a^2) are rounded to bfloat16; the input, the output, dL/dy and
 all sums stay in full precision here.  Weights are passed in already
-rounded.
+rounded.  bf16=False is the unrounded network: every value in FP64.
+
+Error budget of BF16 storage (`storage_noise_budget`): the standard
+probabilistic model of rounding, each stored value a carrying an
+independent error uniform in [-ulp(a)/2, ulp(a)/2] (ulp = the bfloat16
+spacing at a: 8 significant bits, so 2^-8 relative at most).  The budget of
+an output is the RMS, over seeded draws of those errors at the storage
+points, of its deviation from the unrounded network; the tests allow three
+times that (plus the FP32 accumulation term of `fp32_sum_slack`) between
+the device and the unrounded network.  The model itself is pinned against
+the deterministic round-to-nearest network (bf16=True) on the CPU.
 """
 from __future__ import annotations
 
@@ -31,7 +41,7 @@ def conv(x, w, b, iscale=1.0, oscale=1.0):
     z = np.zeros((B, O, H, W))
     for dy, dx in TAPS:
         xs = shift(x, dy, dx) * iscale
-        z += np.einsum("oc,bchw->bohw", w[:, :, dy + 1, dx + 1], xs)
+        z += np.einsum("oc,bchw->bohw", w[:, :, dy + 1, dx + 1], xs, optimize=True)
     return oscale * (z + b[None, :, None, None])
 
 
@@ -42,16 +52,25 @@ def conv_backward(dz, x, w, iscale=1.0, oscale=1.0):
     dx = np.zeros_like(x)
     for dy, dx_ in TAPS:
         xs = shift(x, dy, dx_) * iscale
-        dw[:, :, dy + 1, dx_ + 1] = np.einsum("bohw,bchw->oc", g, xs)
+        dw[:, :, dy + 1, dx_ + 1] = np.einsum("bohw,bchw->oc", g, xs, optimize=True)
         # z[q] uses x[q + off]: dx[p] gets w * g[p - off]
-        dx += iscale * np.einsum("oc,bohw->bchw", w[:, :, dy + 1, dx_ + 1], shift(g, -dy, -dx_))
+        dx += iscale * np.einsum("oc,bohw->bchw", w[:, :, dy + 1, dx_ + 1], shift(g, -dy, -dx_),
+                                optimize=True)
     db = g.sum(axis=(0, 2, 3))
     return dx, dw, db
 
 
-def forward(params, x, s_in, s_out, bf16=False):
-    """params: list of 4 (w, b).  Returns output and the activations."""
-    r = bf16_round if bf16 else (lambda a: a)
+def _store(bf16, store):
+    if store is not None:
+        return store
+    return bf16_round if bf16 else (lambda a: a)
+
+
+def forward(params, x, s_in, s_out, bf16=False, store=None):
+    """params: list of 4 (w, b).  Returns output and the activations.
+    `store`, if given, is applied to each stored hidden activation in place
+    of the bf16 flag's rounding."""
+    r = _store(bf16, store)
     a0 = x[:, None]
     a1 = r(np.tanh(conv(a0, *params[0], iscale=s_in)))
     a2 = r(np.tanh(conv(a1, *params[1])))
@@ -69,9 +88,10 @@ def mse(pred, target, border):
     return (d * d).sum() / n, 2.0 * d / n
 
 
-def backward(params, acts, dy, s_in, s_out, bf16=False):
-    """dL/dx and [(dL/dw, dL/db)] for the layers given dL/dy."""
-    r = bf16_round if bf16 else (lambda a: a)
+def backward(params, acts, dy, s_in, s_out, bf16=False, store=None):
+    """dL/dx and [(dL/dw, dL/db)] for the layers given dL/dy; `store` as in
+    forward, applied to each stored hidden gradient."""
+    r = _store(bf16, store)
     a0, a1, a2, a3 = acts
     grads = [None] * 4
     g = dy[:, None]
@@ -102,3 +122,54 @@ def bf16_round(a):
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_ulp(a):
+    """Spacing of bfloat16 numbers at |a| (8 significant bits): 2^(e - 7)
+    for 2^e <= |a| < 2^(e+1); 0 at 0."""
+    a = np.abs(np.asarray(a, dtype=np.float64))
+    out = np.zeros_like(a)
+    nz = a > 0
+    out[nz] = np.exp2(np.floor(np.log2(a[nz])) - 7.0)
+    return out
+
+
+def _outputs(params, x, s_in, s_out, dy, target, border, store):
+    y, acts = forward(params, x, s_in, s_out, store=store)
+    out = {"y": y}
+    if target is not None:
+        out["loss"], dy = mse(y, target, border)
+    if dy is not None:
+        dx, grads = backward(params, acts, dy, s_in, s_out, store=store)
+        out["dx"] = dx
+        for k, (dw, db) in enumerate(grads):
+            out[f"dW{k}"], out[f"db{k}"] = dw, db
+    return out
+
+
+def storage_noise_budget(params, x, s_in, s_out, dy=None, target=None, border=0,
+                         samples=8, seed=0):
+    """Unrounded outputs and the RMS deviation of each from them under the
+    storage-noise model: y always; with dy (or target and border, the MSE
+    loss) also dx and every dW_k, db_k, and the loss.  Returns
+    (exact, sigma), two dicts of arrays / floats keyed alike."""
+    exact = _outputs(params, x, s_in, s_out, dy, target, border, None)
+    rng = np.random.default_rng(seed)
+
+    def noisy(a):
+        return a + rng.uniform(-0.5, 0.5, a.shape) * bf16_ulp(a)
+
+    acc = {k: 0.0 for k in exact}
+    for _ in range(samples):
+        o = _outputs(params, x, s_in, s_out, dy, target, border, noisy)
+        for k in exact:
+            acc[k] += float(np.sum((np.asarray(o[k]) - np.asarray(exact[k])) ** 2))
+    sigma = {k: np.sqrt(v / samples) for k, v in acc.items()}
+    return exact, sigma
+
+
+def fp32_sum_slack(norm, n_terms, k=3.0):
+    """k standard deviations of the error of FP32 sums of n_terms values
+    (random-walk model, unit roundoff 2^-24 per addition) relative to the
+    norm of the result."""
+    return k * 2.0 ** -24 * np.sqrt(n_terms) * norm

@@ -124,8 +124,50 @@ MUTANTS3 = [
      "zn = (zn % p.nz + p.nz) % p.nz;", "zn = (zn % p.ny + p.ny) % p.ny;"),
 ]
 
+# the conjugate-gradient rules, against their identities
+MUTANTS_NCG = [
+    ("CG: Polak-Ribiere written as Fletcher-Reeves",
+     "return max(0.0, (G * y).sum() / (Gp * Gp).sum())",
+     "return max(0.0, (G * G).sum() / (Gp * Gp).sum())"),
+    ("CG: Polak-Ribiere not clipped at zero",
+     "return max(0.0, (G * y).sum() / (Gp * Gp).sum())", "return (G * y).sum() / (Gp * Gp).sum()"),
+    ("CG: Hestenes-Stiefel with the Polak-Ribiere denominator",
+     "return max(0.0, (G * y).sum() / dy) if dy != 0.0 else 0.0",
+     "return max(0.0, (G * y).sum() / (Gp * Gp).sum()) if dy != 0.0 else 0.0"),
+    ("CG: Dai-Yuan written as Fletcher-Reeves",
+     "return (G * G).sum() / dy if dy != 0.0 else 0.0",
+     "return (G * G).sum() / (Gp * Gp).sum() if dy != 0.0 else 0.0"),
+    ("CG: Dai-Yuan written as Hestenes-Stiefel",
+     "return (G * G).sum() / dy if dy != 0.0 else 0.0",
+     "return (G * y).sum() / dy if dy != 0.0 else 0.0"),
+    ("CG: gradient change with the wrong sign",
+     "y = G - Gp", "y = Gp - G"),
+]
+
+# the surrogate's network reference, Adam, loss and storage-noise model
+MUTANTS_SRG = [
+    ("Adam: b1 in the second-moment decay",
+     "v = b2 * v + (1 - b2) * g * g", "v = b1 * v + (1 - b1) * g * g"),
+    ("Adam: second-moment bias correction with b1",
+     "np.sqrt(v / (1 - b2 ** step))", "np.sqrt(v / (1 - b1 ** step))"),
+    ("MSE: normalised by the whole field",
+     "return (d * d).sum() / n, 2.0 * d / n", "return (d * d).sum() / d.size, 2.0 * d / d.size"),
+    ("MSE: border not excluded",
+     "m[..., border:H - border, border:W - border] = True", "m[...] = True"),
+    ("conv backward: taps not mirrored for the input gradient",
+     "shift(g, -dy, -dx_)", "shift(g, dy, dx_)"),
+    ("network backward: tanh derivative with the wrong sign",
+     "g = r(dx2 * (1 - a2 * a2))", "g = r(dx2 * (1 + a2 * a2))"),
+    ("storage noise: half the bfloat16 spacing",
+     "np.floor(np.log2(a[nz])) - 7.0", "np.floor(np.log2(a[nz])) - 8.0"),
+    ("storage noise: a full spacing either way",
+     "rng.uniform(-0.5, 0.5, a.shape)", "rng.uniform(-1.0, 1.0, a.shape)"),
+]
+
 CASES = ([(m, "mrt_oracle.cpp", "test_oracle_pins.py") for m in MUTANTS] +
-         [(m, "mrt3d_oracle.cpp", "test_oracle3d_pins.py") for m in MUTANTS3])
+         [(m, "mrt3d_oracle.cpp", "test_oracle3d_pins.py") for m in MUTANTS3] +
+         [(m, "ncg_oracle.py", "test_ncg_oracle.py") for m in MUTANTS_NCG] +
+         [(m, "srg_oracle.py", "test_srg_oracle.py") for m in MUTANTS_SRG])
 
 
 def _copy_tree(dst):

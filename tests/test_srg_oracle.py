@@ -75,3 +75,84 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([0.3, -4.0, 1e-3])
     wn, m, v = S.adam(w, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     np.testing.assert_allclose(wn, w - 0.01 * np.sign(g), rtol=0, atol=1e-7)
+
+
+def test_adam_second_moment_decay_closed_form():
+    """Two steps with gradients g then 2g: the bias-corrected moments are the
+    normalised exponentially weighted sums m^ = (b1 g + 2g)(1 - b1)/(1 - b1^2)
+    = (b1 + 2) g/(1 + b1) and v^ = (b2 + 4) g^2/(1 + b2), so the second move
+    is lr (b1 + 2)/(1 + b1) sqrt((1 + b2)/(b2 + 4)) sign(g); it depends on b2
+    (with b1 in its place the move differs by 1.5%)."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.01, 1e-8
+    g = np.array([0.3, -4.0, 2.5e-3, 7.0])
+    w0 = np.array([1.0, -2.0, 0.5, 0.0])
+    w1, m, v = S.adam(w0, g, np.zeros(4), np.zeros(4), 1, lr)
+    w2, m, v = S.adam(w1, 2.0 * g, m, v, 2, lr)
+    move = lr * (b1 + 2.0) / (1.0 + b1) * np.sqrt((1.0 + b2) / (b2 + 4.0))
+    np.testing.assert_allclose(w1 - w2, move * np.sign(g), rtol=1e-5, atol=0)
+    # the raw moments are the weighted sums themselves
+    np.testing.assert_allclose(m, (1 - b1) * (b1 * g + 2.0 * g), rtol=1e-14)
+    np.testing.assert_allclose(v, (1 - b2) * (b2 * g * g + 4.0 * g * g), rtol=1e-14)
+    # a third step back to g: v^ = (b2^2 + 4 b2 + 1) g^2 (1 - b2)/(1 - b2^3)
+    w3, m, v = S.adam(w2, g, m, v, 3, lr)
+    mh = (b1 * b1 + 2.0 * b1 + 1.0) * (1 - b1) / (1 - b1 ** 3)
+    vh = (b2 * b2 + 4.0 * b2 + 1.0) * (1 - b2) / (1 - b2 ** 3)
+    np.testing.assert_allclose(w2 - w3, lr * mh / np.sqrt(vh) * np.sign(g), rtol=1e-5, atol=0)
+
+
+def test_mse_counts_interior_pixels_only():
+    """Hand case: B = 2 fields of 6 x 7 with a border of 2 leave 2 x 3
+    interior pixels each, n = 12.  A unit error on every interior pixel of
+    the first field and errors of 5 on border pixels give loss 6/12 and
+    gradient 2/12 inside, 0 on the border and in the second field."""
+    pred = np.zeros((2, 6, 7))
+    pred[0, 2:4, 2:5] = 1.0
+    pred[0, 0, :] = 5.0
+    pred[1, :, 6] = -5.0
+    pred[1, 5, 3] = 5.0
+    loss, g = S.mse(pred, np.zeros_like(pred), border=2)
+    assert loss == 0.5
+    want = np.zeros_like(pred)
+    want[0, 2:4, 2:5] = 2.0 / 12.0
+    np.testing.assert_array_equal(g, want)
+
+
+@pytest.mark.parametrize("B,H,W", [(3, 24, 20), (2, 37, 45)])
+def test_storage_noise_model_matches_round_to_nearest(B, H, W):
+    """The BF16 storage budget's noise model (independent uniform errors of
+    half a bfloat16 spacing at each stored hidden activation and gradient)
+    predicts the deviation of the deterministic round-to-nearest network
+    from the unrounded one: their ratio is close to 1 for the output, the
+    input gradient and every weight gradient (each a sum of many errors),
+    and within a factor 2 for the bias gradients (sums over few channels)."""
+    rng = np.random.default_rng(B * 7 + H)
+    shapes = [(32, 1), (32, 32), (32, 32), (1, 32)]
+    params = [(S.bf16_round(rng.normal(0, 1 / np.sqrt(9 * c), (o, c, 3, 3))),
+               rng.normal(0, 0.1, o)) for o, c in shapes]
+    x = rng.normal(0, 3.0, (B, H, W))
+    dy = rng.standard_normal((B, H, W))
+    exact, sigma = S.storage_noise_budget(params, x, 0.2, 0.1, dy=dy, samples=8, seed=3)
+    y, acts = S.forward(params, x, 0.2, 0.1, bf16=True)
+    dx, grads = S.backward(params, acts, dy, 0.2, 0.1, bf16=True)
+    det = {"y": y, "dx": dx}
+    for k, (dw, db) in enumerate(grads):
+        det[f"dW{k}"], det[f"db{k}"] = dw, db
+    for k, v in det.items():
+        d = np.linalg.norm(v - exact[k])
+        if k == "db3":  # s_out * sum(dy): nothing stored on its path
+            assert d == 0.0 and sigma[k] == 0.0
+            continue
+        lo, hi = (0.5, 2.0) if k.startswith("db") else (0.7, 1.4)
+        assert lo * sigma[k] <= d <= hi * sigma[k], (k, d / sigma[k])
+    # BF16 storage costs about 2^-8 relative on every output
+    rel = np.linalg.norm(y - exact["y"]) / np.linalg.norm(exact["y"])
+    assert 5e-4 < rel < 1e-2
+
+
+def test_bf16_ulp():
+    a = np.array([1.0, 1.5, 0.75, -3.0, 0.0, 2.0 ** -20])
+    np.testing.assert_array_equal(S.bf16_ulp(a), [2.0 ** -7, 2.0 ** -7, 2.0 ** -8, 2.0 ** -6,
+                                                  0.0, 2.0 ** -27])
+    # every bfloat16 rounding error is within half a spacing
+    x = np.random.default_rng(0).normal(0, 10, 10000)
+    assert np.all(np.abs(S.bf16_round(x) - x) <= 0.5 * S.bf16_ulp(x))
