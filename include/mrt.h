@@ -206,6 +206,23 @@ int cost_gradient(const mrt_problem* p, mrt_tape* t, const void* uN,
                   const double* grad_accum, void* seed_out, void* grad_out,
                   mrt_scalars* out /* host */, void* stream);
 
+/* Allocation-free variant of cost_gradient, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as cost_gradient without the tape: solid nodes come from
+ * p->grid.mask directly (non-zero = solid; NULL = none) and the fluid count
+ * is reduced in the same call.  The block partials live in a static device
+ * array of about 41 KB that each device holds until the process ends; the
+ * call allocates nothing and its results equal cost_gradient's bit for bit.
+ * Maximum size: nx * ny <= 2^30 nodes (MRT_EINVAL beyond).  Calls that
+ * overlap on one device share that array and race: serialise them (one
+ * stream, or host-side ordering).  Synchronises `stream`. */
+int cost_gradient_noalloc(const mrt_problem* p, const void* uN,
+                          const void* u_target, const void* control,
+                          const double* grad_accum, void* seed_out,
+                          void* grad_out, mrt_scalars* out /* host */,
+                          void* stream);
+
 /* Gradient step (Section 2.4, Step 5): control <- clamp(control - zeta *
  * grad, lo, hi) on fluid nodes.  zeta <= 0 selects the heuristic step
  * zeta = min(1, 1/||grad||_inf) (Remark after Step 6), computed on the

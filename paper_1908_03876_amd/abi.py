@@ -93,7 +93,8 @@ MRT_FIELD_UN, MRT_FIELD_VN, MRT_FIELD_GRAD = 4, 5, 6
 
 EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
-           "cost_gradient", "gd_step", "mrt_last_error", "mrt_timing_enable",
+           "cost_gradient", "cost_gradient_noalloc", "gd_step", "mrt_last_error",
+           "mrt_timing_enable",
            "mrt_timing_reset", "mrt_timing_read", "mrt_tlm", "mrt_dot", "mrt_axpby",
            "mrt_cadjoint",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
@@ -129,6 +130,8 @@ def _load():
     L.amrt_adjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cost_gradient.argtypes = [P, vp, vp, vp, vp, vp, vp, vp,
                                 ctypes.POINTER(mrt_scalars), vp]
+    L.cost_gradient_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp,
+                                        ctypes.POINTER(mrt_scalars), vp]
     L.gd_step.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
     L.mrt_tlm.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -263,6 +266,16 @@ def cost_gradient(p, tape, uN, u_target, control, grad_accum=None,
     _check(lib.cost_gradient(ctypes.byref(p), tape, _ptr(uN), _ptr(u_target),
                              _ptr(control), _ptr(grad_accum), _ptr(seed_out),
                              _ptr(grad_out), ctypes.byref(s), _stream(stream)))
+    return {"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
+            "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid}
+
+
+def cost_gradient_noalloc(p, uN, u_target, control, grad_accum=None,
+                          seed_out=None, grad_out=None, stream=None) -> dict:
+    s = mrt_scalars()
+    _check(lib.cost_gradient_noalloc(ctypes.byref(p), _ptr(uN), _ptr(u_target),
+                                     _ptr(control), _ptr(grad_accum), _ptr(seed_out),
+                                     _ptr(grad_out), ctypes.byref(s), _stream(stream)))
     return {"J": s.J, "J_track": s.J_track, "J_reg": s.J_reg,
             "grad_inf": s.grad_inf, "grad_l2": s.grad_l2, "n_fluid": s.n_fluid}
 

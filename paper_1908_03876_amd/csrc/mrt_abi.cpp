@@ -932,6 +932,58 @@ int cost_gradient(const mrt_problem* p, mrt_tape* t, const void* uN,
                                 seed_out, grad_out, out, s);
 }
 
+int cost_gradient_noalloc(const mrt_problem* p, const void* uN, const void* u_target,
+                          const void* control, const double* grad_accum, void* seed_out,
+                          void* grad_out, mrt_scalars* out, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!uN || !u_target || !control)
+    return fail(MRT_EINVAL, "uN, u_target, control required");
+  if (grad_accum && !grad_out)
+    return fail(MRT_EINVAL, "grad_out required with grad_accum");
+  const mrt_grid& gr = p->grid;
+  const size_t nodes = size_t(gr.nx) * size_t(gr.ny);
+  if (nodes > mrt::kNoallocMaxNodes)
+    return fail(MRT_EINVAL,
+                "cost_gradient_noalloc: %zu nodes exceed the maximum of %zu (2^30)", nodes,
+                mrt::kNoallocMaxNodes);
+  mrt::Geometry g{};
+  g.nx = gr.nx;
+  g.ny = gr.ny;
+  g.pitch = gr.pitch;
+  g.periodic = gr.periodic;
+  g.masked = gr.mask != nullptr;
+  g.plane = size_t(gr.ny) * size_t(gr.pitch);
+  g.nsx = (gr.nx + 63) / 64;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double h[2 * mrt::kRedSlots];
+  const hipError_t e =
+      gr.dtype == MRT_F64
+          ? mrt::launch_cost_grad_noalloc<double>(
+                g, gr.mask, static_cast<const double*>(uN),
+                static_cast<const double*>(u_target), static_cast<const double*>(control),
+                grad_accum, static_cast<double*>(seed_out), static_cast<double*>(grad_out),
+                p->alpha, h, s)
+          : mrt::launch_cost_grad_noalloc<float>(
+                g, gr.mask, static_cast<const float*>(uN),
+                static_cast<const float*>(u_target), static_cast<const float*>(control),
+                grad_accum, static_cast<float*>(seed_out), static_cast<float*>(grad_out),
+                p->alpha, h, s);
+  if (e != hipSuccess)
+    return fail(MRT_EHIP, "cost_gradient_noalloc: %s", hipGetErrorString(e));
+  mrt_scalars r{};
+  r.J_track = h[0];
+  r.J_reg = h[1];
+  r.J = h[0] + h[1];
+  r.grad_l2 = grad_accum ? std::sqrt(h[2]) : 0.0;
+  r.grad_inf = grad_accum ? h[3] : 0.0;
+  r.n_fluid = int64_t(h[mrt::kRedSlots]);
+  if (out) *out = r;
+  if (h[4] != 0.0 || !std::isfinite(r.J) || !std::isfinite(r.grad_l2))
+    return fail(MRT_ENONFINITE, "non-finite cost or gradient (%g values)", h[4]);
+  return MRT_OK;
+}
+
 int gd_step(const mrt_problem* p, mrt_tape* t, void* control, const void* grad,
             double zeta, double lo, double hi, double* zeta_used,
             void* stream) {

@@ -183,6 +183,18 @@ void launch_gd_step(const Geometry& g, T* ctrl,
 void launch_count_fluid(const Geometry& g, double* partials, double* result,
                         hipStream_t s);
 
+// Cost and gradient reduction of launch_cost_grad without a tape: solid
+// nodes from the caller's byte mask (null = none), the block partials and
+// results in a device-resident static array of kNoallocScratchDoubles
+// doubles (no allocation).  Writes host_out[0..4] = the reduced slots above
+// and host_out[5] = the fluid node count, and synchronises the stream.
+constexpr int kNoallocScratchDoubles = kRedBlocks * kRedSlots + 2 * kRedSlots;
+constexpr size_t kNoallocMaxNodes = size_t(1) << 30;
+template <typename T>
+hipError_t launch_cost_grad_noalloc(const Geometry& g, const uint8_t* mask, const T* uN,
+                                    const T* ut, const T* ctrl, const double* gacc, T* seed,
+                                    T* grad, double alpha, double* host_out, hipStream_t s);
+
 // Host helpers of the runtime (mrt_abi.cpp), shared with the batch runtime.
 }  // namespace mrt
 

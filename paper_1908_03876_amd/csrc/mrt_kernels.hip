@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "mrt_device.h"
 #include "mrt_internal.h"
@@ -275,16 +276,20 @@ __global__ __launch_bounds__(kBlock) void cadj_step_kernel(
   cadj_collide_store<T, MASKED, FIRST>(g, n, m, cc, fp, fq, rec, dst, gacc, lm);
 }
 
+// Fluid test on the tape's link word (bit 0 = solid) or, for the calls that
+// take no tape, on the caller's byte mask (non-zero = solid).  Null: all fluid.
 __device__ __forceinline__ bool is_fluid(const uint16_t* link, size_t idx) {
   return link == nullptr || !(link[idx] & 1u);
 }
+__device__ __forceinline__ bool is_fluid(const uint8_t* mask, size_t idx) {
+  return mask == nullptr || mask[idx] == 0;
+}
 
-template <typename T>
+template <typename T, typename M>
 __global__ __launch_bounds__(kBlock) void cost_grad_kernel(
-    Geometry g, const T* __restrict__ uN, const T* __restrict__ ut, const T* __restrict__ ctrl,
-    const double* __restrict__ gacc, T* __restrict__ seed, T* __restrict__ grad,
-    double alpha, double* __restrict__ partials) {
-  const uint16_t* link = g.link;
+    Geometry g, const M* __restrict__ link, const T* __restrict__ uN, const T* __restrict__ ut,
+    const T* __restrict__ ctrl, const double* __restrict__ gacc, T* __restrict__ seed,
+    T* __restrict__ grad, double alpha, double* __restrict__ partials) {
   double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const size_t total = size_t(g.nx) * g.ny;
   for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
@@ -409,9 +414,9 @@ __global__ __launch_bounds__(kBlock) void axpby_kernel(Geometry g, const T* __re
   }
 }
 
+template <typename M>
 __global__ __launch_bounds__(kBlock) void count_fluid_kernel(
-    Geometry g, double* __restrict__ partials) {
-  const uint16_t* link = g.link;
+    Geometry g, const M* __restrict__ link, double* __restrict__ partials) {
   double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const size_t total = size_t(g.nx) * g.ny;
   for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
@@ -553,11 +558,70 @@ void launch_cost_grad(const Geometry& g, const T* uN, const T* ut,
                       const T* ctrl, const double* gacc, T* seed, T* grad,
                       double alpha, double* partials, double* result,
                       hipStream_t s) {
-  hipLaunchKernelGGL((cost_grad_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0,
-                     s, g, uN, ut, ctrl, gacc, seed, grad, alpha,
+  hipLaunchKernelGGL((cost_grad_kernel<T, uint16_t>), dim3(kRedBlocks), dim3(kBlock), 0,
+                     s, g, g.link, uN, ut, ctrl, gacc, seed, grad, alpha,
                      partials);
   hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
                      partials, kRedBlocks, result);
+}
+
+// ---- cost and gradient reduction without a tape or any allocation
+//
+// The block partials and the two reduced rows live in this file-scope array,
+// one copy per device for the life of the process.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in symbol):
+// the device address is looked up once per device with hipGetSymbolAddress
+// and that pointer is what the kernels receive.  Every block overwrites its
+// partial row and the finishing kernel its result row, so nothing needs
+// clearing between calls; two calls that overlap on one device share the
+// array and race.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_cost_grad_noalloc(const Geometry& g, const uint8_t* mask, const T* uN,
+                                    const T* ut, const T* ctrl, const double* gacc, T* seed,
+                                    T* grad, double alpha, double* host_out, hipStream_t s) {
+  double* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  double* partials = base;
+  double* result = base + size_t(kRedBlocks) * kRedSlots;  // [2][kRedSlots]
+  hipLaunchKernelGGL((cost_grad_kernel<T, uint8_t>), dim3(kRedBlocks), dim3(kBlock), 0,
+                     s, g, mask, uN, ut, ctrl, gacc, seed, grad, alpha, partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
+                     partials, kRedBlocks, result);
+  hipLaunchKernelGGL((count_fluid_kernel<uint8_t>), dim3(kRedBlocks), dim3(kBlock), 0, s,
+                     g, mask, partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
+                     partials, kRedBlocks, result + kRedSlots);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(host_out, result, sizeof(double) * 2 * kRedSlots,
+                     hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
 }
 
 template <typename T>
@@ -634,8 +698,8 @@ void launch_axpby(const Geometry& g, const T* x, T* y, double a, double b, hipSt
 
 void launch_count_fluid(const Geometry& g, double* partials, double* result,
                         hipStream_t s) {
-  hipLaunchKernelGGL(count_fluid_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s,
-                     g, partials);
+  hipLaunchKernelGGL((count_fluid_kernel<uint16_t>), dim3(kRedBlocks), dim3(kBlock), 0, s,
+                     g, g.link, partials);
   hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s,
                      partials, kRedBlocks, result);
 }
@@ -659,6 +723,9 @@ void launch_count_fluid(const Geometry& g, double* partials, double* result,
   template void launch_cost_grad<T>(const Geometry&, const T*, const T*,    \
                                     const T*, const double*, T*, T*, double, \
                                     double*, double*, hipStream_t);          \
+  template hipError_t launch_cost_grad_noalloc<T>(                           \
+      const Geometry&, const uint8_t*, const T*, const T*, const T*,         \
+      const double*, T*, T*, double, double*, hipStream_t);                  \
   template void launch_gd_step<T>(const Geometry&, T*, const T*, double,     \
                                   double, double, double*, double*,          \
                                   hipStream_t);                              \
