@@ -49,6 +49,7 @@
 //   * Sensitivity LBE (LIBEG-V) as a forward-mode linearisation (TLM).
 //   * Gradient step (Section 2.4, Step 5 and the heuristic step
 //     zeta = min(1, 1/||E||_inf)).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -789,9 +790,86 @@ void run_forward(const OrcProblem& p, const Ops& ops, int nsteps,
   }
 }
 
+// Bytes of states a Trajectory keeps whole; longer runs are checkpointed.
+size_t g_traj_budget = size_t(16) << 30;
+
+// The states phi^n (before step n; phi^N after the last step) of one forward
+// solve, as the backward sweep needs them, newest first.  When all of them
+// fit in g_traj_budget bytes they are kept from the one forward run.
+// Otherwise phi^n (with the previous step's kinetics that source_term 2
+// carries) is kept every K = ceil(sqrt(N)) steps, and the K states of a
+// segment are computed again from its checkpoint when the sweep first asks
+// for one of them.  Each step is a deterministic function of its input, so a
+// recomputed state is the stored one bit for bit: this changes the memory,
+// not the arithmetic.
+class Trajectory {
+ public:
+  Trajectory(const OrcProblem& p, const Ops& ops, int nsteps, const double* u0,
+             const double* v0, const double* c)
+      : p_(p), ops_(ops), c_(c), N_(nsteps),
+        nc_(size_t(p.nx) * p.ny), NQ_(size_t(nspec(p)) * Q) {
+    const size_t sbytes = NQ_ * nc_ * sizeof(double);
+    K_ = (size_t(nsteps) + 1) * sbytes <= g_traj_budget
+             ? std::max(nsteps, 1)
+             : int(std::ceil(std::sqrt(double(nsteps))));
+    post_.assign(NQ_ * nc_, 0.0);
+    fnew_.assign(NQ_ * nc_, 0.0);
+    std::vector<double> f(NQ_ * nc_, 0.0), F(2 * nc_, 0.0);
+    init_equilibrium(p, ops, u0, v0, f.data());
+    const bool all = K_ >= nsteps;
+    if (all) {
+      seg_.assign(size_t(std::max(nsteps, 1)) * NQ_ * nc_, 0.0);
+      seg_start_ = 0;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+      if (all)
+        std::memcpy(seg_.data() + size_t(n) * NQ_ * nc_, f.data(), sbytes);
+      else if (n % K_ == 0) {
+        ckpt_f_.push_back(f);
+        ckpt_F_.push_back(F);
+      }
+      step(p, ops, f.data(), c, post_.data(), fnew_.data(), F.data(), n == 0);
+      std::swap(f, fnew_);
+    }
+    final_ = f;
+  }
+
+  // phi^n, 0 <= n <= N
+  const double* state(int n) {
+    if (n == N_) return final_.data();
+    if (seg_start_ < 0 || n < seg_start_ || n >= seg_start_ + K_) load(n / K_);
+    return seg_.data() + size_t(n - seg_start_) * NQ_ * nc_;
+  }
+
+ private:
+  void load(int s) {
+    const int start = s * K_, len = std::min(K_, N_ - start);
+    seg_.assign(size_t(len) * NQ_ * nc_, 0.0);
+    std::vector<double> f = ckpt_f_[s], F = ckpt_F_[s];
+    for (int j = 0; j < len; ++j) {
+      std::memcpy(seg_.data() + size_t(j) * NQ_ * nc_, f.data(), NQ_ * nc_ * sizeof(double));
+      step(p_, ops_, f.data(), c_, post_.data(), fnew_.data(), F.data(), start + j == 0);
+      std::swap(f, fnew_);
+    }
+    seg_start_ = start;
+  }
+
+  const OrcProblem& p_;
+  const Ops& ops_;
+  const double* c_;
+  int N_, K_ = 1, seg_start_ = -1;
+  size_t nc_, NQ_;
+  std::vector<double> seg_, final_, post_, fnew_;
+  std::vector<std::vector<double>> ckpt_f_, ckpt_F_;
+};
+
 }  // namespace
 
 extern "C" {
+
+// Largest number of bytes of forward states the adjoint keeps whole before
+// it checkpoints (test control; default 16 GiB).
+void orc_set_traj_budget(size_t bytes) { g_traj_budget = bytes; }
 
 // Tables for the lattice pins: E (9x2), weights, M0, M0^-1 (Gauss-Jordan).
 int orc_tables(double* E, double* w, double* M, double* Minv) {
@@ -915,8 +993,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   const size_t nc = size_t(p->nx) * p->ny;
   const int NS = nspec(*p);
   const size_t NQ = size_t(NS) * Q;
-  std::vector<double> f, traj;
-  run_forward(*p, ops, nsteps, u0, v0, c, f, &traj);
+  Trajectory traj(*p, ops, nsteps, u0, v0, c);
   std::vector<double> lam(NQ * nc, 0.0), nu(NQ * nc, 0.0);
   for (size_t cell = 0; cell < nc; ++cell) {
     if (p->solid && p->solid[cell]) continue;
@@ -938,7 +1015,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   const bool implicit = p->source_term == 3;
   for (int n = nsteps - 1; n >= 0; --n) {
     if (implicit) {
-      const double* fa = n + 1 < nsteps ? traj.data() + size_t(n + 1) * NQ * nc : f.data();
+      const double* fa = traj.state(n + 1);
 #pragma omp parallel for schedule(static)
       for (int cell = 0; cell < int(nc); ++cell) {
         if (p->solid && p->solid[cell]) continue;
@@ -967,7 +1044,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
                         : lam[(s * Q + ops.opp[i]) * nc + cell];
           }
       }
-    const double* fn = traj.data() + size_t(n) * NQ * nc;
+    const double* fn = traj.state(n);
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {

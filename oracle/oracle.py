@@ -258,6 +258,16 @@ def cost_complex_step(p, dc, h=1e-20, nsteps=None, control=None,
     return jr.value, ji.value / h
 
 
+def set_traj_budget(nbytes: int) -> None:
+    """Bytes of forward states the adjoint keeps whole before it switches to
+    checkpoints every ceil(sqrt(N)) steps with segment recomputation
+    (default 16 GiB)."""
+    f = lib().orc_set_traj_budget
+    f.argtypes = [ctypes.c_size_t]
+    f.restype = None
+    f(int(nbytes))
+
+
 def cost_gradient(p, nsteps=None, control=None, control_on_u=False):
     """Returns dict(J, J_track, J_reg, grad, uN) of the full discrete gradient."""
     n = p.nsteps if nsteps is None else nsteps

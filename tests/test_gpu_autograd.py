@@ -2,7 +2,6 @@
 checkpointed recomputation (differentiation form of the method: the discrete
 adjoint gives the exact gradient of a functional of the final state,
 Theorem 3)."""
-import os
 
 import numpy as np
 import pytest
@@ -233,17 +232,36 @@ def test_autograd_checkpointed_matches_oracle_2000_steps():
     out["solver"].close()
 
 
-@pytest.mark.skipif(os.environ.get("MRT_LONG_ORACLE") != "1",
-                    reason="FP64 oracle at 10000 steps on 128x128 takes ~2 min "
-                           "and ~24 GB of host memory; set MRT_LONG_ORACLE=1")
+def _mem_available_gb():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) / 2 ** 20
+    except OSError:
+        pass
+    return 0.0
+
+
+@pytest.mark.skipif(_mem_available_gb() < 4.0,
+                    reason="the checkpointed FP64 oracle at 10000 steps needs ~0.6 GB of "
+                           "host memory; less than 4 GB available")
 def test_autograd_long_horizon_matches_oracle():
     """The 128 x 128 copy at the full 10000-step horizon: FP32 device
-    gradient (checkpoints every 100) against the FP64 oracle gradient."""
+    gradient (checkpoints every 100) against the FP64 oracle gradient
+    (which recomputes its own trajectory from checkpoints every 100 steps:
+    about a minute on 16 cores)."""
     import torch
     p = _copy128(10000)
+    print("oracle gradient, 128x128, N = 10000", flush=True)
     ref = O.cost_gradient(p)
     out = _torch_grad(p, torch.float32, ckpt_every=100)
-    assert rel_l2(out["grad"], ref["grad"], p.fluid) <= 1e-4
+    e = rel_l2(out["grad"], ref["grad"], p.fluid)
+    eu = rel_l2(out["uN"], ref["uN"], p.fluid)
+    print(f"N = 10000: rel L2 uN {eu:.2e} grad {e:.2e}", flush=True)
+    assert eu <= 1e-5
+    assert e <= 1e-4
+    assert abs(out["loss"] - ref["J"]) <= 1e-5 * ref["J"]
     out["solver"].close()
 
 

@@ -83,6 +83,12 @@ MUTANTS = [
      "double hx = -(Kw[0] * EX[j] + Kw[1] * EY[j])", "double hx = -(Kv[0] * EX[j] + Kv[1] * EY[j])"),
     ("third species: decay dropped from the source Jacobian",
      "dR[(2 * Q + i) * N2 + (2 * Q + j)] += TAU * wi * (-p.b_w);", ""),
+    ("checkpointed trajectory: previous kinetics dropped at each segment start",
+     "c_, post_.data(), fnew_.data(), F.data(), start + j == 0);",
+     "c_, post_.data(), fnew_.data(), F.data(), j == 0);"),
+    ("checkpointed trajectory: previous kinetics not restored",
+     "std::vector<double> f = ckpt_f_[s], F = ckpt_F_[s];",
+     "std::vector<double> f = ckpt_f_[s], F(2 * nc_, 0.0);"),
     ("third species: w not streamed",
      "for (int s = 0; s < NS; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming",
      "for (int s = 0; s < 2; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming"),
