@@ -134,6 +134,14 @@ def bf16_ulp(a):
     return out
 
 
+def storage_noise(rng):
+    """A store function for forward/backward: adds to each value an
+    independent error uniform within half a bfloat16 spacing."""
+    def noisy(a):
+        return a + rng.uniform(-0.5, 0.5, a.shape) * bf16_ulp(a)
+    return noisy
+
+
 def _outputs(params, x, s_in, s_out, dy, target, border, store):
     y, acts = forward(params, x, s_in, s_out, store=store)
     out = {"y": y}
@@ -154,11 +162,7 @@ def storage_noise_budget(params, x, s_in, s_out, dy=None, target=None, border=0,
     loss) also dx and every dW_k, db_k, and the loss.  Returns
     (exact, sigma), two dicts of arrays / floats keyed alike."""
     exact = _outputs(params, x, s_in, s_out, dy, target, border, None)
-    rng = np.random.default_rng(seed)
-
-    def noisy(a):
-        return a + rng.uniform(-0.5, 0.5, a.shape) * bf16_ulp(a)
-
+    noisy = storage_noise(np.random.default_rng(seed))
     acc = {k: 0.0 for k in exact}
     for _ in range(samples):
         o = _outputs(params, x, s_in, s_out, dy, target, border, noisy)
