@@ -53,6 +53,39 @@ def test_batch_iteration_matches_oracle(prec, graph):
     b.close()
 
 
+def test_batch_large_instances_checkpointed_match_oracle():
+    """The benchmark's launch configuration on its largest instance sizes:
+    1024^2 and 768^2 (with 384^2 and 128^2) in one batch, checkpoints every
+    5 of N = 24 steps (a ragged last segment), autotuned tiles, two
+    graph-replayed iterations; every instance's cost, u^N, gradient and
+    updated control against the oracle's two gradient iterations (FP32)."""
+    import torch
+    sizes = (1024, 768, 384, 128)
+    ps = [I.with_control_bump(I.uneven_batch(seed=45 + k, n=1, nsteps=24, sizes=(L,))[0],
+                              seed=100 + k, amp=2.0) for k, L in enumerate(sizes)]
+    b = _batch(ps, torch.float32, ckpt_every=5)
+    print(f"batch {[p.nx for p in ps]} N=24 K=5 tiles {b.tune(steps=4)}", flush=True)
+    refs = [[], []]
+    ctrl = [p.control.copy() for p in ps]
+    for it in range(2):
+        b.iterate(use_graph=True)
+        sc = b.scalars()
+        grads, ctrls = _grads(b), _controls(b)
+        for k, p in enumerate(ps):
+            q = p.copy(control=ctrl[k])
+            ref = O.cost_gradient(q)
+            c_ref, z_ref = O.gd_step(ctrl[k], ref["grad"])
+            eg = rel_l2(grads[k], ref["grad"])
+            print(f"  iteration {it} L={p.nx}: rel L2 grad {eg:.2e}", flush=True)
+            assert abs(sc[k]["J"] - ref["J"]) <= 1e-5 * abs(ref["J"]), (it, k)
+            assert rel_l2(b.get(k, "uN").double().cpu().numpy(), ref["uN"]) <= 1e-5, (it, k)
+            assert eg <= 1e-4, (it, k)
+            assert abs(sc[k]["zeta"] - z_ref) <= 1e-4 * z_ref, (it, k)
+            assert rel_l2(ctrls[k], c_ref) <= 1e-4, (it, k)
+            ctrl[k] = ctrls[k]  # the next iteration starts from the device's control
+    b.close()
+
+
 def test_batch_graph_replays_equal_eager_iterations():
     """Graph replays, with eager device work and synchronisations between
     them, reproduce eager iterations bit for bit, iteration after iteration."""

@@ -246,53 +246,30 @@ def test_errors_are_reported():
 
 # ------------------------------------------------ full-size workload checks
 
-def _window(p, cx, cy, W, nsteps):
-    """Sub-problem of half-width W around (cx, cy) with solid outside: for
-    N steps it equals the full problem within radius W - 2N - 1 of the
-    centre (information moves one node per step, forward then back)."""
-    sl = (slice(cy - W, cy + W + 1), slice(cx - W, cx + W + 1))
-    n = 2 * W + 1
-    solid = np.zeros((n, n), np.uint8) if p.solid is None else p.solid[sl].copy()
-    return p.copy(nx=n, ny=n, nsteps=nsteps, periodic=False, solid=solid,
-                  u0=p.u0[sl].copy(), v0=p.v0[sl].copy(),
-                  control=p.control[sl].copy(), u_target=p.u_target[sl].copy())
-
-
-def test_full_size_sampled_windows():
+def test_full_size_whole_field_parity():
     """The 2048 x 2048 masked anisotropic workload in the benchmark's launch
-    configuration (FP32, link mask, store-all record), checked on windows
-    the oracle solves exactly: u^N and the adjoint gradient at the window
-    centres match to the FP32 tolerances."""
+    configuration (FP32, link mask, store-all record) at N = 16 against the
+    FP64 oracle over the whole lattice: u^N, v^N, the final distribution
+    state (solid slots included) and the gradient over every fluid node, to
+    the FP32 tolerances (1e-5 on fields, 1e-4 on the gradient)."""
     import torch
     N = 16
     p = I.with_control_bump(I.masked_anisotropic(L=2048, nsteps=N), amp=5.0, sigma=256.0)
+    print("oracle, 2048x2048 masked, N = 16", flush=True)
+    ref = O.cost_gradient(p)
+    fwd = O.forward(p, want_state=True)
+    print("device", flush=True)
     dev = device_gradient(p, torch.float32)
-    assert dev["n_fluid"] == p.n_fluid
-    rng = np.random.default_rng(7)
-    W, r = 2 * N + 8, 6
-    # centres: random, plus ones next to disks and to the outer wall
-    solid = p.solid
-    near = np.argwhere(solid[W + 1:-W - 1, W + 1:-W - 1] != 0)
-    centres = [tuple(rng.integers(W + 1, 2048 - W - 1, 2)) for _ in range(3)]
-    pick = near[rng.integers(0, len(near), 3)] + W + 1
-    centres += [(int(x), int(y)) for y, x in pick]
-    centres.append((W + 1, 1024))
-    for cx, cy in centres:
-        q = _window(p, cx, cy, W, N)
-        ref = O.cost_gradient(q)
-        core = (slice(W - r, W + r + 1), slice(W - r, W + r + 1))
-        full = (slice(cy - r, cy + r + 1), slice(cx - r, cx + r + 1))
-        fl = q.fluid[core]
-        if fl.sum() == 0:
-            continue
-        assert rel_l2(dev["uN"][full], ref["uN"][core], fl) <= 1e-5, (cx, cy)
-        # per-node form of the global criterion ||dg||_2 <= 1e-4 ||g||_2:
-        # the window's error RMS against the RMS of the whole gradient field
-        # (locally the gradient can be ~1e-4 of its global scale, where a
-        # local relative norm only measures FP32 rounding)
-        err = dev["grad"][full][fl] - ref["grad"][core][fl]
-        g_rms = dev["grad_l2"] / np.sqrt(dev["n_fluid"])
-        assert np.sqrt(np.mean(err * err)) <= 1e-4 * g_rms, (cx, cy)
+    f = p.fluid
+    assert dev["n_fluid"] == p.n_fluid == int(f.sum())
+    e = {"uN": rel_l2(dev["uN"], fwd["uN"], f), "vN": rel_l2(dev["vN"], fwd["vN"], f),
+         "state": rel_l2(dev["state"], fwd["state"]),
+         "grad": rel_l2(dev["grad"], ref["grad"], f)}
+    print("2048^2, N = 16, rel L2 " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    assert e["uN"] <= 1e-5 and e["vN"] <= 1e-5 and e["state"] <= 1e-5
+    assert e["grad"] <= 1e-4
+    assert abs(dev["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    assert np.all(dev["grad"][~f] == 0) and np.all(dev["uN"][~f] == 0)
 
 
 def test_full_size_long_horizon_properties():
