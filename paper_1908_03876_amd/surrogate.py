@@ -177,24 +177,43 @@ class Surrogate:
 
 # ------------------------------------------------------------ training data
 
-def render_bumps(n: int, L: int, rng: np.random.Generator, device,
-                 kmin=1, kmax=8, smin=4.0, smax=32.0, amax=5.0) -> torch.Tensor:
-    """n periodic controls, each a sum of K ~ U{kmin..kmax} Gaussian bumps
-    (uniform centres, sigma ~ U[smin, smax], amplitude ~ U[-amax, amax]).
-    The random draws are seeded numpy; the sums are evaluated on the device."""
-    out = torch.zeros((n, L, L), dtype=torch.float32, device=device)
-    ax = torch.arange(L, dtype=torch.float32, device=device)
+def draw_bumps(n: int, L: int, rng: np.random.Generator, kmin=1, kmax=8, smin=4.0,
+               smax=32.0, amax=5.0):
+    """Seeded parameters of n controls, each a sum of K ~ U{kmin..kmax}
+    Gaussian bumps (uniform centres, sigma ~ U[smin, smax], amplitude ~
+    U[-amax, amax]), as [n, kmax] arrays (unused slots have amplitude 0)."""
+    cx, cy = np.zeros((n, kmax)), np.zeros((n, kmax))
+    sig, amp = np.ones((n, kmax)), np.zeros((n, kmax))
     for i in range(n):
         k = int(rng.integers(kmin, kmax + 1))
-        cx, cy = rng.uniform(0, L, k), rng.uniform(0, L, k)
-        sig, amp = rng.uniform(smin, smax, k), rng.uniform(-amax, amax, k)
-        for j in range(k):
-            dx = (ax - float(cx[j])).abs()
-            dx = torch.minimum(dx, L - dx)
-            dy = (ax - float(cy[j])).abs()
-            dy = torch.minimum(dy, L - dy)
-            out[i] += float(amp[j]) * torch.exp(-(dy[:, None] ** 2 + dx[None, :] ** 2)
-                                                / (2.0 * float(sig[j]) ** 2))
+        cx[i, :k], cy[i, :k] = rng.uniform(0, L, k), rng.uniform(0, L, k)
+        sig[i, :k], amp[i, :k] = rng.uniform(smin, smax, k), rng.uniform(-amax, amax, k)
+    return cx, cy, sig, amp
+
+
+def render_bumps(n: int, L: int, rng: np.random.Generator, device,
+                 kmin=1, kmax=8, smin=4.0, smax=32.0, amax=5.0,
+                 chunk: int = 512) -> torch.Tensor:
+    """n periodic controls of draw_bumps on an L x L lattice, evaluated on the
+    device: a periodic Gaussian factors into a row and a column profile, so
+    a control is sum_k a_k g_k(y) h_k(x), one small batched product per chunk
+    of controls."""
+    cx, cy, sig, amp = draw_bumps(n, L, rng, kmin, kmax, smin, smax, amax)
+    out = torch.empty((n, L, L), dtype=torch.float32, device=device)
+    ax = torch.arange(L, dtype=torch.float32, device=device)
+
+    def profile(centre, s2):
+        d = (ax[None, None, :] - centre[:, :, None]).abs()
+        d = torch.minimum(d, L - d)
+        return torch.exp(-(d * d) / s2[:, :, None])
+
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        T = lambda a: torch.tensor(a[s:e], dtype=torch.float32, device=device)
+        s2 = 2.0 * T(sig) ** 2
+        gy = (profile(T(cy), s2) * T(amp)[:, :, None]).transpose(1, 2).contiguous()
+        gx = profile(T(cx), s2).contiguous()
+        torch.bmm(gy, gx, out=out[s:e])
     return out
 
 
@@ -209,7 +228,9 @@ def generate_pairs(n: int, L: int, nsteps: int, seed: int, per_launch: int = 96,
                    device="cuda:0", smax: float = 32.0) -> Dict[str, torch.Tensor]:
     """(control, u(T)) pairs from forward MRT solves of the batched engine
     (one persistent launch per group of `per_launch` controls), and the
-    uncontrolled u(T) = u_base.  The network learns u(T) - u_base."""
+    uncontrolled u(T) = u_base.  The network learns u(T) - u_base.  Also
+    returns the seconds spent rendering the controls, copying them in and
+    out of the batch, and in the MRT launches, with the latter's rate."""
     dev = torch.device(device)
     rng = np.random.default_rng(seed)
     base = physics(L, nsteps)
@@ -218,18 +239,33 @@ def generate_pairs(n: int, L: int, nsteps: int, seed: int, per_launch: int = 96,
     # u_base: the uncontrolled solution
     abi.mrt_batch_forward(b.handle)
     u_base = b.get(0, "uN").clone()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
     controls = render_bumps(n, L, rng, dev, smax=smax)
+    torch.cuda.synchronize(dev)
+    t_render = time.perf_counter() - t0
     responses = torch.empty_like(controls)
+    t_copy = t_solve = 0.0
     for s in range(0, n, m):
         cnt = min(m, n - s)
+        ta = time.perf_counter()
         for k in range(cnt):
             abi.mrt_batch_copy(b.handle, k, abi.MRT_FIELD_CONTROL, True, controls[s + k])
+        torch.cuda.synchronize(dev)
+        tb = time.perf_counter()
         abi.mrt_batch_forward(b.handle)
+        torch.cuda.synchronize(dev)
+        tc = time.perf_counter()
         for k in range(cnt):
             abi.mrt_batch_copy(b.handle, k, abi.MRT_FIELD_UN, False, responses[s + k])
-    torch.cuda.synchronize(dev)
+        torch.cuda.synchronize(dev)
+        t_copy += (tb - ta) + (time.perf_counter() - tc)
+        t_solve += tc - tb
     b.close()
-    return {"controls": controls, "responses": responses, "u_base": u_base}
+    launches = (n + m - 1) // m
+    return {"controls": controls, "responses": responses, "u_base": u_base,
+            "render_s": t_render, "copy_s": t_copy, "solve_s": t_solve,
+            "solve_glups": launches * m * L * L * nsteps / max(t_solve, 1e-9) / 1e9}
 
 
 # ------------------------------------------------------- optimisation loops
@@ -246,7 +282,13 @@ class ControlProblem:
         self.trial = self.dp.empty_field()
         self.n_forward = 0
         self.n_adjoint = 0
+        self.n_tlm = 0
         assert self.dp.pitch == self.dp.nx, "square lattices with nx a multiple of 64"
+
+    @property
+    def solves(self) -> int:
+        """MRT sweeps so far (forward, adjoint and tangent-linear)."""
+        return self.n_forward + self.n_adjoint + self.n_tlm
 
     def cost(self, c: torch.Tensor) -> float:
         dp = self.dp
@@ -272,15 +314,43 @@ class ControlProblem:
         self.n_adjoint += 1
         return r["J"], self.it.grad.clone(), r["grad_inf"], r["grad_l2"]
 
+    def recorded_cost(self, c: torch.Tensor) -> float:
+        """J(c) from one MRT forward that also records the adjoint tape, so
+        that adjoint_gradient(c) can follow without another forward."""
+        self.it.forward(c)
+        self.n_forward += 1
+        return self.it.cost(c)["J"]
+
+    def adjoint_gradient(self, c: torch.Tensor):
+        """E, ||E||_inf, ||E||_2 at c from the AMRT of the last
+        recorded_cost(c) (the same tensor c)."""
+        dp, t = self.dp, self.it.tape.handle
+        abi.amrt_adjoint(dp.struct, t, dp.u0, dp.v0, c, self.it.seed, None, self.it.gacc,
+                         None, None)
+        r = abi.cost_gradient(dp.struct, t, self.it.uN, dp.u_target, c, self.it.gacc, None,
+                              self.it.grad)
+        self.n_adjoint += 1
+        return self.it.grad.clone(), r["grad_inf"], r["grad_l2"]
+
+    def lma_step(self, c: torch.Tensor) -> float:
+        """LMA step size (Section 2.4) at c after gradient(c): one
+        tangent-linear solve."""
+        self.n_tlm += 1
+        return self.it.lma_zeta(control=c)
+
     def close(self):
         self.it.close()
         self.ftape.close()
 
 
-def line_search(cp: ControlProblem, c, E, J0, lam0, max_expand=20, golden=6):
+def line_search(cp: ControlProblem, c, E, J0, lam0, max_bracket=8, golden=4):
     """Line minimisation of J(c - lam E) (Remark after Step 6: zeta_k =
-    argmin J(f - lam E)): bracket by doubling from lam0, then a golden-
-    section refinement with `golden` more MRT forwards.  Returns (lam, J)."""
+    argmin J(f - lam E)), with true MRT forwards: from the first trial lam0
+    (the previous iteration's step, or the heuristic one at the start),
+    shrink or expand by factors of 4 until J(lam) is bracketed, then
+    `golden` golden-section forwards in the bracket.  In the usual case (the
+    previous step still decreases J and four times it does not) that is six
+    forwards.  Returns (lam, J)."""
     f = {0.0: J0}
 
     def J(lam):
@@ -290,90 +360,158 @@ def line_search(cp: ControlProblem, c, E, J0, lam0, max_expand=20, golden=6):
 
     a, b = 0.0, lam0
     if J(b) >= J0:
-        for _ in range(8):  # shrink until a decrease
+        for _ in range(max_bracket):  # shrink until a decrease
             b *= 0.25
             if J(b) < J0:
                 break
         else:
             return 0.0, J0
-    cc = 2.0 * b
-    for _ in range(max_expand):
-        if J(cc) >= J(b):
-            break
-        a, b, cc = b, cc, 2.0 * cc
+        cc = 4.0 * b
+    else:
+        cc = 4.0 * b
+        for _ in range(max_bracket):
+            if J(cc) >= J(b):
+                break
+            a, b, cc = b, cc, 4.0 * cc
     gr = (math.sqrt(5.0) - 1.0) / 2.0
     lo, hi = a, cc
     x1, x2 = hi - gr * (hi - lo), lo + gr * (hi - lo)
-    for _ in range(golden // 2):
-        if J(x1) < J(x2):
-            hi, x2 = x2, x1
+    f1, f2 = J(x1), J(x2)
+    for _ in range(max(golden - 2, 0)):
+        if f1 < f2:
+            hi, x2, f2 = x2, x1, f1
             x1 = hi - gr * (hi - lo)
+            f1 = J(x1)
         else:
-            lo, x1 = x1, x2
+            lo, x1, f1 = x1, x2, f2
             x2 = lo + gr * (hi - lo)
+            f2 = J(x2)
     lam = min(f, key=f.get)
     return lam, f[lam]
 
 
+def _clock(t0: float) -> float:
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _result(cp: ControlProblem, hist, c, t0, **extra) -> dict:
+    out = {"J": hist[-1][1], "hist": [h[1] for h in hist], "times": [h[0] for h in hist],
+           "control": c, "time": _clock(t0), "forwards": cp.n_forward,
+           "adjoints": cp.n_adjoint, "tlms": cp.n_tlm, "solves": cp.solves}
+    out.update(extra)
+    return out
+
+
 def optimize_plain(cp: ControlProblem, iters: int, c0=None) -> dict:
-    """Gradient iterations with the exact line search."""
+    """Gradient iterations with the golden-section line search, its first
+    trial the previous iteration's step.  hist/times: J at each iterate and
+    the wall time at which it was known."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = (cp.dp.field(None) if c0 is None else c0.clone())
+    hist, lam = [], None
+    J = None
+    for _ in range(iters):
+        J, E, einf, _ = cp.gradient(c)
+        if not hist:
+            hist.append((_clock(t0), J))
+        lam0 = min(1.0, 1.0 / max(einf, 1e-300)) if not lam else lam
+        lam, J = line_search(cp, c, E, J, lam0)
+        cp.step(c, E, lam)
+        hist.append((_clock(t0), J))
+    return _result(cp, hist, c, t0)
+
+
+def optimize_lma(cp: ControlProblem, iters: int, c0=None) -> dict:
+    """Gradient iterations with the LMA step (one gradient and one
+    tangent-linear solve per iteration, no line search)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     c = (cp.dp.field(None) if c0 is None else c0.clone())
     hist = []
-    J = None
     for _ in range(iters):
-        J, E, einf, _ = cp.gradient(c)
-        hist.append(J)
-        lam, Jn = line_search(cp, c, E, J, min(1.0, 1.0 / max(einf, 1e-300)))
-        cp.step(c, E, lam)
-        J = Jn
-    hist.append(J)
+        J, E, _, _ = cp.gradient(c)
+        hist.append((_clock(t0), J))
+        z = cp.lma_step(c)
+        cp.step(c, E, z)
+    hist.append((_clock(t0), cp.cost(c)))
+    return _result(cp, hist, c, t0)
+
+
+def optimize_cg(cp: ControlProblem, iters: int, rule: str = "PR") -> dict:
+    """Nonlinear conjugate gradients (Section 2.4, Remark after Step 6) with
+    the Wolfe line search whose first trial is the LMA step along D, from
+    the problem's control."""
+    from .optim import ConjugateGradient
     torch.cuda.synchronize()
-    return {"J": J, "hist": hist, "control": c, "time": time.perf_counter() - t0,
-            "forwards": cp.n_forward, "adjoints": cp.n_adjoint}
+    t0 = time.perf_counter()
+    cg = ConjugateGradient(cp.dp, rule=rule, ckpt_every=-1)
+    hist = [(_clock(t0), cg.start())]
+    for _ in range(iters):
+        hist.append((_clock(t0), cg.iterate()["J"]))
+    cp.n_forward += cg.evals
+    cp.n_adjoint += cg.evals
+    cp.n_tlm += cg.tlms
+    c = cg.control.clone()
+    out = _result(cp, hist, c, t0)
+    cg.close()
+    return out
 
 
 def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: float,
                       max_iters: int = 50, n_cand: int = 16, warm_iters: int = 300) -> dict:
     """Surrogate-assisted gradient loop: warm start from the surrogate, then
-    per iteration one MRT+AMRT gradient, surrogate-scored step candidates in
-    one batched inference, and one MRT forward that verifies the chosen step
-    (Armijo, c1 = 1e-4); a rejected proposal falls back to the exact line
-    search.  Stops once J <= target_J."""
+    per iteration one AMRT gradient, surrogate-scored step candidates in one
+    batched inference (a factor-2 grid, then a finer one around its best),
+    and one MRT forward that verifies the chosen step (Armijo, c1 = 1e-4)
+    and records the tape for the next gradient; a rejected proposal falls
+    back to the exact line search.  Stops once J <= target_J."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nx = cp.dp.nx
     ut = cp.dp.u_target[:, :nx]
     alpha = cp.prob.alpha
     c = srg.warm_start(u_base, ut, alpha, iters=warm_iters)
-    J = cp.cost(c)
-    hist = [J]
+    buf = torch.empty_like(c)
+    J = cp.recorded_cost(c)
+    hist = [(_clock(t0), J)]
     accepted = fallbacks = 0
+    lam_prev = None
     for _ in range(max_iters):
         if J <= target_J:
             break
-        J, E, einf, e2 = cp.gradient(c)
-        lam0 = min(1.0, 1.0 / max(einf, 1e-300))
-        lams = [lam0 * 2.0 ** k for k in range(-2, n_cand - 2)]
-        # surrogate costs of the candidates and of c itself (lambda = 0):
-        # the predicted change is added to the true J
+        E, einf, e2 = cp.adjoint_gradient(c)
+        lam0 = lam_prev if lam_prev else min(1.0, 1.0 / max(einf, 1e-300))
+        lams = [lam0 * 2.0 ** (k - n_cand // 2) for k in range(n_cand)]
         pj = srg.score_steps(c, E, lams + [0.0], u_base, ut, alpha)
-        pred = [pj[k] - pj[-1] + J for k in range(n_cand)]
-        lam = lams[int(np.argmin(pred))]
-        Jn = cp.trial_cost(c, E, lam)
+        best = lams[int(np.argmin(pj[:n_cand]))]
+        fine = [best * 2.0 ** (k / 4.0) for k in range(-3, 4)]
+        pf = srg.score_steps(c, E, fine, u_base, ut, alpha)
+        lam = fine[int(np.argmin(pf))]
+        buf.copy_(c)
+        cp.step(buf, E, lam)
+        Jn = cp.recorded_cost(buf)
         if Jn <= J - 1e-4 * lam * e2 * e2:
             accepted += 1
+            c, buf = buf, c
         else:
             fallbacks += 1
             lam, Jn = line_search(cp, c, E, J, lam0)
-        cp.step(c, E, lam)
+            cp.step(c, E, lam)
+            Jn = cp.recorded_cost(c)
+        lam_prev = lam
         J = Jn
-        hist.append(J)
-    torch.cuda.synchronize()
-    return {"J": J, "hist": hist, "control": c, "time": time.perf_counter() - t0,
-            "forwards": cp.n_forward, "adjoints": cp.n_adjoint,
-            "accepted": accepted, "fallbacks": fallbacks}
+        hist.append((_clock(t0), J))
+    return _result(cp, hist, c, t0, accepted=accepted, fallbacks=fallbacks)
+
+
+def time_to_reach(res: dict, target: float):
+    """Wall time at which a loop first knew a J <= target (None if never)."""
+    for t, J in zip(res["times"], res["hist"]):
+        if J <= target:
+            return t
+    return None
 
 
 def hidden_target_problem(L: int, nsteps: int, seed: int, device="cuda:0",
