@@ -276,6 +276,44 @@ int mrt_dot(const mrt_problem* p, mrt_tape* t, const void* x, const void* y,
 int mrt_axpby(const mrt_problem* p, mrt_tape* t, const void* x, void* y,
               double a, double b, void* stream);
 
+/* Linearised line minimisation (LMA, Section 2.4): the minimiser of the
+ * quadratic model of the cost along a direction d,
+ *   J(c - zeta d) ~ 1/2 |r - zeta P|^2 + alpha/2 |c - zeta d|^2,
+ * i.e. zeta = (<r, P> + alpha <c, d>) / (<P, P> + alpha <d, d>), with
+ * r = u^N - u_target (the seed of cost_gradient), P = F'(c) d the
+ * tangent-linear response of u^N (mrt_tlm) and inner products over the fluid
+ * nodes, accumulated in double in a fixed order.  For the gradient step,
+ * d = grad and c <- c - zeta grad; along a search direction D stepped as
+ * c + s D, s = -zeta.  zeta = 0 if the denominator is not positive.
+ * Synchronises `stream`; MRT_ENONFINITE if a product is not finite. */
+int mrt_lma_step(const mrt_problem* p, mrt_tape* t, const void* control,
+                 const void* dir, const void* resid, const void* P,
+                 double* zeta /* host */, void* stream);
+
+/* Nonlinear conjugate-gradient direction (Section 2.4, Remark after Step 6,
+ * item 2): D <- -G + beta D with beta by the Fletcher-Reeves, Polak-Ribiere
+ * (clipped at 0), Hestenes-Stiefel (clipped at 0) or Dai-Yuan rule, from
+ * the new gradient G, the previous gradient Gprev and direction D (in/out),
+ * gg_old = <Gprev, Gprev> and dg_old = <D, Gprev> of the previous iteration.
+ * A restart (D = -G) is taken at the first iteration, when
+ * |<G, Gprev>| >= 0.2 <G, G> (Powell), or when the new D is not a descent
+ * direction.  Returns <G, G>, beta, the restart flag and dg = <D, G> of the
+ * new direction (the gg_old and dg_old of the next call).  Synchronises
+ * `stream`. */
+enum { MRT_CG_FR = 0, MRT_CG_PR = 1, MRT_CG_HS = 2, MRT_CG_DY = 3 };
+typedef struct mrt_cg_info {
+  double gg;       /* <G, G> */
+  double beta;     /* the rule's value (0 at the first iteration); not
+                      applied when restart is set */
+  double dg;       /* <D, G> of the returned direction (< 0) */
+  int32_t restart; /* 1 if D = -G was taken */
+  int32_t reserved;
+} mrt_cg_info;
+int mrt_cg_direction(const mrt_problem* p, mrt_tape* t, int32_t rule,
+                     int32_t first, const void* G, const void* Gprev, void* D,
+                     double gg_old, double dg_old, mrt_cg_info* out /* host */,
+                     void* stream);
+
 /* Thread-local text of the last error. */
 const char* mrt_last_error(void);
 
@@ -470,6 +508,18 @@ int mrt_srg_score_steps(mrt_srg* s, const float* c, const float* E,
 int mrt_srg_warm_start(mrt_srg* s, const float* u_base, const float* u_target,
                        double alpha, int32_t H, int32_t W, int32_t iters, float lr,
                        float* c, void* stream);
+
+/* Warm start of the control by steepest descent on the surrogate cost with
+ * Barzilai-Borwein steps: c <- c - eta_k g_k with g_k the input gradient of
+ * the cost above at c, eta_0 = step0 / RMS(g_0) (a first move of RMS size
+ * step0) and eta_k = <s, s>/<s, y> for s = c_k - c_{k-1}, y = g_k - g_{k-1}
+ * when that is positive (else the previous step), for `iters` iterations;
+ * c ends as the iterate of least surrogate cost.  One step length for the
+ * whole field, computed on the device.  Asynchronous; c is updated in
+ * place; H * W <= max_h * max_w. */
+int mrt_srg_warm_start_bb(mrt_srg* s, const float* u_base, const float* u_target,
+                          double alpha, int32_t H, int32_t W, int32_t iters,
+                          float step0, float* c, void* stream);
 
 #ifdef __cplusplus
 }

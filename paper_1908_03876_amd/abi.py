@@ -57,6 +57,14 @@ class mrt_scalars(ctypes.Structure):
                 ("grad_l2", ctypes.c_double), ("n_fluid", ctypes.c_int64)]
 
 
+class mrt_cg_info(ctypes.Structure):
+    _fields_ = [("gg", ctypes.c_double), ("beta", ctypes.c_double), ("dg", ctypes.c_double),
+                ("restart", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+MRT_CG_RULES = {"FR": 0, "PR": 1, "HS": 2, "DY": 3}
+
+
 class mrt_tape_info(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("n_segments", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -96,7 +104,7 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "cost_gradient", "cost_gradient_noalloc", "gd_step", "mrt_last_error",
            "mrt_timing_enable",
            "mrt_timing_reset", "mrt_timing_read", "mrt_tlm", "mrt_dot", "mrt_axpby",
-           "mrt_cadjoint",
+           "mrt_cadjoint", "mrt_lma_step", "mrt_cg_direction",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
            "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
            "mrt_batch_tune", "mrt_batch_set_timeout", "mrt_batch_iteration",
@@ -105,7 +113,7 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_srg_sync",
            "mrt_srg_forward", "mrt_srg_backward", "mrt_srg_loss",
            "mrt_srg_train_step", "mrt_srg_gather", "mrt_srg_objective",
-           "mrt_srg_score_steps", "mrt_srg_warm_start",
+           "mrt_srg_score_steps", "mrt_srg_warm_start", "mrt_srg_warm_start_bb",
            "mrt3_validate", "mrt3_tape_bytes", "mrt3_tape_create", "mrt3_tape_destroy",
            "mrt3_tape_query", "mrt3_forward", "amrt3_adjoint", "mrt3_tlm",
            "mrt3_cost_gradient", "mrt3_gd_step"]
@@ -138,6 +146,10 @@ def _load():
     L.mrt_dot.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.mrt_cadjoint.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
     L.mrt_axpby.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
+    L.mrt_lma_step.argtypes = [P, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mrt_cg_direction.argtypes = [P, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                   ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(mrt_cg_info), vp]
     L.mrt_last_error.restype = ctypes.c_char_p
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
     L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -176,6 +188,7 @@ def _load():
     L.mrt_srg_score_steps.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), i32, vp, vp, dbl,
                                       i32, i32, ctypes.POINTER(dbl), vp]
     L.mrt_srg_warm_start.argtypes = [vp, vp, vp, dbl, i32, i32, i32, f32, vp, vp]
+    L.mrt_srg_warm_start_bb.argtypes = [vp, vp, vp, dbl, i32, i32, i32, f32, vp, vp]
     P3 = ctypes.POINTER(mrt3_problem)
     L.mrt3_validate.argtypes = [P3]
     L.mrt3_tape_bytes.argtypes = [P3, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -305,6 +318,22 @@ def mrt_dot(p, tape, x, y, stream=None) -> float:
     _check(lib.mrt_dot(ctypes.byref(p), tape, _ptr(x), _ptr(y), ctypes.byref(v),
                        _stream(stream)))
     return v.value
+
+
+def mrt_lma_step(p, tape, control, direction, resid, P, stream=None) -> float:
+    z = ctypes.c_double()
+    _check(lib.mrt_lma_step(ctypes.byref(p), tape, _ptr(control), _ptr(direction), _ptr(resid),
+                            _ptr(P), ctypes.byref(z), _stream(stream)))
+    return z.value
+
+
+def mrt_cg_direction(p, tape, rule: str, first: bool, G, Gprev, D, gg_old: float,
+                     dg_old: float, stream=None) -> dict:
+    r = mrt_cg_info()
+    _check(lib.mrt_cg_direction(ctypes.byref(p), tape, MRT_CG_RULES[rule], 1 if first else 0,
+                                _ptr(G), _ptr(Gprev), _ptr(D), float(gg_old), float(dg_old),
+                                ctypes.byref(r), _stream(stream)))
+    return {"gg": r.gg, "beta": r.beta, "dg": r.dg, "restart": bool(r.restart)}
 
 
 def mrt_axpby(p, tape, x, y, a: float, b: float, stream=None) -> None:
@@ -477,6 +506,13 @@ def mrt_srg_score_steps(s, c, E, lambdas, u_base, u_target, alpha, H, W, stream=
 def mrt_srg_warm_start(s, u_base, u_target, alpha, H, W, iters, lr, c, stream=None) -> None:
     _check(lib.mrt_srg_warm_start(s, _ptr(u_base), _ptr(u_target), float(alpha), int(H),
                                   int(W), int(iters), float(lr), _ptr(c), _stream(stream)))
+
+
+def mrt_srg_warm_start_bb(s, u_base, u_target, alpha, H, W, iters, step0, c,
+                          stream=None) -> None:
+    _check(lib.mrt_srg_warm_start_bb(s, _ptr(u_base), _ptr(u_target), float(alpha), int(H),
+                                     int(W), int(iters), float(step0), _ptr(c),
+                                     _stream(stream)))
 
 
 # ----------------------------------------------------------- D3Q19 (mrt3.h)

@@ -751,6 +751,56 @@ int cost_impl(mrt_tape* t, double alpha, const void* uN, const void* ut,
   return MRT_OK;
 }
 
+// Inner products <a_k, b_k> (k < n <= 4) over the fluid nodes, in one pass;
+// out[k] for k < n.  Synchronises the stream.
+int dots(const mrt_problem* p, mrt_tape* t, int n, const void* const* a, const void* const* b,
+         double* out, hipStream_t s) {
+  const mrt::Geometry g = geometry(t);
+  if (p->grid.dtype == MRT_F64) {
+    mrt::DotPairs<double> d{};
+    for (int k = 0; k < n; ++k) {
+      d.a[k] = static_cast<const double*>(a[k]);
+      d.b[k] = static_cast<const double*>(b[k]);
+    }
+    d.n = n;
+    mrt::launch_dots<double>(g, d, t->partials, t->result, s);
+  } else {
+    mrt::DotPairs<float> d{};
+    for (int k = 0; k < n; ++k) {
+      d.a[k] = static_cast<const float*>(a[k]);
+      d.b[k] = static_cast<const float*>(b[k]);
+    }
+    d.n = n;
+    mrt::launch_dots<float>(g, d, t->partials, t->result, s);
+  }
+  int rc = last_launch_error();
+  if (rc) return rc;
+  rc = read_result(t, s, mrt::kRedSlots);
+  if (rc) return rc;
+  if (t->host[3] != 0.0) return fail(MRT_ENONFINITE, "non-finite inner product");
+  static const int slot[4] = {0, 1, 2, 4};
+  for (int k = 0; k < n; ++k) out[k] = t->host[slot[k]];
+  return MRT_OK;
+}
+
+void axpby_any(const mrt_problem* p, mrt_tape* t, const void* x, void* y, double a, double b,
+               hipStream_t s) {
+  const mrt::Geometry g = geometry(t);
+  if (p->grid.dtype == MRT_F64)
+    mrt::launch_axpby<double>(g, static_cast<const double*>(x), static_cast<double*>(y), a, b,
+                              s);
+  else
+    mrt::launch_axpby<float>(g, static_cast<const float*>(x), static_cast<float*>(y), a, b, s);
+}
+
+// Products of the scalar formulas below are rounded before they are added
+// (no fused multiply-add), as written.
+double sum_of_products(double a, double x, double b, double y) {
+#pragma clang fp contract(off)
+  const double ax = a * x, by = b * y;
+  return ax + by;
+}
+
 void free_tape(mrt_tape* t) {
   if (!t) return;
   for (void* a : t->allocs) (void)hipFree(a);
@@ -1093,6 +1143,83 @@ int mrt_axpby(const mrt_problem* p, mrt_tape* t, const void* x, void* y, double 
                               s);
   else
     mrt::launch_axpby<float>(g, static_cast<const float*>(x), static_cast<float*>(y), a, b, s);
+  return last_launch_error();
+}
+
+int mrt_lma_step(const mrt_problem* p, mrt_tape* t, const void* control, const void* dir,
+                 const void* resid, const void* P, double* zeta, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!control || !dir || !resid || !P || !zeta)
+    return fail(MRT_EINVAL, "control, dir, resid, P and zeta required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* a[4] = {resid, control, P, dir};
+  const void* b[4] = {P, dir, P, dir};
+  double d[4];
+  rc = dots(p, t, 4, a, b, d, s);
+  if (rc) return rc;
+  const double num = sum_of_products(1.0, d[0], p->alpha, d[1]);
+  const double den = sum_of_products(1.0, d[2], p->alpha, d[3]);
+  *zeta = den > 0.0 ? num / den : 0.0;
+  if (!std::isfinite(*zeta)) return fail(MRT_ENONFINITE, "non-finite LMA step");
+  return MRT_OK;
+}
+
+int mrt_cg_direction(const mrt_problem* p, mrt_tape* t, int32_t rule, int32_t first,
+                     const void* G, const void* Gprev, void* D, double gg_old, double dg_old,
+                     mrt_cg_info* out, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = check_tape(p, t);
+  if (rc) return rc;
+  if (!G || !D || !out || (!first && !Gprev))
+    return fail(MRT_EINVAL, "G, D, out (and Gprev after the first iteration) required");
+  if (rule < MRT_CG_FR || rule > MRT_CG_DY) return fail(MRT_EINVAL, "unknown CG rule %d", rule);
+  if (!first && (!(gg_old > 0.0) || !std::isfinite(dg_old)))
+    return fail(MRT_EINVAL, "previous <G, G> must be positive and <D, G> finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mrt_cg_info r{};
+  if (first) {
+    const void* a[1] = {G};
+    rc = dots(p, t, 1, a, a, &r.gg, s);
+    if (rc) return rc;
+    axpby_any(p, t, G, D, -1.0, 0.0, s);
+    r.restart = 1;
+  } else {
+    const void* a[3] = {G, G, D};
+    const void* b[3] = {G, Gprev, G};
+    double d[3];
+    rc = dots(p, t, 3, a, b, d, s);
+    if (rc) return rc;
+    r.gg = d[0];
+    const double g_go = d[1], d_g = d[2];
+    const double y_g = r.gg - g_go;  // <G_k, G_k - G_{k-1}>
+    const double d_y = d_g - dg_old; // <D_{k-1}, G_k - G_{k-1}>
+    double beta = 0.0;
+    switch (rule) {
+      case MRT_CG_FR: beta = r.gg / gg_old; break;
+      case MRT_CG_PR: beta = std::max(0.0, y_g / gg_old); break;
+      case MRT_CG_HS: beta = d_y != 0.0 ? std::max(0.0, y_g / d_y) : 0.0; break;
+      default: beta = d_y != 0.0 ? r.gg / d_y : 0.0; break;
+    }
+    r.beta = beta;
+    // Powell: restart when consecutive gradients are far from orthogonal
+    r.restart = std::fabs(g_go) >= 0.2 * r.gg ? 1 : 0;
+    axpby_any(p, t, G, D, -1.0, r.restart ? 0.0 : beta, s);
+  }
+  const void* a[1] = {D};
+  const void* b[1] = {G};
+  rc = dots(p, t, 1, a, b, &r.dg, s);
+  if (rc) return rc;
+  if (!r.restart && r.dg >= 0.0) {  // not a descent direction: steepest descent
+    axpby_any(p, t, G, D, -1.0, 0.0, s);
+    r.restart = 1;
+    rc = dots(p, t, 1, a, b, &r.dg, s);
+    if (rc) return rc;
+  }
+  *out = r;
   return last_launch_error();
 }
 

@@ -159,6 +159,17 @@ void launch_tlm_step(const Geometry& g, const ModelCoef<T>& m, const TlmLaunch<T
 template <typename T>
 void launch_dot(const Geometry& g, const T* x, const T* y, double* partials, double* result,
                 hipStream_t s);
+// Up to four inner products <a_k, b_k> over the fluid nodes in one pass:
+// result slots 0, 1, 2, 4 (k = 0..3), slot 3 > 0 if a product is not finite.
+template <typename T>
+struct DotPairs {
+  const T* a[4];
+  const T* b[4];
+  int n;
+};
+template <typename T>
+void launch_dots(const Geometry& g, const DotPairs<T>& d, double* partials, double* result,
+                 hipStream_t s);
 // y <- a x + b y on fluid nodes, 0 on solid nodes.
 template <typename T>
 void launch_axpby(const Geometry& g, const T* x, T* y, double a, double b, hipStream_t s);

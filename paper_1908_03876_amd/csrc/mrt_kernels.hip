@@ -399,6 +399,34 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(Geometry g, const T* __rest
   block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
 }
 
+// Up to four inner products over the fluid nodes in one pass, each summed
+// in the order of dot_kernel (so each equals that kernel's result bit for
+// bit): products k = 0, 1, 2, 3 go to slots 0, 1, 2, 4; slot 3 (a maximum)
+// flags a non-finite product.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dots_kernel(Geometry g, DotPairs<T> d,
+                                                      double* __restrict__ partials) {
+  const uint16_t* link = g.link;
+  double acc[kRedSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(g.nx) * g.ny;
+  for (size_t k = size_t(blockIdx.x) * kBlock + threadIdx.x; k < total;
+       k += size_t(gridDim.x) * kBlock) {
+    const size_t yy = k / g.nx, xx = k % g.nx;
+    const size_t idx = yy * g.pitch + xx;
+    if (is_fluid(link, idx)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < d.n) {
+          const double v = double(d.a[j][idx]) * double(d.b[j][idx]);
+          acc[j < 3 ? j : 4] += v;
+          if (!isfinite(v)) acc[3] = 1.0;
+        }
+      }
+    }
+  }
+  block_reduce_store(acc, partials + size_t(blockIdx.x) * kRedSlots);
+}
+
 // y <- a x + b y on the fluid nodes, 0 on the solid ones.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void axpby_kernel(Geometry g, const T* __restrict__ x,
@@ -692,6 +720,14 @@ void launch_dot(const Geometry& g, const T* x, const T* y, double* partials, dou
 }
 
 template <typename T>
+void launch_dots(const Geometry& g, const DotPairs<T>& d, double* partials, double* result,
+                 hipStream_t s) {
+  hipLaunchKernelGGL((dots_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0, s, g, d, partials);
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(kBlock), 0, s, partials, kRedBlocks,
+                     result);
+}
+
+template <typename T>
 void launch_axpby(const Geometry& g, const T* x, T* y, double a, double b, hipStream_t s) {
   hipLaunchKernelGGL((axpby_kernel<T>), dim3(kRedBlocks), dim3(kBlock), 0, s, g, x, y, a, b);
 }
@@ -705,6 +741,8 @@ void launch_count_fluid(const Geometry& g, double* partials, double* result,
 }
 
 #define MRT_INSTANTIATE(T)                                                   \
+  template void launch_dots<T>(const Geometry&, const DotPairs<T>&, double*, double*,  \
+                               hipStream_t);                                          \
   template void launch_forward_step<T>(const Geometry&, const ModelCoef<T>&, \
                                        const FwdLaunch<T>&, hipStream_t);    \
   template void launch_finalize<T>(const Geometry&, const T*, T*, T*, T*,    \

@@ -58,6 +58,8 @@ struct mrt_srg {
   double* partials = nullptr;
   double* loss_dev = nullptr;
   double* obj_dev = nullptr;  // per-field objectives [kSrgMaxSteps]
+  double* bbpart = nullptr;   // warm start: Barzilai-Borwein partials and state
+  double* bbst = nullptr;
   double* host = nullptr;     // pinned [kSrgMaxSteps + 8]
   int64_t step = 0;
   std::vector<void*> allocs;
@@ -222,6 +224,8 @@ int mrt_srg_create(int32_t channels, int32_t max_batch, int32_t max_h, int32_t m
                       (void**)&s->partials);
   if (!rc) rc = alloc(64, (void**)&s->loss_dev);
   if (!rc) rc = alloc(mrt::kSrgMaxSteps * 8, (void**)&s->obj_dev);
+  if (!rc) rc = alloc(size_t(mrt::kSrgBBBlocks) * 3 * 8, (void**)&s->bbpart);
+  if (!rc) rc = alloc(8 * 8, (void**)&s->bbst);
   if (!rc && hipHostMalloc((void**)&s->host, (mrt::kSrgMaxSteps + 8) * 8) != hipSuccess)
     rc = err(MRT_ENOMEM, "pinned");
   if (rc) {
@@ -414,6 +418,33 @@ int mrt_srg_warm_start(mrt_srg* s, const float* u_base, const float* u_target, d
     objective(s, c, u_base, u_target, float(alpha), 1, H, W, s->wg, st);
     const float c1 = 1.f - std::pow(b1, float(k)), c2 = 1.f - std::pow(b2, float(k));
     mrt::launch_adam(c, nullptr, s->wg, s->wm, s->wv, int(hw), lr, b1, b2, eps, c1, c2, st);
+  }
+  return launch_err();
+}
+
+int mrt_srg_warm_start_bb(mrt_srg* s, const float* u_base, const float* u_target,
+                          double alpha, int32_t H, int32_t W, int32_t iters, float step0,
+                          float* c, void* stream) {
+  if (!s || !u_base || !u_target || !c) return err(MRT_EINVAL, "NULL argument");
+  int rc = check_shape(s, 1, H, W);
+  if (rc) return rc;
+  if (size_t(H) * W > size_t(s->max_h) * s->max_w)
+    return err(MRT_EINVAL, "warm start field larger than max_h x max_w");
+  if (iters < 0 || !(step0 > 0.f) || !std::isfinite(step0))
+    return err(MRT_EINVAL, "iters >= 0 and a finite step0 > 0 required");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return err(MRT_EINVAL, "alpha must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t hw = size_t(H) * W;
+  float *cp = s->wm, *gp = s->wv, *g = s->wg, *best = s->xbuf;
+  for (int k = 0; k < iters; ++k) {
+    objective(s, c, u_base, u_target, float(alpha), 1, H, W, g, st);
+    mrt::launch_bb_step(c, cp, g, gp, hw, s->bbpart, step0, k == 0 ? 1 : 0, s->obj_dev, s->bbst,
+                        st);
+    mrt::launch_bb_update(c, cp, g, gp, best, s->bbst, hw, st);
+  }
+  if (iters > 0) {
+    objective(s, c, u_base, u_target, float(alpha), 1, H, W, nullptr, st);
+    mrt::launch_bb_final(c, best, s->bbst, s->obj_dev, hw, st);
   }
   return launch_err();
 }

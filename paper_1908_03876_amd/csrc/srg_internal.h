@@ -65,4 +65,18 @@ void launch_axpy(float* dx, const float* x, float alpha, size_t n, hipStream_t s
 void launch_candidates(const float* c, const float* E, const SrgSteps& lam, int n, size_t hw,
                        float* X, hipStream_t s);
 
+// Barzilai-Borwein warm start: the step of an iteration into st[0] (from
+// the iterate c, its gradient g and the previous ones cp, gp; eta0 / RMS(g)
+// when first), with the best cost seen (st[2], J[0] being the cost at c)
+// and its flag (st[1]); then the update (best, cp, gp, c), and at the end
+// c <- best if that is better.  part: kSrgBBBlocks * 3 doubles.
+constexpr int kSrgBBBlocks = 512;
+void launch_bb_step(const float* c, const float* cp, const float* g, const float* gp, size_t n,
+                    double* part, float eta0, int first, const double* J, double* st,
+                    hipStream_t s);
+void launch_bb_update(float* c, float* cp, const float* g, float* gp, float* best,
+                      const double* st, size_t n, hipStream_t s);
+void launch_bb_final(float* c, const float* best, const double* st, const double* J, size_t n,
+                     hipStream_t s);
+
 }  // namespace mrt

@@ -23,6 +23,8 @@
 // The one-channel first and last layers stay on the vector ALU.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "srg_internal.h"
 
 namespace mrt {
@@ -854,6 +856,83 @@ __global__ __launch_bounds__(kB) void candidates_kernel(const float* __restrict_
   X[p] = c[q] - lam.v[k] * E[q];
 }
 
+// Barzilai-Borwein steepest descent on the surrogate cost (warm start).
+// With s = c_k - c_{k-1} and y = g_k - g_{k-1}: block partials of <s, s>,
+// <s, y> and <g_k, g_k>, [blk][3].
+__global__ __launch_bounds__(kB) void bb_dots_kernel(const float* __restrict__ c,
+                                                     const float* __restrict__ cp,
+                                                     const float* __restrict__ g,
+                                                     const float* __restrict__ gp, size_t n,
+                                                     double* __restrict__ part) {
+  double a[3] = {0.0, 0.0, 0.0};
+  for (size_t i = size_t(blockIdx.x) * kB + threadIdx.x; i < n; i += size_t(gridDim.x) * kB) {
+    const double gi = double(g[i]);
+    const double sv = double(c[i]) - double(cp[i]), yv = gi - double(gp[i]);
+    a[0] += sv * sv;
+    a[1] += sv * yv;
+    a[2] += gi * gi;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = block_sum_d(a[k]);
+    if (threadIdx.x == 0) part[size_t(blockIdx.x) * 3 + k] = t;
+  }
+}
+
+// One block: sums the partials in a fixed order and sets the step of this
+// iteration, st[0] = <s, s>/<s, y> when that is positive and finite (else the
+// previous step), or eta0 / RMS(g) at the first iteration.  It also keeps
+// the best surrogate cost seen, st[2], and flags st[1] = 1 when the current
+// iterate (cost J[0]) improves on it, so that the update copies it.
+__global__ __launch_bounds__(kB) void bb_step_kernel(const double* __restrict__ part, int nblk,
+                                                     double n, float eta0, int first,
+                                                     const double* __restrict__ J,
+                                                     double* __restrict__ st) {
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kB)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] += part[size_t(b) * 3 + k];
+  double r[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r[k] = block_sum_d(a[k]);
+  if (threadIdx.x == 0) {
+    if (first) {
+      st[0] = r[2] > 0.0 ? double(eta0) / sqrt(r[2] / n) : 0.0;
+      st[2] = INFINITY;
+    } else if (r[1] > 0.0 && isfinite(r[0] / r[1])) {
+      st[0] = r[0] / r[1];
+    }
+    const bool better = J[0] < st[2];
+    st[1] = better ? 1.0 : 0.0;
+    if (better) st[2] = J[0];
+  }
+}
+
+// best <- c (when flagged), cp <- c, gp <- g, c <- c - eta g.
+__global__ __launch_bounds__(kB) void bb_update_kernel(float* __restrict__ c,
+                                                       float* __restrict__ cp,
+                                                       const float* __restrict__ g,
+                                                       float* __restrict__ gp,
+                                                       float* __restrict__ best,
+                                                       const double* __restrict__ st, size_t n) {
+  const size_t i = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (i >= n) return;
+  const float ci = c[i], gi = g[i];
+  if (st[1] != 0.0) best[i] = ci;
+  cp[i] = ci;
+  gp[i] = gi;
+  c[i] = float(double(ci) - st[0] * double(gi));
+}
+
+// c <- best when the best cost seen (st[2]) is below that of c (J[0]).
+__global__ __launch_bounds__(kB) void bb_final_kernel(float* __restrict__ c,
+                                                      const float* __restrict__ best,
+                                                      const double* __restrict__ st,
+                                                      const double* __restrict__ J, size_t n) {
+  const size_t i = size_t(blockIdx.x) * kB + threadIdx.x;
+  if (i < n && st[2] < J[0]) c[i] = best[i];
+}
+
 int blocks_for(size_t n) { return int((n + kB - 1) / kB); }
 
 
@@ -978,6 +1057,26 @@ void launch_objective(float* y, const float* ub, const float* ut, const float* x
 
 void launch_axpy(float* dx, const float* x, float alpha, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(axpy_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, dx, x, alpha, n);
+}
+
+void launch_bb_step(const float* c, const float* cp, const float* g, const float* gp, size_t n,
+                    double* part, float eta0, int first, const double* J, double* st,
+                    hipStream_t s) {
+  const int nb = std::min(kSrgBBBlocks, blocks_for(n));
+  hipLaunchKernelGGL(bb_dots_kernel, dim3(nb), dim3(kB), 0, s, c, cp, g, gp, n, part);
+  hipLaunchKernelGGL(bb_step_kernel, dim3(1), dim3(kB), 0, s, part, nb, double(n), eta0, first,
+                     J, st);
+}
+
+void launch_bb_update(float* c, float* cp, const float* g, float* gp, float* best,
+                      const double* st, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(bb_update_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, c, cp, g, gp, best,
+                     st, n);
+}
+
+void launch_bb_final(float* c, const float* best, const double* st, const double* J, size_t n,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(bb_final_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, c, best, st, J, n);
 }
 
 void launch_candidates(const float* c, const float* E, const SrgSteps& lam, int n, size_t hw,

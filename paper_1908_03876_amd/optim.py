@@ -26,29 +26,15 @@ from .solver import DeviceProblem, GradientIteration
 RULES = ("FR", "PR", "HS", "DY")
 
 
-def beta(rule: str, gg_new: float, gg_old: float, g_new_g_old: float, d_g_new: float,
-         d_g_old: float) -> float:
-    """r_{k-1} from inner products of the new and old gradients and the old
-    direction: gg = <G, G>, g_new_g_old = <G_k, G_{k-1}>, d_g = <D_{k-1}, G>."""
-    y_g = gg_new - g_new_g_old          # <G_k, G_k - G_{k-1}>
-    d_y = d_g_new - d_g_old             # <D_{k-1}, G_k - G_{k-1}>
-    if rule == "FR":
-        return gg_new / gg_old
-    if rule == "PR":
-        return max(0.0, y_g / gg_old)
-    if rule == "HS":
-        return max(0.0, y_g / d_y) if d_y != 0.0 else 0.0
-    if rule == "DY":
-        return gg_new / d_y if d_y != 0.0 else 0.0
-    raise ValueError(f"unknown rule {rule}")
-
-
 class ConjugateGradient:
     """Nonlinear CG on dp (the control is kept in the solver's buffers; the
     result is in `control`)."""
 
     def __init__(self, dp: DeviceProblem, rule: str = "PR", ckpt_every: int = -1,
-                 c1: float = 1e-4, c2: float = 0.1, max_ls: int = 12):
+                 c1: float = 1e-4, c2: float = 0.1, max_ls: int = 12, first_trial=None):
+        """first_trial(cg, dg0) -> step or None: the first trial of the line
+        search along cg.D from cg.c, given dg0 = <D, G> (default, or on None:
+        the LMA step along D)."""
         if rule not in RULES:
             raise ValueError(f"rule must be one of {RULES}")
         self.dp, self.rule, self.c1, self.c2, self.max_ls = dp, rule, c1, c2, max_ls
@@ -66,6 +52,8 @@ class ConjugateGradient:
         self.tlms = 0
         self.J = None
         self.restarts = 0
+        self.first_trial = first_trial
+        self.last_zeta = None             # the previous accepted step
 
     # -- helpers (library calls)
     def _dot(self, x, y) -> float:
@@ -84,13 +72,12 @@ class ConjugateGradient:
     def _lma_along(self, ctrl) -> float:
         """Minimiser of the quadratic model of J(ctrl + zeta D) (LMA): with
         P = F'(ctrl) D, zeta = -(<u^N - u_t, P> + alpha <ctrl, D>) /
-        (<P, P> + alpha <D, D>).  Needs the forward at ctrl on the tape."""
+        (<P, P> + alpha <D, D>) (mrt_lma_step along D, negated since the
+        step is taken along +D).  Needs the forward at ctrl on the tape."""
         P, _ = self.it.tlm(dc=self.D, control=ctrl)
         self.tlms += 1
-        a = self.dp.prob.alpha
-        num = self._dot(self.it.seed, P) + a * self._dot(ctrl, self.D)
-        den = self._dot(P, P) + a * self._dot(self.D, self.D)
-        return -num / den if den > 0 else 0.0
+        return -abi.mrt_lma_step(self.dp.struct, self.it.tape.handle, ctrl, self.D,
+                                 self.it.seed, P)
 
     def start(self) -> float:
         self.J = self._eval(self.c, self.G)
@@ -100,21 +87,12 @@ class ConjugateGradient:
         """One CG iteration: new direction, Wolfe line search, update."""
         if self.J is None:
             self.start()
-        gg = self._dot(self.G, self.G)
-        if self.k == 0:
-            self._axpby(self.G, self.D, -1.0, 0.0)
-            restart = True
-        else:
-            g_go = self._dot(self.G, self.Gprev)
-            d_g = self._dot(self.D, self.G)
-            r = beta(self.rule, gg, self.gg_old, g_go, d_g, self.d_gold)
-            restart = abs(g_go) >= 0.2 * gg  # Powell: gradients far from orthogonal
-            self._axpby(self.G, self.D, -1.0, 0.0 if restart else r)
-            if not restart and self._dot(self.D, self.G) >= 0.0:
-                self._axpby(self.G, self.D, -1.0, 0.0)  # not a descent direction
-                restart = True
+        # D <- -G + beta D with the rule's beta, Powell's restart test and
+        # the descent check (mrt_cg_direction)
+        r = abi.mrt_cg_direction(self.dp.struct, self.it.tape.handle, self.rule, self.k == 0,
+                                 self.G, self.Gprev, self.D, self.gg_old, self.d_gold)
+        gg, restart, dg0 = r["gg"], r["restart"], r["dg"]   # dg0 = phi'(0) < 0
         self.restarts += int(restart and self.k > 0)
-        dg0 = self._dot(self.D, self.G)   # phi'(0) < 0
         zeta, Jn = self._line_search(dg0)
         # accept: c <- c + zeta D (the trial buffer already holds it)
         self.Gprev.copy_(self.G)
@@ -123,6 +101,7 @@ class ConjugateGradient:
         self.c, self.ct = self.ct, self.c
         self.G, self.Gt = self.Gt, self.G
         self.J = Jn
+        self.last_zeta = zeta
         self.k += 1
         return {"J": Jn, "zeta": zeta, "restart": restart}
 
@@ -140,7 +119,9 @@ class ConjugateGradient:
         bisect; the first trial is the LMA step along D.  If the trial budget
         runs out, the best sufficient-decrease step found is taken."""
         J0 = self.J
-        z = self._lma_along(self.c)
+        z = self.first_trial(self, dg0) if self.first_trial is not None else None
+        if z is None:
+            z = self._lma_along(self.c)
         if not (z > 0.0 and math.isfinite(z)):
             z = 1.0 / max(self._dot(self.D, self.D) ** 0.5, 1e-300)
         lo, hi = 0.0, math.inf

@@ -276,12 +276,7 @@ class GradientIteration:
         dp = self.dp
         c = dp.control if control is None else control
         P, _ = self.tlm(dc=self.grad, control=c, stream=stream)
-        t = self.tape.handle
-        num = abi.mrt_dot(dp.struct, t, self.seed, P, stream) + \
-            dp.prob.alpha * abi.mrt_dot(dp.struct, t, c, self.grad, stream)
-        den = abi.mrt_dot(dp.struct, t, P, P, stream) + \
-            dp.prob.alpha * abi.mrt_dot(dp.struct, t, self.grad, self.grad, stream)
-        return num / den
+        return abi.mrt_lma_step(dp.struct, self.tape.handle, c, self.grad, self.seed, P, stream)
 
     def step_lma(self, lo: float = -math.inf, hi: float = math.inf, stream=None) -> dict:
         """One gradient iteration with the LMA step size (one extra
