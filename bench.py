@@ -455,7 +455,7 @@ def bench_surrogate(args):
         f"copies {data['copy_s']:.2f} s, MRT {data['solve_s']:.1f} s "
         f"({data['solve_glups']:.1f} GLUPS)")
     var = float(((data["responses"] - data["u_base"][None]) ** 2).mean())
-    srg = SG.Surrogate(24, 1024, 1024, seed=0)
+    srg = SG.Surrogate(32, 1024, 1024, seed=0)
     t0 = time.perf_counter()
     hist = srg.train(data["controls"][:-64], data["responses"][:-64], steps=3000,
                      batch=64, crop=64, border=4, lr=2e-3, seed=1, log_every=500,
@@ -486,9 +486,11 @@ def bench_surrogate(args):
             cp = SG.ControlProblem(prob)
             fn(cp, 1)
             cp.close()
-        cp = SG.ControlProblem(prob)
-        SG.optimize_assisted(cp, srg, ub, -math.inf, max_iters=1)
-        cp.close()
+        for fn in (lambda cp: SG.optimize_assisted(cp, srg, ub, -math.inf, max_iters=1),
+                   lambda cp: SG.optimize_assisted_cg(cp, srg, ub, -math.inf, max_iters=1)):
+            cp = SG.ControlProblem(prob)
+            fn(cp)
+            cp.close()
         row = {"L": size, "plain": {}}
         for name, fn in loops:
             cp = SG.ControlProblem(prob)
@@ -501,23 +503,36 @@ def bench_surrogate(args):
             log(f"[bench] L={size} {name}: J {r['hist'][0]:.5g} -> {r['J']:.5g} in "
                 f"{r['time']:.3f} s, {r['solves']} solves")
         target = min(v["J"] for v in row["plain"].values()) * (1 + 1e-3)
-        cp = SG.ControlProblem(prob)
-        a = SG.optimize_assisted(cp, srg, ub, target, max_iters=40)
-        cp.close()
-        row["assisted"] = {"J": a["J"], "time_s": round(a["time"], 4), "solves": a["solves"],
-                           "accepted": a["accepted"], "fallbacks": a["fallbacks"],
-                           "J_history": a["hist"], "times": [round(t, 4) for t in a["times"]]}
-        log(f"[bench] L={size} assisted: J {a['hist'][0]:.5g} -> {a['J']:.5g} in "
-            f"{a['time']:.3f} s, {a['solves']} solves, {a['accepted']} accepted")
-        for name, v in row["plain"].items():
-            t_a = SG.time_to_reach(a, v["J"] * (1 + 1e-3))
-            v["reached"] = t_a is not None
-            v["assisted_time_to_target_s"] = None if t_a is None else round(t_a, 4)
-            v["speedup"] = None if t_a is None else round(v["time_to_target_s"] / t_a, 2)
-            log(f"[bench] L={size} vs {name}: reached={v['reached']} speedup={v['speedup']}")
+        # the assisted loop (surrogate warm start, then PR-CG), the same with
+        # the surrogate's curvature steps as the first line-search trials, and
+        # the gradient loop with surrogate steps
+        assisted = (("assisted", lambda cp: SG.optimize_assisted_cg(cp, srg, ub, target)),
+                    ("assisted_surrogate_steps",
+                     lambda cp: SG.optimize_assisted_cg(cp, srg, ub, target, proposals=True)),
+                    ("assisted_gd", lambda cp: SG.optimize_assisted(cp, srg, ub, target,
+                                                                    max_iters=40)))
+        row["assisted_loops"] = {}
+        for name, fn in assisted:
+            cp = SG.ControlProblem(prob)
+            a = fn(cp)
+            cp.close()
+            rec = {"J": a["J"], "time_s": round(a["time"], 4), "solves": a["solves"],
+                   "J_history": a["hist"], "times": [round(t, 4) for t in a["times"]],
+                   "vs": {}}
+            log(f"[bench] L={size} {name}: J {a['hist'][0]:.5g} -> {a['J']:.5g} in "
+                f"{a['time']:.3f} s, {a['solves']} solves")
+            for pname, v in row["plain"].items():
+                t_a = SG.time_to_reach(a, v["J"] * (1 + 1e-3))
+                rec["vs"][pname] = {"reached": t_a is not None,
+                                    "time_to_target_s": None if t_a is None else round(t_a, 4),
+                                    "speedup": None if t_a is None
+                                    else round(v["time_to_target_s"] / t_a, 2)}
+                log(f"[bench] L={size} {name} vs {pname}: {rec['vs'][pname]}")
+            row["assisted_loops"][name] = rec
         res["problems"].append(row)
     srg.close()
-    res["all_reached"] = all(v["reached"] for r in res["problems"] for v in r["plain"].values())
+    res["all_reached"] = all(v["reached"] for r in res["problems"]
+                             for v in r["assisted_loops"]["assisted"]["vs"].values())
     print(json.dumps(res), flush=True)
     if not res["all_reached"]:
         raise SystemExit("assisted loop did not reach every plain loop's cost")

@@ -334,12 +334,13 @@ int mrt_srg_train_step(mrt_srg* s, const float* x, const float* target, int32_t 
   s->step += 1;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const float c1 = 1.f - std::pow(b1, float(s->step)), c2 = 1.f - std::pow(b2, float(s->step));
+  mrt::SrgAdamTable tab{};
   for (int l = 0; l < 4; ++l) {
     Layer& y = s->L[l];
-    mrt::launch_adam(y.w, y.wb, y.dw, y.mw, y.vw, y.nw(), lr, b1, b2, eps, c1, c2, st);
-    mrt::launch_adam(y.b, nullptr, y.db, y.mb, y.vb, y.cout, lr, b1, b2, eps, c1, c2, st);
-    if (y.wf) mrt::launch_srg_pack(y.w, y.wf, y.wt, st);
+    tab.g[tab.n++] = {y.w, y.dw, y.mw, y.vw, y.wb, y.wf, y.wt, y.nw()};
+    tab.g[tab.n++] = {y.b, y.db, y.mb, y.vb, nullptr, nullptr, nullptr, y.cout};
   }
+  mrt::launch_adam_all(tab, lr, b1, b2, eps, c1, c2, st);
   rc = launch_err();
   if (rc) return rc;
   if (loss) {

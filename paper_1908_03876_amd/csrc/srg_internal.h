@@ -45,6 +45,25 @@ void launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, int
                  float lr, float b1, float b2, float eps, float c1, float c2,
                  hipStream_t s);
 void launch_to_bf16(const float* w, uint16_t* wb, int n, hipStream_t s);
+// Adam on every parameter group in one launch, with the compute copies
+// (BF16 weights of the one-channel layers, MFMA fragments of the 32 x 32
+// layers) written from the updated masters.
+struct SrgAdamGroup {
+  float* w;
+  const float* grad;
+  float* m;
+  float* v;
+  uint16_t* wb;  // BF16 copy [n], or null
+  uint16_t* wf;  // MFMA fragments of a 32 x 32 layer (n = 32 * 32 * 9), or null
+  uint16_t* wt;
+  int n;
+};
+struct SrgAdamTable {
+  SrgAdamGroup g[8];
+  int n;
+};
+void launch_adam_all(const SrgAdamTable& tab, float lr, float b1, float b2, float eps, float c1,
+                     float c2, hipStream_t s);
 void launch_gather_crops(const float* src, int L, const int* idx, const int* oy,
                          const int* ox, const float* sub, float* out, int n, int h, int w,
                          hipStream_t s);

@@ -79,6 +79,14 @@ __device__ __forceinline__ int wrap(int i, int n) {
 
 __device__ __forceinline__ size_t pix(int bh, int W, int x) { return size_t(bh) * W + x; }
 
+// A staged coordinate i in [-2, n + k) to [0, n): periodic for -n <= i < 2n
+// (every coordinate a patch's outputs depend on), clamped beyond (halo
+// coordinates past a ragged edge, whose results are not used).
+__device__ __forceinline__ int wrap_any(int i, int n) {
+  i = i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
 // 8 channels (16 bytes) of a channels-last BF16 field as an MFMA fragment.
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
@@ -583,16 +591,33 @@ __global__ __launch_bounds__(kB, 3) void c32_bwd_data_kernel(const uint16_t* __r
 
 // Weight gradients of a hidden layer on the matrix cores:
 //   dW[co][ci][t] = sum_p dz[p][co] a[p + off(t)][ci],  db[co] = sum_p dz[p][co]
-// over chunks of 32 pixels of a row (the MFMA K dimension); each wavefront
-// accumulates all 9 x 2 x 2 output fragments over its chunks, the block's
+// The MFMA's K dimension is 32 pixels of a row, so an operand is 8
+// consecutive pixels of one channel: a block walks the staged patches of the
+// forward (kPR rows x 64 pixels), stages dz and a (with its one-pixel halo)
+// in LDS transposed, channel-major with the pixels contiguous, plus a copy of
+// a shifted by one pixel, so that each operand is one aligned 16-byte read
+// (taps dx = 0, 1) or four 4-byte reads (dx = 2).  Wavefront w takes the
+// 32-pixel chunk column w % 2 of rows 2 (w / 2) and 2 (w / 2) + 1 and
+// accumulates all 9 x 2 x 2 output fragments over its chunks; the block's
 // wavefronts are summed in LDS in a fixed order, and the block writes one
 // partial [kSrgWPart] (weights in master layout, then biases).
-__global__ __launch_bounds__(kB) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
-                                                            const uint16_t* __restrict__ a,
-                                                            float* __restrict__ part, int B,
-                                                            int H, int W) {
+constexpr int kTW = 72;                       // transposed row: 66 pixels, padded
+constexpr int kAT = kC * (kPR + 2) * kTW;     // elements of one transposed a copy
+constexpr int kDT = kC * kPR * 64;            // elements of transposed dz
+constexpr int kWShared = 2 * kAT + kDT;       // uint16 elements of the stage
+static_assert(kWShared * 2 >= kSrgWPart * 4, "the block sum fits in the stage");
+
+__global__ __launch_bounds__(kB, 2) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
+                                                               const uint16_t* __restrict__ a,
+                                                               float* __restrict__ part, int B,
+                                                               int H, int W) {
+  __shared__ __attribute__((aligned(16))) uint16_t sm[kWShared];
+  uint16_t* aT0 = sm;             // [ci][r][p]: a at row y0 - 1 + r, column x0 - 1 + p
+  uint16_t* aT1 = sm + kAT;       // the same at column x0 + p
+  uint16_t* dT = sm + 2 * kAT;    // [co][r][p]: dz at row y0 + r, column x0 + p
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
-  const int wid = blockIdx.x * kWaves + (threadIdx.x >> 6), nw = gridDim.x * kWaves;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int cw = wv & 1, rh = wv >> 1;
   f32x4 acc[9][2][2];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -601,47 +626,78 @@ __global__ __launch_bounds__(kB) void c32_bwd_weight_kernel(const uint16_t* __re
 #pragma unroll
       for (int n = 0; n < 2; ++n) acc[t][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   float dbs[2] = {0.f, 0.f};
-  const int cpr = (W + 31) >> 5;
-  const int nchunks = B * H * cpr;
-  for (int ch = wid; ch < nchunks; ch += nw) {
-    const int bh = ch / cpr, x0 = (ch - bh * cpr) * 32;
-    const int b = bh / H, y = bh - b * H;
-    // A[m = co][k = pixel]: dz of the 8 pixels 8q..8q+7 of the chunk
-    bf16x8 af[2];
+  const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
+  const int npatch = B * pr * pc;
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+    const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
+    const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+    __syncthreads();  // the previous patch's reads are done
+    // a on rows y0 - 1 .. y0 + kPR, columns x0 - 1 .. x0 + 64 (periodic)
+    for (int c = threadIdx.x; c < (kPR + 2) * kSW * 4; c += kB) {
+      const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, prt = rr & 3;
+      const int yy = wrap_any(y0 - 1 + r, H), xx = wrap_any(x0 - 1 + px, W);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(a + pix(b * H + yy, W, xx) * kC + 8 * prt);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int px = x0 + 8 * q + j;
-      const bool in = px < W;
-      const size_t o = pix(bh, W, in ? px : 0) * kC + c16;
+      for (int e = 0; e < 8; ++e) {
+        const uint16_t h = uint16_t(v[e >> 1] >> (16 * (e & 1)));
+        const int o = ((8 * prt + e) * (kPR + 2) + r) * kTW;
+        aT0[o + px] = h;
+        if (px >= 1) aT1[o + px - 1] = h;
+      }
+    }
+    // dz on rows y0 .. y0 + kPR - 1, columns x0 .. x0 + 63; 0 outside the image
+    for (int c = threadIdx.x; c < kPR * 64 * 4; c += kB) {
+      const int r = c >> 8, rr = c & 255, px = rr >> 2, prt = rr & 3;
+      const int yy = y0 + r, xx = x0 + px;
+      u32x4 v = u32x4{0u, 0u, 0u, 0u};
+      if (yy < H && xx < W)
+        v = *reinterpret_cast<const u32x4*>(dz + pix(b * H + yy, W, xx) * kC + 8 * prt);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        dT[((8 * prt + e) * kPR + r) * 64 + px] = uint16_t(v[e >> 1] >> (16 * (e & 1)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jr = 0; jr < 2; ++jr) {
+      const int row = 2 * rh + jr;
+      const int p0 = 32 * cw + 8 * q;  // first pixel of this lane's K slice
+      // A[m = co][k = pixel]: dz of the lane's 8 pixels for co = 16 mb + c16
+      bf16x8 af[2];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
-        const uint16_t v = in ? dz[o + 16 * mb] : uint16_t(0);
-        af[mb][j] = __builtin_bit_cast(__bf16, v);
-        dbs[mb] += bf16_to_f32(v);
-      }
-    }
+        af[mb] = *reinterpret_cast<const bf16x8*>(dT + ((16 * mb + c16) * kPR + row) * 64 + p0);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = wrap(y + t / 3 - 1, H);
-      bf16x8 bf[2];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int px = x0 + 8 * q + j;
-        const int xx = wrap((px < W ? px : W - 1) + t % 3 - 1, W);
-        const size_t o = pix(b * H + yy, W, xx) * kC + c16;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) bf[nb][j] = __builtin_bit_cast(__bf16, a[o + 16 * nb]);
+        for (int j = 0; j < 8; ++j) dbs[mb] += float(af[mb][j]);
       }
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t % 3;
+        // B[k = pixel][n = ci]: a of the lane's 8 pixels shifted by the tap,
+        // ci = 16 nb + c16
+        bf16x8 bf[2];
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[t][mb][nb] =
-              __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf[nb], acc[t][mb][nb], 0, 0, 0);
+        for (int nb = 0; nb < 2; ++nb) {
+          const int o = ((16 * nb + c16) * (kPR + 2) + row + dy) * kTW + p0;
+          if (dx == 0) {
+            bf[nb] = *reinterpret_cast<const bf16x8*>(aT0 + o);
+          } else if (dx == 1) {
+            bf[nb] = *reinterpret_cast<const bf16x8*>(aT1 + o);
+          } else {
+            const uint32_t* w32 = reinterpret_cast<const uint32_t*>(aT0 + o + 2);
+            bf[nb] = __builtin_bit_cast(bf16x8, u32x4{w32[0], w32[1], w32[2], w32[3]});
+          }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[t][mb][nb] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf[nb], acc[t][mb][nb], 0, 0, 0);
+      }
     }
   }
-  __shared__ float red[kSrgWPart];
-  const int wv = threadIdx.x >> 6;
+  __syncthreads();  // the stage becomes the block's sum
+  float* red = reinterpret_cast<float*>(sm);
   float db2[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -777,6 +833,38 @@ __global__ __launch_bounds__(kB) void adam_kernel(float* __restrict__ w, uint16_
   const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   w[i] = wi;
   if (wb) wb[i] = f32_to_bf16(wi);
+}
+
+// One Adam step for every parameter of the network in one launch: thread i
+// finds its group in the table and updates the FP32 master, its moments and
+// its compute copy -- the BF16 weight of a one-channel layer, or, for a
+// 32 x 32 layer, its two MFMA fragment slots (forward: co = 16 mb + lane %
+// 16, ci = 8 (lane / 16) + j; transposed: ci = 16 mb + lane % 16,
+// co = 8 (lane / 16) + j; each master weight occupies one slot of each).
+__global__ __launch_bounds__(kB) void adam_all_kernel(SrgAdamTable tab, float lr, float b1,
+                                                      float b2, float eps, float c1, float c2) {
+  int i = blockIdx.x * kB + threadIdx.x;
+  int g = 0;
+  while (g < tab.n && i >= tab.g[g].n) {
+    i -= tab.g[g].n;
+    ++g;
+  }
+  if (g >= tab.n) return;
+  const SrgAdamGroup& G = tab.g[g];
+  const float gi = G.grad[i];
+  const float mi = b1 * G.m[i] + (1.f - b1) * gi;
+  const float vi = b2 * G.v[i] + (1.f - b2) * gi * gi;
+  G.m[i] = mi;
+  G.v[i] = vi;
+  const float wi = G.w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  G.w[i] = wi;
+  const uint16_t hb = f32_to_bf16(wi);
+  if (G.wb) G.wb[i] = hb;
+  if (G.wf) {  // master layout [co][ci][9], 32 x 32
+    const int t = i % 9, ci = (i / 9) % kC, co = i / (9 * kC);
+    G.wf[((t * 2 + co / 16) * 64 + co % 16 + 16 * (ci / 8)) * 8 + ci % 8] = hb;
+    G.wt[((t * 2 + ci / 16) * 64 + ci % 16 + 16 * (co / 8)) * 8 + co % 8] = hb;
+  }
 }
 
 __global__ __launch_bounds__(kB) void to_bf16_kernel(const float* __restrict__ w,
@@ -1008,9 +1096,8 @@ void launch_srg_c32_bwd_data(const uint16_t* dz, const uint16_t* wt, const uint1
 
 void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* part, float* dw,
                                float* db, int B, int H, int W, hipStream_t s) {
-  const int nchunks = B * H * ((W + 31) / 32);
-  int nb = (nchunks + kWaves - 1) / kWaves;
-  if (nb > kSrgWBlocks) nb = kSrgWBlocks;
+  const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
+  const int nb = np < kSrgWBlocks ? (np > 0 ? np : 1) : kSrgWBlocks;
   hipLaunchKernelGGL(c32_bwd_weight_kernel, dim3(nb), dim3(kB), 0, s, dz, a, part, B, H, W);
   hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + 63) / 64), dim3(kB), 0, s, part, nb,
                      dw, db);
@@ -1031,6 +1118,14 @@ void launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, int
                  float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
   hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(kB), 0, s, w, wb, g, m, v, n, lr,
                      b1, b2, eps, c1, c2);
+}
+
+void launch_adam_all(const SrgAdamTable& tab, float lr, float b1, float b2, float eps, float c1,
+                     float c2, hipStream_t s) {
+  int n = 0;
+  for (int g = 0; g < tab.n; ++g) n += tab.g[g].n;
+  hipLaunchKernelGGL(adam_all_kernel, dim3(blocks_for(size_t(n))), dim3(kB), 0, s, tab, lr, b1,
+                     b2, eps, c1, c2);
 }
 
 void launch_to_bf16(const float* w, uint16_t* wb, int n, hipStream_t s) {

@@ -76,6 +76,7 @@ class Surrogate:
 
     # -- evaluation
     def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """y = S(x)."""
         x = x.contiguous()
         B, H, W = x.shape
         y = torch.empty_like(x)
@@ -134,6 +135,28 @@ class Surrogate:
             else c0.clone().contiguous()
         abi.mrt_srg_warm_start(self.handle, u_base.contiguous(), u_target.contiguous(), alpha,
                                H, W, iters, lr, c)
+        return c
+
+    def zero_response_base(self, u_base: torch.Tensor) -> torch.Tensor:
+        """u_base - S(0): the base field corrected by the network's response to
+        the zero control (a small constant where it should be exactly zero),
+        so that the model's control response, like the true one, vanishes at
+        c = 0.  Without it a warm start spreads a spurious control over every
+        flat region of the lattice to cancel the offset."""
+        z = torch.zeros((1,) + tuple(u_base.shape), dtype=torch.float32, device=self.device)
+        return (u_base - self.forward(z)[0]).contiguous()
+
+    def warm_start_bb(self, u_base, u_target, alpha: float, iters: int = 100,
+                      step0: float = 0.5, c0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Control minimising the surrogate cost by steepest descent with
+        Barzilai-Borwein steps (one step length for the whole field, so flat
+        regions where the surrogate's gradient is only noise stay put), from
+        c0 (default 0); the iterate of least surrogate cost."""
+        H, W = u_target.shape
+        c = torch.zeros((H, W), dtype=torch.float32, device=self.device) if c0 is None \
+            else c0.clone().contiguous()
+        abi.mrt_srg_warm_start_bb(self.handle, u_base.contiguous(), u_target.contiguous(),
+                                  alpha, H, W, iters, step0, c)
         return c
 
     # -- training
@@ -460,19 +483,22 @@ def optimize_cg(cp: ControlProblem, iters: int, rule: str = "PR") -> dict:
 
 
 def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: float,
-                      max_iters: int = 50, n_cand: int = 16, warm_iters: int = 300) -> dict:
-    """Surrogate-assisted gradient loop: warm start from the surrogate, then
-    per iteration one AMRT gradient, surrogate-scored step candidates in one
-    batched inference (a factor-2 grid, then a finer one around its best),
-    and one MRT forward that verifies the chosen step (Armijo, c1 = 1e-4)
-    and records the tape for the next gradient; a rejected proposal falls
-    back to the exact line search.  Stops once J <= target_J."""
+                      max_iters: int = 50, warm_iters: int = 100) -> dict:
+    """Surrogate-assisted gradient loop: warm start from the surrogate
+    (Barzilai-Borwein steps on the surrogate cost), then per iteration one
+    AMRT gradient E, the step along -E from the surrogate's curvature
+    (SurrogateSteps, slope -|E|^2) and one MRT forward that verifies it
+    (Armijo, c1 = 1e-4) and records the tape for the next gradient; a
+    rejected step falls back to the exact line search.  Stops once
+    J <= target_J."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nx = cp.dp.nx
     ut = cp.dp.u_target[:, :nx]
     alpha = cp.prob.alpha
-    c = srg.warm_start(u_base, ut, alpha, iters=warm_iters)
+    u_base = srg.zero_response_base(u_base)
+    steps = SurrogateSteps(srg, u_base, ut, alpha)
+    c = srg.warm_start_bb(u_base, ut, alpha, iters=warm_iters)
     buf = torch.empty_like(c)
     J = cp.recorded_cost(c)
     hist = [(_clock(t0), J)]
@@ -482,17 +508,18 @@ def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: floa
         if J <= target_J:
             break
         E, einf, e2 = cp.adjoint_gradient(c)
+        h = lam_prev if lam_prev else 1.0 / math.sqrt(max(e2 * e2 / cp.it.tape.n_fluid,
+                                                          1e-300))
+        # along D = -E: score c + z D = c - z E, i.e. pass E with the sign
+        # folded into the slope (phi'(0) = -|E|^2) and the points -h, 0, h
+        lam = steps.step(c, E, -e2 * e2, h)
         lam0 = lam_prev if lam_prev else min(1.0, 1.0 / max(einf, 1e-300))
-        lams = [lam0 * 2.0 ** (k - n_cand // 2) for k in range(n_cand)]
-        pj = srg.score_steps(c, E, lams + [0.0], u_base, ut, alpha)
-        best = lams[int(np.argmin(pj[:n_cand]))]
-        fine = [best * 2.0 ** (k / 4.0) for k in range(-3, 4)]
-        pf = srg.score_steps(c, E, fine, u_base, ut, alpha)
-        lam = fine[int(np.argmin(pf))]
-        buf.copy_(c)
-        cp.step(buf, E, lam)
-        Jn = cp.recorded_cost(buf)
-        if Jn <= J - 1e-4 * lam * e2 * e2:
+        Jn = math.inf
+        if lam is not None:
+            buf.copy_(c)
+            cp.step(buf, E, lam)
+            Jn = cp.recorded_cost(buf)
+        if lam is not None and Jn <= J - 1e-4 * lam * e2 * e2:
             accepted += 1
             c, buf = buf, c
         else:
@@ -504,6 +531,69 @@ def optimize_assisted(cp: ControlProblem, srg: Surrogate, u_base, target_J: floa
         J = Jn
         hist.append((_clock(t0), J))
     return _result(cp, hist, c, t0, accepted=accepted, fallbacks=fallbacks)
+
+
+class SurrogateSteps:
+    """Step sizes from the surrogate's curvature: along a direction D from c
+    the cost is phi(z) = J(c + z D); its slope phi'(0) = <G, D> is exact
+    (the adjoint gradient) and its curvature is taken from the surrogate,
+    kappa = (J_s(c + h D) - 2 J_s(c) + J_s(c - h D)) / h^2, three surrogate
+    costs in one batched inference.  The step z = -phi'(0) / kappa is the
+    minimiser of that quadratic model: the linearised line minimisation
+    (LMA) of Section 2.4 with the network's Jacobian in place of the
+    tangent-linear solve.  h is the previous step (or a unit RMS move).  The
+    MRT solve at the trial decides whether it is accepted."""
+
+    def __init__(self, srg: Surrogate, u_base, u_target, alpha: float):
+        self.srg, self.ub, self.ut, self.alpha = srg, u_base, u_target, alpha
+
+    def step(self, c, D, slope: float, h: float):
+        J = self.srg.score_steps(c, D, [-h, 0.0, h], self.ub, self.ut, self.alpha)
+        kappa = (J[0] - 2.0 * J[1] + J[2]) / (h * h)
+        if not (kappa > 0.0 and math.isfinite(kappa)) or not slope < 0.0:
+            return None
+        return -slope / kappa
+
+    def __call__(self, cg, dg0: float):
+        h = cg.last_zeta
+        if not h:
+            dd = abi.mrt_dot(cg.dp.struct, cg.it.tape.handle, cg.D, cg.D)
+            h = 1.0 / math.sqrt(max(dd / cg.it.tape.n_fluid, 1e-300))
+        return self.step(cg.c, cg.D, dg0, h)
+
+
+def optimize_assisted_cg(cp: ControlProblem, srg: Surrogate, u_base, target_J: float,
+                         max_iters: int = 40, warm_iters: int = 100, rule: str = "PR",
+                         proposals: bool = False) -> dict:
+    """Surrogate-assisted conjugate gradients: the warm start minimises the
+    surrogate cost (Barzilai-Borwein steps, base field corrected by the
+    network's zero-control response), then nonlinear CG on the true cost
+    (MRT + AMRT gradients, Wolfe line search from the LMA step); with
+    proposals=True the first trial steps come from the surrogate's curvature
+    instead (no tangent-linear solve).  Stops once J <= target_J."""
+    from .optim import ConjugateGradient
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nx = cp.dp.nx
+    ut = cp.dp.u_target[:, :nx]
+    alpha = cp.prob.alpha
+    u_base = srg.zero_response_base(u_base)
+    c0 = srg.warm_start_bb(u_base, ut, alpha, iters=warm_iters)
+    steps = SurrogateSteps(srg, u_base, ut, alpha) if proposals else None
+    cg = ConjugateGradient(cp.dp, rule=rule, ckpt_every=-1, first_trial=steps)
+    cg.c.copy_(c0)
+    hist = [(_clock(t0), cg.start())]
+    for _ in range(max_iters):
+        if hist[-1][1] <= target_J:
+            break
+        hist.append((_clock(t0), cg.iterate()["J"]))
+    cp.n_forward += cg.evals
+    cp.n_adjoint += cg.evals
+    cp.n_tlm += cg.tlms
+    c = cg.control.clone()
+    out = _result(cp, hist, c, t0, restarts=cg.restarts)
+    cg.close()
+    return out
 
 
 def time_to_reach(res: dict, target: float):
