@@ -160,20 +160,41 @@ __device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const
   }
 }
 
+// Adjoint sweep over this block's tiles, two at a time as the forward:
+// both tiles' gathers are issued before either update.  The two updates
+// run through one copy of the update code (a loop that is not unrolled),
+// so that a node computes the same bits whichever tile of a pair it falls
+// in, for every tile shape.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     const T* rec) {
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const BatchTile tl = a.tiles[t];
-    const int k = __builtin_amdgcn_readfirstlane(tl.k);
-    const Geometry g = inst_geom(__builtin_amdgcn_readfirstlane(tl.L));
-    NodeIdx n;
-    if (!tile_node(tl, a.tile_w, g, n)) continue;
-    const size_t fo = size_t(tl.fo);
-    adjoint_node<T, true, false, FIRST, false>(
-        g, n, a.coef[k], src ? src + 18 * fo : nullptr,
-        dst ? dst + 18 * fo : nullptr, a.seed_u + fo, nullptr, rec + 3 * fo,
-        a.gacc + fo, nullptr, nullptr);
+  const int nb = gridDim.x;
+  for (int t = blockIdx.x; t < a.ntiles; t += 2 * nb) {
+    TileNode<T> A = tile_of(a, t);
+    const bool hasB = t + nb < a.ntiles;
+    const TileNode<T> B = tile_of(a, hasB ? t + nb : t);
+    T ua[9], va[9], wa[9], ub[9], vb[9], wb[9];
+    if (A.ok)
+      adjoint_gather<T, true, false, FIRST>(A.g, A.n, src ? src + 18 * A.fo : nullptr,
+                                            a.seed_u + A.fo, nullptr, 0u, ua, va, wa);
+    if (hasB && B.ok)
+      adjoint_gather<T, true, false, FIRST>(B.g, B.n, src ? src + 18 * B.fo : nullptr,
+                                            a.seed_u + B.fo, nullptr, 0u, ub, vb, wb);
+#pragma unroll 1
+    for (int r = 0; r < (hasB ? 2 : 1); ++r) {
+      if (A.ok)
+        adjoint_update<T, true, false, FIRST, false>(
+            A.g, A.n, a.coef[A.k], ua, va, wa, dst ? dst + 18 * A.fo : nullptr, rec + 3 * A.fo,
+            a.gacc + A.fo, nullptr, nullptr, nullptr, false, 0u);
+      // the second pass updates tile B with the same code
+      A = B;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        ua[i] = ub[i];
+        va[i] = vb[i];
+        wa[i] = wb[i];
+      }
+    }
   }
 }
 

@@ -335,7 +335,7 @@ __device__ __forceinline__ void wall_reads(const Geometry3& g, const T* __restri
   for (int i = 1; i < Q; ++i) {
     own[i] = f[i];
     if ((lm >> (ADJ ? opp(i) : i)) & 1u)
-      own[i] = bload<ADJ ? kNT : 0>(rsrc_of(buf + size_t(opp(i)) * g.planeI), bo, T(0));
+      own[i] = bload<0>(rsrc_of(buf + size_t(opp(i)) * g.planeI), bo, T(0));
   }
 #pragma unroll
   for (int i = 1; i < Q; ++i) f[i] = own[i];
@@ -372,6 +372,12 @@ __device__ __forceinline__ void gather(const Geometry3& g, const Node3& n,
       fu[i] = m.u.w_diag * a;
       fv[i] = m.v.w_diag * b;
     }
+  } else if (MASKED && (lm & 1u)) {
+    // a solid lane of a mixed wavefront: its results are never read, so it
+    // loads nothing (lines that only solid lanes would touch are not
+    // fetched)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fu[i] = fv[i] = T(0);
   } else {
     const T* sv = src + size_t(Q) * g.planeI;
 #pragma unroll
@@ -540,12 +546,16 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
       nu[i] = a.seed_u[s];
       nv[i] = a.seed_v ? a.seed_v[s] : T(0);
     }
+  } else if (MASKED && (lm & 1u)) {
+    // solid lane of a mixed wavefront: nothing to gather (see gather())
+#pragma unroll
+    for (int i = 0; i < Q; ++i) nu[i] = nv[i] = T(0);
   } else {
     const T* sv = a.src + size_t(Q) * g.planeI;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      nu[i] = gather_ld<T, PERIODIC, kNT>(g, n, a.src, i, bo);
-      nv[i] = gather_ld<T, PERIODIC, kNT>(g, n, sv, i, bo);
+      nu[i] = gather_ld<T, PERIODIC, 0>(g, n, a.src, i, bo);
+      nv[i] = gather_ld<T, PERIODIC, 0>(g, n, sv, i, bo);
     }
     if (MASKED && lm != 0u) {
       wall_reads<T, true>(g, a.src, nu, lm, bo);

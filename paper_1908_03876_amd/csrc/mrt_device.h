@@ -632,6 +632,9 @@ __device__ __forceinline__ void forward_node(
     const unsigned flag = wave_flag(g, n);
     if (flag == 2u) return;  // wavefront inside a solid region
     lm = link_of(g, flag, n.r0 + n.x);
+    // a solid node of a mixed wavefront stores nothing (its slots hold the
+    // neighbours' wall stores), so it loads nothing either
+    if (lm & 1u) return;
   }
   T fu[9], fv[9], c;
   forward_gather<T, PERIODIC, FIRST>(g, n, m, src, u0, v0, ctrl, fu, fv, c);
@@ -721,36 +724,21 @@ __device__ __forceinline__ void finalize_node(
 // step, the cost not depending on w): sigma_w enters u's source through
 // a_w, w's own through -b_w; the repulsive flux u Bw j_w adds
 // p . (Bw j_w) to u's and e_i . (u Bw^T p) to w's.
-template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, int VAR = kVarFirst>
-__device__ __forceinline__ void adjoint_node(
-    const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
-    const T* __restrict__ seed_u, const T* __restrict__ seed_v,
-    const T* __restrict__ rec, double* __restrict__ gacc,
-    T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu = nullptr,
-    bool step0 = false) {
+//
+// adjoint_node = adjoint_gather + adjoint_update.
+//
+// Adjoint gather of node n (FIRST: the terminal seeds), the half of the
+// node update that loads; adjoint_update finishes it.  Split so that a
+// caller can issue the loads of two nodes before either update.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, int VAR = kVarFirst>
+__device__ __forceinline__ void adjoint_gather(const Geometry& g, const NodeIdx& n,
+                                               const T* __restrict__ src,
+                                               const T* __restrict__ seed_u,
+                                               const T* __restrict__ seed_v, unsigned lm,
+                                               T nu[9], T nv[9], T nw[9]) {
   const size_t idx = n.r0 + n.x;
-  unsigned lm = 0;
-  if (MASKED) {
-    const unsigned flag = wave_flag(g, n);
-    if (FIRST || LAST) {
-      // single steps: resolve solid nodes up front, they own outputs
-      lm = g.link[idx];
-      if (lm & 1u) {
-        if (FIRST) gacc[idx] = 0.0;
-        if (LAST) {
-          if (adj_u0) adj_u0[idx] = T(0);
-          if (adj_v0) adj_v0[idx] = T(0);
-        }
-        return;
-      }
-    } else {
-      if (flag == 2u) return;  // wavefront inside a solid region
-      lm = link_of(g, flag, idx);
-    }
-  }
   // reverse streaming: nu_i(x) = lambda_i(x + e_i), or lambda_opp(i)(x)
   // when x + e_i is a wall (exact transpose of the pull with bounce-back)
-  T nu[9], nv[9];
   if (FIRST) {
     // terminal condition lambda_i^N = seed for every i (psi(T) = dI0/dphi);
     // the seed fields carry no wall slots, so walls are tested here
@@ -767,12 +755,11 @@ __device__ __forceinline__ void adjoint_node(
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const size_t o = gather_src<PERIODIC>(n, i, g.plane);
-      nu[i] = __builtin_nontemporal_load(&src[o]);
-      nv[i] = __builtin_nontemporal_load(&sv[o]);
+      nu[i] = src[o];
+      nv[i] = sv[o];
     }
   }
   constexpr bool W3 = VAR == kVarThree;
-  T nw[9];
   if (W3) {
     if (FIRST) {
 #pragma unroll
@@ -781,9 +768,21 @@ __device__ __forceinline__ void adjoint_node(
       const T* sw = src + 18 * g.plane;
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        nw[i] = __builtin_nontemporal_load(&sw[gather_src<PERIODIC>(n, i, g.plane)]);
+        nw[i] = sw[gather_src<PERIODIC>(n, i, g.plane)];
     }
   }
+}
+
+// The rest of the adjoint node update after adjoint_gather: sources,
+// collision, gradient accumulation and the stores.
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, int VAR = kVarFirst>
+__device__ __forceinline__ void adjoint_update(
+    const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, T nu[9], T nv[9], T nw[9],
+    T* __restrict__ dst, const T* __restrict__ rec, double* __restrict__ gacc,
+    T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu, bool step0,
+    unsigned lm) {
+  const size_t idx = n.r0 + n.x;
+  constexpr bool W3 = VAR == kVarThree;
   // weighted sums: sigma = w . nu, p = (tau/Cs^2) sum_i w_i nu_u,i e_i
   const T su_ = T(4.0 / 9.0) * nu[0] +
                 T(1.0 / 9.0) * (nu[1] + nu[2] + nu[3] + nu[4]) +
@@ -795,9 +794,6 @@ __device__ __forceinline__ void adjoint_node(
                T(1.0 / 12.0) * (nu[5] - nu[6] - nu[7] + nu[8]);
   const T py = T(1.0 / 3.0) * (nu[2] - nu[4]) +
                T(1.0 / 12.0) * (nu[5] + nu[6] - nu[7] - nu[8]);
-  // solid nodes of mixed wavefronts gathered slots they do not own; they
-  // update nothing
-  if (MASKED && (lm & 1u)) return;
   constexpr bool LAG = VAR == kVarExplicit;
   constexpr bool IMPL = VAR == kVarImplicit;
   // gradient w.r.t. the control on v: dF_v,i/dc = tau w_i (the implicit
@@ -946,6 +942,40 @@ __device__ __forceinline__ void adjoint_node(
       }
     }
   }
+}
+
+template <typename T, bool PERIODIC, bool MASKED, bool FIRST, bool LAST, int VAR = kVarFirst>
+__device__ __forceinline__ void adjoint_node(
+    const Geometry& g, const NodeIdx& n, const ModelCoef<T>& m, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ seed_u, const T* __restrict__ seed_v,
+    const T* __restrict__ rec, double* __restrict__ gacc,
+    T* __restrict__ adj_u0, T* __restrict__ adj_v0, T* __restrict__ mu = nullptr,
+    bool step0 = false) {
+  const size_t idx = n.r0 + n.x;
+  unsigned lm = 0;
+  if (MASKED) {
+    const unsigned flag = wave_flag(g, n);
+    if (FIRST || LAST) {
+      // single steps: resolve solid nodes up front, they own outputs
+      lm = g.link[idx];
+      if (lm & 1u) {
+        if (FIRST) gacc[idx] = 0.0;
+        if (LAST) {
+          if (adj_u0) adj_u0[idx] = T(0);
+          if (adj_v0) adj_v0[idx] = T(0);
+        }
+        return;
+      }
+    } else {
+      if (flag == 2u) return;  // wavefront inside a solid region
+      lm = link_of(g, flag, idx);
+      if (lm & 1u) return;  // solid node of a mixed wavefront: no update
+    }
+  }
+  T nu[9], nv[9], nw[9];
+  adjoint_gather<T, PERIODIC, MASKED, FIRST, VAR>(g, n, src, seed_u, seed_v, lm, nu, nv, nw);
+  adjoint_update<T, PERIODIC, MASKED, FIRST, LAST, VAR>(g, n, m, nu, nv, nw, dst, rec, gacc,
+                                                        adj_u0, adj_v0, mu, step0, lm);
 }
 
 // ------------------------------------------------------------ reductions

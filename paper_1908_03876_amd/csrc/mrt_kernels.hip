@@ -193,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void tlm_step_kernel(
     const unsigned flag = wave_flag(g, n);
     if (flag == 2u) return;  // wavefront inside a solid region
     lm = link_of(g, flag, idx);
+    if (lm & 1u) return;  // solid node of a mixed wavefront: stores nothing
   }
   T fu[9], fv[9];
   if (FIRST) {

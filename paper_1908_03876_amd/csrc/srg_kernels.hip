@@ -334,8 +334,11 @@ __global__ __launch_bounds__(kB) void l3_bwd_data_kernel(const float* __restrict
 // one-channel field S:  out[c][t] = sum_p F[p][c] S[p + sgn off(t)], all nine
 // taps in one pass over F.  Lane = (pixel pp = lane / 8 of the wavefront's 8
 // pixels, channel quad cq = lane % 8); each lane keeps 9 x 4 products, the 4
-// channel sums and (cq = 0) the sum of S.  Block partials: [9][nblk][32]
-// products, [nblk][32] channel sums of F (slot 9), [nblk] sums of S.
+// channel sums and (cq = 0) the sum of S.  A lane's (image, row, column)
+// advances by the grid stride with carries, and its nine S offsets come
+// from three wrapped rows and three wrapped columns.  Block partials:
+// [9][nblk][32] products, [nblk][32] channel sums of F (slot 9), [nblk]
+// sums of S.
 __global__ __launch_bounds__(kB) void thin_wgrad_kernel(const uint16_t* __restrict__ F,
                                                         const float* __restrict__ S, int sgn,
                                                         double* __restrict__ part, int B, int H,
@@ -348,21 +351,57 @@ __global__ __launch_bounds__(kB) void thin_wgrad_kernel(const uint16_t* __restri
   for (int t = 0; t < 9; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[t][j] = 0.f;
-  for (size_t p = (size_t(blockIdx.x) * kWaves + wv) * 8 + pp; p < n;
-       p += size_t(nblk) * kWaves * 8) {
-    const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
-    const u32x2 q = *reinterpret_cast<const u32x2*>(F + p * kC + 4 * cq);
-    const float f[4] = {lo16(q[0]), hi16(q[0]), lo16(q[1]), hi16(q[1])};
-    const float* Sb = S + size_t(b) * hw;
+  // four pixels per lane per pass, all their loads issued before the sums;
+  // the lane's (image, row, column) advances by the grid stride with
+  // carries instead of a division per pixel
+  constexpr int kU = 4;
+  const size_t stride = size_t(nblk) * kWaves * 8;
+  const int sb = int(stride / hw), srem = int(stride % hw), sy = srem / W, sx = srem % W;
+  size_t p0 = (size_t(blockIdx.x) * kWaves + wv) * 8 + pp;
+  int b = int(p0 / hw), py, px;
+  {
+    const int r = int(p0 % hw);
+    py = r / W;
+    px = r % W;
+  }
+  for (; p0 < n; p0 += kU * stride) {
+    u32x2 qv[kU];
+    float sv[kU][9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const float sv = Sb[size_t(wrap(py + sgn * (t / 3 - 1), H)) * W + wrap(px + sgn * (t % 3 - 1), W)];
+    for (int u = 0; u < kU; ++u) {
+      const size_t p = p0 + u * stride;
+      qv[u] = u32x2{0u, 0u};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[t][j] += f[j] * sv;
-      if (t == 4 && cq == 0) ss += sv;
+      for (int t = 0; t < 9; ++t) sv[u][t] = 0.f;
+      if (p < n) {
+        qv[u] = *reinterpret_cast<const u32x2*>(F + p * kC + 4 * cq);
+        const float* Sb = S + size_t(b) * hw;
+        int ro[3], co[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          ro[d] = wrap(py + sgn * (d - 1), H) * W;
+          co[d] = wrap(px + sgn * (d - 1), W);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) sv[u][t] = Sb[ro[t / 3] + co[t % 3]];
+      }
+      px += sx;
+      if (px >= W) { px -= W; ++py; }
+      py += sy;
+      if (py >= H) { py -= H; ++b; }
+      b += sb;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) fs[j] += f[j];
+    for (int u = 0; u < kU; ++u) {
+      const float f[4] = {lo16(qv[u][0]), hi16(qv[u][0]), lo16(qv[u][1]), hi16(qv[u][1])};
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[t][j] += f[j] * sv[u][t];
+      if (cq == 0) ss += sv[u][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fs[j] += f[j];
+    }
   }
   // lanes of one channel quad: xor 8, 16, 32; then the waves in LDS
   constexpr int kV = 9 * 4 + 4 + 1;
@@ -591,30 +630,105 @@ __global__ __launch_bounds__(kB, 3) void c32_bwd_data_kernel(const uint16_t* __r
 
 // Weight gradients of a hidden layer on the matrix cores:
 //   dW[co][ci][t] = sum_p dz[p][co] a[p + off(t)][ci],  db[co] = sum_p dz[p][co]
-// The MFMA's K dimension is 32 pixels of a row, so an operand is 8
-// consecutive pixels of one channel: a block walks the staged patches of the
-// forward (kPR rows x 64 pixels), stages dz and a (with its one-pixel halo)
-// in LDS transposed, channel-major with the pixels contiguous, plus a copy of
-// a shifted by one pixel, so that each operand is one aligned 16-byte read
-// (taps dx = 0, 1) or four 4-byte reads (dx = 2).  Wavefront w takes the
-// 32-pixel chunk column w % 2 of rows 2 (w / 2) and 2 (w / 2) + 1 and
-// accumulates all 9 x 2 x 2 output fragments over its chunks; the block's
-// wavefronts are summed in LDS in a fixed order, and the block writes one
-// partial [kSrgWPart] (weights in master layout, then biases).
-constexpr int kTW = 72;                       // transposed row: 66 pixels, padded
-constexpr int kAT = kC * (kPR + 2) * kTW;     // elements of one transposed a copy
-constexpr int kDT = kC * kPR * 64;            // elements of transposed dz
-constexpr int kWShared = 2 * kAT + kDT;       // uint16 elements of the stage
-static_assert(kWShared * 2 >= kSrgWPart * 4, "the block sum fits in the stage");
+// The MFMA's K dimension is pixels, so an operand is 8 consecutive pixels
+// of one channel: a block walks the staged patches of the forward (kPR rows
+// x 64 pixels) and stages dz and a (with its one-pixel halo) in LDS
+// transposed, channel-major with the pixels contiguous.  A thread stages 8
+// pixels x 8 channels: eight 16-byte loads, a transpose in registers and
+// eight 16-byte LDS writes.  The channel strides (kCSa, kCSd) are 4 dwords
+// modulo 32 (and 36 or 4 modulo 64), so the 16-byte fragment reads of 8
+// or 16 lanes on consecutive channels fall on distinct banks.  For each row
+// of taps a lane reads 8 + 2 staged pixels once: the taps dx = 0, 1, 2 are
+// that window at offsets 0, 1 (realigned with alignbit) and 2.  Wavefront
+// w takes the 32-pixel chunk column w % 2 of rows 2 (w / 2) and
+// 2 (w / 2) + 1 and accumulates all 9 x 2 x 2 output fragments over its
+// chunks.  The block's wavefronts are summed in a fixed order, and the block
+// writes one partial [kSrgWPart] in fragment order: the weights as
+// [t][mb][nb][lane][4] (co = 16 mb + 4 (lane / 16) + j, ci = 16 nb +
+// lane % 16), then the 32 bias sums.
+constexpr int kTW = 72;                          // staged pixels per row of a
+constexpr int kCSa = (kPR + 2) * kTW + 24;       // channel stride of a (228 dwords)
+constexpr int kCSd = kPR * 64 + 8;               // channel stride of dz (132 dwords)
+constexpr int kWShared = kC * kCSa + kC * kCSd;  // uint16 elements of the stage
+constexpr int kAItems = (kPR + 2) * (kTW / 8) * 4;  // (row, 8-pixel group, channel octet)
+constexpr int kDItems = kPR * 8 * 4;
+static_assert((kCSa / 2) % 32 == 4 && (kCSd / 2) % 32 == 4, "conflict-free channel strides");
+// after the last patch the stage holds the four wavefronts' sums
+constexpr int kWLds = kWShared > 2 * kWaves * kSrgWPart ? kWShared : 2 * kWaves * kSrgWPart;
 
-__global__ __launch_bounds__(kB, 2) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
+// Transpose 8 pixels x 8 BF16 channels: v[j] holds channels 0..7 of pixel
+// j; o[c] receives pixels 0..7 of channel c.
+__device__ __forceinline__ void transpose8(const u32x4 (&v)[8], u32x4 (&o)[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // low halves (even channel) or high halves (odd channel) of pixels 2k, 2k + 1
+      const uint32_t lo = v[2 * k][c >> 1], hi = v[2 * k + 1][c >> 1];
+      o[c][k] = (c & 1) ? __builtin_amdgcn_perm(hi, lo, 0x07060302u)
+                        : __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+    }
+}
+
+// Staging item `it` of a patch: its 8 x 16-byte loads (issued, not waited
+// for), and where its 8 channel rows go in the stage.
+constexpr int kWItems = (kAItems + kDItems + kB - 1) / kB;  // items per thread
+static_assert(kWItems == 2, "two staging items per thread");
+
+__device__ __forceinline__ void wgrad_fetch(const uint16_t* __restrict__ dz,
+                                            const uint16_t* __restrict__ a, int it, int b,
+                                            int y0, int x0, int H, int W, u32x4 (&v)[8]) {
+  if (it < kAItems) {
+    // a: group g (pixels 8g .. 8g + 7 of the staged row) fastest
+    const int g = it % (kTW / 8), rest = it / (kTW / 8), prt = rest & 3, r = rest >> 2;
+    const size_t row = size_t(b * H + wrap_any(y0 - 1 + r, H)) * W;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v[j] = *reinterpret_cast<const u32x4*>(a + (row + wrap_any(x0 - 1 + 8 * g + j, W)) * kC +
+                                             8 * prt);
+  } else if (it < kAItems + kDItems) {
+    const int k = it - kAItems, g = k & 7, prt = (k >> 3) & 3, r = k >> 5;
+    const int yy = y0 + r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int xx = x0 + 8 * g + j;
+      v[j] = (yy < H && xx < W)
+                 ? *reinterpret_cast<const u32x4*>(dz + pix(b * H + yy, W, xx) * kC + 8 * prt)
+                 : u32x4{0u, 0u, 0u, 0u};
+    }
+  }
+}
+
+__device__ __forceinline__ void wgrad_stage(uint16_t* aT, uint16_t* dT, int it,
+                                            const u32x4 (&v)[8]) {
+  uint16_t* dst;
+  int cs;
+  if (it < kAItems) {
+    const int g = it % (kTW / 8), rest = it / (kTW / 8), prt = rest & 3, r = rest >> 2;
+    dst = aT + 8 * prt * kCSa + r * kTW + 8 * g;
+    cs = kCSa;
+  } else if (it < kAItems + kDItems) {
+    const int k = it - kAItems, g = k & 7, prt = (k >> 3) & 3, r = k >> 5;
+    dst = dT + 8 * prt * kCSd + r * 64 + 8 * g;
+    cs = kCSd;
+  } else {
+    return;
+  }
+  u32x4 o[8];
+  transpose8(v, o);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) *reinterpret_cast<u32x4*>(dst + c * cs) = o[c];
+}
+
+// One block per CU: the next patch's loads are in flight while the MFMAs of
+// the current one run.
+__global__ __launch_bounds__(kB, 1) void c32_bwd_weight_kernel(const uint16_t* __restrict__ dz,
                                                                const uint16_t* __restrict__ a,
                                                                float* __restrict__ part, int B,
                                                                int H, int W) {
-  __shared__ __attribute__((aligned(16))) uint16_t sm[kWShared];
-  uint16_t* aT0 = sm;             // [ci][r][p]: a at row y0 - 1 + r, column x0 - 1 + p
-  uint16_t* aT1 = sm + kAT;       // the same at column x0 + p
-  uint16_t* dT = sm + 2 * kAT;    // [co][r][p]: dz at row y0 + r, column x0 + p
+  __shared__ __attribute__((aligned(16))) uint16_t sm[kWLds];
+  uint16_t* aT = sm;             // [ci][r][p]: a at row y0 - 1 + r, column x0 - 1 + p
+  uint16_t* dT = sm + kC * kCSa; // [co][r][p]: dz at row y0 + r, column x0 + p
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int cw = wv & 1, rh = wv >> 1;
@@ -628,35 +742,21 @@ __global__ __launch_bounds__(kB, 2) void c32_bwd_weight_kernel(const uint16_t* _
   float dbs[2] = {0.f, 0.f};
   const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
   const int npatch = B * pr * pc;
-  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+  const int it0 = threadIdx.x, it1 = threadIdx.x + kB;
+  u32x4 v0[8], v1[8];
+  auto fetch = [&](int patch) {
     const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
     const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
+    wgrad_fetch(dz, a, it0, b, y0, x0, H, W, v0);
+    wgrad_fetch(dz, a, it1, b, y0, x0, H, W, v1);
+  };
+  if (int(blockIdx.x) < npatch) fetch(blockIdx.x);
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
     __syncthreads();  // the previous patch's reads are done
-    // a on rows y0 - 1 .. y0 + kPR, columns x0 - 1 .. x0 + 64 (periodic)
-    for (int c = threadIdx.x; c < (kPR + 2) * kSW * 4; c += kB) {
-      const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, prt = rr & 3;
-      const int yy = wrap_any(y0 - 1 + r, H), xx = wrap_any(x0 - 1 + px, W);
-      const u32x4 v = *reinterpret_cast<const u32x4*>(a + pix(b * H + yy, W, xx) * kC + 8 * prt);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint16_t h = uint16_t(v[e >> 1] >> (16 * (e & 1)));
-        const int o = ((8 * prt + e) * (kPR + 2) + r) * kTW;
-        aT0[o + px] = h;
-        if (px >= 1) aT1[o + px - 1] = h;
-      }
-    }
-    // dz on rows y0 .. y0 + kPR - 1, columns x0 .. x0 + 63; 0 outside the image
-    for (int c = threadIdx.x; c < kPR * 64 * 4; c += kB) {
-      const int r = c >> 8, rr = c & 255, px = rr >> 2, prt = rr & 3;
-      const int yy = y0 + r, xx = x0 + px;
-      u32x4 v = u32x4{0u, 0u, 0u, 0u};
-      if (yy < H && xx < W)
-        v = *reinterpret_cast<const u32x4*>(dz + pix(b * H + yy, W, xx) * kC + 8 * prt);
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        dT[((8 * prt + e) * kPR + r) * 64 + px] = uint16_t(v[e >> 1] >> (16 * (e & 1)));
-    }
+    wgrad_stage(aT, dT, it0, v0);
+    wgrad_stage(aT, dT, it1, v1);
     __syncthreads();
+    if (patch + int(gridDim.x) < npatch) fetch(patch + gridDim.x);
 #pragma unroll
     for (int jr = 0; jr < 2; ++jr) {
       const int row = 2 * rh + jr;
@@ -665,39 +765,40 @@ __global__ __launch_bounds__(kB, 2) void c32_bwd_weight_kernel(const uint16_t* _
       bf16x8 af[2];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
-        af[mb] = *reinterpret_cast<const bf16x8*>(dT + ((16 * mb + c16) * kPR + row) * 64 + p0);
+        af[mb] = *reinterpret_cast<const bf16x8*>(dT + (16 * mb + c16) * kCSd + row * 64 + p0);
 #pragma unroll
         for (int j = 0; j < 8; ++j) dbs[mb] += float(af[mb][j]);
       }
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3, dx = t % 3;
+      for (int dy = 0; dy < 3; ++dy) {
         // B[k = pixel][n = ci]: a of the lane's 8 pixels shifted by the tap,
-        // ci = 16 nb + c16
-        bf16x8 bf[2];
+        // ci = 16 nb + c16; staged pixels p0 .. p0 + 9 serve dx = 0, 1, 2
+        bf16x8 bf[3][2];
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-          const int o = ((16 * nb + c16) * (kPR + 2) + row + dy) * kTW + p0;
-          if (dx == 0) {
-            bf[nb] = *reinterpret_cast<const bf16x8*>(aT0 + o);
-          } else if (dx == 1) {
-            bf[nb] = *reinterpret_cast<const bf16x8*>(aT1 + o);
-          } else {
-            const uint32_t* w32 = reinterpret_cast<const uint32_t*>(aT0 + o + 2);
-            bf[nb] = __builtin_bit_cast(bf16x8, u32x4{w32[0], w32[1], w32[2], w32[3]});
-          }
+          const uint16_t* src = aT + (16 * nb + c16) * kCSa + (row + dy) * kTW + p0;
+          const u32x4 d = *reinterpret_cast<const u32x4*>(src);
+          const uint32_t d4 = *reinterpret_cast<const uint32_t*>(src + 8);
+          const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+          bf[0][nb] = __builtin_bit_cast(bf16x8, d);
+          bf[1][nb] = __builtin_bit_cast(
+              bf16x8, u32x4{__builtin_amdgcn_alignbit(d1, d0, 16), __builtin_amdgcn_alignbit(d2, d1, 16),
+                            __builtin_amdgcn_alignbit(d3, d2, 16), __builtin_amdgcn_alignbit(d4, d3, 16)});
+          bf[2][nb] = __builtin_bit_cast(bf16x8, u32x4{d1, d2, d3, d4});
         }
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            acc[t][mb][nb] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf[nb], acc[t][mb][nb], 0, 0, 0);
+          for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[3 * dy + dx][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  af[mb], bf[dx][nb], acc[3 * dy + dx][mb][nb], 0, 0, 0);
       }
     }
   }
-  __syncthreads();  // the stage becomes the block's sum
-  float* red = reinterpret_cast<float*>(sm);
+  __syncthreads();  // the stage becomes four regions, one per wavefront
+  float* reg = reinterpret_cast<float*>(sm);
   float db2[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -706,48 +807,42 @@ __global__ __launch_bounds__(kB, 2) void c32_bwd_weight_kernel(const uint16_t* _
     v += __shfl_xor(v, 32, 64);
     db2[mb] = v;
   }
-  for (int k = 0; k < kWaves; ++k) {
-    if (wv == k) {
+  float* mine = reg + wv * kSrgWPart;
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
+  for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int co = 16 * mb + 4 * q + j, ci = 16 * nb + c16;
-              float& r = red[(co * kC + ci) * 9 + t];
-              r = k == 0 ? acc[t][mb][nb][j] : r + acc[t][mb][nb][j];
-            }
-      if (q == 0)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          float& r = red[kC * kC * 9 + 16 * mb + c16];
-          r = k == 0 ? db2[mb] : r + db2[mb];
-        }
-    }
-    __syncthreads();
+      for (int nb = 0; nb < 2; ++nb)
+        *reinterpret_cast<f32x4*>(mine + (((t * 2 + mb) * 2 + nb) * 64 + lane) * 4) =
+            acc[t][mb][nb];
+  if (q == 0) {
+    mine[kC * kC * 9 + c16] = db2[0];
+    mine[kC * kC * 9 + 16 + c16] = db2[1];
   }
+  __syncthreads();
+  // the block's partial in fragment order (wavefronts summed in a fixed order)
   float* P = part + size_t(blockIdx.x) * kSrgWPart;
-  for (int i = threadIdx.x; i < kSrgWPart; i += kB) P[i] = red[i];
+  for (int i = threadIdx.x; i < kSrgWPart; i += kB)
+    P[i] = ((reg[i] + reg[kSrgWPart + i]) + reg[2 * kSrgWPart + i]) + reg[3 * kSrgWPart + i];
 }
 
-// dw[i] = sum over the np block partials, i < kSrgWPart: 64 outputs per
-// block, four slices of the partials per output (each in a fixed order),
-// combined in a fixed order.
+// dw, db = sums over the np block partials of c32_bwd_weight_kernel: 32
+// partial entries per block, eight slices of the partials per entry (each
+// in a fixed order), combined in a fixed order.
 __global__ __launch_bounds__(kB) void wpart_sum_kernel(const float* __restrict__ part, int np,
                                                        float* __restrict__ dw,
                                                        float* __restrict__ db) {
-  const int o = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + o;
-  __shared__ double red[kWaves][64];
+  constexpr int kO = 32, kSl = kB / kO;
+  const int o = threadIdx.x % kO, sl = threadIdx.x / kO;
+  const int i = blockIdx.x * kO + o;
+  __shared__ double red[kSl][kO];
   double s0 = 0.0, s1 = 0.0;
   if (i < kSrgWPart) {
     int k = sl;
-    for (; k + kWaves < np; k += 2 * kWaves) {
+    for (; k + kSl < np; k += 2 * kSl) {
       s0 += part[size_t(k) * kSrgWPart + i];
-      s1 += part[size_t(k + kWaves) * kSrgWPart + i];
+      s1 += part[size_t(k + kSl) * kSrgWPart + i];
     }
     if (k < np) s0 += part[size_t(k) * kSrgWPart + i];
   }
@@ -755,11 +850,16 @@ __global__ __launch_bounds__(kB) void wpart_sum_kernel(const float* __restrict__
   __syncthreads();
   if (sl == 0 && i < kSrgWPart) {
     double s = 0.0;
-    for (int k = 0; k < kWaves; ++k) s += red[k][o];
-    if (i < kC * kC * 9)
-      dw[i] = float(s);
-    else
+    for (int k = 0; k < kSl; ++k) s += red[k][o];
+    if (i < kC * kC * 9) {
+      // fragment order [t][mb][nb][lane][j] to the master layout [co][ci][t]
+      const int j = i & 3, lane = (i >> 2) & 63, slot = i >> 8;
+      const int t = slot >> 2, mb = (slot >> 1) & 1, nb = slot & 1;
+      const int co = 16 * mb + 4 * (lane >> 4) + j, ci = 16 * nb + (lane & 15);
+      dw[(co * kC + ci) * 9 + t] = float(s);
+    } else {
       db[i - kC * kC * 9] = float(s);
+    }
   }
 }
 
@@ -1099,7 +1199,7 @@ void launch_srg_c32_bwd_weight(const uint16_t* dz, const uint16_t* a, float* par
   const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
   const int nb = np < kSrgWBlocks ? (np > 0 ? np : 1) : kSrgWBlocks;
   hipLaunchKernelGGL(c32_bwd_weight_kernel, dim3(nb), dim3(kB), 0, s, dz, a, part, B, H, W);
-  hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + 63) / 64), dim3(kB), 0, s, part, nb,
+  hipLaunchKernelGGL(wpart_sum_kernel, dim3((kSrgWPart + 31) / 32), dim3(kB), 0, s, part, nb,
                      dw, db);
 }
 
