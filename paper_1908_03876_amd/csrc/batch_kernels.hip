@@ -133,68 +133,36 @@ __device__ __forceinline__ TileNode<T> tile_of(const BatchArgs<T>& a, int t) {
   return r;
 }
 
-// Forward sweep over this block's tiles, two at a time: both tiles' loads
-// are issued before either collision, so one tile's loads are in flight
-// while the other is computed.
+// Forward and adjoint sweeps over this block's tiles, one tile at a time.
+// The memory parallelism comes from resident wavefronts: the FP32 kernels
+// are built for 8 wavefronts per SIMD (64 VGPRs), so that up to 8 blocks
+// per CU can stay resident.  Pairing two tiles per pass instead holds both
+// tiles' loads in registers and caps residency at 4 wavefronts per SIMD,
+// which measured slower over a gradient iteration.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     T* rec) {
-  const int nb = gridDim.x;
-  for (int t = blockIdx.x; t < a.ntiles; t += 2 * nb) {
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileNode<T> A = tile_of(a, t);
-    const bool hasB = t + nb < a.ntiles;
-    const TileNode<T> B = tile_of(a, hasB ? t + nb : t);
-    T fa[9], ga[9], ca = T(0), fb[9], gb[9], cb = T(0);
-    if (A.ok)
-      forward_gather<T, true, FIRST>(A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
-                                     a.u0 + A.fo, a.v0 + A.fo, a.ctrl + A.fo, fa, ga, ca);
-    if (hasB && B.ok)
-      forward_gather<T, true, FIRST>(B.g, B.n, a.coef[B.k], src ? src + 18 * B.fo : nullptr,
-                                     a.u0 + B.fo, a.v0 + B.fo, a.ctrl + B.fo, fb, gb, cb);
-    if (A.ok)
-      forward_collide_store<T, false>(A.g, A.n, a.coef[A.k], fa, ga, ca, dst + 18 * A.fo,
-                                      rec ? rec + 3 * A.fo : nullptr, 0u);
-    if (hasB && B.ok)
-      forward_collide_store<T, false>(B.g, B.n, a.coef[B.k], fb, gb, cb, dst + 18 * B.fo,
-                                      rec ? rec + 3 * B.fo : nullptr, 0u);
+    if (!A.ok) continue;
+    T fa[9], ga[9], ca = T(0);
+    forward_gather<T, true, FIRST>(A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
+                                   a.u0 + A.fo, a.v0 + A.fo, a.ctrl + A.fo, fa, ga, ca);
+    forward_collide_store<T, false>(A.g, A.n, a.coef[A.k], fa, ga, ca, dst + 18 * A.fo,
+                                    rec ? rec + 3 * A.fo : nullptr, 0u);
   }
 }
 
-// Adjoint sweep over this block's tiles, two at a time as the forward:
-// both tiles' gathers are issued before either update.  The two updates
-// run through one copy of the update code (a loop that is not unrolled),
-// so that a node computes the same bits whichever tile of a pair it falls
-// in, for every tile shape.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     const T* rec) {
-  const int nb = gridDim.x;
-  for (int t = blockIdx.x; t < a.ntiles; t += 2 * nb) {
-    TileNode<T> A = tile_of(a, t);
-    const bool hasB = t + nb < a.ntiles;
-    const TileNode<T> B = tile_of(a, hasB ? t + nb : t);
-    T ua[9], va[9], wa[9], ub[9], vb[9], wb[9];
-    if (A.ok)
-      adjoint_gather<T, true, false, FIRST>(A.g, A.n, src ? src + 18 * A.fo : nullptr,
-                                            a.seed_u + A.fo, nullptr, 0u, ua, va, wa);
-    if (hasB && B.ok)
-      adjoint_gather<T, true, false, FIRST>(B.g, B.n, src ? src + 18 * B.fo : nullptr,
-                                            a.seed_u + B.fo, nullptr, 0u, ub, vb, wb);
-#pragma unroll 1
-    for (int r = 0; r < (hasB ? 2 : 1); ++r) {
-      if (A.ok)
-        adjoint_update<T, true, false, FIRST, false>(
-            A.g, A.n, a.coef[A.k], ua, va, wa, dst ? dst + 18 * A.fo : nullptr, rec + 3 * A.fo,
-            a.gacc + A.fo, nullptr, nullptr, nullptr, false, 0u);
-      // the second pass updates tile B with the same code
-      A = B;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        ua[i] = ub[i];
-        va[i] = vb[i];
-        wa[i] = wb[i];
-      }
-    }
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const TileNode<T> A = tile_of(a, t);
+    if (!A.ok) continue;
+    adjoint_node<T, true, false, FIRST, false>(
+        A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
+        dst ? dst + 18 * A.fo : nullptr, a.seed_u + A.fo, nullptr, rec + 3 * A.fo,
+        a.gacc + A.fo, nullptr, nullptr);
   }
 }
 
@@ -225,8 +193,9 @@ __device__ void forward_steps(const BatchArgs<T>& a, int n0, int n1, int rec0,
   }
 }
 
+// FP32: at most 64 VGPRs (8 wavefronts per SIMD); FP64: 4 per SIMD.
 template <typename T>
-__global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_forward_kernel(BatchArgs<T> a) {
   bool alive = true;
   // record the last segment (it is the first one the adjoint needs)
   const int rec0 = a.mode > 0 ? (a.nseg - 1) * a.K : a.N;
@@ -234,7 +203,7 @@ __global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_adjoint_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_adjoint_kernel(BatchArgs<T> a) {
   bool alive = true;
   const unsigned nb = gridDim.x;
   const T* asrc = nullptr;

@@ -728,8 +728,7 @@ __device__ __forceinline__ void finalize_node(
 // adjoint_node = adjoint_gather + adjoint_update.
 //
 // Adjoint gather of node n (FIRST: the terminal seeds), the half of the
-// node update that loads; adjoint_update finishes it.  Split so that a
-// caller can issue the loads of two nodes before either update.
+// node update that loads; adjoint_update finishes it.
 template <typename T, bool PERIODIC, bool MASKED, bool FIRST, int VAR = kVarFirst>
 __device__ __forceinline__ void adjoint_gather(const Geometry& g, const NodeIdx& n,
                                                const T* __restrict__ src,
