@@ -985,11 +985,22 @@ double orc_cost(const OrcProblem* p, const double* uN, const double* ut,
 // gradient w.r.t. the control; the control enters Phi_u instead when
 // control_on_u), and optionally dJ/du0, dJ/dv0 through the equilibrium
 // initialisation.
-int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
-                const double* v0, const double* c, const double* seed_u,
-                const double* seed_v, double* g, double* du0, double* dv0) {
+//
+// g_theta (may be NULL; first source form, nsteps >= 1): the paper's
+// trapezoid form of the same gradient (JD-H-B) as a diagnostic.  Its
+// integrand at t_n is the control derivative of step n paired with the
+// adjoint that carries it, h_n = tau sum_i w_i nu_c,i^n (the terms the exact
+// gradient g sums over n = 0 .. N-1), and at t_N the terminal adjoint at the
+// node, h_N = tau sum_i w_i psi_c,i^N; with theta_0 = theta_N = 1/2,
+//   g_theta = g - h_0 / 2 + h_N / 2,
+// an O(1/N) departure from the exact transpose.
+static int adjoint_impl(const OrcProblem* p, int nsteps, const double* u0,
+                        const double* v0, const double* c, const double* seed_u,
+                        const double* seed_v, double* g, double* du0, double* dv0,
+                        double* g_theta) {
   Ops ops;
   if (!build_ops(*p, ops) || nsteps < 0) return -1;
+  if (g_theta && (p->source_term != 1 || nsteps < 1)) return -1;
   const size_t nc = size_t(p->nx) * p->ny;
   const int NS = nspec(*p);
   const size_t NQ = size_t(NS) * Q;
@@ -1004,6 +1015,15 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
   }
   for (size_t cell = 0; cell < nc; ++cell) g[cell] = 0.0;
   const int cs = p->control_on_u ? 0 : 1;
+  if (g_theta) {
+    // theta_N h_N from the terminal condition held in lam
+    for (size_t cell = 0; cell < nc; ++cell) {
+      double s = 0.0;
+      if (!(p->solid && p->solid[cell]))
+        for (int i = 0; i < Q; ++i) s += WGT[i] * lam[(cs * Q + i) * nc + cell];
+      g_theta[cell] = 0.5 * TAU * s;
+    }
+  }
   // source_term 2: the state of the scheme also holds F(t - tau), i.e.
   // Phi_u, Phi_v of the previous step; mu [2][ncell] is its adjoint (the
   // adjoint of the Phi stored by step n, read by step n + 1; 0 after the
@@ -1062,6 +1082,7 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
           double gc = 0.0;
           for (int i = 0; i < Q; ++i) gc += nl[cs * Q + i] * kphi * TAU * WGT[i];
           g[cell] += gc;
+          if (g_theta) g_theta[cell] += (n == 0 ? 0.5 : 1.0) * gc;  // theta_n h_n
           local_adjoint(*p, ops, loc, nl, out, nullptr, kphi);
         } else {
           // out_i = ... + tau w_i Phi + (tau/2) w_i (Phi - F_prev) (n >= 1):
@@ -1093,6 +1114,21 @@ int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0,
     if (dv0) dv0[cell] = b;
   }
   return 0;
+}
+
+int orc_adjoint(const OrcProblem* p, int nsteps, const double* u0, const double* v0,
+                const double* c, const double* seed_u, const double* seed_v, double* g,
+                double* du0, double* dv0) {
+  return adjoint_impl(p, nsteps, u0, v0, c, seed_u, seed_v, g, du0, dv0, nullptr);
+}
+
+// The diagnostic g_theta of adjoint_impl alone.
+int orc_adjoint_theta(const OrcProblem* p, int nsteps, const double* u0, const double* v0,
+                      const double* c, const double* seed_u, const double* seed_v,
+                      double* g_theta) {
+  std::vector<double> g(size_t(p->nx) * p->ny);
+  return adjoint_impl(p, nsteps, u0, v0, c, seed_u, seed_v, g.data(), nullptr, nullptr,
+                      g_theta);
 }
 
 // Sensitivity LBE (LIBEG-V), forward mode: directional derivative of

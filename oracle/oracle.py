@@ -70,6 +70,7 @@ def lib():
         L.orc_cost.argtypes = [P, dp, dp, dp, dp, dp]
         L.orc_cost.restype = ctypes.c_double
         L.orc_adjoint.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_adjoint_theta.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_tlm.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_cost_complex_step.argtypes = [P, ctypes.c_int, dp, dp, dp, dp,
                                             ctypes.c_double, dp, dp, dp]
@@ -230,6 +231,24 @@ def adjoint(p, seed_u, seed_v=None, nsteps=None, control=None, u0=None, v0=None,
     _check(lib().orc_adjoint(pr.ptr, n, _dp(u0), _dp(v0), _dp(c), _dp(_f64(seed_u)),
                              _dp(_f64(seed_v)), _dp(g), _dp(du0), _dp(dv0)))
     return g, du0, dv0
+
+
+def theta_gradient(p, seed_u, seed_v=None, nsteps=None, control=None, u0=None, v0=None,
+                   control_on_u=False):
+    """The paper's trapezoid-in-time form of the gradient (JD-H-B), a
+    diagnostic beside the exact transpose that adjoint() returns: the
+    integrand at t_n is step n's term of the exact gradient, h_n, and at t_N
+    the terminal adjoint's tau sum_i w_i psi_c,i^N; theta_0 = theta_N = 1/2,
+    so g_theta = g - h_0/2 + h_N/2 (first source form, nsteps >= 1)."""
+    n = p.nsteps if nsteps is None else nsteps
+    pr = _Prob(p, control_on_u)
+    u0 = _f64(p.u0 if u0 is None else u0)
+    v0 = _f64(p.v0 if v0 is None else v0)
+    c = _f64(p.control if control is None else control)
+    gt = np.zeros((p.ny, p.nx))
+    _check(lib().orc_adjoint_theta(pr.ptr, n, _dp(u0), _dp(v0), _dp(c), _dp(_f64(seed_u)),
+                                   _dp(_f64(seed_v)), _dp(gt)))
+    return gt
 
 
 def tlm(p, dc=None, du0=None, dv0=None, nsteps=None, control=None,

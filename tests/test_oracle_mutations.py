@@ -89,6 +89,11 @@ MUTANTS = [
     ("checkpointed trajectory: previous kinetics not restored",
      "std::vector<double> f = ckpt_f_[s], F = ckpt_F_[s];",
      "std::vector<double> f = ckpt_f_[s], F(2 * nc_, 0.0);"),
+    ("trapezoid gradient: full weight at the first step",
+     "if (g_theta) g_theta[cell] += (n == 0 ? 0.5 : 1.0) * gc;",
+     "if (g_theta) g_theta[cell] += 1.0 * gc;"),
+    ("trapezoid gradient: terminal level dropped",
+     "g_theta[cell] = 0.5 * TAU * s;", "g_theta[cell] = 0.0 * s;"),
     ("third species: w not streamed",
      "for (int s = 0; s < NS; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming",
      "for (int s = 0; s < 2; ++s)\n        for (int i = 0; i < Q; ++i) {\n          // Streaming"),

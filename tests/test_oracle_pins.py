@@ -223,6 +223,50 @@ def test_single_site_closed_form():
     assert abs(g["grad"][0, 0] - (dc + 0.01 * c)) < 1e-14
 
 
+# ------------------------------------ trapezoid form of the gradient (JD-H-B)
+
+def _stationary(n=6):
+    """Uniform periodic state at the kinetics' fixed point (u = 1, a_uv u =
+    b_v v, no control): every step maps the state to itself, so the adjoint
+    step is one fixed linear map A and streaming acts as the identity."""
+    return I.Problem(nx=n, ny=n, nsteps=9, periodic=True, solid=None,
+                     Du=np.array([[0.3, 0.1], [0.1, 0.2]]), Dv=0.5 * np.eye(2), chi=0.8,
+                     Cchi=np.eye(2), r_u=0.7, a_uv=0.3, b_v=0.45, alpha=0.01,
+                     u0=np.ones((n, n)), v0=np.full((n, n), 0.3 / 0.45),
+                     control=np.zeros((n, n)), u_target=np.full((n, n), 0.9))
+
+
+@pytest.mark.parametrize("N", [1, 5, 9])
+def test_theta_form_stationary_identity(N):
+    """With psi^n = A^(N-n) psi^N the exact gradient is g(N) = tau sum_{k<N}
+    s(A^k seed) (s = sum_i w_i psi_v,i), so its first-step term is
+    h_0 = g(N) - g(N-1) and the terminal term is h_N = tau s(seed) = tau
+    seed_v; the trapezoid weights theta_0 = theta_N = 1/2 then give
+    g_theta(N) = (g(N) + g(N-1))/2 + tau seed_v / 2 (g(0) = 0)."""
+    p = _stationary()
+    su, sv = np.full((6, 6), 0.8), np.full((6, 6), -0.3)
+    gt = O.theta_gradient(p, su, sv, nsteps=N)
+    g = O.adjoint(p, su, sv, nsteps=N)[0]
+    gm = O.adjoint(p, su, sv, nsteps=N - 1)[0] if N > 1 else np.zeros_like(g)
+    np.testing.assert_allclose(gt, 0.5 * (g + gm) + 0.5 * (-0.3), rtol=0, atol=1e-14)
+    if N > 1:  # at N = 1, h_0 = h_N and the forms agree
+        assert np.abs(gt - g).max() > 1e-3
+
+
+def test_theta_form_departs_by_first_and_last_terms():
+    """On a generic problem the trapezoid form differs from the exact
+    transpose by (h_N - h_0)/2, one step's share: a few percent at N = 10,
+    shrinking as N grows (here the adjoint decays, so faster than 1/N)."""
+    gaps = []
+    for N in (10, 20):
+        q = I.tiny(L=8, nsteps=N, seed=5)
+        seed = O.forward(q)["uN"] - q.u_target
+        g = O.adjoint(q, seed, None, nsteps=N)[0]
+        gt = O.theta_gradient(q, seed, None, nsteps=N)
+        gaps.append(np.linalg.norm(gt - g) / np.linalg.norm(g))
+    assert 1e-3 < gaps[0] < 0.2 and gaps[1] < 0.5 * gaps[0]
+
+
 # -------------------------------------------------- adjoint / gradient pins
 
 def _cases():
