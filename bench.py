@@ -162,7 +162,7 @@ def bench_batched(args):
     K = max(1, int(round((N * 6) ** 0.5)))
     log(f"[bench] batched: 96 instances, {sites} sites, N={N}, ckpt every {K}")
     b = Batch(ps, dtype=torch.float32, ckpt_every=K)
-    best = b.tune(steps=10)
+    best = b.tune(steps=30)
     log(f"[bench] autotuner: {best}")
     for w in range(max(args.warmup, 1)):
         b.iterate(use_graph=True)

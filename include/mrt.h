@@ -384,7 +384,8 @@ int mrt_batch_set_tiles(mrt_batch* b, const mrt_batch_tiles* tiles);
 int mrt_batch_get_tiles(mrt_batch* b, mrt_batch_tiles* tiles /* host */);
 
 /* Autotuner: times a `steps`-step forward pass for every tile width and
- * power-of-two residency, keeps the fastest and returns it.  Synchronises
+ * power-of-two residency (the fastest of three passes after a warm-up),
+ * keeps the fastest shape and returns it.  Synchronises
  * `stream`; overwrites the forward work buffers (not the fields). */
 int mrt_batch_tune(mrt_batch* b, int32_t steps, mrt_batch_tiles* best /* host */,
                    void* stream);
