@@ -547,6 +547,43 @@ def traffic_rate(traffic, avg_ms):
     return {"traffic_GBps": round(gbs, 1), "traffic_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def stream_ceiling(reads: int, writes: int, n: int, dev):
+    """Bandwidth of the library's streaming probe (mrt_stream_probe) with a
+    step kernel's access mix, `reads` + `writes` FP32 planes of n nodes with
+    the kernels' non-temporal loads and stores, timed with events on the
+    stream it runs on (mean of 20 launches after 3): the practical ceiling
+    of that mix on this GPU.  Runs after the timed region."""
+    import torch
+    from paper_1908_03876_amd import abi
+    inp = torch.ones(reads * n, dtype=torch.float32, device=dev)
+    out = torch.empty(writes * n, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        abi.mrt_stream_probe(reads, writes, inp, out, n)
+    k = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        abi.mrt_stream_probe(reads, writes, inp, out, n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    del inp, out
+    torch.cuda.empty_cache()
+    gbs = 4.0 * n * (reads + writes) / (ms / 1e3) / 1e9
+    return {"GBps": round(gbs, 1), "avg_ms": round(ms, 5),
+            "mix": f"{reads} read + {writes} write FP32 planes of {n} nodes, non-temporal"}
+
+
+def add_stream_ceiling(roof: dict, reads: int, writes: int, n: int, dev):
+    """The probe's bandwidth beside the roofline, and the dominant kernel's
+    algorithmic (and counted) bandwidth as fractions of it."""
+    c = stream_ceiling(reads, writes, n, dev)
+    roof["stream_ceiling"] = c
+    roof["frac_of_stream_ceiling"] = round(roof["achieved"] / c["GBps"], 4)
+    if roof.get("traffic_GBps"):
+        roof["traffic_frac_of_stream_ceiling"] = round(roof["traffic_GBps"] / c["GBps"], 4)
+
+
 def copy_calibration(out: dict, dev):
     """A plain 1 GiB device copy: the reference of the byte counters, and the
     bandwidth the runtime's own copy reaches (HIP events, best of 3)."""
@@ -672,6 +709,8 @@ def bench_d3q19(args):
                                  "GBps": round(launch_bytes[k] / (kern[k][1] / 1e3) / 1e9, 1)}
                              for k in kern if k != dom and kern[k][0] > 0}}
     roof.update(traffic_rate(traffic, avg_ms))
+    mix = (44, 40) if dom == "amrt3_adjoint_step" else (39, 42)
+    add_stream_ceiling(roof, mix[0], mix[1], L * L * L, dev)
     out = {
         "metric": "coupled MRT+AMRT MLUPS (gradient iteration: forward + adjoint), "
                   "HBM GB/s fraction; s per gradient iteration",
@@ -844,6 +883,9 @@ def main():
             "algorithmic_bytes_per_fluid_node": b_adj if dom == "amrt_adjoint_step" else b_fwd,
             "link_word_bytes_per_launch": 2 * dp.nx * dp.ny}
     roof.update(traffic_rate(traffic, avg_ms))
+    if args.source_term == 1 and args.species == 2:
+        mix = (23, 20) if dom == "amrt_adjoint_step" else (19, 21)
+        add_stream_ceiling(roof, mix[0], mix[1], dp.nx * dp.ny, dev)
     out = {
         "metric": "coupled MRT+AMRT MLUPS (gradient iteration: forward + adjoint), "
                   "HBM GB/s fraction; s per gradient iteration",

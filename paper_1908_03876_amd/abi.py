@@ -103,7 +103,8 @@ EXPORTS = ["mrt_validate", "mrt_tape_bytes", "mrt_tape_create",
            "mrt_tape_destroy", "mrt_tape_query", "mrt_forward", "amrt_adjoint",
            "cost_gradient", "cost_gradient_noalloc", "gd_step", "mrt_last_error",
            "mrt_timing_enable",
-           "mrt_timing_reset", "mrt_timing_read", "mrt_tlm", "mrt_dot", "mrt_axpby",
+           "mrt_timing_reset", "mrt_timing_read", "mrt_stream_probe", "mrt_tlm", "mrt_dot",
+           "mrt_axpby",
            "mrt_cadjoint", "mrt_lma_step", "mrt_cg_direction",
            "mrt_batch_create", "mrt_batch_destroy", "mrt_batch_field",
            "mrt_batch_copy", "mrt_batch_set_tiles", "mrt_batch_get_tiles",
@@ -154,6 +155,8 @@ def _load():
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
     L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
+    L.mrt_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     T = ctypes.POINTER(mrt_batch_tiles)
     L.mrt_batch_create.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
                                    ctypes.POINTER(vp)]
@@ -354,6 +357,11 @@ def mrt_timing_read(kind: int):
     n = ctypes.c_int64()
     _check(lib.mrt_timing_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def mrt_stream_probe(reads: int, writes: int, inp, out, n: int, stream=None) -> None:
+    _check(lib.mrt_stream_probe(int(reads), int(writes), _ptr(inp), _ptr(out), int(n),
+                                _stream(stream)))
 
 
 # ------------------------------------------------------------- batched form

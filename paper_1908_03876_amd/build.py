@@ -19,6 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmrt.so")
 
 SOURCES = ["mrt_kernels.hip", "batch_kernels.hip", "srg_kernels.hip", "mrt3_kernels.hip",
+           "probe_kernels.hip",
            "mrt_abi.cpp", "mrt3_abi.cpp",
            "mrt_batch.cpp", "mrt_srg.cpp"]
 

@@ -17,6 +17,7 @@
 
 #include "mrt_host.h"
 #include "mrt_internal.h"
+#include "probe_internal.h"
 
 namespace {
 
@@ -1246,6 +1247,17 @@ int mrt_timing_reset(void) {
     t.launches[k] = 0;
   }
   return MRT_OK;
+}
+
+int mrt_stream_probe(int32_t reads, int32_t writes, const float* in, float* out, int64_t n,
+                     void* stream) {
+  if (!in || !out || n < 0) return fail(MRT_EINVAL, "NULL buffer or negative size");
+  if (n == 0) return MRT_OK;
+  if (!mrt::launch_stream_probe(reads, writes, in, out, size_t(n),
+                                static_cast<hipStream_t>(stream)))
+    return fail(MRT_EINVAL, "stream probe: mix not built");
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MRT_OK : fail(MRT_EHIP, "%s", hipGetErrorString(e));
 }
 
 int mrt_timing_read(int32_t kind, double* ms, int64_t* launches) {

@@ -1,0 +1,12 @@
+// Streaming probe of the step kernels' access mixes (probe_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace mrt {
+// `reads` + `writes` planes of n floats; false for a mix that is not built
+// (see mrt_stream_probe in include/mrt.h).
+bool launch_stream_probe(int reads, int writes, const float* in, float* out, size_t n,
+                         hipStream_t s);
+}  // namespace mrt
