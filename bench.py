@@ -192,6 +192,20 @@ def bench_batched(args):
            "hbm_frac": round(bytes_it / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
            "J_sum_history": [round(x, 4) for x in js]}
     b.close()
+    # the streaming probe with each launch's access mix at this size: the
+    # iteration's ceiling is its bytes over the sum of each part's bytes at
+    # its own ceiling
+    dev = torch.device("cuda:0")
+    parts = [(19, 18, N * fwd_b), (19, 21, N * rec_b), (23, 20, N * adj_b)]
+    t_ideal = 0.0
+    ceil = {}
+    for r, w, nb in parts:
+        c = stream_ceiling(r, w, sites, dev)
+        ceil[f"{r}+{w}"] = c["GBps"]
+        t_ideal += sites * nb / (c["GBps"] * 1e9)
+    out["stream_ceiling_GBps"] = ceil
+    out["iteration_stream_ceiling_GBps"] = round(bytes_it / t_ideal / 1e9, 1)
+    out["frac_of_stream_ceiling"] = round(t_ideal / (ms / 1e3), 4)
     print(json.dumps(out), flush=True)
 
 
