@@ -122,10 +122,25 @@ struct TileNode {
   int k;
 };
 
+// The tile table and the per-instance coefficients are read-only for the
+// whole launch and are indexed by wave-uniform values, so they are read
+// through the constant address space: scalar loads into SGPRs, instead of
+// a dozen vector loads per wavefront and tile that the compiler would issue
+// for a pointer held in the by-value argument struct.
+template <typename U>
+__device__ __forceinline__ U uniform_load(const U* p) {
+#if __HIP_DEVICE_COMPILE__
+  return *reinterpret_cast<const __attribute__((address_space(4))) U*>(
+      reinterpret_cast<uintptr_t>(p));
+#else
+  return *p;  // the host pass only parses device code
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ TileNode<T> tile_of(const BatchArgs<T>& a, int t) {
   TileNode<T> r;
-  const BatchTile tl = a.tiles[t];
+  const BatchTile tl = uniform_load(a.tiles + t);
   r.k = __builtin_amdgcn_readfirstlane(tl.k);
   r.g = inst_geom(__builtin_amdgcn_readfirstlane(tl.L));
   r.ok = tile_node(tl, a.tile_w, r.g, r.n);
@@ -133,22 +148,21 @@ __device__ __forceinline__ TileNode<T> tile_of(const BatchArgs<T>& a, int t) {
   return r;
 }
 
-// Forward and adjoint sweeps over this block's tiles, one tile at a time.
-// The memory parallelism comes from resident wavefronts: the FP32 kernels
-// are built for 8 wavefronts per SIMD (64 VGPRs), so that up to 8 blocks
-// per CU can stay resident.  Pairing two tiles per pass instead holds both
-// tiles' loads in registers and caps residency at 4 wavefronts per SIMD,
-// which measured slower over a gradient iteration.
+// Forward and adjoint sweeps over this block's tiles, one tile at a time,
+// each tile's descriptor and coefficients in SGPRs.  Holding two tiles'
+// loads in registers (paired, or the next tile's gathers issued before the
+// current collision) measured slower over a gradient iteration.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void forward_sweep_tiles(const BatchArgs<T>& a, const T* src, T* dst,
                                     T* rec) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileNode<T> A = tile_of(a, t);
     if (!A.ok) continue;
+    const ModelCoef<T> m = uniform_load(a.coef + A.k);
     T fa[9], ga[9], ca = T(0);
-    forward_gather<T, true, FIRST>(A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
+    forward_gather<T, true, FIRST>(A.g, A.n, m, src ? src + 18 * A.fo : nullptr,
                                    a.u0 + A.fo, a.v0 + A.fo, a.ctrl + A.fo, fa, ga, ca);
-    forward_collide_store<T, false>(A.g, A.n, a.coef[A.k], fa, ga, ca, dst + 18 * A.fo,
+    forward_collide_store<T, false>(A.g, A.n, m, fa, ga, ca, dst + 18 * A.fo,
                                     rec ? rec + 3 * A.fo : nullptr, 0u);
   }
 }
@@ -159,8 +173,9 @@ __device__ __forceinline__ void adjoint_sweep_tiles(const BatchArgs<T>& a, const
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileNode<T> A = tile_of(a, t);
     if (!A.ok) continue;
+    const ModelCoef<T> m = uniform_load(a.coef + A.k);
     adjoint_node<T, true, false, FIRST, false>(
-        A.g, A.n, a.coef[A.k], src ? src + 18 * A.fo : nullptr,
+        A.g, A.n, m, src ? src + 18 * A.fo : nullptr,
         dst ? dst + 18 * A.fo : nullptr, a.seed_u + A.fo, nullptr, rec + 3 * A.fo,
         a.gacc + A.fo, nullptr, nullptr);
   }
@@ -193,9 +208,8 @@ __device__ void forward_steps(const BatchArgs<T>& a, int n0, int n1, int rec0,
   }
 }
 
-// FP32: at most 64 VGPRs (8 wavefronts per SIMD); FP64: 4 per SIMD.
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_forward_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
   bool alive = true;
   // record the last segment (it is the first one the adjoint needs)
   const int rec0 = a.mode > 0 ? (a.nseg - 1) * a.K : a.N;
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_forward_ker
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_adjoint_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256) void batch_adjoint_kernel(BatchArgs<T> a) {
   bool alive = true;
   const unsigned nb = gridDim.x;
   const T* asrc = nullptr;
