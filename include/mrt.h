@@ -423,7 +423,9 @@ int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,
 
 /* Forward solves only (no record, no adjoint) of every instance from its
  * current u0, v0, control: writes the MRT_FIELD_UN / MRT_FIELD_VN fields.
- * One persistent launch plus the terminal streaming.  Asynchronous. */
+ * One persistent launch plus the terminal streaming.  Synchronises
+ * `stream`; MRT_EHIP if a grid barrier timed out (the outputs are then not
+ * valid). */
 int mrt_batch_forward(mrt_batch* b, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -66,6 +66,11 @@ class Batch:
     def iterate(self, zeta: float = 0.0, use_graph: bool = True) -> None:
         abi.mrt_batch_iteration(self.handle, zeta, use_graph)
 
+    def forward(self) -> None:
+        """Forward solves only (a batch created with ckpt_every < 0):
+        writes uN and vN of every instance; raises on a barrier time-out."""
+        abi.mrt_batch_forward(self.handle)
+
     def scalars(self):
         return abi.mrt_batch_scalars(self.handle, self.count)
 

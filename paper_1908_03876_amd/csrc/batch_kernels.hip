@@ -22,15 +22,19 @@ namespace {
 
 using namespace dev;
 
-// Grid barrier of the persistent kernels.  __syncthreads() has completed
-// the block's stores into its XCD's L2 before thread 0 arrives; the last
-// arriver of each XCD group then releases that L2 once (agent-scope
-// fence), the waiting blocks poll with plain atomic loads, and each block
-// acquires once after the generation has moved on.  A wall-clock limit
-// turns a barrier that never completes into a sticky abort flag.
+// Grid barrier of the persistent kernels.  Every wavefront first waits
+// until its own stores have completed into its XCD's L2 (a work-group
+// barrier alone does not wait for them: it orders memory only within the
+// work-group, whose wavefronts share one CU), so that the block's stores
+// are all in L2 before thread 0 arrives; the last arriver of each XCD
+// group then releases that L2 once (agent-scope fence), the waiting blocks
+// poll with plain atomic loads, and each block acquires once after the
+// generation has moved on.  A wall-clock limit turns a barrier that never
+// completes into a sticky abort flag.
 __device__ __forceinline__ bool grid_sync(BarrierState* bs, unsigned nblocks,
                                           unsigned long long timeout) {
   __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0)
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
@@ -208,8 +212,15 @@ __device__ void forward_steps(const BatchArgs<T>& a, int n0, int n1, int rec0,
   }
 }
 
+// The persistent grids are sized from the runtime's occupancy query, and
+// every work-group must be resident for the grid barrier to complete.  The
+// declared minimum of wavefronts per SIMD (8 for FP32, 4 for FP64) keeps
+// the compiler's vector AND scalar register allocation within what that
+// occupancy allows; without it the scalar-loaded descriptors and
+// coefficients took 106 SGPRs, which leaves room for 7 wavefronts per SIMD
+// where the vector registers alone allow 8.
 template <typename T>
-__global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_forward_kernel(BatchArgs<T> a) {
   bool alive = true;
   // record the last segment (it is the first one the adjoint needs)
   const int rec0 = a.mode > 0 ? (a.nseg - 1) * a.K : a.N;
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(256) void batch_forward_kernel(BatchArgs<T> a) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_adjoint_kernel(BatchArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 8 : 4) void batch_adjoint_kernel(BatchArgs<T> a) {
   bool alive = true;
   const unsigned nb = gridDim.x;
   const T* asrc = nullptr;

@@ -515,7 +515,16 @@ int mrt_batch_forward(mrt_batch* b, void* stream) {
     mrt::launch_batch_forward<float>(a, bf, s);
     mrt::launch_batch_finalize<float>(a, static_cast<const float*>(b->buf[(b->N - 1) & 1]), bs, s);
   }
-  return launch_error();
+  int rc = launch_error();
+  if (rc) return rc;
+  // a barrier that timed out leaves u(T) unwritten: report it here, since
+  // no later call of the forward-only path reads the flag
+  unsigned* ab =
+      reinterpret_cast<unsigned*>(b->host + 2 * size_t(b->count) * mrt::kBatchSlots);
+  HIP_OK(hipMemcpyAsync(ab, &b->barrier->abort.v, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (*ab) return err(MRT_EHIP, "grid barrier timed out: work-groups were not all resident");
+  return MRT_OK;
 }
 
 int mrt_batch_scalars(mrt_batch* b, mrt_scalars* out, double* zeta_used,

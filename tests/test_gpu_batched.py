@@ -180,3 +180,42 @@ def test_batch_barrier_timeout_is_reported():
         b.scalars()
     assert e.value.code == abi.MRT_EHIP
     b.close()
+
+
+def _forward_batch(n=160, L=64, nsteps=12, seed=45):
+    ps = I.uneven_batch(seed=seed, n=n, nsteps=nsteps, sizes=(L,))
+    return [I.with_control_bump(p, seed=300 + k, amp=3.0) for k, p in enumerate(ps)]
+
+
+def test_batch_forward_only_at_full_occupancy_matches_oracle():
+    """The forward-only path launches as many work-groups as the occupancy
+    query allows (160 instances of 64^2 give 2560 tiles, more than 256 CUs x
+    8 resident work-groups), so every work-group must really be resident for
+    the grid barrier to complete; u^N of sampled instances equals the
+    oracle's forward (FP32 1e-5) and differs between instances."""
+    import torch
+    ps = _forward_batch()
+    b = _batch(ps, torch.float32, ckpt_every=-1)
+    t = b.tiles()
+    assert t["tile_w"] * (256 // t["tile_w"]) == 256
+    b.forward()
+    outs = {k: b.get(k, "uN").double().cpu().numpy() for k in (0, 1, 77, len(ps) - 1)}
+    for k, uN in outs.items():
+        ref = O.forward(ps[k])["uN"]
+        assert rel_l2(uN, ref) <= 1e-5, k
+    assert np.abs(outs[0] - outs[1]).max() > 1e-3
+    b.close()
+
+
+def test_batch_forward_timeout_is_reported():
+    """The forward-only path reports a grid-barrier time-out (forced from the
+    host with a zero wait limit) instead of returning stale outputs."""
+    import torch
+    from paper_1908_03876_amd import abi
+    ps = _forward_batch(n=4, nsteps=6)
+    b = _batch(ps, torch.float32, ckpt_every=-1)
+    b.set_timeout(0.0)
+    with pytest.raises(abi.MrtError) as e:
+        b.forward()
+    assert e.value.code == abi.MRT_EHIP
+    b.close()
