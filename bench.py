@@ -564,27 +564,36 @@ def traffic_rate(traffic, avg_ms):
 def stream_ceiling(reads: int, writes: int, n: int, dev):
     """Bandwidth of the library's streaming probe (mrt_stream_probe) with a
     step kernel's access mix, `reads` + `writes` FP32 planes of n nodes with
-    the kernels' non-temporal loads and stores, timed with events on the
-    stream it runs on (mean of 20 launches after 3): the practical ceiling
-    of that mix on this GPU.  Runs after the timed region."""
+    the kernels' non-temporal loads and stores, in both tile orders (launch
+    order and XCD-banded), each timed with events on the stream it runs on
+    (mean of 20 launches after 3).  The better order's bandwidth is the
+    practical ceiling of that mix on this GPU.  Runs after the timed
+    region."""
     import torch
     from paper_1908_03876_amd import abi
     inp = torch.ones(reads * n, dtype=torch.float32, device=dev)
     out = torch.empty(writes * n, dtype=torch.float32, device=dev)
-    for _ in range(3):
-        abi.mrt_stream_probe(reads, writes, inp, out, n)
-    k = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(k):
-        abi.mrt_stream_probe(reads, writes, inp, out, n)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / k
+    per = {}
+    for order in (0, 1):
+        for _ in range(3):
+            abi.mrt_stream_probe(reads, writes, inp, out, n, order=order)
+        k = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            abi.mrt_stream_probe(reads, writes, inp, out, n, order=order)
+        e1.record()
+        torch.cuda.synchronize()
+        per[order] = e0.elapsed_time(e1) / k
     del inp, out
     torch.cuda.empty_cache()
+    best = min(per, key=per.get)
+    ms = per[best]
     gbs = 4.0 * n * (reads + writes) / (ms / 1e3) / 1e9
     return {"GBps": round(gbs, 1), "avg_ms": round(ms, 5),
+            "order": "XCD-banded" if best == 1 else "launch order",
+            "GBps_by_order": {"launch": round(4.0 * n * (reads + writes) / per[0] / 1e6, 1),
+                              "banded": round(4.0 * n * (reads + writes) / per[1] / 1e6, 1)},
             "mix": f"{reads} read + {writes} write FP32 planes of {n} nodes, non-temporal"}
 
 

@@ -331,15 +331,19 @@ int mrt_timing_read(int32_t kind, double* ms /* host */,
 
 /* Streaming probe, for measurement: out[w][i] = sum_r in[r][i] + w over
  * `reads` planes of in and `writes` planes of out, each [n] FP32, with the
- * non-temporal loads and stores of the step kernels.  It reproduces a step
- * kernel's HBM access mix without its arithmetic, so its bandwidth is the
- * practical ceiling for that mix.  Built mixes (reads, writes): (19, 18),
- * (19, 21), (23, 20) (the D2Q9 forward without and with the record, and
- * the AMRT step), (39, 42), (44, 40) (the D3Q19 forward and AMRT step);
- * others return MRT_EINVAL.  Caller-owned device buffers of reads * n and
- * writes * n floats.  Asynchronous on `stream`. */
-int mrt_stream_probe(int32_t reads, int32_t writes, const float* in, float* out, int64_t n,
-                     void* stream);
+ * non-temporal loads and stores of the step kernels, over 256-element
+ * tiles taken in launch order (order = 0) or XCD-banded as in the
+ * single-lattice step kernels (order = 1: XCD k takes a contiguous range).
+ * It reproduces a step kernel's HBM access mix without its arithmetic, so
+ * the better of the two orders' bandwidths is the practical ceiling for
+ * that mix.  Built mixes (reads, writes): (19, 18), (19, 21), (23, 20)
+ * (the D2Q9 forward without and with the record, and the AMRT step),
+ * (39, 42), (44, 40) (the D3Q19 forward and AMRT step); others, another
+ * order, and n of 2^31 or more 256-element tiles, return MRT_EINVAL.
+ * Caller-owned device buffers of reads * n and writes * n floats.
+ * Asynchronous on `stream`. */
+int mrt_stream_probe(int32_t reads, int32_t writes, int32_t order, const float* in, float* out,
+                     int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent control problems of uneven size advanced

@@ -155,8 +155,9 @@ def _load():
     L.mrt_timing_enable.argtypes = [ctypes.c_int32]
     L.mrt_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
-    L.mrt_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    L.mrt_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_void_p]
     T = ctypes.POINTER(mrt_batch_tiles)
     L.mrt_batch_create.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
                                    ctypes.POINTER(vp)]
@@ -359,9 +360,10 @@ def mrt_timing_read(kind: int):
     return ms.value, n.value
 
 
-def mrt_stream_probe(reads: int, writes: int, inp, out, n: int, stream=None) -> None:
-    _check(lib.mrt_stream_probe(int(reads), int(writes), _ptr(inp), _ptr(out), int(n),
-                                _stream(stream)))
+def mrt_stream_probe(reads: int, writes: int, inp, out, n: int, order: int = 1,
+                     stream=None) -> None:
+    _check(lib.mrt_stream_probe(int(reads), int(writes), int(order), _ptr(inp), _ptr(out),
+                                int(n), _stream(stream)))
 
 
 # ------------------------------------------------------------- batched form

@@ -5,8 +5,8 @@
 #include <cstddef>
 
 namespace mrt {
-// `reads` + `writes` planes of n floats; false for a mix that is not built
-// (see mrt_stream_probe in include/mrt.h).
-bool launch_stream_probe(int reads, int writes, const float* in, float* out, size_t n,
-                         hipStream_t s);
+// `reads` + `writes` planes of n floats, in launch order or XCD-banded;
+// false for a mix that is not built (see mrt_stream_probe in include/mrt.h).
+bool launch_stream_probe(int reads, int writes, bool banded, const float* in, float* out,
+                         size_t n, hipStream_t s);
 }  // namespace mrt
