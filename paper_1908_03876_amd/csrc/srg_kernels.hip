@@ -16,8 +16,11 @@
 // The two 32 -> 32 layers are implicit GEMMs on the matrix cores
 // (v_mfma_f32_16x16x32_bf16): per tap t the 32 x 32 weight matrix W_t
 // multiplies the 32 channels of the 16 pixels of a tile, giving an output
-// of channels x pixels whose lanes hold 4 consecutive channels of one pixel
-// (8-byte channels-last stores).  A block keeps the 18 weight fragments
+// of channels x pixels.  In the forward the rows of the two channel blocks
+// are interleaved so that a lane holds 8 consecutive channels of one pixel
+// and the 4 lanes of a pixel write its 64 bytes with one 16-byte store each:
+// a store instruction that leaves part of a 64-byte chunk to another one
+// costs a read-modify-write in memory.  A block keeps the 18 weight fragments
 // (9 taps x 2 channel blocks) in LDS, read per MFMA, and walks many tiles;
 // the forward stages its input patches in LDS as well.
 // The one-channel first and last layers stay on the vector ALU.
@@ -470,9 +473,14 @@ __global__ __launch_bounds__(kB) void thin_wgrad_finish_kernel(const double* __r
 // ------------------------------------------- 32 -> 32 layers on MFMA
 
 // Weight fragments for the matrix cores, from the FP32 masters [32][32][9]:
-//   fwd[t][mb][lane][j] = W[co = 16 mb + lane % 16][ci = 8 (lane / 16) + j][t]
+//   fwd[t][mb][lane][j] = W[co = fwd_row(mb, lane % 16)][ci = 8 (lane / 16) + j][t]
 //   bwd[t][mb][lane][j] = W[co = 8 (lane / 16) + j][ci = 16 mb + lane % 16][t]
-// (A operands of D = W_t X and D = W_t^T G).
+// (A operands of D = W_t X and D = W_t^T G).  Row m of forward channel
+// block mb is channel 8 (m / 4) + 4 mb + m % 4, so that the accumulator
+// lanes (q, pixel) of blocks 0 and 1 hold channels 8q..8q+3 and
+// 8q+4..8q+7.
+__device__ __forceinline__ int fwd_row(int mb, int m) { return 8 * (m >> 2) + 4 * mb + (m & 3); }
+
 __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restrict__ w,
                                                           uint16_t* __restrict__ fwd,
                                                           uint16_t* __restrict__ bwd) {
@@ -480,7 +488,7 @@ __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restric
   if (i >= 9 * 2 * 64 * 8) return;
   const int j = i & 7, lane = (i >> 3) & 63, mb = (i >> 9) & 1, t = i >> 10;
   const int a = 16 * mb + (lane & 15), b = 8 * (lane >> 4) + j;
-  fwd[i] = f32_to_bf16(w[(a * kC + b) * 9 + t]);
+  fwd[i] = f32_to_bf16(w[(fwd_row(mb, lane & 15) * kC + b) * 9 + t]);
   bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
 }
 
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[mb][j] = bias[16 * mb + 4 * q + j];
+    for (int j = 0; j < 4; ++j) bv[mb][j] = bias[8 * q + 4 * mb + j];
   const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
   const int npatch = B * pr * pc;
   // column offsets (bytes) of this lane's three x taps in a staged row
@@ -554,14 +562,14 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
     for (int j = 0; j < kPR; ++j) {
       const int y = y0 + j;
       if (y < H && px < W) {
-        uint16_t* o = out + pix(b * H + y, W, px) * kC + 4 * q;
-        u32x2 r0, r1;
-        r0[0] = pack_bf16(tanh_fast(acc[j][0][0]), tanh_fast(acc[j][0][1]));
-        r0[1] = pack_bf16(tanh_fast(acc[j][0][2]), tanh_fast(acc[j][0][3]));
-        r1[0] = pack_bf16(tanh_fast(acc[j][1][0]), tanh_fast(acc[j][1][1]));
-        r1[1] = pack_bf16(tanh_fast(acc[j][1][2]), tanh_fast(acc[j][1][3]));
-        *reinterpret_cast<u32x2*>(o) = r0;
-        *reinterpret_cast<u32x2*>(o + 16) = r1;
+        // channels 8q..8q+7 of the pixel
+        uint16_t* o = out + pix(b * H + y, W, px) * kC + 8 * q;
+        u32x4 r;
+        r[0] = pack_bf16(tanh_fast(acc[j][0][0]), tanh_fast(acc[j][0][1]));
+        r[1] = pack_bf16(tanh_fast(acc[j][0][2]), tanh_fast(acc[j][0][3]));
+        r[2] = pack_bf16(tanh_fast(acc[j][1][0]), tanh_fast(acc[j][1][1]));
+        r[3] = pack_bf16(tanh_fast(acc[j][1][2]), tanh_fast(acc[j][1][3]));
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4*>(o));
       }
     }
   }
@@ -938,8 +946,8 @@ __global__ __launch_bounds__(kB) void adam_kernel(float* __restrict__ w, uint16_
 // One Adam step for every parameter of the network in one launch: thread i
 // finds its group in the table and updates the FP32 master, its moments and
 // its compute copy -- the BF16 weight of a one-channel layer, or, for a
-// 32 x 32 layer, its two MFMA fragment slots (forward: co = 16 mb + lane %
-// 16, ci = 8 (lane / 16) + j; transposed: ci = 16 mb + lane % 16,
+// 32 x 32 layer, its two MFMA fragment slots (forward: co = fwd_row(mb,
+// lane % 16), ci = 8 (lane / 16) + j; transposed: ci = 16 mb + lane % 16,
 // co = 8 (lane / 16) + j; each master weight occupies one slot of each).
 __global__ __launch_bounds__(kB) void adam_all_kernel(SrgAdamTable tab, float lr, float b1,
                                                       float b2, float eps, float c1, float c2) {
@@ -962,7 +970,9 @@ __global__ __launch_bounds__(kB) void adam_all_kernel(SrgAdamTable tab, float lr
   if (G.wb) G.wb[i] = hb;
   if (G.wf) {  // master layout [co][ci][9], 32 x 32
     const int t = i % 9, ci = (i / 9) % kC, co = i / (9 * kC);
-    G.wf[((t * 2 + co / 16) * 64 + co % 16 + 16 * (ci / 8)) * 8 + ci % 8] = hb;
+    // inverse of fwd_row: co = 8 (m / 4) + 4 mb + m % 4
+    const int mb = (co >> 2) & 1, m = 4 * (co >> 3) + (co & 3);
+    G.wf[((t * 2 + mb) * 64 + m + 16 * (ci / 8)) * 8 + ci % 8] = hb;
     G.wt[((t * 2 + ci / 16) * 64 + ci % 16 + 16 * (co / 8)) * 8 + co % 8] = hb;
   }
 }
