@@ -473,13 +473,13 @@ __global__ __launch_bounds__(kB) void thin_wgrad_finish_kernel(const double* __r
 // ------------------------------------------- 32 -> 32 layers on MFMA
 
 // Weight fragments for the matrix cores, from the FP32 masters [32][32][9]:
-//   fwd[t][mb][lane][j] = W[co = fwd_row(mb, lane % 16)][ci = 8 (lane / 16) + j][t]
-//   bwd[t][mb][lane][j] = W[co = 8 (lane / 16) + j][ci = 16 mb + lane % 16][t]
-// (A operands of D = W_t X and D = W_t^T G).  Row m of forward channel
+//   fwd[t][mb][lane][j] = W[co = frag_row(mb, lane % 16)][ci = 8 (lane / 16) + j][t]
+//   bwd[t][mb][lane][j] = W[co = 8 (lane / 16) + j][ci = frag_row(mb, lane % 16)][t]
+// (A operands of D = W_t X and D = W_t^T G).  Row m of output channel
 // block mb is channel 8 (m / 4) + 4 mb + m % 4, so that the accumulator
 // lanes (q, pixel) of blocks 0 and 1 hold channels 8q..8q+3 and
 // 8q+4..8q+7.
-__device__ __forceinline__ int fwd_row(int mb, int m) { return 8 * (m >> 2) + 4 * mb + (m & 3); }
+__device__ __forceinline__ int frag_row(int mb, int m) { return 8 * (m >> 2) + 4 * mb + (m & 3); }
 
 __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restrict__ w,
                                                           uint16_t* __restrict__ fwd,
@@ -487,8 +487,8 @@ __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restric
   const int i = blockIdx.x * kB + threadIdx.x;  // over 9 * 2 * 64 * 8
   if (i >= 9 * 2 * 64 * 8) return;
   const int j = i & 7, lane = (i >> 3) & 63, mb = (i >> 9) & 1, t = i >> 10;
-  const int a = 16 * mb + (lane & 15), b = 8 * (lane >> 4) + j;
-  fwd[i] = f32_to_bf16(w[(fwd_row(mb, lane & 15) * kC + b) * 9 + t]);
+  const int a = frag_row(mb, lane & 15), b = 8 * (lane >> 4) + j;
+  fwd[i] = f32_to_bf16(w[(a * kC + b) * 9 + t]);
   bwd[i] = f32_to_bf16(w[(b * kC + a) * 9 + t]);
 }
 
@@ -615,22 +615,21 @@ __global__ __launch_bounds__(kB, 3) void c32_bwd_data_kernel(const uint16_t* __r
     for (int j = 0; j < kPR; ++j) {
       const int y = y0 + j;
       if (y < H && px < W) {
-        const size_t o = pix(b * H + y, W, px) * kC + 4 * q;
-        const u32x2 p0 = *reinterpret_cast<const u32x2*>(aprev + o);
-        const u32x2 p1 = *reinterpret_cast<const u32x2*>(aprev + o + 16);
-        const float av[2][4] = {{lo16(p0[0]), hi16(p0[0]), lo16(p0[1]), hi16(p0[1])},
-                                {lo16(p1[0]), hi16(p1[0]), lo16(p1[1]), hi16(p1[1])}};
-        u32x2 r[2];
+        // channels 8q..8q+7 of the pixel (blocks 0 and 1 of the accumulator)
+        const size_t o = pix(b * H + y, W, px) * kC + 8 * q;
+        const u32x4 pa = *reinterpret_cast<const u32x4*>(aprev + o);
+        const float av[2][4] = {{lo16(pa[0]), hi16(pa[0]), lo16(pa[1]), hi16(pa[1])},
+                                {lo16(pa[2]), hi16(pa[2]), lo16(pa[3]), hi16(pa[3])}};
+        u32x4 r;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const float g0 = acc[j][mb][2 * h] * (1.f - av[mb][2 * h] * av[mb][2 * h]);
             const float g1 = acc[j][mb][2 * h + 1] * (1.f - av[mb][2 * h + 1] * av[mb][2 * h + 1]);
-            r[mb][h] = pack_bf16(g0, g1);
+            r[2 * mb + h] = pack_bf16(g0, g1);
           }
-        *reinterpret_cast<u32x2*>(dzprev + o) = r[0];
-        *reinterpret_cast<u32x2*>(dzprev + o + 16) = r[1];
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4*>(dzprev + o));
       }
     }
   }
@@ -946,9 +945,9 @@ __global__ __launch_bounds__(kB) void adam_kernel(float* __restrict__ w, uint16_
 // One Adam step for every parameter of the network in one launch: thread i
 // finds its group in the table and updates the FP32 master, its moments and
 // its compute copy -- the BF16 weight of a one-channel layer, or, for a
-// 32 x 32 layer, its two MFMA fragment slots (forward: co = fwd_row(mb,
-// lane % 16), ci = 8 (lane / 16) + j; transposed: ci = 16 mb + lane % 16,
-// co = 8 (lane / 16) + j; each master weight occupies one slot of each).
+// 32 x 32 layer, its two MFMA fragment slots (forward: co = frag_row(mb,
+// lane % 16), ci = 8 (lane / 16) + j; transposed: ci = frag_row(mb, lane %
+// 16), co = 8 (lane / 16) + j; each master weight occupies one slot of each).
 __global__ __launch_bounds__(kB) void adam_all_kernel(SrgAdamTable tab, float lr, float b1,
                                                       float b2, float eps, float c1, float c2) {
   int i = blockIdx.x * kB + threadIdx.x;
@@ -970,10 +969,11 @@ __global__ __launch_bounds__(kB) void adam_all_kernel(SrgAdamTable tab, float lr
   if (G.wb) G.wb[i] = hb;
   if (G.wf) {  // master layout [co][ci][9], 32 x 32
     const int t = i % 9, ci = (i / 9) % kC, co = i / (9 * kC);
-    // inverse of fwd_row: co = 8 (m / 4) + 4 mb + m % 4
-    const int mb = (co >> 2) & 1, m = 4 * (co >> 3) + (co & 3);
-    G.wf[((t * 2 + mb) * 64 + m + 16 * (ci / 8)) * 8 + ci % 8] = hb;
-    G.wt[((t * 2 + ci / 16) * 64 + ci % 16 + 16 * (co / 8)) * 8 + co % 8] = hb;
+    // inverse of frag_row: c = 8 (m / 4) + 4 mb + m % 4
+    const int mf = (co >> 2) & 1, rf = 4 * (co >> 3) + (co & 3);
+    const int mt = (ci >> 2) & 1, rt = 4 * (ci >> 3) + (ci & 3);
+    G.wf[((t * 2 + mf) * 64 + rf + 16 * (ci / 8)) * 8 + ci % 8] = hb;
+    G.wt[((t * 2 + mt) * 64 + rt + 16 * (co / 8)) * 8 + co % 8] = hb;
   }
 }
 
