@@ -430,7 +430,11 @@ __global__ __launch_bounds__(kBlock) void forward3_kernel(Geometry3 g, Model3Coe
   T jx, jy, jz;
   first_moment(fv, jx, jy, jz);
   const bool solid = MASKED && (lm & 1u);
-  if (a.rec != nullptr && !solid) {
+  // every lane stores the record (zeros at the solid lanes of a mixed
+  // wavefront, read by nobody), so that the stores fill whole chunks: a
+  // store that leaves part of a 64-byte chunk unwritten costs a
+  // read-modify-write in memory
+  if (a.rec != nullptr) {
     __builtin_nontemporal_store(u, &a.rec[n.pub]);
     __builtin_nontemporal_store(jx, &a.rec[size_t(g.plane) + n.pub]);
     __builtin_nontemporal_store(jy, &a.rec[2 * size_t(g.plane) + n.pub]);
@@ -573,12 +577,12 @@ __global__ __launch_bounds__(kBlock) void adjoint3_kernel(Geometry3 g, Model3Coe
     py = T(1.0 / 6.0) * dya + T(1.0 / 12.0) * (py - dya);
     pz = T(1.0 / 6.0) * dza + T(1.0 / 12.0) * (pz - dza);
   }
-  if (!solid) {
-    if (FIRST)
-      a.g[idx] = double(sv);
-    else
-      a.g[idx] += double(sv);
-  }
+  // a solid lane of a mixed wavefront adds the 0 of its zero-filled
+  // gather, so the gradient stays 0 there and the stores fill whole chunks
+  if (FIRST)
+    a.g[idx] = solid ? 0.0 : double(sv);
+  else
+    a.g[idx] += double(sv);
   const T u = __builtin_nontemporal_load(&a.rec[idx]);
   const T jx = __builtin_nontemporal_load(&a.rec[size_t(g.plane) + idx]);
   const T jy = __builtin_nontemporal_load(&a.rec[2 * size_t(g.plane) + idx]);
