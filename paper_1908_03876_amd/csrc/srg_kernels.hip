@@ -254,12 +254,20 @@ __global__ __launch_bounds__(kB, 4) void l3_fwd_kernel(const uint16_t* __restric
   const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
   const int npatch = B * pr * pc;
   const int row = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), col = threadIdx.x & 63;
-  // byte offsets of this lane's three x taps (each quarter) in a staged row
-  uint32_t colo[3][4];
+  // byte offsets of this lane's three x taps (each quarter) in a staged
+  // row, and of the matching weight pairs.  Lane group g = col / 16 takes
+  // the quarters in the order g, g + 1, ... (mod 4), so that the four groups
+  // read different quarters at once, the access of the 32 -> 32 layers for
+  // which the staging rotates the quarters (all 64 lanes on one quarter
+  // conflicted in LDS)
+  uint32_t colo[3][4], wo[4];
 #pragma unroll
-  for (int dx = 0; dx < 3; ++dx)
+  for (int part = 0; part < 4; ++part) {
+    const int pq = (part + (col >> 4)) & 3;
+    wo[part] = uint32_t(4 * pq);
 #pragma unroll
-    for (int part = 0; part < 4; ++part) colo[dx][part] = stage_off(0, col + dx, part);
+    for (int dx = 0; dx < 3; ++dx) colo[dx][part] = stage_off(0, col + dx, pq);
+  }
   const uint32_t rowo = uint32_t(row * kSW * 64);
   u32x4 pre[kChunks];
   if (int(blockIdx.x) < npatch) fetch_patch(a, blockIdx.x, pr, pc, H, W, pre);
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(kB, 4) void l3_fwd_kernel(const uint16_t* __restric
       for (int part = 0; part < 4; ++part) {
         const u32x4 v = *reinterpret_cast<const u32x4*>(st + rowo + colo[dx][part] +
                                                         uint32_t(dy * kSW * 64));
-        const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + 4 * part]);
+        const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + wo[part]]);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           // through scalars: a bit cast of a vector element itself reads element 0
