@@ -339,7 +339,8 @@ int mrt_timing_read(int32_t kind, double* ms /* host */,
  * that mix.  Built mixes (reads, writes): (19, 18), (19, 21), (23, 20)
  * (the D2Q9 forward without and with the record, and the AMRT step),
  * (39, 42), (44, 40) (the D3Q19 forward and AMRT step); others, another
- * order, and n of 2^31 or more 256-element tiles, return MRT_EINVAL.
+ * order, a NULL buffer or a negative n, and n of 2^31 or more 256-element
+ * tiles, return MRT_EINVAL (checked on the host; n = 0 launches nothing).
  * Caller-owned device buffers of reads * n and writes * n floats.
  * Asynchronous on `stream`. */
 int mrt_stream_probe(int32_t reads, int32_t writes, int32_t order, const float* in, float* out,

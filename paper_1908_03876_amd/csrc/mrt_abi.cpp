@@ -1253,10 +1253,12 @@ int mrt_stream_probe(int32_t reads, int32_t writes, int32_t order, const float* 
                      int64_t n, void* stream) {
   if (!in || !out || n < 0) return fail(MRT_EINVAL, "NULL buffer or negative size");
   if (order != 0 && order != 1) return fail(MRT_EINVAL, "order must be 0 or 1");
+  if (!mrt::stream_probe_has_mix(reads, writes))
+    return fail(MRT_EINVAL, "stream probe: mix (%d, %d) not built", int(reads), int(writes));
   if (n == 0) return MRT_OK;
   if (!mrt::launch_stream_probe(reads, writes, order == 1, in, out, size_t(n),
                                 static_cast<hipStream_t>(stream)))
-    return fail(MRT_EINVAL, "stream probe: mix not built or n too large");
+    return fail(MRT_EINVAL, "stream probe: n too large");
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MRT_OK : fail(MRT_EHIP, "%s", hipGetErrorString(e));
 }

@@ -42,6 +42,11 @@ __global__ __launch_bounds__(kProbeBlock) void stream_probe_kernel(const float* 
 
 }  // namespace
 
+bool stream_probe_has_mix(int reads, int writes) {
+  return (reads == 19 && (writes == 18 || writes == 21)) || (reads == 23 && writes == 20) ||
+         (reads == 39 && writes == 42) || (reads == 44 && writes == 40);
+}
+
 bool launch_stream_probe(int reads, int writes, bool banded, const float* in, float* out,
                          size_t n, hipStream_t s) {
   if ((n + kProbeBlock - 1) / kProbeBlock > size_t(INT_MAX)) return false;

@@ -227,3 +227,19 @@ def test_tape3_bytes_layout():
         # a non-periodic lattice uses link words even without a mask
         sw = make_problem3_struct(p.copy(periodic=False), code, pitch, None)
         assert abi.mrt3_tape_bytes(sw, 0) == 2 * state + red + plane * 6 + p.nz * p.ny * 4
+
+
+@pytest.mark.parametrize("reads,writes,order,n,ok", [
+    (19, 18, 0, 0, True), (19, 21, 1, 0, True), (23, 20, 0, 0, True),
+    (39, 42, 1, 0, True), (44, 40, 0, 0, True),
+    (3, 2, 0, 0, False), (19, 19, 1, 0, False), (19, 18, 2, 0, False),
+    (19, 18, -1, 0, False), (23, 20, 1, -1, False)])
+def test_stream_probe_argument_checks(reads, writes, order, n, ok):
+    """The streaming probe validates its mix, tile order and size on the host
+    (n = 0 launches nothing, so the buffers are never touched)."""
+    from paper_1908_03876_amd import abi
+    buf = (ctypes.c_float * 4)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    rc = abi.lib.mrt_stream_probe(reads, writes, order, p, p, n, None)
+    assert rc == (abi.MRT_OK if ok else abi.MRT_EINVAL)
+    assert abi.lib.mrt_stream_probe(19, 18, 0, None, p, 0, None) == abi.MRT_EINVAL
