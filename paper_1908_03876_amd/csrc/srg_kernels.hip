@@ -23,7 +23,9 @@
 // costs a read-modify-write in memory.  A block keeps the 18 weight fragments
 // (9 taps x 2 channel blocks) in LDS, read per MFMA, and walks many tiles;
 // the forward stages its input patches in LDS as well.
-// The one-channel first and last layers stay on the vector ALU.
+// The one-channel first layer runs its 9-tap products on the FP32 matrix
+// cores (v_mfma_f32_16x16x4_f32) and its tanh on the vector ALU; the last
+// layer stays on the vector ALU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,18 +65,23 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
-// Hyperbolic tangent in a few instructions: tanh x = s (1 - 2 / (e^{2|x|} + 1))
-// with s = sign x, from the hardware base-2 exponential and reciprocal
-// (absolute error about 1.5e-7: an ulp of each near 1); for |x| < 1e-3,
-// where that form cancels, x itself (tanh x = x (1 - x^2 / 3 + ...), off by
-// at most 3.4e-10).  Both are far below the BF16 spacing of the stored
-// activations.
+// Hyperbolic tangent in five instructions: tanh x = 1 - 2 / (e^{2x} + 1),
+// from the hardware base-2 exponential and reciprocal.  The absolute error
+// stays within about 3e-7 for every x (an ulp or two of the terms near 1),
+// 0 and the limits +-1 come out exact, and non-finite inputs give +-1 or
+// NaN.  Near zero the form cancels, so the error is absolute, not relative:
+// below the BF16 spacing of every stored activation with |a| > 1e-4, and a
+// few units of 1e-7 on the smaller ones.
 __device__ __forceinline__ float tanh_fast(float x) {
-  const float ax = fabsf(x);
-  const float e = __builtin_amdgcn_exp2f(ax * 2.8853900817779268f);  // 2 log2(e)
-  const float big = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
-  return copysignf(ax < 1e-3f ? ax : big, x);
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
 }
+
+// Row m of output channel block mb of an MFMA product (channels x pixels)
+// is channel 8 (m / 4) + 4 mb + m % 4, so that the accumulator lanes
+// (q, pixel) of blocks 0 and 1 hold channels 8q..8q+3 and 8q+4..8q+7: the 8
+// consecutive channels, 16 bytes, of one pixel.
+__device__ __forceinline__ int frag_row(int mb, int m) { return 8 * (m >> 2) + 4 * mb + (m & 3); }
 
 __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -114,40 +121,79 @@ __device__ __forceinline__ double block_sum_d(double v) {
 
 // ------------------------------------------------ first layer (1 -> 32)
 
-// One thread per pixel: a0 = bf16(tanh(b + W0 * (s_in x))), 32 channels.
+// a0 = bf16(tanh(b + W0 * (s_in x))), 32 channels.  A wavefront takes 64
+// consecutive pixels of one row as four tiles of 16.  Per tile the 32 x 9
+// weight matrix times the 9 x 16 window matrix is six
+// v_mfma_f32_16x16x4_f32 (FP32 operands and accumulation), which takes the
+// 288 multiply-adds per pixel off the vector ALU; the tanh stays there.
+// K-step ks takes the window row y + ks - 1, and its slot q < 3 the column
+// x + q - 1 (slot 3 is zero padding), so a k-step reads one wave-uniform
+// row and a tile's three k-steps share their column offsets.  Lane
+// (q, pixel) ends with channels 8q..8q+7 of its pixel and writes them with
+// one 16-byte store.
 __global__ __launch_bounds__(kB) void l0_fwd_kernel(const float* __restrict__ x,
                                                     const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias,
                                                     uint16_t* __restrict__ out, int B, int H,
                                                     int W, float iscale) {
-  __shared__ float sw[kC * 9];
-  __shared__ float sb[kC];
-  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
-  if (threadIdx.x < kC) sb[threadIdx.x] = bias[threadIdx.x];
-  __syncthreads();
-  const size_t hw = size_t(H) * W;
-  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
-  if (p >= size_t(B) * hw) return;
-  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
-  float v[9];
+  const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
+  // (row, segment) units fit 32 bits: fields hold at most 2^28 pixels
+  const unsigned nseg = unsigned(W + 63) >> 6;
+  const unsigned unit = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (unit >= unsigned(B) * unsigned(H) * nseg) return;  // the whole wavefront
+  const int seg = int(unit % nseg);
+  const unsigned row = unit / nseg;  // image b, row y: b H + y
+  const int y = int(row % unsigned(H));
+  const float* xr[3];  // the three window rows, periodic
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
-    v[t] = iscale * x[size_t(b) * hw + size_t(wrap(py + t / 3 - 1, H)) * W +
-                      wrap(px + t % 3 - 1, W)];
-  uint32_t pk[16];
+  for (int ks = 0; ks < 3; ++ks)
+    xr[ks] = x + size_t(row - y + wrap(y + ks - 1, H)) * W;
+  float wa[2][3];  // A operands: W0[frag_row(mb, n)][3 ks + q], zero for q = 3
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    float z0 = sb[2 * k], z1 = sb[2 * k + 1];
+  for (int ks = 0; ks < 3; ++ks)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      z0 += sw[(2 * k) * 9 + t] * v[t];
-      z1 += sw[(2 * k + 1) * 9 + t] * v[t];
+    for (int mb = 0; mb < 2; ++mb) {
+      const float wv = bf16_to_f32(w[frag_row(mb, n) * 9 + 3 * ks + (q < 3 ? q : 2)]);
+      wa[mb][ks] = q < 3 ? wv : 0.f;
     }
-    pk[k] = pack_bf16(tanh_fast(z0), tanh_fast(z1));
-  }
-  u32x4* o = reinterpret_cast<u32x4*>(out + p * kC);
+  f32x4 b0, b1;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) o[k] = u32x4{pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]};
+  for (int i = 0; i < 4; ++i) {
+    b0[i] = bias[8 * q + i];
+    b1[i] = bias[8 * q + 4 + i];
+  }
+  // the window values of all four tiles, loaded together; every address
+  // is in the row (lanes past a ragged row end and the padding slot read a
+  // valid pixel and use zero)
+  float v[4][3];
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+    const int px = seg * 64 + tile * 16 + n;
+    const bool use = px < W && q < 3;
+    const int col = px < W ? wrap(px + (q < 3 ? q : 1) - 1, W) : 0;
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      const float xv = xr[ks][col];
+      v[tile][ks] = use ? iscale * xv : 0.f;
+    }
+  }
+  uint16_t* orow = out + size_t(row) * W * kC + 8 * q;
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+    const int px = seg * 64 + tile * 16 + n;
+    f32x4 a0 = b0, a1 = b1;
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[0][ks], v[tile][ks], a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[1][ks], v[tile][ks], a1, 0, 0, 0);
+    }
+    if (px < W)
+      __builtin_nontemporal_store(u32x4{pack_bf16(tanh_fast(a0[0]), tanh_fast(a0[1])),
+                                        pack_bf16(tanh_fast(a0[2]), tanh_fast(a0[3])),
+                                        pack_bf16(tanh_fast(a1[0]), tanh_fast(a1[1])),
+                                        pack_bf16(tanh_fast(a1[2]), tanh_fast(a1[3]))},
+                                  reinterpret_cast<u32x4*>(orow + size_t(px) * kC));
+  }
 }
 
 // dx[p] = s_in * sum_t sum_co W0[co][t] dz0[p - off(t)][co]
@@ -483,11 +529,8 @@ __global__ __launch_bounds__(kB) void thin_wgrad_finish_kernel(const double* __r
 // Weight fragments for the matrix cores, from the FP32 masters [32][32][9]:
 //   fwd[t][mb][lane][j] = W[co = frag_row(mb, lane % 16)][ci = 8 (lane / 16) + j][t]
 //   bwd[t][mb][lane][j] = W[co = 8 (lane / 16) + j][ci = frag_row(mb, lane % 16)][t]
-// (A operands of D = W_t X and D = W_t^T G).  Row m of output channel
-// block mb is channel 8 (m / 4) + 4 mb + m % 4, so that the accumulator
-// lanes (q, pixel) of blocks 0 and 1 hold channels 8q..8q+3 and
-// 8q+4..8q+7.
-__device__ __forceinline__ int frag_row(int mb, int m) { return 8 * (m >> 2) + 4 * mb + (m & 3); }
+// (A operands of D = W_t X and D = W_t^T G), with the rows interleaved by
+// frag_row.
 
 __global__ __launch_bounds__(kB) void pack_weights_kernel(const float* __restrict__ w,
                                                           uint16_t* __restrict__ fwd,
@@ -1149,8 +1192,11 @@ int blocks_for_pixels(int B, int H, int W) { return blocks_for(size_t(B) * H * W
 
 void launch_srg_l0_fwd(const float* x, const uint16_t* w, const float* b, uint16_t* out, int B,
                        int H, int W, float iscale, hipStream_t s) {
-  hipLaunchKernelGGL(l0_fwd_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, x, w, b,
-                     out, B, H, W, iscale);
+  // one wavefront per 64-pixel segment of a row
+  const size_t units = size_t(B) * H * ((W + 63) / 64);
+  const int nb = int((units + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(l0_fwd_kernel, dim3(nb > 0 ? nb : 1), dim3(kB), 0, s, x, w, b, out, B, H,
+                     W, iscale);
 }
 
 void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, int B, int H,
