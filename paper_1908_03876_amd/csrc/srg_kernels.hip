@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restr
 constexpr int kPR = 4;                      // output rows per patch
 constexpr int kSW = 66;                     // staged pixels per row
 constexpr int kStage = (kPR + 2) * kSW * 4; // 16-byte chunks staged
-static_assert(kPR == kWaves, "the 32 -> 1 layer maps one wavefront to each patch row");
+static_assert(kPR == 4, "the 32 -> 1 layer maps one wavefront to two patch rows, two per block");
 
 __device__ __forceinline__ uint32_t stage_off(int r, int px, int part) {
   return uint32_t((r * kSW + px) * 64 + (((part + (px >> 1)) & 3) << 4));
@@ -245,14 +245,14 @@ __device__ __forceinline__ uint32_t stage_off(int r, int px, int part) {
 
 // Stage the patch's chunks this thread owns into registers (the caller
 // writes them to LDS once the previous patch is done).
-template <int NCH>
+template <int NCH, int NT = kB>
 __device__ __forceinline__ void fetch_patch(const uint16_t* __restrict__ in, int patch, int pr,
                                             int pc, int H, int W, u32x4 (&pre)[NCH]) {
   const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
   const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
-    const int c = int(threadIdx.x) + k * kB;
+    const int c = int(threadIdx.x) + k * NT;
     if (c < kStage) {
       const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
       int yy = y0 - 1 + r;
@@ -265,11 +265,11 @@ __device__ __forceinline__ void fetch_patch(const uint16_t* __restrict__ in, int
   }
 }
 
-template <int NCH>
+template <int NCH, int NT = kB>
 __device__ __forceinline__ void store_patch(unsigned char* st, const u32x4 (&pre)[NCH]) {
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
-    const int c = int(threadIdx.x) + k * kB;
+    const int c = int(threadIdx.x) + k * NT;
     if (c < kStage) {
       const int r = c / (kSW * 4), rr = c - r * (kSW * 4), px = rr >> 2, part = rr & 3;
       *reinterpret_cast<u32x4*>(st + stage_off(r, px, part)) = pre[k];
@@ -279,27 +279,34 @@ __device__ __forceinline__ void store_patch(unsigned char* st, const u32x4 (&pre
 
 constexpr int kChunks = (kStage + kB - 1) / kB;
 
-// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]): one thread
-// per output pixel of a staged patch (wavefront = patch row), the 32
-// channels of each tap summed as 16 two-channel dot products of BF16 pairs
-// (exact products, FP32 sums) with the weight pairs read as LDS broadcasts.
-__global__ __launch_bounds__(kB, 4) void l3_fwd_kernel(const uint16_t* __restrict__ a,
-                                                    const uint16_t* __restrict__ w,
-                                                    const float* __restrict__ bias,
-                                                    float* __restrict__ y, int B, int H, int W,
-                                                    float oscale) {
+constexpr int kB3 = 128;  // threads of a 32 -> 1 block: two wavefronts
+constexpr int kChunks3 = (kStage + kB3 - 1) / kB3;
+
+// y[p] = s_out * (b + sum_t sum_ci W3[ci][t] a2[p + off(t)][ci]) over a
+// staged patch: wavefront w takes patch rows 2w and 2w + 1, a lane the two
+// pixels of its column.  The 32 channels of a tap are summed as 16
+// two-channel dot products of BF16 pairs (exact products, FP32 sums).  Per
+// column offset dx and channel quarter the lane reads the weight quarters
+// of the three taps (dy, dx) once and the four staged rows its two pixels
+// share once each, 84 LDS reads for two pixels where one pixel at a time
+// took 72; LDS bandwidth bounds this layer.
+__global__ __launch_bounds__(kB3, 3) void l3_fwd_kernel(const uint16_t* __restrict__ a,
+                                                     const uint16_t* __restrict__ w,
+                                                     const float* __restrict__ bias,
+                                                     float* __restrict__ y, int B, int H, int W,
+                                                     float oscale) {
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   // (W3[2j][t], W3[2j+1][t]) as BF16 pairs, [t][j]
   __shared__ __attribute__((aligned(16))) uint32_t wp[9 * 16];
   __shared__ __attribute__((aligned(16))) unsigned char st[kStage * 16];
-  for (int i = threadIdx.x; i < 9 * 16; i += kB) {
+  for (int i = threadIdx.x; i < 9 * 16; i += kB3) {
     const int t = i / 16, j = i - 16 * t;
     wp[i] = uint32_t(w[(2 * j) * 9 + t]) | (uint32_t(w[(2 * j + 1) * 9 + t]) << 16);
   }
   const float b0 = bias[0];
   const int pr = (H + kPR - 1) / kPR, pc = (W + 63) >> 6;
   const int npatch = B * pr * pc;
-  const int row = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), col = threadIdx.x & 63;
+  const int r0 = 2 * __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), col = threadIdx.x & 63;
   // byte offsets of this lane's three x taps (each quarter) in a staged
   // row, and of the matching weight pairs.  Lane group g = col / 16 takes
   // the quarters in the order g, g + 1, ... (mod 4), so that the four groups
@@ -314,36 +321,57 @@ __global__ __launch_bounds__(kB, 4) void l3_fwd_kernel(const uint16_t* __restric
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) colo[dx][part] = stage_off(0, col + dx, pq);
   }
-  const uint32_t rowo = uint32_t(row * kSW * 64);
-  u32x4 pre[kChunks];
-  if (int(blockIdx.x) < npatch) fetch_patch(a, blockIdx.x, pr, pc, H, W, pre);
+  const uint32_t rowo = uint32_t(r0 * kSW * 64);
+  u32x4 pre[kChunks3];
+  if (int(blockIdx.x) < npatch) fetch_patch<kChunks3, kB3>(a, blockIdx.x, pr, pc, H, W, pre);
   for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
     const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
     const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
     __syncthreads();  // the previous patch's reads of st are done (and wp is written)
-    store_patch(st, pre);
+    store_patch<kChunks3, kB3>(st, pre);
     __syncthreads();
-    if (patch + int(gridDim.x) < npatch) fetch_patch(a, patch + gridDim.x, pr, pc, H, W, pre);
-    float acc = 0.f;
+    if (patch + int(gridDim.x) < npatch)
+      fetch_patch<kChunks3, kB3>(a, patch + gridDim.x, pr, pc, H, W, pre);
+    float acc0 = 0.f, acc1 = 0.f;  // patch rows r0 and r0 + 1
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int dy = t / 3, dx = t % 3;
+    for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
       for (int part = 0; part < 4; ++part) {
-        const u32x4 v = *reinterpret_cast<const u32x4*>(st + rowo + colo[dx][part] +
-                                                        uint32_t(dy * kSW * 64));
-        const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + wo[part]]);
+        u32x4 wq[3];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          // through scalars: a bit cast of a vector element itself reads element 0
-          const uint32_t ve = v[e], we = wq[e];
-          acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, ve),
-                                                __builtin_bit_cast(bf16x2, we), acc, false);
+        for (int dy = 0; dy < 3; ++dy)
+          wq[dy] = *reinterpret_cast<const u32x4*>(&wp[(3 * dy + dx) * 16 + wo[part]]);
+#pragma unroll
+        for (int sr = 0; sr < 4; ++sr) {  // staged row r0 + sr
+          const u32x4 v = *reinterpret_cast<const u32x4*>(st + rowo + colo[dx][part] +
+                                                          uint32_t(sr * kSW * 64));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            // through scalars: a bit cast of a vector element itself reads element 0
+            const uint32_t ve = v[e];
+            if (sr < 3) {
+              const uint32_t we = wq[sr][e];
+              acc0 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, ve),
+                                                     __builtin_bit_cast(bf16x2, we), acc0, false);
+            }
+            if (sr > 0) {
+              const uint32_t we = wq[sr - 1][e];
+              acc1 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, ve),
+                                                     __builtin_bit_cast(bf16x2, we), acc1, false);
+            }
+          }
         }
       }
     }
-    const int yo = y0 + row, xo = x0 + col;
-    if (yo < H && xo < W) y[pix(b * H + yo, W, xo)] = oscale * (b0 + acc);
+    // both sums complete here: left to the conditional stores below, the
+    // compiler sinks the dot products into them and keeps all 84 LDS reads
+    // live across the branch (spilling)
+    asm volatile("" : "+v"(acc0), "+v"(acc1));
+    const int yo = y0 + r0, xo = x0 + col;
+    if (xo < W) {
+      if (yo < H) y[pix(b * H + yo, W, xo)] = oscale * (b0 + acc0);
+      if (yo + 1 < H) y[pix(b * H + yo + 1, W, xo)] = oscale * (b0 + acc1);
+    }
   }
 }
 
@@ -1207,11 +1235,12 @@ void launch_srg_l0_bwd_data(const uint16_t* dz, const uint16_t* w, float* dx, in
 
 void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, float* y, int B,
                        int H, int W, float oscale, hipStream_t s) {
-  // patches of kPR rows x 64 pixels; four blocks per CU (the kernel is
-  // built for four wavefronts per SIMD, and four stages fit in 160 KB)
+  // patches of kPR rows x 64 pixels; six two-wavefront blocks per CU (six
+  // 26 KB stages fit in 160 KB; the kernel is built for three wavefronts
+  // per SIMD)
   const int np = B * ((H + kPR - 1) / kPR) * ((W + 63) / 64);
-  const int nb = np < 1024 ? (np > 0 ? np : 1) : 1024;
-  hipLaunchKernelGGL(l3_fwd_kernel, dim3(nb), dim3(kB), 0, s, a, w, b,
+  const int nb = np < 1536 ? (np > 0 ? np : 1) : 1536;
+  hipLaunchKernelGGL(l3_fwd_kernel, dim3(nb), dim3(kB3), 0, s, a, w, b,
                      y, B, H, W, oscale);
 }
 
