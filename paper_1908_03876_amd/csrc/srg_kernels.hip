@@ -196,13 +196,21 @@ __global__ __launch_bounds__(kB) void l0_fwd_kernel(const float* __restrict__ x,
   }
 }
 
-// dx[p] = s_in * sum_t sum_co W0[co][t] dz0[p - off(t)][co]
+// dx[p] = s_in * sum_t sum_co W0[co][t] dz0[p - off(t)][co]: one thread per
+// pixel, the 32 channels of each mirrored tap summed as 16 two-channel dot
+// products of BF16 pairs (exact products, FP32 sums), the weight pairs read
+// as LDS broadcasts.
 __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restrict__ dz,
                                                          const uint16_t* __restrict__ w,
                                                          float* __restrict__ dx, int B, int H,
                                                          int W, float iscale) {
-  __shared__ float sw[kC * 9];
-  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  // (W0[2j][t], W0[2j+1][t]) as BF16 pairs, [t][j]
+  __shared__ __attribute__((aligned(16))) uint32_t wp[9 * 16];
+  for (int i = threadIdx.x; i < 9 * 16; i += kB) {
+    const int t = i / 16, j = i - 16 * t;
+    wp[i] = uint32_t(w[(2 * j) * 9 + t]) | (uint32_t(w[(2 * j + 1) * 9 + t]) << 16);
+  }
   __syncthreads();
   const size_t hw = size_t(H) * W;
   const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
@@ -216,10 +224,13 @@ __global__ __launch_bounds__(kB) void l0_bwd_data_kernel(const uint16_t* __restr
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const u32x4 q = g[k];
+      const u32x4 wq = *reinterpret_cast<const u32x4*>(&wp[t * 16 + 4 * k]);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int co = 8 * k + 2 * e;
-        acc += sw[co * 9 + t] * lo16(q[e]) + sw[(co + 1) * 9 + t] * hi16(q[e]);
+        // through scalars: a bit cast of a vector element itself reads element 0
+        const uint32_t qe = q[e], we = wq[e];
+        acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, qe),
+                                              __builtin_bit_cast(bf16x2, we), acc, false);
       }
     }
   }
@@ -375,43 +386,72 @@ __global__ __launch_bounds__(kB3, 3) void l3_fwd_kernel(const uint16_t* __restri
   }
 }
 
-// dz2[p][ci] = bf16((s_out sum_t W3[ci][t] dy[p - off(t)]) (1 - a2[p][ci]^2))
+// dz2[p][ci] = bf16((s_out sum_t W3[ci][t] dy[p - off(t)]) (1 - a2[p][ci]^2)):
+// the 1 -> 32 product of the first layer's forward with the taps mirrored,
+// on the same FP32 MFMA tiles (a wavefront per 64 pixels of a row, k-step
+// ks on the row y - ks + 1, slot q < 3 on the column x - q + 1), and the
+// tanh derivative of the stored activations in the epilogue.
 __global__ __launch_bounds__(kB) void l3_bwd_data_kernel(const float* __restrict__ dy,
                                                          const uint16_t* __restrict__ w,
                                                          const uint16_t* __restrict__ a,
                                                          uint16_t* __restrict__ dz, int B, int H,
                                                          int W, float oscale) {
-  __shared__ float sw[kC * 9];
-  for (int i = threadIdx.x; i < kC * 9; i += kB) sw[i] = bf16_to_f32(w[i]);
-  __syncthreads();
-  const size_t hw = size_t(H) * W;
-  const size_t p = size_t(blockIdx.x) * kB + threadIdx.x;
-  if (p >= size_t(B) * hw) return;
-  const int b = int(p / hw), r = int(p % hw), py = r / W, px = r % W;
-  float g[9];
+  const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
+  // (row, segment) units fit 32 bits: fields hold at most 2^28 pixels
+  const unsigned nseg = unsigned(W + 63) >> 6;
+  const unsigned unit = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (unit >= unsigned(B) * unsigned(H) * nseg) return;  // the whole wavefront
+  const int seg = int(unit % nseg);
+  const unsigned row = unit / nseg;  // image b, row y: b H + y
+  const int y = int(row % unsigned(H));
+  const float* gr[3];  // the three mirrored window rows, periodic
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
-    g[t] = oscale * dy[size_t(b) * hw + size_t(wrap(py - (t / 3 - 1), H)) * W +
-                       wrap(px - (t % 3 - 1), W)];
-  const u32x4* ap = reinterpret_cast<const u32x4*>(a + p * kC);
-  u32x4* o = reinterpret_cast<u32x4*>(dz + p * kC);
+  for (int ks = 0; ks < 3; ++ks)
+    gr[ks] = dy + size_t(row - y + wrap(y + 1 - ks, H)) * W;
+  float wa[2][3];  // A operands: W3[frag_row(mb, n)][3 ks + q], zero for q = 3
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const u32x4 q = ap[k];
-    u32x4 res;
+  for (int ks = 0; ks < 3; ++ks)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int ci = 8 * k + 2 * e;
-      float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        s0 += sw[ci * 9 + t] * g[t];
-        s1 += sw[(ci + 1) * 9 + t] * g[t];
-      }
-      const float a0 = lo16(q[e]), a1 = hi16(q[e]);
-      res[e] = pack_bf16(s0 * (1.f - a0 * a0), s1 * (1.f - a1 * a1));
+    for (int mb = 0; mb < 2; ++mb) {
+      const float wv = bf16_to_f32(w[frag_row(mb, n) * 9 + 3 * ks + (q < 3 ? q : 2)]);
+      wa[mb][ks] = q < 3 ? wv : 0.f;
     }
-    o[k] = res;
+  float v[4][3];
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+    const int px = seg * 64 + tile * 16 + n;
+    const bool use = px < W && q < 3;
+    const int col = px < W ? wrap(px + 1 - (q < 3 ? q : 1), W) : 0;
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      const float gv = gr[ks][col];
+      v[tile][ks] = use ? oscale * gv : 0.f;
+    }
+  }
+  const size_t rowp = size_t(row) * W;
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+    const int px = seg * 64 + tile * 16 + n;
+    f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[0][ks], v[tile][ks], s0, 0, 0, 0);
+      s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[1][ks], v[tile][ks], s1, 0, 0, 0);
+    }
+    if (px < W) {
+      // channels 8q..8q+7 of the pixel: s0 holds 8q..8q+3, s1 8q+4..8q+7
+      const size_t off = (rowp + size_t(px)) * kC + 8 * q;
+      const u32x4 av = *reinterpret_cast<const u32x4*>(a + off);
+      u32x4 r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float a0 = lo16(av[e]), a1 = hi16(av[e]);
+        const float z0 = e < 2 ? s0[2 * e] : s1[2 * e - 4];
+        const float z1 = e < 2 ? s0[2 * e + 1] : s1[2 * e - 3];
+        r[e] = pack_bf16(z0 * (1.f - a0 * a0), z1 * (1.f - a1 * a1));
+      }
+      *reinterpret_cast<u32x4*>(dz + off) = r;
+    }
   }
 }
 
@@ -1246,8 +1286,11 @@ void launch_srg_l3_fwd(const uint16_t* a, const uint16_t* w, const float* b, flo
 
 void launch_srg_l3_bwd_data(const float* dy, const uint16_t* w, const uint16_t* a, uint16_t* dz,
                             int B, int H, int W, float oscale, hipStream_t s) {
-  hipLaunchKernelGGL(l3_bwd_data_kernel, dim3(blocks_for_pixels(B, H, W)), dim3(kB), 0, s, dy,
-                     w, a, dz, B, H, W, oscale);
+  // one wavefront per 64-pixel segment of a row
+  const size_t units = size_t(B) * H * ((W + 63) / 64);
+  const int nb = int((units + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(l3_bwd_data_kernel, dim3(nb > 0 ? nb : 1), dim3(kB), 0, s, dy, w, a, dz, B,
+                     H, W, oscale);
 }
 
 void launch_srg_thin_wgrad(const uint16_t* F, const float* S, int sgn, double* part, int B,
