@@ -24,8 +24,10 @@
 // (9 taps x 2 channel blocks) in LDS, read per MFMA, and walks many tiles;
 // the forward stages its input patches in LDS as well.
 // The one-channel first layer runs its 9-tap products on the FP32 matrix
-// cores (v_mfma_f32_16x16x4_f32) and its tanh on the vector ALU; the last
-// layer stays on the vector ALU.
+// cores (v_mfma_f32_16x16x4_f32) and its tanh on the vector ALU, and so
+// does the input gradient of the last layer (the same 1 -> 32 product with
+// the taps mirrored); the last layer's forward and the first layer's input
+// gradient (32 -> 1) are BF16 pair dot products on the vector ALU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
