@@ -913,7 +913,11 @@ def main():
     o_rate = o_bytes / (o_ms / 1e3) / 1e9 if o_ms > 0 else 0.0
     side = {"kernel": other, "avg_launch_ms": round(o_ms, 5),
             "algorithmic_bytes_per_launch": int(o_bytes), "achieved": round(o_rate, 1),
-            "unit": "GB/s", "frac": round(o_rate / HBM_PEAK_GBS, 4)}
+            "unit": "GB/s", "frac": round(o_rate / HBM_PEAK_GBS, 4),
+            "traffic": (read_traffic(other, args.L)
+                        if args.source_term == 1 and args.species == 2 else None)}
+    if o_ms > 0:
+        side.update(traffic_rate(side["traffic"], o_ms))
     if args.source_term == 1 and args.species == 2:
         mix = {"amrt_adjoint_step": (23, 20), "mrt_forward_step": (19, 21)}
         add_stream_ceiling(roof, *mix[dom], dp.nx * dp.ny, dev)
