@@ -662,15 +662,27 @@ __global__ __launch_bounds__(kB, 3) void c32_fwd_kernel(const uint16_t* __restri
   for (int dx = 0; dx < 3; ++dx) colo[dx] = stage_off(0, 16 * wv + c16 + dx, q);
   // the next patch's chunks are loaded into registers while the current
   // one computes
+  // A block takes a contiguous run of patches in column-major order (down
+  // a 64-pixel column, row block after row block), so that the two halo
+  // rows it stages for the next patch are rows it fetched for this one
+  // and are still in L2.
+  const int rows = B * pr;  // row blocks over all fields
+  const int per = (npatch + int(gridDim.x) - 1) / int(gridDim.x);
+  const int s0 = int(blockIdx.x) * per, s1 = min(s0 + per, npatch);
+  auto patch_of = [&](int sq) {
+    const int cb = sq / rows;
+    return (sq - cb * rows) * pc + cb;
+  };
   u32x4 pre[kChunks];
-  if (int(blockIdx.x) < npatch) fetch_patch(in, blockIdx.x, pr, pc, H, W, pre);
-  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+  if (s0 < s1) fetch_patch(in, patch_of(s0), pr, pc, H, W, pre);
+  for (int sq = s0; sq < s1; ++sq) {
+    const int patch = patch_of(sq);
     const int b = patch / (pr * pc), rem = patch - b * (pr * pc);
     const int y0 = (rem / pc) * kPR, x0 = (rem - (rem / pc) * pc) * 64;
     __syncthreads();  // the previous patch's reads of st are done (and wl is written)
     store_patch(st, pre);
     __syncthreads();
-    if (patch + int(gridDim.x) < npatch) fetch_patch(in, patch + gridDim.x, pr, pc, H, W, pre);
+    if (sq + 1 < s1) fetch_patch(in, patch_of(sq + 1), pr, pc, H, W, pre);
     f32x4 acc[kPR][2];
 #pragma unroll
     for (int j = 0; j < kPR; ++j) {
